@@ -1,0 +1,216 @@
+"""Oracle: geometric multigrid for the level systems, Section 6.5, and the
+outer residual-correction loop with per-component solvability.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+What the paper fixes (Section 6.5): restriction by "injection", prolongation
+by "linear interpolation", weighted Jacobi with omega = 2/3 as the smoother.
+The readings taken where it is silent:
+
+* restriction of cell averages = the mean of the 2^D children, i.e. eq.
+  (AMR_avergingDownToCrse) applied to residuals;
+* prolongation = face-neighbour linear interpolation,
+  e_child = (1 - D/4) e_P + 1/4 sum_d e_{P +- e_d}, the neighbour taken on the
+  child's side; it reproduces linear functions and reads only the first
+  (homogeneous) ghost layer of the coarse correction;
+* Jacobi and red-black use the diagonal with the ghost fill folded in;
+* red-black colours by the parity of the sum of global indices; each
+  half-sweep updates its colour simultaneously (omega = 1), ghosts refilled
+  before every sweep and half-sweep, red first;
+* the coarsest depth is solved exactly (dense FP64 solve; for a component
+  with a constant null vector, bordered with one zero-mean constraint);
+* stopping: ||r_k||_inf <= max(tol_rel ||r_0||_inf, tol_abs), max-norm over
+  the cells of the level (the composite max norm of Section 7).
+"""
+import numpy as np
+
+from .level import PAD
+
+
+def restrict(fine, r, coarse):
+    """Mean of the 2^D children of every coarse cell."""
+    out = coarse.zeros()
+    n = fine.shape
+    rin = r[fine.inner]
+    acc = np.zeros(tuple(m // 2 for m in n))
+    D = fine.dim
+    for corner in np.ndindex(*(2,) * D):
+        acc += rin[tuple(slice(a, None, 2) for a in corner)]
+    out[coarse.inner] = acc / 2 ** D
+    out[~coarse.mask] = 0.0
+    return out
+
+
+def prolong(coarse, ec, fine):
+    """Face-neighbour linear interpolation of a coarse correction (with its
+    homogeneous ghosts) to the fine cells."""
+    G = coarse.ghosts(ec)
+    D = fine.dim
+    out = fine.zeros()
+    fin = out[fine.inner]
+    for corner in np.ndindex(*(2,) * D):
+        val = (1.0 - D / 4.0) * ec
+        for d in range(D):
+            k = 1 if corner[d] == 1 else -1
+            val = val + 0.25 * coarse.neighbour(ec, G, d, k)
+        fin[tuple(slice(a, None, 2) for a in corner)] = val[coarse.inner]
+    out[~fine.mask] = 0.0
+    return out
+
+
+def jacobi(lev, e, f, op, c, D, omega, nsweeps):
+    for _ in range(nsweeps):
+        r = f - lev.apply(e, op, c)
+        e = e + omega * r / D
+        e[~lev.mask] = 0.0
+    return e
+
+
+def red_black(lev, e, f, op, c, D, nsweeps):
+    red = lev.colour() & lev.mask
+    black = ~lev.colour() & lev.mask
+    for _ in range(nsweeps):
+        for sel in (red, black):
+            r = f - lev.apply(e, op, c)
+            e = e.copy()
+            e[sel] += r[sel] / D[sel]
+    return e
+
+
+def assemble(lev, op, c):
+    """Dense matrix of the homogeneous operator on the masked cells, column j
+    obtained by applying it to the j-th unit vector (probing)."""
+    cells = np.argwhere(lev.mask)
+    n = len(cells)
+    M = np.zeros((n, n))
+    for j, cell in enumerate(cells):
+        e = lev.zeros()
+        e[tuple(cell)] = 1.0
+        M[:, j] = lev.apply(e, op, c)[lev.mask]
+    return M, cells
+
+
+class Bottom:
+    """Exact solve on the coarsest depth (the bottom solver of Section 6.5
+    replaced by a direct FP64 solve)."""
+
+    def __init__(self, lev, op, c):
+        self.lev = lev
+        M, self.cells = assemble(lev, op, c)
+        self.sing = lev.singular_components(op)
+        n = M.shape[0]
+        k = len(self.sing)
+        B = np.zeros((n, k))
+        lab = lev.labels[lev.mask]
+        for j, comp in enumerate(self.sing):
+            B[lab == comp, j] = 1.0
+        self.K = np.block([[M, B], [B.T, np.zeros((k, k))]])
+        self.n = n
+
+    def solve(self, f):
+        rhs = np.concatenate([f[self.lev.mask], np.zeros(self.K.shape[0] - self.n)])
+        sol = np.linalg.solve(self.K, rhs)
+        e = self.lev.zeros()
+        e[self.lev.mask] = sol[: self.n]
+        return e
+
+
+class MG:
+    """V(nu1, nu2) cycle on the multigrid depths of one level."""
+
+    def __init__(self, lev, op, c, nu1=2, nu2=2, smoother="jacobi", omega=2.0 / 3.0):
+        self.levels = lev.hierarchy()
+        self.op, self.c = op, c
+        self.nu1, self.nu2, self.smoother, self.omega = nu1, nu2, smoother, omega
+        self.D = [l.diagonal(op, c) for l in self.levels]
+        self.sing = [l.singular_components(op) for l in self.levels]
+        self.bottom = Bottom(self.levels[-1], op, c)
+
+    def smooth(self, k, e, f, n):
+        lev = self.levels[k]
+        if self.smoother == "jacobi":
+            return jacobi(lev, e, f, self.op, self.c, self.D[k], self.omega, n)
+        return red_black(lev, e, f, self.op, self.c, self.D[k], n)
+
+    def vcycle(self, f, k=0):
+        """Correction e with A_hom e ~= f on depth k (homogeneous ghosts)."""
+        lev = self.levels[k]
+        if k == len(self.levels) - 1:
+            return self.bottom.solve(f)
+        e = self.smooth(k, lev.zeros(), f, self.nu1)
+        r = f - lev.apply(e, self.op, self.c)
+        coarse = self.levels[k + 1]
+        fc = restrict(lev, r, coarse)
+        fc = coarse.comp_mean(fc, self.sing[k + 1])
+        ec = self.vcycle(fc, k + 1)
+        e = e + prolong(coarse, ec, lev)
+        return self.smooth(k, e, f, self.nu2)
+
+
+def solvability_shift(lev, f, fd, comps):
+    """RHS shift so that on each listed component the sum of h^D f equals the
+    sum of h^(D-1) g over its boundary faces (the discrete compatibility
+    condition eq. velocity_disc_solvabilityCond, enforced on the right-hand
+    side; the data g is the outward normal derivative).  Returns the shifted
+    RHS and the defect of each component before the shift."""
+    hD = lev.h ** lev.dim
+    bsum = np.zeros(lev.ncomp)
+    for d in range(lev.dim):
+        for s in (0, 1):
+            end = lev.row_end(d, s)
+            if fd is not None:
+                np.add.at(bsum, lev.labels[end], fd[(d, s)][end] * lev.h ** (lev.dim - 1))
+    out = f.copy()
+    defects = []
+    for c in comps:
+        sel = lev.labels == c
+        defect = hD * f[sel].sum() - bsum[c]
+        defects.append(defect)
+        out[sel] -= defect / (sel.sum() * hD)
+    return out, defects
+
+
+def norm_inf(lev, a):
+    return float(np.abs(a[lev.mask]).max()) if lev.ncells else 0.0
+
+
+def solve(lev, f, op, c, fd=None, cfv=None, x0=None, nu1=2, nu2=2, smoother="jacobi",
+          omega=2.0 / 3.0, tol_rel=1e-10, tol_abs=0.0, max_cycles=50, shift=True, mg=None):
+    """Outer residual-correction loop in FP64:
+    r = f - A(x); s = ||r||_inf; e = V(r / s); x += s e; remove the mean of x
+    on every singular component; stop by the max-norm criterion above."""
+    mg = mg or MG(lev, op, c, nu1, nu2, smoother, omega)
+    sing = mg.sing[0]
+    defects = []
+    if shift and sing:
+        f, defects = solvability_shift(lev, f, fd, sing)
+    x = lev.zeros() if x0 is None else x0.copy()
+    hist = []
+    r = f - lev.apply(x, op, c, fd, cfv)
+    r0 = norm_inf(lev, r)
+    hist.append(r0)
+    target = max(tol_rel * r0, tol_abs)
+    cycles = 0
+    while hist[-1] > target and cycles < max_cycles:
+        r = lev.comp_mean(r, sing)
+        s = norm_inf(lev, r)
+        e = mg.vcycle(r / s)
+        x = x + s * e
+        x = lev.comp_mean(x, sing)
+        r = f - lev.apply(x, op, c, fd, cfv)
+        hist.append(norm_inf(lev, r))
+        cycles += 1
+    return x, {"cycles": cycles, "history": hist, "converged": hist[-1] <= target,
+               "defects": defects, "rhs": f}
+
+
+def direct_solve(lev, f, op, c, fd=None, cfv=None):
+    """Referee for tiny grids: x = M^{-1}(f - b) where A x = M x + b is the
+    affine operator assembled by probing; singular components bordered with
+    a zero-mean constraint, the RHS shifted for solvability first."""
+    sing = lev.singular_components(op)
+    if sing:
+        f, _ = solvability_shift(lev, f, fd, sing)
+    b = lev.apply(lev.zeros(), op, c, fd, cfv)
+    bot = Bottom(lev, op, c)
+    return bot.solve(f - b)
