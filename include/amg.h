@@ -1,0 +1,237 @@
+/*
+ * amg.h -- C ABI of the MI355X multigrid library for the fourth-order
+ * finite-volume Helmholtz and Poisson systems of a block-structured AMR
+ * hierarchy (Zhao & Zhang, arXiv 2506.02663).
+ *
+ * The operations follow the paper's statement of the problem:
+ *   - hierarchy, levels and boxes ............ Section 5.1, eqs. (grids), (AMRHier)
+ *   - operators (I - c L) and L .............. eq. (discreteOps c); (TLS-1..3) of
+ *                                              Section 6.5; c = gamma nu k, eq. (GePUP-IMEX)
+ *   - physical boundary conditions ........... eqs. (velBCHomoDiri5th), (Neumann5);
+ *                                              the assignment of Section 4
+ *   - coarse-fine conditions of a level ...... Definition 6.1, eq. (GePUP-localized)
+ *   - solvability per connected component .... eqs. (GePUP-localized-solvability-
+ *                                              condition), (velocity_disc_solvabilityCond)
+ *   - the multigrid solver ................... Section 6.5
+ *
+ * Conventions shared by every call.
+ *   Index space.  Level l has cell size h_l = h0 / ratio^l.  A box is given by
+ *   its inclusive corners lo/hi in level-l indices (eq. AMRHier); cell i spans
+ *   [i h_l, (i+1) h_l] in each direction.
+ *   Packed level buffer.  Every array of cell averages of a level (solution,
+ *   right-hand side, output of an operator) is ONE device buffer holding all
+ *   boxes of the level, each stored with two ghost layers on every side, x
+ *   fastest.  amg_box_info gives, per box, the element offset of its stored
+ *   corner (ghost index -2 in every direction) and its strides; the interior
+ *   cell (i,j,k) (0-based within the box) is at
+ *       offset + (i+2) stride[0] + (j+2) stride[1] + (k+2) stride[2].
+ *   Ghost entries are written by the library; the caller leaves them alone.
+ *   Face data.  One FP64 device buffer per level; for every box and every face
+ *   (d, side) a dense array over the face's cells (transverse directions in
+ *   increasing order, the first fastest) at the face_offset given by amg_box_info.  Entry
+ *   = face average of the Dirichlet value, or of the derivative along the
+ *   OUTWARD normal for Neumann, on faces that lie on the physical boundary or
+ *   (for AMG_CF_DIRICHLET / AMG_CF_NEUMANN levels) on the coarse-fine
+ *   interface.  Other entries are ignored.  NULL means all zero.
+ *   Ownership.  The caller owns every buffer it passes (device memory); the
+ *   library only reads inputs and writes outputs during the call, on the
+ *   given stream (a hipStream_t passed as void*, NULL = default stream).  The
+ *   library owns its workspace, allocated in amg_finalize and freed in
+ *   amg_destroy; nothing is allocated on the solve path.
+ *   Errors.  Every call returns AMG_OK (0) or a positive error code; the
+ *   message of the last error is amg_last_error(h).  A failed call leaves
+ *   outputs unspecified except where stated.
+ *   Threading.  One hierarchy object must not be used from two host threads
+ *   at once.  Results are bitwise reproducible for identical inputs on one
+ *   device (all reductions have a fixed order).
+ */
+#ifndef AMG_H
+#define AMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define AMG_OK 0
+#define AMG_EINVAL 1          /* bad argument */
+#define AMG_ELAYOUT 2         /* invalid box layout (overlap, nesting, alignment, size) */
+#define AMG_EUNSUPPORTED 3    /* valid but not supported (e.g. box too small) */
+#define AMG_ENOTCONVERGED 4   /* max_cycles reached; x holds the last iterate */
+#define AMG_ENONFINITE 5      /* NaN or Inf in a residual */
+#define AMG_ESOLVABILITY 6    /* Neumann defect above tolerance with enforcement off */
+#define AMG_EDEVICE 7         /* HIP runtime error */
+
+/* operator kinds (Section 6.5) */
+#define AMG_HELMHOLTZ 0 /* (I - c L), (TLS-2) */
+#define AMG_POISSON 1   /* L, (TLS-1) and (TLS-3) */
+
+/* boundary condition types */
+#define AMG_DIRICHLET 0
+#define AMG_NEUMANN 1
+
+/* coarse-fine modes of a level */
+#define AMG_CF_DIRICHLET 0 /* face averages given on the coarse-fine interface */
+#define AMG_CF_NEUMANN 1   /* outward normal derivatives given there */
+#define AMG_CF_INTERP 2    /* ghosts interpolated from level l-1 (composite solves) */
+
+/* smoothers */
+#define AMG_SMOOTH_JACOBI 0 /* weighted Jacobi, Section 6.5 */
+#define AMG_SMOOTH_RB 1     /* red-black: Jacobi within each colour of (sum of indices) mod 2 */
+
+/* precision modes */
+#define AMG_FP64 0  /* every step in FP64 */
+#define AMG_MIXED 1 /* FP32 V-cycle inside FP64 iterative refinement */
+
+/* data types of the step-level entry points */
+#define AMG_F64 0
+#define AMG_F32 1
+
+/* solvability modes for components with a constant null vector */
+#define AMG_SOLV_RHS_SHIFT 0 /* shift the right-hand side to satisfy the discrete condition */
+#define AMG_SOLV_OFF 1       /* do nothing; report the defect */
+
+#define AMG_MAX_HISTORY 128
+#define AMG_MAX_COMP 64
+
+typedef struct amg_hier amg_hier;
+
+typedef struct {
+  int32_t nboxes;
+  int32_t depths;      /* multigrid depths of this level (>= 1) */
+  int32_t ncomp;       /* face-connected components */
+  int32_t nsingular;   /* components with a constant null vector under the operator */
+  int64_t ncells;      /* interior cells */
+  int64_t nstored;     /* elements of the packed buffer */
+  int64_t nface;       /* elements of the face-data buffer */
+} amg_level_desc;
+
+typedef struct {
+  int32_t lo[3], hi[3];       /* inclusive corners (level indices; unused dims 0) */
+  int64_t offset;             /* element offset of the stored corner */
+  int64_t stride[3];          /* element strides (stride[0] = 1) */
+  int64_t face_offset[3][2];  /* element offset of each face's data */
+  int32_t comp;               /* component id */
+  int32_t singular;           /* 1 if that component is singular */
+} amg_box_desc;
+
+typedef struct {
+  int32_t nu1, nu2;      /* pre- and post-smoothing sweeps */
+  int32_t smoother;      /* AMG_SMOOTH_* */
+  int32_t precision;     /* AMG_FP64 or AMG_MIXED */
+  int32_t solvability;   /* AMG_SOLV_* */
+  int32_t max_cycles;
+  double omega;          /* weighted-Jacobi factor (2/3 in the paper) */
+  double tol_rel;        /* stop when ||r||_inf <= max(tol_rel ||r0||_inf, tol_abs) */
+  double tol_abs;
+} amg_solve_opts;
+
+typedef struct {
+  int32_t cycles;
+  int32_t converged;
+  double r0;                           /* ||f - A x0||_inf */
+  double rfinal;                       /* ||f - A x||_inf at return */
+  double history[AMG_MAX_HISTORY];     /* ||r||_inf after each cycle, history[0] = r0 */
+  int32_t ncomp;
+  double defect[AMG_MAX_COMP];         /* h^D sum f - h^(D-1) sum g per singular component, before the shift */
+} amg_solve_stats;
+
+/* Fills opts with the defaults: V(2,2), weighted Jacobi omega = 2/3, mixed
+ * precision, RHS shift, tol_rel 1e-10, tol_abs 0, 100 cycles. */
+void amg_default_opts(amg_solve_opts* opts);
+
+/* Creates a hierarchy of nlevels levels over the grid of base_cells[d] cells
+ * of size h0 in dimension dim (2 or 3) with refinement ratio `ratio` (2),
+ * eq. (grids).  *out receives the handle.  Errors: AMG_EINVAL. */
+int amg_create(int dim, const int32_t* base_cells, double h0, int ratio, int nlevels, amg_hier** out);
+
+/* Frees the hierarchy and all its device workspace.  NULL is a no-op. */
+int amg_destroy(amg_hier* h);
+
+/* Message of the last failed call (a string owned by h, valid until the next
+ * call on h). */
+const char* amg_last_error(const amg_hier* h);
+
+/* Sets the boxes of a level: lo and hi hold nboxes*dim inclusive corners
+ * (eq. AMRHier), copied by the call.  Level 0 must cover the whole grid
+ * unless the level is isolated. */
+int amg_set_level_boxes(amg_hier* h, int level, int nboxes, const int32_t* lo, const int32_t* hi);
+
+/* isolated != 0 makes every box of the level an independent domain with the
+ * physical conditions on all its faces (a batch of independent solves that
+ * share one launch per multigrid step). */
+int amg_set_isolated_boxes(amg_hier* h, int level, int isolated);
+
+/* Physical condition on the domain face (d, side), side 0 = low, 1 = high. */
+int amg_set_physical_bc(amg_hier* h, int d, int side, int type);
+
+/* Coarse-fine mode of a level > 0 (default AMG_CF_DIRICHLET). */
+int amg_set_cf_mode(amg_hier* h, int level, int mode);
+
+/* Operator: AMG_HELMHOLTZ (I - c L), c > 0, or AMG_POISSON L (c ignored). */
+int amg_set_operator(amg_hier* h, int kind, double c);
+
+/* Validates the layout (disjoint boxes inside the grid, proper refinement
+ * eq. (pBlock), boxes of at least 4 cells per side), labels components,
+ * builds the multigrid depths (a level is halved while every box has even
+ * corners and even sides of at least 8), the ghost, tile and bottom-solve
+ * tables, factors the bottom systems, and allocates the workspace.
+ * Errors: AMG_ELAYOUT, AMG_EUNSUPPORTED, AMG_EDEVICE. */
+int amg_finalize(amg_hier* h);
+
+int amg_level_info(const amg_hier* h, int level, amg_level_desc* out);
+
+/* Layout of box `box` of level `level` at multigrid depth `depth` (depth 0 is
+ * the level itself; deeper layouts serve the step-level entry points). */
+int amg_box_info(const amg_hier* h, int level, int depth, int box, amg_box_desc* out);
+int amg_depth_size(const amg_hier* h, int level, int depth, int64_t* nstored, int32_t* nboxes);
+
+/* Solves the level system A x = f on level `level` (lev_lo == lev_hi; the
+ * coarse-fine interface takes the level's face data).  x: initial guess on
+ * entry, solution on return, ghosts filled.  f, face_data as above.
+ * On AMG_ENOTCONVERGED x holds the last iterate and stats are valid. */
+int amg_solve(amg_hier* h, int lev_lo, int lev_hi, double* const* x, const double* const* f,
+              const double* const* face_data, const amg_solve_opts* opts, amg_solve_stats* stats,
+              void* stream);
+
+/* y = A x on level `level` (FP64), ghosts of x filled from face_data
+ * (homogeneous != 0: face data treated as zero).  x's ghosts are written. */
+int amg_apply_operator(amg_hier* h, int level, double* x, const double* face_data, double* y,
+                       int homogeneous, void* stream);
+
+/* ---- step-level entry points (one multigrid step on caller buffers in the
+ * packed layout of (level, depth); dtype AMG_F64 or AMG_F32).  They serve
+ * the per-step parity tests; amg_solve chains the same kernels. ---------- */
+
+/* Ghost fill of u: face data (FP64) at depth 0, or homogeneous if NULL. */
+int amg_fill_ghosts(amg_hier* h, int level, int depth, int dtype, void* u, const double* face_data, void* stream);
+
+/* r = f - A u on the interior; u's ghosts must be filled. */
+int amg_residual(amg_hier* h, int level, int depth, int dtype, const void* u, const void* f, void* r, void* stream);
+
+/* nsweeps homogeneous sweeps of the chosen smoother on u (ghosts refilled
+ * before each sweep and half-sweep); tmp is a second buffer of the same
+ * layout.  The result is in u. */
+int amg_smooth(amg_hier* h, int level, int depth, int dtype, int smoother, int nsweeps, double omega,
+               void* u, const void* f, void* tmp, void* stream);
+
+/* f_coarse (depth+1) = mean of the 2^D children of r (depth). */
+int amg_restrict(amg_hier* h, int level, int depth, int dtype, const void* r, void* f_coarse, void* stream);
+
+/* u (depth) += face-neighbour linear interpolation of e (depth+1); the first
+ * ghost layer of e must be filled (homogeneous). */
+int amg_prolong(amg_hier* h, int level, int depth, int dtype, const void* e_coarse, void* u, void* stream);
+
+/* Exact solve on the coarsest depth: e = A^-1 f (zero-mean per singular
+ * component). */
+int amg_bottom(amg_hier* h, int level, int dtype, const void* f, void* e, void* stream);
+
+/* One homogeneous V(nu1,nu2) cycle from e = 0 on the level: e ~= A^-1 f. */
+int amg_vcycle(amg_hier* h, int level, int dtype, const amg_solve_opts* opts, const void* f, void* e, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMG_H */

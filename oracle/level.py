@@ -218,13 +218,25 @@ class Level:
     # ------------------------------------------------------------------
     # multigrid coarsening
     def can_coarsen(self):
-        """Halve while every box has even corners and even sides of at least 8."""
+        """Halve while every box has even corners and even sides of at least 8,
+        and while two boxes that face each other across a gap along an axis
+        stay at least two cells apart after halving (a one-cell gap would let
+        the radius-2 stencil of one box read the other box directly, coupling
+        boxes that are not face-connected)."""
         if any(n % 2 for n in self.shape):
             return False
         for lo, hi in self.boxes:
             for l, u in zip(lo, hi):
                 if l % 2 or (u + 1) % 2 or (u - l + 1) < 8:
                     return False
+        for a, (alo, ahi) in enumerate(self.boxes):
+            for blo, bhi in self.boxes[a + 1:]:
+                for d in range(self.dim):
+                    if any(max(alo[e], blo[e]) > min(ahi[e], bhi[e]) for e in range(self.dim) if e != d):
+                        continue
+                    gap = max(blo[d] - ahi[d] - 1, alo[d] - bhi[d] - 1)
+                    if 0 < gap < 4:
+                        return False
         return True
 
     def coarsen(self):

@@ -1,0 +1,325 @@
+"""Python binding of the C ABI in include/amg.h (argument marshalling only).
+
+Every numerical step runs in the HIP library ``libamg.so``; this module
+passes device pointers of torch tensors and host arrays of box corners, and
+converts between dense per-box arrays and the packed level layout (pure
+indexing).  Importing it on a machine without the built library raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamg.so")
+
+OK, EINVAL, ELAYOUT, EUNSUPPORTED, ENOTCONVERGED, ENONFINITE, ESOLVABILITY, EDEVICE = range(8)
+HELMHOLTZ, POISSON = 0, 1
+DIRICHLET, NEUMANN = 0, 1
+CF_DIRICHLET, CF_NEUMANN, CF_INTERP = 0, 1, 2
+SMOOTH_JACOBI, SMOOTH_RB = 0, 1
+FP64, MIXED = 0, 1
+F64, F32 = 0, 1
+SOLV_RHS_SHIFT, SOLV_OFF = 0, 1
+MAX_HISTORY, MAX_COMP = 128, 64
+
+
+class LevelDesc(C.Structure):
+    _fields_ = [("nboxes", C.c_int32), ("depths", C.c_int32), ("ncomp", C.c_int32), ("nsingular", C.c_int32),
+                ("ncells", C.c_int64), ("nstored", C.c_int64), ("nface", C.c_int64)]
+
+
+class BoxDesc(C.Structure):
+    _fields_ = [("lo", C.c_int32 * 3), ("hi", C.c_int32 * 3), ("offset", C.c_int64), ("stride", C.c_int64 * 3),
+                ("face_offset", (C.c_int64 * 2) * 3), ("comp", C.c_int32), ("singular", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("smoother", C.c_int32), ("precision", C.c_int32),
+                ("solvability", C.c_int32), ("max_cycles", C.c_int32), ("omega", C.c_double),
+                ("tol_rel", C.c_double), ("tol_abs", C.c_double)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("converged", C.c_int32), ("r0", C.c_double), ("rfinal", C.c_double),
+                ("history", C.c_double * MAX_HISTORY), ("ncomp", C.c_int32), ("defect", C.c_double * MAX_COMP)]
+
+    def as_dict(self):
+        n = min(self.cycles + 1, MAX_HISTORY)
+        return {"cycles": self.cycles, "converged": bool(self.converged), "r0": self.r0, "rfinal": self.rfinal,
+                "history": list(self.history[:n]), "defects": list(self.defect[: self.ncomp])}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libamg.so is not built: run __graft_entry__.build() (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, dbl = C.c_void_p, C.c_int, C.c_double
+        L.amg_create.argtypes = [i32, C.POINTER(C.c_int32), dbl, i32, i32, C.POINTER(vp)]
+        L.amg_destroy.argtypes = [vp]
+        L.amg_last_error.argtypes = [vp]
+        L.amg_last_error.restype = C.c_char_p
+        L.amg_set_level_boxes.argtypes = [vp, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.amg_set_isolated_boxes.argtypes = [vp, i32, i32]
+        L.amg_set_physical_bc.argtypes = [vp, i32, i32, i32]
+        L.amg_set_cf_mode.argtypes = [vp, i32, i32]
+        L.amg_set_operator.argtypes = [vp, i32, dbl]
+        L.amg_finalize.argtypes = [vp]
+        L.amg_level_info.argtypes = [vp, i32, C.POINTER(LevelDesc)]
+        L.amg_box_info.argtypes = [vp, i32, i32, i32, C.POINTER(BoxDesc)]
+        L.amg_depth_size.argtypes = [vp, i32, i32, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+        L.amg_default_opts.argtypes = [C.POINTER(SolveOpts)]
+        L.amg_default_opts.restype = None
+        L.amg_solve.argtypes = [vp, i32, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveOpts),
+                                C.POINTER(SolveStats), vp]
+        L.amg_apply_operator.argtypes = [vp, i32, vp, vp, vp, i32, vp]
+        L.amg_fill_ghosts.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+        L.amg_residual.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
+        L.amg_smooth.argtypes = [vp, i32, i32, i32, i32, i32, dbl, vp, vp, vp, vp]
+        L.amg_restrict.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+        L.amg_prolong.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+        L.amg_bottom.argtypes = [vp, i32, i32, vp, vp, vp]
+        L.amg_vcycle.argtypes = [vp, i32, i32, C.POINTER(SolveOpts), vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+class AmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"amg error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_opts(**kw):
+    o = SolveOpts()
+    lib().amg_default_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Hierarchy:
+    """A box layout and operator; owns the library handle."""
+
+    def __init__(self, dim, base_cells, h0, nlevels=1, ratio=2):
+        self.dim = dim
+        h = C.c_void_p()
+        base = (C.c_int32 * dim)(*base_cells)
+        rc = lib().amg_create(dim, base, float(h0), ratio, nlevels, C.byref(h))
+        if rc:
+            raise AmgError(rc, "amg_create")
+        self.h = h
+        self._layout = {}
+
+    def close(self):
+        if self.h:
+            lib().amg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc:
+            raise AmgError(rc, lib().amg_last_error(self.h).decode())
+        return rc
+
+    # ---- layout ----
+    def set_level_boxes(self, level, boxes):
+        n = len(boxes)
+        lo = (C.c_int32 * (n * self.dim))(*[int(v) for b in boxes for v in b[0]])
+        hi = (C.c_int32 * (n * self.dim))(*[int(v) for b in boxes for v in b[1]])
+        self._check(lib().amg_set_level_boxes(self.h, level, n, lo, hi))
+
+    def set_isolated(self, level, flag=True):
+        self._check(lib().amg_set_isolated_boxes(self.h, level, int(flag)))
+
+    def set_physical_bc(self, d, side, kind):
+        self._check(lib().amg_set_physical_bc(self.h, d, side, kind))
+
+    def set_cf_mode(self, level, mode):
+        self._check(lib().amg_set_cf_mode(self.h, level, mode))
+
+    def set_operator(self, kind, c=0.0):
+        self._check(lib().amg_set_operator(self.h, kind, float(c)))
+
+    def finalize(self):
+        self._check(lib().amg_finalize(self.h))
+
+    def level_info(self, level=0):
+        d = LevelDesc()
+        self._check(lib().amg_level_info(self.h, level, C.byref(d)))
+        return d
+
+    def depth_size(self, level, depth):
+        n = C.c_int64()
+        nb = C.c_int32()
+        self._check(lib().amg_depth_size(self.h, level, depth, C.byref(n), C.byref(nb)))
+        return n.value, nb.value
+
+    def boxes(self, level=0, depth=0):
+        key = (level, depth)
+        if key not in self._layout:
+            _, nb = self.depth_size(level, depth)
+            out = []
+            for b in range(nb):
+                d = BoxDesc()
+                self._check(lib().amg_box_info(self.h, level, depth, b, C.byref(d)))
+                out.append({"lo": tuple(d.lo[: self.dim]), "hi": tuple(d.hi[: self.dim]), "offset": d.offset,
+                            "stride": tuple(d.stride[: self.dim]),
+                            "face_offset": [[d.face_offset[k][s] for s in (0, 1)] for k in range(self.dim)],
+                            "comp": d.comp, "singular": d.singular})
+            self._layout[key] = out
+        return self._layout[key]
+
+    # ---- dense <-> packed (pure indexing) ----
+    def _box_view(self, flat, b, ghosts=False):
+        n = [hi - lo + 1 for lo, hi in zip(b["lo"], b["hi"])]
+        shape = [m + 4 for m in n][::-1]  # (z, y, x) in memory order
+        size = int(np.prod(shape))
+        blk = flat[b["offset"]: b["offset"] + size].reshape(shape)
+        if ghosts:
+            return blk
+        return blk[tuple(slice(2, 2 + m) for m in n[::-1])]
+
+    def pack(self, level, depth, get, dtype=np.float64):
+        """Packed host array; get(b, box) returns the box's interior as an
+        array indexed [x, y(, z)]."""
+        n, _ = self.depth_size(level, depth)
+        flat = np.zeros(n, dtype=dtype)
+        for i, b in enumerate(self.boxes(level, depth)):
+            self._box_view(flat, b)[...] = np.asarray(get(i, b)).T
+        return flat
+
+    def unpack(self, level, depth, flat, ghosts=False):
+        """List of per-box arrays indexed [x, y(, z)] (with the two ghost
+        layers if ghosts=True)."""
+        flat = np.asarray(flat)
+        return [self._box_view(flat, b, ghosts).T.copy() for b in self.boxes(level, depth)]
+
+    def pack_faces(self, level, get):
+        """Face-data host array; get(b, box, d, s) returns the face's values
+        indexed by the transverse directions in increasing order."""
+        info = self.level_info(level)
+        flat = np.zeros(max(info.nface, 1))
+        for i, b in enumerate(self.boxes(level, 0)):
+            for d in range(self.dim):
+                for s in (0, 1):
+                    v = np.asarray(get(i, b, d, s), dtype=np.float64)
+                    off = b["face_offset"][d][s]
+                    # transverse directions in increasing order, the first fastest
+                    flat[off: off + v.size] = v.T.reshape(-1)
+        return flat
+
+    # ---- solve and steps (torch device tensors) ----
+    def _need(self, t, level, depth, name, dtypes=None):
+        """Host-side check that a tensor matches the packed layout the kernels
+        index (so no kernel is launched on a short or misplaced buffer)."""
+        import torch
+        if t is None:
+            raise ValueError(f"{name} is required")
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous device tensor")
+        if dtypes is not None and t.dtype not in dtypes:
+            raise ValueError(f"{name} has dtype {t.dtype}")
+        n = self.depth_size(level, depth)[0]
+        if t.numel() < n:
+            raise ValueError(f"{name} has {t.numel()} elements, the layout needs {n}")
+
+    def _need_faces(self, fd, level):
+        import torch
+        if fd is None:
+            return
+        if not fd.is_cuda or not fd.is_contiguous() or fd.dtype != torch.float64:
+            raise ValueError("face data must be a contiguous float64 device tensor")
+        if fd.numel() < self.level_info(level).nface:
+            raise ValueError("face data too short")
+
+    def solve(self, level, x, f, face_data=None, opts=None, stream=None):
+        import torch
+        self._need(x, level, 0, "x", (torch.float64,))
+        self._need(f, level, 0, "f", (torch.float64,))
+        self._need_faces(face_data, level)
+        o = opts or default_opts()
+        st = SolveStats()
+        xs = (C.c_void_p * (level + 1))()
+        fs = (C.c_void_p * (level + 1))()
+        ds = (C.c_void_p * (level + 1))()
+        xs[level] = x.data_ptr()
+        fs[level] = f.data_ptr()
+        ds[level] = face_data.data_ptr() if face_data is not None else None
+        rc = lib().amg_solve(self.h, level, level, xs, fs, ds, C.byref(o), C.byref(st), stream or _stream())
+        if rc and rc != ENOTCONVERGED:
+            self._check(rc)
+        out = st.as_dict()
+        out["status"] = rc
+        return out
+
+    def apply_operator(self, level, x, y, face_data=None, homogeneous=False):
+        import torch
+        self._need(x, level, 0, "x", (torch.float64,))
+        self._need(y, level, 0, "y", (torch.float64,))
+        self._need_faces(face_data, level)
+        self._check(lib().amg_apply_operator(self.h, level, _ptr(x), _ptr(face_data), _ptr(y), int(homogeneous),
+                                             _stream()))
+
+    @staticmethod
+    def _dt(t):
+        import torch
+        return F64 if t.dtype == torch.float64 else F32
+
+    def fill_ghosts(self, level, depth, u, face_data=None):
+        self._need(u, level, depth, "u")
+        self._need_faces(face_data, level)
+        self._check(lib().amg_fill_ghosts(self.h, level, depth, self._dt(u), _ptr(u), _ptr(face_data), _stream()))
+
+    def residual(self, level, depth, u, f, r):
+        for t, nm in ((u, "u"), (f, "f"), (r, "r")):
+            self._need(t, level, depth, nm, (u.dtype,))
+        self._check(lib().amg_residual(self.h, level, depth, self._dt(u), _ptr(u), _ptr(f), _ptr(r), _stream()))
+
+    def smooth(self, level, depth, u, f, tmp, smoother=SMOOTH_JACOBI, nsweeps=1, omega=2.0 / 3.0):
+        for t, nm in ((u, "u"), (f, "f"), (tmp, "tmp")):
+            self._need(t, level, depth, nm, (u.dtype,))
+        self._check(lib().amg_smooth(self.h, level, depth, self._dt(u), smoother, nsweeps, float(omega), _ptr(u),
+                                     _ptr(f), _ptr(tmp), _stream()))
+
+    def restrict(self, level, depth, r, fc):
+        self._need(r, level, depth, "r")
+        self._need(fc, level, depth + 1, "fc", (r.dtype,))
+        self._check(lib().amg_restrict(self.h, level, depth, self._dt(r), _ptr(r), _ptr(fc), _stream()))
+
+    def prolong(self, level, depth, ec, u):
+        self._need(u, level, depth, "u")
+        self._need(ec, level, depth + 1, "ec", (u.dtype,))
+        self._check(lib().amg_prolong(self.h, level, depth, self._dt(u), _ptr(ec), _ptr(u), _stream()))
+
+    def bottom(self, level, f, e):
+        last = self.level_info(level).depths - 1
+        self._need(f, level, last, "f")
+        self._need(e, level, last, "e", (f.dtype,))
+        self._check(lib().amg_bottom(self.h, level, self._dt(f), _ptr(f), _ptr(e), _stream()))
+
+    def vcycle(self, level, f, e, opts=None):
+        self._need(f, level, 0, "f")
+        self._need(e, level, 0, "e", (f.dtype,))
+        o = opts or default_opts()
+        self._check(lib().amg_vcycle(self.h, level, self._dt(f), C.byref(o), _ptr(f), _ptr(e), _stream()))

@@ -1,0 +1,155 @@
+// Internal structures of the multigrid library: the tables the host planner
+// builds once per layout and the kernels walk.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/amg.h"
+
+namespace amg {
+
+// ---- ghost kinds (per ghost layer of a face column) -------------------------
+// FILL_D / FILL_N: fifth-order fill from the row that ends at the face, eqs.
+// (velBCHomoDiri5th) / (Neumann5), with the face datum of that column.
+// EXCH: the ghost lies in another box of the same level; copy its value.
+// ZERO: coarse-fine interpolated ghost of a correction (homogeneous: 0).
+enum GhostKind : uint8_t { G_ZERO = 0, G_FILL_D = 1, G_FILL_N = 2, G_EXCH = 3 };
+
+// Column code read by the stencil kernels to fold the fill into the diagonal:
+// bits 0-1 = fill kind of layer 1 (0 none, 1 Dirichlet, 2 Neumann), bit 2 =
+// layer 2 is filled from the same row end.
+inline uint8_t column_code(uint8_t k1, uint8_t k2) {
+  uint8_t c = (k1 == G_FILL_D) ? 1 : (k1 == G_FILL_N) ? 2 : 0;
+  if (c && k2 == k1) c |= 4;
+  return c;
+}
+
+struct BoxD {              // one box at one multigrid depth
+  int64_t off;             // element offset of the stored corner (ghost -2,-2,-2)
+  int32_t n[3];            // interior cells per direction (1 for unused dims)
+  int32_t s[3];            // element strides
+  int32_t lo[3];           // global lower corner at this depth (colouring)
+  int32_t code_off[3][2];  // offset of each face's column codes
+  int32_t comp;            // component id
+  int32_t fine;            // index of the same box at depth-1 (-1 at depth 0)
+  int32_t coarse;          // index at depth+1, -1 if the box ends here
+  int32_t pad;
+};
+
+struct TileD {             // a tile of cells of one box
+  int32_t box, x0, y0, z0;
+};
+
+struct ChunkD {            // up to 64 consecutive ghost columns of one face
+  int64_t dst;             // element of the layer-1 ghost of the first column
+  int64_t src1, src2;      // exchange sources of layers 1 and 2 (first column)
+  int64_t fd;              // face-data element of the first column (-1: none)
+  int32_t cstride;         // element stride between consecutive columns
+  int32_t sstride1, sstride2;
+  int32_t nstride;         // outward normal stride (elements, signed)
+  int32_t count;           // columns in the chunk (<= 64)
+  int32_t box;
+  uint8_t kind1, kind2;
+  uint8_t pad[6];
+};
+
+struct BottomGroupD {      // systems sharing one dense inverse
+  int64_t mat;             // offset of the n x n inverse (column-major) in the matrix pool
+  int64_t idx;             // offset of ninst*n element indices in the index pool
+  int32_t n, ninst;
+};
+
+// ---- host-side description ---------------------------------------------------
+struct Box {
+  int lo[3], hi[3];
+  int n(int d) const { return hi[d] - lo[d] + 1; }
+};
+
+struct FaceCols {          // classification of the ghost columns of one box face
+  std::vector<uint8_t> k1, k2;
+  std::vector<int32_t> src1, src2;  // source box of layers 1 and 2 (-1 none)
+};
+
+struct Depth {
+  double h = 0;
+  std::vector<Box> boxes;
+  std::vector<BoxD> boxd;
+  std::vector<int32_t> level_box;    // index of the box at depth 0
+  std::vector<FaceCols> faces;       // [box*6 + d*2 + side]
+  std::vector<uint8_t> codes;
+  std::vector<ChunkD> chunks;
+  std::vector<TileD> tiles;          // all boxes at this depth
+  std::vector<TileD> stiles;         // boxes that smooth at this depth (not at their bottom)
+  std::vector<int32_t> tile_comp_ptr, tile_comp_idx;   // CSR: tiles of each component
+  std::vector<int32_t> chunk_comp_ptr, chunk_comp_idx; // CSR: chunks of each component
+  std::vector<int32_t> bottom_boxes; // boxes solved exactly at this depth
+  std::vector<BottomGroupD> groups;
+  int64_t nstored = 0;
+  // device copies
+  BoxD* d_box = nullptr;
+  uint8_t* d_codes = nullptr;
+  ChunkD* d_chunks = nullptr;
+  TileD* d_tiles = nullptr;
+  TileD* d_stiles = nullptr;
+  int32_t *d_tc_ptr = nullptr, *d_tc_idx = nullptr, *d_cc_ptr = nullptr, *d_cc_idx = nullptr;
+  BottomGroupD* d_groups = nullptr;
+  // work buffers (FP64 and FP32): correction, right-hand side, second buffer
+  double *e64 = nullptr, *f64 = nullptr, *t64 = nullptr;
+  float *e32 = nullptr, *f32 = nullptr, *t32 = nullptr;
+};
+
+struct Level {
+  std::vector<Box> boxes;
+  bool isolated = false;
+  int cf_mode = AMG_CF_DIRICHLET;
+  std::vector<Depth> depths;
+  std::vector<int32_t> box_comp;
+  std::vector<int32_t> comp_singular;
+  std::vector<int64_t> comp_cells;
+  std::vector<int64_t> face_off;     // [box*6 + d*2 + side] element offset of face data
+  int64_t nface = 0;
+  int ncomp = 0, nsingular = 0;
+  int64_t ncells = 0;
+  // device
+  double* d_mat = nullptr;
+  int64_t* d_idx = nullptr;
+  double* r64 = nullptr;     // outer residual
+  double* fsh = nullptr;     // right-hand side after the solvability shift
+  double* partial = nullptr; // tile partials (max over all depth-0 sizes)
+  double* comp_sum = nullptr;
+  int32_t* d_comp_flag = nullptr;  // 1 on singular components
+  double* d_comp_cnt = nullptr;    // cells per component at each depth [depth*ncomp + c]
+  double* d_delta = nullptr;       // per-component shift
+  double* d_bsum = nullptr;        // per-component sum of Neumann face data
+  double* d_defect = nullptr;      // per-component solvability defect
+  double* scal = nullptr;    // device scalars: norms history, scale
+  double* h_scal = nullptr;  // pinned host mirror
+};
+
+}  // namespace amg
+
+struct amg_hier {
+  int dim = 2;
+  int32_t base[3] = {1, 1, 1};
+  double h0 = 1;
+  int ratio = 2;
+  int nlevels = 1;
+  int phys_bc[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  int op = AMG_HELMHOLTZ;
+  double c = 0;
+  bool finalized = false;
+  hipStream_t own = nullptr;  // used when the caller passes no stream
+  std::vector<amg::Level> levels;
+  std::string err;
+};
+
+namespace amg {
+// planner (layout.cpp)
+int plan_level(amg_hier* H, int l, std::string& err);
+// host assembly of the coarsest operator and its inverse (bottom.cpp)
+int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats, std::vector<int64_t>& idx);
+}  // namespace amg

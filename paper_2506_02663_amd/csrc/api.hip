@@ -1,0 +1,657 @@
+// C ABI entry points (include/amg.h) and the solver driver: the V-cycle of
+// Section 6.5 on the multigrid depths of one level, inside an outer
+// residual-correction loop (FP64, or FP32 V-cycles inside FP64 iterative
+// refinement), with the per-component solvability shift and mean removal.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "amg_internal.h"
+#include "kernels.h"
+
+using namespace amg;
+
+namespace {
+
+enum { S_NORM = 0, S_ONE = 1, S_COUNT = 16 };
+
+#define HIPCHK(expr)                                                      \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess) {                                               \
+      H->err = std::string(#expr) + ": " + hipGetErrorString(e_);          \
+      return AMG_EDEVICE;                                                 \
+    }                                                                     \
+  } while (0)
+
+int fail(amg_hier* H, int code, const std::string& msg) {
+  if (H) H->err = msg;
+  return code;
+}
+
+template <typename T>
+int upload(amg_hier* H, T** dst, const std::vector<T>& v) {
+  size_t n = std::max<size_t>(v.size(), 1);
+  HIPCHK(hipMalloc((void**)dst, n * sizeof(T)));
+  if (!v.empty()) HIPCHK(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return AMG_OK;
+}
+
+template <typename T>
+int zalloc(amg_hier* H, T** dst, size_t n) {
+  n = std::max<size_t>(n, 1);
+  HIPCHK(hipMalloc((void**)dst, n * sizeof(T)));
+  HIPCHK(hipMemset(*dst, 0, n * sizeof(T)));
+  return AMG_OK;
+}
+
+#define TRY(expr)               \
+  do {                          \
+    int rc_ = (expr);           \
+    if (rc_ != AMG_OK) return rc_; \
+  } while (0)
+
+// A u = alpha u + beta * (sum of the 1-D stencils), eq. (discreteOps c)
+template <typename T>
+void coefs(const amg_hier* H, const Depth& D, T& alpha, T& beta) {
+  const double K = 1.0 / (12.0 * D.h * D.h);
+  if (H->op == AMG_HELMHOLTZ) {
+    alpha = T(1);
+    beta = T(-H->c * K);
+  } else {
+    alpha = T(0);
+    beta = T(K);
+  }
+}
+
+template <typename T>
+struct Bufs;
+template <>
+struct Bufs<double> {
+  static double* e(Depth& D) { return D.e64; }
+  static double* f(Depth& D) { return D.f64; }
+  static double* t(Depth& D) { return D.t64; }
+};
+template <>
+struct Bufs<float> {
+  static float* e(Depth& D) { return D.e32; }
+  static float* f(Depth& D) { return D.f32; }
+  static float* t(Depth& D) { return D.t32; }
+};
+
+// Struct holding one call's view of a level
+struct Run {
+  amg_hier* H;
+  Level* L;
+  int dim;
+  hipStream_t st;
+};
+
+// Subtract the per-component mean on every singular component (depth k).
+template <typename T>
+void remove_mean(const Run& R, int k, T* a) {
+  Level& L = *R.L;
+  if (!L.nsingular) return;
+  Depth& D = L.depths[k];
+  launch_tile_sum<T>(R.dim, D, a, L.partial, R.st);
+  launch_comp_sum(L.partial, D.d_tc_ptr, D.d_tc_idx, L.ncomp, L.comp_sum, R.st);
+  launch_comp_delta(L.comp_sum, nullptr, L.d_comp_flag, L.d_comp_cnt + (size_t)k * L.ncomp, L.ncomp, 1.0, 0.0,
+                    L.d_delta, nullptr, R.st);
+  launch_comp_shift<T>(R.dim, D, a, L.d_delta, R.st);
+}
+
+// nsweeps homogeneous sweeps at depth k; `cur` holds the iterate (zero if
+// from_zero), `oth` is the second buffer; both may be swapped.
+template <typename T>
+void smooth(const Run& R, int k, int smoother, int nsweeps, double omega, bool from_zero, T*& cur, T*& oth,
+            const T* f) {
+  Depth& D = R.L->depths[k];
+  T alpha, beta;
+  coefs<T>(R.H, D, alpha, beta);
+  if (nsweeps <= 0) {
+    if (from_zero) launch_zero<T>(cur, D.nstored, R.st);
+    return;
+  }
+  if (smoother == AMG_SMOOTH_JACOBI) {
+    for (int s = 0; s < nsweeps; ++s) {
+      if (s == 0 && from_zero) {
+        launch_jacobi<T>(R.dim, D, nullptr, f, cur, alpha, beta, (T)omega, true, R.st);
+        continue;
+      }
+      launch_fill<T>(D, cur, nullptr, R.st);
+      launch_jacobi<T>(R.dim, D, cur, f, oth, alpha, beta, (T)omega, false, R.st);
+      std::swap(cur, oth);
+    }
+  } else {
+    for (int s = 0; s < nsweeps; ++s)
+      for (int col = 0; col < 2; ++col) {
+        if (s == 0 && col == 0 && from_zero) {
+          launch_rb<T>(R.dim, D, nullptr, f, cur, alpha, beta, 0, true, R.st);
+          continue;
+        }
+        launch_fill<T>(D, cur, nullptr, R.st);
+        launch_rb<T>(R.dim, D, cur, f, oth, alpha, beta, col, false, R.st);
+        std::swap(cur, oth);
+      }
+  }
+}
+
+// One homogeneous V-cycle from e = 0; f0 is the depth-0 right-hand side, e0
+// and t0 the two depth-0 buffers.  Returns the buffer that holds e.
+template <typename T>
+T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0) {
+  Level& L = *R.L;
+  const int K = (int)L.depths.size();
+  std::vector<T*> cur(K), oth(K);
+  std::vector<const T*> f(K);
+  for (int k = 0; k < K; ++k) {
+    cur[k] = k ? Bufs<T>::e(L.depths[k]) : e0;
+    oth[k] = k ? Bufs<T>::t(L.depths[k]) : t0;
+    f[k] = k ? Bufs<T>::f(L.depths[k]) : f0;
+  }
+  for (int k = 0; k < K; ++k) {
+    Depth& D = L.depths[k];
+    // boxes that end here: exact solve, written to both buffers of the depth
+    if (!D.groups.empty()) {
+      launch_bottom<T>(D, L.d_mat, L.d_idx, f[k], cur[k], R.st);
+      launch_bottom<T>(D, L.d_mat, L.d_idx, f[k], oth[k], R.st);
+    }
+    if (k + 1 >= K || D.stiles.empty()) break;
+    smooth<T>(R, k, o.smoother, o.nu1, o.omega, true, cur[k], oth[k], f[k]);
+    T alpha, beta;
+    coefs<T>(R.H, D, alpha, beta);
+    launch_fill<T>(D, cur[k], nullptr, R.st);
+    launch_resid_restrict<T>(R.dim, D, L.depths[k + 1], cur[k], f[k], Bufs<T>::f(L.depths[k + 1]), alpha, beta, R.st);
+    remove_mean<T>(R, k + 1, Bufs<T>::f(L.depths[k + 1]));
+  }
+  for (int k = K - 2; k >= 0; --k) {
+    Depth& D = L.depths[k];
+    if (D.stiles.empty()) continue;
+    launch_fill<T>(L.depths[k + 1], cur[k + 1], nullptr, R.st);
+    launch_prolong<T>(R.dim, D, L.depths[k + 1], cur[k + 1], cur[k], R.st);
+    smooth<T>(R, k, o.smoother, o.nu2, o.omega, false, cur[k], oth[k], f[k]);
+  }
+  return cur[0];
+}
+
+bool check_level(amg_hier* H, int level) {
+  if (!H) return false;
+  if (!H->finalized) {
+    H->err = "amg_finalize has not been called";
+    return false;
+  }
+  if (level < 0 || level >= H->nlevels) {
+    H->err = "level out of range";
+    return false;
+  }
+  return true;
+}
+
+hipStream_t stream_of(amg_hier* H, void* s) { return s ? (hipStream_t)s : H->own; }
+
+void free_level(amg::Level& L) {
+  for (auto& D : L.depths) {
+    for (void* p : {(void*)D.d_box, (void*)D.d_codes, (void*)D.d_chunks, (void*)D.d_tiles, (void*)D.d_stiles,
+                    (void*)D.d_tc_ptr, (void*)D.d_tc_idx, (void*)D.d_cc_ptr, (void*)D.d_cc_idx, (void*)D.d_groups,
+                    (void*)D.e64, (void*)D.f64, (void*)D.t64, (void*)D.e32, (void*)D.f32, (void*)D.t32})
+      if (p) (void)hipFree(p);
+  }
+  for (void* p : {(void*)L.d_mat, (void*)L.d_idx, (void*)L.r64, (void*)L.fsh, (void*)L.partial, (void*)L.comp_sum,
+                  (void*)L.scal, (void*)L.d_comp_flag, (void*)L.d_comp_cnt, (void*)L.d_delta, (void*)L.d_bsum,
+                  (void*)L.d_defect})
+    if (p) (void)hipFree(p);
+  if (L.h_scal) (void)hipHostFree(L.h_scal);
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+void amg_default_opts(amg_solve_opts* o) {
+  if (!o) return;
+  o->nu1 = 2;
+  o->nu2 = 2;
+  o->smoother = AMG_SMOOTH_JACOBI;
+  o->precision = AMG_MIXED;
+  o->solvability = AMG_SOLV_RHS_SHIFT;
+  o->max_cycles = 100;
+  o->omega = 2.0 / 3.0;
+  o->tol_rel = 1e-10;
+  o->tol_abs = 0.0;
+}
+
+int amg_create(int dim, const int32_t* base_cells, double h0, int ratio, int nlevels, amg_hier** out) {
+  if (!out) return AMG_EINVAL;
+  *out = nullptr;
+  if ((dim != 2 && dim != 3) || !base_cells || !(h0 > 0) || ratio != 2 || nlevels < 1 || nlevels > 16)
+    return AMG_EINVAL;
+  for (int d = 0; d < dim; ++d)
+    if (base_cells[d] < 4) return AMG_EINVAL;
+  amg_hier* H = new amg_hier();
+  H->dim = dim;
+  for (int d = 0; d < dim; ++d) H->base[d] = base_cells[d];
+  H->h0 = h0;
+  H->ratio = ratio;
+  H->nlevels = nlevels;
+  H->levels.resize(nlevels);
+  *out = H;
+  return AMG_OK;
+}
+
+int amg_destroy(amg_hier* H) {
+  if (!H) return AMG_OK;
+  for (auto& L : H->levels) free_level(L);
+  if (H->own) (void)hipStreamDestroy(H->own);
+  delete H;
+  return AMG_OK;
+}
+
+const char* amg_last_error(const amg_hier* H) { return H ? H->err.c_str() : "null handle"; }
+
+int amg_set_level_boxes(amg_hier* H, int level, int nboxes, const int32_t* lo, const int32_t* hi) {
+  if (!H) return AMG_EINVAL;
+  if (H->finalized) return fail(H, AMG_EINVAL, "layout is final");
+  if (level < 0 || level >= H->nlevels || nboxes < 0 || (nboxes && (!lo || !hi)))
+    return fail(H, AMG_EINVAL, "bad level or box arrays");
+  auto& B = H->levels[level].boxes;
+  B.assign(nboxes, Box());
+  for (int b = 0; b < nboxes; ++b)
+    for (int d = 0; d < 3; ++d) {
+      B[b].lo[d] = d < H->dim ? lo[b * H->dim + d] : 0;
+      B[b].hi[d] = d < H->dim ? hi[b * H->dim + d] : 0;
+    }
+  return AMG_OK;
+}
+
+int amg_set_isolated_boxes(amg_hier* H, int level, int isolated) {
+  if (!H) return AMG_EINVAL;
+  if (H->finalized) return fail(H, AMG_EINVAL, "layout is final");
+  if (level < 0 || level >= H->nlevels) return fail(H, AMG_EINVAL, "level out of range");
+  H->levels[level].isolated = isolated != 0;
+  return AMG_OK;
+}
+
+int amg_set_physical_bc(amg_hier* H, int d, int side, int type) {
+  if (!H) return AMG_EINVAL;
+  if (H->finalized) return fail(H, AMG_EINVAL, "layout is final");
+  if (d < 0 || d >= H->dim || side < 0 || side > 1 || (type != AMG_DIRICHLET && type != AMG_NEUMANN))
+    return fail(H, AMG_EINVAL, "bad boundary condition");
+  H->phys_bc[d][side] = type;
+  return AMG_OK;
+}
+
+int amg_set_cf_mode(amg_hier* H, int level, int mode) {
+  if (!H) return AMG_EINVAL;
+  if (H->finalized) return fail(H, AMG_EINVAL, "layout is final");
+  if (level < 1 || level >= H->nlevels || mode < AMG_CF_DIRICHLET || mode > AMG_CF_INTERP)
+    return fail(H, AMG_EINVAL, "bad coarse-fine mode");
+  H->levels[level].cf_mode = mode;
+  return AMG_OK;
+}
+
+int amg_set_operator(amg_hier* H, int kind, double c) {
+  if (!H) return AMG_EINVAL;
+  if (H->finalized) return fail(H, AMG_EINVAL, "layout is final");
+  if (kind == AMG_HELMHOLTZ && !(c > 0)) return fail(H, AMG_EINVAL, "Helmholtz needs c > 0");
+  if (kind != AMG_HELMHOLTZ && kind != AMG_POISSON) return fail(H, AMG_EINVAL, "bad operator");
+  H->op = kind;
+  H->c = kind == AMG_HELMHOLTZ ? c : 0.0;
+  return AMG_OK;
+}
+
+int amg_finalize(amg_hier* H) {
+  if (!H) return AMG_EINVAL;
+  if (H->finalized) return fail(H, AMG_EINVAL, "already final");
+  HIPCHK(hipStreamCreate(&H->own));
+  for (int l = 0; l < H->nlevels; ++l) {
+    Level& L = H->levels[l];
+    if (L.boxes.empty()) return fail(H, AMG_ELAYOUT, "level " + std::to_string(l) + " has no boxes");
+    std::string err;
+    int rc = plan_level(H, l, err);
+    if (rc != AMG_OK) return fail(H, rc, err);
+    std::vector<double> mats;
+    std::vector<int64_t> idx;
+    rc = build_bottom(H, l, err, mats, idx);
+    if (rc != AMG_OK) return fail(H, rc, err);
+    TRY(upload(H, &L.d_mat, mats));
+    TRY(upload(H, &L.d_idx, idx));
+    size_t maxpart = 1;
+    for (auto& D : L.depths) {
+      TRY(upload(H, &D.d_box, D.boxd));
+      TRY(upload(H, &D.d_codes, D.codes));
+      TRY(upload(H, &D.d_chunks, D.chunks));
+      TRY(upload(H, &D.d_tiles, D.tiles));
+      TRY(upload(H, &D.d_stiles, D.stiles));
+      TRY(upload(H, &D.d_tc_ptr, D.tile_comp_ptr));
+      TRY(upload(H, &D.d_tc_idx, D.tile_comp_idx));
+      TRY(upload(H, &D.d_cc_ptr, D.chunk_comp_ptr));
+      TRY(upload(H, &D.d_cc_idx, D.chunk_comp_idx));
+      TRY(upload(H, &D.d_groups, D.groups));
+      TRY(zalloc(H, &D.e64, D.nstored));
+      TRY(zalloc(H, &D.f64, D.nstored));
+      TRY(zalloc(H, &D.t64, D.nstored));
+      TRY(zalloc(H, &D.e32, D.nstored));
+      TRY(zalloc(H, &D.f32, D.nstored));
+      TRY(zalloc(H, &D.t32, D.nstored));
+      maxpart = std::max(maxpart, std::max(D.tiles.size(), D.chunks.size()));
+    }
+    TRY(zalloc(H, &L.r64, L.depths[0].nstored));
+    TRY(zalloc(H, &L.fsh, L.depths[0].nstored));
+    TRY(zalloc(H, &L.partial, maxpart));
+    TRY(zalloc(H, &L.comp_sum, L.ncomp));
+    TRY(zalloc(H, &L.d_delta, L.ncomp));
+    TRY(zalloc(H, &L.d_bsum, L.ncomp));
+    TRY(zalloc(H, &L.d_defect, L.ncomp));
+    TRY(upload(H, &L.d_comp_flag, L.comp_singular));
+    std::vector<double> cnt((size_t)L.depths.size() * L.ncomp);
+    for (size_t k = 0; k < L.depths.size(); ++k)
+      for (int c = 0; c < L.ncomp; ++c)
+        cnt[k * L.ncomp + c] = (double)L.comp_cells[c] / std::pow(2.0, (double)(H->dim * k));
+    TRY(upload(H, &L.d_comp_cnt, cnt));
+    std::vector<double> sc(S_COUNT, 0.0);
+    sc[S_ONE] = 1.0;
+    TRY(upload(H, &L.scal, sc));
+    HIPCHK(hipHostMalloc((void**)&L.h_scal, S_COUNT * sizeof(double), hipHostMallocDefault));
+  }
+  H->finalized = true;
+  return AMG_OK;
+}
+
+int amg_level_info(const amg_hier* Hc, int level, amg_level_desc* out) {
+  amg_hier* H = const_cast<amg_hier*>(Hc);
+  if (!out || !check_level(H, level)) return AMG_EINVAL;
+  const Level& L = H->levels[level];
+  out->nboxes = (int32_t)L.boxes.size();
+  out->depths = (int32_t)L.depths.size();
+  out->ncomp = L.ncomp;
+  out->nsingular = L.nsingular;
+  out->ncells = L.ncells;
+  out->nstored = L.depths[0].nstored;
+  out->nface = L.nface;
+  return AMG_OK;
+}
+
+int amg_depth_size(const amg_hier* Hc, int level, int depth, int64_t* nstored, int32_t* nboxes) {
+  amg_hier* H = const_cast<amg_hier*>(Hc);
+  if (!check_level(H, level)) return AMG_EINVAL;
+  const Level& L = H->levels[level];
+  if (depth < 0 || depth >= (int)L.depths.size()) return fail(H, AMG_EINVAL, "depth out of range");
+  if (nstored) *nstored = L.depths[depth].nstored;
+  if (nboxes) *nboxes = (int32_t)L.depths[depth].boxes.size();
+  return AMG_OK;
+}
+
+int amg_box_info(const amg_hier* Hc, int level, int depth, int box, amg_box_desc* out) {
+  amg_hier* H = const_cast<amg_hier*>(Hc);
+  if (!out || !check_level(H, level)) return AMG_EINVAL;
+  const Level& L = H->levels[level];
+  if (depth < 0 || depth >= (int)L.depths.size()) return fail(H, AMG_EINVAL, "depth out of range");
+  const Depth& D = L.depths[depth];
+  if (box < 0 || box >= (int)D.boxes.size()) return fail(H, AMG_EINVAL, "box out of range");
+  memset(out, 0, sizeof *out);
+  const BoxD& X = D.boxd[box];
+  for (int d = 0; d < 3; ++d) {
+    out->lo[d] = D.boxes[box].lo[d];
+    out->hi[d] = D.boxes[box].hi[d];
+    out->stride[d] = X.s[d];
+    for (int s = 0; s < 2; ++s)
+      out->face_offset[d][s] = (depth == 0 && d < H->dim) ? L.face_off[D.level_box[box] * 6 + d * 2 + s] : -1;
+  }
+  if (H->dim == 2) out->stride[2] = 0;
+  out->offset = X.off;
+  out->comp = X.comp;
+  out->singular = L.comp_singular[X.comp];
+  return AMG_OK;
+}
+
+int amg_apply_operator(amg_hier* H, int level, double* x, const double* face_data, double* y, int homogeneous,
+                       void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!x || !y) return fail(H, AMG_EINVAL, "bad arguments");
+  Level& L = H->levels[level];
+  Depth& D = L.depths[0];
+  hipStream_t st = stream_of(H, stream);
+  double alpha, beta;
+  coefs<double>(H, D, alpha, beta);
+  launch_fill<double>(D, x, homogeneous ? nullptr : face_data, st);
+  launch_residual<double>(H->dim, D, true, x, nullptr, y, alpha, beta, nullptr, st);
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_fill_ghosts(amg_hier* H, int level, int depth, int dtype, void* u, const double* face_data, void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!u) return fail(H, AMG_EINVAL, "bad arguments");
+  Level& L = H->levels[level];
+  if (depth < 0 || depth >= (int)L.depths.size()) return fail(H, AMG_EINVAL, "depth out of range");
+  if (depth > 0 && face_data) return fail(H, AMG_EINVAL, "face data only at depth 0");
+  hipStream_t st = stream_of(H, stream);
+  if (dtype == AMG_F64)
+    launch_fill<double>(L.depths[depth], (double*)u, face_data, st);
+  else
+    launch_fill<float>(L.depths[depth], (float*)u, face_data, st);
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_residual(amg_hier* H, int level, int depth, int dtype, const void* u, const void* f, void* r, void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!u || !r) return fail(H, AMG_EINVAL, "bad arguments");
+  Level& L = H->levels[level];
+  if (depth < 0 || depth >= (int)L.depths.size()) return fail(H, AMG_EINVAL, "depth out of range");
+  hipStream_t st = stream_of(H, stream);
+  Depth& D = L.depths[depth];
+  if (dtype == AMG_F64) {
+    double a, b;
+    coefs<double>(H, D, a, b);
+    launch_residual<double>(H->dim, D, true, (const double*)u, (const double*)f, (double*)r, a, b, nullptr, st);
+  } else {
+    float a, b;
+    coefs<float>(H, D, a, b);
+    launch_residual<float>(H->dim, D, true, (const float*)u, (const float*)f, (float*)r, a, b, nullptr, st);
+  }
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_smooth(amg_hier* H, int level, int depth, int dtype, int smoother, int nsweeps, double omega, void* u,
+               const void* f, void* tmp, void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!u || !f || !tmp) return fail(H, AMG_EINVAL, "bad arguments");
+  Level& L = H->levels[level];
+  if (depth < 0 || depth >= (int)L.depths.size()) return fail(H, AMG_EINVAL, "depth out of range");
+  if (smoother != AMG_SMOOTH_JACOBI && smoother != AMG_SMOOTH_RB) return fail(H, AMG_EINVAL, "bad smoother");
+  Run R{H, &L, H->dim, stream_of(H, stream)};
+  const size_t bytes = L.depths[depth].nstored * (dtype == AMG_F64 ? 8 : 4);
+  if (dtype == AMG_F64) {
+    double *cur = (double*)u, *oth = (double*)tmp;
+    smooth<double>(R, depth, smoother, nsweeps, omega, false, cur, oth, (const double*)f);
+    if (cur != u) HIPCHK(hipMemcpyAsync(u, cur, bytes, hipMemcpyDeviceToDevice, R.st));
+  } else {
+    float *cur = (float*)u, *oth = (float*)tmp;
+    smooth<float>(R, depth, smoother, nsweeps, omega, false, cur, oth, (const float*)f);
+    if (cur != u) HIPCHK(hipMemcpyAsync(u, cur, bytes, hipMemcpyDeviceToDevice, R.st));
+  }
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_restrict(amg_hier* H, int level, int depth, int dtype, const void* r, void* fc, void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!r || !fc) return fail(H, AMG_EINVAL, "bad arguments");
+  Level& L = H->levels[level];
+  if (depth < 0 || depth + 1 >= (int)L.depths.size()) return fail(H, AMG_EINVAL, "depth out of range");
+  hipStream_t st = stream_of(H, stream);
+  if (dtype == AMG_F64)
+    launch_restrict<double>(H->dim, L.depths[depth], L.depths[depth + 1], (const double*)r, (double*)fc, st);
+  else
+    launch_restrict<float>(H->dim, L.depths[depth], L.depths[depth + 1], (const float*)r, (float*)fc, st);
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_prolong(amg_hier* H, int level, int depth, int dtype, const void* ec, void* u, void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!ec || !u) return fail(H, AMG_EINVAL, "bad arguments");
+  Level& L = H->levels[level];
+  if (depth < 0 || depth + 1 >= (int)L.depths.size()) return fail(H, AMG_EINVAL, "depth out of range");
+  hipStream_t st = stream_of(H, stream);
+  if (dtype == AMG_F64)
+    launch_prolong<double>(H->dim, L.depths[depth], L.depths[depth + 1], (const double*)ec, (double*)u, st);
+  else
+    launch_prolong<float>(H->dim, L.depths[depth], L.depths[depth + 1], (const float*)ec, (float*)u, st);
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_bottom(amg_hier* H, int level, int dtype, const void* f, void* e, void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!f || !e) return fail(H, AMG_EINVAL, "bad arguments");
+  Level& L = H->levels[level];
+  if (L.isolated && L.depths.size() > 1) {
+    for (size_t k = 0; k + 1 < L.depths.size(); ++k)
+      if (!L.depths[k].groups.empty()) return fail(H, AMG_EUNSUPPORTED, "boxes of this level end at several depths");
+  }
+  Depth& D = L.depths.back();
+  hipStream_t st = stream_of(H, stream);
+  if (dtype == AMG_F64)
+    launch_bottom<double>(D, L.d_mat, L.d_idx, (const double*)f, (double*)e, st);
+  else
+    launch_bottom<float>(D, L.d_mat, L.d_idx, (const float*)f, (float*)e, st);
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_vcycle(amg_hier* H, int level, int dtype, const amg_solve_opts* opts, const void* f, void* e, void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!f || !e) return fail(H, AMG_EINVAL, "bad arguments");
+  amg_solve_opts o;
+  amg_default_opts(&o);
+  if (opts) o = *opts;
+  Level& L = H->levels[level];
+  Run R{H, &L, H->dim, stream_of(H, stream)};
+  Depth& D0 = L.depths[0];
+  if (dtype == AMG_F64) {
+    double* res = vcycle<double>(R, o, (const double*)f, (double*)e, D0.t64);
+    if (res != e) HIPCHK(hipMemcpyAsync(e, res, D0.nstored * 8, hipMemcpyDeviceToDevice, R.st));
+  } else {
+    float* res = vcycle<float>(R, o, (const float*)f, (float*)e, D0.t32);
+    if (res != e) HIPCHK(hipMemcpyAsync(e, res, D0.nstored * 4, hipMemcpyDeviceToDevice, R.st));
+  }
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const double* const* f,
+              const double* const* face_data, const amg_solve_opts* opts, amg_solve_stats* stats, void* stream) {
+  if (!check_level(H, lev_lo)) return AMG_EINVAL;
+  if (!x || !f) return fail(H, AMG_EINVAL, "bad arguments");
+  if (lev_hi != lev_lo) return fail(H, AMG_EUNSUPPORTED, "composite solves are not available in this build");
+  amg_solve_opts o;
+  amg_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.nu1 < 0 || o.nu2 < 0 || o.max_cycles < 0 || o.max_cycles > 100000 ||
+      (o.smoother != AMG_SMOOTH_JACOBI && o.smoother != AMG_SMOOTH_RB) ||
+      (o.precision != AMG_FP64 && o.precision != AMG_MIXED) || !(o.omega > 0))
+    return fail(H, AMG_EINVAL, "bad solve options");
+  const int l = lev_lo;
+  Level& L = H->levels[l];
+  if (l > 0 && L.cf_mode == AMG_CF_INTERP)
+    return fail(H, AMG_EUNSUPPORTED, "a level with interpolated coarse-fine ghosts is solved in a composite solve");
+  double* X = x[l];
+  const double* F = f[l];
+  const double* FD = face_data ? face_data[l] : nullptr;
+  if (!X || !F) return fail(H, AMG_EINVAL, "null x or f");
+  Run R{H, &L, H->dim, stream_of(H, stream)};
+  Depth& D0 = L.depths[0];
+  const int dim = H->dim;
+  const double hD = std::pow(D0.h, dim), hD1 = std::pow(D0.h, dim - 1);
+  if (stats) memset(stats, 0, sizeof *stats);
+
+  // ---- solvability: defect per singular component and the RHS shift ----
+  const double* frhs = F;
+  if (L.nsingular) {
+    launch_tile_sum<double>(dim, D0, F, L.partial, R.st);
+    launch_comp_sum(L.partial, D0.d_tc_ptr, D0.d_tc_idx, L.ncomp, L.comp_sum, R.st);
+    const double* bsum = nullptr;
+    if (FD) {
+      launch_chunk_fdsum(D0, FD, L.partial, R.st);
+      launch_comp_sum(L.partial, D0.d_cc_ptr, D0.d_cc_idx, L.ncomp, L.d_bsum, R.st);
+      bsum = L.d_bsum;
+    }
+    launch_comp_delta(L.comp_sum, bsum, L.d_comp_flag, L.d_comp_cnt, L.ncomp, hD, hD1, L.d_delta, L.d_defect, R.st);
+    if (o.solvability == AMG_SOLV_RHS_SHIFT) {
+      launch_shift_copy(dim, D0, F, L.fsh, L.d_delta, R.st);
+      frhs = L.fsh;
+    }
+    if (stats) {
+      std::vector<double> df(L.ncomp);
+      HIPCHK(hipMemcpyAsync(df.data(), L.d_defect, L.ncomp * sizeof(double), hipMemcpyDeviceToHost, R.st));
+      HIPCHK(hipStreamSynchronize(R.st));
+      int j = 0;
+      for (int c = 0; c < L.ncomp && j < AMG_MAX_COMP; ++c)
+        if (L.comp_singular[c]) stats->defect[j++] = df[c];
+      stats->ncomp = j;
+    }
+  }
+
+  const bool mixed = o.precision == AMG_MIXED;
+  double* Rb = mixed ? L.r64 : D0.f64;
+  double alpha, beta;
+  coefs<double>(H, D0, alpha, beta);
+  auto residual_norm = [&]() {
+    launch_fill<double>(D0, X, FD, R.st);
+    launch_residual<double>(dim, D0, true, X, frhs, Rb, alpha, beta, L.partial, R.st);
+    launch_reduce_max(L.partial, (int)D0.tiles.size(), L.scal + S_NORM, R.st);
+  };
+  auto read_norm = [&](double& v) -> int {
+    HIPCHK(hipMemcpyAsync(L.h_scal, L.scal + S_NORM, sizeof(double), hipMemcpyDeviceToHost, R.st));
+    HIPCHK(hipStreamSynchronize(R.st));
+    v = L.h_scal[0];
+    return AMG_OK;
+  };
+  residual_norm();
+  HIPCHK(hipGetLastError());
+  double r0 = 0;
+  TRY(read_norm(r0));
+  if (!std::isfinite(r0)) return fail(H, AMG_ENONFINITE, "non-finite initial residual");
+  const double target = std::max(o.tol_rel * r0, o.tol_abs);
+  double rn = r0;
+  int cycles = 0;
+  if (stats) {
+    stats->r0 = r0;
+    stats->history[0] = r0;
+  }
+  while (rn > target && cycles < o.max_cycles) {
+    remove_mean<double>(R, 0, Rb);
+    if (mixed) {
+      launch_to32(dim, D0, Rb, D0.f32, L.scal + S_NORM, R.st);
+      float* e = vcycle<float>(R, o, D0.f32, D0.e32, D0.t32);
+      launch_update<float>(dim, D0, X, e, L.scal + S_NORM, R.st);
+    } else {
+      double* e = vcycle<double>(R, o, D0.f64, D0.e64, D0.t64);
+      launch_update<double>(dim, D0, X, e, L.scal + S_ONE, R.st);
+    }
+    remove_mean<double>(R, 0, X);
+    residual_norm();
+    HIPCHK(hipGetLastError());
+    TRY(read_norm(rn));
+    ++cycles;
+    if (stats && cycles < AMG_MAX_HISTORY) stats->history[cycles] = rn;
+    if (!std::isfinite(rn)) return fail(H, AMG_ENONFINITE, "non-finite residual");
+  }
+  if (stats) {
+    stats->cycles = cycles;
+    stats->rfinal = rn;
+    stats->converged = rn <= target;
+  }
+  if (rn > target) return fail(H, AMG_ENOTCONVERGED, "max_cycles reached");
+  return AMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,230 @@
+// Host side of the exact bottom solve (the coarsest multigrid depth).
+//
+// The paper uses weighted Jacobi (TLS-2) or ILU-preconditioned GMRES (TLS-1,
+// TLS-3) at the coarsest multigrid level (Section 6.5); this library solves
+// that level exactly instead.  Here the homogeneous operator of the coarsest
+// depth -- the stencil of eq. (discreteOps c) with the ghost fills of eqs.
+// (velBCHomoDiri5th) / (Neumann5) folded in -- is assembled row by row for
+// each independent system (a face-connected component of a coupled level, or
+// one isolated box), and inverted in FP64 by Gauss-Jordan elimination with
+// partial pivoting.  A component on which the operator has a constant null
+// vector is bordered with one zero-mean constraint; the top-left block of the
+// bordered inverse maps a consistent right-hand side to the zero-mean
+// solution.  Identical systems (isolated boxes of equal shape) share one
+// inverse.
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <tuple>
+
+#include "amg_internal.h"
+
+namespace amg {
+
+namespace {
+
+// coefficient of the m-th cell behind the row end (m = 0 is the end cell) in
+// the first / second ghost
+const double kFillD[2][4] = {{-77.0 / 12, 43.0 / 12, -17.0 / 12, 3.0 / 12},
+                             {-505.0 / 12, 335.0 / 12, -145.0 / 12, 27.0 / 12}};
+const double kFillN[2][4] = {{5.0 / 10, 9.0 / 10, -5.0 / 10, 1.0 / 10},
+                             {-75.0 / 10, 145.0 / 10, -75.0 / 10, 15.0 / 10}};
+
+bool invert(std::vector<double>& A, int n) {
+  // in-place Gauss-Jordan with partial pivoting, row-major n x n
+  std::vector<int> piv(n);
+  std::vector<double> inv((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int col = 0; col < n; ++col) {
+    int p = col;
+    double best = std::fabs(A[(size_t)col * n + col]);
+    for (int r = col + 1; r < n; ++r) {
+      double v = std::fabs(A[(size_t)r * n + col]);
+      if (v > best) best = v, p = r;
+    }
+    if (best == 0.0) return false;
+    if (p != col)
+      for (int j = 0; j < n; ++j) {
+        std::swap(A[(size_t)p * n + j], A[(size_t)col * n + j]);
+        std::swap(inv[(size_t)p * n + j], inv[(size_t)col * n + j]);
+      }
+    double d = 1.0 / A[(size_t)col * n + col];
+    for (int j = 0; j < n; ++j) {
+      A[(size_t)col * n + j] *= d;
+      inv[(size_t)col * n + j] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      double f = A[(size_t)r * n + col];
+      if (f == 0.0) continue;
+      double* ar = &A[(size_t)r * n];
+      const double* ac = &A[(size_t)col * n];
+      double* ir = &inv[(size_t)r * n];
+      const double* ic = &inv[(size_t)col * n];
+      for (int j = 0; j < n; ++j) {
+        ar[j] -= f * ac[j];
+        ir[j] -= f * ic[j];
+      }
+    }
+  }
+  A.swap(inv);
+  return true;
+}
+
+}  // namespace
+
+int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats, std::vector<int64_t>& idx) {
+  Level& L = H->levels[l];
+  const int dim = H->dim;
+  for (size_t k = 0; k < L.depths.size(); ++k) {
+    Depth& D = L.depths[k];
+    D.groups.clear();
+    if (D.bottom_boxes.empty()) continue;
+    // systems: lists of boxes (at this depth)
+    std::vector<std::vector<int>> systems;
+    if (L.isolated) {
+      for (int b : D.bottom_boxes) systems.push_back({b});
+    } else {
+      std::vector<std::vector<int>> bycomp(L.ncomp);
+      for (int b : D.bottom_boxes) bycomp[D.boxd[b].comp].push_back(b);
+      for (auto& v : bycomp)
+        if (!v.empty()) systems.push_back(v);
+    }
+    const double K = 1.0 / (12.0 * D.h * D.h);
+    std::map<std::tuple<int, int, int>, int> shared;  // isolated: shape -> group
+    std::vector<std::vector<int64_t>> group_elems;
+    for (auto& sys : systems) {
+      // local numbering
+      std::vector<int64_t> start(D.boxes.size(), -1);
+      int64_t n = 0;
+      for (int b : sys) {
+        start[b] = n;
+        n += (int64_t)D.boxd[b].n[0] * D.boxd[b].n[1] * D.boxd[b].n[2];
+      }
+      const int comp = D.boxd[sys[0]].comp;
+      const bool sing = L.comp_singular[comp] != 0;
+      // element indices of this instance
+      std::vector<int64_t> elems;
+      for (int b : sys) {
+        const BoxD& X = D.boxd[b];
+        for (int z = 0; z < X.n[2]; ++z)
+          for (int y = 0; y < X.n[1]; ++y)
+            for (int x = 0; x < X.n[0]; ++x)
+              elems.push_back(X.off + (int64_t)(x + 2) * X.s[0] + (int64_t)(y + 2) * X.s[1] +
+                              (dim == 3 ? (int64_t)(z + 2) * X.s[2] : 0));
+      }
+      if (L.isolated) {
+        const BoxD& X = D.boxd[sys[0]];
+        auto key = std::make_tuple(X.n[0], X.n[1], X.n[2]);
+        auto it = shared.find(key);
+        if (it != shared.end()) {
+          D.groups[it->second].ninst += 1;
+          auto& ge = group_elems[it->second];
+          ge.insert(ge.end(), elems.begin(), elems.end());
+          continue;
+        }
+      }
+      if (n > 8192) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "coarsest system of level %d has %lld unknowns (limit 8192)", l, (long long)n);
+        err = buf;
+        return AMG_EUNSUPPORTED;
+      }
+      const int m = (int)n + (sing ? 1 : 0);
+      std::vector<double> A((size_t)m * m, 0.0);
+      auto lidx = [&](int b, int x, int y, int z) -> int64_t {
+        const BoxD& X = D.boxd[b];
+        return start[b] + x + (int64_t)X.n[0] * (y + (int64_t)X.n[1] * z);
+      };
+      for (int b : sys) {
+        const BoxD& X = D.boxd[b];
+        const Box& B = D.boxes[b];
+        for (int z = 0; z < X.n[2]; ++z)
+          for (int y = 0; y < X.n[1]; ++y)
+            for (int x = 0; x < X.n[0]; ++x) {
+              int64_t row = lidx(b, x, y, z);
+              double* R = &A[(size_t)row * m];
+              int loc[3] = {x, y, z};
+              R[row] += -30.0 * dim * K;
+              for (int d = 0; d < dim; ++d) {
+                int t0 = -1, t1 = -1;
+                for (int e = 0; e < dim; ++e)
+                  if (e != d) (t0 < 0 ? t0 : t1) = e;
+                for (int o : {-2, -1, 1, 2}) {
+                  double w = (o == 1 || o == -1) ? 16.0 * K : -1.0 * K;
+                  int p = loc[d] + o;
+                  if (p >= 0 && p < X.n[d]) {
+                    int q[3] = {x, y, z};
+                    q[d] = p;
+                    R[lidx(b, q[0], q[1], q[2])] += w;
+                    continue;
+                  }
+                  int s = o > 0 ? 1 : 0;
+                  int layer = s ? p - (X.n[d] - 1) : -p;
+                  size_t col = (size_t)loc[t0] + (size_t)X.n[t0] * (dim == 3 ? loc[t1] : 0);
+                  const FaceCols& fc = D.faces[b * 6 + d * 2 + s];
+                  uint8_t kind = layer == 1 ? fc.k1[col] : fc.k2[col];
+                  if (kind == G_FILL_D || kind == G_FILL_N) {
+                    const double* a = kind == G_FILL_D ? kFillD[layer - 1] : kFillN[layer - 1];
+                    int e0 = s ? X.n[d] - 1 : 0;
+                    for (int mm = 0; mm < 4; ++mm) {
+                      int q[3] = {x, y, z};
+                      q[d] = s ? e0 - mm : e0 + mm;
+                      R[lidx(b, q[0], q[1], q[2])] += w * a[mm];
+                    }
+                  } else if (kind == G_EXCH) {
+                    int j = layer == 1 ? fc.src1[col] : fc.src2[col];
+                    const Box& C = D.boxes[j];
+                    int g[3] = {B.lo[0] + x, B.lo[1] + y, B.lo[2] + z};
+                    g[d] = B.lo[d] + p;
+                    if (start[j] < 0) {
+                      err = "exchange source outside the bottom system";
+                      return AMG_EUNSUPPORTED;
+                    }
+                    R[lidx(j, g[0] - C.lo[0], g[1] - C.lo[1], dim == 3 ? g[2] - C.lo[2] : 0)] += w;
+                  }
+                }
+              }
+            }
+      }
+      if (H->op == AMG_HELMHOLTZ) {
+        for (int64_t i = 0; i < n; ++i)
+          for (int64_t j = 0; j < n; ++j) A[(size_t)i * m + j] = (i == j ? 1.0 : 0.0) - H->c * A[(size_t)i * m + j];
+      }
+      if (sing) {
+        for (int64_t i = 0; i < n; ++i) {
+          A[(size_t)i * m + n] = 1.0;
+          A[(size_t)n * m + i] = 1.0;
+        }
+      }
+      if (!invert(A, m)) {
+        err = "singular bottom system";
+        return AMG_EUNSUPPORTED;
+      }
+      BottomGroupD G;
+      G.mat = (int64_t)mats.size();
+      G.idx = -1;
+      G.n = (int32_t)n;
+      G.ninst = 1;
+      // column-major top-left n x n block
+      size_t base = mats.size();
+      mats.resize(base + (size_t)n * n);
+      for (int64_t c = 0; c < n; ++c)
+        for (int64_t r = 0; r < n; ++r) mats[base + (size_t)c * n + r] = A[(size_t)r * m + c];
+      group_elems.push_back(elems);
+      if (L.isolated) {
+        const BoxD& X = D.boxd[sys[0]];
+        shared[std::make_tuple(X.n[0], X.n[1], X.n[2])] = (int)D.groups.size();
+      }
+      D.groups.push_back(G);
+    }
+    // instances of one group are contiguous in the index pool
+    for (size_t g = 0; g < D.groups.size(); ++g) {
+      D.groups[g].idx = (int64_t)idx.size();
+      idx.insert(idx.end(), group_elems[g].begin(), group_elems[g].end());
+    }
+  }
+  return AMG_OK;
+}
+
+}  // namespace amg

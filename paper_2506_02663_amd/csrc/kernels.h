@@ -1,0 +1,47 @@
+// Launchers of the HIP kernels (kernels.hip), called by the solver driver.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "amg_internal.h"
+
+namespace amg {
+template <typename T>
+void launch_fill(const Depth& D, T* u, const double* fd, hipStream_t st);
+template <typename T>
+void launch_residual(int dim, const Depth& D, bool all, const T* u, const T* f, T* r, T alpha, T beta, double* part,
+                     hipStream_t st);
+template <typename T>
+void launch_jacobi(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, T omega, bool zero,
+                   hipStream_t st);
+template <typename T>
+void launch_rb(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, int col, bool zero,
+               hipStream_t st);
+template <typename T>
+void launch_resid_restrict(int dim, const Depth& F, const Depth& C, const T* u, const T* f, T* fc, T alpha, T beta,
+                           hipStream_t st);
+template <typename T>
+void launch_restrict(int dim, const Depth& F, const Depth& C, const T* r, T* fc, hipStream_t st);
+template <typename T>
+void launch_prolong(int dim, const Depth& F, const Depth& C, const T* ec, T* u, hipStream_t st);
+template <typename T>
+void launch_bottom(const Depth& D, const double* mats, const int64_t* idx, const T* f, T* e, hipStream_t st);
+template <typename T>
+void launch_tile_sum(int dim, const Depth& D, const T* a, double* part, hipStream_t st);
+template <typename T>
+void launch_tile_absmax(int dim, const Depth& D, const T* a, double* part, hipStream_t st);
+void launch_reduce_max(const double* part, int n, double* out, hipStream_t st);
+void launch_comp_sum(const double* part, const int32_t* ptr, const int32_t* ids, int ncomp, double* out,
+                     hipStream_t st);
+void launch_comp_delta(const double* sum, const double* bsum, const int32_t* flag, const double* cnt, int ncomp,
+                       double scale_sum, double scale_b, double* delta, double* defect, hipStream_t st);
+template <typename T>
+void launch_comp_shift(int dim, const Depth& D, T* a, const double* delta, hipStream_t st);
+void launch_chunk_fdsum(const Depth& D, const double* fd, double* part, hipStream_t st);
+template <typename T>
+void launch_update(int dim, const Depth& D, double* x, const T* e, const double* scal, hipStream_t st);
+void launch_to32(int dim, const Depth& D, const double* r, float* r32, const double* scal, hipStream_t st);
+void launch_shift_copy(int dim, const Depth& D, const double* f, double* out, const double* delta, hipStream_t st);
+void launch_set_scale(const double* src, double* dst, hipStream_t st);
+template <typename T>
+void launch_zero(T* a, int64_t n, hipStream_t st);
+}  // namespace amg

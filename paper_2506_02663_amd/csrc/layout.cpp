@@ -1,0 +1,447 @@
+// Host planner: validates a level's box layout and builds the tables the
+// kernels walk -- box descriptors, ghost-column classification and chunks,
+// tiles, component lists -- at every multigrid depth.
+//
+// Layout rules (Section 5.1): boxes are disjoint rectangles of the level's
+// grid, eq. (AMRHier); a level > 0 is properly refined, eq. (pBlock), i.e.
+// its corners are multiples of the refinement ratio.  The fills read four
+// cells of the row that ends at a face, so every box has at least 4 cells
+// per side.  A level is halved for the next multigrid depth while every box
+// has even corners and even sides of at least 8 (an isolated box: even sides
+// of at least 8).
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+#include "amg_internal.h"
+#include "tiles.h"
+
+namespace amg {
+
+namespace {
+
+int64_t grid_cells(const amg_hier* H, int l, int d) {
+  int64_t n = H->base[d];
+  for (int i = 0; i < l; ++i) n *= H->ratio;
+  return n;
+}
+
+bool touch(const Box& a, const Box& b, int dim) {
+  // face contact: adjacent along one direction, overlapping with positive
+  // extent in all others (corner or edge contact does not connect)
+  for (int d = 0; d < dim; ++d) {
+    bool adj = (a.hi[d] + 1 == b.lo[d]) || (b.hi[d] + 1 == a.lo[d]);
+    if (!adj) continue;
+    bool ok = true;
+    for (int e = 0; e < dim; ++e) {
+      if (e == d) continue;
+      if (std::max(a.lo[e], b.lo[e]) > std::min(a.hi[e], b.hi[e])) ok = false;
+    }
+    if (ok) return true;
+  }
+  return false;
+}
+
+bool overlap(const Box& a, const Box& b, int dim) {
+  for (int d = 0; d < dim; ++d)
+    if (std::max(a.lo[d], b.lo[d]) > std::min(a.hi[d], b.hi[d])) return false;
+  return true;
+}
+
+int find(std::vector<int>& p, int x) {
+  while (p[x] != x) x = p[x] = p[p[x]];
+  return x;
+}
+
+// transverse directions of face d, in increasing order
+void transverse(int dim, int d, int t[2]) {
+  int k = 0;
+  t[0] = t[1] = -1;
+  for (int e = 0; e < dim; ++e)
+    if (e != d) t[k++] = e;
+}
+
+}  // namespace
+
+int plan_level(amg_hier* H, int l, std::string& err) {
+  Level& L = H->levels[l];
+  const int dim = H->dim;
+  const int nb = (int)L.boxes.size();
+  char buf[256];
+  if (nb == 0) {
+    err = "level has no boxes";
+    return AMG_ELAYOUT;
+  }
+  int64_t gn[3] = {1, 1, 1};
+  for (int d = 0; d < dim; ++d) gn[d] = grid_cells(H, l, d);
+
+  // ---- validation -----------------------------------------------------------
+  int64_t vol = 0;
+  for (int b = 0; b < nb; ++b) {
+    const Box& B = L.boxes[b];
+    int64_t v = 1;
+    for (int d = 0; d < dim; ++d) {
+      if (B.n(d) < 4) {
+        snprintf(buf, sizeof buf, "box %d has %d < 4 cells along direction %d", b, B.n(d), d);
+        err = buf;
+        return AMG_ELAYOUT;
+      }
+      if (!L.isolated && (B.lo[d] < 0 || B.hi[d] >= gn[d])) {
+        snprintf(buf, sizeof buf, "box %d leaves the grid of level %d", b, l);
+        err = buf;
+        return AMG_ELAYOUT;
+      }
+      if (l > 0 && !L.isolated && (B.lo[d] % H->ratio || (B.hi[d] + 1) % H->ratio)) {
+        snprintf(buf, sizeof buf, "box %d of level %d is not properly refined (corners not multiples of %d)", b, l,
+                 H->ratio);
+        err = buf;
+        return AMG_ELAYOUT;
+      }
+      v *= B.n(d);
+    }
+    vol += v;
+  }
+  if (!L.isolated) {
+    for (int a = 0; a < nb; ++a)
+      for (int b = a + 1; b < nb; ++b)
+        if (overlap(L.boxes[a], L.boxes[b], dim)) {
+          snprintf(buf, sizeof buf, "boxes %d and %d overlap", a, b);
+          err = buf;
+          return AMG_ELAYOUT;
+        }
+    if (l == 0) {
+      int64_t g = 1;
+      for (int d = 0; d < dim; ++d) g *= gn[d];
+      if (g != vol) {
+        err = "level 0 must cover the whole grid";
+        return AMG_ELAYOUT;
+      }
+    }
+  }
+  L.ncells = vol;
+
+  // ---- components (union-find over face contact) ------------------------------
+  std::vector<int> par(nb);
+  std::iota(par.begin(), par.end(), 0);
+  if (!L.isolated)
+    for (int a = 0; a < nb; ++a)
+      for (int b = a + 1; b < nb; ++b)
+        if (touch(L.boxes[a], L.boxes[b], dim)) par[find(par, a)] = find(par, b);
+  std::vector<int> root_id(nb, -1);
+  L.box_comp.assign(nb, 0);
+  L.ncomp = 0;
+  for (int b = 0; b < nb; ++b) {
+    int r = find(par, b);
+    if (root_id[r] < 0) root_id[r] = L.ncomp++;
+    L.box_comp[b] = root_id[r];
+  }
+
+  // ---- multigrid depths ---------------------------------------------------------
+  std::vector<int> bottom(nb, 0);
+  if (L.isolated) {
+    for (int b = 0; b < nb; ++b) {
+      int n[3] = {L.boxes[b].n(0), L.boxes[b].n(1), dim == 3 ? L.boxes[b].n(2) : 8};
+      int k = 0;
+      while (true) {
+        bool ok = true;
+        for (int d = 0; d < dim; ++d)
+          if ((n[d] >> k) % 2 || (n[d] >> k) < 8) ok = false;
+        if (!ok) break;
+        ++k;
+      }
+      bottom[b] = k;
+    }
+  } else {
+    int k = 0;
+    while (true) {
+      bool ok = true;
+      for (int d = 0; d < dim; ++d)
+        if ((gn[d] >> k) % 2) ok = false;
+      for (int b = 0; b < nb && ok; ++b)
+        for (int d = 0; d < dim; ++d) {
+          int lo = L.boxes[b].lo[d] >> k, n = L.boxes[b].n(d) >> k;
+          if (lo % 2 || n % 2 || n < 8) ok = false;
+        }
+      // boxes facing each other across a gap must stay two cells apart
+      // after halving, or the radius-2 stencil would couple them directly
+      for (int a = 0; a < nb && ok; ++a)
+        for (int b = a + 1; b < nb && ok; ++b)
+          for (int d = 0; d < dim && ok; ++d) {
+            bool facing = true;
+            for (int e = 0; e < dim; ++e)
+              if (e != d && std::max(L.boxes[a].lo[e], L.boxes[b].lo[e]) > std::min(L.boxes[a].hi[e], L.boxes[b].hi[e]))
+                facing = false;
+            if (!facing) continue;
+            int gap = std::max(L.boxes[b].lo[d] - L.boxes[a].hi[d] - 1, L.boxes[a].lo[d] - L.boxes[b].hi[d] - 1) >> k;
+            if (gap > 0 && gap < 4) ok = false;
+          }
+      if (!ok) break;
+      ++k;
+    }
+    std::fill(bottom.begin(), bottom.end(), k);
+  }
+  const int ndepth = 1 + *std::max_element(bottom.begin(), bottom.end());
+  L.depths.assign(ndepth, Depth());
+
+  const int gk1 = (L.cf_mode == AMG_CF_DIRICHLET) ? G_FILL_D : (L.cf_mode == AMG_CF_NEUMANN) ? G_FILL_N : G_ZERO;
+
+  // face-data layout (depth 0 only)
+  L.face_off.assign((size_t)nb * 6, -1);
+  L.nface = 0;
+  for (int b = 0; b < nb; ++b)
+    for (int d = 0; d < dim; ++d)
+      for (int s = 0; s < 2; ++s) {
+        int t[2];
+        transverse(dim, d, t);
+        int64_t area = 1;
+        for (int q = 0; q < dim - 1; ++q) area *= L.boxes[b].n(t[q]);
+        L.face_off[b * 6 + d * 2 + s] = L.nface;
+        L.nface += area;
+      }
+
+  std::vector<int> prev_index(nb, -1);  // box b's index at the previous depth
+  for (int k = 0; k < ndepth; ++k) {
+    Depth& D = L.depths[k];
+    D.h = H->h0;
+    for (int i = 0; i < l; ++i) D.h /= H->ratio;
+    for (int i = 0; i < k; ++i) D.h *= 2;
+    std::vector<int> cur_index(nb, -1);
+    for (int b = 0; b < nb; ++b) {
+      if (bottom[b] < k) continue;
+      Box B;
+      for (int d = 0; d < 3; ++d) {
+        if (d < dim) {
+          B.lo[d] = L.isolated ? 0 : (L.boxes[b].lo[d] >> k);
+          B.hi[d] = B.lo[d] + (L.boxes[b].n(d) >> k) - 1;
+        } else {
+          B.lo[d] = B.hi[d] = 0;
+        }
+      }
+      cur_index[b] = (int)D.boxes.size();
+      D.boxes.push_back(B);
+      D.level_box.push_back(b);
+      if (bottom[b] == k) D.bottom_boxes.push_back(cur_index[b]);
+    }
+    const int nbk = (int)D.boxes.size();
+    // storage: each box with two ghost layers, x fastest, box starts aligned to 64 elements
+    D.boxd.resize(nbk);
+    int64_t off = 0;
+    for (int i = 0; i < nbk; ++i) {
+      const Box& B = D.boxes[i];
+      BoxD& X = D.boxd[i];
+      memset(&X, 0, sizeof X);
+      int64_t sx = B.n(0) + 4, sy = B.n(1) + 4;
+      int64_t sz = dim == 3 ? B.n(2) + 4 : 1;
+      X.off = off;
+      X.n[0] = B.n(0);
+      X.n[1] = B.n(1);
+      X.n[2] = dim == 3 ? B.n(2) : 1;
+      X.s[0] = 1;
+      X.s[1] = (int32_t)sx;
+      X.s[2] = (int32_t)(sx * sy);
+      for (int d = 0; d < 3; ++d) X.lo[d] = B.lo[d];
+      X.comp = L.box_comp[D.level_box[i]];
+      X.fine = k > 0 ? prev_index[D.level_box[i]] : -1;
+      X.coarse = -1;
+      off += ((sx * sy * sz + 63) / 64) * 64;
+    }
+    D.nstored = off;
+    if (k > 0) {
+      Depth& F = L.depths[k - 1];
+      for (int i = 0; i < nbk; ++i) F.boxd[D.boxd[i].fine].coarse = i;
+    }
+    // domain at this depth
+    int64_t dn[3] = {1, 1, 1};
+    for (int d = 0; d < dim; ++d) dn[d] = gn[d] >> k;
+
+    // ---- ghost-column classification ----
+    D.faces.assign((size_t)nbk * 6, FaceCols());
+    for (int i = 0; i < nbk; ++i) {
+      const Box& B = D.boxes[i];
+      for (int d = 0; d < dim; ++d) {
+        int t[2];
+        transverse(dim, d, t);
+        int n0 = t[0] >= 0 ? B.n(t[0]) : 1;
+        int n1 = (dim == 3) ? B.n(t[1]) : 1;
+        for (int s = 0; s < 2; ++s) {
+          FaceCols& fc = D.faces[i * 6 + d * 2 + s];
+          size_t area = (size_t)n0 * n1;
+          int p1 = s ? B.hi[d] + 1 : B.lo[d] - 1;
+          bool phys = L.isolated ? true : (p1 < 0 || p1 >= dn[d]);
+          uint8_t kk = phys ? ((H->phys_bc[d][s] == AMG_DIRICHLET) ? G_FILL_D : G_FILL_N) : gk1;
+          fc.k1.assign(area, kk);
+          fc.k2.assign(area, kk);
+          fc.src1.assign(area, -1);
+          fc.src2.assign(area, -1);
+          if (L.isolated || phys) continue;
+          for (int layer = 1; layer <= 2; ++layer) {
+            int p = s ? B.hi[d] + layer : B.lo[d] - layer;
+            for (int j = 0; j < nbk; ++j) {
+              if (j == i) continue;
+              const Box& C = D.boxes[j];
+              if (p < C.lo[d] || p > C.hi[d]) continue;
+              int a0 = std::max(B.lo[t[0]], C.lo[t[0]]), b0 = std::min(B.hi[t[0]], C.hi[t[0]]);
+              if (a0 > b0) continue;
+              int a1 = 0, b1 = 0;
+              if (dim == 3) {
+                a1 = std::max(B.lo[t[1]], C.lo[t[1]]);
+                b1 = std::min(B.hi[t[1]], C.hi[t[1]]);
+                if (a1 > b1) continue;
+              }
+              for (int q1 = a1; q1 <= b1; ++q1)
+                for (int q0 = a0; q0 <= b0; ++q0) {
+                  size_t col = (size_t)(q0 - B.lo[t[0]]) + (size_t)n0 * (dim == 3 ? (q1 - B.lo[t[1]]) : 0);
+                  if (layer == 1) {
+                    fc.k1[col] = G_EXCH;
+                    fc.src1[col] = j;
+                  } else {
+                    fc.k2[col] = G_EXCH;
+                    fc.src2[col] = j;
+                  }
+                }
+            }
+          }
+        }
+      }
+    }
+    // column codes
+    D.codes.clear();
+    for (int i = 0; i < nbk; ++i)
+      for (int d = 0; d < 3; ++d)
+        for (int s = 0; s < 2; ++s) {
+          if (d >= dim) {
+            D.boxd[i].code_off[d][s] = 0;
+            continue;
+          }
+          FaceCols& fc = D.faces[i * 6 + d * 2 + s];
+          D.boxd[i].code_off[d][s] = (int32_t)D.codes.size();
+          for (size_t c = 0; c < fc.k1.size(); ++c) D.codes.push_back(column_code(fc.k1[c], fc.k2[c]));
+        }
+    if (D.codes.empty()) D.codes.push_back(0);
+
+    // ---- ghost chunks ----
+    auto addr = [&](int box, int x, int y, int z) -> int64_t {  // global index -> element
+      const BoxD& X = D.boxd[box];
+      const Box& B = D.boxes[box];
+      int64_t a = X.off + (int64_t)(x - B.lo[0] + 2) * X.s[0] + (int64_t)(y - B.lo[1] + 2) * X.s[1];
+      if (dim == 3) a += (int64_t)(z - B.lo[2] + 2) * X.s[2];
+      return a;
+    };
+    D.chunks.clear();
+    std::vector<std::vector<int32_t>> comp_chunks(L.ncomp);
+    for (int i = 0; i < nbk; ++i) {
+      const Box& B = D.boxes[i];
+      for (int d = 0; d < dim; ++d) {
+        int t[2];
+        transverse(dim, d, t);
+        int n0 = B.n(t[0]);
+        int n1 = (dim == 3) ? B.n(t[1]) : 1;
+        for (int s = 0; s < 2; ++s) {
+          FaceCols& fc = D.faces[i * 6 + d * 2 + s];
+          int step = s ? 1 : -1;
+          for (int q1 = 0; q1 < n1; ++q1) {
+            int q0 = 0;
+            while (q0 < n0) {
+              size_t col = (size_t)q0 + (size_t)n0 * q1;
+              int q = q0 + 1;
+              while (q < n0 && q - q0 < 64) {
+                size_t c2 = (size_t)q + (size_t)n0 * q1;
+                if (fc.k1[c2] != fc.k1[col] || fc.k2[c2] != fc.k2[col] || fc.src1[c2] != fc.src1[col] ||
+                    fc.src2[c2] != fc.src2[col])
+                  break;
+                ++q;
+              }
+              ChunkD ch;
+              memset(&ch, 0, sizeof ch);
+              int g[3] = {0, 0, 0};  // global index of the layer-1 ghost of the first column
+              g[d] = s ? B.hi[d] + 1 : B.lo[d] - 1;
+              g[t[0]] = B.lo[t[0]] + q0;
+              if (dim == 3) g[t[1]] = B.lo[t[1]] + q1;
+              ch.dst = addr(i, g[0], g[1], g[2]);
+              ch.cstride = D.boxd[i].s[t[0]];
+              ch.nstride = step * D.boxd[i].s[d];
+              ch.count = q - q0;
+              ch.box = i;
+              ch.kind1 = fc.k1[col];
+              ch.kind2 = fc.k2[col];
+              ch.src1 = ch.src2 = -1;
+              if (fc.src1[col] >= 0) {
+                ch.src1 = addr(fc.src1[col], g[0], g[1], g[2]);
+                ch.sstride1 = D.boxd[fc.src1[col]].s[t[0]];
+              }
+              if (fc.src2[col] >= 0) {
+                int g2[3] = {g[0], g[1], g[2]};
+                g2[d] += step;
+                ch.src2 = addr(fc.src2[col], g2[0], g2[1], g2[2]);
+                ch.sstride2 = D.boxd[fc.src2[col]].s[t[0]];
+              }
+              ch.fd = -1;
+              if (k == 0 && (ch.kind1 == G_FILL_D || ch.kind1 == G_FILL_N))
+                ch.fd = L.face_off[D.level_box[i] * 6 + d * 2 + s] + (int64_t)q0 + (int64_t)n0 * q1;
+              comp_chunks[D.boxd[i].comp].push_back((int32_t)D.chunks.size());
+              D.chunks.push_back(ch);
+              q0 = q;
+            }
+          }
+        }
+      }
+    }
+    D.chunk_comp_ptr.assign(1, 0);
+    D.chunk_comp_idx.clear();
+    for (int c = 0; c < L.ncomp; ++c) {
+      D.chunk_comp_idx.insert(D.chunk_comp_idx.end(), comp_chunks[c].begin(), comp_chunks[c].end());
+      D.chunk_comp_ptr.push_back((int32_t)D.chunk_comp_idx.size());
+    }
+
+    // ---- tiles ----
+    D.tiles.clear();
+    D.stiles.clear();
+    std::vector<std::vector<int32_t>> comp_tiles(L.ncomp);
+    const int TX = dim == 2 ? TILE2_X : TILE3_X, TY = dim == 2 ? TILE2_Y : TILE3_Y, TZ = dim == 2 ? 1 : TILE3_Z;
+    for (int i = 0; i < nbk; ++i) {
+      const BoxD& X = D.boxd[i];
+      bool smooths = bottom[D.level_box[i]] > k;
+      for (int z = 0; z < X.n[2]; z += TZ)
+        for (int y = 0; y < X.n[1]; y += TY)
+          for (int x = 0; x < X.n[0]; x += TX) {
+            TileD T{i, x, y, z};
+            comp_tiles[X.comp].push_back((int32_t)D.tiles.size());
+            D.tiles.push_back(T);
+            if (smooths) D.stiles.push_back(T);
+          }
+    }
+    D.tile_comp_ptr.assign(1, 0);
+    D.tile_comp_idx.clear();
+    for (int c = 0; c < L.ncomp; ++c) {
+      D.tile_comp_idx.insert(D.tile_comp_idx.end(), comp_tiles[c].begin(), comp_tiles[c].end());
+      D.tile_comp_ptr.push_back((int32_t)D.tile_comp_idx.size());
+    }
+    prev_index = cur_index;
+  }
+
+  // ---- singular components (Poisson, no Dirichlet-type column at depth 0) -----
+  L.comp_singular.assign(L.ncomp, 0);
+  L.comp_cells.assign(L.ncomp, 0);
+  for (int b = 0; b < nb; ++b) {
+    int64_t v = 1;
+    for (int d = 0; d < dim; ++d) v *= L.boxes[b].n(d);
+    L.comp_cells[L.box_comp[b]] += v;
+  }
+  if (H->op == AMG_POISSON) {
+    std::vector<int> has_dir(L.ncomp, 0);
+    Depth& D0 = L.depths[0];
+    for (size_t i = 0; i < D0.boxes.size(); ++i)
+      for (int d = 0; d < dim; ++d)
+        for (int s = 0; s < 2; ++s) {
+          const FaceCols& fc = D0.faces[i * 6 + d * 2 + s];
+          for (size_t c = 0; c < fc.k1.size(); ++c)
+            if (fc.k1[c] == G_FILL_D || fc.k1[c] == G_ZERO) has_dir[D0.boxd[i].comp] = 1;
+        }
+    for (int c = 0; c < L.ncomp; ++c) L.comp_singular[c] = !has_dir[c];
+  }
+  L.nsingular = (int)std::count(L.comp_singular.begin(), L.comp_singular.end(), 1);
+  return AMG_OK;
+}
+
+}  // namespace amg

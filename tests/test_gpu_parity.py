@@ -1,0 +1,173 @@
+"""Parity of every step of the HIP path with the FP64 oracle, element by
+element, through the C ABI (one multigrid step at a time, then whole
+V-cycles and solves).  Layouts span single boxes, box-to-box exchange,
+coarse-fine faces with two components, a one-cell gap between boxes one
+depth down, 2D and 3D, Dirichlet, Neumann and mixed conditions."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import mg  # noqa: E402
+from paper_2506_02663_amd import amg as A  # noqa: E402
+from tests.gpuhelp import (MIXED_BC, cf_level, faces_to_dev, from_dev, gap_level, ghost_values,  # noqa: E402
+                           make_hier, random_faces, random_field, relerr, tiled_level, unit_level, to_dev)
+
+TOL64 = 1e-11
+
+LAYOUTS = {
+    "2d_dir": lambda: unit_level(32, 2, "D"),
+    "2d_neu": lambda: unit_level(32, 2, "N"),
+    "2d_mixed": lambda: unit_level(32, 2, MIXED_BC),
+    "2d_tiled": lambda: tiled_level(32, 2, "D"),
+    "2d_cf_dir": lambda: cf_level("D", "N"),
+    "2d_cf_neu": lambda: cf_level("N", "N"),
+    "2d_gap": lambda: gap_level("D"),
+    "3d_dir": lambda: unit_level(16, 3, "D"),
+    "3d_neu_tiled": lambda: tiled_level(16, 3, "N"),
+}
+OPS = [("helmholtz", 0.37), ("poisson", 0.0)]
+
+
+def _c(op, c, lev):
+    return c * lev.h if op == "helmholtz" else 0.0
+
+
+@pytest.mark.parametrize("name", list(LAYOUTS))
+@pytest.mark.parametrize("op,c0", OPS)
+def test_ghost_fill_and_operator(name, op, c0):
+    lev = LAYOUTS[name]()
+    c = _c(op, c0, lev)
+    H, L = make_hier(lev, op, c)
+    u = random_field(lev, 1)
+    fd = random_faces(lev, 2)
+    ud = to_dev(H, L, 0, u)
+    fdd = faces_to_dev(H, L, lev, fd)
+    y = torch.zeros_like(ud)
+    H.apply_operator(L, ud, y, fdd)
+    torch.cuda.synchronize()
+    want = lev.apply(u, op, c, fd)
+    assert relerr(from_dev(H, L, 0, y, lev), want, lev.mask) < TOL64
+    # the ghosts apply_operator wrote equal the oracle's fill (row ends only;
+    # ghosts inside other boxes hold those boxes' values)
+    G = lev.ghosts(u, fd)
+    for g, o, m in ghost_values(H, L, 0, ud, lev, G):
+        assert np.allclose(np.where(m, 0.0, g), o, rtol=1e-12, atol=1e-12 * np.abs(o).max(initial=1.0))
+
+
+@pytest.mark.parametrize("name", list(LAYOUTS))
+@pytest.mark.parametrize("op,c0", OPS)
+@pytest.mark.parametrize("smoother", ["jacobi", "rb"])
+def test_smoother(name, op, c0, smoother):
+    lev = LAYOUTS[name]()
+    c = _c(op, c0, lev)
+    H, L = make_hier(lev, op, c)
+    e = random_field(lev, 3)
+    f = random_field(lev, 4)
+    D = lev.diagonal(op, c)
+    if smoother == "jacobi":
+        want = mg.jacobi(lev, e, f, op, c, D, 2.0 / 3.0, 2)
+        sm, n = A.SMOOTH_JACOBI, 2
+    else:
+        want = mg.red_black(lev, e, f, op, c, D, 1)
+        sm, n = A.SMOOTH_RB, 1
+    for dt, tol in ((torch.float64, TOL64), (torch.float32, 2e-5)):
+        ed = to_dev(H, L, 0, e, dt)
+        fdv = to_dev(H, L, 0, f, dt)
+        tmp = torch.zeros_like(ed)
+        H.smooth(L, 0, ed, fdv, tmp, sm, n)
+        torch.cuda.synchronize()
+        assert relerr(from_dev(H, L, 0, ed, lev), want, lev.mask) < tol, str(dt)
+
+
+@pytest.mark.parametrize("name", list(LAYOUTS))
+@pytest.mark.parametrize("op,c0", OPS)
+def test_residual_restriction_prolongation(name, op, c0):
+    lev = LAYOUTS[name]()
+    c = _c(op, c0, lev)
+    H, L = make_hier(lev, op, c)
+    levels = lev.hierarchy()
+    assert H.level_info(L).depths == len(levels)
+    coarse = levels[1]
+    u = random_field(lev, 5)
+    f = random_field(lev, 6)
+    ec = random_field(coarse, 7)
+    ud, fdv = to_dev(H, L, 0, u), to_dev(H, L, 0, f)
+    H.fill_ghosts(L, 0, ud)
+    r = torch.zeros_like(ud)
+    H.residual(L, 0, ud, fdv, r)
+    want_r = f - lev.apply(u, op, c)
+    assert relerr(from_dev(H, L, 0, r, lev), want_r, lev.mask) < TOL64
+    fc = torch.zeros(H.depth_size(L, 1)[0], dtype=torch.float64, device="cuda")
+    H.restrict(L, 0, r, fc)
+    assert relerr(from_dev(H, L, 1, fc, coarse), mg.restrict(lev, want_r, coarse), coarse.mask) < TOL64
+    ecd = to_dev(H, L, 1, ec)
+    H.fill_ghosts(L, 1, ecd)
+    H.prolong(L, 0, ecd, ud)
+    torch.cuda.synchronize()
+    assert relerr(from_dev(H, L, 0, ud, lev), u + mg.prolong(coarse, ec, lev), lev.mask) < TOL64
+
+
+@pytest.mark.parametrize("name", ["2d_dir", "2d_neu", "2d_cf_neu", "3d_dir", "3d_neu_tiled"])
+@pytest.mark.parametrize("op,c0", OPS)
+def test_bottom_and_vcycle(name, op, c0):
+    lev = LAYOUTS[name]()
+    c = _c(op, c0, lev)
+    H, L = make_hier(lev, op, c)
+    M = mg.MG(lev, op, c)
+    bot = M.levels[-1]
+    f = random_field(bot, 8)
+    f = bot.comp_mean(f, M.sing[-1])
+    last = len(M.levels) - 1
+    fd_, ed_ = to_dev(H, L, last, f), torch.zeros(H.depth_size(L, last)[0], dtype=torch.float64, device="cuda")
+    H.bottom(L, fd_, ed_)
+    torch.cuda.synchronize()
+    assert relerr(from_dev(H, L, last, ed_, bot), M.bottom.solve(f), bot.mask) < TOL64
+    # one V(2,2) cycle on a consistent right-hand side
+    g = lev.comp_mean(random_field(lev, 9), M.sing[0])
+    gd = to_dev(H, L, 0, g)
+    e = torch.zeros_like(gd)
+    H.vcycle(L, gd, e)
+    torch.cuda.synchronize()
+    assert relerr(from_dev(H, L, 0, e, lev), M.vcycle(g), lev.mask) < TOL64
+    # and the same with red-black smoothing
+    M.smoother = "rb"
+    e = torch.zeros_like(gd)
+    H.vcycle(L, gd, e, A.default_opts(smoother=A.SMOOTH_RB))
+    torch.cuda.synchronize()
+    assert relerr(from_dev(H, L, 0, e, lev), M.vcycle(g), lev.mask) < TOL64
+
+
+@pytest.mark.parametrize("name", ["2d_dir", "2d_neu", "2d_mixed", "2d_cf_dir", "2d_cf_neu", "2d_gap", "3d_dir",
+                                  "3d_neu_tiled"])
+@pytest.mark.parametrize("op,c0", OPS)
+def test_solve_fp64_and_mixed(name, op, c0):
+    lev = LAYOUTS[name]()
+    c = _c(op, c0, lev)
+    H, L = make_hier(lev, op, c)
+    f = random_field(lev, 10)
+    fd = random_faces(lev, 11)
+    x_or, st_or = mg.solve(lev, f, op, c, fd, tol_rel=1e-12, max_cycles=200)
+    assert st_or["converged"]
+    sing = lev.singular_components(op)
+    fdd = faces_to_dev(H, L, lev, fd)
+    fdev = to_dev(H, L, 0, f)
+    for prec, tol in ((A.FP64, TOL64), (A.MIXED, 1e-9)):
+        x = torch.zeros_like(fdev)
+        st = H.solve(L, x, fdev, fdd, A.default_opts(precision=prec, tol_rel=1e-12, max_cycles=200))
+        assert st["status"] == 0 and st["converged"], st
+        got = lev.comp_mean(from_dev(H, L, 0, x, lev), sing)
+        assert relerr(got, lev.comp_mean(x_or, sing), lev.mask) < tol, (prec, st["cycles"], st_or["cycles"])
+        if prec == A.FP64:
+            # the same cycle, so the same residual history
+            hist = np.array(st["history"])
+            ho = np.array(st_or["history"])
+            assert len(hist) == len(ho)
+            assert np.allclose(hist[:4], ho[:4], rtol=1e-6, atol=1e-13 * ho[0])
+        if sing:
+            assert len(st["defects"]) == len(sing)
+            assert np.allclose(st["defects"], st_or["defects"], rtol=1e-9, atol=1e-12)
