@@ -1,0 +1,199 @@
+#!/usr/bin/env python
+"""Benchmark of the multigrid solve path: DOF/s to 1e-10 relative residual.
+
+One step = the two systems of the 3D single-level workload solved from
+x0 = 0 to ||r||_inf <= 1e-10 ||r0||_inf: the fourth-order Helmholtz system
+(I - cL) u = f with c = 0.5 nu k, nu = 1e-4, k = h, homogeneous Dirichlet
+conditions, and the pure-Neumann Poisson system L q = f, on 256^3 cells of
+[0,1]^3.  Right-hand sides are closed-form cell averages of
+sin(2 pi x) sin(2 pi y) sin(2 pi z) through (I - cL) and of
+cos(2 pi x) cos(2 pi y) cos(2 pi z) through L, plus seeded N(0, 1e-3^2)
+noise (the Poisson one made mean-free).  DOF per step = 2 * 256^3.
+
+Prints one JSON line.  --workload c1 runs the 2D 128^2 workload instead;
+--workload c4 the batch of 1024 independent 2D boxes.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--workload", default="c3", choices=["c1", "c3", "c4"])
+    p.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    p.add_argument("--smoother", default="jacobi", choices=["jacobi", "rb"])
+    p.add_argument("--n", type=int, default=0, help="cells per direction (default: the workload's)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-timing", action="store_true", help="skip the per-kernel event timing")
+    return p.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# workloads (inputs only; every solve step runs in the HIP library)
+def single_level_problems(dim, n, nu):
+    from paper_2506_02663_amd import workloads as W
+    h = 1.0 / n
+    c = 0.5 * nu * h
+    shape = (n,) * dim
+    helm = (1.0 + dim * 4 * math.pi ** 2 * c) * W.sinprod_avg(shape, h) + W.noise(shape, 0)
+    pois = -dim * 4 * math.pi ** 2 * W.cosprod_avg(shape, h) + W.noise(shape, 1)
+    pois -= pois.mean()
+    return h, c, [("helmholtz", "D", helm), ("poisson", "N", pois)]
+
+
+def cpu_baseline(dim, n, nu):
+    """The FP64 oracle on a bounded sample of the same workload (same recipe,
+    smaller grid), single-threaded, timed on the host."""
+    import numpy as np
+
+    from oracle import mg
+    from oracle.level import Level
+    h, c, probs = single_level_problems(dim, n, nu)
+    dof = 0
+    t0 = time.perf_counter()
+    for op, bc, f in probs:
+        lev = Level((n,) * dim, h, [((0,) * dim, (n - 1,) * dim)], {(d, s): bc for d in range(dim) for s in (0, 1)})
+        fa = lev.zeros()
+        fa[lev.inner] = f
+        x, st = mg.solve(lev, fa, op, c, tol_rel=1e-10, max_cycles=100)
+        assert st["converged"]
+        dof += lev.ncells
+    dt = time.perf_counter() - t0
+    return {"value": dof / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"{dim}D {n}^{dim}: Helmholtz (Dirichlet) + Neumann Poisson solves to 1e-10, "
+                      f"same recipe as the timed workload, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path in this build "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    if args.workload == "c3":
+        dim, n, nu = 3, args.n or 256, 1e-4
+        sample = (3, 32, 1e-4)
+    elif args.workload == "c1":
+        dim, n, nu = 2, args.n or 128, 1e-3
+        sample = (2, 64, 1e-3)
+    else:
+        return bench_batched(args)
+
+    base = None
+    if not args.no_cpu_baseline:
+        # before the GPU is touched: single-threaded numpy
+        base = cpu_baseline(*sample)
+
+    import torch
+
+    from paper_2506_02663_amd import amg as A
+
+    h, c, probs = single_level_problems(dim, n, nu)
+    prec = A.MIXED if args.precision == "mixed" else A.FP64
+    sm = A.SMOOTH_JACOBI if args.smoother == "jacobi" else A.SMOOTH_RB
+    opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100)
+    systems = []
+    for op, bc, f in probs:
+        H = A.Hierarchy(dim, (n,) * dim, h, 1)
+        H.set_level_boxes(0, [((0,) * dim, (n - 1,) * dim)])
+        for d in range(dim):
+            for s in (0, 1):
+                H.set_physical_bc(d, s, A.DIRICHLET if bc == "D" else A.NEUMANN)
+        H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c)
+        H.finalize()
+        fd = torch.tensor(H.pack(0, 0, lambda i, b: f), device="cuda")
+        x = torch.zeros_like(fd)
+        systems.append((op, H, x, fd))
+    del probs
+    dof_step = len(systems) * n ** dim
+
+    cycles = {}
+
+    def step():
+        for op, H, x, fd in systems:
+            x.zero_()
+            st = H.solve(0, x, fd, None, opts)
+            if st["status"] != 0 or not st["converged"]:
+                raise RuntimeError(f"{op} solve did not converge: {st}")
+            cycles[op] = st["cycles"]
+
+    for _ in range(args.warmup):
+        step()
+    if not args.no_timing:
+        for _, H, _, _ in systems:
+            H.timing(True)
+            for k in range(A.T_KINDS):
+                H.timing_read(k, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt * 1e3 / args.steps
+
+    out = {
+        "metric": "MG solve DOF/s to 1e-10 rel. residual, FP32-refined vs FP64; % HBM peak",
+        "value": dof_step * args.steps / dt,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-in-f64" if prec == A.MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{dim}D single level {n}^{dim}, Helmholtz (Dirichlet, nu={nu}) + Neumann Poisson",
+                   "cells": n ** dim, "dof_per_step": dof_step, "tol_rel": 1e-10,
+                   "cycles": cycles, "smoother": args.smoother, "precision": args.precision,
+                   "vcycle": "V(2,2)"},
+    }
+    if not args.no_timing:
+        # dominant kernel: the smoothing sweep on the finest depth
+        cnt, tot = 0, 0.0
+        kinds = {}
+        for _, H, _, _ in systems:
+            for k, name in enumerate(("sweep", "fill", "resid_restrict", "prolong", "residual64")):
+                c_, t_ = H.timing_read(k, reset=False)
+                a = kinds.setdefault(name, [0, 0.0])
+                a[0] += c_
+                a[1] += t_
+        cnt, tot = kinds["sweep"]
+        avg_s = tot / cnt / 1e3
+        word = 4 if prec == A.MIXED else 8
+        if args.smoother == "jacobi":
+            bytes_launch = 3 * word * n ** dim          # read u, read f, write u_new
+        else:
+            bytes_launch = 2.5 * word * n ** dim        # read u, f on one colour, write u_new
+        ach = bytes_launch / avg_s / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": f"{args.smoother} sweep, finest depth, {'FP32' if word == 4 else 'FP64'}",
+                           "avg_us": avg_s * 1e6, "launches": cnt, "bytes_per_launch": bytes_launch}
+        out["kernel_ms_per_step"] = {k: v[1] / args.steps for k, v in kinds.items()}
+    if base is not None:
+        out["cpu_baseline"] = base
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    raise SystemExit("the batched workload is run by --workload c4 once it is built")
+
+
+if __name__ == "__main__":
+    main()

@@ -93,6 +93,14 @@ extern "C" {
 #define AMG_SOLV_RHS_SHIFT 0 /* shift the right-hand side to satisfy the discrete condition */
 #define AMG_SOLV_OFF 1       /* do nothing; report the defect */
 
+/* kernel kinds of the optional event timing (finest multigrid depth) */
+#define AMG_T_SWEEP 0     /* one smoothing sweep or half-sweep */
+#define AMG_T_FILL 1      /* one ghost fill */
+#define AMG_T_RESTRICT 2  /* fused residual and restriction */
+#define AMG_T_PROLONG 3   /* prolongation and correction */
+#define AMG_T_RESIDUAL 4  /* outer FP64 residual with its norm partials */
+#define AMG_T_KINDS 5
+
 #define AMG_MAX_HISTORY 128
 #define AMG_MAX_COMP 64
 
@@ -230,6 +238,17 @@ int amg_bottom(amg_hier* h, int level, int dtype, const void* f, void* e, void* 
 
 /* One homogeneous V(nu1,nu2) cycle from e = 0 on the level: e ~= A^-1 f. */
 int amg_vcycle(amg_hier* h, int level, int dtype, const amg_solve_opts* opts, const void* f, void* e, void* stream);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/* on != 0: every later amg_solve records a HIP event before and after each
+ * launch of the AMG_T_* kernels on the finest depth (on the solve's stream)
+ * and accumulates their durations; creates the event pool on first use. */
+int amg_timing_enable(amg_hier* h, int on);
+
+/* Launch count and summed duration (ms) of kernel kind `kind` since the last
+ * reset; reset != 0 clears the counters after reading. */
+int amg_timing_read(amg_hier* h, int kind, int64_t* count, double* total_ms, int reset);
 
 #ifdef __cplusplus
 }

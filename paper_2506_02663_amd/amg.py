@@ -21,6 +21,7 @@ SMOOTH_JACOBI, SMOOTH_RB = 0, 1
 FP64, MIXED = 0, 1
 F64, F32 = 0, 1
 SOLV_RHS_SHIFT, SOLV_OFF = 0, 1
+T_SWEEP, T_FILL, T_RESTRICT, T_PROLONG, T_RESIDUAL, T_KINDS = range(6)
 MAX_HISTORY, MAX_COMP = 128, 64
 
 
@@ -86,6 +87,8 @@ def lib():
         L.amg_prolong.argtypes = [vp, i32, i32, i32, vp, vp, vp]
         L.amg_bottom.argtypes = [vp, i32, i32, vp, vp, vp]
         L.amg_vcycle.argtypes = [vp, i32, i32, C.POINTER(SolveOpts), vp, vp, vp]
+        L.amg_timing_enable.argtypes = [vp, i32]
+        L.amg_timing_read.argtypes = [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double), i32]
         _lib = L
     return _lib
 
@@ -317,6 +320,15 @@ class Hierarchy:
         self._need(f, level, last, "f")
         self._need(e, level, last, "e", (f.dtype,))
         self._check(lib().amg_bottom(self.h, level, self._dt(f), _ptr(f), _ptr(e), _stream()))
+
+    def timing(self, on=True):
+        self._check(lib().amg_timing_enable(self.h, int(on)))
+
+    def timing_read(self, kind, reset=True):
+        n = C.c_int64()
+        ms = C.c_double()
+        self._check(lib().amg_timing_read(self.h, kind, C.byref(n), C.byref(ms), int(reset)))
+        return n.value, ms.value
 
     def vcycle(self, level, f, e, opts=None):
         self._need(f, level, 0, "f")

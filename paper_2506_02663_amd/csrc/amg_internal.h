@@ -132,7 +132,21 @@ struct Level {
 
 }  // namespace amg
 
+namespace amg {
+// Optional per-kernel timing with HIP events recorded on the solve's stream
+// around the launches of a few kernel kinds (finest depth only).
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+  std::vector<std::pair<int, size_t>> pending;  // (kind, index of the start event)
+  int64_t count[AMG_T_KINDS] = {};
+  double total_ms[AMG_T_KINDS] = {};
+};
+}  // namespace amg
+
 struct amg_hier {
+  amg::Timer timer;
   int dim = 2;
   int32_t base[3] = {1, 1, 1};
   double h0 = 1;

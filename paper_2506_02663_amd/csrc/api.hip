@@ -91,6 +91,38 @@ struct Run {
   hipStream_t st;
 };
 
+// event timing around launches of one kernel kind (finest depth only)
+struct Timed {
+  Timer* t;
+  hipStream_t st;
+  bool active;
+  size_t idx;
+  Timed(const Run& R, int kind, int depth) : t(&R.H->timer), st(R.st), active(false), idx(0) {
+    if (!t->on || depth != 0 || t->next + 2 > t->pool.size()) return;
+    active = true;
+    idx = t->next;
+    t->pending.push_back({kind, idx});
+    (void)hipEventRecord(t->pool[idx], st);
+    t->next += 2;
+  }
+  ~Timed() {
+    if (active) (void)hipEventRecord(t->pool[idx + 1], st);
+  }
+};
+
+// accumulate the durations of all recorded pairs (after the stream is idle)
+void collect_timing(Timer& t) {
+  for (auto& p : t.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.pool[p.second], t.pool[p.second + 1]) == hipSuccess) {
+      t.count[p.first] += 1;
+      t.total_ms[p.first] += ms;
+    }
+  }
+  t.pending.clear();
+  t.next = 0;
+}
+
 // Subtract the per-component mean on every singular component (depth k).
 template <typename T>
 void remove_mean(const Run& R, int k, T* a) {
@@ -122,8 +154,14 @@ void smooth(const Run& R, int k, int smoother, int nsweeps, double omega, bool f
         launch_jacobi<T>(R.dim, D, nullptr, f, cur, alpha, beta, (T)omega, true, R.st);
         continue;
       }
-      launch_fill<T>(D, cur, nullptr, R.st);
-      launch_jacobi<T>(R.dim, D, cur, f, oth, alpha, beta, (T)omega, false, R.st);
+      {
+        Timed tm(R, AMG_T_FILL, k);
+        launch_fill<T>(D, cur, nullptr, R.st);
+      }
+      {
+        Timed tm(R, AMG_T_SWEEP, k);
+        launch_jacobi<T>(R.dim, D, cur, f, oth, alpha, beta, (T)omega, false, R.st);
+      }
       std::swap(cur, oth);
     }
   } else {
@@ -133,8 +171,14 @@ void smooth(const Run& R, int k, int smoother, int nsweeps, double omega, bool f
           launch_rb<T>(R.dim, D, nullptr, f, cur, alpha, beta, 0, true, R.st);
           continue;
         }
-        launch_fill<T>(D, cur, nullptr, R.st);
-        launch_rb<T>(R.dim, D, cur, f, oth, alpha, beta, col, false, R.st);
+        {
+          Timed tm(R, AMG_T_FILL, k);
+          launch_fill<T>(D, cur, nullptr, R.st);
+        }
+        {
+          Timed tm(R, AMG_T_SWEEP, k);
+          launch_rb<T>(R.dim, D, cur, f, oth, alpha, beta, col, false, R.st);
+        }
         std::swap(cur, oth);
       }
   }
@@ -164,15 +208,25 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0) {
     smooth<T>(R, k, o.smoother, o.nu1, o.omega, true, cur[k], oth[k], f[k]);
     T alpha, beta;
     coefs<T>(R.H, D, alpha, beta);
-    launch_fill<T>(D, cur[k], nullptr, R.st);
-    launch_resid_restrict<T>(R.dim, D, L.depths[k + 1], cur[k], f[k], Bufs<T>::f(L.depths[k + 1]), alpha, beta, R.st);
+    {
+      Timed tm(R, AMG_T_FILL, k);
+      launch_fill<T>(D, cur[k], nullptr, R.st);
+    }
+    {
+      Timed tm(R, AMG_T_RESTRICT, k);
+      launch_resid_restrict<T>(R.dim, D, L.depths[k + 1], cur[k], f[k], Bufs<T>::f(L.depths[k + 1]), alpha, beta,
+                               R.st);
+    }
     remove_mean<T>(R, k + 1, Bufs<T>::f(L.depths[k + 1]));
   }
   for (int k = K - 2; k >= 0; --k) {
     Depth& D = L.depths[k];
     if (D.stiles.empty()) continue;
     launch_fill<T>(L.depths[k + 1], cur[k + 1], nullptr, R.st);
-    launch_prolong<T>(R.dim, D, L.depths[k + 1], cur[k + 1], cur[k], R.st);
+    {
+      Timed tm(R, AMG_T_PROLONG, k);
+      launch_prolong<T>(R.dim, D, L.depths[k + 1], cur[k + 1], cur[k], R.st);
+    }
     smooth<T>(R, k, o.smoother, o.nu2, o.omega, false, cur[k], oth[k], f[k]);
   }
   return cur[0];
@@ -245,6 +299,7 @@ int amg_create(int dim, const int32_t* base_cells, double h0, int ratio, int nle
 
 int amg_destroy(amg_hier* H) {
   if (!H) return AMG_OK;
+  for (auto& e : H->timer.pool) (void)hipEventDestroy(e);
   for (auto& L : H->levels) free_level(L);
   if (H->own) (void)hipStreamDestroy(H->own);
   delete H;
@@ -606,7 +661,10 @@ int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const doubl
   coefs<double>(H, D0, alpha, beta);
   auto residual_norm = [&]() {
     launch_fill<double>(D0, X, FD, R.st);
-    launch_residual<double>(dim, D0, true, X, frhs, Rb, alpha, beta, L.partial, R.st);
+    {
+      Timed tm(R, AMG_T_RESIDUAL, 0);
+      launch_residual<double>(dim, D0, true, X, frhs, Rb, alpha, beta, L.partial, R.st);
+    }
     launch_reduce_max(L.partial, (int)D0.tiles.size(), L.scal + S_NORM, R.st);
   };
   auto read_norm = [&](double& v) -> int {
@@ -650,7 +708,29 @@ int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const doubl
     stats->rfinal = rn;
     stats->converged = rn <= target;
   }
+  if (H->timer.on) collect_timing(H->timer);
   if (rn > target) return fail(H, AMG_ENOTCONVERGED, "max_cycles reached");
+  return AMG_OK;
+}
+
+int amg_timing_enable(amg_hier* H, int on) {
+  if (!H) return AMG_EINVAL;
+  H->timer.on = on != 0;
+  if (H->timer.on && H->timer.pool.empty()) {
+    H->timer.pool.resize(8192);
+    for (auto& e : H->timer.pool) HIPCHK(hipEventCreate(&e));
+  }
+  return AMG_OK;
+}
+
+int amg_timing_read(amg_hier* H, int kind, int64_t* count, double* total_ms, int reset) {
+  if (!H || kind < 0 || kind >= AMG_T_KINDS) return AMG_EINVAL;
+  if (count) *count = H->timer.count[kind];
+  if (total_ms) *total_ms = H->timer.total_ms[kind];
+  if (reset) {
+    H->timer.count[kind] = 0;
+    H->timer.total_ms[kind] = 0.0;
+  }
   return AMG_OK;
 }
 
