@@ -134,6 +134,8 @@ typedef struct {
   double omega;          /* weighted-Jacobi factor (2/3 in the paper) */
   double tol_rel;        /* stop when ||r||_inf <= max(tol_rel ||r0||_inf, tol_abs) */
   double tol_abs;
+  int32_t use_graph;     /* 1: capture the outer cycle once into a HIP graph and replay it */
+  int32_t pad_;
 } amg_solve_opts;
 
 typedef struct {
@@ -143,6 +145,8 @@ typedef struct {
   double rfinal;                       /* ||f - A x||_inf at return */
   double history[AMG_MAX_HISTORY];     /* ||r||_inf after each cycle, history[0] = r0 */
   int32_t ncomp;
+  int32_t used_graph;                  /* 1 if the cycles ran as replays of a captured HIP graph */
+  int32_t pad_;
   double defect[AMG_MAX_COMP];         /* h^D sum f - h^(D-1) sum g per singular component, before the shift */
 } amg_solve_stats;
 
@@ -180,6 +184,17 @@ int amg_set_cf_mode(amg_hier* h, int level, int mode);
 
 /* Operator: AMG_HELMHOLTZ (I - c L), c > 0, or AMG_POISSON L (c ignored). */
 int amg_set_operator(amg_hier* h, int kind, double c);
+
+/* Tuning knobs of the kernels' work layout, set before amg_finalize:
+ * AMG_TUNE_MARCH2 / AMG_TUNE_MARCH3: the longest march (cells a tile walks
+ * along the last direction) in 2D / 3D, even, 2..4096; each multigrid depth
+ * uses the longest even march up to it that still gives about 1024 tiles; AMG_TUNE_ROW_ALIGN: rows of the packed
+ * layout are padded so that every box row starts on a multiple of this many
+ * elements (power of two, 2..256).  They change speed, not results. */
+#define AMG_TUNE_MARCH2 0
+#define AMG_TUNE_MARCH3 1
+#define AMG_TUNE_ROW_ALIGN 2
+int amg_set_tuning(amg_hier* h, int key, int value);
 
 /* Validates the layout (disjoint boxes inside the grid, proper refinement
  * eq. (pBlock), boxes of at least 4 cells per side), labels components,

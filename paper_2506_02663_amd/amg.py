@@ -22,6 +22,7 @@ FP64, MIXED = 0, 1
 F64, F32 = 0, 1
 SOLV_RHS_SHIFT, SOLV_OFF = 0, 1
 T_SWEEP, T_FILL, T_RESTRICT, T_PROLONG, T_RESIDUAL, T_KINDS = range(6)
+TUNE_MARCH2, TUNE_MARCH3, TUNE_ROW_ALIGN = range(3)
 MAX_HISTORY, MAX_COMP = 128, 64
 
 
@@ -38,17 +39,19 @@ class BoxDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("smoother", C.c_int32), ("precision", C.c_int32),
                 ("solvability", C.c_int32), ("max_cycles", C.c_int32), ("omega", C.c_double),
-                ("tol_rel", C.c_double), ("tol_abs", C.c_double)]
+                ("tol_rel", C.c_double), ("tol_abs", C.c_double), ("use_graph", C.c_int32), ("pad_", C.c_int32)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("cycles", C.c_int32), ("converged", C.c_int32), ("r0", C.c_double), ("rfinal", C.c_double),
-                ("history", C.c_double * MAX_HISTORY), ("ncomp", C.c_int32), ("defect", C.c_double * MAX_COMP)]
+                ("history", C.c_double * MAX_HISTORY), ("ncomp", C.c_int32), ("used_graph", C.c_int32),
+                ("pad_", C.c_int32), ("defect", C.c_double * MAX_COMP)]
 
     def as_dict(self):
         n = min(self.cycles + 1, MAX_HISTORY)
         return {"cycles": self.cycles, "converged": bool(self.converged), "r0": self.r0, "rfinal": self.rfinal,
-                "history": list(self.history[:n]), "defects": list(self.defect[: self.ncomp])}
+                "history": list(self.history[:n]), "defects": list(self.defect[: self.ncomp]),
+                "graph": bool(self.used_graph)}
 
 
 _lib = None
@@ -88,6 +91,7 @@ def lib():
         L.amg_bottom.argtypes = [vp, i32, i32, vp, vp, vp]
         L.amg_vcycle.argtypes = [vp, i32, i32, C.POINTER(SolveOpts), vp, vp, vp]
         L.amg_timing_enable.argtypes = [vp, i32]
+        L.amg_set_tuning.argtypes = [vp, i32, i32]
         L.amg_timing_read.argtypes = [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double), i32]
         _lib = L
     return _lib
@@ -164,6 +168,9 @@ class Hierarchy:
     def set_operator(self, kind, c=0.0):
         self._check(lib().amg_set_operator(self.h, kind, float(c)))
 
+    def set_tuning(self, key, value):
+        self._check(lib().amg_set_tuning(self.h, key, int(value)))
+
     def finalize(self):
         self._check(lib().amg_finalize(self.h))
 
@@ -196,9 +203,11 @@ class Hierarchy:
     # ---- dense <-> packed (pure indexing) ----
     def _box_view(self, flat, b, ghosts=False):
         n = [hi - lo + 1 for lo, hi in zip(b["lo"], b["hi"])]
-        shape = [m + 4 for m in n][::-1]  # (z, y, x) in memory order
-        size = int(np.prod(shape))
-        blk = flat[b["offset"]: b["offset"] + size].reshape(shape)
+        st = b["stride"]
+        rows = int(np.prod([m + 4 for m in n[1:]]))  # stored rows of the box
+        blk = flat[b["offset"]: b["offset"] + rows * st[1]]
+        shape = [m + 4 for m in n[1:]][::-1] + [st[1]]  # (z, y, padded x) in memory order
+        blk = blk.reshape(shape)[..., : n[0] + 4]
         if ghosts:
             return blk
         return blk[tuple(slice(2, 2 + m) for m in n[::-1])]

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/amg.h"
+#include "tiles.h"
 
 namespace amg {
 
@@ -37,11 +38,15 @@ struct BoxD {              // one box at one multigrid depth
   int32_t comp;            // component id
   int32_t fine;            // index of the same box at depth-1 (-1 at depth 0)
   int32_t coarse;          // index at depth+1, -1 if the box ends here
-  int32_t pad;
+  uint8_t ucode[3][2];     // column code shared by a whole face, 0xFF if the face mixes codes
+  uint8_t pad[2];
 };
 
-struct TileD {             // a tile of cells of one box
-  int32_t box, x0, y0, z0;
+struct TileD {             // a column block of one box, marched along the last direction
+  int32_t box;
+  int32_t x0, y0, z0;      // first cell (2D: y0 is the first row of the march)
+  int32_t len;             // cells along the march direction
+  int32_t pad[3];
 };
 
 struct ChunkD {            // up to 64 consecutive ghost columns of one face
@@ -56,6 +61,9 @@ struct ChunkD {            // up to 64 consecutive ghost columns of one face
   uint8_t kind1, kind2;
   uint8_t pad[6];
 };
+
+constexpr int kSeg = 2048;          // tiles per first-stage reduction segment
+constexpr int64_t kTargetTiles = 1024;  // tiles a depth should offer the 256 CUs
 
 struct BottomGroupD {      // systems sharing one dense inverse
   int64_t mat;             // offset of the n x n inverse (column-major) in the matrix pool
@@ -84,25 +92,44 @@ struct Depth {
   std::vector<ChunkD> chunks;
   std::vector<TileD> tiles;          // all boxes at this depth
   std::vector<TileD> stiles;         // boxes that smooth at this depth (not at their bottom)
-  std::vector<int32_t> tile_comp_ptr, tile_comp_idx;   // CSR: tiles of each component
+  std::vector<int32_t> seg_ptr;       // reduction segments: ranges of at most kSeg tiles within one component
+  std::vector<int32_t> comp_seg_ptr;  // segments of each component (range into seg_ptr)
   std::vector<int32_t> chunk_comp_ptr, chunk_comp_idx; // CSR: chunks of each component
   std::vector<int32_t> bottom_boxes; // boxes solved exactly at this depth
   std::vector<BottomGroupD> groups;
   int64_t nstored = 0;
+  int march = 2;  // cells each tile marches along the last direction
   // device copies
   BoxD* d_box = nullptr;
   uint8_t* d_codes = nullptr;
   ChunkD* d_chunks = nullptr;
   TileD* d_tiles = nullptr;
   TileD* d_stiles = nullptr;
-  int32_t *d_tc_ptr = nullptr, *d_tc_idx = nullptr, *d_cc_ptr = nullptr, *d_cc_idx = nullptr;
+  int32_t *d_seg = nullptr, *d_cseg = nullptr, *d_cc_ptr = nullptr, *d_cc_idx = nullptr;
   BottomGroupD* d_groups = nullptr;
   // work buffers (FP64 and FP32): correction, right-hand side, second buffer
   double *e64 = nullptr, *f64 = nullptr, *t64 = nullptr;
   float *e32 = nullptr, *f32 = nullptr, *t32 = nullptr;
 };
 
+struct GraphCache {  // the captured outer cycle of one level
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int64_t> key;
+  std::vector<std::pair<int, size_t>> timed;  // event pairs inside the graph
+  bool broken = false;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    key.clear();
+    timed.clear();
+  }
+};
+
 struct Level {
+  GraphCache graph;
   std::vector<Box> boxes;
   bool isolated = false;
   int cf_mode = AMG_CF_DIRICHLET;
@@ -119,7 +146,8 @@ struct Level {
   int64_t* d_idx = nullptr;
   double* r64 = nullptr;     // outer residual
   double* fsh = nullptr;     // right-hand side after the solvability shift
-  double* partial = nullptr; // tile partials (max over all depth-0 sizes)
+  double* partial = nullptr; // tile partials (max over all depths)
+  double* partial2 = nullptr; // segment partials
   double* comp_sum = nullptr;
   int32_t* d_comp_flag = nullptr;  // 1 on singular components
   double* d_comp_cnt = nullptr;    // cells per component at each depth [depth*ncomp + c]
@@ -139,6 +167,7 @@ struct Timer {
   bool on = false;
   std::vector<hipEvent_t> pool;
   size_t next = 0;
+  size_t base = 0;  // events below base belong to a captured graph
   std::vector<std::pair<int, size_t>> pending;  // (kind, index of the start event)
   int64_t count[AMG_T_KINDS] = {};
   double total_ms[AMG_T_KINDS] = {};
@@ -147,6 +176,8 @@ struct Timer {
 
 struct amg_hier {
   amg::Timer timer;
+  int march2 = MARCH2_DEFAULT, march3 = MARCH3_DEFAULT;  // tile march lengths
+  int row_align = ROW_ALIGN_DEFAULT;                       // row alignment of the packed layout (elements)
   int dim = 2;
   int32_t base[3] = {1, 1, 1};
   double h0 = 1;

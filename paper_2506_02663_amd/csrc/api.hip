@@ -110,17 +110,39 @@ struct Timed {
   }
 };
 
-// accumulate the durations of all recorded pairs (after the stream is idle)
-void collect_timing(Timer& t) {
-  for (auto& p : t.pending) {
+// accumulate the durations of recorded event pairs (after the stream is idle)
+void accumulate(Timer& t, const std::vector<std::pair<int, size_t>>& pairs) {
+  for (auto& p : pairs) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, t.pool[p.second], t.pool[p.second + 1]) == hipSuccess) {
       t.count[p.first] += 1;
       t.total_ms[p.first] += ms;
+    } else {
+      (void)hipGetLastError();
     }
   }
+}
+
+void collect_timing(Timer& t) {
+  accumulate(t, t.pending);
   t.pending.clear();
-  t.next = 0;
+  t.next = t.base;
+}
+
+// per-component sums of the tile partials in L.partial (two fixed-order stages)
+void comp_sums(const Run& R, const Depth& D, double* out) {
+  Level& L = *R.L;
+  const int nseg = (int)D.seg_ptr.size() - 1;
+  launch_seg_reduce(L.partial, D.d_seg, nseg, 0, L.partial2, false, R.st);
+  launch_seg_reduce(L.partial2, D.d_cseg, L.ncomp, 0, out, false, R.st);
+}
+
+// max of the tile partials in L.partial
+void global_max(const Run& R, const Depth& D, double* out) {
+  Level& L = *R.L;
+  const int nseg = (int)D.seg_ptr.size() - 1;
+  launch_seg_reduce(L.partial, D.d_seg, nseg, 0, L.partial2, true, R.st);
+  launch_seg_reduce(L.partial2, nullptr, 1, nseg, out, true, R.st);
 }
 
 // Subtract the per-component mean on every singular component (depth k).
@@ -130,7 +152,7 @@ void remove_mean(const Run& R, int k, T* a) {
   if (!L.nsingular) return;
   Depth& D = L.depths[k];
   launch_tile_sum<T>(R.dim, D, a, L.partial, R.st);
-  launch_comp_sum(L.partial, D.d_tc_ptr, D.d_tc_idx, L.ncomp, L.comp_sum, R.st);
+  comp_sums(R, D, L.comp_sum);
   launch_comp_delta(L.comp_sum, nullptr, L.d_comp_flag, L.d_comp_cnt + (size_t)k * L.ncomp, L.ncomp, 1.0, 0.0,
                     L.d_delta, nullptr, R.st);
   launch_comp_shift<T>(R.dim, D, a, L.d_delta, R.st);
@@ -250,11 +272,11 @@ hipStream_t stream_of(amg_hier* H, void* s) { return s ? (hipStream_t)s : H->own
 void free_level(amg::Level& L) {
   for (auto& D : L.depths) {
     for (void* p : {(void*)D.d_box, (void*)D.d_codes, (void*)D.d_chunks, (void*)D.d_tiles, (void*)D.d_stiles,
-                    (void*)D.d_tc_ptr, (void*)D.d_tc_idx, (void*)D.d_cc_ptr, (void*)D.d_cc_idx, (void*)D.d_groups,
+                    (void*)D.d_seg, (void*)D.d_cseg, (void*)D.d_cc_ptr, (void*)D.d_cc_idx, (void*)D.d_groups,
                     (void*)D.e64, (void*)D.f64, (void*)D.t64, (void*)D.e32, (void*)D.f32, (void*)D.t32})
       if (p) (void)hipFree(p);
   }
-  for (void* p : {(void*)L.d_mat, (void*)L.d_idx, (void*)L.r64, (void*)L.fsh, (void*)L.partial, (void*)L.comp_sum,
+  for (void* p : {(void*)L.d_mat, (void*)L.d_idx, (void*)L.r64, (void*)L.fsh, (void*)L.partial, (void*)L.partial2, (void*)L.comp_sum,
                   (void*)L.scal, (void*)L.d_comp_flag, (void*)L.d_comp_cnt, (void*)L.d_delta, (void*)L.d_bsum,
                   (void*)L.d_defect})
     if (p) (void)hipFree(p);
@@ -277,6 +299,7 @@ void amg_default_opts(amg_solve_opts* o) {
   o->omega = 2.0 / 3.0;
   o->tol_rel = 1e-10;
   o->tol_abs = 0.0;
+  o->use_graph = 1;
 }
 
 int amg_create(int dim, const int32_t* base_cells, double h0, int ratio, int nlevels, amg_hier** out) {
@@ -299,6 +322,7 @@ int amg_create(int dim, const int32_t* base_cells, double h0, int ratio, int nle
 
 int amg_destroy(amg_hier* H) {
   if (!H) return AMG_OK;
+  for (auto& L : H->levels) L.graph.release();
   for (auto& e : H->timer.pool) (void)hipEventDestroy(e);
   for (auto& L : H->levels) free_level(L);
   if (H->own) (void)hipStreamDestroy(H->own);
@@ -359,6 +383,24 @@ int amg_set_operator(amg_hier* H, int kind, double c) {
   return AMG_OK;
 }
 
+int amg_set_tuning(amg_hier* H, int key, int value) {
+  if (!H) return AMG_EINVAL;
+  if (H->finalized) return fail(H, AMG_EINVAL, "layout is final");
+  switch (key) {
+    case AMG_TUNE_MARCH2:
+    case AMG_TUNE_MARCH3:
+      if (value < 2 || value > 4096 || (value & 1)) return fail(H, AMG_EINVAL, "march length must be even, 2..4096");
+      (key == AMG_TUNE_MARCH2 ? H->march2 : H->march3) = value;
+      return AMG_OK;
+    case AMG_TUNE_ROW_ALIGN:
+      if (value < 2 || value > 256 || (value & (value - 1)))
+        return fail(H, AMG_EINVAL, "alignment must be a power of two of at least 2");
+      H->row_align = value;
+      return AMG_OK;
+  }
+  return fail(H, AMG_EINVAL, "unknown tuning key");
+}
+
 int amg_finalize(amg_hier* H) {
   if (!H) return AMG_EINVAL;
   if (H->finalized) return fail(H, AMG_EINVAL, "already final");
@@ -375,15 +417,15 @@ int amg_finalize(amg_hier* H) {
     if (rc != AMG_OK) return fail(H, rc, err);
     TRY(upload(H, &L.d_mat, mats));
     TRY(upload(H, &L.d_idx, idx));
-    size_t maxpart = 1;
+    size_t maxpart = 1, maxseg = 1;
     for (auto& D : L.depths) {
       TRY(upload(H, &D.d_box, D.boxd));
       TRY(upload(H, &D.d_codes, D.codes));
       TRY(upload(H, &D.d_chunks, D.chunks));
       TRY(upload(H, &D.d_tiles, D.tiles));
       TRY(upload(H, &D.d_stiles, D.stiles));
-      TRY(upload(H, &D.d_tc_ptr, D.tile_comp_ptr));
-      TRY(upload(H, &D.d_tc_idx, D.tile_comp_idx));
+      TRY(upload(H, &D.d_seg, D.seg_ptr));
+      TRY(upload(H, &D.d_cseg, D.comp_seg_ptr));
       TRY(upload(H, &D.d_cc_ptr, D.chunk_comp_ptr));
       TRY(upload(H, &D.d_cc_idx, D.chunk_comp_idx));
       TRY(upload(H, &D.d_groups, D.groups));
@@ -394,10 +436,12 @@ int amg_finalize(amg_hier* H) {
       TRY(zalloc(H, &D.f32, D.nstored));
       TRY(zalloc(H, &D.t32, D.nstored));
       maxpart = std::max(maxpart, std::max(D.tiles.size(), D.chunks.size()));
+      maxseg = std::max(maxseg, D.seg_ptr.size());
     }
     TRY(zalloc(H, &L.r64, L.depths[0].nstored));
     TRY(zalloc(H, &L.fsh, L.depths[0].nstored));
     TRY(zalloc(H, &L.partial, maxpart));
+    TRY(zalloc(H, &L.partial2, maxseg));
     TRY(zalloc(H, &L.comp_sum, L.ncomp));
     TRY(zalloc(H, &L.d_delta, L.ncomp));
     TRY(zalloc(H, &L.d_bsum, L.ncomp));
@@ -632,7 +676,7 @@ int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const doubl
   const double* frhs = F;
   if (L.nsingular) {
     launch_tile_sum<double>(dim, D0, F, L.partial, R.st);
-    launch_comp_sum(L.partial, D0.d_tc_ptr, D0.d_tc_idx, L.ncomp, L.comp_sum, R.st);
+    comp_sums(R, D0, L.comp_sum);
     const double* bsum = nullptr;
     if (FD) {
       launch_chunk_fdsum(D0, FD, L.partial, R.st);
@@ -665,7 +709,7 @@ int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const doubl
       Timed tm(R, AMG_T_RESIDUAL, 0);
       launch_residual<double>(dim, D0, true, X, frhs, Rb, alpha, beta, L.partial, R.st);
     }
-    launch_reduce_max(L.partial, (int)D0.tiles.size(), L.scal + S_NORM, R.st);
+    global_max(R, D0, L.scal + S_NORM);
   };
   auto read_norm = [&](double& v) -> int {
     HIPCHK(hipMemcpyAsync(L.h_scal, L.scal + S_NORM, sizeof(double), hipMemcpyDeviceToHost, R.st));
@@ -685,7 +729,8 @@ int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const doubl
     stats->r0 = r0;
     stats->history[0] = r0;
   }
-  while (rn > target && cycles < o.max_cycles) {
+  // one outer cycle: r -> V-cycle -> x += s e -> new residual and its norm
+  auto body = [&]() {
     remove_mean<double>(R, 0, Rb);
     if (mixed) {
       launch_to32(dim, D0, Rb, D0.f32, L.scal + S_NORM, R.st);
@@ -697,8 +742,56 @@ int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const doubl
     }
     remove_mean<double>(R, 0, X);
     residual_norm();
+  };
+  // the cycle is captured once into a HIP graph and replayed
+  GraphCache& G = L.graph;
+  // event timing needs per-launch events, which a replayed graph does not
+  // provide: with timing on, the cycle runs as direct launches
+  bool use_graph = o.use_graph != 0 && !G.broken && !H->timer.on;
+  if (use_graph) {
+    std::vector<int64_t> key = {(int64_t)(intptr_t)X, (int64_t)(intptr_t)frhs, (int64_t)(intptr_t)FD, o.precision,
+                                o.smoother, o.nu1, o.nu2, (int64_t)H->timer.on};
+    int64_t ob;
+    memcpy(&ob, &o.omega, sizeof ob);
+    key.push_back(ob);
+    if (!G.exec || G.key != key) {
+      G.release();
+      Timer& T = H->timer;
+      const size_t p0 = T.pending.size();
+      hipGraph_t g = nullptr;
+      hipError_t e1 = hipStreamBeginCapture(R.st, hipStreamCaptureModeRelaxed);
+      if (e1 == hipSuccess) {
+        body();
+        e1 = hipStreamEndCapture(R.st, &g);
+      }
+      hipGraphExec_t ex = nullptr;
+      if (e1 == hipSuccess && g) e1 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      if (e1 != hipSuccess || !ex) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        G.broken = true;  // fall back to direct launches from now on
+        use_graph = false;
+        T.pending.resize(p0);
+        T.next = T.base;
+      } else {
+        G.graph = g;
+        G.exec = ex;
+        G.key = key;
+        // event pairs captured into the graph are re-recorded by every replay
+        G.timed.assign(T.pending.begin() + p0, T.pending.end());
+        T.pending.resize(p0);
+        T.base = T.next;
+      }
+    }
+  }
+  while (rn > target && cycles < o.max_cycles) {
+    if (use_graph)
+      HIPCHK(hipGraphLaunch(G.exec, R.st));
+    else
+      body();
     HIPCHK(hipGetLastError());
     TRY(read_norm(rn));
+    if (use_graph && H->timer.on) accumulate(H->timer, G.timed);
     ++cycles;
     if (stats && cycles < AMG_MAX_HISTORY) stats->history[cycles] = rn;
     if (!std::isfinite(rn)) return fail(H, AMG_ENONFINITE, "non-finite residual");
@@ -707,6 +800,7 @@ int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const doubl
     stats->cycles = cycles;
     stats->rfinal = rn;
     stats->converged = rn <= target;
+    stats->used_graph = use_graph && cycles > 0;
   }
   if (H->timer.on) collect_timing(H->timer);
   if (rn > target) return fail(H, AMG_ENOTCONVERGED, "max_cycles reached");
@@ -716,6 +810,9 @@ int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const doubl
 int amg_timing_enable(amg_hier* H, int on) {
   if (!H) return AMG_EINVAL;
   H->timer.on = on != 0;
+  for (auto& L : H->levels) L.graph.release();  // recapture with or without events
+  H->timer.pending.clear();
+  H->timer.next = H->timer.base = 0;
   if (H->timer.on && H->timer.pool.empty()) {
     H->timer.pool.resize(8192);
     for (auto& e : H->timer.pool) HIPCHK(hipEventCreate(&e));

@@ -1,31 +1,31 @@
 // HIP kernels of the multigrid path for gfx950 (CDNA4).
 //
-// Every cell kernel walks a tile table that covers all boxes of one
-// multigrid depth of one level, one workgroup per tile, one thread per cell
-// (64-wide rows of x, the fastest direction, so each wavefront reads one
-// coalesced row segment).  Ghost values are read from the two stored ghost
-// layers; the diagonal of the operator with the ghost fill folded in is
-// computed on the fly from per-face column codes, so no coefficient array
-// is streamed.  All reductions are two-stage with a fixed order, so results
-// are bitwise reproducible.
+// Layout of the work.  Every cell kernel walks a tile table covering all
+// boxes of one multigrid depth of one level.  A tile is a column block that
+// is marched along the last direction (y in 2D, z in 3D): in 2D one
+// wavefront of 64 consecutive x cells, in 3D a 64 x 4 block of (x, y)
+// columns (four wavefronts).  Each thread keeps the five values of its own
+// column at offsets -2..+2 along the march direction in registers, so every
+// cell value is fetched from memory once per sweep for that direction; the
+// x (and y) neighbours are re-read from the L1/L2 caches, where the
+// neighbouring columns just put them.  Blocks are ordered so that each of
+// the 8 XCDs walks one contiguous part of the tile table (neighbouring tiles
+// share that XCD's L2).
+//
+// Ghost values are read from the two stored ghost layers.  The diagonal of
+// the operator with the ghost fill folded in is computed on the fly from
+// per-face column codes (no coefficient array is streamed), and its inverse
+// is a constant away from the faces.  All reductions are two-stage with a
+// fixed order, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "amg_internal.h"
 #include "kernels.h"
 #include "tiles.h"
 
 namespace amg {
-
-template <int DIM>
-struct Shape;
-template <>
-struct Shape<2> {
-  static constexpr int X = TILE2_X, Y = TILE2_Y, Z = 1;
-};
-template <>
-struct Shape<3> {
-  static constexpr int X = TILE3_X, Y = TILE3_Y, Z = TILE3_Z;
-};
 
 // Increment of the diagonal (in units of 1/(12 h^2)) from the ghost fill of
 // one face, for the cell at distance `dist` (0 or 1) from that face.  The
@@ -44,57 +44,130 @@ __device__ __forceinline__ T fold(uint8_t code, int dist) {
   return kind == 1 ? T(-43.0 / 12.0) : T(-0.9);
 }
 
-struct Cell {
-  int x, y, z;
-  int64_t c;
-  bool ok;
+// XCD-aware block order: the hardware hands consecutive workgroups to the 8
+// XCDs in turn, so block b runs on XCD b % 8.  Block b takes tile
+// (b % 8) * ceil(n/8) + b / 8: each XCD walks one contiguous eighth of the
+// (spatially ordered) tile table.
+__device__ __forceinline__ int tile_of_block(int n) {
+  const int per = (n + 7) >> 3;
+  const int t = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  return t < n ? t : -1;
+}
+
+template <int DIM>
+constexpr int block_threads() {
+  return DIM == 2 ? 64 : 256;
+}
+
+// One thread's column of a tile: cells (x, y, p) for p in [p0, p1), with p
+// the coordinate along the march direction (y in 2D, z in 3D).
+// Each thread owns two neighbouring x-columns (x, x+1), x even, so every
+// row access is a 2-element vector load (rows are aligned: the first
+// interior cell of every row sits on an even element).
+struct Column {
+  int x, y;        // x even; 2D: y unused
+  int p0, p1;
+  bool ok, ok1;    // cell x / cell x+1 inside the box
+  int64_t base;    // element of (x, y, stored march index 0)
+  int64_t sm;      // march stride
 };
 
 template <int DIM>
-__device__ __forceinline__ Cell tile_cell(const TileD& t, const BoxD& b) {
-  using S = Shape<DIM>;
+__device__ __forceinline__ Column column_of(const TileD& t, const BoxD& b) {
+  Column c;
   const int tid = threadIdx.x;
-  Cell q;
-  q.x = t.x0 + tid % S::X;
-  q.y = t.y0 + (tid / S::X) % S::Y;
-  q.z = DIM == 3 ? t.z0 + tid / (S::X * S::Y) : 0;
-  q.ok = q.x < b.n[0] && q.y < b.n[1] && (DIM == 2 || q.z < b.n[2]);
-  q.c = b.off + (q.x + 2) + (int64_t)(q.y + 2) * b.s[1] + (DIM == 3 ? (int64_t)(q.z + 2) * b.s[2] : 0);
-  return q;
+  c.x = t.x0 + 2 * (DIM == 2 ? tid : (tid & 63));
+  c.y = DIM == 2 ? 0 : t.y0 + (tid >> 6);
+  c.ok = c.x < b.n[0] && (DIM == 2 || c.y < b.n[1]);
+  c.ok1 = c.ok && c.x + 1 < b.n[0];
+  c.p0 = DIM == 2 ? t.y0 : t.z0;
+  c.p1 = min(c.p0 + t.len, b.n[DIM - 1]);
+  c.sm = b.s[DIM - 1];
+  c.base = b.off + (c.x + 2) + (DIM == 3 ? (int64_t)(c.y + 2) * b.s[1] : 0);
+  return c;
 }
 
-// sum over directions of (-u[-2] + 16u[-1] - 30u[0] + 16u[1] - u[2])
-template <typename T, int DIM>
-__device__ __forceinline__ T lap_sum(const T* __restrict__ u, int64_t c, const BoxD& b) {
-  T u0 = u[c];
-  T acc = T(-30 * DIM) * u0;
-  acc += T(16) * (u[c - 1] + u[c + 1]) - (u[c - 2] + u[c + 2]);
-  const int64_t sy = b.s[1];
-  acc += T(16) * (u[c - sy] + u[c + sy]) - (u[c - 2 * sy] + u[c + 2 * sy]);
-  if (DIM == 3) {
-    const int64_t sz = b.s[2];
-    acc += T(16) * (u[c - sz] + u[c + sz]) - (u[c - 2 * sz] + u[c + 2 * sz]);
-  }
-  return acc;
+// One x-column per thread over the same tiles (blocks of 128 threads in 2D,
+// 512 in 3D): lanes of a wavefront take 64 consecutive x cells.
+template <int DIM>
+__device__ __forceinline__ Column column1_of(const TileD& t, const BoxD& b) {
+  Column c;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  c.x = t.x0 + 64 * (w & 1) + lane;
+  c.y = DIM == 2 ? 0 : t.y0 + (w >> 1);
+  c.ok = c.x < b.n[0] && (DIM == 2 || c.y < b.n[1]);
+  c.ok1 = false;
+  c.p0 = DIM == 2 ? t.y0 : t.z0;
+  c.p1 = min(c.p0 + t.len, b.n[DIM - 1]);
+  c.sm = b.s[DIM - 1];
+  c.base = b.off + (c.x + 2) + (DIM == 3 ? (int64_t)(c.y + 2) * b.s[1] : 0);
+  return c;
 }
 
-// -30 DIM plus the folded fill increments of the faces within two cells
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+  T a, b;
+};
+template <typename T>
+__device__ __forceinline__ Pair<T> ld2(const T* p) {
+  return *reinterpret_cast<const Pair<T>*>(p);
+}
+template <typename T>
+__device__ __forceinline__ void st2(T* p, T a, T b) {
+  *reinterpret_cast<Pair<T>*>(p) = Pair<T>{a, b};
+}
+
+// element of cell (x, y, z) in box b (0-based interior indices)
+template <int DIM>
+__device__ __forceinline__ int64_t cell_index(const BoxD& b, int x, int y, int z) {
+  return b.off + (x + 2) + (int64_t)(y + 2) * b.s[1] + (DIM == 3 ? (int64_t)(z + 2) * b.s[2] : 0);
+}
+
+// folded diagonal increments of the faces within two cells of (x, y, z)
 template <typename T, int DIM>
-__device__ __forceinline__ T diag_units(const Cell& q, const BoxD& b, const uint8_t* __restrict__ codes) {
-  T S = T(-30 * DIM);
-  const int p[3] = {q.x, q.y, q.z};
+__device__ __forceinline__ T fold_at(const BoxD& b, const uint8_t* __restrict__ codes, int x, int y, int z) {
+  T S = T(0);
+  const int p[3] = {x, y, z};
+#pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const int lo = p[d], hi = b.n[d] - 1 - p[d];
     if (lo >= 2 && hi >= 2) continue;
     int col;
     if (DIM == 2)
-      col = d == 0 ? q.y : q.x;
+      col = d == 0 ? y : x;
     else
-      col = d == 0 ? q.y + b.n[1] * q.z : (d == 1 ? q.x + b.n[0] * q.z : q.x + b.n[0] * q.y);
+      col = d == 0 ? y + b.n[1] * z : (d == 1 ? x + b.n[0] * z : x + b.n[0] * y);
     if (lo < 2) S += fold<T>(codes[b.code_off[d][0] + col], lo);
     if (hi < 2) S += fold<T>(codes[b.code_off[d][1] + col], hi);
   }
   return S;
+}
+
+// true if (x, y, z) is within two cells of some face (the folded band)
+template <int DIM>
+__device__ __forceinline__ bool near_face(const BoxD& b, int x, int y, int z) {
+  bool r = x < 2 || x > b.n[0] - 3 || y < 2 || y > b.n[1] - 3;
+  if (DIM == 3) r = r || z < 2 || z > b.n[2] - 3;
+  return r;
+}
+
+// (16 (u[-1] + u[1]) - (u[-2] + u[2])) along the non-march directions
+template <typename T, int DIM>
+__device__ __forceinline__ T cross_sum(const T* __restrict__ u, int64_t c, const BoxD& b) {
+  T acc = T(16) * (u[c - 1] + u[c + 1]) - (u[c - 2] + u[c + 2]);
+  if (DIM == 3) {
+    const int64_t sy = b.s[1];
+    acc += T(16) * (u[c - sy] + u[c + sy]) - (u[c - 2 * sy] + u[c + 2 * sy]);
+  }
+  return acc;
+}
+
+// full stencil sum at c by direct loads (all directions)
+template <typename T, int DIM>
+__device__ __forceinline__ T lap_sum(const T* __restrict__ u, int64_t c, const BoxD& b) {
+  const int64_t sm = b.s[DIM - 1];
+  return cross_sum<T, DIM>(u, c, b) + T(16) * (u[c - sm] + u[c + sm]) - (u[c - 2 * sm] + u[c + 2 * sm]) +
+         T(-30 * DIM) * u[c];
 }
 
 template <typename T>
@@ -119,6 +192,452 @@ __device__ __forceinline__ T block_max(T v, T* sh) {
   if (threadIdx.x == 0)
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r = fmax(r, sh[i]);
   return r;
+}
+
+// ---------------------------------------------------------------------------
+// stencil sweeps marched along the last direction
+enum { OP_RESID = 0, OP_JACOBI = 1, OP_RB = 2, OP_RESTRICT = 3 };
+
+// Inverse of the folded diagonal along one thread's column.  The faces
+// across the march direction contribute a constant (from the per-face
+// uniform code; a face with mixed codes is looked up cell by cell); the two
+// faces at the ends of the march contribute only in the first and last two
+// cells, from the column's own codes.
+template <typename T, int DIM>
+struct DiagColumn {
+  T alpha, beta, Sfix, inv_mid, flo[2], fhi[2];
+  bool mixed;
+  int nm;
+  __device__ __forceinline__ void init(const BoxD& b, const uint8_t* __restrict__ codes, int x, int y, T a, T be,
+                                       bool ok) {
+    alpha = a;
+    beta = be;
+    Sfix = T(-30 * DIM);
+    mixed = false;
+    const int q[2] = {x, y};
+#pragma unroll
+    for (int d = 0; d < DIM - 1; ++d) {
+      const int lo = q[d], hi = b.n[d] - 1 - q[d];
+      if (lo < 2) {
+        const uint8_t cd = b.ucode[d][0];
+        if (cd == 0xFF) mixed = true;
+        else Sfix += fold<T>(cd, lo);
+      }
+      if (hi < 2) {
+        const uint8_t cd = b.ucode[d][1];
+        if (cd == 0xFF) mixed = true;
+        else Sfix += fold<T>(cd, hi);
+      }
+    }
+    constexpr int M = DIM - 1;
+    nm = b.n[M];
+    flo[0] = flo[1] = fhi[0] = fhi[1] = T(0);
+    if (ok) {
+      const int col = DIM == 2 ? x : x + b.n[0] * y;
+      const uint8_t cl = codes[b.code_off[M][0] + col], ch = codes[b.code_off[M][1] + col];
+      flo[0] = fold<T>(cl, 0);
+      flo[1] = fold<T>(cl, 1);
+      fhi[0] = fold<T>(ch, 0);
+      fhi[1] = fold<T>(ch, 1);
+    }
+    inv_mid = T(1) / (alpha + beta * Sfix);
+  }
+  // p: march coordinate; (x, y, z) of the cell for the mixed-face lookup
+  __device__ __forceinline__ T inv(const BoxD& b, const uint8_t* __restrict__ codes, int p, int x, int y,
+                                   int z) const {
+    if (mixed) return T(1) / (alpha + beta * (T(-30 * DIM) + fold_at<T, DIM>(b, codes, x, y, z)));
+    if (p >= 2 && p <= nm - 3) return inv_mid;
+    T S = Sfix;
+    if (p < 2) S += flo[p];
+    if (p > nm - 3) S += fhi[nm - 1 - p];
+    return T(1) / (alpha + beta * S);
+  }
+};
+
+// OP_RESID : out = f - A u (f == NULL: out = A u); PART: per-tile max |out|
+// OP_JACOBI: out = u + omega (f - A u) / diag
+// OP_RB    : out = u + (f - A u) / diag on cells of colour `col`, else u
+// with A u = alpha u + beta * (sum of the 1-D stencils of eq. discreteOps c).
+// Along the march direction the neighbours come from the thread's register
+// queue; across it they are re-read through the L1/L2 caches (the
+// neighbouring columns of the same tile and of the neighbouring tiles of
+// the same XCD have just fetched them).
+// One cell per thread and step; the neighbours across the march direction
+// are re-read through the L1/L2 caches (the neighbouring columns of the same
+// tile and the neighbouring tiles on the same XCD have just fetched them).
+template <typename T, int DIM, int OP, bool PART>
+__global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles, int ntiles,
+                                                const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
+                                                const T* __restrict__ u, const T* __restrict__ f, T* __restrict__ out,
+                                                T alpha, T beta, T omega, int col, double* __restrict__ part) {
+  __shared__ double sh[8];
+  const int ti = tile_of_block(ntiles);
+  if (ti < 0) return;
+  const TileD t = tiles[ti];
+  const BoxD b = boxes[t.box];
+  const Column C = column1_of<DIM>(t, b);
+  double vmax = 0.0;
+  if (C.ok) {
+    const int64_t sm = C.sm;
+    int64_t c = C.base + (int64_t)(C.p0 + 2) * sm;
+    T q0 = u[c - 2 * sm], q1 = u[c - sm], q2 = u[c], q3 = u[c + sm];
+    DiagColumn<T, DIM> dg;
+    if (OP != OP_RESID) dg.init(b, codes, C.x, C.y, alpha, beta, true);
+    const int par0 = (b.lo[0] + C.x + (DIM == 3 ? b.lo[1] + C.y : 0) + b.lo[DIM - 1]) & 1;
+    for (int p = C.p0; p < C.p1; ++p, c += sm) {
+      const T q4 = u[c + 2 * sm];
+      T ls = T(16) * (u[c - 1] + u[c + 1]) - (u[c - 2] + u[c + 2]) + T(16) * (q1 + q3) - (q0 + q4) +
+             T(-30 * DIM) * q2;
+      if (DIM == 3) {
+        const int64_t sy = b.s[1];
+        ls += T(16) * (u[c - sy] + u[c + sy]) - (u[c - 2 * sy] + u[c + 2 * sy]);
+      }
+      const T Au = alpha * q2 + beta * ls;
+      if (OP == OP_RESID) {
+        const T v = f ? f[c] - Au : Au;
+        out[c] = v;
+        if (PART) {
+          double av = fabs((double)v);
+          vmax = fmax(vmax, (av == av) ? av : (double)INFINITY);  // a NaN must not vanish in fmax
+        }
+      } else if (OP == OP_JACOBI || (((par0 + p) & 1) == col)) {
+        out[c] = q2 + (OP == OP_JACOBI ? omega : T(1)) * (f[c] - Au) *
+                          dg.inv(b, codes, p, C.x, DIM == 2 ? p : C.y, DIM == 2 ? 0 : p);
+      } else {
+        out[c] = q2;
+      }
+      q0 = q1;
+      q1 = q2;
+      q2 = q3;
+      q3 = q4;
+    }
+  }
+  if (PART) {
+    const double m = block_max<double>(vmax, sh);
+    if (threadIdx.x == 0) part[ti] = m;
+  }
+}
+
+// Two cells (x, x+1) per thread and step.  x neighbours: the two cells on
+// each side come from the adjacent lanes (shuffles); the end lanes of the
+// wavefront read them from memory.  y neighbours (3D): vector loads through
+// the caches.  OP_RESTRICT computes the residual like OP_RESID and averages
+// it over the 2^DIM children of each coarse cell on the fly (x pairs inside
+// the thread, z or y pairs over two steps, y pairs in 3D through LDS), so the
+// fine residual is never stored: out is the coarse right-hand side.
+template <typename T, int DIM, int OP, bool PART>
+__global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, int ntiles,
+                                               const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
+                                               const T* __restrict__ u, const T* __restrict__ f, T* __restrict__ out,
+                                               T alpha, T beta, T omega, int col, double* __restrict__ part,
+                                               const BoxD* __restrict__ cboxes) {
+  __shared__ double sh[4];
+  __shared__ T R[2][64];
+  const int ti = tile_of_block(ntiles);
+  if (ti < 0) return;
+  const TileD t = tiles[ti];
+  const BoxD b = boxes[t.box];
+  const Column C = column_of<DIM>(t, b);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // lanes up to two cells past the box feed the x-neighbours of the last cells
+  const bool has = C.x < b.n[0] + 2 && (DIM == 2 || C.y < b.n[1]);
+  const int64_t sm = C.sm, sy = b.s[1];
+  int64_t c = C.base + (int64_t)(C.p0 + 2) * sm;
+  Pair<T> q0{}, q1{}, q2{}, q3{}, q4{};
+  if (has) {
+    q0 = ld2(u + c - 2 * sm);
+    q1 = ld2(u + c - sm);
+    q2 = ld2(u + c);
+    q3 = ld2(u + c + sm);
+  }
+  DiagColumn<T, DIM> d0, d1;
+  if (OP == OP_JACOBI || OP == OP_RB) {
+    d0.init(b, codes, C.x, C.y, alpha, beta, C.ok);
+    d1.init(b, codes, C.x + 1, C.y, alpha, beta, C.ok1);
+  }
+  const int par0 = (b.lo[0] + C.x + (DIM == 3 ? b.lo[1] + C.y : 0) + b.lo[DIM - 1]) & 1;
+  double vmax = 0.0;
+  T acc = T(0);
+  for (int p = C.p0; p < C.p1; ++p, c += sm) {
+    if (has) q4 = ld2(u + c + 2 * sm);
+    T La = __shfl_up(q2.a, 1, 64), Lb = __shfl_up(q2.b, 1, 64);
+    T Ra = __shfl_down(q2.a, 1, 64), Rb = __shfl_down(q2.b, 1, 64);
+    T o0 = T(0), o1 = T(0);
+    if (C.ok) {
+      if (lane == 0) {
+        La = u[c - 2];
+        Lb = u[c - 1];
+      }
+      if (lane == 63) {
+        Ra = u[c + 2];
+        Rb = u[c + 3];
+      }
+      T s0 = T(16) * (Lb + q2.b) - (La + Ra) + T(16) * (q1.a + q3.a) - (q0.a + q4.a) + T(-30 * DIM) * q2.a;
+      T s1 = T(16) * (q2.a + Ra) - (Lb + Rb) + T(16) * (q1.b + q3.b) - (q0.b + q4.b) + T(-30 * DIM) * q2.b;
+      if (DIM == 3) {
+        const Pair<T> ym1 = ld2(u + c - sy), yp1 = ld2(u + c + sy), ym2 = ld2(u + c - 2 * sy),
+                      yp2 = ld2(u + c + 2 * sy);
+        s0 += T(16) * (ym1.a + yp1.a) - (ym2.a + yp2.a);
+        s1 += T(16) * (ym1.b + yp1.b) - (ym2.b + yp2.b);
+      }
+      const T A0 = alpha * q2.a + beta * s0, A1 = alpha * q2.b + beta * s1;
+      Pair<T> fv{};
+      if (OP != OP_RESID || f) fv = ld2(f + c);
+      if (OP == OP_RESID || OP == OP_RESTRICT) {
+        o0 = f ? fv.a - A0 : A0;
+        o1 = f ? fv.b - A1 : A1;
+        if (PART) {
+          double a0 = fabs((double)o0), a1 = C.ok1 ? fabs((double)o1) : 0.0;
+          a0 = (a0 == a0) ? a0 : (double)INFINITY;  // a NaN must not vanish in fmax
+          a1 = (a1 == a1) ? a1 : (double)INFINITY;
+          vmax = fmax(vmax, fmax(a0, a1));
+        }
+      } else {
+        const int cy = DIM == 2 ? p : C.y, cz = DIM == 2 ? 0 : p;
+        const bool u0 = OP == OP_JACOBI || (((par0 + p) & 1) == col);
+        const bool u1 = OP == OP_JACOBI || (((par0 + p + 1) & 1) == col);
+        const T wgt = OP == OP_JACOBI ? omega : T(1);
+        o0 = u0 ? q2.a + wgt * (fv.a - A0) * d0.inv(b, codes, p, C.x, cy, cz) : q2.a;
+        o1 = u1 ? q2.b + wgt * (fv.b - A1) * d1.inv(b, codes, p, C.x + 1, cy, cz) : q2.b;
+      }
+      if (OP != OP_RESTRICT) {
+        if (C.ok1)
+          st2(out + c, o0, o1);
+        else
+          out[c] = o0;
+      }
+    }
+    if (OP == OP_RESTRICT) {
+      acc += o0 + o1;  // x pair (fine sizes are even, so both cells exist)
+      if ((p - C.p0) & 1) {
+        if (DIM == 3) {
+          if (w & 1) R[w >> 1][lane] = acc;
+          __syncthreads();
+          if (!(w & 1) && C.ok) {
+            const BoxD cb = cboxes[b.coarse];
+            out[cell_index<DIM>(cb, C.x >> 1, C.y >> 1, p >> 1)] = (acc + R[w >> 1][lane]) * T(0.125);
+          }
+          __syncthreads();
+        } else if (C.ok) {
+          const BoxD cb = cboxes[b.coarse];
+          out[cell_index<DIM>(cb, C.x >> 1, p >> 1, 0)] = acc * T(0.25);
+        }
+        acc = T(0);
+      }
+    }
+    q0 = q1;
+    q1 = q2;
+    q2 = q3;
+    q3 = q4;
+  }
+  if (PART) {
+    const double m = block_max<double>(vmax, sh);
+    if (threadIdx.x == 0) part[ti] = m;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pointwise kernels over the same tiles (two columns per thread)
+#define FOR_COLUMN(DIM_)                                             \
+  const int ti = tile_of_block(ntiles);                             \
+  if (ti < 0) return;                                               \
+  const TileD t = tiles[ti];                                        \
+  const BoxD b = boxes[t.box];                                      \
+  const Column C = column_of<DIM_>(t, b);                           \
+  if (C.ok)                                                         \
+    for (int p = C.p0; p < C.p1; ++p)
+
+// first sweep from a zero iterate: Jacobi out = omega f / diag; red-black
+// (red half) out = f / diag on red cells, 0 on black ones
+template <typename T, int DIM, bool RB>
+__global__ void __launch_bounds__(256) k_sweep0(const TileD* __restrict__ tiles, int ntiles,
+                                                const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
+                                                const T* __restrict__ f, T* __restrict__ out, T alpha, T beta,
+                                                T omega) {
+  const int ti = tile_of_block(ntiles);
+  if (ti < 0) return;
+  const TileD t = tiles[ti];
+  const BoxD b = boxes[t.box];
+  const Column C = column_of<DIM>(t, b);
+  if (!C.ok) return;
+  DiagColumn<T, DIM> d0, d1;
+  d0.init(b, codes, C.x, C.y, alpha, beta, true);
+  d1.init(b, codes, C.x + 1, C.y, alpha, beta, C.ok1);
+  const int par0 = (b.lo[0] + C.x + (DIM == 3 ? b.lo[1] + C.y : 0) + b.lo[DIM - 1]) & 1;
+  const T w = RB ? T(1) : omega;
+  for (int p = C.p0; p < C.p1; ++p) {
+    const int cy = DIM == 2 ? p : C.y, cz = DIM == 2 ? 0 : p;
+    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+    const Pair<T> fv = C.ok1 ? ld2(f + c) : Pair<T>{f[c], T(0)};
+    const bool red0 = !RB || (((par0 + p) & 1) == 0), red1 = !RB || (((par0 + p + 1) & 1) == 0);
+    const T o0 = red0 ? w * fv.a * d0.inv(b, codes, p, C.x, cy, cz) : T(0);
+    const T o1 = red1 ? w * fv.b * d1.inv(b, codes, p, C.x + 1, cy, cz) : T(0);
+    if (C.ok1)
+      st2(out + c, o0, o1);
+    else
+      out[c] = o0;
+  }
+}
+
+// x += s e (x FP64, e FP32 or FP64), s = scal[0]
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_update(const TileD* __restrict__ tiles, int ntiles,
+                                                const BoxD* __restrict__ boxes, double* __restrict__ x,
+                                                const T* __restrict__ e, const double* __restrict__ scal) {
+  const double s = scal[0];
+  FOR_COLUMN(DIM) {
+    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+    if (C.ok1) {
+      const Pair<double> xv = ld2(x + c);
+      const Pair<T> ev = ld2(e + c);
+      st2(x + c, xv.a + s * (double)ev.a, xv.b + s * (double)ev.b);
+    } else {
+      x[c] += s * (double)e[c];
+    }
+  }
+}
+
+// r32 = fp32(r / s), s = scal[0]
+template <int DIM>
+__global__ void __launch_bounds__(256) k_to32(const TileD* __restrict__ tiles, int ntiles,
+                                              const BoxD* __restrict__ boxes, const double* __restrict__ r,
+                                              float* __restrict__ r32, const double* __restrict__ scal) {
+  const double inv = 1.0 / scal[0];
+  FOR_COLUMN(DIM) {
+    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+    if (C.ok1) {
+      const Pair<double> rv = ld2(r + c);
+      st2(r32 + c, (float)(rv.a * inv), (float)(rv.b * inv));
+    } else {
+      r32[c] = (float)(r[c] * inv);
+    }
+  }
+}
+
+// a -= delta[comp] (components with a zero delta untouched)
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_comp_shift(const TileD* __restrict__ tiles, int ntiles,
+                                                    const BoxD* __restrict__ boxes, T* __restrict__ a,
+                                                    const double* __restrict__ delta) {
+  FOR_COLUMN(DIM) {
+    const double d = delta[b.comp];
+    if (d == 0.0) break;
+    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+    a[c] = (T)((double)a[c] - d);
+    if (C.ok1) a[c + 1] = (T)((double)a[c + 1] - d);
+  }
+}
+
+// out = f - delta[comp]
+template <int DIM>
+__global__ void __launch_bounds__(256) k_shift_copy(const TileD* __restrict__ tiles, int ntiles,
+                                                    const BoxD* __restrict__ boxes, const double* __restrict__ f,
+                                                    double* __restrict__ out, const double* __restrict__ delta) {
+  FOR_COLUMN(DIM) {
+    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+    out[c] = f[c] - delta[b.comp];
+    if (C.ok1) out[c + 1] = f[c + 1] - delta[b.comp];
+  }
+}
+
+// per-tile sum (MAX = false) or max |.| (MAX = true) of the interior
+template <typename T, int DIM, bool MAX>
+__global__ void __launch_bounds__(256) k_tile_reduce(const TileD* __restrict__ tiles, int ntiles,
+                                                     const BoxD* __restrict__ boxes, const T* __restrict__ a,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int ti = tile_of_block(ntiles);
+  if (ti < 0) return;
+  const TileD t = tiles[ti];
+  const BoxD b = boxes[t.box];
+  const Column C = column_of<DIM>(t, b);
+  double v = 0.0;
+  if (C.ok)
+    for (int p = C.p0; p < C.p1; ++p) {
+      const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+      const double x0 = (double)a[c], x1 = C.ok1 ? (double)a[c + 1] : 0.0;
+      v = MAX ? fmax(v, fmax(fabs(x0), fabs(x1))) : v + (x0 + x1);
+    }
+  v = MAX ? block_max<double>(v, sh) : block_sum<double>(v, sh);
+  if (threadIdx.x == 0) part[ti] = v;
+}
+
+// ---------------------------------------------------------------------------
+// inter-depth transfers
+
+// residual of the fine cell c, by direct loads
+template <typename T, int DIM>
+__device__ __forceinline__ T resid_at(const T* __restrict__ u, const T* __restrict__ f, int64_t c, const BoxD& fb,
+                                      T alpha, T beta) {
+  return f[c] - (alpha * u[c] + beta * lap_sum<T, DIM>(u, c, fb));
+}
+
+// fused residual and restriction: fc = mean over the 2^DIM children of
+// (f - A u); marched over coarse tiles, two coarse cells per thread and step
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_resid_restrict(const TileD* __restrict__ tiles, int ntiles,
+                                                        const BoxD* __restrict__ boxes,
+                                                        const BoxD* __restrict__ fboxes, const T* __restrict__ u,
+                                                        const T* __restrict__ f, T* __restrict__ fc, T alpha,
+                                                        T beta) {
+  FOR_COLUMN(DIM) {
+    const int cy = DIM == 2 ? p : C.y, cz = DIM == 2 ? 0 : p;
+    const BoxD fb = fboxes[b.fine];
+    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (j == 1 && !C.ok1) break;
+      T acc = T(0);
+#pragma unroll
+      for (int a = 0; a < (1 << DIM); ++a)
+        acc += resid_at<T, DIM>(u, f,
+                                cell_index<DIM>(fb, 2 * (C.x + j) + (a & 1), 2 * cy + ((a >> 1) & 1),
+                                                DIM == 3 ? 2 * cz + ((a >> 2) & 1) : 0),
+                                fb, alpha, beta);
+      fc[c + j] = acc * T(DIM == 2 ? 0.25 : 0.125);
+    }
+  }
+}
+
+// plain restriction: fc = mean of the 2^DIM children of r
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_restrict(const TileD* __restrict__ tiles, int ntiles,
+                                                  const BoxD* __restrict__ boxes, const BoxD* __restrict__ fboxes,
+                                                  const T* __restrict__ r, T* __restrict__ fc) {
+  FOR_COLUMN(DIM) {
+    const int cy = DIM == 2 ? p : C.y, cz = DIM == 2 ? 0 : p;
+    const BoxD fb = fboxes[b.fine];
+    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (j == 1 && !C.ok1) break;
+      T acc = T(0);
+#pragma unroll
+      for (int a = 0; a < (1 << DIM); ++a)
+        acc += r[cell_index<DIM>(fb, 2 * (C.x + j) + (a & 1), 2 * cy + ((a >> 1) & 1),
+                                 DIM == 3 ? 2 * cz + ((a >> 2) & 1) : 0)];
+      fc[c + j] = acc * T(DIM == 2 ? 0.25 : 0.125);
+    }
+  }
+}
+
+// u += face-neighbour linear interpolation of the coarse correction:
+// (1 - DIM/4) e_P + 1/4 sum_d e_{P + s_d e_d}, s_d the child's side;
+// marched over fine tiles.  The thread's two cells x, x+1 share the parent.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_prolong(const TileD* __restrict__ tiles, int ntiles,
+                                                 const BoxD* __restrict__ boxes, const BoxD* __restrict__ cboxes,
+                                                 const T* __restrict__ ec, T* __restrict__ u) {
+  FOR_COLUMN(DIM) {
+    const int cy = DIM == 2 ? p : C.y, cz = DIM == 2 ? 0 : p;
+    const BoxD cb = cboxes[b.coarse];
+    const int64_t q = cell_index<DIM>(cb, C.x >> 1, cy >> 1, cz >> 1);
+    T common = T(1.0 - DIM * 0.25) * ec[q] + T(0.25) * ec[q + ((cy & 1) ? cb.s[1] : -cb.s[1])];
+    if (DIM == 3) common += T(0.25) * ec[q + ((cz & 1) ? cb.s[2] : -cb.s[2])];
+    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+    u[c] += common + T(0.25) * ec[q - 1];
+    if (C.ok1) u[c + 1] += common + T(0.25) * ec[q + 1];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -154,143 +673,6 @@ __global__ void __launch_bounds__(256) k_fill(const ChunkD* __restrict__ chunks,
   if (ch.kind2 == G_EXCH) v2 = u[ch.src2 + (int64_t)lane * ch.sstride2];
   u[g1] = v1;
   u[g1 + n] = v2;
-}
-
-// ---------------------------------------------------------------------------
-// r = f - A u  (A u = alpha u + beta lap_sum); optional per-tile max |r|
-template <typename T, int DIM, bool PART>
-__global__ void __launch_bounds__(256) k_residual(const TileD* __restrict__ tiles, const BoxD* __restrict__ boxes,
-                                                  const T* __restrict__ u, const T* __restrict__ f,
-                                                  T* __restrict__ r, T alpha, T beta, double* __restrict__ part) {
-  __shared__ T sh[4];
-  const TileD t = tiles[blockIdx.x];
-  const BoxD b = boxes[t.box];
-  const Cell q = tile_cell<DIM>(t, b);
-  T v = T(0);
-  if (q.ok) {
-    const T Au = alpha * u[q.c] + beta * lap_sum<T, DIM>(u, q.c, b);
-    v = f ? f[q.c] - Au : Au;  // f == NULL: the operator itself
-    r[q.c] = v;
-  }
-  if (PART) {
-    T av = fabs(v);
-    av = (av == av) ? av : T(INFINITY);  // a NaN residual must not vanish in fmax
-    T m = block_max<T>(av, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = (double)m;
-  }
-}
-
-// weighted Jacobi sweep: out = u + omega (f - A u) / diag
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_jacobi(const TileD* __restrict__ tiles, const BoxD* __restrict__ boxes,
-                                                const uint8_t* __restrict__ codes, const T* __restrict__ u,
-                                                const T* __restrict__ f, T* __restrict__ out, T alpha, T beta,
-                                                T omega) {
-  const TileD t = tiles[blockIdx.x];
-  const BoxD b = boxes[t.box];
-  const Cell q = tile_cell<DIM>(t, b);
-  if (!q.ok) return;
-  const T uc = u[q.c];
-  const T Au = alpha * uc + beta * lap_sum<T, DIM>(u, q.c, b);
-  const T dg = alpha + beta * diag_units<T, DIM>(q, b, codes);
-  out[q.c] = uc + omega * (f[q.c] - Au) / dg;
-}
-
-// first weighted-Jacobi sweep from a zero iterate: out = omega f / diag
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_jacobi0(const TileD* __restrict__ tiles, const BoxD* __restrict__ boxes,
-                                                 const uint8_t* __restrict__ codes, const T* __restrict__ f,
-                                                 T* __restrict__ out, T alpha, T beta, T omega) {
-  const TileD t = tiles[blockIdx.x];
-  const BoxD b = boxes[t.box];
-  const Cell q = tile_cell<DIM>(t, b);
-  if (!q.ok) return;
-  const T dg = alpha + beta * diag_units<T, DIM>(q, b, codes);
-  out[q.c] = omega * f[q.c] / dg;
-}
-
-// red-black half-sweep of colour `col` (parity of the sum of global indices):
-// cells of that colour updated simultaneously from u, the others copied
-template <typename T, int DIM, bool ZERO>
-__global__ void __launch_bounds__(256) k_rb(const TileD* __restrict__ tiles, const BoxD* __restrict__ boxes,
-                                            const uint8_t* __restrict__ codes, const T* __restrict__ u,
-                                            const T* __restrict__ f, T* __restrict__ out, T alpha, T beta,
-                                            int col) {
-  const TileD t = tiles[blockIdx.x];
-  const BoxD b = boxes[t.box];
-  const Cell q = tile_cell<DIM>(t, b);
-  if (!q.ok) return;
-  const int par = (b.lo[0] + q.x + b.lo[1] + q.y + (DIM == 3 ? b.lo[2] + q.z : 0)) & 1;
-  const T uc = ZERO ? T(0) : u[q.c];
-  if (par != col) {
-    out[q.c] = uc;
-    return;
-  }
-  const T Au = ZERO ? T(0) : alpha * uc + beta * lap_sum<T, DIM>(u, q.c, b);
-  const T dg = alpha + beta * diag_units<T, DIM>(q, b, codes);
-  out[q.c] = uc + (f[q.c] - Au) / dg;
-}
-
-// fused residual and restriction: fc = mean over the 2^DIM children of
-// (f - A u); one thread per coarse cell
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_resid_restrict(const TileD* __restrict__ ctiles,
-                                                        const BoxD* __restrict__ cboxes,
-                                                        const BoxD* __restrict__ fboxes, const T* __restrict__ u,
-                                                        const T* __restrict__ f, T* __restrict__ fc, T alpha,
-                                                        T beta) {
-  const TileD t = ctiles[blockIdx.x];
-  const BoxD cb = cboxes[t.box];
-  const Cell q = tile_cell<DIM>(t, cb);
-  if (!q.ok) return;
-  const BoxD fb = fboxes[cb.fine];
-  T acc = T(0);
-#pragma unroll
-  for (int a = 0; a < (1 << DIM); ++a) {
-    const int x = 2 * q.x + (a & 1), y = 2 * q.y + ((a >> 1) & 1), z = DIM == 3 ? 2 * q.z + ((a >> 2) & 1) : 0;
-    const int64_t c = fb.off + (x + 2) + (int64_t)(y + 2) * fb.s[1] + (DIM == 3 ? (int64_t)(z + 2) * fb.s[2] : 0);
-    acc += f[c] - (alpha * u[c] + beta * lap_sum<T, DIM>(u, c, fb));
-  }
-  fc[q.c] = acc * T(DIM == 2 ? 0.25 : 0.125);
-}
-
-// plain restriction: fc = mean of the 2^DIM children of r
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_restrict(const TileD* __restrict__ ctiles, const BoxD* __restrict__ cboxes,
-                                                  const BoxD* __restrict__ fboxes, const T* __restrict__ r,
-                                                  T* __restrict__ fc) {
-  const TileD t = ctiles[blockIdx.x];
-  const BoxD cb = cboxes[t.box];
-  const Cell q = tile_cell<DIM>(t, cb);
-  if (!q.ok) return;
-  const BoxD fb = fboxes[cb.fine];
-  T acc = T(0);
-#pragma unroll
-  for (int a = 0; a < (1 << DIM); ++a) {
-    const int x = 2 * q.x + (a & 1), y = 2 * q.y + ((a >> 1) & 1), z = DIM == 3 ? 2 * q.z + ((a >> 2) & 1) : 0;
-    const int64_t c = fb.off + (x + 2) + (int64_t)(y + 2) * fb.s[1] + (DIM == 3 ? (int64_t)(z + 2) * fb.s[2] : 0);
-    acc += r[c];
-  }
-  fc[q.c] = acc * T(DIM == 2 ? 0.25 : 0.125);
-}
-
-// u += face-neighbour linear interpolation of the coarse correction:
-// (1 - DIM/4) e_P + 1/4 sum_d e_{P + s_d e_d}, s_d the child's side
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_prolong(const TileD* __restrict__ ftiles, const BoxD* __restrict__ fboxes,
-                                                 const BoxD* __restrict__ cboxes, const T* __restrict__ ec,
-                                                 T* __restrict__ u) {
-  const TileD t = ftiles[blockIdx.x];
-  const BoxD fb = fboxes[t.box];
-  const Cell q = tile_cell<DIM>(t, fb);
-  if (!q.ok) return;
-  const BoxD cb = cboxes[fb.coarse];
-  const int px = q.x >> 1, py = q.y >> 1, pz = q.z >> 1;
-  const int64_t p = cb.off + (px + 2) + (int64_t)(py + 2) * cb.s[1] + (DIM == 3 ? (int64_t)(pz + 2) * cb.s[2] : 0);
-  T v = T(1.0 - DIM * 0.25) * ec[p];
-  T nb = ec[p + ((q.x & 1) ? 1 : -1)] + ec[p + ((q.y & 1) ? cb.s[1] : -cb.s[1])];
-  if (DIM == 3) nb += ec[p + ((q.z & 1) ? cb.s[2] : -cb.s[2])];
-  u[q.c] += v + T(0.25) * nb;
 }
 
 // exact bottom solve: e = M f for every instance of every group
@@ -330,53 +712,22 @@ __global__ void __launch_bounds__(256) k_bottom(const BottomGroupD* __restrict__
   }
 }
 
-// ---------------------------------------------------------------------------
-// reductions and vector updates (interior cells only)
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_tile_sum(const TileD* __restrict__ tiles, const BoxD* __restrict__ boxes,
-                                                  const T* __restrict__ a, double* __restrict__ part) {
+// segmented reduction in a fixed order: out[s] = sum (or max) of in over
+// [ptr[s], ptr[s+1]); ptr == NULL means the single segment [0, n).  One
+// block per segment.
+template <bool MAX>
+__global__ void __launch_bounds__(256) k_seg_reduce(const double* __restrict__ in, const int32_t* __restrict__ ptr,
+                                                    int n, double* __restrict__ out) {
   __shared__ double sh[4];
-  const TileD t = tiles[blockIdx.x];
-  const BoxD b = boxes[t.box];
-  const Cell q = tile_cell<DIM>(t, b);
-  double v = q.ok ? (double)a[q.c] : 0.0;
-  v = block_sum<double>(v, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = v;
-}
-
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_tile_absmax(const TileD* __restrict__ tiles, const BoxD* __restrict__ boxes,
-                                                     const T* __restrict__ a, double* __restrict__ part) {
-  __shared__ double sh[4];
-  const TileD t = tiles[blockIdx.x];
-  const BoxD b = boxes[t.box];
-  const Cell q = tile_cell<DIM>(t, b);
-  double v = q.ok ? fabs((double)a[q.c]) : 0.0;
-  v = block_max<double>(v, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = v;
-}
-
-// out[slot] = max of part[0..n); NaN propagates (fmax drops NaN, so count it)
-__global__ void __launch_bounds__(256) k_reduce_max(const double* __restrict__ part, int n, double* __restrict__ out) {
-  __shared__ double sh[4];
+  const int s = blockIdx.x;
+  const int a = ptr ? ptr[s] : 0, b = ptr ? ptr[s + 1] : n;
   double v = 0.0;
-  int bad = 0;
-  for (int i = threadIdx.x; i < n; i += 256) {
-    const double p = part[i];
-    if (!(p <= 1e300)) bad = 1;
-    v = fmax(v, p);
-  }
-  v = block_max<double>(v, sh);
-  __syncthreads();
-  __shared__ int anybad;
-  if (threadIdx.x == 0) anybad = 0;
-  __syncthreads();
-  if (bad) atomicOr(&anybad, 1);
-  __syncthreads();
-  if (threadIdx.x == 0) *out = anybad ? __builtin_nan("") : v;
+  for (int j = a + (int)threadIdx.x; j < b; j += 256) v = MAX ? fmax(v, in[j]) : v + in[j];
+  v = MAX ? block_max<double>(v, sh) : block_sum<double>(v, sh);
+  if (threadIdx.x == 0) out[s] = v;
 }
 
-// per-component sums of tile partials in a fixed order; one block per component
+// per-component sums of chunk partials in a fixed order; one block per component
 __global__ void __launch_bounds__(256) k_comp_sum(const double* __restrict__ part, const int32_t* __restrict__ ptr,
                                                   const int32_t* __restrict__ ids, double* __restrict__ out) {
   __shared__ double sh[4];
@@ -385,18 +736,6 @@ __global__ void __launch_bounds__(256) k_comp_sum(const double* __restrict__ par
   for (int j = ptr[c] + threadIdx.x; j < ptr[c + 1]; j += 256) v += part[ids[j]];
   v = block_sum<double>(v, sh);
   if (threadIdx.x == 0) out[c] = v;
-}
-
-// a -= coef * sum[comp] on cells of components with flag[comp] != 0
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_comp_shift(const TileD* __restrict__ tiles, const BoxD* __restrict__ boxes,
-                                                    T* __restrict__ a, const double* __restrict__ delta) {
-  const TileD t = tiles[blockIdx.x];
-  const BoxD b = boxes[t.box];
-  const Cell q = tile_cell<DIM>(t, b);
-  if (!q.ok) return;
-  const double d = delta[b.comp];
-  if (d != 0.0) a[q.c] = (T)((double)a[q.c] - d);
 }
 
 // per-component deltas: delta[c] = flag[c] ? (sum[c] - bsum[c]) * scale / cnt[c] : 0
@@ -426,42 +765,6 @@ __global__ void __launch_bounds__(256) k_chunk_fdsum(const ChunkD* __restrict__ 
   part[ci] = s;
 }
 
-// x += s e (x FP64, e FP32 or FP64), s = scal[0]
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_update(const TileD* __restrict__ tiles, const BoxD* __restrict__ boxes,
-                                                double* __restrict__ x, const T* __restrict__ e,
-                                                const double* __restrict__ scal) {
-  const TileD t = tiles[blockIdx.x];
-  const BoxD b = boxes[t.box];
-  const Cell q = tile_cell<DIM>(t, b);
-  if (!q.ok) return;
-  x[q.c] += scal[0] * (double)e[q.c];
-}
-
-// r32 = fp32(r / s), s = scal[0]
-template <int DIM>
-__global__ void __launch_bounds__(256) k_to32(const TileD* __restrict__ tiles, const BoxD* __restrict__ boxes,
-                                              const double* __restrict__ r, float* __restrict__ r32,
-                                              const double* __restrict__ scal) {
-  const TileD t = tiles[blockIdx.x];
-  const BoxD b = boxes[t.box];
-  const Cell q = tile_cell<DIM>(t, b);
-  if (!q.ok) return;
-  r32[q.c] = (float)(r[q.c] / scal[0]);
-}
-
-// f_shift = f - delta[comp]
-template <int DIM>
-__global__ void __launch_bounds__(256) k_shift_copy(const TileD* __restrict__ tiles, const BoxD* __restrict__ boxes,
-                                                    const double* __restrict__ f, double* __restrict__ out,
-                                                    const double* __restrict__ delta) {
-  const TileD t = tiles[blockIdx.x];
-  const BoxD b = boxes[t.box];
-  const Cell q = tile_cell<DIM>(t, b);
-  if (!q.ok) return;
-  out[q.c] = f[q.c] - delta[b.comp];
-}
-
 // scal[dst] = src[0] (device-side scalar copy, keeps the scale on the device)
 __global__ void k_set_scale(const double* __restrict__ src, double* __restrict__ dst) { *dst = *src; }
 
@@ -472,11 +775,24 @@ __global__ void k_zero(T* __restrict__ a, int64_t n) {
   if (i < n) a[i] = T(0);
 }
 
+
 // ===========================================================================
 // host-side launchers
 namespace {
-inline dim3 g1(size_t n) { return dim3((unsigned)n); }
+inline dim3 grid8(size_t n) { return dim3((unsigned)(8 * ((n + 7) / 8))); }
+template <int DIM>
+inline dim3 threads() {
+  return dim3(block_threads<DIM>());
+}
 }  // namespace
+
+#define DISPATCH_DIM(dim, KERNEL, ...)                                                   \
+  do {                                                                                   \
+    if ((dim) == 2)                                                                      \
+      hipLaunchKernelGGL(KERNEL<2>, grid8(n), threads<2>(), 0, st, __VA_ARGS__);         \
+    else                                                                                 \
+      hipLaunchKernelGGL(KERNEL<3>, grid8(n), threads<3>(), 0, st, __VA_ARGS__);         \
+  } while (0)
 
 template <typename T>
 void launch_fill(const Depth& D, T* u, const double* fd, hipStream_t st) {
@@ -485,23 +801,41 @@ void launch_fill(const Depth& D, T* u, const double* fd, hipStream_t st) {
   hipLaunchKernelGGL(k_fill<T>, dim3((n + 3) / 4), dim3(256), 0, st, D.d_chunks, n, u, fd, D.h);
 }
 
+// FP32 sweeps run one cell per thread (k_march1), FP64 sweeps two (k_march):
+// the faster of the two forms measured for each precision on gfx950.
+template <typename T, int OP, bool PART>
+struct MarchK {
+  template <int DIM>
+  static void go(const TileD* tl, size_t n, const Depth& D, const T* u, const T* f, T* out, T a, T b, T w, int col,
+                 double* part, const BoxD* cboxes, hipStream_t st) {
+    if (sizeof(T) == 4 && OP != OP_RESTRICT)
+      hipLaunchKernelGGL((k_march1<T, DIM, OP, PART>), grid8(n), dim3(DIM == 2 ? 128 : 512), 0, st, tl, (int)n,
+                         D.d_box, D.d_codes, u, f, out, a, b, w, col, part);
+    else
+      hipLaunchKernelGGL((k_march<T, DIM, OP, PART>), grid8(n), threads<DIM>(), 0, st, tl, (int)n, D.d_box, D.d_codes,
+                         u, f, out, a, b, w, col, part, cboxes);
+  }
+};
+
+template <typename T, int OP, bool PART>
+void march(int dim, const TileD* tl, size_t n, const Depth& D, const T* u, const T* f, T* out, T a, T b, T w, int col,
+           double* part, hipStream_t st, const BoxD* cboxes = nullptr) {
+  if (!n) return;
+  if (dim == 2)
+    MarchK<T, OP, PART>::template go<2>(tl, n, D, u, f, out, a, b, w, col, part, cboxes, st);
+  else
+    MarchK<T, OP, PART>::template go<3>(tl, n, D, u, f, out, a, b, w, col, part, cboxes, st);
+}
+
 template <typename T>
 void launch_residual(int dim, const Depth& D, bool all, const T* u, const T* f, T* r, T alpha, T beta,
                      double* part, hipStream_t st) {
   const TileD* tl = all ? D.d_tiles : D.d_stiles;
   const size_t n = all ? D.tiles.size() : D.stiles.size();
-  if (!n) return;
-  if (dim == 2) {
-    if (part)
-      hipLaunchKernelGGL((k_residual<T, 2, true>), g1(n), dim3(256), 0, st, tl, D.d_box, u, f, r, alpha, beta, part);
-    else
-      hipLaunchKernelGGL((k_residual<T, 2, false>), g1(n), dim3(256), 0, st, tl, D.d_box, u, f, r, alpha, beta, part);
-  } else {
-    if (part)
-      hipLaunchKernelGGL((k_residual<T, 3, true>), g1(n), dim3(256), 0, st, tl, D.d_box, u, f, r, alpha, beta, part);
-    else
-      hipLaunchKernelGGL((k_residual<T, 3, false>), g1(n), dim3(256), 0, st, tl, D.d_box, u, f, r, alpha, beta, part);
-  }
+  if (part)
+    march<T, OP_RESID, true>(dim, tl, n, D, u, f, r, alpha, beta, T(0), 0, part, st);
+  else
+    march<T, OP_RESID, false>(dim, tl, n, D, u, f, r, alpha, beta, T(0), 0, nullptr, st);
 }
 
 template <typename T>
@@ -509,21 +843,16 @@ void launch_jacobi(int dim, const Depth& D, const T* u, const T* f, T* out, T al
                    hipStream_t st) {
   const size_t n = D.stiles.size();
   if (!n) return;
-  if (dim == 2) {
-    if (zero)
-      hipLaunchKernelGGL((k_jacobi0<T, 2>), g1(n), dim3(256), 0, st, D.d_stiles, D.d_box, D.d_codes, f, out, alpha, beta,
-                         omega);
+  if (zero) {
+    if (dim == 2)
+      hipLaunchKernelGGL((k_sweep0<T, 2, false>), grid8(n), threads<2>(), 0, st, D.d_stiles, (int)n, D.d_box, D.d_codes,
+                         f, out, alpha, beta, omega);
     else
-      hipLaunchKernelGGL((k_jacobi<T, 2>), g1(n), dim3(256), 0, st, D.d_stiles, D.d_box, D.d_codes, u, f, out, alpha,
-                         beta, omega);
-  } else {
-    if (zero)
-      hipLaunchKernelGGL((k_jacobi0<T, 3>), g1(n), dim3(256), 0, st, D.d_stiles, D.d_box, D.d_codes, f, out, alpha, beta,
-                         omega);
-    else
-      hipLaunchKernelGGL((k_jacobi<T, 3>), g1(n), dim3(256), 0, st, D.d_stiles, D.d_box, D.d_codes, u, f, out, alpha,
-                         beta, omega);
+      hipLaunchKernelGGL((k_sweep0<T, 3, false>), grid8(n), threads<3>(), 0, st, D.d_stiles, (int)n, D.d_box, D.d_codes,
+                         f, out, alpha, beta, omega);
+    return;
   }
+  march<T, OP_JACOBI, false>(dim, D.d_stiles, n, D, u, f, out, alpha, beta, omega, 0, nullptr, st);
 }
 
 template <typename T>
@@ -531,34 +860,24 @@ void launch_rb(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha,
                hipStream_t st) {
   const size_t n = D.stiles.size();
   if (!n) return;
-  if (dim == 2) {
-    if (zero)
-      hipLaunchKernelGGL((k_rb<T, 2, true>), g1(n), dim3(256), 0, st, D.d_stiles, D.d_box, D.d_codes, u, f, out, alpha,
-                         beta, col);
+  if (zero) {
+    if (dim == 2)
+      hipLaunchKernelGGL((k_sweep0<T, 2, true>), grid8(n), threads<2>(), 0, st, D.d_stiles, (int)n, D.d_box, D.d_codes,
+                         f, out, alpha, beta, T(1));
     else
-      hipLaunchKernelGGL((k_rb<T, 2, false>), g1(n), dim3(256), 0, st, D.d_stiles, D.d_box, D.d_codes, u, f, out, alpha,
-                         beta, col);
-  } else {
-    if (zero)
-      hipLaunchKernelGGL((k_rb<T, 3, true>), g1(n), dim3(256), 0, st, D.d_stiles, D.d_box, D.d_codes, u, f, out, alpha,
-                         beta, col);
-    else
-      hipLaunchKernelGGL((k_rb<T, 3, false>), g1(n), dim3(256), 0, st, D.d_stiles, D.d_box, D.d_codes, u, f, out, alpha,
-                         beta, col);
+      hipLaunchKernelGGL((k_sweep0<T, 3, true>), grid8(n), threads<3>(), 0, st, D.d_stiles, (int)n, D.d_box, D.d_codes,
+                         f, out, alpha, beta, T(1));
+    return;
   }
+  march<T, OP_RB, false>(dim, D.d_stiles, n, D, u, f, out, alpha, beta, T(1), col, nullptr, st);
 }
 
 template <typename T>
 void launch_resid_restrict(int dim, const Depth& F, const Depth& C, const T* u, const T* f, T* fc, T alpha, T beta,
                            hipStream_t st) {
-  const size_t n = C.tiles.size();
-  if (!n) return;
-  if (dim == 2)
-    hipLaunchKernelGGL((k_resid_restrict<T, 2>), g1(n), dim3(256), 0, st, C.d_tiles, C.d_box, F.d_box, u, f, fc, alpha,
-                       beta);
-  else
-    hipLaunchKernelGGL((k_resid_restrict<T, 3>), g1(n), dim3(256), 0, st, C.d_tiles, C.d_box, F.d_box, u, f, fc, alpha,
-                       beta);
+  // marched over the fine tiles of the boxes that continue to depth+1
+  march<T, OP_RESTRICT, false>(dim, F.d_stiles, F.stiles.size(), F, u, f, fc, alpha, beta, T(0), 0, nullptr, st,
+                               C.d_box);
 }
 
 template <typename T>
@@ -566,9 +885,9 @@ void launch_restrict(int dim, const Depth& F, const Depth& C, const T* r, T* fc,
   const size_t n = C.tiles.size();
   if (!n) return;
   if (dim == 2)
-    hipLaunchKernelGGL((k_restrict<T, 2>), g1(n), dim3(256), 0, st, C.d_tiles, C.d_box, F.d_box, r, fc);
+    hipLaunchKernelGGL((k_restrict<T, 2>), grid8(n), threads<2>(), 0, st, C.d_tiles, (int)n, C.d_box, F.d_box, r, fc);
   else
-    hipLaunchKernelGGL((k_restrict<T, 3>), g1(n), dim3(256), 0, st, C.d_tiles, C.d_box, F.d_box, r, fc);
+    hipLaunchKernelGGL((k_restrict<T, 3>), grid8(n), threads<3>(), 0, st, C.d_tiles, (int)n, C.d_box, F.d_box, r, fc);
 }
 
 template <typename T>
@@ -576,9 +895,9 @@ void launch_prolong(int dim, const Depth& F, const Depth& C, const T* ec, T* u, 
   const size_t n = F.stiles.size();
   if (!n) return;
   if (dim == 2)
-    hipLaunchKernelGGL((k_prolong<T, 2>), g1(n), dim3(256), 0, st, F.d_stiles, F.d_box, C.d_box, ec, u);
+    hipLaunchKernelGGL((k_prolong<T, 2>), grid8(n), threads<2>(), 0, st, F.d_stiles, (int)n, F.d_box, C.d_box, ec, u);
   else
-    hipLaunchKernelGGL((k_prolong<T, 3>), g1(n), dim3(256), 0, st, F.d_stiles, F.d_box, C.d_box, ec, u);
+    hipLaunchKernelGGL((k_prolong<T, 3>), grid8(n), threads<3>(), 0, st, F.d_stiles, (int)n, F.d_box, C.d_box, ec, u);
 }
 
 template <typename T>
@@ -593,23 +912,30 @@ void launch_bottom(const Depth& D, const double* mats, const int64_t* idx, const
 template <typename T>
 void launch_tile_sum(int dim, const Depth& D, const T* a, double* part, hipStream_t st) {
   const size_t n = D.tiles.size();
+  if (!n) return;
   if (dim == 2)
-    hipLaunchKernelGGL((k_tile_sum<T, 2>), g1(n), dim3(256), 0, st, D.d_tiles, D.d_box, a, part);
+    hipLaunchKernelGGL((k_tile_reduce<T, 2, false>), grid8(n), threads<2>(), 0, st, D.d_tiles, (int)n, D.d_box, a, part);
   else
-    hipLaunchKernelGGL((k_tile_sum<T, 3>), g1(n), dim3(256), 0, st, D.d_tiles, D.d_box, a, part);
+    hipLaunchKernelGGL((k_tile_reduce<T, 3, false>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, a, part);
 }
 
 template <typename T>
 void launch_tile_absmax(int dim, const Depth& D, const T* a, double* part, hipStream_t st) {
   const size_t n = D.tiles.size();
+  if (!n) return;
   if (dim == 2)
-    hipLaunchKernelGGL((k_tile_absmax<T, 2>), g1(n), dim3(256), 0, st, D.d_tiles, D.d_box, a, part);
+    hipLaunchKernelGGL((k_tile_reduce<T, 2, true>), grid8(n), threads<2>(), 0, st, D.d_tiles, (int)n, D.d_box, a, part);
   else
-    hipLaunchKernelGGL((k_tile_absmax<T, 3>), g1(n), dim3(256), 0, st, D.d_tiles, D.d_box, a, part);
+    hipLaunchKernelGGL((k_tile_reduce<T, 3, true>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, a, part);
 }
 
-void launch_reduce_max(const double* part, int n, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(256), 0, st, part, n, out);
+void launch_seg_reduce(const double* in, const int32_t* ptr, int nseg, int n, double* out, bool is_max,
+                       hipStream_t st) {
+  if (nseg <= 0) return;
+  if (is_max)
+    hipLaunchKernelGGL(k_seg_reduce<true>, dim3(nseg), dim3(256), 0, st, in, ptr, n, out);
+  else
+    hipLaunchKernelGGL(k_seg_reduce<false>, dim3(nseg), dim3(256), 0, st, in, ptr, n, out);
 }
 
 void launch_comp_sum(const double* part, const int32_t* ptr, const int32_t* ids, int ncomp, double* out,
@@ -626,40 +952,39 @@ void launch_comp_delta(const double* sum, const double* bsum, const int32_t* fla
 template <typename T>
 void launch_comp_shift(int dim, const Depth& D, T* a, const double* delta, hipStream_t st) {
   const size_t n = D.tiles.size();
+  if (!n) return;
   if (dim == 2)
-    hipLaunchKernelGGL((k_comp_shift<T, 2>), g1(n), dim3(256), 0, st, D.d_tiles, D.d_box, a, delta);
+    hipLaunchKernelGGL((k_comp_shift<T, 2>), grid8(n), threads<2>(), 0, st, D.d_tiles, (int)n, D.d_box, a, delta);
   else
-    hipLaunchKernelGGL((k_comp_shift<T, 3>), g1(n), dim3(256), 0, st, D.d_tiles, D.d_box, a, delta);
+    hipLaunchKernelGGL((k_comp_shift<T, 3>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, a, delta);
 }
 
 void launch_chunk_fdsum(const Depth& D, const double* fd, double* part, hipStream_t st) {
   const int n = (int)D.chunks.size();
+  if (!n) return;
   hipLaunchKernelGGL(k_chunk_fdsum, dim3((n + 255) / 256), dim3(256), 0, st, D.d_chunks, n, fd, part);
 }
 
 template <typename T>
 void launch_update(int dim, const Depth& D, double* x, const T* e, const double* scal, hipStream_t st) {
   const size_t n = D.tiles.size();
+  if (!n) return;
   if (dim == 2)
-    hipLaunchKernelGGL((k_update<T, 2>), g1(n), dim3(256), 0, st, D.d_tiles, D.d_box, x, e, scal);
+    hipLaunchKernelGGL((k_update<T, 2>), grid8(n), threads<2>(), 0, st, D.d_tiles, (int)n, D.d_box, x, e, scal);
   else
-    hipLaunchKernelGGL((k_update<T, 3>), g1(n), dim3(256), 0, st, D.d_tiles, D.d_box, x, e, scal);
+    hipLaunchKernelGGL((k_update<T, 3>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, x, e, scal);
 }
 
 void launch_to32(int dim, const Depth& D, const double* r, float* r32, const double* scal, hipStream_t st) {
   const size_t n = D.tiles.size();
-  if (dim == 2)
-    hipLaunchKernelGGL(k_to32<2>, g1(n), dim3(256), 0, st, D.d_tiles, D.d_box, r, r32, scal);
-  else
-    hipLaunchKernelGGL(k_to32<3>, g1(n), dim3(256), 0, st, D.d_tiles, D.d_box, r, r32, scal);
+  if (!n) return;
+  DISPATCH_DIM(dim, k_to32, D.d_tiles, (int)n, D.d_box, r, r32, scal);
 }
 
 void launch_shift_copy(int dim, const Depth& D, const double* f, double* out, const double* delta, hipStream_t st) {
   const size_t n = D.tiles.size();
-  if (dim == 2)
-    hipLaunchKernelGGL(k_shift_copy<2>, g1(n), dim3(256), 0, st, D.d_tiles, D.d_box, f, out, delta);
-  else
-    hipLaunchKernelGGL(k_shift_copy<3>, g1(n), dim3(256), 0, st, D.d_tiles, D.d_box, f, out, delta);
+  if (!n) return;
+  DISPATCH_DIM(dim, k_shift_copy, D.d_tiles, (int)n, D.d_box, f, out, delta);
 }
 
 void launch_set_scale(const double* src, double* dst, hipStream_t st) {

@@ -231,8 +231,12 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       const Box& B = D.boxes[i];
       BoxD& X = D.boxd[i];
       memset(&X, 0, sizeof X);
-      int64_t sx = B.n(0) + 4, sy = B.n(1) + 4;
+      // rows padded to a multiple of A elements and the first interior cell
+      // of every row placed on an A-element boundary (aligned row loads)
+      const int64_t A = std::max(1, H->row_align);
+      int64_t sx = ((B.n(0) + 4 + A - 1) / A) * A, sy = B.n(1) + 4;
       int64_t sz = dim == 3 ? B.n(2) + 4 : 1;
+      off = ((off + 2 + A - 1) / A) * A - 2;
       X.off = off;
       X.n[0] = B.n(0);
       X.n[1] = B.n(1);
@@ -244,9 +248,9 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       X.comp = L.box_comp[D.level_box[i]];
       X.fine = k > 0 ? prev_index[D.level_box[i]] : -1;
       X.coarse = -1;
-      off += ((sx * sy * sz + 63) / 64) * 64;
+      off += sx * sy * sz;
     }
-    D.nstored = off;
+    D.nstored = off + 64;
     if (k > 0) {
       Depth& F = L.depths[k - 1];
       for (int i = 0; i < nbk; ++i) F.boxd[D.boxd[i].fine].coarse = i;
@@ -316,7 +320,13 @@ int plan_level(amg_hier* H, int l, std::string& err) {
           }
           FaceCols& fc = D.faces[i * 6 + d * 2 + s];
           D.boxd[i].code_off[d][s] = (int32_t)D.codes.size();
-          for (size_t c = 0; c < fc.k1.size(); ++c) D.codes.push_back(column_code(fc.k1[c], fc.k2[c]));
+          uint8_t u0 = column_code(fc.k1[0], fc.k2[0]);
+          for (size_t c = 0; c < fc.k1.size(); ++c) {
+            const uint8_t cc = column_code(fc.k1[c], fc.k2[c]);
+            D.codes.push_back(cc);
+            if (cc != u0) u0 = 0xFF;
+          }
+          D.boxd[i].ucode[d][s] = u0;
         }
     if (D.codes.empty()) D.codes.push_back(0);
 
@@ -394,28 +404,58 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       D.chunk_comp_ptr.push_back((int32_t)D.chunk_comp_idx.size());
     }
 
-    // ---- tiles ----
+    // ---- tiles (grouped by component, so each component is one range) ----
     D.tiles.clear();
     D.stiles.clear();
-    std::vector<std::vector<int32_t>> comp_tiles(L.ncomp);
-    const int TX = dim == 2 ? TILE2_X : TILE3_X, TY = dim == 2 ? TILE2_Y : TILE3_Y, TZ = dim == 2 ? 1 : TILE3_Z;
-    for (int i = 0; i < nbk; ++i) {
-      const BoxD& X = D.boxd[i];
-      bool smooths = bottom[D.level_box[i]] > k;
-      for (int z = 0; z < X.n[2]; z += TZ)
-        for (int y = 0; y < X.n[1]; y += TY)
-          for (int x = 0; x < X.n[0]; x += TX) {
-            TileD T{i, x, y, z};
-            comp_tiles[X.comp].push_back((int32_t)D.tiles.size());
-            D.tiles.push_back(T);
-            if (smooths) D.stiles.push_back(T);
-          }
+    // march length of this depth: long marches amortise each column's set-up,
+    // but a depth must still give about kTargetTiles tiles to fill the chip;
+    // always even, so restriction pairs never straddle two tiles
+    int CH;
+    {
+      int64_t R = 0;  // tile rows: (x-tiles x y-tiles) x cells along the march direction
+      for (int i = 0; i < nbk; ++i) {
+        const BoxD& X = D.boxd[i];
+        const int64_t base = (int64_t)((X.n[0] + TILE_X - 1) / TILE_X) * (dim == 3 ? (X.n[1] + TILE3_Y - 1) / TILE3_Y : 1);
+        R += base * X.n[dim - 1];
+      }
+      const int cap = dim == 2 ? H->march2 : H->march3;
+      int64_t m = R / kTargetTiles;
+      m = std::max<int64_t>(2, std::min<int64_t>(cap, m));
+      CH = (int)(m & ~int64_t(1));
     }
-    D.tile_comp_ptr.assign(1, 0);
-    D.tile_comp_idx.clear();
+    D.march = CH;
+    D.comp_seg_ptr.assign(1, 0);
+    D.seg_ptr.assign(1, 0);
     for (int c = 0; c < L.ncomp; ++c) {
-      D.tile_comp_idx.insert(D.tile_comp_idx.end(), comp_tiles[c].begin(), comp_tiles[c].end());
-      D.tile_comp_ptr.push_back((int32_t)D.tile_comp_idx.size());
+      const size_t first = D.tiles.size();
+      for (int i = 0; i < nbk; ++i) {
+        const BoxD& X = D.boxd[i];
+        if (X.comp != c) continue;
+        bool smooths = bottom[D.level_box[i]] > k;
+        auto add = [&](int x0, int y0, int z0, int len) {
+          TileD T;
+          memset(&T, 0, sizeof T);
+          T.box = i;
+          T.x0 = x0;
+          T.y0 = y0;
+          T.z0 = z0;
+          T.len = len;
+          D.tiles.push_back(T);
+          if (smooths) D.stiles.push_back(T);
+        };
+        if (dim == 2) {
+          for (int y0 = 0; y0 < X.n[1]; y0 += CH)
+            for (int x0 = 0; x0 < X.n[0]; x0 += TILE_X) add(x0, y0, 0, std::min(CH, X.n[1] - y0));
+        } else {
+          for (int z0 = 0; z0 < X.n[2]; z0 += CH)
+            for (int y0 = 0; y0 < X.n[1]; y0 += TILE3_Y)
+              for (int x0 = 0; x0 < X.n[0]; x0 += TILE_X) add(x0, y0, z0, std::min(CH, X.n[2] - z0));
+        }
+      }
+      // reduction segments of at most kSeg tiles inside the component
+      for (size_t a = first; a < D.tiles.size(); a += kSeg)
+        D.seg_ptr.push_back((int32_t)std::min(D.tiles.size(), a + kSeg));
+      D.comp_seg_ptr.push_back((int32_t)D.seg_ptr.size() - 1);
     }
     prev_index = cur_index;
   }

@@ -163,11 +163,37 @@ def test_solve_fp64_and_mixed(name, op, c0):
         got = lev.comp_mean(from_dev(H, L, 0, x, lev), sing)
         assert relerr(got, lev.comp_mean(x_or, sing), lev.mask) < tol, (prec, st["cycles"], st_or["cycles"])
         if prec == A.FP64:
-            # the same cycle, so the same residual history
+            # the same cycle, so the same residual history (rounding may move
+            # a norm that lands right at the tolerance across it: one cycle)
             hist = np.array(st["history"])
             ho = np.array(st_or["history"])
-            assert len(hist) == len(ho)
-            assert np.allclose(hist[:4], ho[:4], rtol=1e-6, atol=1e-13 * ho[0])
+            assert abs(len(hist) - len(ho)) <= 1
+            k = min(len(hist), len(ho))
+            assert np.allclose(hist[:k], ho[:k], rtol=1e-5, atol=1e-14 * ho[0])
         if sing:
             assert len(st["defects"]) == len(sing)
             assert np.allclose(st["defects"], st_or["defects"], rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["2d_cf_neu", "3d_dir"])
+def test_graph_replays_match_direct_launches_bitwise(name):
+    """The captured outer cycle, replayed many times (with eager host work
+    and synchronisations between solves), gives bit-identical iterates to
+    direct launches, and repeated solves are bitwise reproducible."""
+    lev = LAYOUTS[name]()
+    op, c = "poisson", 0.0
+    H, L = make_hier(lev, op, c)
+    f = random_field(lev, 12)
+    fd = random_faces(lev, 13)
+    fdd, fdev = faces_to_dev(H, L, lev, fd), to_dev(H, L, 0, f)
+    results = []
+    for graph in (0, 1, 1, 0, 1):
+        x = torch.zeros_like(fdev)
+        st = H.solve(L, x, fdev, fdd, A.default_opts(use_graph=graph, tol_rel=1e-12, max_cycles=200))
+        torch.cuda.synchronize()
+        assert st["converged"] and st["graph"] == bool(graph)
+        results.append((x.cpu().numpy().copy(), st["history"]))
+        _ = (fdev * 2).sum().item()  # unrelated eager work between solves
+    for x, hist in results[1:]:
+        assert np.array_equal(x, results[0][0])
+        assert hist == results[0][1]
