@@ -1,0 +1,132 @@
+"""Pins of the oracle's composite (multi-level) operators: coarse-fine
+interpolation weights in exact arithmetic, polynomial reproduction of the
+composite operator and solve, conservation of the refluxed operator, and the
+directly solved composite system as referee."""
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+from oracle import amr
+from tests.polyfix import Poly1, problem
+
+
+def avg_mono(k, a, b):
+    return (Fr(b) ** (k + 1) - Fr(a) ** (k + 1)) / ((k + 1) * (Fr(b) - Fr(a)))
+
+
+def test_centred_weights_match_hand_derived_values():
+    # derived by hand for the centred window (child 0); child 1 is its mirror
+    want0 = [Fr(-3, 128), Fr(11, 64), Fr(1), Fr(-11, 64), Fr(3, 128)]
+    assert amr.cfi_weights_1d(0, 0) == want0
+    assert amr.cfi_weights_1d(0, 1) == want0[::-1]
+
+
+@pytest.mark.parametrize("shift", range(-2, 3))
+@pytest.mark.parametrize("child", (0, 1))
+def test_weights_exact_to_degree_4_and_not_5(shift, child):
+    w = amr.cfi_weights_1d(shift, child)
+    mp = 2 - shift
+    x0 = Fr(mp) + Fr(child, 2)
+    for k in range(6):
+        data = [avg_mono(k, m, m + 1) for m in range(5)]
+        got = sum(wi * di for wi, di in zip(w, data))
+        assert (got == avg_mono(k, x0, x0 + Fr(1, 2))) == (k <= 4)
+
+
+@pytest.mark.parametrize("shift", range(-2, 3))
+def test_weights_are_conservative(shift):
+    w0, w1 = amr.cfi_weights_1d(shift, 0), amr.cfi_weights_1d(shift, 1)
+    mean = [(a + b) / 2 for a, b in zip(w0, w1)]
+    assert mean == [Fr(1) if m == 2 - shift else Fr(0) for m in range(5)]
+
+
+P4a = Poly1([0.3, -1.0, 0.5, 2.0, -1.5])
+P4b = Poly1([1.0, 0.7, -2.0, 0.25, 1.0])
+P3 = Poly1([-0.2, 1.1, 0.4, -0.9])
+
+
+def two_level(bc):
+    return amr.Hierarchy((16, 16), 1.0 / 16, [[((0, 0), (15, 15))], [((8, 8), (15, 23)), ((16, 8), (23, 15))]],
+                         {(d, s): bc for d in range(2) for s in (0, 1)})
+
+
+def three_level(bc):
+    return amr.Hierarchy((16, 16), 1.0 / 16,
+                         [[((0, 0), (15, 15))], [((4, 4), (27, 27))], [((16, 16), (31, 31))]],
+                         {(d, s): bc for d in range(2) for s in (0, 1)})
+
+
+def poly_data(H, op, c):
+    us, fs, fds = [], [], []
+    for lev in H.levels:
+        u, f, fd = problem(lev, [(P4a, P4b), (P3, P4a)], op, c)
+        us.append(u)
+        fs.append(f)
+        fds.append(fd)
+    return us, fs, fds
+
+
+def rel(U, V, H):
+    num = max(np.abs(U[l] - V[l])[H.valid[l]].max() for l in range(H.nlev))
+    return num / max(np.abs(V[l][H.valid[l]]).max() for l in range(H.nlev))
+
+
+@pytest.mark.parametrize("make", [two_level, three_level])
+@pytest.mark.parametrize("op,bc,c", [("helmholtz", "D", 0.5 / 16), ("poisson", "N", 0.0), ("poisson", "D", 0.0)])
+def test_composite_reproduces_polynomials(make, op, bc, c):
+    H = make(bc)
+    us, fs, fds = poly_data(H, op, c)
+    A = H.composite_apply(H.average_down_all(us), op, c, fds)
+    assert rel(A, fs, H) < 1e-12
+    U, st = amr.composite_solve(H, fs, op, c, fds, tol_rel=1e-12, max_cycles=80)
+    assert st["converged"]
+    if H.singular(op):
+        m = H.composite_mean(us)
+        us = [np.where(H.levels[l].mask, us[l] - m, 0.0) for l in range(H.nlev)]
+        assert abs(st["defect"]) < 1e-12
+    assert rel(U, us, H) < 1e-9
+
+
+def test_refluxed_operator_is_conservative():
+    H = two_level("N")
+    rng = np.random.default_rng(0)
+    U = []
+    for l, lev in enumerate(H.levels):
+        u = lev.zeros()
+        u[lev.mask] = rng.normal(size=lev.ncells)
+        U.append(u)
+    U = H.average_down_all(U)
+    fds = []
+    for lev in H.levels:
+        fd = lev.zero_face_data()
+        for k in fd:
+            e = lev.end_is_physical(*k)
+            fd[k][e] = rng.normal(size=int(e.sum()))
+        fds.append(fd)
+    L = H.composite_apply(U, "poisson", 0.0, fds)
+    vol = sum(L[l][H.valid[l]].sum() * H.levels[l].h ** 2 for l in range(H.nlev))
+    bnd = sum(fds[l][k][H.levels[l].end_is_physical(*k) & H.valid[l]].sum() * H.levels[l].h
+              for l in range(H.nlev) for k in fds[l])
+    scale = sum(np.abs(L[l][H.valid[l]]).sum() * H.levels[l].h ** 2 for l in range(H.nlev))
+    assert abs(vol - bnd) < 1e-13 * scale
+
+
+@pytest.mark.parametrize("op,bc,c", [("helmholtz", "D", 0.3 / 16), ("poisson", "N", 0.0)])
+def test_composite_solve_equals_direct_solve(op, bc, c):
+    H = two_level(bc)
+    rng = np.random.default_rng(4)
+    fs = []
+    for lev in H.levels:
+        f = lev.zeros()
+        f[lev.mask] = rng.normal(size=lev.ncells)
+        fs.append(f)
+    U, st = amr.composite_solve(H, fs, op, c, None, tol_rel=1e-13, max_cycles=120)
+    Ud = amr.composite_direct(H, fs, op, c, None)
+    assert rel(U, Ud, H) < 1e-10
+
+
+def test_nesting_is_checked():
+    with pytest.raises(ValueError):
+        amr.Hierarchy((16, 16), 1.0 / 16, [[((0, 0), (15, 15))], [((4, 4), (11, 11))], [((2, 2), (9, 9))]],
+                      {(d, s): "D" for d in range(2) for s in (0, 1)})
