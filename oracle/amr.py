@@ -20,14 +20,18 @@ Readings taken where the paper points to other papers:
   ghosts.
 * Average-down (COH-4, eq. AMR_avergingDownToCrse) puts on every coarse cell
   covered by the next level the mean of its 2^D children.
-* Composite solve: residual correction.  Each cycle computes the composite
-  residual, averages it down to level 0, corrects level 0 with one V-cycle
-  of the level-0 multigrid, then, level by level upwards, adds the
-  face-neighbour linear prolongation of the coarse level's total correction,
-  recomputes the level residual with ghosts interpolated from the corrected
-  coarse level, and corrects that level with one V-cycle of its own
-  multigrid (interpolated ghosts of a correction are zero); finally the data
-  is averaged down.
+* Composite solve (the paper cites an adaptive multigrid for the inverse of
+  the composite operator): multiplicative correction by levels in V order,
+  finest to level 1, then level 0, then level 1 to finest.  Each correction
+  of level l recomputes the composite residual (data averaged down first,
+  covered cells carrying the averaged finer residual), runs one V-cycle of
+  level l's own multigrid on it (interpolated ghosts of a correction are
+  zero), adds the correction to level l and its face-neighbour linear
+  prolongation to every finer level.  After the sweep the data is averaged
+  down.  (Correcting the fine levels only once per cycle, after level 0,
+  diverges when a fine box sits in a corner of a Dirichlet domain: the fine
+  correction ignores how its own values reach its interpolated ghosts
+  through the averaged-down coarse cells.)
 """
 from fractions import Fraction as Fr
 
@@ -302,10 +306,29 @@ def composite_residual(H, U, f, op, c, fd=None):
     return R
 
 
+def correct_level(H, U, f, op, c, fd, MGl, l, sing):
+    """One correction of level l: composite residual, a V-cycle of level l's
+    multigrid on it (scaled by its max norm), the correction added to level
+    l and prolonged onto every finer level."""
+    U = H.average_down_all(U)
+    R = composite_residual(H, U, f, op, c, fd)
+    rl = R[l]
+    if l == 0 and sing:
+        rl = H.levels[0].comp_mean(rl, [0])
+    s = float(np.abs(rl[H.levels[l].mask]).max()) or 1.0
+    e = MGl.vcycle(rl / s) * s
+    U[l] = U[l] + e
+    E = e
+    for m in range(l + 1, H.nlev):
+        dU = mg.prolong(H.levels[m - 1], E, H.levels[m])
+        U[m] = U[m] + dU
+        E = dU
+    return U
+
+
 def composite_solve(H, f, op, c, fd=None, tol_rel=1e-10, tol_abs=0.0, max_cycles=100, nu1=2, nu2=2,
                     smoother="jacobi", shift=True):
-    """The composite residual-correction cycle described in the module
-    docstring, from U = 0."""
+    """The composite cycle described in the module docstring, from U = 0."""
     MG = [mg.MG(lev, op, c, nu1, nu2, smoother) for lev in H.levels]
     sing = H.singular(op)
     defect = 0.0
@@ -315,25 +338,11 @@ def composite_solve(H, f, op, c, fd=None, tol_rel=1e-10, tol_abs=0.0, max_cycles
     R = composite_residual(H, U, f, op, c, fd)
     hist = [H.norm_inf(R)]
     target = max(tol_rel * hist[0], tol_abs)
+    order = list(range(H.nlev - 1, 0, -1)) + list(range(H.nlev))
     cycles = 0
     while hist[-1] > target and cycles < max_cycles:
-        s = hist[-1]
-        r0 = R[0]
-        if sing:
-            r0 = H.levels[0].comp_mean(r0, [0])
-        e = MG[0].vcycle(r0 / s) * s
-        U[0] = U[0] + e
-        E = e
-        for l in range(1, H.nlev):
-            dU = mg.prolong(H.levels[l - 1], E, H.levels[l])
-            U[l] = U[l] + dU
-            lev = H.levels[l]
-            cfv = H.amrcfi(l, U[l - 1])
-            rl = np.where(lev.mask, f[l] - lev.apply(U[l], op, c, fd[l] if fd else None, cfv), 0.0)
-            sl = float(np.abs(rl[lev.mask]).max()) or 1.0
-            el = MG[l].vcycle(rl / sl) * sl
-            U[l] = U[l] + el
-            E = dU + el
+        for l in order:
+            U = correct_level(H, U, f, op, c, fd, MG[l], l, sing)
         U = H.average_down_all(U)
         if sing:
             m = H.composite_mean(U)

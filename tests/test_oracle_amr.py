@@ -112,9 +112,17 @@ def test_refluxed_operator_is_conservative():
     assert abs(vol - bnd) < 1e-13 * scale
 
 
-@pytest.mark.parametrize("op,bc,c", [("helmholtz", "D", 0.3 / 16), ("poisson", "N", 0.0)])
-def test_composite_solve_equals_direct_solve(op, bc, c):
-    H = two_level(bc)
+def corner(bc):
+    # a fine box in a corner of the domain (interpolation windows shifted
+    # along both directions next to it)
+    return amr.Hierarchy((16, 8), 1.0 / 16, [[((0, 0), (15, 7))], [((0, 0), (7, 7))]],
+                         {(d, s): bc for d in range(2) for s in (0, 1)})
+
+
+@pytest.mark.parametrize("make", [two_level, corner])
+@pytest.mark.parametrize("op,bc,c", [("helmholtz", "D", 0.3 / 16), ("poisson", "N", 0.0), ("poisson", "D", 0.0)])
+def test_composite_solve_equals_direct_solve(make, op, bc, c):
+    H = make(bc)
     rng = np.random.default_rng(4)
     fs = []
     for lev in H.levels:
