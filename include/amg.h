@@ -212,12 +212,28 @@ int amg_box_info(const amg_hier* h, int level, int depth, int box, amg_box_desc*
 int amg_depth_size(const amg_hier* h, int level, int depth, int64_t* nstored, int32_t* nboxes);
 
 /* Solves the level system A x = f on level `level` (lev_lo == lev_hi; the
- * coarse-fine interface takes the level's face data).  x: initial guess on
+ * coarse-fine interface takes the level's face data), or, with lev_lo = 0 <
+ * lev_hi, the composite system over levels 0..lev_hi (levels >= 1 in mode
+ * AMG_CF_INTERP): each cycle corrects level 0 by a V-cycle of its multigrid,
+ * then every finer level by the prolonged coarse correction plus a V-cycle
+ * of its own multigrid on its residual, averages down and recomputes the
+ * composite residual (see amg_composite_residual); x holds the composite
+ * solution (covered cells: averages of the finer level).  x: initial guess on
  * entry, solution on return, ghosts filled.  f, face_data as above.
  * On AMG_ENOTCONVERGED x holds the last iterate and stats are valid. */
 int amg_solve(amg_hier* h, int lev_lo, int lev_hi, double* const* x, const double* const* f,
               const double* const* face_data, const amg_solve_opts* opts, amg_solve_stats* stats,
               void* stream);
+
+/* Composite residual r = f - A^comp x over levels 0..lev_hi (COH-1..4 of
+ * Section 5.3): x is averaged down onto covered cells (eq.
+ * AMR_avergingDownToCrse), every level's ghosts are filled (coarse-fine ones
+ * interpolated from the level below), the coarse fluxes through coarse-fine
+ * faces are replaced by the mean fine fluxes (refluxing), and r on covered
+ * cells is the average of the finer level's r.  x, f, face_data, r: one
+ * packed FP64 buffer per level (face_data may be NULL or hold NULLs). */
+int amg_composite_residual(amg_hier* h, int lev_hi, double* const* x, const double* const* f,
+                           const double* const* face_data, double* const* r, void* stream);
 
 /* y = A x on level `level` (FP64), ghosts of x filled from face_data
  * (homogeneous != 0: face data treated as zero).  x's ghosts are written. */

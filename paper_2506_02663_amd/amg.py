@@ -91,6 +91,7 @@ def lib():
         L.amg_bottom.argtypes = [vp, i32, i32, vp, vp, vp]
         L.amg_vcycle.argtypes = [vp, i32, i32, C.POINTER(SolveOpts), vp, vp, vp]
         L.amg_timing_enable.argtypes = [vp, i32]
+        L.amg_composite_residual.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
         L.amg_set_tuning.argtypes = [vp, i32, i32]
         L.amg_timing_read.argtypes = [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double), i32]
         _lib = L
@@ -284,6 +285,42 @@ class Hierarchy:
         out = st.as_dict()
         out["status"] = rc
         return out
+
+    def _level_ptrs(self, ts, n):
+        arr = (C.c_void_p * n)()
+        for i, t in enumerate(ts):
+            arr[i] = None if t is None else t.data_ptr()
+        return arr
+
+    def solve_composite(self, xs, fs, fds=None, opts=None):
+        """Composite solve over levels 0..len(xs)-1 (one tensor per level)."""
+        import torch
+        n = len(xs)
+        fds = fds or [None] * n
+        for l in range(n):
+            self._need(xs[l], l, 0, "x", (torch.float64,))
+            self._need(fs[l], l, 0, "f", (torch.float64,))
+            self._need_faces(fds[l], l)
+        o = opts or default_opts()
+        st = SolveStats()
+        rc = lib().amg_solve(self.h, 0, n - 1, self._level_ptrs(xs, n), self._level_ptrs(fs, n),
+                             self._level_ptrs(fds, n), C.byref(o), C.byref(st), _stream())
+        if rc and rc != ENOTCONVERGED:
+            self._check(rc)
+        out = st.as_dict()
+        out["status"] = rc
+        return out
+
+    def composite_residual(self, xs, fs, rs, fds=None):
+        import torch
+        n = len(xs)
+        fds = fds or [None] * n
+        for l in range(n):
+            for t, nm in ((xs[l], "x"), (fs[l], "f"), (rs[l], "r")):
+                self._need(t, l, 0, nm, (torch.float64,))
+            self._need_faces(fds[l], l)
+        self._check(lib().amg_composite_residual(self.h, n - 1, self._level_ptrs(xs, n), self._level_ptrs(fs, n),
+                                                 self._level_ptrs(fds, n), self._level_ptrs(rs, n), _stream()))
 
     def apply_operator(self, level, x, y, face_data=None, homogeneous=False):
         import torch

@@ -71,6 +71,49 @@ struct BottomGroupD {      // systems sharing one dense inverse
   int32_t n, ninst;
 };
 
+// ---- composite (multi-level) tables -------------------------------------------
+struct AvgD {     // one coarse cell under the finer level
+  int64_t ce;     // coarse element
+  int64_t fe;     // element of its child with the smallest indices
+  int32_t fs1, fs2;  // fine strides along y and z
+};
+
+struct RfxFaceD {  // one coarse-fine face of a valid coarse cell
+  int64_t fe;      // first fine cell past the face (transverse offset 0)
+  int32_t fsn;     // fine stride along the normal n (pointing into the fine level)
+  int32_t ft0, ft1;  // fine strides across the face
+  int32_t csn;     // coarse stride along n
+};
+
+struct ProlD {     // one fine cell and its coarse parent
+  int64_t fe, pe;
+  int32_t cs1, cs2;  // coarse strides along y and z
+  int32_t child;     // bit d set: the child lies on the high side along d
+  int32_t pad;
+};
+
+struct Composite {  // tables of level l against level l-1 (l >= 1)
+  double w[10][5];  // interpolation weights, [(shift + 2) * 2 + child][window cell]
+  std::vector<int64_t> cfi_dst;
+  std::vector<int32_t> cfi_src;  // 5^D coarse elements per ghost
+  std::vector<uint8_t> cfi_w;    // D weight-set indices per ghost
+  std::vector<AvgD> avg;
+  std::vector<int64_t> rfx_cell;  // coarse cells with coarse-fine faces
+  std::vector<int32_t> rfx_ptr;   // CSR into rfx_face
+  std::vector<RfxFaceD> rfx_face;
+  std::vector<ProlD> pro;
+  // device
+  double* d_w = nullptr;
+  int64_t* d_cfi_dst = nullptr;
+  int32_t* d_cfi_src = nullptr;
+  uint8_t* d_cfi_w = nullptr;
+  AvgD* d_avg = nullptr;
+  int64_t* d_rfx_cell = nullptr;
+  int32_t* d_rfx_ptr = nullptr;
+  RfxFaceD* d_rfx_face = nullptr;
+  ProlD* d_pro = nullptr;
+};
+
 // ---- host-side description ---------------------------------------------------
 struct Box {
   int lo[3], hi[3];
@@ -130,6 +173,10 @@ struct GraphCache {  // the captured outer cycle of one level
 
 struct Level {
   GraphCache graph;
+  Composite cmp;                    // against level l-1 (l >= 1)
+  std::vector<uint8_t> face_valid;  // face-data entries not under level l+1
+  uint8_t* d_face_valid = nullptr;
+  double* E64 = nullptr;            // total correction of this level in a composite cycle
   std::vector<Box> boxes;
   bool isolated = false;
   int cf_mode = AMG_CF_DIRICHLET;
@@ -195,6 +242,8 @@ struct amg_hier {
 namespace amg {
 // planner (layout.cpp)
 int plan_level(amg_hier* H, int l, std::string& err);
+// composite tables of level l against level l-1 (composite.cpp)
+int build_composite(amg_hier* H, int l, std::string& err);
 // host assembly of the coarsest operator and its inverse (bottom.cpp)
 int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats, std::vector<int64_t>& idx);
 }  // namespace amg

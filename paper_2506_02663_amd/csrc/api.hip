@@ -17,7 +17,9 @@ using namespace amg;
 
 namespace {
 
-enum { S_NORM = 0, S_ONE = 1, S_COUNT = 16 };
+// device scalar slots of a level: residual norm, the constant 1, per-level
+// norms of a composite cycle (level 0's array), per-level face-data sums
+enum { S_NORM = 0, S_ONE = 1, S_LEV = 2, S_FD = 20, S_FSUM = 38, S_DELTA = 39, S_COUNT = 40 };
 
 #define HIPCHK(expr)                                                      \
   do {                                                                    \
@@ -281,6 +283,117 @@ void free_level(amg::Level& L) {
                   (void*)L.d_defect})
     if (p) (void)hipFree(p);
   if (L.h_scal) (void)hipHostFree(L.h_scal);
+  const Composite& X = L.cmp;
+  for (void* p : {(void*)L.E64, (void*)L.d_face_valid, (void*)X.d_w, (void*)X.d_cfi_dst, (void*)X.d_cfi_src,
+                  (void*)X.d_cfi_w, (void*)X.d_avg, (void*)X.d_rfx_cell, (void*)X.d_rfx_ptr, (void*)X.d_rfx_face,
+                  (void*)X.d_pro})
+    if (p) (void)hipFree(p);
+}
+
+// ---- composite (multi-level) solve -------------------------------------------
+struct Comp {
+  amg_hier* H;
+  int hi;  // finest level of the composite (level 0 is the coarsest)
+  hipStream_t st;
+  std::vector<double*> X, R;
+  std::vector<const double*> F, FD;
+};
+
+// Composite residual (COH-1..4): average the data down, fill every level's
+// ghosts (coarse-fine ones by interpolation from the level below), level
+// residuals, refluxing at coarse cells next to finer levels, and the
+// residual averaged down onto covered cells.  Norm (max over all cells of
+// all levels, which equals the max over valid cells since covered cells
+// hold averages) into level 0's S_NORM slot.
+void comp_residual(Comp& C) {
+  amg_hier* H = C.H;
+  const int dim = H->dim;
+  Level& L0 = H->levels[0];
+  for (int l = C.hi; l >= 1; --l) launch_avgdown(dim, H->levels[l].cmp, C.X[l], C.X[l - 1], C.st);
+  for (int l = 0; l <= C.hi; ++l) {
+    Level& L = H->levels[l];
+    Depth& D = L.depths[0];
+    launch_fill<double>(D, C.X[l], C.FD[l], C.st);
+    if (l) launch_cfi(dim, L.cmp, C.X[l - 1], C.X[l], C.st);
+    double a, b;
+    coefs<double>(H, D, a, b);
+    launch_residual<double>(dim, D, true, C.X[l], C.F[l], C.R[l], a, b, nullptr, C.st);
+  }
+  const double kappa = H->op == AMG_HELMHOLTZ ? H->c : -1.0;
+  for (int l = 1; l <= C.hi; ++l)
+    launch_reflux(dim, H->levels[l].cmp, C.X[l - 1], C.X[l], C.R[l - 1], kappa, H->levels[l - 1].depths[0].h,
+                  H->levels[l].depths[0].h, C.st);
+  for (int l = C.hi; l >= 1; --l) launch_avgdown(dim, H->levels[l].cmp, C.R[l], C.R[l - 1], C.st);
+  for (int l = 0; l <= C.hi; ++l) {
+    Level& L = H->levels[l];
+    Run R{H, &L, dim, C.st};
+    launch_tile_absmax<double>(dim, L.depths[0], C.R[l], L.partial, C.st);
+    global_max(R, L.depths[0], L0.scal + S_LEV + l);
+  }
+  launch_max_slots(L0.scal + S_LEV, C.hi + 1, L0.scal + S_NORM, C.st);
+}
+
+// one V-cycle of level l's multigrid on the residual Rl (scaled by the norm
+// in `sc`); x += s e and E += s e
+void comp_level_vcycle(Comp& C, int l, const amg_solve_opts& o, double* Rl, const double* sc) {
+  amg_hier* H = C.H;
+  Level& L = H->levels[l];
+  Depth& D0 = L.depths[0];
+  Run R{H, &L, H->dim, C.st};
+  if (o.precision == AMG_MIXED) {
+    launch_to32(H->dim, D0, Rl, D0.f32, sc, C.st);
+    float* e = vcycle<float>(R, o, D0.f32, D0.e32, D0.t32);
+    launch_update2<float>(H->dim, D0, C.X[l], L.E64, e, sc, C.st);
+  } else {
+    double* e = vcycle<double>(R, o, Rl, D0.e64, D0.t64);
+    launch_update2<double>(H->dim, D0, C.X[l], L.E64, e, H->levels[0].scal + S_ONE, C.st);
+  }
+}
+
+// one correction of level l: composite residual, a V-cycle of level l's
+// multigrid on it (scaled by its max norm over the level), x_l += s e, and
+// the correction prolonged onto every finer level of the composite
+void comp_correct(Comp& C, const amg_solve_opts& o, int l) {
+  amg_hier* H = C.H;
+  const int dim = H->dim;
+  Level& L0 = H->levels[0];
+  comp_residual(C);
+  if (l == 0 && L0.nsingular) {
+    Run R0{H, &L0, dim, C.st};
+    remove_mean<double>(R0, 0, C.R[0]);
+    launch_tile_absmax<double>(dim, L0.depths[0], C.R[0], L0.partial, C.st);
+    global_max(R0, L0.depths[0], L0.scal + S_LEV);
+  }
+  Level& L = H->levels[l];
+  launch_zero<double>(L.E64, L.depths[0].nstored, C.st);
+  comp_level_vcycle(C, l, o, C.R[l], L0.scal + S_LEV + l);
+  for (int m = l + 1; m <= C.hi; ++m) {
+    launch_fill<double>(H->levels[m - 1].depths[0], H->levels[m - 1].E64, nullptr, C.st);
+    launch_amr_prolong(dim, H->levels[m].cmp, H->levels[m - 1].E64, C.X[m], H->levels[m].E64, C.st);
+  }
+}
+
+// one composite cycle: corrections of the levels in V order (finest .. 1,
+// 0, 1 .. finest), average-down, composite mean removal (pure Neumann), and
+// the new composite residual and its norm
+void comp_cycle(Comp& C, const amg_solve_opts& o) {
+  amg_hier* H = C.H;
+  const int dim = H->dim;
+  Level& L0 = H->levels[0];
+  for (int l = C.hi; l >= 1; --l) comp_correct(C, o, l);
+  for (int l = 0; l <= C.hi; ++l) comp_correct(C, o, l);
+  for (int l = C.hi; l >= 1; --l) launch_avgdown(dim, H->levels[l].cmp, C.X[l], C.X[l - 1], C.st);
+  if (L0.nsingular) {
+    // composite mean over valid cells = mean over all level-0 cells, since
+    // covered cells hold the averages of the finer levels
+    Run R0{H, &L0, dim, C.st};
+    launch_tile_sum<double>(dim, L0.depths[0], C.X[0], L0.partial, C.st);
+    comp_sums(R0, L0.depths[0], L0.comp_sum);
+    launch_comp_delta(L0.comp_sum, nullptr, L0.d_comp_flag, L0.d_comp_cnt, L0.ncomp, 1.0, 0.0, L0.d_delta, nullptr,
+                      C.st);
+    for (int l = 0; l <= C.hi; ++l) launch_sub_scalar(dim, H->levels[l].depths[0], C.X[l], L0.d_delta, C.st);
+  }
+  comp_residual(C);
 }
 
 }  // namespace
@@ -456,7 +569,29 @@ int amg_finalize(amg_hier* H) {
     sc[S_ONE] = 1.0;
     TRY(upload(H, &L.scal, sc));
     HIPCHK(hipHostMalloc((void**)&L.h_scal, S_COUNT * sizeof(double), hipHostMallocDefault));
+    TRY(zalloc(H, &L.E64, L.depths[0].nstored));
+    L.face_valid.assign((size_t)std::max<int64_t>(L.nface, 1), 1);
   }
+  // composite tables of every interpolated level against the one below
+  for (int l = 1; l < H->nlevels; ++l) {
+    Level& L = H->levels[l];
+    if (L.cf_mode != AMG_CF_INTERP) continue;
+    std::string err;
+    int rc = build_composite(H, l, err);
+    if (rc != AMG_OK) return fail(H, rc, err);
+    Composite& X = L.cmp;
+    std::vector<double> w(&X.w[0][0], &X.w[0][0] + 50);
+    TRY(upload(H, &X.d_w, w));
+    TRY(upload(H, &X.d_cfi_dst, X.cfi_dst));
+    TRY(upload(H, &X.d_cfi_src, X.cfi_src));
+    TRY(upload(H, &X.d_cfi_w, X.cfi_w));
+    TRY(upload(H, &X.d_avg, X.avg));
+    TRY(upload(H, &X.d_rfx_cell, X.rfx_cell));
+    TRY(upload(H, &X.d_rfx_ptr, X.rfx_ptr));
+    TRY(upload(H, &X.d_rfx_face, X.rfx_face));
+    TRY(upload(H, &X.d_pro, X.pro));
+  }
+  for (auto& L : H->levels) TRY(upload(H, &L.d_face_valid, L.face_valid));
   H->finalized = true;
   return AMG_OK;
 }
@@ -646,11 +781,145 @@ int amg_vcycle(amg_hier* H, int level, int dtype, const amg_solve_opts* opts, co
   return AMG_OK;
 }
 
+static int check_opts(amg_hier* H, const amg_solve_opts& o) {
+  if (o.nu1 < 0 || o.nu2 < 0 || o.max_cycles < 0 || o.max_cycles > 100000 ||
+      (o.smoother != AMG_SMOOTH_JACOBI && o.smoother != AMG_SMOOTH_RB) ||
+      (o.precision != AMG_FP64 && o.precision != AMG_MIXED) || !(o.omega > 0))
+    return fail(H, AMG_EINVAL, "bad solve options");
+  return AMG_OK;
+}
+
+static int make_comp(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const double* const* f,
+                     const double* const* face_data, void* stream, Comp& C) {
+  if (lev_lo != 0) return fail(H, AMG_EUNSUPPORTED, "a composite solve starts at level 0");
+  if (lev_hi < 1 || lev_hi >= H->nlevels) return fail(H, AMG_EINVAL, "level out of range");
+  for (int l = 1; l <= lev_hi; ++l)
+    if (H->levels[l].cf_mode != AMG_CF_INTERP)
+      return fail(H, AMG_EINVAL, "levels of a composite solve take interpolated coarse-fine ghosts");
+  C.H = H;
+  C.hi = lev_hi;
+  C.st = stream_of(H, stream);
+  for (int l = 0; l <= lev_hi; ++l) {
+    if (!x[l] || !f[l]) return fail(H, AMG_EINVAL, "null x or f");
+    C.X.push_back(x[l]);
+    C.F.push_back(f[l]);
+    C.FD.push_back(face_data ? face_data[l] : nullptr);
+    C.R.push_back(H->levels[l].r64);
+  }
+  return AMG_OK;
+}
+
+static int composite_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const double* const* f,
+                           const double* const* face_data, const amg_solve_opts* opts, amg_solve_stats* stats,
+                           void* stream) {
+  amg_solve_opts o;
+  amg_default_opts(&o);
+  if (opts) o = *opts;
+  TRY(check_opts(H, o));
+  Comp C;
+  TRY(make_comp(H, lev_lo, lev_hi, x, f, face_data, stream, C));
+  const int dim = H->dim;
+  Level& L0 = H->levels[0];
+  if (stats) memset(stats, 0, sizeof *stats);
+  // solvability of the pure-Neumann composite problem: one constant shift of
+  // the right-hand side on every level (sums over valid cells and over the
+  // physical faces of valid cells)
+  if (L0.nsingular) {
+    for (int l = 0; l <= C.hi; ++l)
+      HIPCHK(hipMemcpyAsync(H->levels[l].fsh, C.F[l], H->levels[l].depths[0].nstored * sizeof(double),
+                            hipMemcpyDeviceToDevice, C.st));
+    for (int l = C.hi; l >= 1; --l) launch_avgdown(dim, H->levels[l].cmp, H->levels[l].fsh, H->levels[l - 1].fsh, C.st);
+    Run R0{H, &L0, dim, C.st};
+    launch_tile_sum<double>(dim, L0.depths[0], L0.fsh, L0.partial, C.st);
+    comp_sums(R0, L0.depths[0], L0.scal + S_FSUM);
+    for (int l = 0; l <= C.hi; ++l) {
+      Level& L = H->levels[l];
+      Depth& D = L.depths[0];
+      if (C.FD[l] && !D.chunks.empty()) {
+        launch_chunk_fdsum(D, C.FD[l], l < H->nlevels - 1 && l < C.hi ? L.d_face_valid : nullptr, L.partial, C.st);
+        launch_seg_reduce(L.partial, nullptr, 1, (int)D.chunks.size(), L0.scal + S_FD + l, false, C.st);
+      } else {
+        launch_zero<double>(L0.scal + S_FD + l, 1, C.st);
+      }
+    }
+    std::vector<double> hs(S_COUNT);
+    HIPCHK(hipMemcpyAsync(hs.data(), L0.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, C.st));
+    HIPCHK(hipStreamSynchronize(C.st));
+    const double h0 = L0.depths[0].h;
+    double g = 0.0;
+    for (int l = 0; l <= C.hi; ++l) g += hs[S_FD + l] * std::pow(H->levels[l].depths[0].h, dim - 1);
+    const double defect = hs[S_FSUM] * std::pow(h0, dim) - g;
+    const double vol = (double)L0.ncells * std::pow(h0, dim);
+    if (stats) {
+      stats->ncomp = 1;
+      stats->defect[0] = defect;
+    }
+    if (o.solvability == AMG_SOLV_RHS_SHIFT) {
+      L0.h_scal[0] = defect / vol;
+      HIPCHK(hipMemcpyAsync(L0.scal + S_DELTA, L0.h_scal, sizeof(double), hipMemcpyHostToDevice, C.st));
+      for (int l = 0; l <= C.hi; ++l) {
+        HIPCHK(hipMemcpyAsync(H->levels[l].fsh, C.F[l], H->levels[l].depths[0].nstored * sizeof(double),
+                              hipMemcpyDeviceToDevice, C.st));
+        launch_sub_scalar(dim, H->levels[l].depths[0], H->levels[l].fsh, L0.scal + S_DELTA, C.st);
+        C.F[l] = H->levels[l].fsh;
+      }
+    }
+  }
+  auto read_norm = [&](double& v) -> int {
+    HIPCHK(hipMemcpyAsync(L0.h_scal, L0.scal + S_NORM, sizeof(double), hipMemcpyDeviceToHost, C.st));
+    HIPCHK(hipStreamSynchronize(C.st));
+    v = L0.h_scal[0];
+    return AMG_OK;
+  };
+  comp_residual(C);
+  HIPCHK(hipGetLastError());
+  double r0 = 0;
+  TRY(read_norm(r0));
+  if (!std::isfinite(r0)) return fail(H, AMG_ENONFINITE, "non-finite initial residual");
+  const double target = std::max(o.tol_rel * r0, o.tol_abs);
+  double rn = r0;
+  int cycles = 0;
+  if (stats) {
+    stats->r0 = r0;
+    stats->history[0] = r0;
+  }
+  while (rn > target && cycles < o.max_cycles) {
+    comp_cycle(C, o);
+    HIPCHK(hipGetLastError());
+    TRY(read_norm(rn));
+    ++cycles;
+    if (stats && cycles < AMG_MAX_HISTORY) stats->history[cycles] = rn;
+    if (!std::isfinite(rn)) return fail(H, AMG_ENONFINITE, "non-finite residual");
+  }
+  if (stats) {
+    stats->cycles = cycles;
+    stats->rfinal = rn;
+    stats->converged = rn <= target;
+  }
+  if (rn > target) return fail(H, AMG_ENOTCONVERGED, "max_cycles reached");
+  return AMG_OK;
+}
+
+int amg_composite_residual(amg_hier* H, int lev_hi, double* const* x, const double* const* f,
+                           const double* const* face_data, double* const* r, void* stream) {
+  if (!H || !H->finalized) return fail(H, AMG_EINVAL, "amg_finalize has not been called");
+  if (!x || !f || !r) return fail(H, AMG_EINVAL, "bad arguments");
+  Comp C;
+  TRY(make_comp(H, 0, lev_hi, x, f, face_data, stream, C));
+  for (int l = 0; l <= lev_hi; ++l) {
+    if (!r[l]) return fail(H, AMG_EINVAL, "null r");
+    C.R[l] = r[l];
+  }
+  comp_residual(C);
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
 int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const double* const* f,
               const double* const* face_data, const amg_solve_opts* opts, amg_solve_stats* stats, void* stream) {
   if (!check_level(H, lev_lo)) return AMG_EINVAL;
   if (!x || !f) return fail(H, AMG_EINVAL, "bad arguments");
-  if (lev_hi != lev_lo) return fail(H, AMG_EUNSUPPORTED, "composite solves are not available in this build");
+  if (lev_hi != lev_lo) return composite_solve(H, lev_lo, lev_hi, x, f, face_data, opts, stats, stream);
   amg_solve_opts o;
   amg_default_opts(&o);
   if (opts) o = *opts;
@@ -679,7 +948,7 @@ int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const doubl
     comp_sums(R, D0, L.comp_sum);
     const double* bsum = nullptr;
     if (FD) {
-      launch_chunk_fdsum(D0, FD, L.partial, R.st);
+      launch_chunk_fdsum(D0, FD, nullptr, L.partial, R.st);
       launch_comp_sum(L.partial, D0.d_cc_ptr, D0.d_cc_idx, L.ncomp, L.d_bsum, R.st);
       bsum = L.d_bsum;
     }

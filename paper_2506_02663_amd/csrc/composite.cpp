@@ -1,0 +1,303 @@
+// Host planner of the composite (multi-level) operator: the index tables of
+// coarse-fine interpolation, average-down, refluxing and the prolongation of
+// a coarse level's correction onto the next finer level.
+//
+//  * Coarse-fine interpolation (AMRCFI, Section 5.2): each interpolated ghost
+//    of level l is a fixed combination of a 5^D window of level-(l-1) cells.
+//    Per direction the weights give the average over the child of the
+//    quartic whose averages over the five window cells equal the data; the
+//    window is centred on the parent and shifted by the least amount that
+//    keeps it inside the domain.  The weights are computed here by solving
+//    the 5 x 5 moment system.
+//  * Average-down (eq. AMR_avergingDownToCrse, COH-4): coarse cell := mean of
+//    its 2^D children.
+//  * Refluxing (COH-3): at a valid coarse cell, the coarse flux through a face
+//    bordering level l is replaced by the mean of the fine fluxes through the
+//    fine faces covering it (fourth-order face derivatives, eq. cell2face).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "amg_internal.h"
+
+namespace amg {
+
+namespace {
+
+// weights[(s + 2) * 2 + child][m]: five window cells m = 0..4, window shifted
+// by s cells from the parent's centred position (parent = window cell 2 - s)
+void cfi_weights(double W[10][5]) {
+  for (int s = -2; s <= 2; ++s)
+    for (int a = 0; a < 2; ++a) {
+      // moment matrix M[m][k] = average of x^k over [m, m+1]; child average of
+      // the quartic = c . coef with M coef = U, so the weights solve M^T w = c
+      long double A[5][6];
+      const long double x0 = (2 - s) + 0.5L * a, x1 = x0 + 0.5L;
+      for (int k = 0; k < 5; ++k) {
+        for (int m = 0; m < 5; ++m) A[k][m] = (std::pow((long double)(m + 1), k + 1) - std::pow((long double)m, k + 1)) / (k + 1);
+        A[k][5] = (std::pow(x1, k + 1) - std::pow(x0, k + 1)) / ((k + 1) * (x1 - x0));
+      }
+      for (int c = 0; c < 5; ++c) {
+        int p = c;
+        for (int r = c + 1; r < 5; ++r)
+          if (std::fabs(A[r][c]) > std::fabs(A[p][c])) p = r;
+        for (int j = 0; j < 6; ++j) std::swap(A[c][j], A[p][j]);
+        for (int r = 0; r < 5; ++r) {
+          if (r == c) continue;
+          const long double f = A[r][c] / A[c][c];
+          for (int j = 0; j < 6; ++j) A[r][j] -= f * A[c][j];
+        }
+      }
+      for (int m = 0; m < 5; ++m) W[(s + 2) * 2 + a][m] = (double)(A[m][5] / A[m][m]);
+    }
+}
+
+struct Owner {  // dense map grid cell -> box at depth 0 of a level
+  int dim;
+  int64_t n[3];
+  std::vector<int32_t> box;
+  int32_t at(const int* g) const {
+    for (int d = 0; d < dim; ++d)
+      if (g[d] < 0 || g[d] >= n[d]) return -1;
+    int64_t i = g[0] + n[0] * (g[1] + (dim == 3 ? n[1] * (int64_t)g[2] : 0));
+    return box[i];
+  }
+};
+
+Owner make_owner(const amg_hier* H, const Level& L, int l) {
+  Owner o;
+  o.dim = H->dim;
+  for (int d = 0; d < 3; ++d) {
+    o.n[d] = 1;
+    if (d < H->dim) {
+      o.n[d] = H->base[d];
+      for (int i = 0; i < l; ++i) o.n[d] *= H->ratio;
+    }
+  }
+  o.box.assign((size_t)(o.n[0] * o.n[1] * o.n[2]), -1);
+  const Depth& D = L.depths[0];
+  for (size_t b = 0; b < D.boxes.size(); ++b) {
+    const Box& B = D.boxes[b];
+    for (int z = B.lo[2]; z <= B.hi[2]; ++z)
+      for (int y = B.lo[1]; y <= B.hi[1]; ++y)
+        for (int x = B.lo[0]; x <= B.hi[0]; ++x) o.box[x + o.n[0] * (y + o.n[1] * (int64_t)z)] = (int32_t)b;
+  }
+  return o;
+}
+
+int64_t elem(const Depth& D, int b, const int* g, int dim) {
+  const BoxD& X = D.boxd[b];
+  const Box& B = D.boxes[b];
+  int64_t e = X.off + (int64_t)(g[0] - B.lo[0] + 2) * X.s[0] + (int64_t)(g[1] - B.lo[1] + 2) * X.s[1];
+  if (dim == 3) e += (int64_t)(g[2] - B.lo[2] + 2) * X.s[2];
+  return e;
+}
+
+int floordiv2(int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
+
+}  // namespace
+
+int build_composite(amg_hier* H, int l, std::string& err) {
+  Level& F = H->levels[l];
+  Level& C = H->levels[l - 1];
+  Composite& X = F.cmp;
+  const int dim = H->dim;
+  char buf[256];
+  cfi_weights(X.w);
+  const Owner oc = make_owner(H, C, l - 1), of = make_owner(H, F, l);
+  const Depth& DF = F.depths[0];
+  const Depth& DC = C.depths[0];
+  const int nwin = dim == 2 ? 25 : 125;
+
+  // every fine cell's parent must be a cell of the coarse level (nesting)
+  for (size_t b = 0; b < DF.boxes.size(); ++b) {
+    const Box& B = DF.boxes[b];
+    int g[3];
+    for (g[2] = B.lo[2]; g[2] <= B.hi[2]; g[2] += (dim == 3 ? 2 : 1))
+      for (g[1] = B.lo[1]; g[1] <= B.hi[1]; g[1] += 2)
+        for (g[0] = B.lo[0]; g[0] <= B.hi[0]; g[0] += 2) {
+          int p[3] = {g[0] / 2, g[1] / 2, dim == 3 ? g[2] / 2 : 0};
+          if (oc.at(p) < 0) {
+            snprintf(buf, sizeof buf, "level %d is not nested in level %d", l, l - 1);
+            err = buf;
+            return AMG_ELAYOUT;
+          }
+        }
+  }
+
+  // ---- coarse-fine interpolation of the ghost cells of kind ZERO ----
+  X.cfi_dst.clear();
+  X.cfi_src.clear();
+  X.cfi_w.clear();
+  for (size_t b = 0; b < DF.boxes.size(); ++b) {
+    const Box& B = DF.boxes[b];
+    for (int d = 0; d < dim; ++d) {
+      int t[2] = {-1, -1}, k = 0;
+      for (int e = 0; e < dim; ++e)
+        if (e != d) t[k++] = e;
+      const int n0 = B.n(t[0]);
+      const int n1 = dim == 3 ? B.n(t[1]) : 1;
+      for (int s = 0; s < 2; ++s) {
+        const FaceCols& fc = DF.faces[b * 6 + d * 2 + s];
+        for (int q1 = 0; q1 < n1; ++q1)
+          for (int q0 = 0; q0 < n0; ++q0) {
+            const size_t col = (size_t)q0 + (size_t)n0 * q1;
+            for (int layer = 1; layer <= 2; ++layer) {
+              const uint8_t kind = layer == 1 ? fc.k1[col] : fc.k2[col];
+              if (kind != G_ZERO) continue;
+              int g[3] = {0, 0, 0};
+              g[d] = s ? B.hi[d] + layer : B.lo[d] - layer;
+              g[t[0]] = B.lo[t[0]] + q0;
+              if (dim == 3) g[t[1]] = B.lo[t[1]] + q1;
+              X.cfi_dst.push_back(elem(DF, (int)b, g, dim));
+              int lo[3] = {0, 0, 0};
+              for (int e = 0; e < dim; ++e) {
+                const int P = floordiv2(g[e]);
+                const int N = (int)oc.n[e];
+                int sh = 0;
+                if (P < 2) sh = 2 - P;
+                if (P > N - 3) sh = (N - 3) - P;
+                lo[e] = P + sh - 2;
+                X.cfi_w.push_back((uint8_t)((sh + 2) * 2 + (g[e] - 2 * P)));
+              }
+              for (int w = 0; w < nwin; ++w) {
+                int q[3] = {lo[0] + w % 5, lo[1] + (w / 5) % 5, dim == 3 ? lo[2] + w / 25 : 0};
+                const int cb = oc.at(q);
+                if (cb < 0) {
+                  snprintf(buf, sizeof buf, "interpolation window of level %d leaves level %d", l, l - 1);
+                  err = buf;
+                  return AMG_EUNSUPPORTED;
+                }
+                const int64_t e = elem(DC, cb, q, dim);
+                if (e > INT32_MAX) {
+                  err = "coarse level too large for 32-bit interpolation indices";
+                  return AMG_EUNSUPPORTED;
+                }
+                X.cfi_src.push_back((int32_t)e);
+              }
+            }
+          }
+      }
+    }
+  }
+
+  // ---- average-down (coarse cells under level l) ----
+  X.avg.clear();
+  std::vector<uint8_t> covered((size_t)(oc.n[0] * oc.n[1] * oc.n[2]), 0);
+  for (size_t b = 0; b < DF.boxes.size(); ++b) {
+    const Box& B = DF.boxes[b];
+    const BoxD& Y = DF.boxd[b];
+    int g[3];
+    for (g[2] = B.lo[2]; g[2] <= B.hi[2]; g[2] += (dim == 3 ? 2 : 1))
+      for (g[1] = B.lo[1]; g[1] <= B.hi[1]; g[1] += 2)
+        for (g[0] = B.lo[0]; g[0] <= B.hi[0]; g[0] += 2) {
+          int p[3] = {g[0] / 2, g[1] / 2, dim == 3 ? g[2] / 2 : 0};
+          AvgD a;
+          memset(&a, 0, sizeof a);
+          a.ce = elem(DC, oc.at(p), p, dim);
+          a.fe = elem(DF, (int)b, g, dim);
+          a.fs1 = Y.s[1];
+          a.fs2 = dim == 3 ? Y.s[2] : 0;
+          X.avg.push_back(a);
+          covered[p[0] + oc.n[0] * (p[1] + oc.n[1] * (int64_t)p[2])] = 1;
+        }
+  }
+  auto is_cov = [&](const int* p) {
+    for (int d = 0; d < dim; ++d)
+      if (p[d] < 0 || p[d] >= oc.n[d]) return false;
+    return covered[p[0] + oc.n[0] * (p[1] + oc.n[1] * (int64_t)p[2])] != 0;
+  };
+
+  // ---- refluxing at valid coarse cells next to level l ----
+  X.rfx_cell.clear();
+  X.rfx_ptr.assign(1, 0);
+  X.rfx_face.clear();
+  for (size_t b = 0; b < DC.boxes.size(); ++b) {
+    const Box& B = DC.boxes[b];
+    const BoxD& Y = DC.boxd[b];
+    int i[3];
+    for (i[2] = B.lo[2]; i[2] <= B.hi[2]; ++i[2])
+      for (i[1] = B.lo[1]; i[1] <= B.hi[1]; ++i[1])
+        for (i[0] = B.lo[0]; i[0] <= B.hi[0]; ++i[0]) {
+          if (is_cov(i)) continue;
+          size_t nf0 = X.rfx_face.size();
+          for (int d = 0; d < dim; ++d)
+            for (int sg = -1; sg <= 1; sg += 2) {
+              int j[3] = {i[0], i[1], i[2]};
+              j[d] += sg;
+              if (!is_cov(j)) continue;
+              // first fine cell past the face, transverse offset 0
+              int f0[3] = {2 * i[0], 2 * i[1], dim == 3 ? 2 * i[2] : 0};
+              f0[d] = sg > 0 ? 2 * j[d] : 2 * j[d] + 1;
+              const int fb = of.at(f0);
+              if (fb < 0) {
+                err = "refluxing: the fine cell past a coarse-fine face is not in the fine level";
+                return AMG_ELAYOUT;
+              }
+              const BoxD& Z = DF.boxd[fb];
+              RfxFaceD r;
+              memset(&r, 0, sizeof r);
+              r.fe = elem(DF, fb, f0, dim);
+              r.fsn = sg * Z.s[d];
+              int t[2] = {-1, -1}, k = 0;
+              for (int e = 0; e < dim; ++e)
+                if (e != d) t[k++] = e;
+              r.ft0 = Z.s[t[0]];
+              r.ft1 = dim == 3 ? Z.s[t[1]] : 0;
+              r.csn = sg * Y.s[d];
+              X.rfx_face.push_back(r);
+            }
+          if (X.rfx_face.size() > nf0) {
+            X.rfx_cell.push_back(elem(DC, (int)b, i, dim));
+            X.rfx_ptr.push_back((int32_t)X.rfx_face.size());
+          }
+        }
+  }
+
+  // ---- prolongation of a level-(l-1) correction onto level l ----
+  X.pro.clear();
+  for (size_t b = 0; b < DF.boxes.size(); ++b) {
+    const Box& B = DF.boxes[b];
+    int g[3];
+    for (g[2] = B.lo[2]; g[2] <= B.hi[2]; ++g[2])
+      for (g[1] = B.lo[1]; g[1] <= B.hi[1]; ++g[1])
+        for (g[0] = B.lo[0]; g[0] <= B.hi[0]; ++g[0]) {
+          int p[3] = {g[0] / 2, g[1] / 2, dim == 3 ? g[2] / 2 : 0};
+          const int cb = oc.at(p);
+          ProlD r;
+          memset(&r, 0, sizeof r);
+          r.fe = elem(DF, (int)b, g, dim);
+          r.pe = elem(DC, cb, p, dim);
+          r.cs1 = DC.boxd[cb].s[1];
+          r.cs2 = dim == 3 ? DC.boxd[cb].s[2] : 0;
+          r.child = (g[0] & 1) | ((g[1] & 1) << 1) | (dim == 3 ? ((g[2] & 1) << 2) : 0);
+          X.pro.push_back(r);
+        }
+  }
+
+  // ---- physical face columns of level l-1 lying under level l ----
+  C.face_valid.assign((size_t)std::max<int64_t>(C.nface, 1), 1);
+  for (size_t b = 0; b < DC.boxes.size(); ++b) {
+    const Box& B = DC.boxes[b];
+    for (int d = 0; d < dim; ++d) {
+      int t[2] = {-1, -1}, k = 0;
+      for (int e = 0; e < dim; ++e)
+        if (e != d) t[k++] = e;
+      const int n0 = B.n(t[0]);
+      const int n1 = dim == 3 ? B.n(t[1]) : 1;
+      for (int s = 0; s < 2; ++s)
+        for (int q1 = 0; q1 < n1; ++q1)
+          for (int q0 = 0; q0 < n0; ++q0) {
+            int i[3] = {0, 0, 0};
+            i[d] = s ? B.hi[d] : B.lo[d];
+            i[t[0]] = B.lo[t[0]] + q0;
+            if (dim == 3) i[t[1]] = B.lo[t[1]] + q1;
+            if (is_cov(i)) C.face_valid[C.face_off[b * 6 + d * 2 + s] + q0 + (int64_t)n0 * q1] = 0;
+          }
+    }
+  }
+  return AMG_OK;
+}
+
+}  // namespace amg

@@ -38,7 +38,16 @@ void launch_comp_delta(const double* sum, const double* bsum, const int32_t* fla
                        double scale_sum, double scale_b, double* delta, double* defect, hipStream_t st);
 template <typename T>
 void launch_comp_shift(int dim, const Depth& D, T* a, const double* delta, hipStream_t st);
-void launch_chunk_fdsum(const Depth& D, const double* fd, double* part, hipStream_t st);
+void launch_chunk_fdsum(const Depth& D, const double* fd, const uint8_t* valid, double* part, hipStream_t st);
+void launch_cfi(int dim, const Composite& X, const double* uc, double* uf, hipStream_t st);
+void launch_avgdown(int dim, const Composite& X, const double* uf, double* uc, hipStream_t st);
+void launch_reflux(int dim, const Composite& X, const double* uc, const double* uf, double* r, double kappa,
+                   double hc, double hf, hipStream_t st);
+void launch_amr_prolong(int dim, const Composite& X, const double* ec, double* u, double* ef, hipStream_t st);
+void launch_max_slots(const double* in, int n, double* out, hipStream_t st);
+void launch_sub_scalar(int dim, const Depth& D, double* a, const double* s, hipStream_t st);
+template <typename T>
+void launch_update2(int dim, const Depth& D, double* x, double* E, const T* e, const double* scal, hipStream_t st);
 template <typename T>
 void launch_update(int dim, const Depth& D, double* x, const T* e, const double* scal, hipStream_t st);
 void launch_to32(int dim, const Depth& D, const double* r, float* r32, const double* scal, hipStream_t st);

@@ -755,13 +755,15 @@ __global__ void k_comp_delta(const double* __restrict__ sum, const double* __res
 
 // sum of face data over Neumann-filled ghost columns of each chunk
 __global__ void __launch_bounds__(256) k_chunk_fdsum(const ChunkD* __restrict__ chunks, int nchunks,
-                                                     const double* __restrict__ fd, double* __restrict__ part) {
+                                                     const double* __restrict__ fd, const uint8_t* __restrict__ valid,
+                                                     double* __restrict__ part) {
   const int ci = blockIdx.x * 256 + threadIdx.x;
   if (ci >= nchunks) return;
   const ChunkD ch = chunks[ci];
   double s = 0.0;
   if (ch.kind1 == G_FILL_N && ch.fd >= 0)
-    for (int i = 0; i < ch.count; ++i) s += fd[ch.fd + i];
+    for (int i = 0; i < ch.count; ++i)
+      if (!valid || valid[ch.fd + i]) s += fd[ch.fd + i];
   part[ci] = s;
 }
 
@@ -775,6 +777,135 @@ __global__ void k_zero(T* __restrict__ a, int64_t n) {
   if (i < n) a[i] = T(0);
 }
 
+
+// ---------------------------------------------------------------------------
+// composite (multi-level) operator
+
+// interpolated ghosts of the finer level: u_f[dst] = sum over the 5^DIM
+// window of the tensor-product weights times the coarse values
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_cfi(int n, const int64_t* __restrict__ dst, const int32_t* __restrict__ src,
+                                             const uint8_t* __restrict__ wsel, const double* __restrict__ W,
+                                             const T* __restrict__ uc, T* __restrict__ uf) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  constexpr int NW = DIM == 2 ? 25 : 125;
+  const int32_t* s = src + (int64_t)i * NW;
+  const double* wx = W + 5 * wsel[i * DIM];
+  const double* wy = W + 5 * wsel[i * DIM + 1];
+  const double* wz = DIM == 3 ? W + 5 * wsel[i * DIM + 2] : nullptr;
+  double acc = 0.0;
+  for (int k = 0; k < (DIM == 3 ? 5 : 1); ++k) {
+    double plane = 0.0;
+    for (int j = 0; j < 5; ++j) {
+      double row = 0.0;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) row += wx[m] * (double)uc[s[k * 25 + j * 5 + m]];
+      plane += wy[j] * row;
+    }
+    acc += (DIM == 3 ? wz[k] : 1.0) * plane;
+  }
+  uf[dst[i]] = (T)acc;
+}
+
+// coarse cell := mean of its 2^DIM children
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_avgdown(int n, const AvgD* __restrict__ a, const T* __restrict__ uf,
+                                                 T* __restrict__ uc) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const AvgD e = a[i];
+  T s = uf[e.fe] + uf[e.fe + 1] + uf[e.fe + e.fs1] + uf[e.fe + e.fs1 + 1];
+  if (DIM == 3) s += uf[e.fe + e.fs2] + uf[e.fe + e.fs2 + 1] + uf[e.fe + e.fs2 + e.fs1] + uf[e.fe + e.fs2 + e.fs1 + 1];
+  uc[e.ce] = s * T(DIM == 2 ? 0.25 : 0.125);
+}
+
+// refluxing: r[c] += kappa * sum over the cell's coarse-fine faces of
+// (mean fine flux - coarse flux) / hc, fluxes = fourth-order derivatives
+// along the normal n pointing into the finer level
+template <int DIM>
+__global__ void __launch_bounds__(256) k_reflux(int ncell, const int64_t* __restrict__ cell,
+                                                const int32_t* __restrict__ ptr, const RfxFaceD* __restrict__ faces,
+                                                const double* __restrict__ uc, const double* __restrict__ uf,
+                                                double* __restrict__ r, double kappa, double inv12hc, double inv12hf,
+                                                double inv_hc) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= ncell) return;
+  const int64_t c = cell[i];
+  double corr = 0.0;
+  for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+    const RfxFaceD F = faces[k];
+    const int64_t n = F.csn;
+    const double Fc = (-uc[c + 2 * n] + 15.0 * uc[c + n] - 15.0 * uc[c] + uc[c - n]) * inv12hc;
+    const int64_t fn = F.fsn;
+    double Ff = 0.0;
+#pragma unroll
+    for (int t = 0; t < (1 << (DIM - 1)); ++t) {
+      const int64_t e = F.fe + ((t & 1) ? F.ft0 : 0) + ((t & 2) ? F.ft1 : 0);
+      Ff += (-uf[e + fn] + 15.0 * uf[e] - 15.0 * uf[e - fn] + uf[e - 2 * fn]) * inv12hf;
+    }
+    Ff *= 1.0 / (1 << (DIM - 1));
+    corr += (Ff - Fc) * inv_hc;
+  }
+  r[c] += kappa * corr;
+}
+
+// prolongation of a coarse correction onto the finer level (face-neighbour
+// linear): v = (1 - DIM/4) E[P] + 1/4 sum_d E[P +- e_d]; u += v, and ef = v
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_amr_prolong(int n, const ProlD* __restrict__ p, const T* __restrict__ ec,
+                                                     T* __restrict__ u, T* __restrict__ ef) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const ProlD q = p[i];
+  T v = T(1.0 - DIM * 0.25) * ec[q.pe] +
+        T(0.25) * (ec[q.pe + ((q.child & 1) ? 1 : -1)] + ec[q.pe + ((q.child & 2) ? q.cs1 : -q.cs1)]);
+  if (DIM == 3) v += T(0.25) * ec[q.pe + ((q.child & 4) ? q.cs2 : -q.cs2)];
+  u[q.fe] += v;
+  if (ef) ef[q.fe] = v;
+}
+
+// out = max over n slots
+__global__ void k_max_slots(const double* __restrict__ in, int n, double* __restrict__ out) {
+  double m = 0.0;
+  for (int i = 0; i < n; ++i) m = fmax(m, in[i]);
+  for (int i = 0; i < n; ++i)
+    if (!(in[i] <= 1e308)) m = in[i];  // NaN / Inf propagate
+  *out = m;
+}
+
+// a -= s[0] on every interior cell
+template <int DIM>
+__global__ void __launch_bounds__(256) k_sub_scalar(const TileD* __restrict__ tiles, int ntiles,
+                                                    const BoxD* __restrict__ boxes, double* __restrict__ a,
+                                                    const double* __restrict__ s) {
+  const double v = s[0];
+  FOR_COLUMN(DIM) {
+    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+    a[c] -= v;
+    if (C.ok1) a[c + 1] -= v;
+  }
+}
+
+// x += s e and E += s e (FP64 x and E, e FP32 or FP64), s = scal[0]
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_update2(const TileD* __restrict__ tiles, int ntiles,
+                                                 const BoxD* __restrict__ boxes, double* __restrict__ x,
+                                                 double* __restrict__ E, const T* __restrict__ e,
+                                                 const double* __restrict__ scal) {
+  const double s = scal[0];
+  FOR_COLUMN(DIM) {
+    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+    const double v0 = s * (double)e[c];
+    x[c] += v0;
+    E[c] += v0;
+    if (C.ok1) {
+      const double v1 = s * (double)e[c + 1];
+      x[c + 1] += v1;
+      E[c + 1] += v1;
+    }
+  }
+}
 
 // ===========================================================================
 // host-side launchers
@@ -959,11 +1090,74 @@ void launch_comp_shift(int dim, const Depth& D, T* a, const double* delta, hipSt
     hipLaunchKernelGGL((k_comp_shift<T, 3>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, a, delta);
 }
 
-void launch_chunk_fdsum(const Depth& D, const double* fd, double* part, hipStream_t st) {
+void launch_chunk_fdsum(const Depth& D, const double* fd, const uint8_t* valid, double* part, hipStream_t st) {
   const int n = (int)D.chunks.size();
   if (!n) return;
-  hipLaunchKernelGGL(k_chunk_fdsum, dim3((n + 255) / 256), dim3(256), 0, st, D.d_chunks, n, fd, part);
+  hipLaunchKernelGGL(k_chunk_fdsum, dim3((n + 255) / 256), dim3(256), 0, st, D.d_chunks, n, fd, valid, part);
 }
+
+void launch_cfi(int dim, const Composite& X, const double* uc, double* uf, hipStream_t st) {
+  const int n = (int)X.cfi_dst.size();
+  if (!n) return;
+  if (dim == 2)
+    hipLaunchKernelGGL((k_cfi<double, 2>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_cfi_dst, X.d_cfi_src,
+                       X.d_cfi_w, X.d_w, uc, uf);
+  else
+    hipLaunchKernelGGL((k_cfi<double, 3>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_cfi_dst, X.d_cfi_src,
+                       X.d_cfi_w, X.d_w, uc, uf);
+}
+
+void launch_avgdown(int dim, const Composite& X, const double* uf, double* uc, hipStream_t st) {
+  const int n = (int)X.avg.size();
+  if (!n) return;
+  if (dim == 2)
+    hipLaunchKernelGGL((k_avgdown<double, 2>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_avg, uf, uc);
+  else
+    hipLaunchKernelGGL((k_avgdown<double, 3>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_avg, uf, uc);
+}
+
+void launch_reflux(int dim, const Composite& X, const double* uc, const double* uf, double* r, double kappa,
+                   double hc, double hf, hipStream_t st) {
+  const int n = (int)X.rfx_cell.size();
+  if (!n) return;
+  if (dim == 2)
+    hipLaunchKernelGGL(k_reflux<2>, dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_rfx_cell, X.d_rfx_ptr,
+                       X.d_rfx_face, uc, uf, r, kappa, 1.0 / (12 * hc), 1.0 / (12 * hf), 1.0 / hc);
+  else
+    hipLaunchKernelGGL(k_reflux<3>, dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_rfx_cell, X.d_rfx_ptr,
+                       X.d_rfx_face, uc, uf, r, kappa, 1.0 / (12 * hc), 1.0 / (12 * hf), 1.0 / hc);
+}
+
+void launch_amr_prolong(int dim, const Composite& X, const double* ec, double* u, double* ef, hipStream_t st) {
+  const int n = (int)X.pro.size();
+  if (!n) return;
+  if (dim == 2)
+    hipLaunchKernelGGL((k_amr_prolong<double, 2>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_pro, ec, u, ef);
+  else
+    hipLaunchKernelGGL((k_amr_prolong<double, 3>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_pro, ec, u, ef);
+}
+
+void launch_max_slots(const double* in, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_max_slots, dim3(1), dim3(1), 0, st, in, n, out);
+}
+
+void launch_sub_scalar(int dim, const Depth& D, double* a, const double* s, hipStream_t st) {
+  const size_t n = D.tiles.size();
+  if (!n) return;
+  DISPATCH_DIM(dim, k_sub_scalar, D.d_tiles, (int)n, D.d_box, a, s);
+}
+
+template <typename T>
+void launch_update2(int dim, const Depth& D, double* x, double* E, const T* e, const double* scal, hipStream_t st) {
+  const size_t n = D.tiles.size();
+  if (!n) return;
+  if (dim == 2)
+    hipLaunchKernelGGL((k_update2<T, 2>), grid8(n), threads<2>(), 0, st, D.d_tiles, (int)n, D.d_box, x, E, e, scal);
+  else
+    hipLaunchKernelGGL((k_update2<T, 3>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, x, E, e, scal);
+}
+template void launch_update2<float>(int, const Depth&, double*, double*, const float*, const double*, hipStream_t);
+template void launch_update2<double>(int, const Depth&, double*, double*, const double*, const double*, hipStream_t);
 
 template <typename T>
 void launch_update(int dim, const Depth& D, double* x, const T* e, const double* scal, hipStream_t st) {

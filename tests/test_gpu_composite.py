@@ -1,0 +1,123 @@
+"""Composite (multi-level) path on the GPU against the oracle: the composite
+residual (interpolated coarse-fine ghosts, refluxing, average-down) element
+by element, and whole composite solves in FP64 (same cycle, same residual
+history) and mixed precision."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import amr  # noqa: E402
+from paper_2506_02663_amd import amg as A  # noqa: E402
+from tests.gpuhelp import faces_to_dev, from_dev, to_dev  # noqa: E402
+
+
+def make_oracle(name, bc):
+    phys = {(d, s): bc for d in range(2) for s in (0, 1)}
+    if name == "two_level":
+        boxes = [[((0, 0), (15, 15))], [((8, 8), (15, 23)), ((16, 8), (23, 15))]]
+        return amr.Hierarchy((16, 16), 1.0 / 16, boxes, phys), (16, 16), 1.0 / 16, boxes
+    if name == "three_level":
+        boxes = [[((0, 0), (15, 15))], [((4, 4), (27, 27))], [((16, 16), (31, 31))]]
+        return amr.Hierarchy((16, 16), 1.0 / 16, boxes, phys), (16, 16), 1.0 / 16, boxes
+    if name == "corner":  # a fine box in a corner of the domain
+        boxes = [[((0, 0), (15, 7))], [((0, 0), (7, 7))]]
+        return amr.Hierarchy((16, 8), 1.0 / 16, boxes, phys), (16, 8), 1.0 / 16, boxes
+    if name == "boundary":  # fine boxes touching the physical boundary, two of them face to face
+        boxes = [[((0, 0), (15, 15)), ((16, 0), (31, 15))], [((0, 0), (15, 15)), ((16, 0), (23, 11))]]
+        return amr.Hierarchy((32, 16), 1.0 / 32, boxes, phys), (32, 16), 1.0 / 32, boxes
+    raise KeyError(name)
+
+
+def make_gpu(base, h0, boxes, bc, op, c):
+    H = A.Hierarchy(2, base, h0, len(boxes))
+    for l, bl in enumerate(boxes):
+        H.set_level_boxes(l, bl)
+        if l:
+            H.set_cf_mode(l, A.CF_INTERP)
+    for d in range(2):
+        for s in (0, 1):
+            H.set_physical_bc(d, s, A.DIRICHLET if bc == "D" else A.NEUMANN)
+    H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c)
+    H.finalize()
+    return H
+
+
+def random_levels(OH, seed, faces=False):
+    rng = np.random.default_rng(seed)
+    out = []
+    for lev in OH.levels:
+        if faces:
+            fd = lev.zero_face_data()
+            for k in fd:
+                e = lev.end_is_physical(*k)
+                fd[k][e] = rng.normal(size=int(e.sum()))
+            out.append(fd)
+        else:
+            u = lev.zeros()
+            u[lev.mask] = rng.normal(size=lev.ncells)
+            out.append(u)
+    return out
+
+
+def relmax(G, O, masks):
+    num = max(np.abs(G[l] - O[l])[masks[l]].max() for l in range(len(G)))
+    den = max(np.abs(O[l])[masks[l]].max() for l in range(len(G)))
+    return num / den
+
+
+CASES = [("corner", "D", "helmholtz", 0.3 / 16), ("corner", "N", "poisson", 0.0),
+         ("two_level", "D", "helmholtz", 0.4 / 16), ("two_level", "N", "poisson", 0.0),
+         ("three_level", "D", "poisson", 0.0), ("three_level", "N", "helmholtz", 0.2 / 16),
+         ("boundary", "N", "poisson", 0.0), ("boundary", "D", "helmholtz", 0.3 / 32)]
+
+
+@pytest.mark.parametrize("name,bc,op,c", CASES)
+def test_composite_residual(name, bc, op, c):
+    OH, base, h0, boxes = make_oracle(name, bc)
+    H = make_gpu(base, h0, boxes, bc, op, c)
+    U = random_levels(OH, 1)
+    F = random_levels(OH, 2)
+    FD = random_levels(OH, 3, faces=True)
+    xs = [to_dev(H, l, 0, U[l]) for l in range(OH.nlev)]
+    fs = [to_dev(H, l, 0, F[l]) for l in range(OH.nlev)]
+    fds = [faces_to_dev(H, l, OH.levels[l], FD[l]) for l in range(OH.nlev)]
+    rs = [torch.zeros_like(x) for x in xs]
+    H.composite_residual(xs, fs, rs, fds)
+    torch.cuda.synchronize()
+    want = amr.composite_residual(OH, OH.average_down_all(U), F, op, c, FD)
+    got = [from_dev(H, l, 0, rs[l], OH.levels[l]) for l in range(OH.nlev)]
+    # valid cells and covered cells (averaged residual) alike
+    assert relmax(got, want, [lev.mask for lev in OH.levels]) < 1e-11
+    # x comes back averaged down
+    xd = [from_dev(H, l, 0, xs[l], OH.levels[l]) for l in range(OH.nlev)]
+    assert relmax(xd, OH.average_down_all(U), [lev.mask for lev in OH.levels]) < 1e-14
+
+
+@pytest.mark.parametrize("name,bc,op,c", CASES)
+def test_composite_solve(name, bc, op, c):
+    OH, base, h0, boxes = make_oracle(name, bc)
+    H = make_gpu(base, h0, boxes, bc, op, c)
+    F = random_levels(OH, 4)
+    FD = random_levels(OH, 5, faces=True)
+    Uo, sto = amr.composite_solve(OH, F, op, c, FD, tol_rel=1e-12, max_cycles=200)
+    assert sto["converged"]
+    fs = [to_dev(H, l, 0, F[l]) for l in range(OH.nlev)]
+    fds = [faces_to_dev(H, l, OH.levels[l], FD[l]) for l in range(OH.nlev)]
+    for prec, tol in ((A.FP64, 1e-11), (A.MIXED, 1e-9)):
+        xs = [torch.zeros_like(f) for f in fs]
+        st = H.solve_composite(xs, fs, fds, A.default_opts(precision=prec, tol_rel=1e-12, max_cycles=200))
+        assert st["status"] == 0 and st["converged"], st
+        got = [from_dev(H, l, 0, xs[l], OH.levels[l]) for l in range(OH.nlev)]
+        assert relmax(got, Uo, OH.valid) < tol, (prec, st["cycles"], sto["cycles"])
+        if prec == A.FP64:
+            hist, ho = np.array(st["history"]), np.array(sto["history"])
+            assert abs(len(hist) - len(ho)) <= 1
+            k = min(len(hist), len(ho))
+            assert np.allclose(hist[:k], ho[:k], rtol=1e-5, atol=1e-14 * ho[0])
+        if OH.singular(op):
+            assert np.isclose(st["defects"][0], sto["defect"], rtol=1e-9, atol=1e-13)
