@@ -31,7 +31,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="c3", choices=["c1", "c3", "c4"])
+    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
     p.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     p.add_argument("--smoother", default="jacobi", choices=["jacobi", "rb"])
     p.add_argument("--n", type=int, default=0, help="cells per direction (default: the workload's)")
@@ -89,6 +89,8 @@ def main():
     elif args.workload == "c1":
         dim, n, nu = 2, args.n or 128, 1e-3
         sample = (2, 64, 1e-3)
+    elif args.workload == "c2":
+        return bench_amr(args)
     else:
         return bench_batched(args)
 
@@ -198,6 +200,89 @@ def main():
                            "avg_us": avg_s * 1e6, "launches": cnt, "bytes_per_launch": bytes_launch}
         out["kernel_ms_per_step"] = {k: v[1] / args.steps for k, v in kinds.items()}
         out["ms_per_step_event_pass"] = timed_ms
+    if base is not None:
+        out["cpu_baseline"] = base
+    print(json.dumps(out), flush=True)
+
+
+def bench_amr(args):
+    """Two-level AMR workload: level 0 = 256^2 cells on [0,1]^2, level 1 = the
+    56 boxes of 32^2 cells (h = 1/512) tiling two disks.  One step = the
+    composite Helmholtz solve (Dirichlet, c = 0.5 nu k, nu = 1e-3, k = 1/256)
+    and the composite pure-Neumann Poisson solve, each from 0 to 1e-10;
+    DOF = valid cells of the composite (108,544) per solve."""
+    from paper_2506_02663_amd import workloads as W
+    boxes = W.amr_two_level_boxes()
+    c = 0.5e-3 / 256
+    base = None
+    if not args.no_cpu_baseline:
+        from oracle import amr
+        t0 = time.perf_counter()
+        OH = amr.Hierarchy((256, 256), 1.0 / 256, boxes, {(d, s): "D" for d in range(2) for s in (0, 1)})
+        F = []
+        for l, lev in enumerate(OH.levels):
+            f = lev.zeros()
+            f[lev.inner] = W.single_level_rhs(lev.shape, lev.h, "helmholtz", c, seed=l)
+            F.append(f)
+        _, st = amr.composite_solve(OH, F, "helmholtz", c, None, tol_rel=1e-10)
+        dt = time.perf_counter() - t0
+        nvalid = sum(int(v.sum()) for v in OH.valid)
+        base = {"value": nvalid / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+                "sample": f"the composite Helmholtz solve of the workload (one of its two solves), {dt:.1f} s"}
+    import torch
+
+    from paper_2506_02663_amd import amg as A
+    prec = A.MIXED if args.precision == "mixed" else A.FP64
+    sm = A.SMOOTH_JACOBI if args.smoother == "jacobi" else A.SMOOTH_RB
+    opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100)
+    systems = []
+    for op, bc in (("helmholtz", "D"), ("poisson", "N")):
+        H = A.Hierarchy(2, (256, 256), 1.0 / 256, 2)
+        for l, bl in enumerate(boxes):
+            H.set_level_boxes(l, bl)
+        H.set_cf_mode(1, A.CF_INTERP)
+        for d in range(2):
+            for s in (0, 1):
+                H.set_physical_bc(d, s, A.DIRICHLET if bc == "D" else A.NEUMANN)
+        H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c if op == "helmholtz" else 0.0)
+        H.finalize()
+        fs = []
+        for l in range(2):
+            n = 256 * 2 ** l
+            f = W.single_level_rhs((n, n), 1.0 / n, op, c if op == "helmholtz" else 0.0, seed=l)
+            fs.append(torch.tensor(H.pack(l, 0, lambda i, b, f=f: f[b["lo"][0]:b["hi"][0] + 1,
+                                                                    b["lo"][1]:b["hi"][1] + 1]), device="cuda"))
+        xs = [torch.zeros_like(f) for f in fs]
+        systems.append((op, H, xs, fs))
+    nvalid = 256 * 256 - 57344 // 4 + 57344
+    cycles = {}
+
+    def step():
+        for op, H, xs, fs in systems:
+            for x in xs:
+                x.zero_()
+            st = H.solve_composite(xs, fs, None, opts)
+            if st["status"] != 0 or not st["converged"]:
+                raise RuntimeError(f"{op} composite solve did not converge: {st}")
+            cycles[op] = st["cycles"]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {
+        "metric": "MG solve DOF/s to 1e-10 rel. residual, FP32-refined vs FP64; % HBM peak",
+        "value": 2 * nvalid * args.steps / dt, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32-in-f64" if prec == A.MIXED else "f64", "data": "synthetic",
+        "config": {"workload": "2D two-level AMR 256^2 + 56 boxes of 32^2 (ratio 2), composite Helmholtz + "
+                               "composite Neumann Poisson", "dof_per_step": 2 * nvalid, "tol_rel": 1e-10,
+                   "cycles": cycles, "smoother": args.smoother, "precision": args.precision},
+    }
     if base is not None:
         out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)

@@ -105,3 +105,11 @@ def disk_boxes(centres_radii, nfine, bs):
             if any((cx - x) ** 2 + (cy - y) ** 2 < r * r for (x, y), r in centres_radii):
                 boxes.append(((bi * bs, bj * bs), (bi * bs + bs - 1, bj * bs + bs - 1)))
     return boxes
+
+
+def amr_two_level_boxes():
+    """Two-level layout: level 0 one 256^2 box on [0,1]^2; level 1 the 32^2
+    boxes of the 512^2 grid whose centres lie inside the disk of radius 0.25
+    at (0.5, 0.5) or the disk of radius 0.08 at (0.8, 0.2) (56 boxes, two
+    face-connected components)."""
+    return [[((0, 0), (255, 255))], disk_boxes([((0.5, 0.5), 0.25), ((0.8, 0.2), 0.08)], 512, 32)]
