@@ -33,11 +33,53 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
     p.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    p.add_argument("--smoother", default="jacobi", choices=["jacobi", "rb"])
+    p.add_argument("--smoother", default="rb", choices=["jacobi", "rb"])
     p.add_argument("--n", type=int, default=0, help="cells per direction (default: the workload's)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-timing", action="store_true", help="skip the per-kernel event timing")
+    p.add_argument("--copy-probe", action="store_true",
+                   help="first run a plain 256 MiB device copy three times (the reference kernel that "
+                        "calibrates the HBM byte counters)")
     return p.parse_args()
+
+
+def copy_probe():
+    """Three launches of a plain device-to-device copy of 2^25 doubles
+    (256 MiB read + 256 MiB written per launch)."""
+    import torch
+    src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def measured_traffic(name):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary profiles/<name>: FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+    each scaled by the factor that the same counter shows for the plain copy
+    kernel.  None when the summary is missing or was taken on a different
+    kernels.hip (its sha256 is recorded in the summary)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", " ")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2506_02663_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("kernels_hip_sha256") != sha:
+        return None
+    try:
+        fetch = float(kv["fetch_kib_per_launch"]) * float(kv["fetch_factor"])
+        write = float(kv["write_kib_per_launch"]) * float(kv["write_factor"])
+    except (KeyError, ValueError):
+        return None
+    return (fetch + write) * 1024.0
 
 
 # ---------------------------------------------------------------------------
@@ -53,9 +95,9 @@ def single_level_problems(dim, n, nu):
     return h, c, [("helmholtz", "D", helm), ("poisson", "N", pois)]
 
 
-def cpu_baseline(dim, n, nu):
+def cpu_baseline(dim, n, nu, smoother):
     """The FP64 oracle on a bounded sample of the same workload (same recipe,
-    smaller grid), single-threaded, timed on the host."""
+    same smoother, smaller grid), single-threaded, timed on the host."""
     import numpy as np
 
     from oracle import mg
@@ -67,13 +109,13 @@ def cpu_baseline(dim, n, nu):
         lev = Level((n,) * dim, h, [((0,) * dim, (n - 1,) * dim)], {(d, s): bc for d in range(dim) for s in (0, 1)})
         fa = lev.zeros()
         fa[lev.inner] = f
-        x, st = mg.solve(lev, fa, op, c, tol_rel=1e-10, max_cycles=100)
+        x, st = mg.solve(lev, fa, op, c, tol_rel=1e-10, max_cycles=100, smoother=smoother)
         assert st["converged"]
         dof += lev.ncells
     dt = time.perf_counter() - t0
     return {"value": dof / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
             "sample": f"{dim}D {n}^{dim}: Helmholtz (Dirichlet) + Neumann Poisson solves to 1e-10, "
-                      f"same recipe as the timed workload, {dt:.1f} s"}
+                      f"same recipe and smoother ({smoother}) as the timed workload, {dt:.1f} s"}
 
 
 def main():
@@ -85,7 +127,7 @@ def main():
 
     if args.workload == "c3":
         dim, n, nu = 3, args.n or 256, 1e-4
-        sample = (3, 32, 1e-4)
+        sample = (3, 64, 1e-4)
     elif args.workload == "c1":
         dim, n, nu = 2, args.n or 128, 1e-3
         sample = (2, 64, 1e-3)
@@ -97,9 +139,11 @@ def main():
     base = None
     if not args.no_cpu_baseline:
         # before the GPU is touched: single-threaded numpy
-        base = cpu_baseline(*sample)
+        base = cpu_baseline(*sample, args.smoother)
 
     import torch
+    if args.copy_probe:
+        copy_probe()
 
     from paper_2506_02663_amd import amg as A
 
@@ -192,12 +236,37 @@ def main():
         if args.smoother == "jacobi":
             bytes_launch = 3 * word * n ** dim          # read u, read f, write u_new
         else:
-            bytes_launch = 2.5 * word * n ** dim        # read u, f on one colour, write u_new
+            # one half-sweep: read u, read f on one colour, write that colour
+            bytes_launch = 2 * word * n ** dim
         ach = bytes_launch / avg_s / 1e9
+        traffic = None
+        if dim == 3 and n == 256 and word == 4:
+            traffic = measured_traffic(f"{args.smoother}_sweep_fp32_256cubed_counters.txt")
+        # the same kernel launched back to back (20 sweeps of amg_smooth on the
+        # finest depth of the Helmholtz system): the launches queue up on the
+        # stream, so the events bracket the kernel and not the host's
+        # launch gaps of the solve
+        _, H0, x0, f0 = systems[0]
+        dt_ = torch.float32 if word == 4 else torch.float64
+        u_ = (f0 * 1e-3).to(dt_)
+        f_ = f0.to(dt_)
+        t_ = torch.zeros_like(u_)
+        H0.timing(True)
+        H0.smooth(0, 0, u_, f_, t_, smoother=sm, nsweeps=2)  # warm
+        H0.timing_read(A.T_SWEEP, reset=True)
+        H0.smooth(0, 0, u_, f_, t_, smoother=sm, nsweeps=20)
+        torch.cuda.synchronize()
+        bcnt, btot = H0.timing_read(A.T_SWEEP, reset=True)
+        H0.timing(False)
+        del u_, f_, t_
+        bavg_s = btot / bcnt / 1e3
+        ach = bytes_launch / bavg_s / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                           "kernel": f"{args.smoother} sweep, finest depth, {'FP32' if word == 4 else 'FP64'}",
-                           "avg_us": avg_s * 1e6, "launches": cnt, "bytes_per_launch": bytes_launch}
+                           "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                           "kernel": f"{args.smoother} {'half-' if args.smoother == 'rb' else ''}sweep, finest depth, "
+                                     f"{'FP32' if word == 4 else 'FP64'}",
+                           "avg_us": bavg_s * 1e6, "launches": bcnt, "bytes_per_launch": bytes_launch,
+                           "avg_us_inside_solves": avg_s * 1e6, "launches_inside_solves": cnt}
         out["kernel_ms_per_step"] = {k: v[1] / args.steps for k, v in kinds.items()}
         out["ms_per_step_event_pass"] = timed_ms
     if base is not None:
@@ -224,7 +293,7 @@ def bench_amr(args):
             f = lev.zeros()
             f[lev.inner] = W.single_level_rhs(lev.shape, lev.h, "helmholtz", c, seed=l)
             F.append(f)
-        _, st = amr.composite_solve(OH, F, "helmholtz", c, None, tol_rel=1e-10)
+        _, st = amr.composite_solve(OH, F, "helmholtz", c, None, tol_rel=1e-10, smoother=args.smoother)
         dt = time.perf_counter() - t0
         nvalid = sum(int(v.sum()) for v in OH.valid)
         base = {"value": nvalid / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
@@ -311,7 +380,7 @@ def bench_batched(args):
             lev = Level((s, s), h, [((0, 0), (s - 1, s - 1))], {(d, sd): "D" for d in range(2) for sd in (0, 1)})
             f = lev.zeros()
             f[lev.inner] = fs[i]
-            x, st = mg.solve(lev, f, "helmholtz", c, tol_rel=1e-10)
+            x, st = mg.solve(lev, f, "helmholtz", c, tol_rel=1e-10, smoother=args.smoother)
             assert st["converged"]
             dof += s * s
         dt = time.perf_counter() - t0
@@ -378,7 +447,7 @@ def bench_batched(args):
         cnt, tot = H.timing_read(A.T_SWEEP, reset=False)
         avg_s = tot / cnt / 1e3
         word = 4 if prec == A.MIXED else 8
-        bytes_launch = (3 if args.smoother == "jacobi" else 2.5) * word * ncell
+        bytes_launch = (3 if args.smoother == "jacobi" else 2) * word * ncell
         ach = bytes_launch / avg_s / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": None,

@@ -278,7 +278,8 @@ int amg_vcycle(amg_hier* h, int level, int dtype, const amg_solve_opts* opts, co
 int amg_timing_enable(amg_hier* h, int on);
 
 /* Launch count and summed duration (ms) of kernel kind `kind` since the last
- * reset; reset != 0 clears the counters after reading. */
+ * reset; reset != 0 clears the counters after reading.  Launches made by the
+ * step-level calls (amg_smooth, ...) are waited for and collected first. */
 int amg_timing_read(amg_hier* h, int kind, int64_t* count, double* total_ms, int reset);
 
 #ifdef __cplusplus

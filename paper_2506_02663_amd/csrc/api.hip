@@ -1084,13 +1084,18 @@ int amg_timing_enable(amg_hier* H, int on) {
   H->timer.next = H->timer.base = 0;
   if (H->timer.on && H->timer.pool.empty()) {
     H->timer.pool.resize(8192);
-    for (auto& e : H->timer.pool) HIPCHK(hipEventCreate(&e));
+    // timing-only events: no system-scope fence when they complete
+    for (auto& e : H->timer.pool) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
   return AMG_OK;
 }
 
 int amg_timing_read(amg_hier* H, int kind, int64_t* count, double* total_ms, int reset) {
   if (!H || kind < 0 || kind >= AMG_T_KINDS) return AMG_EINVAL;
+  if (!H->timer.pending.empty()) {  // launches made outside a solve (step-level calls)
+    (void)hipEventSynchronize(H->timer.pool[H->timer.pending.back().second + 1]);
+    collect_timing(H->timer);
+  }
   if (count) *count = H->timer.count[kind];
   if (total_ms) *total_ms = H->timer.total_ms[kind];
   if (reset) {
