@@ -194,6 +194,60 @@ class Level:
         out[~self.mask] = 0.0
         return out
 
+    def apply_T(self, lam, op, c):
+        """Transpose of the homogeneous operator: the A_T with
+        <A_hom u, lam> = <u, A_T lam> for all u (the adjoint of the level
+        system; not in the paper).
+
+        The homogeneous A is "fill the ghosts from the level's own cells, then
+        apply the stencil".  Its transpose applies the (symmetric) stencil to
+        lam extended by zero, where the neighbour is a cell of the level
+        (other boxes included: exchange ghosts are plain cells here), then
+        sends every ghost's adjoint mu (the stencil weights the cells next to
+        that ghost put on it) back to the cells the fill read, with the fill
+        weights.  The fill weights are taken from the fill formulas
+        themselves (applied to unit vectors), not retyped."""
+        dim = self.dim
+        zero = self.zeros()
+        # stencil on lam extended by zero (G = 0 everywhere)
+        Ltl = self.laplacian(lam, {(d, s): zero for d in range(dim) for s in (0, 1)})
+        back = self.zeros()
+        k12 = 12.0 * self.h * self.h
+        unit = [[1.0 if m == j else 0.0 for m in range(4)] for j in range(4)]
+        wd = [fv.dirichlet_ghosts(*unit[j], 0.0) for j in range(4)]
+        wn = [fv.neumann_ghosts(*unit[j], 0.0, self.h) for j in range(4)]
+        for d in range(dim):
+            for s in (0, 1):
+                step = 1 if s == 1 else -1
+                end = self.row_end(d, s)
+                kinds = self.end_kind(d, s)
+                lam0 = np.where(self.mask, lam, 0.0)
+                lam1 = _shift(lam0, d, -step)
+                # stencil weights on the first ghost (from the end cell and the
+                # next cell) and on the second ghost (from the end cell), at
+                # the row end; a ghost position that is a cell of the level
+                # is not a ghost (the neighbour() rule)
+                g1_is_ghost = ~_shift(self.mask, d, step)
+                g2_is_ghost = ~_shift(self.mask, d, 2 * step)
+                mu1 = np.where(g1_is_ghost, (16.0 * lam0 - lam1) / k12, 0.0)
+                mu2 = np.where(g2_is_ghost, -lam0 / k12, 0.0)
+                for kind, w in ((DIRICHLET, wd), (NEUMANN, wn)):
+                    sel = end & (kinds == kind)
+                    if not sel.any():
+                        continue
+                    for j in range(4):
+                        contrib = np.where(sel, w[j][0] * mu1 + w[j][1] * mu2, 0.0)
+                        back += _shift(contrib, d, j * step)
+        back[~self.mask] = 0.0
+        if op == "helmholtz":
+            out = lam - c * (Ltl + back)
+        elif op == "poisson":
+            out = Ltl + back
+        else:
+            raise ValueError(op)
+        out[~self.mask] = 0.0
+        return out
+
     def diagonal(self, op, c):
         """Coefficient of u_i in (A u)_i with the homogeneous ghost fill
         folded in.  Obtained by probing: along direction d the folded 1-D

@@ -58,20 +58,24 @@ def prolong(coarse, ec, fine):
     return out
 
 
-def jacobi(lev, e, f, op, c, D, omega, nsweeps):
+def _A(lev, u, op, c, transpose):
+    return lev.apply_T(u, op, c) if transpose else lev.apply(u, op, c)
+
+
+def jacobi(lev, e, f, op, c, D, omega, nsweeps, transpose=False):
     for _ in range(nsweeps):
-        r = f - lev.apply(e, op, c)
+        r = f - _A(lev, e, op, c, transpose)
         e = e + omega * r / D
         e[~lev.mask] = 0.0
     return e
 
 
-def red_black(lev, e, f, op, c, D, nsweeps):
+def red_black(lev, e, f, op, c, D, nsweeps, transpose=False):
     red = lev.colour() & lev.mask
     black = ~lev.colour() & lev.mask
     for _ in range(nsweeps):
         for sel in (red, black):
-            r = f - lev.apply(e, op, c)
+            r = f - _A(lev, e, op, c, transpose)
             e = e.copy()
             e[sel] += r[sel] / D[sel]
     return e
@@ -92,11 +96,14 @@ def assemble(lev, op, c):
 
 class Bottom:
     """Exact solve on the coarsest depth (the bottom solver of Section 6.5
-    replaced by a direct FP64 solve)."""
+    replaced by a direct FP64 solve).  transpose: solve with the transposed
+    matrix (the adjoint system); the zero-mean border is the same."""
 
-    def __init__(self, lev, op, c):
+    def __init__(self, lev, op, c, transpose=False):
         self.lev = lev
         M, self.cells = assemble(lev, op, c)
+        if transpose:
+            M = M.T.copy()
         self.sing = lev.singular_components(op)
         n = M.shape[0]
         k = len(self.sing)
@@ -116,21 +123,27 @@ class Bottom:
 
 
 class MG:
-    """V(nu1, nu2) cycle on the multigrid depths of one level."""
+    """V(nu1, nu2) cycle on the multigrid depths of one level.
 
-    def __init__(self, lev, op, c, nu1=2, nu2=2, smoother="jacobi", omega=2.0 / 3.0):
+    transpose=True gives the V-cycle of the adjoint system: the transposed
+    operator at every depth (same diagonal, since a matrix and its transpose
+    share it), the same restriction and prolongation, the transposed bottom
+    matrix."""
+
+    def __init__(self, lev, op, c, nu1=2, nu2=2, smoother="jacobi", omega=2.0 / 3.0, transpose=False):
         self.levels = lev.hierarchy()
         self.op, self.c = op, c
+        self.transpose = transpose
         self.nu1, self.nu2, self.smoother, self.omega = nu1, nu2, smoother, omega
         self.D = [l.diagonal(op, c) for l in self.levels]
         self.sing = [l.singular_components(op) for l in self.levels]
-        self.bottom = Bottom(self.levels[-1], op, c)
+        self.bottom = Bottom(self.levels[-1], op, c, transpose)
 
     def smooth(self, k, e, f, n):
         lev = self.levels[k]
         if self.smoother == "jacobi":
-            return jacobi(lev, e, f, self.op, self.c, self.D[k], self.omega, n)
-        return red_black(lev, e, f, self.op, self.c, self.D[k], n)
+            return jacobi(lev, e, f, self.op, self.c, self.D[k], self.omega, n, self.transpose)
+        return red_black(lev, e, f, self.op, self.c, self.D[k], n, self.transpose)
 
     def vcycle(self, f, k=0):
         """Correction e with A_hom e ~= f on depth k (homogeneous ghosts)."""
@@ -138,7 +151,7 @@ class MG:
         if k == len(self.levels) - 1:
             return self.bottom.solve(f)
         e = self.smooth(k, lev.zeros(), f, self.nu1)
-        r = f - lev.apply(e, self.op, self.c)
+        r = f - _A(lev, e, self.op, self.c, self.transpose)
         coarse = self.levels[k + 1]
         fc = restrict(lev, r, coarse)
         fc = coarse.comp_mean(fc, self.sing[k + 1])
@@ -175,18 +188,24 @@ def norm_inf(lev, a):
 
 
 def solve(lev, f, op, c, fd=None, cfv=None, x0=None, nu1=2, nu2=2, smoother="jacobi",
-          omega=2.0 / 3.0, tol_rel=1e-10, tol_abs=0.0, max_cycles=50, shift=True, mg=None):
+          omega=2.0 / 3.0, tol_rel=1e-10, tol_abs=0.0, max_cycles=50, shift=True, mg=None, transpose=False):
     """Outer residual-correction loop in FP64:
     r = f - A(x); s = ||r||_inf; e = V(r / s); x += s e; remove the mean of x
-    on every singular component; stop by the max-norm criterion above."""
-    mg = mg or MG(lev, op, c, nu1, nu2, smoother, omega)
+    on every singular component; stop by the max-norm criterion above.
+
+    transpose=True solves the adjoint system A_hom^T x = f (homogeneous: no
+    face data); on a singular component the right-hand side is first made
+    mean-free, which is the RHS shift with zero face data."""
+    if transpose and (fd is not None or cfv is not None):
+        raise ValueError("the adjoint system is homogeneous")
+    mg = mg or MG(lev, op, c, nu1, nu2, smoother, omega, transpose)
     sing = mg.sing[0]
     defects = []
     if shift and sing:
         f, defects = solvability_shift(lev, f, fd, sing)
     x = lev.zeros() if x0 is None else x0.copy()
     hist = []
-    r = f - lev.apply(x, op, c, fd, cfv)
+    r = f - _A(lev, x, op, c, transpose) if transpose else f - lev.apply(x, op, c, fd, cfv)
     r0 = norm_inf(lev, r)
     hist.append(r0)
     target = max(tol_rel * r0, tol_abs)
@@ -197,7 +216,7 @@ def solve(lev, f, op, c, fd=None, cfv=None, x0=None, nu1=2, nu2=2, smoother="jac
         e = mg.vcycle(r / s)
         x = x + s * e
         x = lev.comp_mean(x, sing)
-        r = f - lev.apply(x, op, c, fd, cfv)
+        r = f - _A(lev, x, op, c, transpose) if transpose else f - lev.apply(x, op, c, fd, cfv)
         hist.append(norm_inf(lev, r))
         cycles += 1
     return x, {"cycles": cycles, "history": hist, "converged": hist[-1] <= target,
@@ -214,3 +233,13 @@ def direct_solve(lev, f, op, c, fd=None, cfv=None):
     b = lev.apply(lev.zeros(), op, c, fd, cfv)
     bot = Bottom(lev, op, c)
     return bot.solve(f - b)
+
+
+def grad_c(lev, lam, u, fd=None, cfv=None):
+    """Derivative of a loss J(u) with respect to the Helmholtz coefficient c,
+    u the solution of (I - cL) u = f with data fd: differentiating
+    u - c L(u) = f gives (I - c L_hom) du/dc = L(u), so
+    dJ/dc = <lam, L(u)> with lam the adjoint solution for dJ/du and L(u) the
+    Laplacian of u with its data (sum over the level's cells)."""
+    Lu = lev.laplacian(u, lev.ghosts(u, fd, cfv))
+    return float((lam[lev.mask] * Lu[lev.mask]).sum())
