@@ -270,6 +270,52 @@ int amg_bottom(amg_hier* h, int level, int dtype, const void* f, void* e, void* 
 /* One homogeneous V(nu1,nu2) cycle from e = 0 on the level: e ~= A^-1 f. */
 int amg_vcycle(amg_hier* h, int level, int dtype, const amg_solve_opts* opts, const void* f, void* e, void* stream);
 
+/* ---- adjoint of the level system --------------------------------------------
+ * Not in the paper: the derivative of a loss J(x) of a level solution
+ * x = A^-1 (f - b(face data)) with respect to f is lam = A_h^-T dJ/dx, with
+ * A_h the homogeneous operator (ghost fill with zero data, then the stencil
+ * of eq. discreteOps c, as I - cL or L).  Its transpose applies the
+ * (symmetric) stencil to lam with the filled ghosts set to zero and sends
+ * each ghost's stencil weight back onto the four cells its fill read (eqs.
+ * velBCHomoDiri5th, Neumann5); exchange ghosts are symmetric and stay
+ * copies.  On a singular (pure-Neumann) component the source is made
+ * mean-free first and lam is returned mean-free.  The derivative with
+ * respect to the Helmholtz coefficient is dJ/dc = <lam, L x> (L with the
+ * solve's face data), so dJ/dnu = gamma k <lam, L x> for c = gamma nu k. */
+
+/* Solves A_h^T lam = g on level `level` (a level solved on its own, not
+ * AMG_CF_INTERP) by the same outer loop and V-cycle as amg_solve with the
+ * transposed operator at every depth (same diagonal, same restriction and
+ * prolongation, transposed bottom matrix).  lam: initial guess on entry,
+ * solution on return with its face ghost cells set to 0 (corner and row
+ * padding entries are not written; starting from a zeroed buffer lam is the
+ * gradient with respect to the packed f); g: packed FP64 buffer of the
+ * level, read on the level's cells only.  Errors as amg_solve. */
+int amg_solve_adjoint(amg_hier* h, int level, double* lam, const double* g, const amg_solve_opts* opts,
+                      amg_solve_stats* stats, void* stream);
+
+/* One V(nu1,nu2) cycle of the adjoint system from e = 0: e ~= A_h^-T f. */
+int amg_vcycle_adjoint(amg_hier* h, int level, int dtype, const amg_solve_opts* opts, const void* f, void* e,
+                       void* stream);
+
+/* y = A_h^T x (FP64) on depth 0 of `level`; x's ghosts are overwritten (zero
+ * on filled columns, copies on exchange columns); x != y. */
+int amg_apply_transpose(amg_hier* h, int level, double* x, double* y, void* stream);
+
+/* y = L x (FP64): the Laplacian of eq. (discreteOps c) with x's ghosts filled
+ * from face_data (NULL: zero data), whatever operator the hierarchy holds;
+ * x != y.  With x a Helmholtz solution, dJ/dc = <lam, y>. */
+int amg_apply_laplacian(amg_hier* h, int level, double* x, const double* face_data, double* y, void* stream);
+
+/* *out = sum over the level's cells of a_i b_i (FP64, fixed summation order:
+ * bitwise reproducible); synchronises the stream. */
+int amg_dot(amg_hier* h, int level, const double* a, const double* b, double* out, void* stream);
+
+/* Changes the Helmholtz coefficient c (> 0) of a finalized hierarchy: the
+ * bottom inverses are recomputed on the host and captured graphs dropped.
+ * Not on the hot path; AMG_EINVAL if the operator is not Helmholtz. */
+int amg_set_coefficient(amg_hier* h, double c);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* on != 0: every later amg_solve records a HIP event before and after each

@@ -94,6 +94,12 @@ def lib():
         L.amg_composite_residual.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
         L.amg_set_tuning.argtypes = [vp, i32, i32]
         L.amg_timing_read.argtypes = [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double), i32]
+        L.amg_solve_adjoint.argtypes = [vp, i32, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
+        L.amg_vcycle_adjoint.argtypes = [vp, i32, i32, C.POINTER(SolveOpts), vp, vp, vp]
+        L.amg_apply_transpose.argtypes = [vp, i32, vp, vp, vp]
+        L.amg_apply_laplacian.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.amg_dot.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_double), vp]
+        L.amg_set_coefficient.argtypes = [vp, dbl]
         _lib = L
     return _lib
 
@@ -168,6 +174,7 @@ class Hierarchy:
 
     def set_operator(self, kind, c=0.0):
         self._check(lib().amg_set_operator(self.h, kind, float(c)))
+        self.op_kind, self.c = kind, float(c)
 
     def set_tuning(self, key, value):
         self._check(lib().amg_set_tuning(self.h, key, int(value)))
@@ -381,3 +388,49 @@ class Hierarchy:
         self._need(e, level, 0, "e", (f.dtype,))
         o = opts or default_opts()
         self._check(lib().amg_vcycle(self.h, level, self._dt(f), C.byref(o), _ptr(f), _ptr(e), _stream()))
+
+    # ---- adjoint ----
+    def solve_adjoint(self, level, lam, g, opts=None):
+        """A_h^T lam = g (lam: initial guess in, solution out, face ghosts 0)."""
+        import torch
+        self._need(lam, level, 0, "lam", (torch.float64,))
+        self._need(g, level, 0, "g", (torch.float64,))
+        o = opts or default_opts()
+        st = SolveStats()
+        rc = lib().amg_solve_adjoint(self.h, level, _ptr(lam), _ptr(g), C.byref(o), C.byref(st), _stream())
+        if rc and rc != ENOTCONVERGED:
+            self._check(rc)
+        out = st.as_dict()
+        out["status"] = rc
+        return out
+
+    def vcycle_adjoint(self, level, f, e, opts=None):
+        self._need(f, level, 0, "f")
+        self._need(e, level, 0, "e", (f.dtype,))
+        o = opts or default_opts()
+        self._check(lib().amg_vcycle_adjoint(self.h, level, self._dt(f), C.byref(o), _ptr(f), _ptr(e), _stream()))
+
+    def apply_transpose(self, level, x, y):
+        import torch
+        self._need(x, level, 0, "x", (torch.float64,))
+        self._need(y, level, 0, "y", (torch.float64,))
+        self._check(lib().amg_apply_transpose(self.h, level, _ptr(x), _ptr(y), _stream()))
+
+    def apply_laplacian(self, level, x, y, face_data=None):
+        import torch
+        self._need(x, level, 0, "x", (torch.float64,))
+        self._need(y, level, 0, "y", (torch.float64,))
+        self._need_faces(face_data, level)
+        self._check(lib().amg_apply_laplacian(self.h, level, _ptr(x), _ptr(face_data), _ptr(y), _stream()))
+
+    def dot(self, level, a, b):
+        import torch
+        self._need(a, level, 0, "a", (torch.float64,))
+        self._need(b, level, 0, "b", (torch.float64,))
+        out = C.c_double()
+        self._check(lib().amg_dot(self.h, level, _ptr(a), _ptr(b), C.byref(out), _stream()))
+        return out.value
+
+    def set_coefficient(self, c):
+        self._check(lib().amg_set_coefficient(self.h, float(c)))
+        self.c = float(c)

@@ -1,0 +1,59 @@
+"""torch.autograd binding of a level solve.
+
+``level_solve(f, c, H, level, face_data, opts)`` returns x with
+A x = f - b(face_data) on one level of the hierarchy H (the Helmholtz
+system (I - cL) or the Poisson system L; pure-Neumann components solved for
+the mean-free x after the right-hand-side shift).  It is differentiable in f
+and, for the Helmholtz operator, in the coefficient c = gamma nu k, so a
+caller that builds c from nu obtains dJ/dnu = gamma k dJ/dc by autograd.
+
+Backward (the adjoint of the level system, not in the paper): lam solves
+A_h^T lam = dJ/dx by the library's adjoint multigrid solve (mean-free source
+and solution on singular components); dJ/df = lam and dJ/dc = <lam, L x>
+with L the Laplacian of x with the solve's face data.  Only the cells of the
+level carry gradient: the ghost entries of dJ/dx are ignored and those of
+dJ/df are zero.  No gradient flows to the face data.  Every step runs in the
+HIP library; this module only passes tensors.
+"""
+import torch
+
+from . import amg as A
+
+
+class LevelSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, f, c, H, level, face_data, opts):
+        if H.op_kind == A.HELMHOLTZ:
+            cv = float(c)
+            if cv != H.c:
+                H.set_coefficient(cv)
+        x = torch.zeros_like(f)
+        st = H.solve(level, x, f.contiguous(), face_data, opts)
+        if st["status"] != 0:
+            raise A.AmgError(st["status"], f"level solve did not converge: {st}")
+        ctx.H, ctx.level, ctx.face_data, ctx.opts = H, level, face_data, opts
+        ctx.c_is_tensor = torch.is_tensor(c)
+        ctx.c_meta = (c.dtype, c.device) if ctx.c_is_tensor else None
+        ctx.save_for_backward(x)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        H, level = ctx.H, ctx.level
+        lam = torch.zeros_like(x)
+        st = H.solve_adjoint(level, lam, gx.contiguous(), ctx.opts)
+        if st["status"] != 0:
+            raise A.AmgError(st["status"], f"adjoint solve did not converge: {st}")
+        gc = None
+        if ctx.c_is_tensor and ctx.needs_input_grad[1] and H.op_kind == A.HELMHOLTZ:
+            xx = x.clone()
+            y = torch.zeros_like(x)
+            H.apply_laplacian(level, xx, y, ctx.face_data)
+            gc = torch.tensor(H.dot(level, lam, y), dtype=ctx.c_meta[0], device=ctx.c_meta[1])
+        return lam, gc, None, None, None, None
+
+
+def level_solve(f, c, H, level=0, face_data=None, opts=None):
+    """x = A^-1 (f - b(face_data)), differentiable in f and (Helmholtz) c."""
+    return LevelSolve.apply(f, c, H, level, face_data, opts)

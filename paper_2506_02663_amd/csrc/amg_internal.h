@@ -62,6 +62,20 @@ struct ChunkD {            // up to 64 consecutive ghost columns of one face
   uint8_t pad[6];
 };
 
+// Up to 256 cells of the band of one box face that the transposed ghost
+// fill touches: the first four cells of every row ending at a face with
+// filled (Dirichlet / Neumann) ghost columns.  Cells are numbered within the
+// face's 4-deep slab; a cell within reach of several such faces belongs to
+// the first of them (faces ordered d * 2 + side).
+struct BandChunkD {
+  int32_t box;
+  int32_t face;   // d * 2 + side
+  int32_t start;  // first slab cell of the chunk
+  int32_t count;  // cells in the chunk (<= 256)
+  int32_t fmask;  // bit f: face f of the box has filled ghost columns
+  int32_t pad;
+};
+
 constexpr int kSeg = 2048;          // tiles per first-stage reduction segment
 constexpr int64_t kTargetTiles = 1024;  // tiles a depth should offer the 256 CUs
 
@@ -138,6 +152,7 @@ struct Depth {
   std::vector<int32_t> seg_ptr;       // reduction segments: ranges of at most kSeg tiles within one component
   std::vector<int32_t> comp_seg_ptr;  // segments of each component (range into seg_ptr)
   std::vector<int32_t> chunk_comp_ptr, chunk_comp_idx; // CSR: chunks of each component
+  std::vector<BandChunkD> band;      // cells the transposed fill touches
   std::vector<int32_t> bottom_boxes; // boxes solved exactly at this depth
   std::vector<BottomGroupD> groups;
   int64_t nstored = 0;
@@ -150,6 +165,7 @@ struct Depth {
   TileD* d_stiles = nullptr;
   int32_t *d_seg = nullptr, *d_cseg = nullptr, *d_cc_ptr = nullptr, *d_cc_idx = nullptr;
   BottomGroupD* d_groups = nullptr;
+  BandChunkD* d_band = nullptr;
   // work buffers (FP64 and FP32): correction, right-hand side, second buffer
   double *e64 = nullptr, *f64 = nullptr, *t64 = nullptr;
   float *e32 = nullptr, *f32 = nullptr, *t32 = nullptr;
@@ -172,7 +188,8 @@ struct GraphCache {  // the captured outer cycle of one level
 };
 
 struct Level {
-  GraphCache graph;
+  GraphCache graph;                 // captured outer cycle of the level solve
+  GraphCache graphT;                // the same for the adjoint solve
   Composite cmp;                    // against level l-1 (l >= 1)
   std::vector<uint8_t> face_valid;  // face-data entries not under level l+1
   uint8_t* d_face_valid = nullptr;
@@ -191,6 +208,7 @@ struct Level {
   // device
   double* d_mat = nullptr;
   int64_t* d_idx = nullptr;
+  size_t nmat = 0;           // doubles in d_mat
   double* r64 = nullptr;     // outer residual
   double* fsh = nullptr;     // right-hand side after the solvability shift
   double* partial = nullptr; // tile partials (max over all depths)

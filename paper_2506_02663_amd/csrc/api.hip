@@ -19,7 +19,7 @@ namespace {
 
 // device scalar slots of a level: residual norm, the constant 1, per-level
 // norms of a composite cycle (level 0's array), per-level face-data sums
-enum { S_NORM = 0, S_ONE = 1, S_LEV = 2, S_FD = 20, S_FSUM = 38, S_DELTA = 39, S_COUNT = 40 };
+enum { S_NORM = 0, S_ONE = 1, S_LEV = 2, S_FD = 20, S_FSUM = 38, S_DELTA = 39, S_DOT = 40, S_COUNT = 41 };
 
 #define HIPCHK(expr)                                                      \
   do {                                                                    \
@@ -85,13 +85,25 @@ struct Bufs<float> {
   static float* t(Depth& D) { return D.t32; }
 };
 
-// Struct holding one call's view of a level
+// Struct holding one call's view of a level; tr: the adjoint system (the
+// transposed operator at every depth)
 struct Run {
   amg_hier* H;
   Level* L;
   int dim;
   hipStream_t st;
+  bool tr = false;
 };
+
+// ghosts before an operator application: the fill of the homogeneous
+// operator, or of its transpose
+template <typename T>
+void fill_op(const Run& R, const Depth& D, T* u) {
+  if (R.tr)
+    launch_fill_tr<T>(D, u, R.st);
+  else
+    launch_fill<T>(D, u, nullptr, R.st);
+}
 
 // event timing around launches of one kernel kind (finest depth only)
 struct Timed {
@@ -180,12 +192,13 @@ void smooth(const Run& R, int k, int smoother, int nsweeps, double omega, bool f
       }
       {
         Timed tm(R, AMG_T_FILL, k);
-        launch_fill<T>(D, cur, nullptr, R.st);
+        fill_op<T>(R, D, cur);
       }
       {
         Timed tm(R, AMG_T_SWEEP, k);
         launch_jacobi<T>(R.dim, D, cur, f, oth, alpha, beta, (T)omega, false, R.st);
       }
+      if (R.tr) launch_band<T>(R.dim, D, 1, cur, oth, alpha, beta, -(T)omega * beta, 0, R.st);
       std::swap(cur, oth);
     }
   } else {
@@ -197,12 +210,13 @@ void smooth(const Run& R, int k, int smoother, int nsweeps, double omega, bool f
         }
         {
           Timed tm(R, AMG_T_FILL, k);
-          launch_fill<T>(D, cur, nullptr, R.st);
+          fill_op<T>(R, D, cur);
         }
         {
           Timed tm(R, AMG_T_SWEEP, k);
           launch_rb<T>(R.dim, D, cur, f, oth, alpha, beta, col, false, R.st);
         }
+        if (R.tr) launch_band<T>(R.dim, D, 2, cur, oth, alpha, beta, -beta, col, R.st);
         std::swap(cur, oth);
       }
   }
@@ -225,8 +239,8 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0) {
     Depth& D = L.depths[k];
     // boxes that end here: exact solve, written to both buffers of the depth
     if (!D.groups.empty()) {
-      launch_bottom<T>(D, L.d_mat, L.d_idx, f[k], cur[k], R.st);
-      launch_bottom<T>(D, L.d_mat, L.d_idx, f[k], oth[k], R.st);
+      launch_bottom<T>(D, L.d_mat, L.d_idx, f[k], cur[k], R.tr, R.st);
+      launch_bottom<T>(D, L.d_mat, L.d_idx, f[k], oth[k], R.tr, R.st);
     }
     if (k + 1 >= K || D.stiles.empty()) break;
     smooth<T>(R, k, o.smoother, o.nu1, o.omega, true, cur[k], oth[k], f[k]);
@@ -234,9 +248,14 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0) {
     coefs<T>(R.H, D, alpha, beta);
     {
       Timed tm(R, AMG_T_FILL, k);
-      launch_fill<T>(D, cur[k], nullptr, R.st);
+      fill_op<T>(R, D, cur[k]);
     }
-    {
+    if (R.tr) {
+      // residual of the transposed operator into the free buffer, then restrict
+      launch_residual<T>(R.dim, D, false, cur[k], f[k], oth[k], alpha, beta, nullptr, R.st);
+      launch_band<T>(R.dim, D, 0, cur[k], oth[k], alpha, beta, -beta, 0, R.st);
+      launch_restrict<T>(R.dim, D, L.depths[k + 1], oth[k], Bufs<T>::f(L.depths[k + 1]), R.st);
+    } else {
       Timed tm(R, AMG_T_RESTRICT, k);
       launch_resid_restrict<T>(R.dim, D, L.depths[k + 1], cur[k], f[k], Bufs<T>::f(L.depths[k + 1]), alpha, beta,
                                R.st);
@@ -274,7 +293,7 @@ hipStream_t stream_of(amg_hier* H, void* s) { return s ? (hipStream_t)s : H->own
 void free_level(amg::Level& L) {
   for (auto& D : L.depths) {
     for (void* p : {(void*)D.d_box, (void*)D.d_codes, (void*)D.d_chunks, (void*)D.d_tiles, (void*)D.d_stiles,
-                    (void*)D.d_seg, (void*)D.d_cseg, (void*)D.d_cc_ptr, (void*)D.d_cc_idx, (void*)D.d_groups,
+                    (void*)D.d_seg, (void*)D.d_cseg, (void*)D.d_cc_ptr, (void*)D.d_cc_idx, (void*)D.d_groups, (void*)D.d_band,
                     (void*)D.e64, (void*)D.f64, (void*)D.t64, (void*)D.e32, (void*)D.f32, (void*)D.t32})
       if (p) (void)hipFree(p);
   }
@@ -529,6 +548,7 @@ int amg_finalize(amg_hier* H) {
     rc = build_bottom(H, l, err, mats, idx);
     if (rc != AMG_OK) return fail(H, rc, err);
     TRY(upload(H, &L.d_mat, mats));
+    L.nmat = mats.size();
     TRY(upload(H, &L.d_idx, idx));
     size_t maxpart = 1, maxseg = 1;
     for (auto& D : L.depths) {
@@ -542,6 +562,7 @@ int amg_finalize(amg_hier* H) {
       TRY(upload(H, &D.d_cc_ptr, D.chunk_comp_ptr));
       TRY(upload(H, &D.d_cc_idx, D.chunk_comp_idx));
       TRY(upload(H, &D.d_groups, D.groups));
+      TRY(upload(H, &D.d_band, D.band));
       TRY(zalloc(H, &D.e64, D.nstored));
       TRY(zalloc(H, &D.f64, D.nstored));
       TRY(zalloc(H, &D.t64, D.nstored));
@@ -754,9 +775,9 @@ int amg_bottom(amg_hier* H, int level, int dtype, const void* f, void* e, void* 
   Depth& D = L.depths.back();
   hipStream_t st = stream_of(H, stream);
   if (dtype == AMG_F64)
-    launch_bottom<double>(D, L.d_mat, L.d_idx, (const double*)f, (double*)e, st);
+    launch_bottom<double>(D, L.d_mat, L.d_idx, (const double*)f, (double*)e, false, st);
   else
-    launch_bottom<float>(D, L.d_mat, L.d_idx, (const float*)f, (float*)e, st);
+    launch_bottom<float>(D, L.d_mat, L.d_idx, (const float*)f, (float*)e, false, st);
   HIPCHK(hipGetLastError());
   return AMG_OK;
 }
@@ -915,27 +936,14 @@ int amg_composite_residual(amg_hier* H, int lev_hi, double* const* x, const doub
   return AMG_OK;
 }
 
-int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const double* const* f,
-              const double* const* face_data, const amg_solve_opts* opts, amg_solve_stats* stats, void* stream) {
-  if (!check_level(H, lev_lo)) return AMG_EINVAL;
-  if (!x || !f) return fail(H, AMG_EINVAL, "bad arguments");
-  if (lev_hi != lev_lo) return composite_solve(H, lev_lo, lev_hi, x, f, face_data, opts, stats, stream);
-  amg_solve_opts o;
-  amg_default_opts(&o);
-  if (opts) o = *opts;
-  if (o.nu1 < 0 || o.nu2 < 0 || o.max_cycles < 0 || o.max_cycles > 100000 ||
-      (o.smoother != AMG_SMOOTH_JACOBI && o.smoother != AMG_SMOOTH_RB) ||
-      (o.precision != AMG_FP64 && o.precision != AMG_MIXED) || !(o.omega > 0))
-    return fail(H, AMG_EINVAL, "bad solve options");
-  const int l = lev_lo;
+// the outer loop of a level solve (tr: of the adjoint system, homogeneous)
+static int level_solve(amg_hier* H, int l, double* X, const double* F, const double* FD, const amg_solve_opts& o,
+                       amg_solve_stats* stats, void* stream, bool tr) {
   Level& L = H->levels[l];
   if (l > 0 && L.cf_mode == AMG_CF_INTERP)
     return fail(H, AMG_EUNSUPPORTED, "a level with interpolated coarse-fine ghosts is solved in a composite solve");
-  double* X = x[l];
-  const double* F = f[l];
-  const double* FD = face_data ? face_data[l] : nullptr;
   if (!X || !F) return fail(H, AMG_EINVAL, "null x or f");
-  Run R{H, &L, H->dim, stream_of(H, stream)};
+  Run R{H, &L, H->dim, stream_of(H, stream), tr};
   Depth& D0 = L.depths[0];
   const int dim = H->dim;
   const double hD = std::pow(D0.h, dim), hD1 = std::pow(D0.h, dim - 1);
@@ -973,8 +981,13 @@ int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const doubl
   double alpha, beta;
   coefs<double>(H, D0, alpha, beta);
   auto residual_norm = [&]() {
-    launch_fill<double>(D0, X, FD, R.st);
-    {
+    if (tr) {
+      launch_fill_tr<double>(D0, X, R.st);
+      launch_residual<double>(dim, D0, true, X, frhs, Rb, alpha, beta, nullptr, R.st);
+      launch_band<double>(dim, D0, 0, X, Rb, alpha, beta, -beta, 0, R.st);
+      launch_tile_absmax<double>(dim, D0, Rb, L.partial, R.st);
+    } else {
+      launch_fill<double>(D0, X, FD, R.st);
       Timed tm(R, AMG_T_RESIDUAL, 0);
       launch_residual<double>(dim, D0, true, X, frhs, Rb, alpha, beta, L.partial, R.st);
     }
@@ -1013,7 +1026,7 @@ int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const doubl
     residual_norm();
   };
   // the cycle is captured once into a HIP graph and replayed
-  GraphCache& G = L.graph;
+  GraphCache& G = tr ? L.graphT : L.graph;
   // event timing needs per-launch events, which a replayed graph does not
   // provide: with timing on, the cycle runs as direct launches
   bool use_graph = o.use_graph != 0 && !G.broken && !H->timer.on;
@@ -1072,7 +1085,119 @@ int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const doubl
     stats->used_graph = use_graph && cycles > 0;
   }
   if (H->timer.on) collect_timing(H->timer);
+  if (tr) {  // the adjoint solution as a gradient: zero outside the cells
+    launch_fill_zero<double>(D0, X, R.st);
+    HIPCHK(hipGetLastError());
+  }
   if (rn > target) return fail(H, AMG_ENOTCONVERGED, "max_cycles reached");
+  return AMG_OK;
+}
+
+int amg_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const double* const* f,
+              const double* const* face_data, const amg_solve_opts* opts, amg_solve_stats* stats, void* stream) {
+  if (!check_level(H, lev_lo)) return AMG_EINVAL;
+  if (!x || !f) return fail(H, AMG_EINVAL, "bad arguments");
+  if (lev_hi != lev_lo) return composite_solve(H, lev_lo, lev_hi, x, f, face_data, opts, stats, stream);
+  amg_solve_opts o;
+  amg_default_opts(&o);
+  if (opts) o = *opts;
+  TRY(check_opts(H, o));
+  return level_solve(H, lev_lo, x[lev_lo], f[lev_lo], face_data ? face_data[lev_lo] : nullptr, o, stats, stream,
+                     false);
+}
+
+int amg_solve_adjoint(amg_hier* H, int level, double* lam, const double* g, const amg_solve_opts* opts,
+                      amg_solve_stats* stats, void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!lam || !g) return fail(H, AMG_EINVAL, "bad arguments");
+  amg_solve_opts o;
+  amg_default_opts(&o);
+  if (opts) o = *opts;
+  TRY(check_opts(H, o));
+  return level_solve(H, level, lam, g, nullptr, o, stats, stream, true);
+}
+
+int amg_vcycle_adjoint(amg_hier* H, int level, int dtype, const amg_solve_opts* opts, const void* f, void* e,
+                       void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!f || !e) return fail(H, AMG_EINVAL, "bad arguments");
+  amg_solve_opts o;
+  amg_default_opts(&o);
+  if (opts) o = *opts;
+  TRY(check_opts(H, o));
+  Level& L = H->levels[level];
+  Run R{H, &L, H->dim, stream_of(H, stream), true};
+  Depth& D0 = L.depths[0];
+  if (dtype == AMG_F64) {
+    double* res = vcycle<double>(R, o, (const double*)f, (double*)e, D0.t64);
+    if (res != e) HIPCHK(hipMemcpyAsync(e, res, D0.nstored * 8, hipMemcpyDeviceToDevice, R.st));
+  } else {
+    float* res = vcycle<float>(R, o, (const float*)f, (float*)e, D0.t32);
+    if (res != e) HIPCHK(hipMemcpyAsync(e, res, D0.nstored * 4, hipMemcpyDeviceToDevice, R.st));
+  }
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_apply_transpose(amg_hier* H, int level, double* x, double* y, void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!x || !y || x == y) return fail(H, AMG_EINVAL, "bad arguments");
+  Level& L = H->levels[level];
+  Depth& D = L.depths[0];
+  hipStream_t st = stream_of(H, stream);
+  double alpha, beta;
+  coefs<double>(H, D, alpha, beta);
+  launch_fill_tr<double>(D, x, st);
+  launch_residual<double>(H->dim, D, true, x, nullptr, y, alpha, beta, nullptr, st);
+  launch_band<double>(H->dim, D, 0, x, y, alpha, beta, beta, 0, st);
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_apply_laplacian(amg_hier* H, int level, double* x, const double* face_data, double* y, void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!x || !y || x == y) return fail(H, AMG_EINVAL, "bad arguments");
+  Level& L = H->levels[level];
+  Depth& D = L.depths[0];
+  hipStream_t st = stream_of(H, stream);
+  launch_fill<double>(D, x, face_data, st);
+  launch_residual<double>(H->dim, D, true, x, nullptr, y, 0.0, 1.0 / (12.0 * D.h * D.h), nullptr, st);
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_dot(amg_hier* H, int level, const double* a, const double* b, double* out, void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!a || !b || !out) return fail(H, AMG_EINVAL, "bad arguments");
+  Level& L = H->levels[level];
+  Depth& D = L.depths[0];
+  hipStream_t st = stream_of(H, stream);
+  launch_tile_dot(H->dim, D, a, b, L.partial, st);
+  launch_seg_reduce(L.partial, nullptr, 1, (int)D.tiles.size(), L.scal + S_DOT, false, st);
+  HIPCHK(hipMemcpyAsync(L.h_scal + S_DOT, L.scal + S_DOT, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *out = L.h_scal[S_DOT];
+  return AMG_OK;
+}
+
+int amg_set_coefficient(amg_hier* H, double c) {
+  if (!H) return AMG_EINVAL;
+  if (H->op != AMG_HELMHOLTZ) return fail(H, AMG_EINVAL, "the coefficient belongs to the Helmholtz operator");
+  if (!(c > 0)) return fail(H, AMG_EINVAL, "Helmholtz needs c > 0");
+  H->c = c;
+  if (!H->finalized) return AMG_OK;
+  for (int l = 0; l < H->nlevels; ++l) {
+    Level& L = H->levels[l];
+    std::string err;
+    std::vector<double> mats;
+    std::vector<int64_t> idx;
+    const int rc = build_bottom(H, l, err, mats, idx);
+    if (rc != AMG_OK) return fail(H, rc, err);
+    if (mats.size() != L.nmat) return fail(H, AMG_EDEVICE, "bottom matrices changed size");
+    if (!mats.empty()) HIPCHK(hipMemcpy(L.d_mat, mats.data(), mats.size() * sizeof(double), hipMemcpyHostToDevice));
+    L.graph.release();
+    L.graphT.release();
+  }
   return AMG_OK;
 }
 

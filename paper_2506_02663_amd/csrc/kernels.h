@@ -8,6 +8,14 @@ namespace amg {
 template <typename T>
 void launch_fill(const Depth& D, T* u, const double* fd, hipStream_t st);
 template <typename T>
+void launch_fill_tr(const Depth& D, T* u, hipStream_t st);
+template <typename T>
+void launch_fill_zero(const Depth& D, T* u, hipStream_t st);
+template <typename T>
+void launch_band(int dim, const Depth& D, int mode, const T* u, T* out, T alpha, T beta, T scale, int col,
+                 hipStream_t st);
+void launch_tile_dot(int dim, const Depth& D, const double* a, const double* b, double* part, hipStream_t st);
+template <typename T>
 void launch_residual(int dim, const Depth& D, bool all, const T* u, const T* f, T* r, T alpha, T beta, double* part,
                      hipStream_t st);
 template <typename T>
@@ -24,7 +32,7 @@ void launch_restrict(int dim, const Depth& F, const Depth& C, const T* r, T* fc,
 template <typename T>
 void launch_prolong(int dim, const Depth& F, const Depth& C, const T* ec, T* u, hipStream_t st);
 template <typename T>
-void launch_bottom(const Depth& D, const double* mats, const int64_t* idx, const T* f, T* e, hipStream_t st);
+void launch_bottom(const Depth& D, const double* mats, const int64_t* idx, const T* f, T* e, bool tr, hipStream_t st);
 template <typename T>
 void launch_tile_sum(int dim, const Depth& D, const T* a, double* part, hipStream_t st);
 template <typename T>

@@ -641,8 +641,11 @@ __global__ void __launch_bounds__(256) k_prolong(const TileD* __restrict__ tiles
 }
 
 // ---------------------------------------------------------------------------
-// ghost fill: one wavefront per chunk of up to 64 face columns
-template <typename T>
+// ghost fill: one wavefront per chunk of up to 64 face columns.  MODE 0: the
+// fill; 1: the ghosts of the transposed operator (filled columns 0,
+// exchange copied; the fill's contribution is added by k_band instead);
+// 2: every ghost 0
+template <typename T, int MODE>
 __global__ void __launch_bounds__(256) k_fill(const ChunkD* __restrict__ chunks, int nchunks, T* __restrict__ u,
                                               const double* __restrict__ fd, double h) {
   const int ci = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -654,7 +657,7 @@ __global__ void __launch_bounds__(256) k_fill(const ChunkD* __restrict__ chunks,
   const int64_t n = ch.nstride;
   const int64_t e = g1 - n;
   T v1 = T(0), v2 = T(0);
-  if (ch.kind1 == G_FILL_D || ch.kind1 == G_FILL_N || ch.kind2 == G_FILL_D || ch.kind2 == G_FILL_N) {
+  if (MODE == 0 && (ch.kind1 == G_FILL_D || ch.kind1 == G_FILL_N || ch.kind2 == G_FILL_D || ch.kind2 == G_FILL_N)) {
     const T u0 = u[e], u1 = u[e - n], u2 = u[e - 2 * n], u3 = u[e - 3 * n];
     const T g = (fd && ch.fd >= 0) ? T(fd[ch.fd + lane]) : T(0);
     const int k = (ch.kind1 == G_FILL_D || ch.kind1 == G_FILL_N) ? ch.kind1 : ch.kind2;
@@ -669,14 +672,15 @@ __global__ void __launch_bounds__(256) k_fill(const ChunkD* __restrict__ chunks,
     if (ch.kind1 == G_FILL_D || ch.kind1 == G_FILL_N) v1 = f1;
     if (ch.kind2 == G_FILL_D || ch.kind2 == G_FILL_N) v2 = f2;
   }
-  if (ch.kind1 == G_EXCH) v1 = u[ch.src1 + (int64_t)lane * ch.sstride1];
-  if (ch.kind2 == G_EXCH) v2 = u[ch.src2 + (int64_t)lane * ch.sstride2];
+  if (MODE != 2 && ch.kind1 == G_EXCH) v1 = u[ch.src1 + (int64_t)lane * ch.sstride1];
+  if (MODE != 2 && ch.kind2 == G_EXCH) v2 = u[ch.src2 + (int64_t)lane * ch.sstride2];
   u[g1] = v1;
   u[g1 + n] = v2;
 }
 
-// exact bottom solve: e = M f for every instance of every group
-template <typename T>
+// exact bottom solve: e = M f (TR: e = M^T f, the adjoint system) for every
+// instance of every group
+template <typename T, bool TR>
 __global__ void __launch_bounds__(256) k_bottom(const BottomGroupD* __restrict__ groups,
                                                 const double* __restrict__ mats, const int64_t* __restrict__ idx,
                                                 const T* __restrict__ f, T* __restrict__ e) {
@@ -701,7 +705,7 @@ __global__ void __launch_bounds__(256) k_bottom(const BottomGroupD* __restrict__
       __syncthreads();
       if (r < G.n) {
         for (int k = 0; k < kc; ++k) {
-          const double m = M[(int64_t)(k0 + k) * G.n + r];
+          const double m = TR ? M[(int64_t)r * G.n + k0 + k] : M[(int64_t)(k0 + k) * G.n + r];
 #pragma unroll
           for (int i = 0; i < NI; ++i) acc[i] += m * xs[i][k];
         }
@@ -710,6 +714,112 @@ __global__ void __launch_bounds__(256) k_bottom(const BottomGroupD* __restrict__
     if (r < G.n)
       for (int i = 0; i < ni; ++i) e[idx[G.idx + (int64_t)(i0 + i) * G.n + r]] = (T)acc[i];
   }
+}
+
+// ---------------------------------------------------------------------------
+// transposed operator (adjoint system): contribution of the ghost fill.
+//
+// The homogeneous operator reads the two ghosts of a filled column, which the
+// fill computes from the first four cells of that row; the end cell puts
+// weight 16 on ghost 1 and -1 on ghost 2, the next cell -1 on ghost 1.  The
+// transpose therefore adds to the cell at distance p (0..3) from the face
+//   w1[p] (16 l0 - l1) + w2[p] (-l0)   (units of 1 / 12 h^2),
+// l0, l1 the first two cells of the row and w1, w2 the coefficients of the
+// cell in the first and second ghost of eqs. (velBCHomoDiri5th) and
+// (Neumann5).  The stencil part of the transpose is the stencil itself (it is
+// symmetric) on the array whose filled ghosts are 0 (k_fill<T, true>).
+// MODE 0: out += scale * delta (residual or operator); 1: Jacobi, out +=
+// scale * delta / diag; 2: red-black, the same on cells of colour `col`.
+__constant__ double kFillW[2][2][4] = {
+    {{-77.0 / 12, 43.0 / 12, -17.0 / 12, 3.0 / 12}, {-505.0 / 12, 335.0 / 12, -145.0 / 12, 27.0 / 12}},
+    {{0.5, 0.9, -0.5, 0.1}, {-7.5, 14.5, -7.5, 1.5}}};
+
+template <typename T, int DIM, int MODE>
+__global__ void __launch_bounds__(256) k_band(const BandChunkD* __restrict__ chunks, int nchunks,
+                                              const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
+                                              const T* __restrict__ u, T* __restrict__ out, T alpha, T beta, T scale,
+                                              int col) {
+  const int ci = blockIdx.x;
+  if (ci >= nchunks) return;
+  const BandChunkD ch = chunks[ci];
+  if ((int)threadIdx.x >= ch.count) return;
+  const BoxD b = boxes[ch.box];
+  const int k = ch.start + (int)threadIdx.x;
+  const int d = ch.face >> 1, s = ch.face & 1;
+  int x[3] = {0, 0, 0};
+  if (d == 0) {  // distance fastest: rows along x are contiguous
+    const int p = k & 3, r = k >> 2;
+    x[0] = s ? b.n[0] - 1 - p : p;
+    x[1] = r % b.n[1];
+    x[2] = r / b.n[1];
+  } else if (d == 1) {
+    const int r = k / b.n[0], p = r & 3;
+    x[0] = k % b.n[0];
+    x[1] = s ? b.n[1] - 1 - p : p;
+    x[2] = r >> 2;
+  } else {
+    const int r = k / b.n[0], p = r / b.n[1];
+    x[0] = k % b.n[0];
+    x[1] = r % b.n[1];
+    x[2] = s ? b.n[2] - 1 - p : p;
+  }
+  for (int f = 0; f < ch.face; ++f) {  // owned by an earlier filled face
+    if (!((ch.fmask >> f) & 1)) continue;
+    const int e = f >> 1;
+    if (((f & 1) ? b.n[e] - 1 - x[e] : x[e]) < 4) return;
+  }
+  T delta = T(0);
+#pragma unroll
+  for (int f = 0; f < 2 * DIM; ++f) {
+    if (!((ch.fmask >> f) & 1)) continue;
+    const int e = f >> 1, sd = f & 1;
+    const int dist = sd ? b.n[e] - 1 - x[e] : x[e];
+    if (dist >= 4) continue;
+    int colx;
+    if (DIM == 2)
+      colx = e == 0 ? x[1] : x[0];
+    else
+      colx = e == 0 ? x[1] + b.n[1] * x[2] : (e == 1 ? x[0] + b.n[0] * x[2] : x[0] + b.n[0] * x[1]);
+    const uint8_t cd = codes[b.code_off[e][sd] + colx];
+    const int kind = cd & 3;
+    if (!kind) continue;
+    int y[3] = {x[0], x[1], x[2]};
+    y[e] = sd ? b.n[e] - 1 : 0;
+    const int64_t e0 = cell_index<DIM>(b, y[0], y[1], y[2]);
+    const int64_t in = (e == 0 ? 1 : (int64_t)b.s[e]) * (sd ? -1 : 1);
+    const T l0 = u[e0], l1 = u[e0 + in];
+    delta += T(kFillW[kind - 1][0][dist]) * (T(16) * l0 - l1);
+    if (cd & 4) delta -= T(kFillW[kind - 1][1][dist]) * l0;
+  }
+  const int64_t c = cell_index<DIM>(b, x[0], x[1], x[2]);
+  if (MODE == 0) {
+    out[c] += scale * delta;
+    return;
+  }
+  if (MODE == 2 && ((b.lo[0] + x[0] + b.lo[1] + x[1] + (DIM == 3 ? b.lo[2] + x[2] : 0)) & 1) != col) return;
+  out[c] += scale * delta / (alpha + beta * (T(-30 * DIM) + fold_at<T, DIM>(b, codes, x[0], x[1], x[2])));
+}
+
+// per-tile sum of a * b over the interior (dot products)
+template <int DIM>
+__global__ void __launch_bounds__(256) k_tile_dot(const TileD* __restrict__ tiles, int ntiles,
+                                                  const BoxD* __restrict__ boxes, const double* __restrict__ a,
+                                                  const double* __restrict__ bb, double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int ti = tile_of_block(ntiles);
+  if (ti < 0) return;
+  const TileD t = tiles[ti];
+  const BoxD b = boxes[t.box];
+  const Column C = column_of<DIM>(t, b);
+  double v = 0.0;
+  if (C.ok)
+    for (int p = C.p0; p < C.p1; ++p) {
+      const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+      v += a[c] * bb[c];
+      if (C.ok1) v += a[c + 1] * bb[c + 1];
+    }
+  v = block_sum<double>(v, sh);
+  if (threadIdx.x == 0) part[ti] = v;
 }
 
 // segmented reduction in a fixed order: out[s] = sum (or max) of in over
@@ -929,7 +1039,55 @@ template <typename T>
 void launch_fill(const Depth& D, T* u, const double* fd, hipStream_t st) {
   const int n = (int)D.chunks.size();
   if (!n) return;
-  hipLaunchKernelGGL(k_fill<T>, dim3((n + 3) / 4), dim3(256), 0, st, D.d_chunks, n, u, fd, D.h);
+  hipLaunchKernelGGL((k_fill<T, 0>), dim3((n + 3) / 4), dim3(256), 0, st, D.d_chunks, n, u, fd, D.h);
+}
+
+template <typename T>
+void launch_fill_tr(const Depth& D, T* u, hipStream_t st) {
+  const int n = (int)D.chunks.size();
+  if (!n) return;
+  hipLaunchKernelGGL((k_fill<T, 1>), dim3((n + 3) / 4), dim3(256), 0, st, D.d_chunks, n, u, nullptr, D.h);
+}
+
+template <typename T>
+void launch_fill_zero(const Depth& D, T* u, hipStream_t st) {
+  const int n = (int)D.chunks.size();
+  if (!n) return;
+  hipLaunchKernelGGL((k_fill<T, 2>), dim3((n + 3) / 4), dim3(256), 0, st, D.d_chunks, n, u, nullptr, D.h);
+}
+
+template <typename T>
+void launch_band(int dim, const Depth& D, int mode, const T* u, T* out, T alpha, T beta, T scale, int col,
+                 hipStream_t st) {
+  const int n = (int)D.band.size();
+  if (!n) return;
+#define BAND_(DIM_, MODE_)                                                                                        \
+  hipLaunchKernelGGL((k_band<T, DIM_, MODE_>), dim3(n), dim3(256), 0, st, D.d_band, n, D.d_box, D.d_codes, u, out, \
+                     alpha, beta, scale, col)
+  if (dim == 2) {
+    if (mode == 0) {
+      BAND_(2, 0);
+    } else if (mode == 1) {
+      BAND_(2, 1);
+    } else {
+      BAND_(2, 2);
+    }
+  } else {
+    if (mode == 0) {
+      BAND_(3, 0);
+    } else if (mode == 1) {
+      BAND_(3, 1);
+    } else {
+      BAND_(3, 2);
+    }
+  }
+#undef BAND_
+}
+
+void launch_tile_dot(int dim, const Depth& D, const double* a, const double* b, double* part, hipStream_t st) {
+  const size_t n = D.tiles.size();
+  if (!n) return;
+  DISPATCH_DIM(dim, k_tile_dot, D.d_tiles, (int)n, D.d_box, a, b, part);
 }
 
 // FP32 sweeps run one cell per thread (k_march1), FP64 sweeps two (k_march):
@@ -1032,12 +1190,16 @@ void launch_prolong(int dim, const Depth& F, const Depth& C, const T* ec, T* u, 
 }
 
 template <typename T>
-void launch_bottom(const Depth& D, const double* mats, const int64_t* idx, const T* f, T* e, hipStream_t st) {
+void launch_bottom(const Depth& D, const double* mats, const int64_t* idx, const T* f, T* e, bool tr,
+                   hipStream_t st) {
   if (D.groups.empty()) return;
   int maxn = 0;
   for (auto& g : D.groups) maxn = std::max(maxn, g.n);
-  hipLaunchKernelGGL(k_bottom<T>, dim3((maxn + 255) / 256, (unsigned)D.groups.size()), dim3(256), 0, st, D.d_groups,
-                     mats, idx, f, e);
+  const dim3 grid((maxn + 255) / 256, (unsigned)D.groups.size());
+  if (tr)
+    hipLaunchKernelGGL((k_bottom<T, true>), grid, dim3(256), 0, st, D.d_groups, mats, idx, f, e);
+  else
+    hipLaunchKernelGGL((k_bottom<T, false>), grid, dim3(256), 0, st, D.d_groups, mats, idx, f, e);
 }
 
 template <typename T>
@@ -1193,6 +1355,9 @@ void launch_zero(T* a, int64_t n, hipStream_t st) {
 
 #define INST(T)                                                                                                   \
   template void launch_fill<T>(const Depth&, T*, const double*, hipStream_t);                                     \
+  template void launch_fill_tr<T>(const Depth&, T*, hipStream_t);                                                 \
+  template void launch_fill_zero<T>(const Depth&, T*, hipStream_t);                                               \
+  template void launch_band<T>(int, const Depth&, int, const T*, T*, T, T, T, int, hipStream_t);                  \
   template void launch_residual<T>(int, const Depth&, bool, const T*, const T*, T*, T, T, double*, hipStream_t);  \
   template void launch_jacobi<T>(int, const Depth&, const T*, const T*, T*, T, T, T, bool, hipStream_t);          \
   template void launch_rb<T>(int, const Depth&, const T*, const T*, T*, T, T, int, bool, hipStream_t);            \
@@ -1200,7 +1365,7 @@ void launch_zero(T* a, int64_t n, hipStream_t st) {
                                          hipStream_t);                                                            \
   template void launch_restrict<T>(int, const Depth&, const Depth&, const T*, T*, hipStream_t);                   \
   template void launch_prolong<T>(int, const Depth&, const Depth&, const T*, T*, hipStream_t);                    \
-  template void launch_bottom<T>(const Depth&, const double*, const int64_t*, const T*, T*, hipStream_t);         \
+  template void launch_bottom<T>(const Depth&, const double*, const int64_t*, const T*, T*, bool, hipStream_t);   \
   template void launch_tile_sum<T>(int, const Depth&, const T*, double*, hipStream_t);                            \
   template void launch_tile_absmax<T>(int, const Depth&, const T*, double*, hipStream_t);                         \
   template void launch_comp_shift<T>(int, const Depth&, T*, const double*, hipStream_t);                          \

@@ -330,6 +330,30 @@ int plan_level(amg_hier* H, int l, std::string& err) {
         }
     if (D.codes.empty()) D.codes.push_back(0);
 
+    // ---- band of the transposed fill: 4-deep slabs of faces with filled columns ----
+    D.band.clear();
+    for (int i = 0; i < nbk; ++i) {
+      const Box& B = D.boxes[i];
+      int fmask = 0;
+      for (int d = 0; d < dim; ++d)
+        for (int s = 0; s < 2; ++s) {
+          const FaceCols& fc = D.faces[i * 6 + d * 2 + s];
+          for (size_t c = 0; c < fc.k1.size(); ++c)
+            if (column_code(fc.k1[c], fc.k2[c]) & 3) {
+              fmask |= 1 << (d * 2 + s);
+              break;
+            }
+        }
+      for (int f = 0; f < 2 * dim; ++f) {
+        if (!((fmask >> f) & 1)) continue;
+        int64_t cells = 4;
+        for (int e = 0; e < dim; ++e)
+          if (e != f / 2) cells *= B.n(e);
+        for (int64_t k = 0; k < cells; k += 256)
+          D.band.push_back(BandChunkD{i, f, (int32_t)k, (int32_t)std::min<int64_t>(256, cells - k), fmask, 0});
+      }
+    }
+
     // ---- ghost chunks ----
     auto addr = [&](int box, int x, int y, int z) -> int64_t {  // global index -> element
       const BoxD& X = D.boxd[box];
