@@ -26,8 +26,14 @@ class Poly1:
     def der(self, x):
         return sum(k * a * x ** (k - 1) for k, a in enumerate(self.c) if k)
 
+    def d1(self):
+        return Poly1([k * a for k, a in enumerate(self.c)][1:] or [0.0])
+
     def d2(self):
         return Poly1([k * (k - 1) * a for k, a in enumerate(self.c)][2:] or [0.0])
+
+    def __neg__(self):
+        return Poly1([-a for a in self.c])
 
 
 class Trig1:
