@@ -311,6 +311,39 @@ int amg_apply_laplacian(amg_hier* h, int level, double* x, const double* face_da
  * bitwise reproducible); synchronises the stream. */
 int amg_dot(amg_hier* h, int level, const double* a, const double* b, double* out, void* stream);
 
+/* ---- gradient, divergence and the approximate projection --------------------
+ * Eqs. (discreteOps a-b) on one level (lev_lo == lev_hi) or in composite form
+ * over levels 0..lev_hi (COH-1..4 of Section 5.3: ghosts by the hierarchy's
+ * fill and AMRCFI, the divergence refluxed with the face averages of eq.
+ * cell2face, results averaged down onto covered cells).  Per-component
+ * arrays are indexed [level * dim + d] from level 0 (entries below lev_lo are
+ * not read); every buffer is a packed FP64 level buffer.  Inputs have their
+ * ghosts written and, in composite form, their covered cells replaced by the
+ * averages of the finer level. */
+
+/* g[l*dim+d] = G_d phi[l]; phi's ghosts from the hierarchy's own fill
+ * (face_data[l] may be NULL: zero data). */
+int amg_gradient(amg_hier* h, int lev_lo, int lev_hi, double* const* phi, const double* const* face_data,
+                 double* const* g, void* stream);
+
+/* out[l] = D w = sum_d G_d w[l*dim+d]; component d's ghosts from the
+ * hierarchy's fill with face_data[l*dim+d] (face averages of that component;
+ * the array or its entries may be NULL). */
+int amg_divergence(amg_hier* h, int lev_lo, int lev_hi, double* const* w, const double* const* face_data,
+                   double* const* out, void* stream);
+
+/* The approximate projection u = w - G phi, L phi = D w (eq. appProj, or eq.
+ * comp_ProjOp in composite form).  hw: the hierarchy whose fill the velocity
+ * components take (normally Dirichlet, face data wb = boundary velocity face
+ * averages, [l*dim+d], may be NULL); hp: a hierarchy with the same boxes and
+ * the Poisson operator with pure-Neumann conditions, which solves for phi
+ * (homogeneous Neumann data, RHS shifted for solvability, mean-free phi) with
+ * opts, reporting in stats.  phi[l]: initial guess in, potential out.
+ * u[l*dim+d] may alias w.  AMG_EINVAL if the layouts differ. */
+int amg_project(amg_hier* hw, amg_hier* hp, int lev_lo, int lev_hi, double* const* w, const double* const* wb,
+                double* const* phi, double* const* u, const amg_solve_opts* opts, amg_solve_stats* stats,
+                void* stream);
+
 /* Changes the Helmholtz coefficient c (> 0) of a finalized hierarchy: the
  * bottom inverses are recomputed on the host and captured graphs dropped.
  * Not on the hot path; AMG_EINVAL if the operator is not Helmholtz. */

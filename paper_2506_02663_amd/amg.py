@@ -100,6 +100,10 @@ def lib():
         L.amg_apply_laplacian.argtypes = [vp, i32, vp, vp, vp, vp]
         L.amg_dot.argtypes = [vp, i32, vp, vp, C.POINTER(C.c_double), vp]
         L.amg_set_coefficient.argtypes = [vp, dbl]
+        pp = C.POINTER(vp)
+        L.amg_gradient.argtypes = [vp, i32, i32, pp, pp, pp, vp]
+        L.amg_divergence.argtypes = [vp, i32, i32, pp, pp, pp, vp]
+        L.amg_project.argtypes = [vp, vp, i32, i32, pp, pp, pp, pp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
         _lib = L
     return _lib
 
@@ -434,3 +438,80 @@ class Hierarchy:
     def set_coefficient(self, c):
         self._check(lib().amg_set_coefficient(self.h, float(c)))
         self.c = float(c)
+
+    # ---- gradient, divergence, projection ----
+    # level lists start at level lev_lo; component lists are [level][d]
+    def _comp_ptrs(self, lev_lo, comps, need=True):
+        import torch
+        n = (lev_lo + len(comps)) * self.dim
+        arr = (C.c_void_p * max(n, 1))()
+        for i, per in enumerate(comps):
+            l = lev_lo + i
+            for d in range(self.dim):
+                t = None if per is None else per[d]
+                if t is None:
+                    if need:
+                        raise ValueError("missing component")
+                    continue
+                self._need(t, l, 0, "component", (torch.float64,))
+                arr[l * self.dim + d] = t.data_ptr()
+        return arr
+
+    def _lev_ptrs(self, lev_lo, ts, faces=False):
+        import torch
+        arr = (C.c_void_p * (lev_lo + len(ts)))()
+        for i, t in enumerate(ts):
+            if t is None:
+                continue
+            if faces:
+                self._need_faces(t, lev_lo + i)
+            else:
+                self._need(t, lev_lo + i, 0, "array", (torch.float64,))
+            arr[lev_lo + i] = t.data_ptr()
+        return arr
+
+    def gradient(self, phis, gs, fds=None, lev_lo=0):
+        """gs[i][d] = G_d phis[i] on levels lev_lo.. (composite if more than one)."""
+        n = len(phis)
+        self._check(lib().amg_gradient(self.h, lev_lo, lev_lo + n - 1, self._lev_ptrs(lev_lo, phis),
+                                       self._lev_ptrs(lev_lo, fds or [None] * n, True),
+                                       self._comp_ptrs(lev_lo, gs), _stream()))
+
+    def divergence(self, ws, outs, wbs=None, lev_lo=0):
+        """outs[i] = D ws[i] (ws[i][d] components); wbs[i][d] face data or None."""
+        n = len(ws)
+        wb = None
+        if wbs is not None:
+            wb = (C.c_void_p * ((lev_lo + n) * self.dim))()
+            for i, per in enumerate(wbs):
+                for d in range(self.dim):
+                    t = None if per is None else per[d]
+                    if t is not None:
+                        self._need_faces(t, lev_lo + i)
+                        wb[(lev_lo + i) * self.dim + d] = t.data_ptr()
+        self._check(lib().amg_divergence(self.h, lev_lo, lev_lo + n - 1, self._comp_ptrs(lev_lo, ws), wb,
+                                         self._lev_ptrs(lev_lo, outs), _stream()))
+
+
+def project(Hw, Hp, ws, phis, us, wbs=None, opts=None, lev_lo=0):
+    """u = w - G phi with L phi = D w (see amg_project); Hw: velocity fill,
+    Hp: pure-Neumann Poisson hierarchy with the same boxes."""
+    n = len(ws)
+    wb = None
+    if wbs is not None:
+        wb = (C.c_void_p * ((lev_lo + n) * Hw.dim))()
+        for i, per in enumerate(wbs):
+            for d in range(Hw.dim):
+                t = None if per is None else per[d]
+                if t is not None:
+                    Hw._need_faces(t, lev_lo + i)
+                    wb[(lev_lo + i) * Hw.dim + d] = t.data_ptr()
+    o = opts or default_opts()
+    st = SolveStats()
+    rc = lib().amg_project(Hw.h, Hp.h, lev_lo, lev_lo + n - 1, Hw._comp_ptrs(lev_lo, ws), wb,
+                           Hp._lev_ptrs(lev_lo, phis), Hp._comp_ptrs(lev_lo, us), C.byref(o), C.byref(st), _stream())
+    if rc and rc != ENOTCONVERGED:
+        Hp._check(rc)
+    out = st.as_dict()
+    out["status"] = rc
+    return out

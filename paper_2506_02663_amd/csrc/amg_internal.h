@@ -97,6 +97,8 @@ struct RfxFaceD {  // one coarse-fine face of a valid coarse cell
   int32_t fsn;     // fine stride along the normal n (pointing into the fine level)
   int32_t ft0, ft1;  // fine strides across the face
   int32_t csn;     // coarse stride along n
+  int32_t d;       // direction of the normal
+  int32_t sg;      // +1: n = +e_d, -1: n = -e_d
 };
 
 struct ProlD {     // one fine cell and its coarse parent

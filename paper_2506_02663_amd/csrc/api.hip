@@ -1201,6 +1201,144 @@ int amg_set_coefficient(amg_hier* H, double c) {
   return AMG_OK;
 }
 
+// ---- gradient, divergence, projection (eqs. discreteOps a-b, appProj,
+// comp_ProjOp) ----------------------------------------------------------------
+static int check_range(amg_hier* H, int lev_lo, int lev_hi) {
+  if (!H || !H->finalized) return fail(H, AMG_EINVAL, "amg_finalize has not been called");
+  if (lev_lo < 0 || lev_hi >= H->nlevels || lev_hi < lev_lo) return fail(H, AMG_EINVAL, "level out of range");
+  if (lev_lo != lev_hi) {
+    if (lev_lo != 0) return fail(H, AMG_EUNSUPPORTED, "a composite operator starts at level 0");
+    for (int l = 1; l <= lev_hi; ++l)
+      if (H->levels[l].cf_mode != AMG_CF_INTERP)
+        return fail(H, AMG_EINVAL, "levels of a composite operator take interpolated coarse-fine ghosts");
+  } else if (lev_lo > 0 && H->levels[lev_lo].cf_mode == AMG_CF_INTERP) {
+    return fail(H, AMG_EUNSUPPORTED, "a level with interpolated coarse-fine ghosts is used in composite form");
+  }
+  return AMG_OK;
+}
+
+// the ghosts of level l's array u: the level's fill from face data fd, then
+// (composite) AMRCFI from the level below
+static void fill_level(amg_hier* H, int l, double* u, const double* fd, const double* uc, hipStream_t st) {
+  Level& L = H->levels[l];
+  launch_fill<double>(L.depths[0], u, fd, st);
+  if (uc) launch_cfi(H->dim, L.cmp, uc, u, st);
+}
+
+static int gradient_impl(amg_hier* H, int lo, int hi, double* const* phi, const double* const* fd,
+                         double* const* g, const double* const* w, hipStream_t st) {
+  const int dim = H->dim;
+  const bool comp = hi > lo;
+  for (int l = lo; l <= hi; ++l) {
+    if (!phi[l]) return fail(H, AMG_EINVAL, "null phi");
+    for (int d = 0; d < dim; ++d)
+      if (!g[l * dim + d] || (w && !w[l * dim + d])) return fail(H, AMG_EINVAL, "null component");
+  }
+  if (comp)
+    for (int l = hi; l >= 1; --l) launch_avgdown(dim, H->levels[l].cmp, phi[l], phi[l - 1], st);
+  for (int l = lo; l <= hi; ++l) {
+    fill_level(H, l, phi[l], fd ? fd[l] : nullptr, comp && l > lo ? phi[l - 1] : nullptr, st);
+    DPtrs gp{};
+    CPtrs wp{};
+    for (int d = 0; d < dim; ++d) {
+      gp.p[d] = g[l * dim + d];
+      wp.p[d] = w ? w[l * dim + d] : nullptr;
+    }
+    launch_grad(dim, H->levels[l].depths[0], phi[l], gp, wp, w != nullptr, st);
+  }
+  if (comp)
+    for (int l = hi; l >= 1; --l)
+      for (int d = 0; d < dim; ++d) launch_avgdown(dim, H->levels[l].cmp, g[l * dim + d], g[(l - 1) * dim + d], st);
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+static int divergence_impl(amg_hier* H, int lo, int hi, double* const* w, const double* const* wb,
+                           double* const* out, hipStream_t st) {
+  const int dim = H->dim;
+  const bool comp = hi > lo;
+  for (int l = lo; l <= hi; ++l) {
+    if (!out[l]) return fail(H, AMG_EINVAL, "null output");
+    for (int d = 0; d < dim; ++d)
+      if (!w[l * dim + d]) return fail(H, AMG_EINVAL, "null component");
+  }
+  if (comp)
+    for (int l = hi; l >= 1; --l)
+      for (int d = 0; d < dim; ++d) launch_avgdown(dim, H->levels[l].cmp, w[l * dim + d], w[(l - 1) * dim + d], st);
+  for (int l = lo; l <= hi; ++l) {
+    CPtrs wp{};
+    for (int d = 0; d < dim; ++d) {
+      fill_level(H, l, w[l * dim + d], wb ? wb[l * dim + d] : nullptr, comp && l > lo ? w[(l - 1) * dim + d] : nullptr,
+                 st);
+      wp.p[d] = w[l * dim + d];
+    }
+    launch_div(dim, H->levels[l].depths[0], wp, out[l], st);
+  }
+  if (comp) {
+    for (int l = 1; l <= hi; ++l) {
+      CPtrs wc{}, wf{};
+      for (int d = 0; d < dim; ++d) {
+        wc.p[d] = w[(l - 1) * dim + d];
+        wf.p[d] = w[l * dim + d];
+      }
+      launch_reflux_div(dim, H->levels[l].cmp, wc, wf, out[l - 1], H->levels[l - 1].depths[0].h, st);
+    }
+    for (int l = hi; l >= 1; --l) launch_avgdown(dim, H->levels[l].cmp, out[l], out[l - 1], st);
+  }
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_gradient(amg_hier* H, int lev_lo, int lev_hi, double* const* phi, const double* const* face_data,
+                 double* const* g, void* stream) {
+  TRY(check_range(H, lev_lo, lev_hi));
+  if (!phi || !g) return fail(H, AMG_EINVAL, "bad arguments");
+  return gradient_impl(H, lev_lo, lev_hi, phi, face_data, g, nullptr, stream_of(H, stream));
+}
+
+int amg_divergence(amg_hier* H, int lev_lo, int lev_hi, double* const* w, const double* const* face_data,
+                   double* const* out, void* stream) {
+  TRY(check_range(H, lev_lo, lev_hi));
+  if (!w || !out) return fail(H, AMG_EINVAL, "bad arguments");
+  return divergence_impl(H, lev_lo, lev_hi, w, face_data, out, stream_of(H, stream));
+}
+
+int amg_project(amg_hier* Hw, amg_hier* Hp, int lev_lo, int lev_hi, double* const* w, const double* const* wb,
+                double* const* phi, double* const* u, const amg_solve_opts* opts, amg_solve_stats* stats,
+                void* stream) {
+  TRY(check_range(Hw, lev_lo, lev_hi));
+  TRY(check_range(Hp, lev_lo, lev_hi));
+  if (!w || !phi || !u) return fail(Hp, AMG_EINVAL, "bad arguments");
+  if (Hp->op != AMG_POISSON) return fail(Hp, AMG_EINVAL, "the potential's hierarchy must hold the Poisson operator");
+  // the two hierarchies must share the packed layout of every level
+  if (Hw->dim != Hp->dim || Hw->nlevels != Hp->nlevels) return fail(Hp, AMG_EINVAL, "hierarchies differ");
+  for (int l = lev_lo; l <= lev_hi; ++l) {
+    const Depth& A0 = Hw->levels[l].depths[0];
+    const Depth& B0 = Hp->levels[l].depths[0];
+    if (A0.boxes.size() != B0.boxes.size() || A0.nstored != B0.nstored) return fail(Hp, AMG_EINVAL, "layouts differ");
+    for (size_t b = 0; b < A0.boxes.size(); ++b)
+      if (A0.boxd[b].off != B0.boxd[b].off || memcmp(A0.boxes[b].lo, B0.boxes[b].lo, sizeof(int) * 3) ||
+          memcmp(A0.boxes[b].hi, B0.boxes[b].hi, sizeof(int) * 3))
+        return fail(Hp, AMG_EINVAL, "layouts differ");
+  }
+  hipStream_t st = stream_of(Hp, stream);
+  std::vector<double*> div(lev_hi + 1, nullptr);
+  for (int l = lev_lo; l <= lev_hi; ++l) div[l] = Hw->levels[l].fsh;
+  int rc = divergence_impl(Hw, lev_lo, lev_hi, w, wb, div.data(), st);
+  if (rc != AMG_OK) return fail(Hp, rc, Hw->err);
+  amg_solve_opts o;
+  amg_default_opts(&o);
+  if (opts) o = *opts;
+  TRY(check_opts(Hp, o));
+  std::vector<const double*> f(div.begin(), div.end());
+  if (lev_hi > lev_lo)
+    rc = composite_solve(Hp, lev_lo, lev_hi, phi, f.data(), nullptr, &o, stats, st);
+  else
+    rc = level_solve(Hp, lev_lo, phi[lev_lo], f[lev_lo], nullptr, o, stats, st, false);
+  if (rc != AMG_OK) return rc;
+  return gradient_impl(Hp, lev_lo, lev_hi, phi, nullptr, u, w, st);
+}
+
 int amg_timing_enable(amg_hier* H, int on) {
   if (!H) return AMG_EINVAL;
   H->timer.on = on != 0;

@@ -246,6 +246,8 @@ int build_composite(amg_hier* H, int l, std::string& err) {
               r.ft0 = Z.s[t[0]];
               r.ft1 = dim == 3 ? Z.s[t[1]] : 0;
               r.csn = sg * Y.s[d];
+              r.d = d;
+              r.sg = sg;
               X.rfx_face.push_back(r);
             }
           if (X.rfx_face.size() > nf0) {

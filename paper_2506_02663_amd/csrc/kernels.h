@@ -15,6 +15,17 @@ template <typename T>
 void launch_band(int dim, const Depth& D, int mode, const T* u, T* out, T alpha, T beta, T scale, int col,
                  hipStream_t st);
 void launch_tile_dot(int dim, const Depth& D, const double* a, const double* b, double* part, hipStream_t st);
+// per-direction device pointers, passed by value
+struct DPtrs {
+  double* p[3];
+};
+struct CPtrs {
+  const double* p[3];
+};
+// g[d] = G_d u, or w[d] - G_d u if sub
+void launch_grad(int dim, const Depth& D, const double* u, DPtrs g, CPtrs w, bool sub, hipStream_t st);
+void launch_div(int dim, const Depth& D, CPtrs w, double* out, hipStream_t st);
+void launch_reflux_div(int dim, const Composite& X, CPtrs wc, CPtrs wf, double* div, double hc, hipStream_t st);
 template <typename T>
 void launch_residual(int dim, const Depth& D, bool all, const T* u, const T* f, T* r, T alpha, T beta, double* part,
                      hipStream_t st);

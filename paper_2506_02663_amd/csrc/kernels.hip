@@ -800,6 +800,53 @@ __global__ void __launch_bounds__(256) k_band(const BandChunkD* __restrict__ chu
   out[c] += scale * delta / (alpha + beta * (T(-30 * DIM) + fold_at<T, DIM>(b, codes, x[0], x[1], x[2])));
 }
 
+// discrete gradient, eq. (discreteOps a): g[d] = (-u[+2] + 8 u[+1] - 8 u[-1]
+// + u[-2]) / 12h along d, from u with its ghosts filled; w != NULL: g[d] =
+// w[d] - that (the projection's correction u = w - G phi)
+template <int DIM>
+__global__ void __launch_bounds__(256) k_grad(const TileD* __restrict__ tiles, int ntiles,
+                                              const BoxD* __restrict__ boxes, const double* __restrict__ u,
+                                              DPtrs g, CPtrs w, bool sub, double inv12h) {
+  FOR_COLUMN(DIM) {
+    const int64_t c0 = C.base + (int64_t)(p + 2) * C.sm;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (j == 1 && !C.ok1) break;
+      const int64_t c = c0 + j;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int64_t s = d == 0 ? 1 : (int64_t)b.s[d];
+        const double v = (-u[c + 2 * s] + 8.0 * u[c + s] - 8.0 * u[c - s] + u[c - 2 * s]) * inv12h;
+        g.p[d][c] = sub ? w.p[d][c] - v : v;
+      }
+    }
+  }
+}
+
+// discrete divergence, eq. (discreteOps b): sum over d of the gradient of
+// w[d] along d (ghosts of every component filled)
+template <int DIM>
+__global__ void __launch_bounds__(256) k_div(const TileD* __restrict__ tiles, int ntiles,
+                                             const BoxD* __restrict__ boxes, CPtrs w, double* __restrict__ out,
+                                             double inv12h) {
+  FOR_COLUMN(DIM) {
+    const int64_t c0 = C.base + (int64_t)(p + 2) * C.sm;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (j == 1 && !C.ok1) break;
+      const int64_t c = c0 + j;
+      double acc = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int64_t s = d == 0 ? 1 : (int64_t)b.s[d];
+        const double* a = w.p[d];
+        acc += (-a[c + 2 * s] + 8.0 * a[c + s] - 8.0 * a[c - s] + a[c - 2 * s]);
+      }
+      out[c] = acc * inv12h;
+    }
+  }
+}
+
 // per-tile sum of a * b over the interior (dot products)
 template <int DIM>
 __global__ void __launch_bounds__(256) k_tile_dot(const TileD* __restrict__ tiles, int ntiles,
@@ -960,6 +1007,39 @@ __global__ void __launch_bounds__(256) k_reflux(int ncell, const int64_t* __rest
   r[c] += kappa * corr;
 }
 
+// refluxing of the divergence (COH-3 for eq. discreteOps b in divergence
+// form): div[c] += sum over the cell's coarse-fine faces of
+// sg (mean fine face average - coarse face average of w_d) / hc, face
+// averages by eq. (cell2face, first row); w[d]: component d
+template <int DIM>
+__global__ void __launch_bounds__(256) k_reflux_div(int ncell, const int64_t* __restrict__ cell,
+                                                    const int32_t* __restrict__ ptr,
+                                                    const RfxFaceD* __restrict__ faces, CPtrs wc, CPtrs wf,
+                                                    double* __restrict__ div,
+                                                    double inv_hc) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= ncell) return;
+  const int64_t c = cell[i];
+  double corr = 0.0;
+  for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+    const RfxFaceD F = faces[k];
+    const double* uc = F.d == 0 ? wc.p[0] : (F.d == 1 ? wc.p[1] : wc.p[2]);
+    const double* uf = F.d == 0 ? wf.p[0] : (F.d == 1 ? wf.p[1] : wf.p[2]);
+    const int64_t n = F.csn;
+    const double Fc = (-uc[c + 2 * n] + 7.0 * uc[c + n] + 7.0 * uc[c] - uc[c - n]) * (1.0 / 12.0);
+    const int64_t fn = F.fsn;
+    double Ff = 0.0;
+#pragma unroll
+    for (int t = 0; t < (1 << (DIM - 1)); ++t) {
+      const int64_t e = F.fe + ((t & 1) ? F.ft0 : 0) + ((t & 2) ? F.ft1 : 0);
+      Ff += (-uf[e + fn] + 7.0 * uf[e] + 7.0 * uf[e - fn] - uf[e - 2 * fn]) * (1.0 / 12.0);
+    }
+    Ff *= 1.0 / (1 << (DIM - 1));
+    corr += F.sg * (Ff - Fc) * inv_hc;
+  }
+  div[c] += corr;
+}
+
 // prolongation of a coarse correction onto the finer level (face-neighbour
 // linear): v = (1 - DIM/4) E[P] + 1/4 sum_d E[P +- e_d]; u += v, and ef = v
 template <typename T, int DIM>
@@ -1082,6 +1162,29 @@ void launch_band(int dim, const Depth& D, int mode, const T* u, T* out, T alpha,
     }
   }
 #undef BAND_
+}
+
+void launch_grad(int dim, const Depth& D, const double* u, DPtrs g, CPtrs w, bool sub, hipStream_t st) {
+  const size_t n = D.tiles.size();
+  if (!n) return;
+  DISPATCH_DIM(dim, k_grad, D.d_tiles, (int)n, D.d_box, u, g, w, sub, 1.0 / (12.0 * D.h));
+}
+
+void launch_div(int dim, const Depth& D, CPtrs w, double* out, hipStream_t st) {
+  const size_t n = D.tiles.size();
+  if (!n) return;
+  DISPATCH_DIM(dim, k_div, D.d_tiles, (int)n, D.d_box, w, out, 1.0 / (12.0 * D.h));
+}
+
+void launch_reflux_div(int dim, const Composite& X, CPtrs wc, CPtrs wf, double* div, double hc, hipStream_t st) {
+  const int n = (int)X.rfx_cell.size();
+  if (!n) return;
+  if (dim == 2)
+    hipLaunchKernelGGL(k_reflux_div<2>, dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_rfx_cell, X.d_rfx_ptr,
+                       X.d_rfx_face, wc, wf, div, 1.0 / hc);
+  else
+    hipLaunchKernelGGL(k_reflux_div<3>, dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_rfx_cell, X.d_rfx_ptr,
+                       X.d_rfx_face, wc, wf, div, 1.0 / hc);
 }
 
 void launch_tile_dot(int dim, const Depth& D, const double* a, const double* b, double* part, hipStream_t st) {
