@@ -183,12 +183,46 @@ def solvability_shift(lev, f, fd, comps):
     return out, defects
 
 
+def cf_delta_correction(lev, f, fd, comps):
+    """Solvability by correcting the coarse-fine face data (eq.
+    correctingFaceAvg): on each listed component that has coarse-fine
+    (non-physical) Neumann faces, one constant delta is added to the face
+    data of all of them so that the sum of h^D f equals the sum of
+    h^(D-1) g over the component's boundary faces; a component without such
+    faces takes the RHS shift instead.  Returns (f, fd, defects)."""
+    hD, hD1 = lev.h ** lev.dim, lev.h ** (lev.dim - 1)
+    fd = {k: (v.copy() if fd is not None else lev.zeros()) for k, v in (fd or lev.zero_face_data()).items()}
+    f = f.copy()
+    defects = []
+    for c in comps:
+        sel = lev.labels == c
+        bsum, ncf = 0.0, 0
+        cf_ends = []
+        for d in range(lev.dim):
+            for s in (0, 1):
+                end = lev.row_end(d, s) & sel
+                bsum += fd[(d, s)][end].sum() * hD1
+                cf = end & ~lev.end_is_physical(d, s) & (lev.end_kind(d, s) == "N")
+                ncf += int(cf.sum())
+                cf_ends.append(((d, s), cf))
+        defect = hD * f[sel].sum() - bsum
+        defects.append(defect)
+        if ncf:
+            delta = defect / (hD1 * ncf)
+            for k, cf in cf_ends:
+                fd[k][cf] += delta
+        else:
+            f[sel] -= defect / (sel.sum() * hD)
+    return f, fd, defects
+
+
 def norm_inf(lev, a):
     return float(np.abs(a[lev.mask]).max()) if lev.ncells else 0.0
 
 
 def solve(lev, f, op, c, fd=None, cfv=None, x0=None, nu1=2, nu2=2, smoother="jacobi",
-          omega=2.0 / 3.0, tol_rel=1e-10, tol_abs=0.0, max_cycles=50, shift=True, mg=None, transpose=False):
+          omega=2.0 / 3.0, tol_rel=1e-10, tol_abs=0.0, max_cycles=50, shift=True, mg=None, transpose=False,
+          cf_delta=False):
     """Outer residual-correction loop in FP64:
     r = f - A(x); s = ||r||_inf; e = V(r / s); x += s e; remove the mean of x
     on every singular component; stop by the max-norm criterion above.
@@ -201,7 +235,9 @@ def solve(lev, f, op, c, fd=None, cfv=None, x0=None, nu1=2, nu2=2, smoother="jac
     mg = mg or MG(lev, op, c, nu1, nu2, smoother, omega, transpose)
     sing = mg.sing[0]
     defects = []
-    if shift and sing:
+    if shift and sing and cf_delta:
+        f, fd, defects = cf_delta_correction(lev, f, fd, sing)
+    elif shift and sing:
         f, defects = solvability_shift(lev, f, fd, sing)
     x = lev.zeros() if x0 is None else x0.copy()
     hist = []
@@ -220,7 +256,7 @@ def solve(lev, f, op, c, fd=None, cfv=None, x0=None, nu1=2, nu2=2, smoother="jac
         hist.append(norm_inf(lev, r))
         cycles += 1
     return x, {"cycles": cycles, "history": hist, "converged": hist[-1] <= target,
-               "defects": defects, "rhs": f}
+               "defects": defects, "rhs": f, "fd": fd}
 
 
 def direct_solve(lev, f, op, c, fd=None, cfv=None):
