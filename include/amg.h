@@ -92,6 +92,11 @@ extern "C" {
 /* solvability modes for components with a constant null vector */
 #define AMG_SOLV_RHS_SHIFT 0 /* shift the right-hand side to satisfy the discrete condition */
 #define AMG_SOLV_OFF 1       /* do nothing; report the defect */
+/* eq. (correctingFaceAvg): add one constant delta to the Neumann face data of
+ * every coarse-fine face of the component (|faces| delta h^(D-1) = defect);
+ * a component without coarse-fine Neumann faces takes the RHS shift.  Level
+ * solves only (a composite solve treats it as AMG_SOLV_RHS_SHIFT). */
+#define AMG_SOLV_CF_DELTA 2
 
 /* kernel kinds of the optional event timing (finest multigrid depth) */
 #define AMG_T_SWEEP 0     /* one smoothing sweep or half-sweep */

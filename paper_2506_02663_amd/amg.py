@@ -20,7 +20,7 @@ CF_DIRICHLET, CF_NEUMANN, CF_INTERP = 0, 1, 2
 SMOOTH_JACOBI, SMOOTH_RB = 0, 1
 FP64, MIXED = 0, 1
 F64, F32 = 0, 1
-SOLV_RHS_SHIFT, SOLV_OFF = 0, 1
+SOLV_RHS_SHIFT, SOLV_OFF, SOLV_CF_DELTA = 0, 1, 2
 T_SWEEP, T_FILL, T_RESTRICT, T_PROLONG, T_RESIDUAL, T_KINDS = range(6)
 TUNE_MARCH2, TUNE_MARCH3, TUNE_ROW_ALIGN = range(3)
 MAX_HISTORY, MAX_COMP = 128, 64

@@ -59,7 +59,8 @@ struct ChunkD {            // up to 64 consecutive ghost columns of one face
   int32_t count;           // columns in the chunk (<= 64)
   int32_t box;
   uint8_t kind1, kind2;
-  uint8_t pad[6];
+  uint8_t cf;              // 1: the face is not on the physical boundary
+  uint8_t pad[5];
 };
 
 // Up to 256 cells of the band of one box face that the transposed ghost
@@ -203,6 +204,7 @@ struct Level {
   std::vector<int32_t> box_comp;
   std::vector<int32_t> comp_singular;
   std::vector<int64_t> comp_cells;
+  std::vector<double> comp_ncf;      // coarse-fine Neumann face columns per component (depth 0)
   std::vector<int64_t> face_off;     // [box*6 + d*2 + side] element offset of face data
   int64_t nface = 0;
   int ncomp = 0, nsingular = 0;
@@ -221,6 +223,9 @@ struct Level {
   double* d_delta = nullptr;       // per-component shift
   double* d_bsum = nullptr;        // per-component sum of Neumann face data
   double* d_defect = nullptr;      // per-component solvability defect
+  double* d_comp_ncf = nullptr;    // comp_ncf on the device
+  double* d_dfd = nullptr;         // per-component face-data correction
+  double* fdc = nullptr;           // corrected face data (nface)
   double* scal = nullptr;    // device scalars: norms history, scale
   double* h_scal = nullptr;  // pinned host mirror
 };

@@ -299,7 +299,7 @@ void free_level(amg::Level& L) {
   }
   for (void* p : {(void*)L.d_mat, (void*)L.d_idx, (void*)L.r64, (void*)L.fsh, (void*)L.partial, (void*)L.partial2, (void*)L.comp_sum,
                   (void*)L.scal, (void*)L.d_comp_flag, (void*)L.d_comp_cnt, (void*)L.d_delta, (void*)L.d_bsum,
-                  (void*)L.d_defect})
+                  (void*)L.d_defect, (void*)L.d_dfd, (void*)L.fdc, (void*)L.d_comp_ncf})
     if (p) (void)hipFree(p);
   if (L.h_scal) (void)hipHostFree(L.h_scal);
   const Composite& X = L.cmp;
@@ -580,6 +580,9 @@ int amg_finalize(amg_hier* H) {
     TRY(zalloc(H, &L.d_delta, L.ncomp));
     TRY(zalloc(H, &L.d_bsum, L.ncomp));
     TRY(zalloc(H, &L.d_defect, L.ncomp));
+    TRY(zalloc(H, &L.d_dfd, L.ncomp));
+    TRY(zalloc(H, &L.fdc, (size_t)std::max<int64_t>(L.nface, 1)));
+    TRY(upload(H, &L.d_comp_ncf, L.comp_ncf));
     TRY(upload(H, &L.d_comp_flag, L.comp_singular));
     std::vector<double> cnt((size_t)L.depths.size() * L.ncomp);
     for (size_t k = 0; k < L.depths.size(); ++k)
@@ -805,7 +808,8 @@ int amg_vcycle(amg_hier* H, int level, int dtype, const amg_solve_opts* opts, co
 static int check_opts(amg_hier* H, const amg_solve_opts& o) {
   if (o.nu1 < 0 || o.nu2 < 0 || o.max_cycles < 0 || o.max_cycles > 100000 ||
       (o.smoother != AMG_SMOOTH_JACOBI && o.smoother != AMG_SMOOTH_RB) ||
-      (o.precision != AMG_FP64 && o.precision != AMG_MIXED) || !(o.omega > 0))
+      (o.precision != AMG_FP64 && o.precision != AMG_MIXED) || !(o.omega > 0) ||
+      (o.solvability != AMG_SOLV_RHS_SHIFT && o.solvability != AMG_SOLV_OFF && o.solvability != AMG_SOLV_CF_DELTA))
     return fail(H, AMG_EINVAL, "bad solve options");
   return AMG_OK;
 }
@@ -875,7 +879,7 @@ static int composite_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x
       stats->ncomp = 1;
       stats->defect[0] = defect;
     }
-    if (o.solvability == AMG_SOLV_RHS_SHIFT) {
+    if (o.solvability != AMG_SOLV_OFF) {
       L0.h_scal[0] = defect / vol;
       HIPCHK(hipMemcpyAsync(L0.scal + S_DELTA, L0.h_scal, sizeof(double), hipMemcpyHostToDevice, C.st));
       for (int l = 0; l <= C.hi; ++l) {
@@ -961,7 +965,15 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
       bsum = L.d_bsum;
     }
     launch_comp_delta(L.comp_sum, bsum, L.d_comp_flag, L.d_comp_cnt, L.ncomp, hD, hD1, L.d_delta, L.d_defect, R.st);
-    if (o.solvability == AMG_SOLV_RHS_SHIFT) {
+    if (o.solvability == AMG_SOLV_CF_DELTA && !tr) {
+      // eq. (correctingFaceAvg): the face data of coarse-fine Neumann faces
+      // take the correction, the right-hand side only where there are none
+      launch_cf_delta(L.d_defect, L.d_comp_flag, L.d_comp_ncf, L.d_comp_cnt, L.ncomp, hD, hD1, L.d_delta, L.d_dfd,
+                      R.st);
+      launch_fd_correct(D0, FD, L.d_dfd, L.fdc, R.st);
+      FD = L.fdc;
+    }
+    if (o.solvability == AMG_SOLV_RHS_SHIFT || o.solvability == AMG_SOLV_CF_DELTA) {
       launch_shift_copy(dim, D0, F, L.fsh, L.d_delta, R.st);
       frhs = L.fsh;
     }

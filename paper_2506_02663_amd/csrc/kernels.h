@@ -58,6 +58,9 @@ void launch_comp_delta(const double* sum, const double* bsum, const int32_t* fla
 template <typename T>
 void launch_comp_shift(int dim, const Depth& D, T* a, const double* delta, hipStream_t st);
 void launch_chunk_fdsum(const Depth& D, const double* fd, const uint8_t* valid, double* part, hipStream_t st);
+void launch_cf_delta(const double* defect, const int32_t* flag, const double* ncf, const double* cnt, int ncomp,
+                     double hD, double hD1, double* delta, double* dfd, hipStream_t st);
+void launch_fd_correct(const Depth& D, const double* fd, const double* dfd, double* out, hipStream_t st);
 void launch_cfi(int dim, const Composite& X, const double* uc, double* uf, hipStream_t st);
 void launch_avgdown(int dim, const Composite& X, const double* uf, double* uc, hipStream_t st);
 void launch_reflux(int dim, const Composite& X, const double* uc, const double* uf, double* r, double kappa,

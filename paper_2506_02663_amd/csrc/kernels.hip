@@ -910,6 +910,40 @@ __global__ void k_comp_delta(const double* __restrict__ sum, const double* __res
   delta[c] = dv;
 }
 
+// solvability by the coarse-fine face-data correction (eq. correctingFaceAvg):
+// per singular component with coarse-fine Neumann faces, dfd = defect /
+// (h^(D-1) ncf) and no RHS shift; otherwise the RHS shift of k_comp_delta
+__global__ void k_cf_delta(const double* __restrict__ defect, const int32_t* __restrict__ flag,
+                           const double* __restrict__ ncf, const double* __restrict__ cnt, int ncomp, double hD,
+                           double hD1, double* __restrict__ delta, double* __restrict__ dfd) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncomp) return;
+  double dv = 0.0, dq = 0.0;
+  if (flag[c]) {
+    if (ncf[c] > 0)
+      dq = defect[c] / (hD1 * ncf[c]);
+    else
+      dv = defect[c] / (cnt[c] * hD);
+  }
+  delta[c] = dv;
+  dfd[c] = dq;
+}
+
+// corrected face data: out = fd (0 if NULL) + dfd[component] on coarse-fine
+// Neumann columns
+__global__ void __launch_bounds__(256) k_fd_correct(const ChunkD* __restrict__ chunks, int nchunks,
+                                                    const BoxD* __restrict__ boxes, const double* __restrict__ fd,
+                                                    const double* __restrict__ dfd, double* __restrict__ out) {
+  const int ci = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (ci >= nchunks) return;
+  const ChunkD ch = chunks[ci];
+  if (lane >= ch.count || ch.fd < 0) return;
+  double v = fd ? fd[ch.fd + lane] : 0.0;
+  if (ch.cf && ch.kind1 == G_FILL_N) v += dfd[boxes[ch.box].comp];
+  out[ch.fd + lane] = v;
+}
+
 // sum of face data over Neumann-filled ghost columns of each chunk
 __global__ void __launch_bounds__(256) k_chunk_fdsum(const ChunkD* __restrict__ chunks, int nchunks,
                                                      const double* __restrict__ fd, const uint8_t* __restrict__ valid,
@@ -1353,6 +1387,18 @@ void launch_comp_shift(int dim, const Depth& D, T* a, const double* delta, hipSt
     hipLaunchKernelGGL((k_comp_shift<T, 2>), grid8(n), threads<2>(), 0, st, D.d_tiles, (int)n, D.d_box, a, delta);
   else
     hipLaunchKernelGGL((k_comp_shift<T, 3>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, a, delta);
+}
+
+void launch_cf_delta(const double* defect, const int32_t* flag, const double* ncf, const double* cnt, int ncomp,
+                     double hD, double hD1, double* delta, double* dfd, hipStream_t st) {
+  hipLaunchKernelGGL(k_cf_delta, dim3((ncomp + 255) / 256), dim3(256), 0, st, defect, flag, ncf, cnt, ncomp, hD, hD1,
+                     delta, dfd);
+}
+
+void launch_fd_correct(const Depth& D, const double* fd, const double* dfd, double* out, hipStream_t st) {
+  const int n = (int)D.chunks.size();
+  if (!n) return;
+  hipLaunchKernelGGL(k_fd_correct, dim3((n + 3) / 4), dim3(256), 0, st, D.d_chunks, n, D.d_box, fd, dfd, out);
 }
 
 void launch_chunk_fdsum(const Depth& D, const double* fd, const uint8_t* valid, double* part, hipStream_t st) {

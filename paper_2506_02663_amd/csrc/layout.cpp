@@ -410,6 +410,10 @@ int plan_level(amg_hier* H, int l, std::string& err) {
                 ch.src2 = addr(fc.src2[col], g2[0], g2[1], g2[2]);
                 ch.sstride2 = D.boxd[fc.src2[col]].s[t[0]];
               }
+              {
+                const int p1 = s ? B.hi[d] + 1 : B.lo[d] - 1;
+                ch.cf = (!L.isolated && p1 >= 0 && p1 < dn[d]) ? 1 : 0;
+              }
               ch.fd = -1;
               if (k == 0 && (ch.kind1 == G_FILL_D || ch.kind1 == G_FILL_N))
                 ch.fd = L.face_off[D.level_box[i] * 6 + d * 2 + s] + (int64_t)q0 + (int64_t)n0 * q1;
@@ -505,6 +509,9 @@ int plan_level(amg_hier* H, int l, std::string& err) {
     for (int c = 0; c < L.ncomp; ++c) L.comp_singular[c] = !has_dir[c];
   }
   L.nsingular = (int)std::count(L.comp_singular.begin(), L.comp_singular.end(), 1);
+  L.comp_ncf.assign(L.ncomp, 0.0);
+  for (const ChunkD& ch : L.depths[0].chunks)
+    if (ch.cf && ch.kind1 == G_FILL_N && ch.fd >= 0) L.comp_ncf[L.depths[0].boxd[ch.box].comp] += ch.count;
   return AMG_OK;
 }
 
