@@ -299,6 +299,30 @@ int amg_vcycle(amg_hier* h, int level, int dtype, const amg_solve_opts* opts, co
 int amg_solve_adjoint(amg_hier* h, int level, double* lam, const double* g, const amg_solve_opts* opts,
                       amg_solve_stats* stats, void* stream);
 
+/* Composite adjoint: solves (A^comp)^T lam = g on the valid cells of levels
+ * 0..lev_hi (levels >= 1 in AMG_CF_INTERP), A^comp the homogeneous composite
+ * operator of amg_solve's composite form.  Its transpose reverses the
+ * average-down (a covered cell's adjoint goes to its children in equal
+ * parts), AMRCFI (ghost adjoints back onto the coarse window), the fills and
+ * stencils (as for a level) and the refluxing (the adjoint of a refluxed
+ * coarse cell onto the coarse and fine values its fluxes read).  The cycle
+ * is the composite cycle of amg_solve with each level's transposed multigrid
+ * and volume-weighted transfers (covered cells carry the sum of the finer
+ * residual; prolonged corrections are divided by 2^D).  Pure Neumann: g is
+ * projected along the volume weights w (h_l^D) so that it sums to zero, and
+ * lam is returned with zero plain sum (the gradient in f of a solution that
+ * amg_solve returns with zero volume-weighted mean).  lam[l]: initial guess
+ * in, solution out (covered cells and face ghosts 0); g[l] read on valid
+ * cells only.  Errors as amg_solve. */
+int amg_solve_adjoint_composite(amg_hier* h, int lev_hi, double* const* lam, const double* const* g,
+                                const amg_solve_opts* opts, amg_solve_stats* stats, void* stream);
+
+/* r = g - (A^comp)^T lam on the valid cells of levels 0..lev_hi (covered
+ * cells of r: the sum of their children's values, the convention of the
+ * adjoint cycle).  lam's covered cells are set to 0 and its ghosts written. */
+int amg_composite_residual_adjoint(amg_hier* h, int lev_hi, double* const* lam, const double* const* g,
+                                   double* const* r, void* stream);
+
 /* One V(nu1,nu2) cycle of the adjoint system from e = 0: e ~= A_h^-T f. */
 int amg_vcycle_adjoint(amg_hier* h, int level, int dtype, const amg_solve_opts* opts, const void* f, void* e,
                        void* stream);

@@ -104,6 +104,8 @@ def lib():
         L.amg_gradient.argtypes = [vp, i32, i32, pp, pp, pp, vp]
         L.amg_divergence.argtypes = [vp, i32, i32, pp, pp, pp, vp]
         L.amg_project.argtypes = [vp, vp, i32, i32, pp, pp, pp, pp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
+        L.amg_solve_adjoint_composite.argtypes = [vp, i32, pp, pp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
+        L.amg_composite_residual_adjoint.argtypes = [vp, i32, pp, pp, pp, vp]
         _lib = L
     return _lib
 
@@ -407,6 +409,32 @@ class Hierarchy:
         out = st.as_dict()
         out["status"] = rc
         return out
+
+    def solve_adjoint_composite(self, lams, gs, opts=None):
+        """(A^comp)^T lam = g over levels 0..len(lams)-1."""
+        import torch
+        n = len(lams)
+        for l in range(n):
+            self._need(lams[l], l, 0, "lam", (torch.float64,))
+            self._need(gs[l], l, 0, "g", (torch.float64,))
+        o = opts or default_opts()
+        st = SolveStats()
+        rc = lib().amg_solve_adjoint_composite(self.h, n - 1, self._level_ptrs(lams, n), self._level_ptrs(gs, n),
+                                               C.byref(o), C.byref(st), _stream())
+        if rc and rc != ENOTCONVERGED:
+            self._check(rc)
+        out = st.as_dict()
+        out["status"] = rc
+        return out
+
+    def composite_residual_adjoint(self, lams, gs, rs):
+        import torch
+        n = len(lams)
+        for l in range(n):
+            for t, nm in ((lams[l], "lam"), (gs[l], "g"), (rs[l], "r")):
+                self._need(t, l, 0, nm, (torch.float64,))
+        self._check(lib().amg_composite_residual_adjoint(self.h, n - 1, self._level_ptrs(lams, n),
+                                                         self._level_ptrs(gs, n), self._level_ptrs(rs, n), _stream()))
 
     def vcycle_adjoint(self, level, f, e, opts=None):
         self._need(f, level, 0, "f")

@@ -119,6 +119,18 @@ struct Composite {  // tables of level l against level l-1 (l >= 1)
   std::vector<int32_t> rfx_ptr;   // CSR into rfx_face
   std::vector<RfxFaceD> rfx_face;
   std::vector<ProlD> pro;
+  // transposes for the adjoint of the composite operator (gathers in a
+  // fixed order): per interpolated ghost its row end, inward stride and layer;
+  // AMRCFI by coarse target element; refluxing by target element of level
+  // l-1 and of level l (coefficient times the adjoint of the refluxed cell)
+  std::vector<int64_t> cfi_e0;
+  std::vector<int32_t> cfi_in;
+  std::vector<uint8_t> cfi_layer;
+  std::vector<int64_t> cfiT_elem;
+  std::vector<int32_t> cfiT_ptr, cfiT_ent;  // ent = ghost * 5^D + window cell
+  std::vector<int64_t> rfxTc_elem, rfxTf_elem;
+  std::vector<int32_t> rfxTc_ptr, rfxTf_ptr, rfxTc_src, rfxTf_src;  // src: index into rfx_cell
+  std::vector<double> rfxTc_coef, rfxTf_coef;
   // device
   double* d_w = nullptr;
   int64_t* d_cfi_dst = nullptr;
@@ -129,6 +141,14 @@ struct Composite {  // tables of level l against level l-1 (l >= 1)
   int32_t* d_rfx_ptr = nullptr;
   RfxFaceD* d_rfx_face = nullptr;
   ProlD* d_pro = nullptr;
+  int64_t* d_cfi_e0 = nullptr;
+  int32_t* d_cfi_in = nullptr;
+  uint8_t* d_cfi_layer = nullptr;
+  int64_t* d_cfiT_elem = nullptr;
+  int32_t *d_cfiT_ptr = nullptr, *d_cfiT_ent = nullptr;
+  int64_t *d_rfxTc_elem = nullptr, *d_rfxTf_elem = nullptr;
+  int32_t *d_rfxTc_ptr = nullptr, *d_rfxTf_ptr = nullptr, *d_rfxTc_src = nullptr, *d_rfxTf_src = nullptr;
+  double *d_rfxTc_coef = nullptr, *d_rfxTf_coef = nullptr;
 };
 
 // ---- host-side description ---------------------------------------------------
@@ -156,6 +176,12 @@ struct Depth {
   std::vector<int32_t> comp_seg_ptr;  // segments of each component (range into seg_ptr)
   std::vector<int32_t> chunk_comp_ptr, chunk_comp_idx; // CSR: chunks of each component
   std::vector<BandChunkD> band;      // cells the transposed fill touches
+  // exchange transpose (depth 0): source element -> ghost slots that copy it
+  std::vector<int64_t> exT_elem, exT_slot;
+  std::vector<int32_t> exT_ptr;
+  int64_t* d_exT_elem = nullptr;
+  int64_t* d_exT_slot = nullptr;
+  int32_t* d_exT_ptr = nullptr;
   std::vector<int32_t> bottom_boxes; // boxes solved exactly at this depth
   std::vector<BottomGroupD> groups;
   int64_t nstored = 0;
@@ -197,6 +223,8 @@ struct Level {
   std::vector<uint8_t> face_valid;  // face-data entries not under level l+1
   uint8_t* d_face_valid = nullptr;
   double* E64 = nullptr;            // total correction of this level in a composite cycle
+  double* A64 = nullptr;            // adjoint accumulator (composite adjoint)
+  double* mu = nullptr;             // adjoints of the interpolated ghosts
   std::vector<Box> boxes;
   bool isolated = false;
   int cf_mode = AMG_CF_DIRICHLET;

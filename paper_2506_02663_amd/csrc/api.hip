@@ -305,8 +305,14 @@ void free_level(amg::Level& L) {
   const Composite& X = L.cmp;
   for (void* p : {(void*)L.E64, (void*)L.d_face_valid, (void*)X.d_w, (void*)X.d_cfi_dst, (void*)X.d_cfi_src,
                   (void*)X.d_cfi_w, (void*)X.d_avg, (void*)X.d_rfx_cell, (void*)X.d_rfx_ptr, (void*)X.d_rfx_face,
-                  (void*)X.d_pro})
+                  (void*)X.d_pro, (void*)L.A64, (void*)L.mu, (void*)X.d_cfi_e0, (void*)X.d_cfi_in,
+                  (void*)X.d_cfi_layer, (void*)X.d_cfiT_elem, (void*)X.d_cfiT_ptr, (void*)X.d_cfiT_ent,
+                  (void*)X.d_rfxTc_elem, (void*)X.d_rfxTc_ptr, (void*)X.d_rfxTc_src, (void*)X.d_rfxTc_coef,
+                  (void*)X.d_rfxTf_elem, (void*)X.d_rfxTf_ptr, (void*)X.d_rfxTf_src, (void*)X.d_rfxTf_coef})
     if (p) (void)hipFree(p);
+  for (auto& D : L.depths)
+    for (void* p : {(void*)D.d_exT_elem, (void*)D.d_exT_slot, (void*)D.d_exT_ptr})
+      if (p) (void)hipFree(p);
 }
 
 // ---- composite (multi-level) solve -------------------------------------------
@@ -314,6 +320,7 @@ struct Comp {
   amg_hier* H;
   int hi;  // finest level of the composite (level 0 is the coarsest)
   hipStream_t st;
+  bool tr = false;  // the adjoint (transposed) composite system
   std::vector<double*> X, R;
   std::vector<const double*> F, FD;
 };
@@ -358,7 +365,7 @@ void comp_level_vcycle(Comp& C, int l, const amg_solve_opts& o, double* Rl, cons
   amg_hier* H = C.H;
   Level& L = H->levels[l];
   Depth& D0 = L.depths[0];
-  Run R{H, &L, H->dim, C.st};
+  Run R{H, &L, H->dim, C.st, C.tr};
   if (o.precision == AMG_MIXED) {
     launch_to32(H->dim, D0, Rl, D0.f32, sc, C.st);
     float* e = vcycle<float>(R, o, D0.f32, D0.e32, D0.t32);
@@ -413,6 +420,102 @@ void comp_cycle(Comp& C, const amg_solve_opts& o) {
     for (int l = 0; l <= C.hi; ++l) launch_sub_scalar(dim, H->levels[l].depths[0], C.X[l], L0.d_delta, C.st);
   }
   comp_residual(C);
+}
+
+// ---- composite adjoint (the transposed composite system) ---------------------
+// R_l = g_l - (A^comp)^T lam on the valid cells (see the oracle's reverse of
+// average-down, AMRCFI, fills, stencils and refluxing); covered cells of R end
+// as the sum of their children's residuals (volume-weighted transfers of the
+// adjoint), the max norm over valid cells in level 0's S_NORM slot and the
+// per-level max (covered cells included) in S_LEV + l.
+void comp_residual_T(Comp& C) {
+  amg_hier* H = C.H;
+  const int dim = H->dim;
+  Level& L0 = H->levels[0];
+  const double lscale = H->op == AMG_HELMHOLTZ ? -H->c : 1.0;
+  for (int l = 0; l < C.hi; ++l) launch_zero_covered(H->levels[l + 1].cmp, C.X[l], C.st);
+  for (int l = 0; l <= C.hi; ++l) launch_zero<double>(H->levels[l].A64, H->levels[l].depths[0].nstored, C.st);
+  for (int l = 1; l <= C.hi; ++l)
+    launch_rfx_T(H->levels[l].cmp, C.X[l - 1], lscale, H->levels[l - 1].A64, H->levels[l].A64, C.st);
+  for (int l = 0; l <= C.hi; ++l) {
+    Level& L = H->levels[l];
+    Depth& D = L.depths[0];
+    double a, b;
+    coefs<double>(H, D, a, b);
+    launch_fill_tr<double>(D, C.X[l], C.st);
+    launch_residual<double>(dim, D, true, C.X[l], C.F[l], C.R[l], a, b, nullptr, C.st);
+    launch_band_ab(dim, D, C.X[l], L.A64, C.R[l], b, C.st);
+    launch_exch_T(D, L.A64, C.R[l], C.st);
+    launch_sub_array(dim, D, L.A64, C.R[l], C.st);
+    if (l) launch_cfi_T(dim, L.cmp, C.X[l], L.A64, b, L.mu, C.R[l - 1], C.st);
+  }
+  const double down = 1.0 / (1 << dim);
+  for (int l = 1; l <= C.hi; ++l) {
+    launch_pass_down(H->levels[l].cmp, C.R[l - 1], C.R[l], down, C.st);
+    launch_zero_covered(H->levels[l].cmp, C.R[l - 1], C.st);
+  }
+  for (int l = 0; l <= C.hi; ++l) {
+    Level& L = H->levels[l];
+    Run R{H, &L, dim, C.st};
+    launch_tile_absmax<double>(dim, L.depths[0], C.R[l], L.partial, C.st);
+    global_max(R, L.depths[0], L0.scal + S_LEV + l);
+  }
+  launch_max_slots(L0.scal + S_LEV, C.hi + 1, L0.scal + S_NORM, C.st);
+  for (int l = C.hi; l >= 1; --l) {
+    launch_sumdown(dim, H->levels[l].cmp, C.R[l], C.R[l - 1], 1.0, C.st);
+    Level& L = H->levels[l - 1];
+    Run R{H, &L, dim, C.st};
+    launch_tile_absmax<double>(dim, L.depths[0], C.R[l - 1], L.partial, C.st);
+    global_max(R, L.depths[0], L0.scal + S_LEV + l - 1);
+  }
+}
+
+// a -= w (sum over valid cells of a) / (sum of w), w = h_l^D per valid cell:
+// the projection of the pure-Neumann adjoint along the volume weights
+void proj_w(Comp& C, double* const* a) {
+  amg_hier* H = C.H;
+  const int dim = H->dim;
+  Level& L0 = H->levels[0];
+  for (int l = 0; l < C.hi; ++l) launch_zero_covered(H->levels[l + 1].cmp, a[l], C.st);
+  for (int l = C.hi; l >= 1; --l) launch_sumdown(dim, H->levels[l].cmp, a[l], a[l - 1], 1.0, C.st);
+  Run R0{H, &L0, dim, C.st};
+  launch_tile_sum<double>(dim, L0.depths[0], a[0], L0.partial, C.st);
+  comp_sums(R0, L0.depths[0], L0.comp_sum);  // level 0 is one component
+  const double vol = (double)L0.ncells * std::pow(L0.depths[0].h, dim);
+  for (int l = 0; l <= C.hi; ++l) {
+    launch_set_scaled(L0.comp_sum, std::pow(H->levels[l].depths[0].h, dim) / vol, L0.scal + S_LEV + l, C.st);
+    launch_sub_scalar(dim, H->levels[l].depths[0], a[l], L0.scal + S_LEV + l, C.st);
+  }
+  for (int l = 0; l < C.hi; ++l) launch_zero_covered(H->levels[l + 1].cmp, a[l], C.st);
+}
+
+void comp_correct_T(Comp& C, const amg_solve_opts& o, int l) {
+  amg_hier* H = C.H;
+  const int dim = H->dim;
+  Level& L0 = H->levels[0];
+  comp_residual_T(C);
+  if (l == 0 && L0.nsingular) {
+    Run R0{H, &L0, dim, C.st};
+    remove_mean<double>(R0, 0, C.R[0]);
+    launch_tile_absmax<double>(dim, L0.depths[0], C.R[0], L0.partial, C.st);
+    global_max(R0, L0.depths[0], L0.scal + S_LEV);
+  }
+  Level& L = H->levels[l];
+  launch_zero<double>(L.E64, L.depths[0].nstored, C.st);
+  comp_level_vcycle(C, l, o, C.R[l], L0.scal + S_LEV + l);
+  const double down = 1.0 / (1 << dim);
+  for (int m = l + 1; m <= C.hi; ++m) {
+    launch_fill<double>(H->levels[m - 1].depths[0], H->levels[m - 1].E64, nullptr, C.st);
+    launch_amr_prolong(dim, H->levels[m].cmp, H->levels[m - 1].E64, C.X[m], H->levels[m].E64, C.st, down);
+  }
+}
+
+void comp_cycle_T(Comp& C, const amg_solve_opts& o) {
+  amg_hier* H = C.H;
+  for (int l = C.hi; l >= 1; --l) comp_correct_T(C, o, l);
+  for (int l = 0; l <= C.hi; ++l) comp_correct_T(C, o, l);
+  if (H->levels[0].nsingular) proj_w(C, C.X.data());
+  comp_residual_T(C);
 }
 
 }  // namespace
@@ -594,6 +697,13 @@ int amg_finalize(amg_hier* H) {
     TRY(upload(H, &L.scal, sc));
     HIPCHK(hipHostMalloc((void**)&L.h_scal, S_COUNT * sizeof(double), hipHostMallocDefault));
     TRY(zalloc(H, &L.E64, L.depths[0].nstored));
+    TRY(zalloc(H, &L.A64, L.depths[0].nstored));
+    {
+      Depth& D0 = L.depths[0];
+      TRY(upload(H, &D0.d_exT_elem, D0.exT_elem));
+      TRY(upload(H, &D0.d_exT_slot, D0.exT_slot));
+      TRY(upload(H, &D0.d_exT_ptr, D0.exT_ptr));
+    }
     L.face_valid.assign((size_t)std::max<int64_t>(L.nface, 1), 1);
   }
   // composite tables of every interpolated level against the one below
@@ -614,6 +724,21 @@ int amg_finalize(amg_hier* H) {
     TRY(upload(H, &X.d_rfx_ptr, X.rfx_ptr));
     TRY(upload(H, &X.d_rfx_face, X.rfx_face));
     TRY(upload(H, &X.d_pro, X.pro));
+    TRY(upload(H, &X.d_cfi_e0, X.cfi_e0));
+    TRY(upload(H, &X.d_cfi_in, X.cfi_in));
+    TRY(upload(H, &X.d_cfi_layer, X.cfi_layer));
+    TRY(upload(H, &X.d_cfiT_elem, X.cfiT_elem));
+    TRY(upload(H, &X.d_cfiT_ptr, X.cfiT_ptr));
+    TRY(upload(H, &X.d_cfiT_ent, X.cfiT_ent));
+    TRY(upload(H, &X.d_rfxTc_elem, X.rfxTc_elem));
+    TRY(upload(H, &X.d_rfxTc_ptr, X.rfxTc_ptr));
+    TRY(upload(H, &X.d_rfxTc_src, X.rfxTc_src));
+    TRY(upload(H, &X.d_rfxTc_coef, X.rfxTc_coef));
+    TRY(upload(H, &X.d_rfxTf_elem, X.rfxTf_elem));
+    TRY(upload(H, &X.d_rfxTf_ptr, X.rfxTf_ptr));
+    TRY(upload(H, &X.d_rfxTf_src, X.rfxTf_src));
+    TRY(upload(H, &X.d_rfxTf_coef, X.rfxTf_coef));
+    TRY(zalloc(H, &L.mu, X.cfi_dst.size()));
   }
   for (auto& L : H->levels) TRY(upload(H, &L.d_face_valid, L.face_valid));
   H->finalized = true;
@@ -1127,6 +1252,93 @@ int amg_solve_adjoint(amg_hier* H, int level, double* lam, const double* g, cons
   if (opts) o = *opts;
   TRY(check_opts(H, o));
   return level_solve(H, level, lam, g, nullptr, o, stats, stream, true);
+}
+
+int amg_composite_residual_adjoint(amg_hier* H, int lev_hi, double* const* lam, const double* const* g,
+                                   double* const* r, void* stream) {
+  if (!H || !H->finalized) return fail(H, AMG_EINVAL, "amg_finalize has not been called");
+  if (!lam || !g || !r) return fail(H, AMG_EINVAL, "bad arguments");
+  Comp C;
+  TRY(make_comp(H, 0, lev_hi, lam, g, nullptr, stream, C));
+  C.tr = true;
+  for (int l = 0; l <= lev_hi; ++l) {
+    if (!r[l]) return fail(H, AMG_EINVAL, "null r");
+    C.R[l] = r[l];
+    // the source on the valid cells only
+    HIPCHK(hipMemcpyAsync(H->levels[l].fsh, C.F[l], H->levels[l].depths[0].nstored * sizeof(double),
+                          hipMemcpyDeviceToDevice, C.st));
+    if (l < lev_hi) launch_zero_covered(H->levels[l + 1].cmp, H->levels[l].fsh, C.st);
+    C.F[l] = H->levels[l].fsh;
+  }
+  comp_residual_T(C);
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_solve_adjoint_composite(amg_hier* H, int lev_hi, double* const* lam, const double* const* g,
+                                const amg_solve_opts* opts, amg_solve_stats* stats, void* stream) {
+  if (!H || !H->finalized) return fail(H, AMG_EINVAL, "amg_finalize has not been called");
+  if (!lam || !g) return fail(H, AMG_EINVAL, "bad arguments");
+  amg_solve_opts o;
+  amg_default_opts(&o);
+  if (opts) o = *opts;
+  TRY(check_opts(H, o));
+  Comp C;
+  TRY(make_comp(H, 0, lev_hi, lam, g, nullptr, stream, C));
+  C.tr = true;
+  const int dim = H->dim;
+  Level& L0 = H->levels[0];
+  if (stats) memset(stats, 0, sizeof *stats);
+  // the source on the valid cells only (library copy); pure Neumann: its
+  // projection along the volume weights
+  std::vector<double*> G(C.hi + 1);
+  for (int l = 0; l <= C.hi; ++l) {
+    G[l] = H->levels[l].fsh;
+    HIPCHK(hipMemcpyAsync(G[l], C.F[l], H->levels[l].depths[0].nstored * sizeof(double), hipMemcpyDeviceToDevice,
+                          C.st));
+  }
+  for (int l = 0; l < C.hi; ++l) launch_zero_covered(H->levels[l + 1].cmp, G[l], C.st);
+  if (L0.nsingular) proj_w(C, G.data());
+  for (int l = 0; l <= C.hi; ++l) C.F[l] = G[l];
+  auto read_norm = [&](double& v) -> int {
+    HIPCHK(hipMemcpyAsync(L0.h_scal, L0.scal + S_NORM, sizeof(double), hipMemcpyDeviceToHost, C.st));
+    HIPCHK(hipStreamSynchronize(C.st));
+    v = L0.h_scal[0];
+    return AMG_OK;
+  };
+  comp_residual_T(C);
+  HIPCHK(hipGetLastError());
+  double r0 = 0;
+  TRY(read_norm(r0));
+  if (!std::isfinite(r0)) return fail(H, AMG_ENONFINITE, "non-finite initial residual");
+  const double target = std::max(o.tol_rel * r0, o.tol_abs);
+  double rn = r0;
+  int cycles = 0;
+  if (stats) {
+    stats->r0 = r0;
+    stats->history[0] = r0;
+  }
+  while (rn > target && cycles < o.max_cycles) {
+    comp_cycle_T(C, o);
+    HIPCHK(hipGetLastError());
+    TRY(read_norm(rn));
+    ++cycles;
+    if (stats && cycles < AMG_MAX_HISTORY) stats->history[cycles] = rn;
+    if (!std::isfinite(rn)) return fail(H, AMG_ENONFINITE, "non-finite residual");
+  }
+  // the adjoint lives on the valid cells: covered cells and face ghosts 0
+  for (int l = 0; l <= C.hi; ++l) {
+    if (l < C.hi) launch_zero_covered(H->levels[l + 1].cmp, C.X[l], C.st);
+    launch_fill_zero<double>(H->levels[l].depths[0], C.X[l], C.st);
+  }
+  HIPCHK(hipGetLastError());
+  if (stats) {
+    stats->cycles = cycles;
+    stats->rfinal = rn;
+    stats->converged = rn <= target;
+  }
+  if (rn > target) return fail(H, AMG_ENOTCONVERGED, "max_cycles reached");
+  return AMG_OK;
 }
 
 int amg_vcycle_adjoint(amg_hier* H, int level, int dtype, const amg_solve_opts* opts, const void* f, void* e,

@@ -151,6 +151,13 @@ int build_composite(amg_hier* H, int l, std::string& err) {
               g[t[0]] = B.lo[t[0]] + q0;
               if (dim == 3) g[t[1]] = B.lo[t[1]] + q1;
               X.cfi_dst.push_back(elem(DF, (int)b, g, dim));
+              {
+                int g0[3] = {g[0], g[1], g[2]};
+                g0[d] = s ? B.hi[d] : B.lo[d];
+                X.cfi_e0.push_back(elem(DF, (int)b, g0, dim));
+                X.cfi_in.push_back((s ? -1 : 1) * DF.boxd[b].s[d]);
+                X.cfi_layer.push_back((uint8_t)layer);
+              }
               int lo[3] = {0, 0, 0};
               for (int e = 0; e < dim; ++e) {
                 const int P = floordiv2(g[e]);
@@ -255,6 +262,72 @@ int build_composite(amg_hier* H, int l, std::string& err) {
             X.rfx_ptr.push_back((int32_t)X.rfx_face.size());
           }
         }
+  }
+
+  // ---- transposes for the adjoint ----
+  {
+    // AMRCFI: coarse window cell -> (ghost, window cell) pairs
+    const size_t ng = X.cfi_dst.size();
+    std::vector<std::pair<int64_t, int32_t>> pairs;
+    pairs.reserve(ng * nwin);
+    for (size_t i = 0; i < ng; ++i)
+      for (int m = 0; m < nwin; ++m) pairs.push_back({(int64_t)X.cfi_src[i * nwin + m], (int32_t)(i * nwin + m)});
+    std::stable_sort(pairs.begin(), pairs.end(),
+                     [](const std::pair<int64_t, int32_t>& a, const std::pair<int64_t, int32_t>& b) {
+                       return a.first < b.first;
+                     });
+    X.cfiT_elem.clear();
+    X.cfiT_ptr.assign(1, 0);
+    X.cfiT_ent.clear();
+    for (size_t k = 0; k < pairs.size(); ++k) {
+      if (k == 0 || pairs[k].first != pairs[k - 1].first) {
+        if (k) X.cfiT_ptr.push_back((int32_t)k);
+        X.cfiT_elem.push_back(pairs[k].first);
+      }
+      X.cfiT_ent.push_back(pairs[k].second);
+    }
+    if (!pairs.empty()) X.cfiT_ptr.push_back((int32_t)pairs.size());
+    // refluxing: d(correction at coarse cell i) / d(value at element), per
+    // target element of each level; the correction is
+    // (1/hc) sum_faces [mean_t Ff_t - Fc], fluxes (-v[+2] + 15 v[+1] - 15 v[0]
+    // + v[-1]) / 12h along the face normal n
+    const double hc = DC.h, hf = DF.h;
+    const double nf = (double)(1 << (dim - 1));
+    std::vector<std::pair<int64_t, std::pair<int32_t, double>>> tc, tf;
+    const int cw[4] = {1, -15, 15, -1};  // offsets -1, 0, 1, 2 along n
+    for (size_t i = 0; i + 1 < X.rfx_ptr.size(); ++i) {
+      const int64_t c = X.rfx_cell[i];
+      for (int k = X.rfx_ptr[i]; k < X.rfx_ptr[i + 1]; ++k) {
+        const RfxFaceD& F = X.rfx_face[k];
+        for (int o = 0; o < 4; ++o)
+          tc.push_back({c + (int64_t)(o - 1) * F.csn, {(int32_t)i, -cw[o] / (12.0 * hc * hc)}});
+        for (int t = 0; t < (1 << (dim - 1)); ++t) {
+          const int64_t e = F.fe + ((t & 1) ? F.ft0 : 0) + ((t & 2) ? F.ft1 : 0);
+          // fine flux at the face: offsets -2, -1, 0, 1 from e along n
+          for (int o = 0; o < 4; ++o)
+            tf.push_back({e + (int64_t)(o - 2) * F.fsn, {(int32_t)i, cw[o] / (12.0 * hf * hc * nf)}});
+        }
+      }
+    }
+    auto build = [](std::vector<std::pair<int64_t, std::pair<int32_t, double>>>& v, std::vector<int64_t>& elem,
+                    std::vector<int32_t>& ptr, std::vector<int32_t>& src, std::vector<double>& coef) {
+      std::stable_sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+      elem.clear();
+      ptr.assign(1, 0);
+      src.clear();
+      coef.clear();
+      for (size_t k = 0; k < v.size(); ++k) {
+        if (k == 0 || v[k].first != v[k - 1].first) {
+          if (k) ptr.push_back((int32_t)k);
+          elem.push_back(v[k].first);
+        }
+        src.push_back(v[k].second.first);
+        coef.push_back(v[k].second.second);
+      }
+      if (!v.empty()) ptr.push_back((int32_t)v.size());
+    };
+    build(tc, X.rfxTc_elem, X.rfxTc_ptr, X.rfxTc_src, X.rfxTc_coef);
+    build(tf, X.rfxTf_elem, X.rfxTf_ptr, X.rfxTf_src, X.rfxTf_coef);
   }
 
   // ---- prolongation of a level-(l-1) correction onto level l ----

@@ -65,7 +65,19 @@ void launch_cfi(int dim, const Composite& X, const double* uc, double* uf, hipSt
 void launch_avgdown(int dim, const Composite& X, const double* uf, double* uc, hipStream_t st);
 void launch_reflux(int dim, const Composite& X, const double* uc, const double* uf, double* r, double kappa,
                    double hc, double hf, hipStream_t st);
-void launch_amr_prolong(int dim, const Composite& X, const double* ec, double* u, double* ef, hipStream_t st);
+void launch_amr_prolong(int dim, const Composite& X, const double* ec, double* u, double* ef, hipStream_t st,
+                        double scale = 1.0);
+// adjoint of the composite operator
+void launch_zero_covered(const Composite& X, double* u, hipStream_t st);
+void launch_sumdown(int dim, const Composite& X, const double* uf, double* uc, double scale, hipStream_t st);
+void launch_rfx_T(const Composite& X, const double* lam_c, double lscale, double* abc, double* abf, hipStream_t st);
+void launch_exch_T(const Depth& D, const double* ab, double* r, hipStream_t st);
+void launch_cfi_T(int dim, const Composite& X, const double* lam_f, const double* abf, double beta, double* mu,
+                  double* rc, hipStream_t st);
+void launch_pass_down(const Composite& X, const double* rc, double* rf, double scale, hipStream_t st);
+void launch_sub_array(int dim, const Depth& D, const double* a, double* r, hipStream_t st);
+void launch_band_ab(int dim, const Depth& D, const double* u, const double* ab, double* out, double beta,
+                    hipStream_t st);
 void launch_max_slots(const double* in, int n, double* out, hipStream_t st);
 void launch_sub_scalar(int dim, const Depth& D, double* a, const double* s, hipStream_t st);
 template <typename T>
@@ -75,6 +87,7 @@ void launch_update(int dim, const Depth& D, double* x, const T* e, const double*
 void launch_to32(int dim, const Depth& D, const double* r, float* r32, const double* scal, hipStream_t st);
 void launch_shift_copy(int dim, const Depth& D, const double* f, double* out, const double* delta, hipStream_t st);
 void launch_set_scale(const double* src, double* dst, hipStream_t st);
+void launch_set_scaled(const double* src, double f, double* dst, hipStream_t st);
 template <typename T>
 void launch_zero(T* a, int64_t n, hipStream_t st);
 }  // namespace amg

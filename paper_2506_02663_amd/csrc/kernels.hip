@@ -960,6 +960,7 @@ __global__ void __launch_bounds__(256) k_chunk_fdsum(const ChunkD* __restrict__ 
 
 // scal[dst] = src[0] (device-side scalar copy, keeps the scale on the device)
 __global__ void k_set_scale(const double* __restrict__ src, double* __restrict__ dst) { *dst = *src; }
+__global__ void k_set_scaled(const double* __restrict__ src, double f, double* __restrict__ dst) { *dst = f * *src; }
 
 // zero a whole buffer (used in place of memset nodes in captured graphs)
 template <typename T>
@@ -1078,16 +1079,183 @@ __global__ void __launch_bounds__(256) k_reflux_div(int ncell, const int64_t* __
 // linear): v = (1 - DIM/4) E[P] + 1/4 sum_d E[P +- e_d]; u += v, and ef = v
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_amr_prolong(int n, const ProlD* __restrict__ p, const T* __restrict__ ec,
-                                                     T* __restrict__ u, T* __restrict__ ef) {
+                                                     T* __restrict__ u, T* __restrict__ ef, T scale) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const ProlD q = p[i];
   T v = T(1.0 - DIM * 0.25) * ec[q.pe] +
         T(0.25) * (ec[q.pe + ((q.child & 1) ? 1 : -1)] + ec[q.pe + ((q.child & 2) ? q.cs1 : -q.cs1)]);
   if (DIM == 3) v += T(0.25) * ec[q.pe + ((q.child & 4) ? q.cs2 : -q.cs2)];
+  v *= scale;
   u[q.fe] += v;
   if (ef) ef[q.fe] = v;
 }
+
+// ---------------------------------------------------------------------------
+// adjoint of the composite operator (gathers over host-built transposes)
+
+// a[e] = 0 on the coarse cells under the finer level
+__global__ void __launch_bounds__(256) k_zero_covered(int n, const AvgD* __restrict__ a, double* __restrict__ u) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) u[a[i].ce] = 0.0;
+}
+
+// coarse cell := scale * (sum of its 2^DIM children)
+template <int DIM>
+__global__ void __launch_bounds__(256) k_sumdown(int n, const AvgD* __restrict__ a, const double* __restrict__ uf,
+                                                 double* __restrict__ uc, double scale) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const AvgD e = a[i];
+  double s = uf[e.fe] + uf[e.fe + 1] + uf[e.fe + e.fs1] + uf[e.fe + e.fs1 + 1];
+  if (DIM == 3) s += uf[e.fe + e.fs2] + uf[e.fe + e.fs2 + 1] + uf[e.fe + e.fs2 + e.fs1] + uf[e.fe + e.fs2 + e.fs1 + 1];
+  uc[e.ce] = s * scale;
+}
+
+// refluxing, transposed: out[elem[k]] += lscale * sum over entries of
+// coef * lam[cell[src]]
+__global__ void __launch_bounds__(256) k_rfx_T(int n, const int64_t* __restrict__ elem,
+                                               const int32_t* __restrict__ ptr, const int32_t* __restrict__ src,
+                                               const double* __restrict__ coef, const int64_t* __restrict__ cell,
+                                               const double* __restrict__ lam, double lscale,
+                                               double* __restrict__ out) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  double acc = 0.0;
+  for (int j = ptr[k]; j < ptr[k + 1]; ++j) acc += coef[j] * lam[cell[src[j]]];
+  out[elem[k]] += lscale * acc;
+}
+
+// exchange, transposed: r[source] -= sum of the adjoints in the ghost slots
+// that copy it
+__global__ void __launch_bounds__(256) k_exch_T(int n, const int64_t* __restrict__ elem,
+                                                const int32_t* __restrict__ ptr, const int64_t* __restrict__ slot,
+                                                const double* __restrict__ ab, double* __restrict__ r) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  double acc = 0.0;
+  for (int j = ptr[k]; j < ptr[k + 1]; ++j) acc += ab[slot[j]];
+  r[elem[k]] -= acc;
+}
+
+// adjoint of every interpolated ghost: the stencil weight its own row puts
+// on it (beta (16 l0 - l1) for layer 1, -beta l0 for layer 2) plus what
+// refluxing put in its slot
+__global__ void __launch_bounds__(256) k_cfi_mu(int n, const int64_t* __restrict__ e0, const int32_t* __restrict__ in,
+                                                const uint8_t* __restrict__ layer, const int64_t* __restrict__ dst,
+                                                const double* __restrict__ lam, const double* __restrict__ ab,
+                                                double beta, double* __restrict__ mu) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double l0 = lam[e0[i]];
+  const double v = layer[i] == 1 ? 16.0 * l0 - lam[e0[i] + in[i]] : -l0;
+  mu[i] = beta * v + ab[dst[i]];
+}
+
+// AMRCFI, transposed: r[coarse window cell] -= sum of weight * mu
+template <int DIM>
+__global__ void __launch_bounds__(256) k_cfi_T(int n, const int64_t* __restrict__ elem, const int32_t* __restrict__ ptr,
+                                               const int32_t* __restrict__ ent, const uint8_t* __restrict__ wsel,
+                                               const double* __restrict__ W, const double* __restrict__ mu,
+                                               double* __restrict__ r) {
+  constexpr int NW = DIM == 2 ? 25 : 125;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  double acc = 0.0;
+  for (int j = ptr[k]; j < ptr[k + 1]; ++j) {
+    const int i = ent[j] / NW, m = ent[j] % NW;
+    double w = W[5 * wsel[i * DIM] + m % 5] * W[5 * wsel[i * DIM + 1] + (m / 5) % 5];
+    if (DIM == 3) w *= W[5 * wsel[i * DIM + 2] + m / 25];
+    acc += w * mu[i];
+  }
+  r[elem[k]] -= acc;
+}
+
+// adjoint of the average-down: rf[child] += rc[parent] / 2^DIM
+__global__ void __launch_bounds__(256) k_pass_down(int n, const ProlD* __restrict__ p, const double* __restrict__ rc,
+                                                   double* __restrict__ rf, double scale) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const ProlD q = p[i];
+  rf[q.fe] += scale * rc[q.pe];
+}
+
+// r -= a on the interior (cells of the tiles)
+template <int DIM>
+__global__ void __launch_bounds__(256) k_sub_array(const TileD* __restrict__ tiles, int ntiles,
+                                                   const BoxD* __restrict__ boxes, const double* __restrict__ a,
+                                                   double* __restrict__ r) {
+  FOR_COLUMN(DIM) {
+    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+    r[c] -= a[c];
+    if (C.ok1) r[c + 1] -= a[c + 1];
+  }
+}
+
+// fill-band transpose for the composite adjoint: like k_band (residual mode,
+// scale -1) with the ghost adjoints beta * (stencil weights) plus what
+// refluxing put in the ghost slots (ab)
+template <int DIM>
+__global__ void __launch_bounds__(256) k_band_ab(const BandChunkD* __restrict__ chunks, int nchunks,
+                                                 const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
+                                                 const double* __restrict__ u, const double* __restrict__ ab,
+                                                 double* __restrict__ out, double beta) {
+  const int ci = blockIdx.x;
+  if (ci >= nchunks) return;
+  const BandChunkD ch = chunks[ci];
+  if ((int)threadIdx.x >= ch.count) return;
+  const BoxD b = boxes[ch.box];
+  const int k = ch.start + (int)threadIdx.x;
+  const int d = ch.face >> 1, s = ch.face & 1;
+  int x[3] = {0, 0, 0};
+  if (d == 0) {
+    const int p = k & 3, r = k >> 2;
+    x[0] = s ? b.n[0] - 1 - p : p;
+    x[1] = r % b.n[1];
+    x[2] = r / b.n[1];
+  } else if (d == 1) {
+    const int r = k / b.n[0], p = r & 3;
+    x[0] = k % b.n[0];
+    x[1] = s ? b.n[1] - 1 - p : p;
+    x[2] = r >> 2;
+  } else {
+    const int r = k / b.n[0], p = r / b.n[1];
+    x[0] = k % b.n[0];
+    x[1] = r % b.n[1];
+    x[2] = s ? b.n[2] - 1 - p : p;
+  }
+  for (int f = 0; f < ch.face; ++f) {
+    if (!((ch.fmask >> f) & 1)) continue;
+    const int e = f >> 1;
+    if (((f & 1) ? b.n[e] - 1 - x[e] : x[e]) < 4) return;
+  }
+  double delta = 0.0;
+#pragma unroll
+  for (int f = 0; f < 2 * DIM; ++f) {
+    if (!((ch.fmask >> f) & 1)) continue;
+    const int e = f >> 1, sd = f & 1;
+    const int dist = sd ? b.n[e] - 1 - x[e] : x[e];
+    if (dist >= 4) continue;
+    int colx;
+    if (DIM == 2)
+      colx = e == 0 ? x[1] : x[0];
+    else
+      colx = e == 0 ? x[1] + b.n[1] * x[2] : (e == 1 ? x[0] + b.n[0] * x[2] : x[0] + b.n[0] * x[1]);
+    const uint8_t cd = codes[b.code_off[e][sd] + colx];
+    const int kind = cd & 3;
+    if (!kind) continue;
+    int y[3] = {x[0], x[1], x[2]};
+    y[e] = sd ? b.n[e] - 1 : 0;
+    const int64_t e0 = cell_index<DIM>(b, y[0], y[1], y[2]);
+    const int64_t in = (e == 0 ? 1 : (int64_t)b.s[e]) * (sd ? -1 : 1);
+    const double l0 = u[e0], l1 = u[e0 + in];
+    delta += kFillW[kind - 1][0][dist] * (beta * (16.0 * l0 - l1) + ab[e0 - in]);
+    if (cd & 4) delta += kFillW[kind - 1][1][dist] * (-beta * l0 + ab[e0 - 2 * in]);
+  }
+  out[cell_index<DIM>(b, x[0], x[1], x[2])] -= delta;
+}
+
+
 
 // out = max over n slots
 __global__ void k_max_slots(const double* __restrict__ in, int n, double* __restrict__ out) {
@@ -1439,14 +1607,79 @@ void launch_reflux(int dim, const Composite& X, const double* uc, const double* 
                        X.d_rfx_face, uc, uf, r, kappa, 1.0 / (12 * hc), 1.0 / (12 * hf), 1.0 / hc);
 }
 
-void launch_amr_prolong(int dim, const Composite& X, const double* ec, double* u, double* ef, hipStream_t st) {
+void launch_amr_prolong(int dim, const Composite& X, const double* ec, double* u, double* ef, hipStream_t st,
+                        double scale) {
   const int n = (int)X.pro.size();
   if (!n) return;
   if (dim == 2)
-    hipLaunchKernelGGL((k_amr_prolong<double, 2>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_pro, ec, u, ef);
+    hipLaunchKernelGGL((k_amr_prolong<double, 2>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_pro, ec, u, ef,
+                       scale);
   else
-    hipLaunchKernelGGL((k_amr_prolong<double, 3>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_pro, ec, u, ef);
+    hipLaunchKernelGGL((k_amr_prolong<double, 3>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_pro, ec, u, ef,
+                       scale);
 }
+
+#define GRID1(n) dim3((unsigned)(((n) + 255) / 256)), dim3(256)
+void launch_zero_covered(const Composite& X, double* u, hipStream_t st) {
+  const int n = (int)X.avg.size();
+  if (n) hipLaunchKernelGGL(k_zero_covered, GRID1(n), 0, st, n, X.d_avg, u);
+}
+void launch_sumdown(int dim, const Composite& X, const double* uf, double* uc, double scale, hipStream_t st) {
+  const int n = (int)X.avg.size();
+  if (!n) return;
+  if (dim == 2)
+    hipLaunchKernelGGL(k_sumdown<2>, GRID1(n), 0, st, n, X.d_avg, uf, uc, scale);
+  else
+    hipLaunchKernelGGL(k_sumdown<3>, GRID1(n), 0, st, n, X.d_avg, uf, uc, scale);
+}
+void launch_rfx_T(const Composite& X, const double* lam_c, double lscale, double* abc, double* abf, hipStream_t st) {
+  int n = (int)X.rfxTc_elem.size();
+  if (n)
+    hipLaunchKernelGGL(k_rfx_T, GRID1(n), 0, st, n, X.d_rfxTc_elem, X.d_rfxTc_ptr, X.d_rfxTc_src, X.d_rfxTc_coef,
+                       X.d_rfx_cell, lam_c, lscale, abc);
+  n = (int)X.rfxTf_elem.size();
+  if (n)
+    hipLaunchKernelGGL(k_rfx_T, GRID1(n), 0, st, n, X.d_rfxTf_elem, X.d_rfxTf_ptr, X.d_rfxTf_src, X.d_rfxTf_coef,
+                       X.d_rfx_cell, lam_c, lscale, abf);
+}
+void launch_exch_T(const Depth& D, const double* ab, double* r, hipStream_t st) {
+  const int n = (int)D.exT_elem.size();
+  if (n) hipLaunchKernelGGL(k_exch_T, GRID1(n), 0, st, n, D.d_exT_elem, D.d_exT_ptr, D.d_exT_slot, ab, r);
+}
+void launch_cfi_T(int dim, const Composite& X, const double* lam_f, const double* abf, double beta, double* mu,
+                  double* rc, hipStream_t st) {
+  const int n = (int)X.cfi_dst.size();
+  if (!n) return;
+  hipLaunchKernelGGL(k_cfi_mu, GRID1(n), 0, st, n, X.d_cfi_e0, X.d_cfi_in, X.d_cfi_layer, X.d_cfi_dst, lam_f, abf,
+                     beta, mu);
+  const int m = (int)X.cfiT_elem.size();
+  if (!m) return;
+  if (dim == 2)
+    hipLaunchKernelGGL(k_cfi_T<2>, GRID1(m), 0, st, m, X.d_cfiT_elem, X.d_cfiT_ptr, X.d_cfiT_ent, X.d_cfi_w, X.d_w,
+                       mu, rc);
+  else
+    hipLaunchKernelGGL(k_cfi_T<3>, GRID1(m), 0, st, m, X.d_cfiT_elem, X.d_cfiT_ptr, X.d_cfiT_ent, X.d_cfi_w, X.d_w,
+                       mu, rc);
+}
+void launch_pass_down(const Composite& X, const double* rc, double* rf, double scale, hipStream_t st) {
+  const int n = (int)X.pro.size();
+  if (n) hipLaunchKernelGGL(k_pass_down, GRID1(n), 0, st, n, X.d_pro, rc, rf, scale);
+}
+void launch_sub_array(int dim, const Depth& D, const double* a, double* r, hipStream_t st) {
+  const size_t n = D.tiles.size();
+  if (!n) return;
+  DISPATCH_DIM(dim, k_sub_array, D.d_tiles, (int)n, D.d_box, a, r);
+}
+void launch_band_ab(int dim, const Depth& D, const double* u, const double* ab, double* out, double beta,
+                    hipStream_t st) {
+  const int n = (int)D.band.size();
+  if (!n) return;
+  if (dim == 2)
+    hipLaunchKernelGGL(k_band_ab<2>, dim3(n), dim3(256), 0, st, D.d_band, n, D.d_box, D.d_codes, u, ab, out, beta);
+  else
+    hipLaunchKernelGGL(k_band_ab<3>, dim3(n), dim3(256), 0, st, D.d_band, n, D.d_box, D.d_codes, u, ab, out, beta);
+}
+#undef GRID1
 
 void launch_max_slots(const double* in, int n, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_max_slots, dim3(1), dim3(1), 0, st, in, n, out);
@@ -1494,6 +1727,9 @@ void launch_shift_copy(int dim, const Depth& D, const double* f, double* out, co
 
 void launch_set_scale(const double* src, double* dst, hipStream_t st) {
   hipLaunchKernelGGL(k_set_scale, dim3(1), dim3(1), 0, st, src, dst);
+}
+void launch_set_scaled(const double* src, double f, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_scaled, dim3(1), dim3(1), 0, st, src, f, dst);
 }
 
 template <typename T>

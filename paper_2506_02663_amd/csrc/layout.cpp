@@ -509,6 +509,33 @@ int plan_level(amg_hier* H, int l, std::string& err) {
     for (int c = 0; c < L.ncomp; ++c) L.comp_singular[c] = !has_dir[c];
   }
   L.nsingular = (int)std::count(L.comp_singular.begin(), L.comp_singular.end(), 1);
+  // exchange transpose at depth 0: every source cell with the ghost slots
+  // that copy it
+  {
+    Depth& D0 = L.depths[0];
+    std::vector<std::pair<int64_t, int64_t>> pairs;
+    for (const ChunkD& ch : D0.chunks)
+      for (int lane = 0; lane < ch.count; ++lane) {
+        const int64_t g1 = ch.dst + (int64_t)lane * ch.cstride;
+        if (ch.kind1 == G_EXCH) pairs.push_back({ch.src1 + (int64_t)lane * ch.sstride1, g1});
+        if (ch.kind2 == G_EXCH) pairs.push_back({ch.src2 + (int64_t)lane * ch.sstride2, g1 + ch.nstride});
+      }
+    std::stable_sort(pairs.begin(), pairs.end(),
+                     [](const std::pair<int64_t, int64_t>& a, const std::pair<int64_t, int64_t>& b) {
+                       return a.first < b.first;
+                     });
+    D0.exT_elem.clear();
+    D0.exT_slot.clear();
+    D0.exT_ptr.assign(1, 0);
+    for (size_t k = 0; k < pairs.size(); ++k) {
+      if (k == 0 || pairs[k].first != pairs[k - 1].first) {
+        if (k) D0.exT_ptr.push_back((int32_t)k);
+        D0.exT_elem.push_back(pairs[k].first);
+      }
+      D0.exT_slot.push_back(pairs[k].second);
+    }
+    if (!pairs.empty()) D0.exT_ptr.push_back((int32_t)pairs.size());
+  }
   L.comp_ncf.assign(L.ncomp, 0.0);
   for (const ChunkD& ch : L.depths[0].chunks)
     if (ch.cf && ch.kind1 == G_FILL_N && ch.fd >= 0) L.comp_ncf[L.depths[0].boxd[ch.box].comp] += ch.count;

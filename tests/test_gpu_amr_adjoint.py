@@ -1,0 +1,96 @@
+"""Composite adjoint on the GPU against the oracle: the transposed composite
+residual element by element (reversed average-down, AMRCFI, fills, stencils
+and refluxing) and whole composite adjoint solves in FP64 (same residual
+history) and mixed precision, on two- and three-level hierarchies."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import amr, amr_adj  # noqa: E402
+from paper_2506_02663_amd import amg as A  # noqa: E402
+from tests.gpuhelp import from_dev, to_dev  # noqa: E402
+
+LAYOUTS = {
+    "two_level": ((16, 16), 1 / 16, [[((0, 0), (15, 15))], [((8, 8), (15, 23)), ((16, 8), (23, 15))]]),
+    "three_level": ((16, 16), 1 / 16, [[((0, 0), (15, 15))], [((4, 4), (27, 27))], [((16, 16), (31, 31))]]),
+    "corner": ((16, 8), 1 / 16, [[((0, 0), (15, 7))], [((0, 0), (7, 7))]]),
+    "boundary": ((32, 16), 1 / 32, [[((0, 0), (15, 15)), ((16, 0), (31, 15))],
+                                   [((0, 0), (15, 15)), ((16, 0), (23, 11))]]),
+}
+CASES = [("D", "helmholtz", 0.3), ("N", "poisson", 0.0), ("D", "poisson", 0.0), ("N", "helmholtz", 0.5)]
+
+
+def build(name, bc, op, c0):
+    base, h0, boxes = LAYOUTS[name]
+    OH = amr.Hierarchy(base, h0, boxes, {(d, s): bc for d in range(2) for s in (0, 1)})
+    H = A.Hierarchy(2, base, h0, len(boxes))
+    for l, bl in enumerate(boxes):
+        H.set_level_boxes(l, bl)
+        if l:
+            H.set_cf_mode(l, A.CF_INTERP)
+    for d in range(2):
+        for s in (0, 1):
+            H.set_physical_bc(d, s, A.DIRICHLET if bc == "D" else A.NEUMANN)
+    c = c0 * h0
+    H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c)
+    H.finalize()
+    return OH, H, c
+
+
+def rand_valid(OH, seed):
+    rng = np.random.default_rng(seed)
+    return [np.where(OH.valid[l], rng.normal(size=lev.pshape), 0.0) for l, lev in enumerate(OH.levels)]
+
+
+def relmax(G, O, masks):
+    num = max(np.abs(G[l] - O[l])[masks[l]].max() for l in range(len(G)))
+    den = max(np.abs(O[l])[masks[l]].max() for l in range(len(G)))
+    return num / den
+
+
+@pytest.mark.parametrize("name", sorted(LAYOUTS))
+@pytest.mark.parametrize("bc,op,c0", CASES)
+def test_transposed_composite_residual(name, bc, op, c0):
+    OH, H, c = build(name, bc, op, c0)
+    lam = rand_valid(OH, 1)
+    g = rand_valid(OH, 2)
+    nl = OH.nlev
+    # garbage on covered cells must not matter (the adjoint lives on valid cells)
+    lam_dev = [to_dev(H, l, 0, np.where(OH.levels[l].mask, lam[l] + 7.0 * ~OH.valid[l], 0.0)) for l in range(nl)]
+    g_dev = [to_dev(H, l, 0, np.where(OH.levels[l].mask, g[l] - 3.0 * ~OH.valid[l], 0.0)) for l in range(nl)]
+    r = [torch.zeros_like(x) for x in lam_dev]
+    H.composite_residual_adjoint(lam_dev, g_dev, r)
+    torch.cuda.synchronize()
+    want = amr_adj.composite_residual_T(OH, lam, g, op, c)
+    got = [from_dev(H, l, 0, r[l], OH.levels[l]) for l in range(nl)]
+    # valid cells, and covered cells holding the sums of their children
+    assert relmax(got, want, [lev.mask for lev in OH.levels]) < 1e-11
+
+
+@pytest.mark.parametrize("name", sorted(LAYOUTS))
+@pytest.mark.parametrize("bc,op,c0", CASES[:3])
+def test_composite_adjoint_solve(name, bc, op, c0):
+    OH, H, c = build(name, bc, op, c0)
+    g = rand_valid(OH, 3)
+    lam_o, st_o = amr_adj.composite_solve_T(OH, g, op, c, tol_rel=1e-12, max_cycles=200)
+    assert st_o["converged"]
+    nl = OH.nlev
+    gd = [to_dev(H, l, 0, g[l]) for l in range(nl)]
+    for prec, tol in ((A.FP64, 1e-10), (A.MIXED, 1e-9)):
+        lam = [torch.zeros_like(x) for x in gd]
+        st = H.solve_adjoint_composite(lam, gd, A.default_opts(precision=prec, tol_rel=1e-12, max_cycles=200))
+        assert st["status"] == 0 and st["converged"], st
+        got = [from_dev(H, l, 0, lam[l], OH.levels[l]) for l in range(nl)]
+        assert relmax(got, lam_o, OH.valid) < tol, (prec, st["cycles"], st_o["cycles"])
+        for l in range(nl):
+            assert np.all(got[l][OH.levels[l].mask & ~OH.valid[l]] == 0.0)
+        if prec == A.FP64:
+            hist, ho = np.array(st["history"]), np.array(st_o["history"])
+            assert abs(len(hist) - len(ho)) <= 1
+            k = min(len(hist), len(ho))
+            assert np.allclose(hist[:k], ho[:k], rtol=1e-5, atol=1e-14 * ho[0])
