@@ -317,6 +317,14 @@ int amg_solve_adjoint(amg_hier* h, int level, double* lam, const double* g, cons
 int amg_solve_adjoint_composite(amg_hier* h, int lev_hi, double* const* lam, const double* const* g,
                                 const amg_solve_opts* opts, amg_solve_stats* stats, void* stream);
 
+/* y = L^comp x over levels 0..lev_hi: the composite Laplacian (COH-1..4,
+ * refluxed, averaged down) of x with its face data, whatever operator the
+ * hierarchy holds; x is averaged down and its ghosts written; y != x.  With x
+ * a composite Helmholtz solution and lam its adjoint, dJ/dc = sum over levels
+ * of <lam, y> (lam is zero on covered cells). */
+int amg_composite_laplacian(amg_hier* h, int lev_hi, double* const* x, const double* const* face_data,
+                            double* const* y, void* stream);
+
 /* r = g - (A^comp)^T lam on the valid cells of levels 0..lev_hi (covered
  * cells of r: the sum of their children's values, the convention of the
  * adjoint cycle).  lam's covered cells are set to 0 and its ghosts written. */

@@ -106,6 +106,7 @@ def lib():
         L.amg_project.argtypes = [vp, vp, i32, i32, pp, pp, pp, pp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
         L.amg_solve_adjoint_composite.argtypes = [vp, i32, pp, pp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
         L.amg_composite_residual_adjoint.argtypes = [vp, i32, pp, pp, pp, vp]
+        L.amg_composite_laplacian.argtypes = [vp, i32, pp, pp, pp, vp]
         _lib = L
     return _lib
 
@@ -426,6 +427,17 @@ class Hierarchy:
         out = st.as_dict()
         out["status"] = rc
         return out
+
+    def composite_laplacian(self, xs, ys, fds=None):
+        import torch
+        n = len(xs)
+        fds = fds or [None] * n
+        for l in range(n):
+            self._need(xs[l], l, 0, "x", (torch.float64,))
+            self._need(ys[l], l, 0, "y", (torch.float64,))
+            self._need_faces(fds[l], l)
+        self._check(lib().amg_composite_laplacian(self.h, n - 1, self._level_ptrs(xs, n), self._level_ptrs(fds, n),
+                                                  self._level_ptrs(ys, n), _stream()))
 
     def composite_residual_adjoint(self, lams, gs, rs):
         import torch

@@ -1,4 +1,4 @@
-"""torch.autograd binding of a level solve.
+"""torch.autograd binding of level and composite solves.
 
 ``level_solve(f, c, H, level, face_data, opts)`` returns x with
 A x = f - b(face_data) on one level of the hierarchy H (the Helmholtz
@@ -14,6 +14,12 @@ with L the Laplacian of x with the solve's face data.  Only the cells of the
 level carry gradient: the ghost entries of dJ/dx are ignored and those of
 dJ/df are zero.  No gradient flows to the face data.  Every step runs in the
 HIP library; this module only passes tensors.
+
+``composite_solve(fs, c, H, face_data, opts)`` does the same for the
+composite system over levels 0..len(fs)-1 (x on every level, covered cells
+holding averages): backward solves the composite adjoint system, dJ/df_l =
+lam_l (zero on covered cells) and dJ/dc = sum_l <lam_l, (L^comp x)_l>.
+Gradients reach x through its valid cells only.
 """
 import torch
 
@@ -57,3 +63,44 @@ class LevelSolve(torch.autograd.Function):
 def level_solve(f, c, H, level=0, face_data=None, opts=None):
     """x = A^-1 (f - b(face_data)), differentiable in f and (Helmholtz) c."""
     return LevelSolve.apply(f, c, H, level, face_data, opts)
+
+
+class CompositeSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, c, H, face_data, opts, *fs):
+        if H.op_kind == A.HELMHOLTZ:
+            cv = float(c)
+            if cv != H.c:
+                H.set_coefficient(cv)
+        xs = [torch.zeros_like(f) for f in fs]
+        st = H.solve_composite(xs, [f.contiguous() for f in fs], face_data, opts)
+        if st["status"] != 0:
+            raise A.AmgError(st["status"], f"composite solve did not converge: {st}")
+        ctx.H, ctx.face_data, ctx.opts = H, face_data, opts
+        ctx.c_meta = (c.dtype, c.device) if torch.is_tensor(c) else None
+        ctx.save_for_backward(*xs)
+        return tuple(xs)
+
+    @staticmethod
+    def backward(ctx, *gxs):
+        xs = ctx.saved_tensors
+        H = ctx.H
+        lams = [torch.zeros_like(x) for x in xs]
+        gs = [g.contiguous() if g is not None else torch.zeros_like(x) for g, x in zip(gxs, xs)]
+        st = H.solve_adjoint_composite(lams, gs, ctx.opts)
+        if st["status"] != 0:
+            raise A.AmgError(st["status"], f"composite adjoint solve did not converge: {st}")
+        gc = None
+        if ctx.c_meta is not None and ctx.needs_input_grad[0] and H.op_kind == A.HELMHOLTZ:
+            xx = [x.clone() for x in xs]
+            ys = [torch.zeros_like(x) for x in xs]
+            H.composite_laplacian(xx, ys, ctx.face_data)
+            tot = sum(H.dot(l, lams[l], ys[l]) for l in range(len(xs)))
+            gc = torch.tensor(tot, dtype=ctx.c_meta[0], device=ctx.c_meta[1])
+        return (gc, None, None, None, *lams)
+
+
+def composite_solve(fs, c, H, face_data=None, opts=None):
+    """[x_l] solving the composite system, differentiable in every f_l and
+    (Helmholtz) c."""
+    return list(CompositeSolve.apply(c, H, face_data, opts, *fs))

@@ -321,6 +321,7 @@ struct Comp {
   int hi;  // finest level of the composite (level 0 is the coarsest)
   hipStream_t st;
   bool tr = false;  // the adjoint (transposed) composite system
+  bool lap = false;  // comp_residual with F = NULL gives L^comp x (the Laplacian, whatever the operator)
   std::vector<double*> X, R;
   std::vector<const double*> F, FD;
 };
@@ -343,9 +344,13 @@ void comp_residual(Comp& C) {
     if (l) launch_cfi(dim, L.cmp, C.X[l - 1], C.X[l], C.st);
     double a, b;
     coefs<double>(H, D, a, b);
+    if (C.lap) {
+      a = 0.0;
+      b = 1.0 / (12.0 * D.h * D.h);
+    }
     launch_residual<double>(dim, D, true, C.X[l], C.F[l], C.R[l], a, b, nullptr, C.st);
   }
-  const double kappa = H->op == AMG_HELMHOLTZ ? H->c : -1.0;
+  const double kappa = C.lap ? 1.0 : (H->op == AMG_HELMHOLTZ ? H->c : -1.0);
   for (int l = 1; l <= C.hi; ++l)
     launch_reflux(dim, H->levels[l].cmp, C.X[l - 1], C.X[l], C.R[l - 1], kappa, H->levels[l - 1].depths[0].h,
                   H->levels[l].depths[0].h, C.st);
@@ -1252,6 +1257,23 @@ int amg_solve_adjoint(amg_hier* H, int level, double* lam, const double* g, cons
   if (opts) o = *opts;
   TRY(check_opts(H, o));
   return level_solve(H, level, lam, g, nullptr, o, stats, stream, true);
+}
+
+int amg_composite_laplacian(amg_hier* H, int lev_hi, double* const* x, const double* const* face_data,
+                            double* const* y, void* stream) {
+  if (!H || !H->finalized) return fail(H, AMG_EINVAL, "amg_finalize has not been called");
+  if (!x || !y) return fail(H, AMG_EINVAL, "bad arguments");
+  Comp C;
+  TRY(make_comp(H, 0, lev_hi, x, (const double* const*)x, face_data, stream, C));
+  C.lap = true;
+  for (int l = 0; l <= lev_hi; ++l) {
+    if (!y[l] || y[l] == x[l]) return fail(H, AMG_EINVAL, "bad y");
+    C.R[l] = y[l];
+    C.F[l] = nullptr;
+  }
+  comp_residual(C);
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
 }
 
 int amg_composite_residual_adjoint(amg_hier* H, int lev_hi, double* const* lam, const double* const* g,

@@ -94,3 +94,55 @@ def test_composite_adjoint_solve(name, bc, op, c0):
             assert abs(len(hist) - len(ho)) <= 1
             k = min(len(hist), len(ho))
             assert np.allclose(hist[:k], ho[:k], rtol=1e-5, atol=1e-14 * ho[0])
+
+
+def rand_faces(OH, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for lev in OH.levels:
+        fd = lev.zero_face_data()
+        for k in fd:
+            e = lev.end_is_physical(*k)
+            fd[k][e] = rng.normal(size=int(e.sum()))
+        out.append(fd)
+    return out
+
+
+@pytest.mark.parametrize("name", ["two_level", "three_level"])
+def test_composite_laplacian(name):
+    from tests.gpuhelp import faces_to_dev
+    OH, H, c = build(name, "D", "helmholtz", 0.3)
+    U = rand_valid(OH, 4)
+    FD = rand_faces(OH, 5)
+    xs = [to_dev(H, l, 0, U[l]) for l in range(OH.nlev)]
+    ys = [torch.zeros_like(x) for x in xs]
+    H.composite_laplacian(xs, ys, [faces_to_dev(H, l, OH.levels[l], FD[l]) for l in range(OH.nlev)])
+    want = OH.composite_apply(OH.average_down_all(U), "poisson", 0.0, FD)
+    got = [from_dev(H, l, 0, ys[l], OH.levels[l]) for l in range(OH.nlev)]
+    assert relmax(got, want, [lev.mask for lev in OH.levels]) < 1e-11
+
+
+@pytest.mark.parametrize("name", ["two_level", "three_level"])
+def test_composite_autograd_against_oracle(name):
+    from paper_2506_02663_amd.autograd import composite_solve
+    from tests.gpuhelp import faces_to_dev
+    OH, H, c = build(name, "D", "helmholtz", 0.4)
+    F, T = rand_valid(OH, 6), rand_valid(OH, 7)
+    FD = rand_faces(OH, 8)
+    nl = OH.nlev
+    fds = [faces_to_dev(H, l, OH.levels[l], FD[l]) for l in range(nl)]
+    fs = [to_dev(H, l, 0, F[l]).requires_grad_(True) for l in range(nl)]
+    ts = [to_dev(H, l, 0, T[l]) for l in range(nl)]
+    masks = [to_dev(H, l, 0, OH.valid[l].astype(float)) for l in range(nl)]
+    cdev = torch.tensor(c, dtype=torch.float64, requires_grad=True)
+    opts = A.default_opts(precision=A.FP64, tol_rel=1e-13, max_cycles=300)
+    xs = composite_solve(fs, cdev, H, fds, opts)
+    J = sum(0.5 * (((xs[l] - ts[l]) * masks[l]) ** 2).sum() for l in range(nl))
+    J.backward()
+    U, _ = amr.composite_solve(OH, F, "helmholtz", c, FD, tol_rel=1e-13, max_cycles=300)
+    lam, _ = amr_adj.composite_solve_T(OH, [U[l] - T[l] for l in range(nl)], "helmholtz", c, tol_rel=1e-13,
+                                       max_cycles=300)
+    got = [from_dev(H, l, 0, fs[l].grad, OH.levels[l]) for l in range(nl)]
+    assert relmax(got, lam, OH.valid) < 1e-8
+    gc = amr_adj.grad_c(OH, lam, U, FD)
+    assert abs(cdev.grad.item() - gc) < 1e-7 * abs(gc)
