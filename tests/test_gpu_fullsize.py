@@ -1,0 +1,108 @@
+"""The benchmark workloads at full size, in the configuration the benchmark
+times (mixed precision, red-black V(2,2), 1e-10): the GPU solutions satisfy
+the oracle's discrete systems, checked by evaluating the oracle's operator
+on the GPU solution everywhere (3D 256^3) or on a sample of boxes (the batch
+of 1024 boxes), and one operator application agrees with the oracle element
+by element at full size.  The oracle's multigrid is too slow at these sizes;
+its operator is not."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import mg  # noqa: E402
+from oracle.level import Level  # noqa: E402
+from paper_2506_02663_amd import amg as A  # noqa: E402
+from paper_2506_02663_amd import workloads as W  # noqa: E402
+
+OPTS = dict(precision=A.MIXED, smoother=A.SMOOTH_RB, tol_rel=1e-10, max_cycles=100)
+
+
+def single_level(n, bc, op, c):
+    H = A.Hierarchy(3, (n,) * 3, 1.0 / n, 1)
+    H.set_level_boxes(0, [((0,) * 3, (n - 1,) * 3)])
+    for d in range(3):
+        for s in (0, 1):
+            H.set_physical_bc(d, s, A.DIRICHLET if bc == "D" else A.NEUMANN)
+    H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c)
+    H.finalize()
+    return H
+
+
+@pytest.mark.parametrize("op,bc", [("helmholtz", "D"), ("poisson", "N")])
+def test_3d_256_solution_satisfies_oracle_system(op, bc):
+    n, nu = 256, 1e-4
+    h = 1.0 / n
+    c = 0.5 * nu * h if op == "helmholtz" else 0.0
+    shape = (n,) * 3
+    if op == "helmholtz":
+        f = (1.0 + 12 * math.pi ** 2 * c) * W.sinprod_avg(shape, h) + W.noise(shape, 0)
+    else:
+        f = -12 * math.pi ** 2 * W.cosprod_avg(shape, h) + W.noise(shape, 1)
+        f -= f.mean()
+    H = single_level(n, bc, op, c)
+    fd = torch.tensor(H.pack(0, 0, lambda i, b: f), device="cuda")
+    x = torch.zeros_like(fd)
+    st = H.solve(0, x, fd, None, A.default_opts(**OPTS))
+    assert st["status"] == 0 and st["converged"], st
+    lev = Level(shape, h, [((0,) * 3, (n - 1,) * 3)], {(d, s): bc for d in range(3) for s in (0, 1)})
+    xs = lev.zeros()
+    xs[lev.inner] = H.unpack(0, 0, x.cpu().numpy())[0]
+    fo = lev.zeros()
+    fo[lev.inner] = f
+    sing = lev.singular_components(op)
+    if sing:
+        fo, _ = mg.solvability_shift(lev, fo, None, sing)
+    r = fo - lev.apply(xs, op, c)
+    r0 = np.abs(fo[lev.mask]).max()
+    assert np.abs(r[lev.mask]).max() <= 2e-10 * r0, (np.abs(r[lev.mask]).max() / r0, st["cycles"])
+    # one operator application at full size, element by element
+    u = np.random.default_rng(3).normal(size=shape)
+    ud = torch.tensor(H.pack(0, 0, lambda i, b: u), device="cuda")
+    y = torch.zeros_like(ud)
+    H.apply_operator(0, ud, y)
+    uo = lev.zeros()
+    uo[lev.inner] = u
+    want = lev.apply(uo, op, c)[lev.inner]
+    got = H.unpack(0, 0, y.cpu().numpy())[0]
+    assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
+
+
+def test_batch_of_1024_boxes_satisfies_oracle_systems():
+    h = 1.0 / 256
+    c = 0.5 * 1e-3 * h
+    sides = W.batched_boxes(1024, seed=0)
+    fs = [W.batched_rhs(s, h, seed=i) for i, s in enumerate(sides)]
+    H = A.Hierarchy(2, (256, 256), h, 1)
+    boxes, x0 = [], 0
+    for s in sides:
+        boxes.append(((x0, 0), (x0 + s - 1, s - 1)))
+        x0 += s
+    H.set_isolated(0)
+    H.set_level_boxes(0, boxes)
+    for d in range(2):
+        for sd in (0, 1):
+            H.set_physical_bc(d, sd, A.DIRICHLET)
+    H.set_operator(A.HELMHOLTZ, c)
+    H.finalize()
+    fd = torch.tensor(H.pack(0, 0, lambda i, b: fs[i]), device="cuda")
+    x = torch.zeros_like(fd)
+    st = H.solve(0, x, fd, None, A.default_opts(**OPTS))
+    assert st["status"] == 0 and st["converged"], st
+    xs = H.unpack(0, 0, x.cpu().numpy())
+    r0 = max(np.abs(f).max() for f in fs)
+    sample = sorted(set(list(range(0, 1024, 32)) + [int(np.argmax(sides)), int(np.argmin(sides))]))
+    for i in sample:
+        s = sides[i]
+        lev = Level((s, s), h, [((0, 0), (s - 1, s - 1))], {(d, sd): "D" for d in range(2) for sd in (0, 1)})
+        xo, fo = lev.zeros(), lev.zeros()
+        xo[lev.inner] = xs[i]
+        fo[lev.inner] = fs[i]
+        r = fo - lev.apply(xo, "helmholtz", c)
+        assert np.abs(r[lev.mask]).max() <= 2e-10 * r0, (i, s)
