@@ -242,24 +242,19 @@ def main():
         traffic = None
         if dim == 3 and n == 256 and word == 4:
             traffic = measured_traffic(f"{args.smoother}_sweep_fp32_256cubed_counters.txt")
-        # the same kernel launched back to back (20 sweeps of amg_smooth on the
-        # finest depth of the Helmholtz system): the launches queue up on the
-        # stream, so the events bracket the kernel and not the host's
-        # launch gaps of the solve
+        # the same kernel launched 50 times back to back by the library
+        # (amg_time_sweep, HIP events on its stream around the batch): the
+        # events bracket the kernels, not the fills and launch gaps between
+        # them inside a solve
         _, H0, x0, f0 = systems[0]
         dt_ = torch.float32 if word == 4 else torch.float64
         u_ = (f0 * 1e-3).to(dt_)
         f_ = f0.to(dt_)
         t_ = torch.zeros_like(u_)
-        H0.timing(True)
-        H0.smooth(0, 0, u_, f_, t_, smoother=sm, nsweeps=2)  # warm
-        H0.timing_read(A.T_SWEEP, reset=True)
-        H0.smooth(0, 0, u_, f_, t_, smoother=sm, nsweeps=20)
-        torch.cuda.synchronize()
-        bcnt, btot = H0.timing_read(A.T_SWEEP, reset=True)
-        H0.timing(False)
+        H0.time_sweep(0, u_, f_, t_, smoother=sm, n=4)  # warm
+        bcnt = 50
+        bavg_s = H0.time_sweep(0, u_, f_, t_, smoother=sm, n=bcnt) / 1e3
         del u_, f_, t_
-        bavg_s = btot / bcnt / 1e3
         ach = bytes_launch / bavg_s / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
@@ -437,21 +432,22 @@ def bench_batched(args):
                    "precision": args.precision, "vcycle": "V(2,2)", "setup_s": setup_s},
     }
     if not args.no_timing:
-        H.timing(True)
-        for k in range(A.T_KINDS):
-            H.timing_read(k, reset=True)
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        H.timing(False)
-        cnt, tot = H.timing_read(A.T_SWEEP, reset=False)
-        avg_s = tot / cnt / 1e3
+        # the finest sweep over all 1024 boxes, 50 launches back to back
+        # between HIP events on the library's stream (amg_time_sweep)
         word = 4 if prec == A.MIXED else 8
+        dt_ = torch.float32 if word == 4 else torch.float64
+        u_ = (fd * 1e-3).to(dt_)
+        f_ = fd.to(dt_)
+        t_ = torch.zeros_like(u_)
+        H.time_sweep(0, u_, f_, t_, smoother=sm, n=4)
+        cnt = 50
+        avg_s = H.time_sweep(0, u_, f_, t_, smoother=sm, n=cnt) / 1e3
+        del u_, f_, t_
         bytes_launch = (3 if args.smoother == "jacobi" else 2) * word * ncell
         ach = bytes_launch / avg_s / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                           "kernel": f"{args.smoother} sweep, finest depth, all 1024 boxes in one launch",
+                           "kernel": f"{args.smoother} {'half-' if args.smoother == 'rb' else ''}sweep, finest depth, all 1024 boxes in one launch",
                            "avg_us": avg_s * 1e6, "launches": cnt, "bytes_per_launch": bytes_launch}
     if base is not None:
         out["cpu_baseline"] = base

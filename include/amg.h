@@ -393,6 +393,15 @@ int amg_set_coefficient(amg_hier* h, double c);
  * and accumulates their durations; creates the event pool on first use. */
 int amg_timing_enable(amg_hier* h, int on);
 
+/* Measurement of the dominant kernel: the finest-depth smoothing kernel of
+ * `level` (one Jacobi sweep, or one red-black half-sweep alternating the
+ * colours) launched n times back to back on the stream, u and tmp swapping
+ * roles, with no ghost fill in between, bracketed by two HIP events;
+ * *avg_ms = elapsed / n.  The values written are not a smoothing result
+ * (ghosts are not refilled): for timing only.  u != tmp. */
+int amg_time_sweep(amg_hier* h, int level, int dtype, int smoother, int n, void* u, const void* f, void* tmp,
+                   double* avg_ms, void* stream);
+
 /* Launch count and summed duration (ms) of kernel kind `kind` since the last
  * reset; reset != 0 clears the counters after reading.  Launches made by the
  * step-level calls (amg_smooth, ...) are waited for and collected first. */

@@ -107,6 +107,7 @@ def lib():
         L.amg_solve_adjoint_composite.argtypes = [vp, i32, pp, pp, C.POINTER(SolveOpts), C.POINTER(SolveStats), vp]
         L.amg_composite_residual_adjoint.argtypes = [vp, i32, pp, pp, pp, vp]
         L.amg_composite_laplacian.argtypes = [vp, i32, pp, pp, pp, vp]
+        L.amg_time_sweep.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, C.POINTER(C.c_double), vp]
         _lib = L
     return _lib
 
@@ -380,6 +381,16 @@ class Hierarchy:
         self._need(f, level, last, "f")
         self._need(e, level, last, "e", (f.dtype,))
         self._check(lib().amg_bottom(self.h, level, self._dt(f), _ptr(f), _ptr(e), _stream()))
+
+    def time_sweep(self, level, u, f, tmp, smoother=SMOOTH_JACOBI, n=50):
+        """Average duration (ms) of the finest-depth smoothing kernel launched
+        n times back to back (values meaningless: timing only)."""
+        for t, nm in ((u, "u"), (f, "f"), (tmp, "tmp")):
+            self._need(t, level, 0, nm, (u.dtype,))
+        ms = C.c_double()
+        self._check(lib().amg_time_sweep(self.h, level, self._dt(u), smoother, int(n), _ptr(u), _ptr(f), _ptr(tmp),
+                                         C.byref(ms), _stream()))
+        return ms.value
 
     def timing(self, on=True):
         self._check(lib().amg_timing_enable(self.h, int(on)))

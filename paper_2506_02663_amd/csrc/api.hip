@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "amg_internal.h"
@@ -144,10 +145,10 @@ void collect_timing(Timer& t) {
 }
 
 // per-component sums of the tile partials in L.partial (two fixed-order stages)
-void comp_sums(const Run& R, const Depth& D, double* out) {
+void comp_sums(const Run& R, const Depth& D, double* out, const double* in = nullptr) {
   Level& L = *R.L;
   const int nseg = (int)D.seg_ptr.size() - 1;
-  launch_seg_reduce(L.partial, D.d_seg, nseg, 0, L.partial2, false, R.st);
+  launch_seg_reduce(in ? in : L.partial, D.d_seg, nseg, 0, L.partial2, false, R.st);
   launch_seg_reduce(L.partial2, D.d_cseg, L.ncomp, 0, out, false, R.st);
 }
 
@@ -165,6 +166,13 @@ void remove_mean(const Run& R, int k, T* a) {
   Level& L = *R.L;
   if (!L.nsingular) return;
   Depth& D = L.depths[k];
+  // small depths: one launch, one block per component
+  int64_t maxc = 0;
+  for (int c = 0; c < L.ncomp; ++c) maxc = std::max<int64_t>(maxc, L.comp_cells[c] >> (R.dim * k));
+  if (maxc <= 16384 && D.boxes.size() <= 64) {
+    launch_comp_mean_small<T>(R.dim, D, L.ncomp, L.d_comp_flag, L.d_comp_cnt + (size_t)k * L.ncomp, a, R.st);
+    return;
+  }
   launch_tile_sum<T>(R.dim, D, a, L.partial, R.st);
   comp_sums(R, D, L.comp_sum);
   launch_comp_delta(L.comp_sum, nullptr, L.d_comp_flag, L.d_comp_cnt + (size_t)k * L.ncomp, L.ncomp, 1.0, 0.0,
@@ -238,10 +246,7 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0) {
   for (int k = 0; k < K; ++k) {
     Depth& D = L.depths[k];
     // boxes that end here: exact solve, written to both buffers of the depth
-    if (!D.groups.empty()) {
-      launch_bottom<T>(D, L.d_mat, L.d_idx, f[k], cur[k], R.tr, R.st);
-      launch_bottom<T>(D, L.d_mat, L.d_idx, f[k], oth[k], R.tr, R.st);
-    }
+    if (!D.groups.empty()) launch_bottom<T>(D, L.d_mat, L.d_idx, f[k], cur[k], R.tr, R.st, oth[k]);
     if (k + 1 >= K || D.stiles.empty()) break;
     smooth<T>(R, k, o.smoother, o.nu1, o.omega, true, cur[k], oth[k], f[k]);
     T alpha, beta;
@@ -682,7 +687,7 @@ int amg_finalize(amg_hier* H) {
     }
     TRY(zalloc(H, &L.r64, L.depths[0].nstored));
     TRY(zalloc(H, &L.fsh, L.depths[0].nstored));
-    TRY(zalloc(H, &L.partial, maxpart));
+    TRY(zalloc(H, &L.partial, 2 * maxpart));  // per-tile max and per-tile sum of a residual
     TRY(zalloc(H, &L.partial2, maxseg));
     TRY(zalloc(H, &L.comp_sum, L.ncomp));
     TRY(zalloc(H, &L.d_delta, L.ncomp));
@@ -1154,17 +1159,33 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
     stats->history[0] = r0;
   }
   // one outer cycle: r -> V-cycle -> x += s e -> new residual and its norm
+  // per-component means of the residual: from the per-tile sums the
+  // residual kernel wrote next to its maxima (the transposed residual has
+  // none: a separate sum pass)
+  auto residual_mean = [&]() {
+    if (tr) {
+      launch_tile_sum<double>(dim, D0, Rb, L.partial, R.st);
+      comp_sums(R, D0, L.comp_sum);
+    } else {
+      comp_sums(R, D0, L.comp_sum, L.partial + D0.tiles.size());
+    }
+    launch_comp_delta(L.comp_sum, nullptr, L.d_comp_flag, L.d_comp_cnt, L.ncomp, 1.0, 0.0, L.d_delta, nullptr, R.st);
+  };
+  // The solution's mean on singular components does not change the
+  // residual (the operator annihilates constants), so it is removed once
+  // after the loop rather than after every cycle.
   auto body = [&]() {
-    remove_mean<double>(R, 0, Rb);
+    if (L.nsingular) residual_mean();
     if (mixed) {
-      launch_to32(dim, D0, Rb, D0.f32, L.scal + S_NORM, R.st);
+      // the mean removal fused into the FP32 conversion
+      launch_to32(dim, D0, Rb, D0.f32, L.scal + S_NORM, R.st, L.nsingular ? L.d_delta : nullptr);
       float* e = vcycle<float>(R, o, D0.f32, D0.e32, D0.t32);
       launch_update<float>(dim, D0, X, e, L.scal + S_NORM, R.st);
     } else {
+      if (L.nsingular) launch_comp_shift<double>(dim, D0, Rb, L.d_delta, R.st);
       double* e = vcycle<double>(R, o, D0.f64, D0.e64, D0.t64);
       launch_update<double>(dim, D0, X, e, L.scal + S_ONE, R.st);
     }
-    remove_mean<double>(R, 0, X);
     residual_norm();
   };
   // the cycle is captured once into a HIP graph and replayed
@@ -1227,6 +1248,7 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
     stats->used_graph = use_graph && cycles > 0;
   }
   if (H->timer.on) collect_timing(H->timer);
+  remove_mean<double>(R, 0, X);
   if (tr) {  // the adjoint solution as a gradient: zero outside the cells
     launch_fill_zero<double>(D0, X, R.st);
     HIPCHK(hipGetLastError());
@@ -1583,6 +1605,46 @@ int amg_project(amg_hier* Hw, amg_hier* Hp, int lev_lo, int lev_hi, double* cons
     rc = level_solve(Hp, lev_lo, phi[lev_lo], f[lev_lo], nullptr, o, stats, st, false);
   if (rc != AMG_OK) return rc;
   return gradient_impl(Hp, lev_lo, lev_hi, phi, nullptr, u, w, st);
+}
+
+int amg_time_sweep(amg_hier* H, int level, int dtype, int smoother, int n, void* u, const void* f, void* tmp,
+                   double* avg_ms, void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!u || !f || !tmp || !avg_ms || n < 1 || u == tmp) return fail(H, AMG_EINVAL, "bad arguments");
+  if (smoother != AMG_SMOOTH_JACOBI && smoother != AMG_SMOOTH_RB) return fail(H, AMG_EINVAL, "bad smoother");
+  Level& L = H->levels[level];
+  Depth& D = L.depths[0];
+  hipStream_t st = stream_of(H, stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+  HIPCHK(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+  auto run = [&](auto* cur, auto* oth, const auto* ff) {
+    using T = std::remove_const_t<std::remove_pointer_t<decltype(ff)>>;
+    T a, b;
+    coefs<T>(H, D, a, b);
+    (void)hipEventRecord(e0, st);
+    for (int i = 0; i < n; ++i) {
+      if (smoother == AMG_SMOOTH_JACOBI)
+        launch_jacobi<T>(H->dim, D, cur, ff, oth, a, b, T(2.0 / 3.0), false, st);
+      else
+        launch_rb<T>(H->dim, D, cur, ff, oth, a, b, i & 1, false, st);
+      std::swap(cur, oth);
+    }
+    (void)hipEventRecord(e1, st);
+  };
+  if (dtype == AMG_F64)
+    run((double*)u, (double*)tmp, (const double*)f);
+  else
+    run((float*)u, (float*)tmp, (const float*)f);
+  hipError_t err = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(err);
+  HIPCHK(hipGetLastError());
+  *avg_ms = (double)ms / n;
+  return AMG_OK;
 }
 
 int amg_timing_enable(amg_hier* H, int on) {

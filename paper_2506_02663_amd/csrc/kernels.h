@@ -43,7 +43,8 @@ void launch_restrict(int dim, const Depth& F, const Depth& C, const T* r, T* fc,
 template <typename T>
 void launch_prolong(int dim, const Depth& F, const Depth& C, const T* ec, T* u, hipStream_t st);
 template <typename T>
-void launch_bottom(const Depth& D, const double* mats, const int64_t* idx, const T* f, T* e, bool tr, hipStream_t st);
+void launch_bottom(const Depth& D, const double* mats, const int64_t* idx, const T* f, T* e, bool tr, hipStream_t st,
+                   T* e2 = nullptr);
 template <typename T>
 void launch_tile_sum(int dim, const Depth& D, const T* a, double* part, hipStream_t st);
 template <typename T>
@@ -58,6 +59,10 @@ void launch_comp_delta(const double* sum, const double* bsum, const int32_t* fla
 template <typename T>
 void launch_comp_shift(int dim, const Depth& D, T* a, const double* delta, hipStream_t st);
 void launch_chunk_fdsum(const Depth& D, const double* fd, const uint8_t* valid, double* part, hipStream_t st);
+// per-component mean removal of a small depth in one launch (one block per component)
+template <typename T>
+void launch_comp_mean_small(int dim, const Depth& D, int ncomp, const int32_t* flag, const double* cnt, T* a,
+                            hipStream_t st);
 void launch_cf_delta(const double* defect, const int32_t* flag, const double* ncf, const double* cnt, int ncomp,
                      double hD, double hD1, double* delta, double* dfd, hipStream_t st);
 void launch_fd_correct(const Depth& D, const double* fd, const double* dfd, double* out, hipStream_t st);
@@ -84,7 +89,9 @@ template <typename T>
 void launch_update2(int dim, const Depth& D, double* x, double* E, const T* e, const double* scal, hipStream_t st);
 template <typename T>
 void launch_update(int dim, const Depth& D, double* x, const T* e, const double* scal, hipStream_t st);
-void launch_to32(int dim, const Depth& D, const double* r, float* r32, const double* scal, hipStream_t st);
+// r32 = (r - delta[component]) / scal[0] (delta may be NULL)
+void launch_to32(int dim, const Depth& D, const double* r, float* r32, const double* scal, hipStream_t st,
+                 const double* delta = nullptr);
 void launch_shift_copy(int dim, const Depth& D, const double* f, double* out, const double* delta, hipStream_t st);
 void launch_set_scale(const double* src, double* dst, hipStream_t st);
 void launch_set_scaled(const double* src, double f, double* dst, hipStream_t st);

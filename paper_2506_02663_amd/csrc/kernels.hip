@@ -73,9 +73,8 @@ struct Column {
 };
 
 template <int DIM>
-__device__ __forceinline__ Column column_of(const TileD& t, const BoxD& b) {
+__device__ __forceinline__ Column column_at(const TileD& t, const BoxD& b, int tid) {
   Column c;
-  const int tid = threadIdx.x;
   c.x = t.x0 + 2 * (DIM == 2 ? tid : (tid & 63));
   c.y = DIM == 2 ? 0 : t.y0 + (tid >> 6);
   c.ok = c.x < b.n[0] && (DIM == 2 || c.y < b.n[1]);
@@ -85,6 +84,11 @@ __device__ __forceinline__ Column column_of(const TileD& t, const BoxD& b) {
   c.sm = b.s[DIM - 1];
   c.base = b.off + (c.x + 2) + (DIM == 3 ? (int64_t)(c.y + 2) * b.s[1] : 0);
   return c;
+}
+
+template <int DIM>
+__device__ __forceinline__ Column column_of(const TileD& t, const BoxD& b) {
+  return column_at<DIM>(t, b, (int)threadIdx.x);
 }
 
 // One x-column per thread over the same tiles (blocks of 128 threads in 2D,
@@ -276,7 +280,7 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
   const TileD t = tiles[ti];
   const BoxD b = boxes[t.box];
   const Column C = column1_of<DIM>(t, b);
-  double vmax = 0.0;
+  double vmax = 0.0, vsum = 0.0;
   if (C.ok) {
     const int64_t sm = C.sm;
     int64_t c = C.base + (int64_t)(C.p0 + 2) * sm;
@@ -299,6 +303,7 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
         if (PART) {
           double av = fabs((double)v);
           vmax = fmax(vmax, (av == av) ? av : (double)INFINITY);  // a NaN must not vanish in fmax
+          vsum += (double)v;
         }
       } else if (OP == OP_JACOBI || (((par0 + p) & 1) == col)) {
         out[c] = q2 + (OP == OP_JACOBI ? omega : T(1)) * (f[c] - Au) *
@@ -314,7 +319,12 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
   }
   if (PART) {
     const double m = block_max<double>(vmax, sh);
-    if (threadIdx.x == 0) part[ti] = m;
+    __syncthreads();
+    const double sm = block_sum<double>(vsum, sh);
+    if (threadIdx.x == 0) {
+      part[ti] = m;
+      part[ntiles + ti] = sm;
+    }
   }
 }
 
@@ -356,7 +366,7 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
     d1.init(b, codes, C.x + 1, C.y, alpha, beta, C.ok1);
   }
   const int par0 = (b.lo[0] + C.x + (DIM == 3 ? b.lo[1] + C.y : 0) + b.lo[DIM - 1]) & 1;
-  double vmax = 0.0;
+  double vmax = 0.0, vsum = 0.0;
   T acc = T(0);
   for (int p = C.p0; p < C.p1; ++p, c += sm) {
     if (has) q4 = ld2(u + c + 2 * sm);
@@ -391,6 +401,7 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
           a0 = (a0 == a0) ? a0 : (double)INFINITY;  // a NaN must not vanish in fmax
           a1 = (a1 == a1) ? a1 : (double)INFINITY;
           vmax = fmax(vmax, fmax(a0, a1));
+          vsum += (double)o0 + (C.ok1 ? (double)o1 : 0.0);
         }
       } else {
         const int cy = DIM == 2 ? p : C.y, cz = DIM == 2 ? 0 : p;
@@ -432,7 +443,12 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
   }
   if (PART) {
     const double m = block_max<double>(vmax, sh);
-    if (threadIdx.x == 0) part[ti] = m;
+    __syncthreads();
+    const double sm = block_sum<double>(vsum, sh);
+    if (threadIdx.x == 0) {
+      part[ti] = m;
+      part[ntiles + ti] = sm;
+    }
   }
 }
 
@@ -501,15 +517,17 @@ __global__ void __launch_bounds__(256) k_update(const TileD* __restrict__ tiles,
 template <int DIM>
 __global__ void __launch_bounds__(256) k_to32(const TileD* __restrict__ tiles, int ntiles,
                                               const BoxD* __restrict__ boxes, const double* __restrict__ r,
-                                              float* __restrict__ r32, const double* __restrict__ scal) {
+                                              float* __restrict__ r32, const double* __restrict__ scal,
+                                              const double* __restrict__ delta) {
   const double inv = 1.0 / scal[0];
   FOR_COLUMN(DIM) {
+    const double dv = delta ? delta[b.comp] : 0.0;
     const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
     if (C.ok1) {
       const Pair<double> rv = ld2(r + c);
-      st2(r32 + c, (float)(rv.a * inv), (float)(rv.b * inv));
+      st2(r32 + c, (float)((rv.a - dv) * inv), (float)((rv.b - dv) * inv));
     } else {
-      r32[c] = (float)(r[c] * inv);
+      r32[c] = (float)((r[c] - dv) * inv);
     }
   }
 }
@@ -525,6 +543,43 @@ __global__ void __launch_bounds__(256) k_comp_shift(const TileD* __restrict__ ti
     const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
     a[c] = (T)((double)a[c] - d);
     if (C.ok1) a[c + 1] = (T)((double)a[c + 1] - d);
+  }
+}
+
+// Per-component mean removal of a small depth in one launch: one block per
+// component walks the cells of the component's boxes in a fixed order,
+// sums, and subtracts sum / cells on singular components.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(1024) k_comp_mean_small(int nboxes, const BoxD* __restrict__ boxes,
+                                                          const int32_t* __restrict__ flag,
+                                                          const double* __restrict__ cnt, T* __restrict__ a) {
+  __shared__ double sh[16];
+  __shared__ double mean;
+  const int comp = blockIdx.x;
+  if (!flag[comp]) return;
+  double v = 0.0;
+  for (int bi = 0; bi < nboxes; ++bi) {
+    const BoxD b = boxes[bi];
+    if (b.comp != comp) continue;
+    const int n = b.n[0] * b.n[1] * (DIM == 3 ? b.n[2] : 1);
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) {
+      const int x = i % b.n[0], r = i / b.n[0];
+      v += (double)a[cell_index<DIM>(b, x, DIM == 3 ? r % b.n[1] : r, DIM == 3 ? r / b.n[1] : 0)];
+    }
+  }
+  v = block_sum<double>(v, sh);
+  if (threadIdx.x == 0) mean = v / cnt[comp];
+  __syncthreads();
+  const double m = mean;
+  for (int bi = 0; bi < nboxes; ++bi) {
+    const BoxD b = boxes[bi];
+    if (b.comp != comp) continue;
+    const int n = b.n[0] * b.n[1] * (DIM == 3 ? b.n[2] : 1);
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) {
+      const int x = i % b.n[0], r = i / b.n[0];
+      const int64_t c = cell_index<DIM>(b, x, DIM == 3 ? r % b.n[1] : r, DIM == 3 ? r / b.n[1] : 0);
+      a[c] = (T)((double)a[c] - m);
+    }
   }
 }
 
@@ -683,7 +738,7 @@ __global__ void __launch_bounds__(256) k_fill(const ChunkD* __restrict__ chunks,
 template <typename T, bool TR>
 __global__ void __launch_bounds__(256) k_bottom(const BottomGroupD* __restrict__ groups,
                                                 const double* __restrict__ mats, const int64_t* __restrict__ idx,
-                                                const T* __restrict__ f, T* __restrict__ e) {
+                                                const T* __restrict__ f, T* __restrict__ e, T* __restrict__ e2) {
   constexpr int NI = 8, KC = 512;
   __shared__ double xs[NI][KC];
   const BottomGroupD G = groups[blockIdx.y];
@@ -704,6 +759,7 @@ __global__ void __launch_bounds__(256) k_bottom(const BottomGroupD* __restrict__
       }
       __syncthreads();
       if (r < G.n) {
+#pragma unroll 8
         for (int k = 0; k < kc; ++k) {
           const double m = TR ? M[(int64_t)r * G.n + k0 + k] : M[(int64_t)(k0 + k) * G.n + r];
 #pragma unroll
@@ -712,7 +768,11 @@ __global__ void __launch_bounds__(256) k_bottom(const BottomGroupD* __restrict__
       }
     }
     if (r < G.n)
-      for (int i = 0; i < ni; ++i) e[idx[G.idx + (int64_t)(i0 + i) * G.n + r]] = (T)acc[i];
+      for (int i = 0; i < ni; ++i) {
+        const int64_t q = idx[G.idx + (int64_t)(i0 + i) * G.n + r];
+        e[q] = (T)acc[i];
+        if (e2) e2[q] = (T)acc[i];
+      }
   }
 }
 
@@ -1496,15 +1556,15 @@ void launch_prolong(int dim, const Depth& F, const Depth& C, const T* ec, T* u, 
 
 template <typename T>
 void launch_bottom(const Depth& D, const double* mats, const int64_t* idx, const T* f, T* e, bool tr,
-                   hipStream_t st) {
+                   hipStream_t st, T* e2) {
   if (D.groups.empty()) return;
   int maxn = 0;
   for (auto& g : D.groups) maxn = std::max(maxn, g.n);
   const dim3 grid((maxn + 255) / 256, (unsigned)D.groups.size());
   if (tr)
-    hipLaunchKernelGGL((k_bottom<T, true>), grid, dim3(256), 0, st, D.d_groups, mats, idx, f, e);
+    hipLaunchKernelGGL((k_bottom<T, true>), grid, dim3(256), 0, st, D.d_groups, mats, idx, f, e, e2);
   else
-    hipLaunchKernelGGL((k_bottom<T, false>), grid, dim3(256), 0, st, D.d_groups, mats, idx, f, e);
+    hipLaunchKernelGGL((k_bottom<T, false>), grid, dim3(256), 0, st, D.d_groups, mats, idx, f, e, e2);
 }
 
 template <typename T>
@@ -1556,6 +1616,20 @@ void launch_comp_shift(int dim, const Depth& D, T* a, const double* delta, hipSt
   else
     hipLaunchKernelGGL((k_comp_shift<T, 3>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, a, delta);
 }
+
+template <typename T>
+void launch_comp_mean_small(int dim, const Depth& D, int ncomp, const int32_t* flag, const double* cnt, T* a,
+                            hipStream_t st) {
+  if (D.tiles.empty() || ncomp <= 0) return;
+  const int nb = (int)D.boxes.size();
+  if (dim == 2)
+    hipLaunchKernelGGL((k_comp_mean_small<T, 2>), dim3(ncomp), dim3(1024), 0, st, nb, D.d_box, flag, cnt, a);
+  else
+    hipLaunchKernelGGL((k_comp_mean_small<T, 3>), dim3(ncomp), dim3(1024), 0, st, nb, D.d_box, flag, cnt, a);
+}
+template void launch_comp_mean_small<float>(int, const Depth&, int, const int32_t*, const double*, float*, hipStream_t);
+template void launch_comp_mean_small<double>(int, const Depth&, int, const int32_t*, const double*, double*,
+                                             hipStream_t);
 
 void launch_cf_delta(const double* defect, const int32_t* flag, const double* ncf, const double* cnt, int ncomp,
                      double hD, double hD1, double* delta, double* dfd, hipStream_t st) {
@@ -1713,10 +1787,11 @@ void launch_update(int dim, const Depth& D, double* x, const T* e, const double*
     hipLaunchKernelGGL((k_update<T, 3>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, x, e, scal);
 }
 
-void launch_to32(int dim, const Depth& D, const double* r, float* r32, const double* scal, hipStream_t st) {
+void launch_to32(int dim, const Depth& D, const double* r, float* r32, const double* scal, hipStream_t st,
+                 const double* delta) {
   const size_t n = D.tiles.size();
   if (!n) return;
-  DISPATCH_DIM(dim, k_to32, D.d_tiles, (int)n, D.d_box, r, r32, scal);
+  DISPATCH_DIM(dim, k_to32, D.d_tiles, (int)n, D.d_box, r, r32, scal, delta);
 }
 
 void launch_shift_copy(int dim, const Depth& D, const double* f, double* out, const double* delta, hipStream_t st) {
@@ -1750,7 +1825,7 @@ void launch_zero(T* a, int64_t n, hipStream_t st) {
                                          hipStream_t);                                                            \
   template void launch_restrict<T>(int, const Depth&, const Depth&, const T*, T*, hipStream_t);                   \
   template void launch_prolong<T>(int, const Depth&, const Depth&, const T*, T*, hipStream_t);                    \
-  template void launch_bottom<T>(const Depth&, const double*, const int64_t*, const T*, T*, bool, hipStream_t);   \
+  template void launch_bottom<T>(const Depth&, const double*, const int64_t*, const T*, T*, bool, hipStream_t, T*); \
   template void launch_tile_sum<T>(int, const Depth&, const T*, double*, hipStream_t);                            \
   template void launch_tile_absmax<T>(int, const Depth&, const T*, double*, hipStream_t);                         \
   template void launch_comp_shift<T>(int, const Depth&, T*, const double*, hipStream_t);                          \
