@@ -37,6 +37,7 @@ def parse():
     p.add_argument("--n", type=int, default=0, help="cells per direction (default: the workload's)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-timing", action="store_true", help="skip the per-kernel event timing")
+    p.add_argument("--no-autotune", action="store_true", help="keep the default tile march length")
     p.add_argument("--copy-probe", action="store_true",
                    help="first run a plain 256 MiB device copy three times (the reference kernel that "
                         "calibrates the HBM byte counters)")
@@ -152,6 +153,7 @@ def main():
     sm = A.SMOOTH_JACOBI if args.smoother == "jacobi" else A.SMOOTH_RB
     opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100)
     systems = []
+    march = None
     for op, bc, f in probs:
         H = A.Hierarchy(dim, (n,) * dim, h, 1)
         H.set_level_boxes(0, [((0,) * dim, (n - 1,) * dim)])
@@ -159,6 +161,11 @@ def main():
             for s in (0, 1):
                 H.set_physical_bc(d, s, A.DIRICHLET if bc == "D" else A.NEUMANN)
         H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c)
+        if not args.no_autotune:
+            # tile march length of the finest sweep, timed once (setup, untimed)
+            if march is None:
+                march, _ = H.autotune(0, A.F32 if prec == A.MIXED else A.F64, sm)
+            H.set_tuning(A.TUNE_MARCH2 if dim == 2 else A.TUNE_MARCH3, march)
         H.finalize()
         fd = torch.tensor(H.pack(0, 0, lambda i, b: f), device="cuda")
         x = torch.zeros_like(fd)
@@ -218,7 +225,7 @@ def main():
         "config": {"workload": f"{dim}D single level {n}^{dim}, Helmholtz (Dirichlet, nu={nu}) + Neumann Poisson",
                    "cells": n ** dim, "dof_per_step": dof_step, "tol_rel": 1e-10,
                    "cycles": cycles, "smoother": args.smoother, "precision": args.precision,
-                   "vcycle": "V(2,2)"},
+                   "vcycle": "V(2,2)", "march": march},
     }
     if not args.no_timing:
         # dominant kernel: the smoothing sweep on the finest depth

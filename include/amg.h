@@ -402,6 +402,14 @@ int amg_timing_enable(amg_hier* h, int on);
 int amg_time_sweep(amg_hier* h, int level, int dtype, int smoother, int n, void* u, const void* f, void* tmp,
                    double* avg_ms, void* stream);
 
+/* Autotuning of the tile march length (cells a tile marches along the last
+ * direction, AMG_TUNE_MARCH2/3) before amg_finalize: for each candidate
+ * (8, 16, 32, 64, 128) a finalized copy of the layout times the finest-depth
+ * smoothing kernel of `level` (amg_time_sweep, nreps launches, zero data);
+ * the fastest candidate is set on h.  *best, *best_ms (may be NULL) receive
+ * it and its time per launch.  Allocates and frees device memory. */
+int amg_autotune(amg_hier* h, int level, int dtype, int smoother, int nreps, int* best, double* best_ms);
+
 /* Launch count and summed duration (ms) of kernel kind `kind` since the last
  * reset; reset != 0 clears the counters after reading.  Launches made by the
  * step-level calls (amg_smooth, ...) are waited for and collected first. */

@@ -108,6 +108,7 @@ def lib():
         L.amg_composite_residual_adjoint.argtypes = [vp, i32, pp, pp, pp, vp]
         L.amg_composite_laplacian.argtypes = [vp, i32, pp, pp, pp, vp]
         L.amg_time_sweep.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, C.POINTER(C.c_double), vp]
+        L.amg_autotune.argtypes = [vp, i32, i32, i32, i32, C.POINTER(C.c_int), C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -186,6 +187,13 @@ class Hierarchy:
 
     def set_tuning(self, key, value):
         self._check(lib().amg_set_tuning(self.h, key, int(value)))
+
+    def autotune(self, level=0, dtype=F32, smoother=SMOOTH_RB, nreps=20):
+        """Pick the tile march length by timing the finest sweep (before finalize)."""
+        best = C.c_int()
+        ms = C.c_double()
+        self._check(lib().amg_autotune(self.h, level, dtype, smoother, nreps, C.byref(best), C.byref(ms)))
+        return best.value, ms.value
 
     def finalize(self):
         self._check(lib().amg_finalize(self.h))

@@ -1647,6 +1647,63 @@ int amg_time_sweep(amg_hier* H, int level, int dtype, int smoother, int n, void*
   return AMG_OK;
 }
 
+int amg_autotune(amg_hier* H, int level, int dtype, int smoother, int nreps, int* best, double* best_ms) {
+  if (!H) return AMG_EINVAL;
+  if (H->finalized) return fail(H, AMG_EINVAL, "autotuning runs before amg_finalize");
+  if (level < 0 || level >= H->nlevels || nreps < 1) return fail(H, AMG_EINVAL, "bad arguments");
+  const int cands[] = {8, 16, 32, 64, 128};
+  int arg = H->dim == 2 ? H->march2 : H->march3;
+  double tbest = 1e300;
+  for (int m : cands) {
+    // a finalized copy of the layout with march length m
+    amg_hier* T = nullptr;
+    int rc = amg_create(H->dim, H->base, H->h0, H->ratio, H->nlevels, &T);
+    if (rc != AMG_OK) return fail(H, rc, "autotune: amg_create failed");
+    for (int l = 0; l < H->nlevels && rc == AMG_OK; ++l) {
+      T->levels[l].boxes = H->levels[l].boxes;
+      T->levels[l].isolated = H->levels[l].isolated;
+      T->levels[l].cf_mode = H->levels[l].cf_mode;
+    }
+    memcpy(T->phys_bc, H->phys_bc, sizeof H->phys_bc);
+    T->op = H->op;
+    T->c = H->c;
+    T->row_align = H->row_align;
+    T->march2 = T->march3 = m;
+    rc = amg_finalize(T);
+    if (rc != AMG_OK) {
+      const std::string e = T->err;
+      amg_destroy(T);
+      return fail(H, rc, "autotune: " + e);
+    }
+    const size_t bytes = T->levels[level].depths[0].nstored * (dtype == AMG_F64 ? 8 : 4);
+    void *u = nullptr, *f = nullptr, *t = nullptr;
+    hipError_t e = hipMalloc(&u, bytes);
+    if (e == hipSuccess) e = hipMalloc(&f, bytes);
+    if (e == hipSuccess) e = hipMalloc(&t, bytes);
+    if (e == hipSuccess) e = hipMemset(u, 0, bytes);
+    if (e == hipSuccess) e = hipMemset(f, 0, bytes);
+    double ms = 0.0;
+    if (e == hipSuccess) {
+      rc = amg_time_sweep(T, level, dtype, smoother, 4, u, f, t, &ms, nullptr);
+      if (rc == AMG_OK) rc = amg_time_sweep(T, level, dtype, smoother, nreps, u, f, t, &ms, nullptr);
+    }
+    for (void* p : {u, f, t})
+      if (p) (void)hipFree(p);
+    const std::string terr = T->err;
+    amg_destroy(T);
+    if (e != hipSuccess) return fail(H, AMG_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+    if (rc != AMG_OK) return fail(H, rc, "autotune: " + terr);
+    if (ms < tbest) {
+      tbest = ms;
+      arg = m;
+    }
+  }
+  (H->dim == 2 ? H->march2 : H->march3) = arg;
+  if (best) *best = arg;
+  if (best_ms) *best_ms = tbest;
+  return AMG_OK;
+}
+
 int amg_timing_enable(amg_hier* H, int on) {
   if (!H) return AMG_EINVAL;
   H->timer.on = on != 0;

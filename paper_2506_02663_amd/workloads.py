@@ -113,3 +113,82 @@ def amr_two_level_boxes():
     at (0.5, 0.5) or the disk of radius 0.08 at (0.8, 0.2) (56 boxes, two
     face-connected components)."""
     return [[((0, 0), (255, 255))], disk_boxes([((0.5, 0.5), 0.25), ((0.8, 0.2), 0.08)], 512, 32)]
+
+
+# ----------------------------------------------------------------------------
+# three-level vortex workload
+def _tag_boxes(centres, radius, n, bs):
+    """bs^2 boxes of the n^2 grid on [0,1]^2 whose centre lies within radius
+    of one of the centres; as a set of (bi, bj) box indices."""
+    hb = bs / n
+    out = set()
+    for bj in range(n // bs):
+        for bi in range(n // bs):
+            cx, cy = (bi + 0.5) * hb, (bj + 0.5) * hb
+            if any((cx - x) ** 2 + (cy - y) ** 2 <= radius * radius for x, y in centres):
+                out.add((bi, bj))
+    return out
+
+
+def vortex_centres(seed=0):
+    rng = np.random.default_rng(seed)
+    return [tuple(rng.uniform(0.3, 0.7, size=2)) for _ in range(2)]
+
+
+def three_level_vortex_boxes(seed=0, base=512, bs=64, r1=0.15, r2=0.075, buffer=4):
+    """Level 0: one base^2 box on [0,1]^2.  Level 1 (2 base)^2 and level 2
+    (4 base)^2: the bs^2 boxes whose centre lies within r1 / r2 of one of two
+    seeded vortex centres (uniform in [0.3, 0.7]^2), level 1 grown so that it
+    covers the parent cells of every level-2 box plus `buffer` level-1 cells
+    around them (room for the coarse-fine interpolation windows)."""
+    centres = vortex_centres(seed)
+    n1, n2 = 2 * base, 4 * base
+    l2 = _tag_boxes(centres, r2, n2, bs)
+    l1 = _tag_boxes(centres, r1, n1, bs)
+    for bi, bj in l2:
+        lo = (bi * bs // 2 - buffer, bj * bs // 2 - buffer)
+        hi = ((bi + 1) * bs // 2 - 1 + buffer, (bj + 1) * bs // 2 - 1 + buffer)
+        for ci in range(max(lo[0], 0) // bs, min(hi[0], n1 - 1) // bs + 1):
+            for cj in range(max(lo[1], 0) // bs, min(hi[1], n1 - 1) // bs + 1):
+                l1.add((ci, cj))
+
+    def boxes(tags):
+        return [((bi * bs, bj * bs), (bi * bs + bs - 1, bj * bs + bs - 1)) for bi, bj in sorted(tags)]
+    return [[((0, 0), (base - 1, base - 1))], boxes(l1), boxes(l2)], centres
+
+
+def lamb_oseen_avg(centres, lo, n, h, circ=(1.0, -1.0), sigma=0.05, order=3):
+    """Cell averages (Gauss-Legendre, order^2 points per cell) of the velocity
+    of Lamb-Oseen vortices of circulations circ at the centres, on the n[0] x
+    n[1] cells starting at index lo with cell size h.  Returns (u, v) indexed
+    [x, y]."""
+    g, w = np.polynomial.legendre.leggauss(order)
+    g, w = 0.5 * (g + 1.0), 0.5 * w
+    xs = (lo[0] + np.arange(n[0]))[:, None] * h
+    ys = (lo[1] + np.arange(n[1]))[None, :] * h
+    u = np.zeros(n)
+    v = np.zeros(n)
+    for a, wa in zip(g, w):
+        for b, wb in zip(g, w):
+            x = xs + a * h
+            y = ys + b * h
+            for (cx, cy), G in zip(centres, circ):
+                dx, dy = x - cx, y - cy
+                r2 = dx * dx + dy * dy
+                fac = G / (2 * math.pi) * (1.0 - np.exp(-r2 / sigma ** 2)) / np.maximum(r2, 1e-300)
+                u += wa * wb * (-dy * fac)
+                v += wa * wb * (dx * fac)
+    return u, v
+
+
+def smooth_field_avg(lo, n, h, seed, nmodes=4):
+    """Cell averages of a seeded smooth field sum_j a_j sin(p_j pi x + s_j)
+    sin(q_j pi y + t_j) on the cells starting at index lo."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros(n)
+    for _ in range(nmodes):
+        p, q = rng.integers(1, 5, size=2)
+        s, t = rng.uniform(0, 2 * math.pi, size=2)
+        a = rng.normal()
+        out += a * outer(avg_sin(p * math.pi, s, lo[0] * h, h, n[0]), avg_sin(q * math.pi, t, lo[1] * h, h, n[1]))
+    return out
