@@ -185,6 +185,7 @@ struct Depth {
   std::vector<int32_t> bottom_boxes; // boxes solved exactly at this depth
   std::vector<BottomGroupD> groups;
   int64_t nstored = 0;
+  bool fill_only = false;  // every ghost column is filled from its own row (no exchange or interpolated ghosts)
   int march = 2;  // cells each tile marches along the last direction
   // device copies
   BoxD* d_box = nullptr;

@@ -192,19 +192,23 @@ void smooth(const Run& R, int k, int smoother, int nsweeps, double omega, bool f
     if (from_zero) launch_zero<T>(cur, D.nstored, R.st);
     return;
   }
+  // FP32 forward sweeps compute the ghosts of filled columns where they read
+  // them: no fill launch when the depth has no other ghosts
+  const int gr = (sizeof(T) == 4 && !R.tr) ? 1 : 0;
+  const bool fill = !(gr && D.fill_only);
   if (smoother == AMG_SMOOTH_JACOBI) {
     for (int s = 0; s < nsweeps; ++s) {
       if (s == 0 && from_zero) {
         launch_jacobi<T>(R.dim, D, nullptr, f, cur, alpha, beta, (T)omega, true, R.st);
         continue;
       }
-      {
+      if (fill) {
         Timed tm(R, AMG_T_FILL, k);
         fill_op<T>(R, D, cur);
       }
       {
         Timed tm(R, AMG_T_SWEEP, k);
-        launch_jacobi<T>(R.dim, D, cur, f, oth, alpha, beta, (T)omega, false, R.st);
+        launch_jacobi<T>(R.dim, D, cur, f, oth, alpha, beta, (T)omega, false, R.st, gr);
       }
       if (R.tr) launch_band<T>(R.dim, D, 1, cur, oth, alpha, beta, -(T)omega * beta, 0, R.st);
       std::swap(cur, oth);
@@ -216,13 +220,13 @@ void smooth(const Run& R, int k, int smoother, int nsweeps, double omega, bool f
           launch_rb<T>(R.dim, D, nullptr, f, cur, alpha, beta, 0, true, R.st);
           continue;
         }
-        {
+        if (fill) {
           Timed tm(R, AMG_T_FILL, k);
           fill_op<T>(R, D, cur);
         }
         {
           Timed tm(R, AMG_T_SWEEP, k);
-          launch_rb<T>(R.dim, D, cur, f, oth, alpha, beta, col, false, R.st);
+          launch_rb<T>(R.dim, D, cur, f, oth, alpha, beta, col, false, R.st, gr);
         }
         if (R.tr) launch_band<T>(R.dim, D, 2, cur, oth, alpha, beta, -beta, col, R.st);
         std::swap(cur, oth);
@@ -1624,10 +1628,11 @@ int amg_time_sweep(amg_hier* H, int level, int dtype, int smoother, int n, void*
     coefs<T>(H, D, a, b);
     (void)hipEventRecord(e0, st);
     for (int i = 0; i < n; ++i) {
+      const int gr = sizeof(T) == 4 ? 1 : 0;  // the form the FP32 V-cycle launches
       if (smoother == AMG_SMOOTH_JACOBI)
-        launch_jacobi<T>(H->dim, D, cur, ff, oth, a, b, T(2.0 / 3.0), false, st);
+        launch_jacobi<T>(H->dim, D, cur, ff, oth, a, b, T(2.0 / 3.0), false, st, gr);
       else
-        launch_rb<T>(H->dim, D, cur, ff, oth, a, b, i & 1, false, st);
+        launch_rb<T>(H->dim, D, cur, ff, oth, a, b, i & 1, false, st, gr);
       std::swap(cur, oth);
     }
     (void)hipEventRecord(e1, st);

@@ -29,12 +29,14 @@ void launch_reflux_div(int dim, const Composite& X, CPtrs wc, CPtrs wf, double* 
 template <typename T>
 void launch_residual(int dim, const Depth& D, bool all, const T* u, const T* f, T* r, T alpha, T beta, double* part,
                      hipStream_t st);
+// gr != 0 (FP32 only): filled ghost columns computed where they are read, no
+// fill needed before the sweep for them
 template <typename T>
 void launch_jacobi(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, T omega, bool zero,
-                   hipStream_t st);
+                   hipStream_t st, int gr = 0);
 template <typename T>
 void launch_rb(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, int col, bool zero,
-               hipStream_t st);
+               hipStream_t st, int gr = 0);
 template <typename T>
 void launch_resid_restrict(int dim, const Depth& F, const Depth& C, const T* u, const T* f, T* fc, T alpha, T beta,
                            hipStream_t st);

@@ -252,11 +252,86 @@ struct DiagColumn {
     if (mixed) return T(1) / (alpha + beta * (T(-30 * DIM) + fold_at<T, DIM>(b, codes, x, y, z)));
     if (p >= 2 && p <= nm - 3) return inv_mid;
     T S = Sfix;
-    if (p < 2) S += flo[p];
-    if (p > nm - 3) S += fhi[nm - 1 - p];
+    if (p < 2) S += p == 0 ? flo[0] : flo[1];  // selects: no indexed private array
+    if (p > nm - 3) S += p == nm - 1 ? fhi[0] : fhi[1];
     return T(1) / (alpha + beta * S);
   }
 };
+
+// The two ghosts beyond the row end e0 (first four cells e0 + m in, m = 0..3)
+// of the homogeneous fill of a column with code cd: eqs. (velBCHomoDiri5th)
+// and (Neumann5) with zero data, computed where they are read instead of by a
+// fill launch.  Returns false if the column is not filled (its ghosts are in
+// memory); a second layer that is not filled from this row is read from memory.
+template <typename T>
+__device__ __forceinline__ bool gfill(uint8_t cd, const T* __restrict__ u, int64_t e0, int64_t in, T& g1, T& g2) {
+  const T u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
+  const int kind = cd & 3;
+  if (!kind) return false;
+  if (kind == 1) {
+    g1 = (T(-77) * u0 + T(43) * u1 - T(17) * u2 + T(3) * u3) * T(1.0 / 12.0);
+    g2 = (cd & 4) ? (T(-505) * u0 + T(335) * u1 - T(145) * u2 + T(27) * u3) * T(1.0 / 12.0) : u[e0 - 2 * in];
+  } else {
+    g1 = (T(5) * u0 + T(9) * u1 - T(5) * u2 + u3) * T(0.1);
+    g2 = (cd & 4) ? (T(-75) * u0 + T(145) * u1 - T(75) * u2 + T(15) * u3) * T(0.1) : u[e0 - 2 * in];
+  }
+  return true;
+}
+
+// First and second ghost of a filled column with code cd from the first four
+// cells of its row (u0 at the face): eqs. (velBCHomoDiri5th) and (Neumann5)
+// with zero data.
+template <typename T>
+__device__ __forceinline__ T ghost1(uint8_t cd, T u0, T u1, T u2, T u3) {
+  return (cd & 3) == 1 ? (T(-77) * u0 + T(43) * u1 - T(17) * u2 + T(3) * u3) * T(1.0 / 12.0)
+                       : (T(5) * u0 + T(9) * u1 - T(5) * u2 + u3) * T(0.1);
+}
+template <typename T>
+__device__ __forceinline__ T ghost2(uint8_t cd, T u0, T u1, T u2, T u3) {
+  return (cd & 3) == 1 ? (T(-505) * u0 + T(335) * u1 - T(145) * u2 + T(27) * u3) * T(1.0 / 12.0)
+                       : (T(-75) * u0 + T(145) * u1 - T(75) * u2 + T(15) * u3) * T(0.1);
+}
+
+// Ghosts of the tile's cells across the march direction, written into u by
+// the block before its march (read-time fill): x faces for the tile's rows,
+// y faces (3D) for its columns, on faces filled uniformly (code uf); each of
+// these ghosts is read only by this tile.
+template <typename T, int DIM>
+__device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __restrict__ u) {
+  const int p0 = DIM == 2 ? t.y0 : t.z0;
+  const int len = min(t.len, b.n[DIM - 1] - p0);
+  const int ny = DIM == 3 ? min(TILE3_Y, b.n[1] - t.y0) : 1;
+  const int nx = min(TILE_X, b.n[0] - t.x0);
+  // x faces: one thread per (row, side)
+  for (int side = 0; side < 2; ++side) {
+    const uint8_t cd = b.ucode[0][side];
+    if (cd == 0xFF || !(cd & 3)) continue;
+    if (side == 0 ? t.x0 != 0 : t.x0 + nx != b.n[0]) continue;
+    for (int r = (int)threadIdx.x; r < ny * len; r += (int)blockDim.x) {
+      const int y = DIM == 3 ? t.y0 + r % ny : 0, p = p0 + r / ny;
+      const int64_t e0 = cell_index<DIM>(b, side ? b.n[0] - 1 : 0, DIM == 3 ? y : p, DIM == 3 ? p : 0);
+      const int64_t in = side ? -1 : 1;
+      const T u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
+      u[e0 - in] = ghost1<T>(cd, u0, u1, u2, u3);
+      if (cd & 4) u[e0 - 2 * in] = ghost2<T>(cd, u0, u1, u2, u3);
+    }
+  }
+  if (DIM == 3) {
+    for (int side = 0; side < 2; ++side) {
+      const uint8_t cd = b.ucode[1][side];
+      if (cd == 0xFF || !(cd & 3)) continue;
+      if (side == 0 ? t.y0 != 0 : t.y0 + ny != b.n[1]) continue;
+      for (int r = (int)threadIdx.x; r < nx * len; r += (int)blockDim.x) {
+        const int x = t.x0 + r % nx, p = p0 + r / nx;
+        const int64_t e0 = cell_index<DIM>(b, x, side ? b.n[1] - 1 : 0, p);
+        const int64_t in = (side ? -1 : 1) * (int64_t)b.s[1];
+        const T u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
+        u[e0 - in] = ghost1<T>(cd, u0, u1, u2, u3);
+        if (cd & 4) u[e0 - 2 * in] = ghost2<T>(cd, u0, u1, u2, u3);
+      }
+    }
+  }
+}
 
 // OP_RESID : out = f - A u (f == NULL: out = A u); PART: per-tile max |out|
 // OP_JACOBI: out = u + omega (f - A u) / diag
@@ -269,27 +344,85 @@ struct DiagColumn {
 // One cell per thread and step; the neighbours across the march direction
 // are re-read through the L1/L2 caches (the neighbouring columns of the same
 // tile and the neighbouring tiles on the same XCD have just fetched them).
+//
+// gr != 0: the ghosts of filled columns (physical and coarse-fine face-data
+// faces, homogeneous) are computed where they are read (gfill), so no fill
+// launch is needed before the sweep for them; ghosts of exchange and
+// interpolated columns still come from memory.
 template <typename T, int DIM, int OP, bool PART>
 __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles, int ntiles,
                                                 const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
-                                                const T* __restrict__ u, const T* __restrict__ f, T* __restrict__ out,
-                                                T alpha, T beta, T omega, int col, double* __restrict__ part) {
+                                                const T* u, const T* __restrict__ f, T* __restrict__ out,
+                                                T alpha, T beta, T omega, int col, double* __restrict__ part,
+                                                int gr) {
   __shared__ double sh[8];
   const int ti = tile_of_block(ntiles);
   if (ti < 0) return;
   const TileD t = tiles[ti];
   const BoxD b = boxes[t.box];
   const Column C = column1_of<DIM>(t, b);
+  // read-time fill across the march: a block whose tile touches a uniformly
+  // filled x or y face writes the ghosts its cells read there (each such
+  // ghost is read only by this tile) before marching; the input array is
+  // complete when the kernel starts
+  if (gr) {
+    const int nx = min(TILE_X, b.n[0] - t.x0);
+    const uint8_t ux0 = b.ucode[0][0], ux1 = b.ucode[0][1];
+    const bool xf = (ux0 != 0xFF && (ux0 & 3) && t.x0 == 0) || (ux1 != 0xFF && (ux1 & 3) && t.x0 + nx == b.n[0]);
+    const bool yf = DIM == 3 && (t.y0 == 0 || t.y0 + TILE3_Y >= b.n[1]);
+    if (xf || yf) {  // block-uniform
+      tile_ghosts<T, DIM>(t, b, const_cast<T*>(u));
+      __syncthreads();
+    }
+  }
   double vmax = 0.0, vsum = 0.0;
   if (C.ok) {
     const int64_t sm = C.sm;
+    constexpr int M = DIM - 1;
+    const int nm = b.n[M];
     int64_t c = C.base + (int64_t)(C.p0 + 2) * sm;
     T q0 = u[c - 2 * sm], q1 = u[c - sm], q2 = u[c], q3 = u[c + sm];
+    // march-direction ghosts of this column (homogeneous fill, if filled):
+    // the low ones once here, the high ones from the register queue
+    uint8_t chi = 0;
+    if (gr) {
+      const int mcol = DIM == 2 ? C.x : C.x + b.n[0] * C.y;
+      T g1, g2;
+      if (C.p0 < 2 && gfill<T>(codes[b.code_off[M][0] + mcol], u, c - (int64_t)C.p0 * sm, sm, g1, g2)) {
+        if (C.p0 == 0) {
+          q0 = g2;
+          q1 = g1;
+        } else {
+          q0 = g1;
+        }
+      }
+      if (C.p1 + 2 > nm) {
+        chi = codes[b.code_off[M][1] + mcol];
+        if ((chi & 3) && C.p0 + 1 >= nm && gfill<T>(chi, u, c + (int64_t)(nm - 1 - C.p0) * sm, -sm, g1, g2))
+          q3 = g1;  // a one-cell tile at the end of the column
+      }
+    }
+    const int hk = chi & 3;  // fill kind of the high march-direction face (0: ghosts in memory)
+    T g2n = T(0);            // second high ghost, computed one step ahead
     DiagColumn<T, DIM> dg;
     if (OP != OP_RESID) dg.init(b, codes, C.x, C.y, alpha, beta, true);
     const int par0 = (b.lo[0] + C.x + (DIM == 3 ? b.lo[1] + C.y : 0) + b.lo[DIM - 1]) & 1;
     for (int p = C.p0; p < C.p1; ++p, c += sm) {
-      const T q4 = u[c + 2 * sm];
+      T q4;
+      if (hk && p + 2 == nm) {  // q0..q3 hold the last four cells of the column
+        if (hk == 1) {
+          q4 = (T(-77) * q3 + T(43) * q2 - T(17) * q1 + T(3) * q0) * T(1.0 / 12.0);
+          g2n = (chi & 4) ? (T(-505) * q3 + T(335) * q2 - T(145) * q1 + T(27) * q0) * T(1.0 / 12.0)
+                          : u[c + 3 * sm];
+        } else {
+          q4 = (T(5) * q3 + T(9) * q2 - T(5) * q1 + q0) * T(0.1);
+          g2n = (chi & 4) ? (T(-75) * q3 + T(145) * q2 - T(75) * q1 + T(15) * q0) * T(0.1) : u[c + 3 * sm];
+        }
+      } else if (hk && p + 2 == nm + 1) {
+        q4 = g2n;
+      } else {
+        q4 = u[c + 2 * sm];
+      }
       T ls = T(16) * (u[c - 1] + u[c + 1]) - (u[c - 2] + u[c + 2]) + T(16) * (q1 + q3) - (q0 + q4) +
              T(-30 * DIM) * q2;
       if (DIM == 3) {
@@ -1461,10 +1594,10 @@ template <typename T, int OP, bool PART>
 struct MarchK {
   template <int DIM>
   static void go(const TileD* tl, size_t n, const Depth& D, const T* u, const T* f, T* out, T a, T b, T w, int col,
-                 double* part, const BoxD* cboxes, hipStream_t st) {
+                 double* part, const BoxD* cboxes, hipStream_t st, int gr) {
     if (sizeof(T) == 4 && OP != OP_RESTRICT)
       hipLaunchKernelGGL((k_march1<T, DIM, OP, PART>), grid8(n), dim3(DIM == 2 ? 128 : 512), 0, st, tl, (int)n,
-                         D.d_box, D.d_codes, u, f, out, a, b, w, col, part);
+                         D.d_box, D.d_codes, u, f, out, a, b, w, col, part, gr);
     else
       hipLaunchKernelGGL((k_march<T, DIM, OP, PART>), grid8(n), threads<DIM>(), 0, st, tl, (int)n, D.d_box, D.d_codes,
                          u, f, out, a, b, w, col, part, cboxes);
@@ -1473,12 +1606,12 @@ struct MarchK {
 
 template <typename T, int OP, bool PART>
 void march(int dim, const TileD* tl, size_t n, const Depth& D, const T* u, const T* f, T* out, T a, T b, T w, int col,
-           double* part, hipStream_t st, const BoxD* cboxes = nullptr) {
+           double* part, hipStream_t st, const BoxD* cboxes = nullptr, int gr = 0) {
   if (!n) return;
   if (dim == 2)
-    MarchK<T, OP, PART>::template go<2>(tl, n, D, u, f, out, a, b, w, col, part, cboxes, st);
+    MarchK<T, OP, PART>::template go<2>(tl, n, D, u, f, out, a, b, w, col, part, cboxes, st, gr);
   else
-    MarchK<T, OP, PART>::template go<3>(tl, n, D, u, f, out, a, b, w, col, part, cboxes, st);
+    MarchK<T, OP, PART>::template go<3>(tl, n, D, u, f, out, a, b, w, col, part, cboxes, st, gr);
 }
 
 template <typename T>
@@ -1494,7 +1627,7 @@ void launch_residual(int dim, const Depth& D, bool all, const T* u, const T* f, 
 
 template <typename T>
 void launch_jacobi(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, T omega, bool zero,
-                   hipStream_t st) {
+                   hipStream_t st, int gr) {
   const size_t n = D.stiles.size();
   if (!n) return;
   if (zero) {
@@ -1506,12 +1639,12 @@ void launch_jacobi(int dim, const Depth& D, const T* u, const T* f, T* out, T al
                          f, out, alpha, beta, omega);
     return;
   }
-  march<T, OP_JACOBI, false>(dim, D.d_stiles, n, D, u, f, out, alpha, beta, omega, 0, nullptr, st);
+  march<T, OP_JACOBI, false>(dim, D.d_stiles, n, D, u, f, out, alpha, beta, omega, 0, nullptr, st, nullptr, gr);
 }
 
 template <typename T>
 void launch_rb(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, int col, bool zero,
-               hipStream_t st) {
+               hipStream_t st, int gr) {
   const size_t n = D.stiles.size();
   if (!n) return;
   if (zero) {
@@ -1523,7 +1656,7 @@ void launch_rb(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha,
                          f, out, alpha, beta, T(1));
     return;
   }
-  march<T, OP_RB, false>(dim, D.d_stiles, n, D, u, f, out, alpha, beta, T(1), col, nullptr, st);
+  march<T, OP_RB, false>(dim, D.d_stiles, n, D, u, f, out, alpha, beta, T(1), col, nullptr, st, nullptr, gr);
 }
 
 template <typename T>
@@ -1819,8 +1952,8 @@ void launch_zero(T* a, int64_t n, hipStream_t st) {
   template void launch_fill_zero<T>(const Depth&, T*, hipStream_t);                                               \
   template void launch_band<T>(int, const Depth&, int, const T*, T*, T, T, T, int, hipStream_t);                  \
   template void launch_residual<T>(int, const Depth&, bool, const T*, const T*, T*, T, T, double*, hipStream_t);  \
-  template void launch_jacobi<T>(int, const Depth&, const T*, const T*, T*, T, T, T, bool, hipStream_t);          \
-  template void launch_rb<T>(int, const Depth&, const T*, const T*, T*, T, T, int, bool, hipStream_t);            \
+  template void launch_jacobi<T>(int, const Depth&, const T*, const T*, T*, T, T, T, bool, hipStream_t, int);     \
+  template void launch_rb<T>(int, const Depth&, const T*, const T*, T*, T, T, int, bool, hipStream_t, int);       \
   template void launch_resid_restrict<T>(int, const Depth&, const Depth&, const T*, const T*, T*, T, T,           \
                                          hipStream_t);                                                            \
   template void launch_restrict<T>(int, const Depth&, const Depth&, const T*, T*, hipStream_t);                   \

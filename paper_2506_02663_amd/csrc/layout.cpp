@@ -432,6 +432,11 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       D.chunk_comp_ptr.push_back((int32_t)D.chunk_comp_idx.size());
     }
 
+    D.fill_only = true;
+    for (const ChunkD& ch : D.chunks)
+      if (!((ch.kind1 == G_FILL_D || ch.kind1 == G_FILL_N) && (ch.kind2 == G_FILL_D || ch.kind2 == G_FILL_N)))
+        D.fill_only = false;
+
     // ---- tiles (grouped by component, so each component is one range) ----
     D.tiles.clear();
     D.stiles.clear();
