@@ -38,6 +38,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-timing", action="store_true", help="skip the per-kernel event timing")
     p.add_argument("--no-autotune", action="store_true", help="keep the default tile march length")
+    p.add_argument("--bottom-cells", type=int, default=512,
+                   help="single-level workloads: exact bottom solve once a depth has at most this many cells "
+                        "(0: coarsen as far as the layout allows)")
     p.add_argument("--copy-probe", action="store_true",
                    help="first run a plain 256 MiB device copy three times (the reference kernel that "
                         "calibrates the HBM byte counters)")
@@ -166,6 +169,8 @@ def main():
             if march is None:
                 march, _ = H.autotune(0, A.F32 if prec == A.MIXED else A.F64, sm)
             H.set_tuning(A.TUNE_MARCH2 if dim == 2 else A.TUNE_MARCH3, march)
+        if args.bottom_cells:
+            H.set_bottom_cells(args.bottom_cells)
         H.finalize()
         fd = torch.tensor(H.pack(0, 0, lambda i, b: f), device="cuda")
         x = torch.zeros_like(fd)
@@ -225,7 +230,8 @@ def main():
         "config": {"workload": f"{dim}D single level {n}^{dim}, Helmholtz (Dirichlet, nu={nu}) + Neumann Poisson",
                    "cells": n ** dim, "dof_per_step": dof_step, "tol_rel": 1e-10,
                    "cycles": cycles, "smoother": args.smoother, "precision": args.precision,
-                   "vcycle": "V(2,2)", "march": march},
+                   "vcycle": "V(2,2)", "march": march, "bottom_cells": args.bottom_cells,
+                   "depths": systems[0][1].level_info(0).depths},
     }
     if not args.no_timing:
         # dominant kernel: the smoothing sweep on the finest depth

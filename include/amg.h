@@ -201,6 +201,18 @@ int amg_set_operator(amg_hier* h, int kind, double c);
 #define AMG_TUNE_ROW_ALIGN 2
 int amg_set_tuning(amg_hier* h, int key, int value);
 
+/* Size of the exactly solved coarsest systems (Section 6.5 leaves the bottom
+ * solver open; this library solves the coarsest depth exactly).  Coarsening
+ * stops at the first depth where every component of a level (of an isolated
+ * level: every box) has at most `cells` cells, or where the layout rule below
+ * stops it; `cells` = 0 (the default) coarsens as far as the layout allows.
+ * A larger bottom replaces the smallest, launch-bound depths by one dense
+ * FP64 solve; it changes the multigrid hierarchy, hence the iterates (not
+ * the converged solution).  0..1024 (the inverse is formed on the host in
+ * O(cells^3)), set before amg_finalize.
+ * Errors: AMG_EINVAL (range, or the layout is final). */
+int amg_set_bottom_cells(amg_hier* h, int cells);
+
 /* Validates the layout (disjoint boxes inside the grid, proper refinement
  * eq. (pBlock), boxes of at least 4 cells per side), labels components,
  * builds the multigrid depths (a level is halved while every box has even

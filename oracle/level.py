@@ -297,9 +297,16 @@ class Level:
         boxes = [(tuple(l // 2 for l in lo), tuple((u + 1) // 2 - 1 for u in hi)) for lo, hi in self.boxes]
         return Level(tuple(n // 2 for n in self.shape), 2 * self.h, boxes, self.phys_bc, self.cf_kind)
 
-    def hierarchy(self):
+    def largest_component(self):
+        """Cells of the largest face-connected component."""
+        return int(np.bincount(self.labels[self.mask]).max())
+
+    def hierarchy(self, bottom_cells=0):
+        """The multigrid depths: halve while can_coarsen() allows and, with
+        bottom_cells > 0, while some component has more than bottom_cells
+        cells (the depth that first has none is solved exactly)."""
         levels = [self]
-        while levels[-1].can_coarsen():
+        while levels[-1].can_coarsen() and not (bottom_cells and levels[-1].largest_component() <= bottom_cells):
             levels.append(levels[-1].coarsen())
         return levels
 

@@ -130,8 +130,9 @@ class MG:
     share it), the same restriction and prolongation, the transposed bottom
     matrix."""
 
-    def __init__(self, lev, op, c, nu1=2, nu2=2, smoother="jacobi", omega=2.0 / 3.0, transpose=False):
-        self.levels = lev.hierarchy()
+    def __init__(self, lev, op, c, nu1=2, nu2=2, smoother="jacobi", omega=2.0 / 3.0, transpose=False,
+                 bottom_cells=0):
+        self.levels = lev.hierarchy(bottom_cells)
         self.op, self.c = op, c
         self.transpose = transpose
         self.nu1, self.nu2, self.smoother, self.omega = nu1, nu2, smoother, omega
@@ -222,7 +223,7 @@ def norm_inf(lev, a):
 
 def solve(lev, f, op, c, fd=None, cfv=None, x0=None, nu1=2, nu2=2, smoother="jacobi",
           omega=2.0 / 3.0, tol_rel=1e-10, tol_abs=0.0, max_cycles=50, shift=True, mg=None, transpose=False,
-          cf_delta=False):
+          cf_delta=False, bottom_cells=0):
     """Outer residual-correction loop in FP64:
     r = f - A(x); s = ||r||_inf; e = V(r / s); x += s e; remove the mean of x
     on every singular component; stop by the max-norm criterion above.
@@ -232,7 +233,7 @@ def solve(lev, f, op, c, fd=None, cfv=None, x0=None, nu1=2, nu2=2, smoother="jac
     mean-free, which is the RHS shift with zero face data."""
     if transpose and (fd is not None or cfv is not None):
         raise ValueError("the adjoint system is homogeneous")
-    mg = mg or MG(lev, op, c, nu1, nu2, smoother, omega, transpose)
+    mg = mg or MG(lev, op, c, nu1, nu2, smoother, omega, transpose, bottom_cells)
     sing = mg.sing[0]
     defects = []
     if shift and sing and cf_delta:

@@ -73,6 +73,7 @@ def lib():
         L.amg_set_isolated_boxes.argtypes = [vp, i32, i32]
         L.amg_set_physical_bc.argtypes = [vp, i32, i32, i32]
         L.amg_set_cf_mode.argtypes = [vp, i32, i32]
+        L.amg_set_bottom_cells.argtypes = [vp, i32]
         L.amg_set_operator.argtypes = [vp, i32, dbl]
         L.amg_finalize.argtypes = [vp]
         L.amg_level_info.argtypes = [vp, i32, C.POINTER(LevelDesc)]
@@ -180,6 +181,9 @@ class Hierarchy:
 
     def set_cf_mode(self, level, mode):
         self._check(lib().amg_set_cf_mode(self.h, level, mode))
+
+    def set_bottom_cells(self, cells):
+        self._check(lib().amg_set_bottom_cells(self.h, int(cells)))
 
     def set_operator(self, kind, c=0.0):
         self._check(lib().amg_set_operator(self.h, kind, float(c)))

@@ -84,6 +84,7 @@ struct BottomGroupD {      // systems sharing one dense inverse
   int64_t mat;             // offset of the n x n inverse (column-major) in the matrix pool
   int64_t idx;             // offset of ninst*n element indices in the index pool
   int32_t n, ninst;
+  int64_t matT;            // offset of its transpose (column-major) in the matrix pool
 };
 
 // ---- composite (multi-level) tables -------------------------------------------
@@ -279,6 +280,7 @@ struct amg_hier {
   amg::Timer timer;
   int march2 = MARCH2_DEFAULT, march3 = MARCH3_DEFAULT;  // tile march lengths
   int row_align = ROW_ALIGN_DEFAULT;                       // row alignment of the packed layout (elements)
+  int bottom_cells = 0;  // coarsening stops once every component has at most this many cells (0: off)
   int dim = 2;
   int32_t base[3] = {1, 1, 1};
   double h0 = 1;

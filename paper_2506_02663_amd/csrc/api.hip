@@ -650,6 +650,14 @@ int amg_set_tuning(amg_hier* H, int key, int value) {
   return fail(H, AMG_EINVAL, "unknown tuning key");
 }
 
+int amg_set_bottom_cells(amg_hier* H, int cells) {
+  if (!H) return AMG_EINVAL;
+  if (H->finalized) return fail(H, AMG_EINVAL, "layout is final");
+  if (cells < 0 || cells > 1024) return fail(H, AMG_EINVAL, "bottom cells must be 0..1024");
+  H->bottom_cells = cells;
+  return AMG_OK;
+}
+
 int amg_finalize(amg_hier* H) {
   if (!H) return AMG_EINVAL;
   if (H->finalized) return fail(H, AMG_EINVAL, "already final");
@@ -1334,7 +1342,6 @@ int amg_solve_adjoint_composite(amg_hier* H, int lev_hi, double* const* lam, con
   Comp C;
   TRY(make_comp(H, 0, lev_hi, lam, g, nullptr, stream, C));
   C.tr = true;
-  const int dim = H->dim;
   Level& L0 = H->levels[0];
   if (stats) memset(stats, 0, sizeof *stats);
   // the source on the valid cells only (library copy); pure Neumann: its
@@ -1673,6 +1680,7 @@ int amg_autotune(amg_hier* H, int level, int dtype, int smoother, int nreps, int
     T->op = H->op;
     T->c = H->c;
     T->row_align = H->row_align;
+    T->bottom_cells = H->bottom_cells;
     T->march2 = T->march3 = m;
     rc = amg_finalize(T);
     if (rc != AMG_OK) {

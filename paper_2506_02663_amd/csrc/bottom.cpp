@@ -206,11 +206,15 @@ int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats
       G.idx = -1;
       G.n = (int32_t)n;
       G.ninst = 1;
-      // column-major top-left n x n block
+      // column-major top-left n x n block, then its transpose (column-major)
       size_t base = mats.size();
-      mats.resize(base + (size_t)n * n);
+      G.matT = (int64_t)(base + (size_t)n * n);
+      mats.resize(base + 2 * (size_t)n * n);
       for (int64_t c = 0; c < n; ++c)
-        for (int64_t r = 0; r < n; ++r) mats[base + (size_t)c * n + r] = A[(size_t)r * m + c];
+        for (int64_t r = 0; r < n; ++r) {
+          mats[base + (size_t)c * n + r] = A[(size_t)r * m + c];
+          mats[G.matT + (size_t)c * n + r] = A[(size_t)c * m + r];
+        }
       group_elems.push_back(elems);
       if (L.isolated) {
         const BoxD& X = D.boxd[sys[0]];

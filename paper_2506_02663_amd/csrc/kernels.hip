@@ -292,23 +292,22 @@ __device__ __forceinline__ T ghost2(uint8_t cd, T u0, T u1, T u2, T u3) {
                        : (T(-75) * u0 + T(145) * u1 - T(75) * u2 + T(15) * u3) * T(0.1);
 }
 
-// Ghosts of the tile's cells across the march direction, written into u by
-// the block before its march (read-time fill): x faces for the tile's rows,
-// y faces (3D) for its columns, on faces filled uniformly (code uf); each of
-// these ghosts is read only by this tile.
+// Ghosts across the march direction of the cells x0..x0+nx-1, y0..y0+ny-1
+// (3D; 2D: y0 = 0, ny = 1), march planes p0..p0+len-1, on faces filled
+// uniformly (code uf), written into u by the block before its march
+// (read-time fill): x faces for the rows that reach them, y faces (3D) for
+// the columns that reach them.  Each of these ghosts is read only by the
+// block that writes it.
 template <typename T, int DIM>
-__device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __restrict__ u) {
-  const int p0 = DIM == 2 ? t.y0 : t.z0;
-  const int len = min(t.len, b.n[DIM - 1] - p0);
-  const int ny = DIM == 3 ? min(TILE3_Y, b.n[1] - t.y0) : 1;
-  const int nx = min(TILE_X, b.n[0] - t.x0);
+__device__ __forceinline__ void face_ghosts(const BoxD& b, T* __restrict__ u, int x0, int nx, int y0, int ny, int p0,
+                                            int len) {
   // x faces: one thread per (row, side)
   for (int side = 0; side < 2; ++side) {
     const uint8_t cd = b.ucode[0][side];
     if (cd == 0xFF || !(cd & 3)) continue;
-    if (side == 0 ? t.x0 != 0 : t.x0 + nx != b.n[0]) continue;
+    if (side == 0 ? x0 != 0 : x0 + nx != b.n[0]) continue;
     for (int r = (int)threadIdx.x; r < ny * len; r += (int)blockDim.x) {
-      const int y = DIM == 3 ? t.y0 + r % ny : 0, p = p0 + r / ny;
+      const int y = DIM == 3 ? y0 + r % ny : 0, p = p0 + r / ny;
       const int64_t e0 = cell_index<DIM>(b, side ? b.n[0] - 1 : 0, DIM == 3 ? y : p, DIM == 3 ? p : 0);
       const int64_t in = side ? -1 : 1;
       const T u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
@@ -320,9 +319,9 @@ __device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __
     for (int side = 0; side < 2; ++side) {
       const uint8_t cd = b.ucode[1][side];
       if (cd == 0xFF || !(cd & 3)) continue;
-      if (side == 0 ? t.y0 != 0 : t.y0 + ny != b.n[1]) continue;
+      if (side == 0 ? y0 != 0 : y0 + ny != b.n[1]) continue;
       for (int r = (int)threadIdx.x; r < nx * len; r += (int)blockDim.x) {
-        const int x = t.x0 + r % nx, p = p0 + r / nx;
+        const int x = x0 + r % nx, p = p0 + r / nx;
         const int64_t e0 = cell_index<DIM>(b, x, side ? b.n[1] - 1 : 0, p);
         const int64_t in = (side ? -1 : 1) * (int64_t)b.s[1];
         const T u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
@@ -331,6 +330,14 @@ __device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __
       }
     }
   }
+}
+
+// the same for the cells of one column tile
+template <typename T, int DIM>
+__device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __restrict__ u) {
+  const int p0 = DIM == 2 ? t.y0 : t.z0;
+  face_ghosts<T, DIM>(b, u, t.x0, min(TILE_X, b.n[0] - t.x0), DIM == 3 ? t.y0 : 0,
+                      DIM == 3 ? min(TILE3_Y, b.n[1] - t.y0) : 1, p0, min(t.len, b.n[DIM - 1] - p0));
 }
 
 // OP_RESID : out = f - A u (f == NULL: out = A u); PART: per-tile max |out|
@@ -385,6 +392,7 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
     // march-direction ghosts of this column (homogeneous fill, if filled):
     // the low ones once here, the high ones from the register queue
     uint8_t chi = 0;
+    T g2n = T(0);  // second high ghost, computed one step ahead
     if (gr) {
       const int mcol = DIM == 2 ? C.x : C.x + b.n[0] * C.y;
       T g1, g2;
@@ -398,12 +406,13 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
       }
       if (C.p1 + 2 > nm) {
         chi = codes[b.code_off[M][1] + mcol];
-        if ((chi & 3) && C.p0 + 1 >= nm && gfill<T>(chi, u, c + (int64_t)(nm - 1 - C.p0) * sm, -sm, g1, g2))
+        if ((chi & 3) && C.p0 + 1 >= nm && gfill<T>(chi, u, c + (int64_t)(nm - 1 - C.p0) * sm, -sm, g1, g2)) {
           q3 = g1;  // a one-cell tile at the end of the column
+          g2n = g2;
+        }
       }
     }
     const int hk = chi & 3;  // fill kind of the high march-direction face (0: ghosts in memory)
-    T g2n = T(0);            // second high ghost, computed one step ahead
     DiagColumn<T, DIM> dg;
     if (OP != OP_RESID) dg.init(b, codes, C.x, C.y, alpha, beta, true);
     const int par0 = (b.lo[0] + C.x + (DIM == 3 ? b.lo[1] + C.y : 0) + b.lo[DIM - 1]) & 1;
@@ -867,17 +876,23 @@ __global__ void __launch_bounds__(256) k_fill(const ChunkD* __restrict__ chunks,
 }
 
 // exact bottom solve: e = M f (TR: e = M^T f, the adjoint system) for every
-// instance of every group
+// instance of every group.  Both M and M^T are stored column-major, so the
+// lanes of a column read consecutive rows.  A block takes 8 rows; its 32
+// thread groups split the columns (group p takes columns p, p + 32, ...), so
+// every thread has only n / 32 independent loads per instance batch, and the
+// 32 partial sums of a row are added in LDS.
 template <typename T, bool TR>
 __global__ void __launch_bounds__(256) k_bottom(const BottomGroupD* __restrict__ groups,
                                                 const double* __restrict__ mats, const int64_t* __restrict__ idx,
                                                 const T* __restrict__ f, T* __restrict__ e, T* __restrict__ e2) {
-  constexpr int NI = 8, KC = 512;
+  constexpr int NI = 8, KC = 512, RB = 8, KP = 32;
   __shared__ double xs[NI][KC];
+  __shared__ double red[KP][NI][RB];
   const BottomGroupD G = groups[blockIdx.y];
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if ((int)(blockIdx.x * 256) >= G.n) return;  // uniform per block
-  const double* M = mats + G.mat;
+  if ((int)(blockIdx.x * RB) >= G.n) return;  // uniform per block
+  const int rl = (int)threadIdx.x % RB, part = (int)threadIdx.x / RB;
+  const int r = blockIdx.x * RB + rl;
+  const double* M = mats + (TR ? G.matT : G.mat);
   for (int i0 = 0; i0 < G.ninst; i0 += NI) {
     const int ni = min(NI, G.ninst - i0);
     double acc[NI];
@@ -892,19 +907,24 @@ __global__ void __launch_bounds__(256) k_bottom(const BottomGroupD* __restrict__
       }
       __syncthreads();
       if (r < G.n) {
-#pragma unroll 8
-        for (int k = 0; k < kc; ++k) {
-          const double m = TR ? M[(int64_t)r * G.n + k0 + k] : M[(int64_t)(k0 + k) * G.n + r];
+#pragma unroll 4
+        for (int k = part; k < kc; k += KP) {
+          const double m = M[(int64_t)(k0 + k) * G.n + r];
 #pragma unroll
           for (int i = 0; i < NI; ++i) acc[i] += m * xs[i][k];
         }
       }
     }
-    if (r < G.n)
+#pragma unroll
+    for (int i = 0; i < NI; ++i) red[part][i][rl] = acc[i];
+    __syncthreads();
+    if (part == 0 && r < G.n)
       for (int i = 0; i < ni; ++i) {
+        double s = 0.0;
+        for (int p = 0; p < KP; ++p) s += red[p][i][rl];
         const int64_t q = idx[G.idx + (int64_t)(i0 + i) * G.n + r];
-        e[q] = (T)acc[i];
-        if (e2) e2[q] = (T)acc[i];
+        e[q] = (T)s;
+        if (e2) e2[q] = (T)s;
       }
   }
 }
@@ -1693,7 +1713,7 @@ void launch_bottom(const Depth& D, const double* mats, const int64_t* idx, const
   if (D.groups.empty()) return;
   int maxn = 0;
   for (auto& g : D.groups) maxn = std::max(maxn, g.n);
-  const dim3 grid((maxn + 255) / 256, (unsigned)D.groups.size());
+  const dim3 grid((maxn + 7) / 8, (unsigned)D.groups.size());
   if (tr)
     hipLaunchKernelGGL((k_bottom<T, true>), grid, dim3(256), 0, st, D.d_groups, mats, idx, f, e, e2);
   else

@@ -8,7 +8,8 @@
 // cells of the row that ends at a face, so every box has at least 4 cells
 // per side.  A level is halved for the next multigrid depth while every box
 // has even corners and even sides of at least 8 (an isolated box: even sides
-// of at least 8).
+// of at least 8) and, with a bottom size B set, while some component (an
+// isolated box) has more than B cells.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -147,6 +148,11 @@ int plan_level(amg_hier* H, int l, std::string& err) {
         bool ok = true;
         for (int d = 0; d < dim; ++d)
           if ((n[d] >> k) % 2 || (n[d] >> k) < 8) ok = false;
+        if (ok && H->bottom_cells > 0) {  // small enough for the exact solve
+          int64_t cells = 1;
+          for (int d = 0; d < dim; ++d) cells *= n[d] >> k;
+          if (cells <= H->bottom_cells) ok = false;
+        }
         if (!ok) break;
         ++k;
       }
@@ -176,6 +182,15 @@ int plan_level(amg_hier* H, int l, std::string& err) {
             int gap = std::max(L.boxes[b].lo[d] - L.boxes[a].hi[d] - 1, L.boxes[a].lo[d] - L.boxes[b].hi[d] - 1) >> k;
             if (gap > 0 && gap < 4) ok = false;
           }
+      if (ok && H->bottom_cells > 0) {  // every component small enough for the exact solve
+        std::vector<int64_t> cc(L.ncomp, 0);
+        for (int b = 0; b < nb; ++b) {
+          int64_t v = 1;
+          for (int d = 0; d < dim; ++d) v *= L.boxes[b].n(d) >> k;
+          cc[L.box_comp[b]] += v;
+        }
+        if (*std::max_element(cc.begin(), cc.end()) <= H->bottom_cells) ok = false;
+      }
       if (!ok) break;
       ++k;
     }
@@ -436,6 +451,11 @@ int plan_level(amg_hier* H, int l, std::string& err) {
     for (const ChunkD& ch : D.chunks)
       if (!((ch.kind1 == G_FILL_D || ch.kind1 == G_FILL_N) && (ch.kind2 == G_FILL_D || ch.kind2 == G_FILL_N)))
         D.fill_only = false;
+    // the read-time fill writes the ghosts across the march direction only on
+    // faces with one code; a face across it that mixes codes keeps the launch
+    for (const BoxD& X : D.boxd)
+      for (int d = 0; d + 1 < dim; ++d)
+        if (X.ucode[d][0] == 0xFF || X.ucode[d][1] == 0xFF) D.fill_only = false;
 
     // ---- tiles (grouped by component, so each component is one range) ----
     D.tiles.clear();

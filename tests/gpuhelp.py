@@ -9,10 +9,11 @@ def covers_domain(lev):
     return lev.ncells == int(np.prod(lev.shape))
 
 
-def make_hier(lev, op, c, cf_mode=None):
+def make_hier(lev, op, c, cf_mode=None, bottom_cells=0):
     """Hierarchy whose level `index` has the oracle level's boxes.  A level
     that does not cover its grid becomes level 1 of a two-level hierarchy
-    (level 0 one box over the half-resolution grid)."""
+    (level 0 one box over the half-resolution grid).  bottom_cells: the
+    exact-solve size of the multigrid hierarchy (0: the layout's own)."""
     import torch  # noqa: F401  (initialises the HIP runtime the library uses)
     from paper_2506_02663_amd import amg as A
 
@@ -30,6 +31,8 @@ def make_hier(lev, op, c, cf_mode=None):
     for (d, s), kind in lev.phys_bc.items():
         H.set_physical_bc(d, s, A.DIRICHLET if kind == "D" else A.NEUMANN)
     H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c)
+    if bottom_cells:
+        H.set_bottom_cells(bottom_cells)
     H.finalize()
     return H, index
 

@@ -47,6 +47,9 @@ def test_host_argument_checks(lib):
     assert b"c > 0" in L.amg_last_error(h)
     assert L.amg_set_physical_bc(h, 2, 0, A.DIRICHLET) == A.EINVAL          # d >= dim
     assert L.amg_set_cf_mode(h, 0, A.CF_NEUMANN) == A.EINVAL                 # level 0 has no interface
+    assert L.amg_set_bottom_cells(h, -1) == A.EINVAL
+    assert L.amg_set_bottom_cells(h, 1025) == A.EINVAL                      # host inverse O(n^3)
+    assert L.amg_set_bottom_cells(h, 512) == A.OK
     assert L.amg_solve(h, 0, 0, None, None, None, None, None, None) == A.EINVAL  # not finalized
     assert b"finalize" in L.amg_last_error(h)
     assert L.amg_destroy(h) == A.OK

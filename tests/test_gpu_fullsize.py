@@ -24,19 +24,22 @@ from paper_2506_02663_amd import workloads as W  # noqa: E402
 OPTS = dict(precision=A.MIXED, smoother=A.SMOOTH_RB, tol_rel=1e-10, max_cycles=100)
 
 
-def single_level(n, bc, op, c):
+def single_level(n, bc, op, c, bottom_cells=0):
     H = A.Hierarchy(3, (n,) * 3, 1.0 / n, 1)
     H.set_level_boxes(0, [((0,) * 3, (n - 1,) * 3)])
     for d in range(3):
         for s in (0, 1):
             H.set_physical_bc(d, s, A.DIRICHLET if bc == "D" else A.NEUMANN)
     H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c)
+    if bottom_cells:
+        H.set_bottom_cells(bottom_cells)
     H.finalize()
     return H
 
 
-@pytest.mark.parametrize("op,bc", [("helmholtz", "D"), ("poisson", "N")])
-def test_3d_256_solution_satisfies_oracle_system(op, bc):
+# the benchmark's exact bottom of 512 cells (8^3), and the layout's own (4^3)
+@pytest.mark.parametrize("op,bc,bottom", [("helmholtz", "D", 512), ("poisson", "N", 512), ("poisson", "N", 0)])
+def test_3d_256_solution_satisfies_oracle_system(op, bc, bottom):
     n, nu = 256, 1e-4
     h = 1.0 / n
     c = 0.5 * nu * h if op == "helmholtz" else 0.0
@@ -46,7 +49,8 @@ def test_3d_256_solution_satisfies_oracle_system(op, bc):
     else:
         f = -12 * math.pi ** 2 * W.cosprod_avg(shape, h) + W.noise(shape, 1)
         f -= f.mean()
-    H = single_level(n, bc, op, c)
+    H = single_level(n, bc, op, c, bottom)
+    assert H.level_info(0).depths == (6 if bottom else 7)
     fd = torch.tensor(H.pack(0, 0, lambda i, b: f), device="cuda")
     x = torch.zeros_like(fd)
     st = H.solve(0, x, fd, None, A.default_opts(**OPTS))
