@@ -38,6 +38,11 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-timing", action="store_true", help="skip the per-kernel event timing")
     p.add_argument("--no-autotune", action="store_true", help="keep the default tile march length")
+    p.add_argument("--nu", default=None,
+                   help="pre,post smoothing steps of the V-cycle (default: 1,3 for the 3D single level, "
+                        "whose 1e-10 solve it reaches fastest of V(0..2, 1..4); 2,2 otherwise)")
+    p.add_argument("--no-graph", action="store_true",
+                   help="launch every kernel of a cycle directly instead of replaying its HIP graph")
     p.add_argument("--bottom-cells", type=int, default=512,
                    help="single-level workloads: exact bottom solve once a depth has at most this many cells "
                         "(0: coarsen as far as the layout allows)")
@@ -99,9 +104,10 @@ def single_level_problems(dim, n, nu):
     return h, c, [("helmholtz", "D", helm), ("poisson", "N", pois)]
 
 
-def cpu_baseline(dim, n, nu, smoother):
+def cpu_baseline(dim, n, nu, smoother, nu1=2, nu2=2, bottom_cells=0):
     """The FP64 oracle on a bounded sample of the same workload (same recipe,
-    same smoother, smaller grid), single-threaded, timed on the host."""
+    same smoother, V-cycle and bottom size, smaller grid), single-threaded,
+    timed on the host."""
     import numpy as np
 
     from oracle import mg
@@ -113,13 +119,15 @@ def cpu_baseline(dim, n, nu, smoother):
         lev = Level((n,) * dim, h, [((0,) * dim, (n - 1,) * dim)], {(d, s): bc for d in range(dim) for s in (0, 1)})
         fa = lev.zeros()
         fa[lev.inner] = f
-        x, st = mg.solve(lev, fa, op, c, tol_rel=1e-10, max_cycles=100, smoother=smoother)
+        x, st = mg.solve(lev, fa, op, c, tol_rel=1e-10, max_cycles=100, smoother=smoother, nu1=nu1, nu2=nu2,
+                         bottom_cells=bottom_cells)
         assert st["converged"]
         dof += lev.ncells
     dt = time.perf_counter() - t0
     return {"value": dof / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
             "sample": f"{dim}D {n}^{dim}: Helmholtz (Dirichlet) + Neumann Poisson solves to 1e-10, "
-                      f"same recipe and smoother ({smoother}) as the timed workload, {dt:.1f} s"}
+                      f"same recipe, smoother ({smoother}), V({nu1},{nu2}) and bottom size ({bottom_cells}) "
+                      f"as the timed workload, {dt:.1f} s"}
 
 
 def main():
@@ -140,10 +148,11 @@ def main():
     else:
         return bench_batched(args)
 
+    nu1, nu2 = map(int, (args.nu or ("1,3" if dim == 3 else "2,2")).split(","))
     base = None
     if not args.no_cpu_baseline:
         # before the GPU is touched: single-threaded numpy
-        base = cpu_baseline(*sample, args.smoother)
+        base = cpu_baseline(*sample, args.smoother, nu1, nu2, args.bottom_cells)
 
     import torch
     if args.copy_probe:
@@ -154,7 +163,8 @@ def main():
     h, c, probs = single_level_problems(dim, n, nu)
     prec = A.MIXED if args.precision == "mixed" else A.FP64
     sm = A.SMOOTH_JACOBI if args.smoother == "jacobi" else A.SMOOTH_RB
-    opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100)
+    opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100, nu1=nu1, nu2=nu2,
+                          use_graph=0 if args.no_graph else 1)
     systems = []
     march = None
     for op, bc, f in probs:
@@ -230,7 +240,7 @@ def main():
         "config": {"workload": f"{dim}D single level {n}^{dim}, Helmholtz (Dirichlet, nu={nu}) + Neumann Poisson",
                    "cells": n ** dim, "dof_per_step": dof_step, "tol_rel": 1e-10,
                    "cycles": cycles, "smoother": args.smoother, "precision": args.precision,
-                   "vcycle": "V(2,2)", "march": march, "bottom_cells": args.bottom_cells,
+                   "graph": not args.no_graph, "vcycle": f"V({nu1},{nu2})", "march": march, "bottom_cells": args.bottom_cells,
                    "depths": systems[0][1].level_info(0).depths},
     }
     if not args.no_timing:
@@ -311,7 +321,8 @@ def bench_amr(args):
     from paper_2506_02663_amd import amg as A
     prec = A.MIXED if args.precision == "mixed" else A.FP64
     sm = A.SMOOTH_JACOBI if args.smoother == "jacobi" else A.SMOOTH_RB
-    opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100)
+    opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100,
+                          use_graph=0 if args.no_graph else 1)
     systems = []
     for op, bc in (("helmholtz", "D"), ("poisson", "N")):
         H = A.Hierarchy(2, (256, 256), 1.0 / 256, 2)
@@ -400,7 +411,8 @@ def bench_batched(args):
     from paper_2506_02663_amd import amg as A
     prec = A.MIXED if args.precision == "mixed" else A.FP64
     sm = A.SMOOTH_JACOBI if args.smoother == "jacobi" else A.SMOOTH_RB
-    opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100)
+    opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100,
+                          use_graph=0 if args.no_graph else 1)
     H = A.Hierarchy(2, (256, 256), h, 1)
     boxes, x0 = [], 0
     for s in sides:
