@@ -119,6 +119,8 @@ typedef struct {
   int64_t ncells;      /* interior cells */
   int64_t nstored;     /* elements of the packed buffer */
   int64_t nface;       /* elements of the face-data buffer */
+  int32_t fused_rb;    /* bit k set: FP32 red-black sweeps at depth k run both colours in one launch */
+  int32_t pad_;
 } amg_level_desc;
 
 typedef struct {
@@ -199,6 +201,13 @@ int amg_set_operator(amg_hier* h, int kind, double c);
 #define AMG_TUNE_MARCH2 0
 #define AMG_TUNE_MARCH3 1
 #define AMG_TUNE_ROW_ALIGN 2
+/* AMG_TUNE_FUSED_RB: 1 lets FP32 red-black sweeps run both colours in one
+ * launch on depths whose faces are all filled uniformly (single or isolated
+ * boxes with physical conditions, rows of 128 m or 128 m + (>= 4) cells,
+ * rows per plane a multiple of 4; such depths then use tiles of >= 4
+ * planes); 0 (default) keeps two launches per sweep, the faster form on
+ * gfx950 as measured.  The two forms agree to rounding. */
+#define AMG_TUNE_FUSED_RB 3
 int amg_set_tuning(amg_hier* h, int key, int value);
 
 /* Size of the exactly solved coarsest systems (Section 6.5 leaves the bottom

@@ -187,6 +187,7 @@ struct Depth {
   std::vector<BottomGroupD> groups;
   int64_t nstored = 0;
   bool fill_only = false;  // every ghost column is filled from its own row (no exchange or interpolated ghosts)
+  bool fuse_rb = false;    // the fused red-black sweep (k_rb2) applies to this depth
   int march = 2;  // cells each tile marches along the last direction
   // device copies
   BoxD* d_box = nullptr;
@@ -281,6 +282,7 @@ struct amg_hier {
   int march2 = MARCH2_DEFAULT, march3 = MARCH3_DEFAULT;  // tile march lengths
   int row_align = ROW_ALIGN_DEFAULT;                       // row alignment of the packed layout (elements)
   int bottom_cells = 0;  // coarsening stops once every component has at most this many cells (0: off)
+  int fuse_rb = 0;       // FP32 red-black sweeps in one launch where the depth allows it (opt-in)
   int dim = 2;
   int32_t base[3] = {1, 1, 1};
   double h0 = 1;

@@ -214,7 +214,22 @@ void smooth(const Run& R, int k, int smoother, int nsweeps, double omega, bool f
       std::swap(cur, oth);
     }
   } else {
-    for (int s = 0; s < nsweeps; ++s)
+    // FP32 forward sweeps after the first run both colours in one launch
+    // where the depth allows it
+    const bool fused = sizeof(T) == 4 && !R.tr && D.fuse_rb && R.H->fuse_rb;
+    for (int s = 0; s < nsweeps; ++s) {
+      if (fused && !(s == 0 && from_zero)) {
+        if (fill) {
+          Timed tm(R, AMG_T_FILL, k);
+          fill_op<T>(R, D, cur);
+        }
+        {
+          Timed tm(R, AMG_T_SWEEP, k);
+          launch_rb2<T>(D, cur, f, oth, alpha, beta, R.st);
+        }
+        std::swap(cur, oth);
+        continue;
+      }
       for (int col = 0; col < 2; ++col) {
         if (s == 0 && col == 0 && from_zero) {
           launch_rb<T>(R.dim, D, nullptr, f, cur, alpha, beta, 0, true, R.st);
@@ -231,6 +246,7 @@ void smooth(const Run& R, int k, int smoother, int nsweeps, double omega, bool f
         if (R.tr) launch_band<T>(R.dim, D, 2, cur, oth, alpha, beta, -beta, col, R.st);
         std::swap(cur, oth);
       }
+    }
   }
 }
 
@@ -641,6 +657,10 @@ int amg_set_tuning(amg_hier* H, int key, int value) {
       if (value < 2 || value > 4096 || (value & 1)) return fail(H, AMG_EINVAL, "march length must be even, 2..4096");
       (key == AMG_TUNE_MARCH2 ? H->march2 : H->march3) = value;
       return AMG_OK;
+    case AMG_TUNE_FUSED_RB:
+      if (value != 0 && value != 1) return fail(H, AMG_EINVAL, "fused red-black switch must be 0 or 1");
+      H->fuse_rb = value;
+      return AMG_OK;
     case AMG_TUNE_ROW_ALIGN:
       if (value < 2 || value > 256 || (value & (value - 1)))
         return fail(H, AMG_EINVAL, "alignment must be a power of two of at least 2");
@@ -778,6 +798,10 @@ int amg_level_info(const amg_hier* Hc, int level, amg_level_desc* out) {
   out->ncells = L.ncells;
   out->nstored = L.depths[0].nstored;
   out->nface = L.nface;
+  out->fused_rb = 0;
+  for (size_t k = 0; k < L.depths.size() && k < 31; ++k)
+    if (H->fuse_rb && L.depths[k].fuse_rb) out->fused_rb |= 1 << k;
+  out->pad_ = 0;
   return AMG_OK;
 }
 
@@ -1638,6 +1662,8 @@ int amg_time_sweep(amg_hier* H, int level, int dtype, int smoother, int n, void*
       const int gr = sizeof(T) == 4 ? 1 : 0;  // the form the FP32 V-cycle launches
       if (smoother == AMG_SMOOTH_JACOBI)
         launch_jacobi<T>(H->dim, D, cur, ff, oth, a, b, T(2.0 / 3.0), false, st, gr);
+      else if (sizeof(T) == 4 && D.fuse_rb && H->fuse_rb)
+        launch_rb2<T>(D, cur, ff, oth, a, b, st);  // one launch = both colours
       else
         launch_rb<T>(H->dim, D, cur, ff, oth, a, b, i & 1, false, st, gr);
       std::swap(cur, oth);
@@ -1681,6 +1707,7 @@ int amg_autotune(amg_hier* H, int level, int dtype, int smoother, int nreps, int
     T->c = H->c;
     T->row_align = H->row_align;
     T->bottom_cells = H->bottom_cells;
+    T->fuse_rb = H->fuse_rb;
     T->march2 = T->march3 = m;
     rc = amg_finalize(T);
     if (rc != AMG_OK) {

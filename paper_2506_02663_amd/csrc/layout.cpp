@@ -457,6 +457,17 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       for (int d = 0; d + 1 < dim; ++d)
         if (X.ucode[d][0] == 0xFF || X.ucode[d][1] == 0xFF) D.fill_only = false;
 
+    // the fused red-black sweep (3D) needs every face filled uniformly with
+    // both layers from its row, a last x-tile at least 4 wide, whole 4-row
+    // tiles and tiles of at least 4 planes
+    bool fuse_ok = H->fuse_rb && dim == 3 && D.fill_only && H->march3 >= 4;
+    for (const BoxD& X : D.boxd) {
+      for (int d = 0; d < 3; ++d)
+        for (int s = 0; s < 2; ++s)
+          if (X.ucode[d][s] != 5 && X.ucode[d][s] != 6) fuse_ok = false;
+      if ((X.n[0] % TILE_X != 0 && X.n[0] % TILE_X < 4) || X.n[1] % TILE3_Y != 0) fuse_ok = false;
+    }
+
     // ---- tiles (grouped by component, so each component is one range) ----
     D.tiles.clear();
     D.stiles.clear();
@@ -473,7 +484,7 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       }
       const int cap = dim == 2 ? H->march2 : H->march3;
       int64_t m = R / kTargetTiles;
-      m = std::max<int64_t>(2, std::min<int64_t>(cap, m));
+      m = std::max<int64_t>(fuse_ok ? 4 : 2, std::min<int64_t>(cap, m));
       CH = (int)(m & ~int64_t(1));
     }
     D.march = CH;
@@ -510,6 +521,9 @@ int plan_level(amg_hier* H, int l, std::string& err) {
         D.seg_ptr.push_back((int32_t)std::min(D.tiles.size(), a + kSeg));
       D.comp_seg_ptr.push_back((int32_t)D.seg_ptr.size() - 1);
     }
+    D.fuse_rb = fuse_ok && !D.stiles.empty();
+    for (const TileD& T : D.stiles)
+      if (T.len < 4) D.fuse_rb = false;
     prev_index = cur_index;
   }
 
