@@ -43,6 +43,9 @@ def parse():
                         "whose 1e-10 solve it reaches fastest of V(0..2, 1..4); 2,2 otherwise)")
     p.add_argument("--no-graph", action="store_true",
                    help="launch every kernel of a cycle directly instead of replaying its HIP graph")
+    p.add_argument("--plain", action="store_true",
+                   help="batched workload: the plain FP64 solver (every box solved on its own, its kernels "
+                        "launched directly, no graph) instead of the batched solve")
     p.add_argument("--bottom-cells", type=int, default=512,
                    help="single-level workloads: exact bottom solve once a depth has at most this many cells "
                         "(0: coarsen as far as the layout allows)")
@@ -376,6 +379,64 @@ def bench_amr(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_batched_plain(args, sides, fs, h, c, base):
+    """The plain FP64 solver on the batched workload: each box solved on its
+    own (one hierarchy per box size, reused for the boxes of that size), FP64
+    throughout, every kernel launched directly (no graph), the same smoother
+    and V(2,2) to 1e-10.  One step = all 1024 solves."""
+    import torch
+
+    from paper_2506_02663_amd import amg as A
+    sm = A.SMOOTH_JACOBI if args.smoother == "jacobi" else A.SMOOTH_RB
+    opts = A.default_opts(precision=A.FP64, smoother=sm, tol_rel=1e-10, max_cycles=100, use_graph=0)
+    hier = {}
+    for s in sorted(set(sides)):
+        H = A.Hierarchy(2, (s, s), h, 1)
+        H.set_level_boxes(0, [((0, 0), (s - 1, s - 1))])
+        for d in range(2):
+            for sd in (0, 1):
+                H.set_physical_bc(d, sd, A.DIRICHLET)
+        H.set_operator(A.HELMHOLTZ, c)
+        H.finalize()
+        hier[s] = H
+    fds = [torch.tensor(hier[s].pack(0, 0, lambda i, b, f=fs[k]: f), device="cuda") for k, s in enumerate(sides)]
+    xs = [torch.zeros_like(f) for f in fds]
+    ncell = int(sum(s * s for s in sides))
+    info = {"cycles": 0}
+
+    def step():
+        cyc = 0
+        for k, s in enumerate(sides):
+            xs[k].zero_()
+            st = hier[s].solve(0, xs[k], fds[k], None, opts)
+            if st["status"] != 0 or not st["converged"]:
+                raise RuntimeError(f"box {k} did not converge: {st}")
+            cyc = max(cyc, st["cycles"])
+        info["cycles"] = cyc
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {
+        "metric": "MG solve DOF/s to 1e-10 rel. residual, FP32-refined vs FP64; % HBM peak",
+        "value": ncell * args.steps / dt, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch of 1024 independent 2D boxes, sides 8m, m~U{2..32}, Dirichlet Helmholtz",
+                   "cells": ncell, "tol_rel": 1e-10, "cycles_max": info["cycles"], "smoother": args.smoother,
+                   "precision": "fp64", "solver": "plain: one box per solve, direct launches, no graph",
+                   "vcycle": "V(2,2)"},
+    }
+    if base:
+        out["cpu_baseline"] = base
+    print(json.dumps(out))
+
+
 def bench_batched(args):
     """1024 independent 2D boxes, sides 8m with m ~ U{2..32} (seed 0), h = 1/256,
     Dirichlet Helmholtz (I - cL) with c = 0.5 nu k, nu = 1e-3, k = h; each
@@ -409,6 +470,8 @@ def bench_batched(args):
     import torch
 
     from paper_2506_02663_amd import amg as A
+    if args.plain:
+        return bench_batched_plain(args, sides, fs, h, c, base)
     prec = A.MIXED if args.precision == "mixed" else A.FP64
     sm = A.SMOOTH_JACOBI if args.smoother == "jacobi" else A.SMOOTH_RB
     opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100,

@@ -972,14 +972,17 @@ __global__ void __launch_bounds__(1024) k_comp_mean_small(int nboxes, const BoxD
   __shared__ double mean;
   const int comp = blockIdx.x;
   if (!flag[comp]) return;
+  // rows of the box's cells: wavefront w takes rows w, w + 16, ..., its
+  // lanes the cells of the row (no per-cell index division)
+  const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
   double v = 0.0;
   for (int bi = 0; bi < nboxes; ++bi) {
     const BoxD b = boxes[bi];
     if (b.comp != comp) continue;
-    const int n = b.n[0] * b.n[1] * (DIM == 3 ? b.n[2] : 1);
-    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) {
-      const int x = i % b.n[0], r = i / b.n[0];
-      v += (double)a[cell_index<DIM>(b, x, DIM == 3 ? r % b.n[1] : r, DIM == 3 ? r / b.n[1] : 0)];
+    const int nrow = b.n[1] * (DIM == 3 ? b.n[2] : 1);
+    for (int r = w; r < nrow; r += 16) {
+      const int64_t c0 = cell_index<DIM>(b, 0, DIM == 3 ? r % b.n[1] : r, DIM == 3 ? r / b.n[1] : 0);
+      for (int x = lane; x < b.n[0]; x += 64) v += (double)a[c0 + x];
     }
   }
   v = block_sum<double>(v, sh);
@@ -989,11 +992,10 @@ __global__ void __launch_bounds__(1024) k_comp_mean_small(int nboxes, const BoxD
   for (int bi = 0; bi < nboxes; ++bi) {
     const BoxD b = boxes[bi];
     if (b.comp != comp) continue;
-    const int n = b.n[0] * b.n[1] * (DIM == 3 ? b.n[2] : 1);
-    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) {
-      const int x = i % b.n[0], r = i / b.n[0];
-      const int64_t c = cell_index<DIM>(b, x, DIM == 3 ? r % b.n[1] : r, DIM == 3 ? r / b.n[1] : 0);
-      a[c] = (T)((double)a[c] - m);
+    const int nrow = b.n[1] * (DIM == 3 ? b.n[2] : 1);
+    for (int r = w; r < nrow; r += 16) {
+      const int64_t c0 = cell_index<DIM>(b, 0, DIM == 3 ? r % b.n[1] : r, DIM == 3 ? r / b.n[1] : 0);
+      for (int x = lane; x < b.n[0]; x += 64) a[c0 + x] = (T)((double)a[c0 + x] - m);
     }
   }
 }
