@@ -635,14 +635,49 @@ __global__ void __launch_bounds__(512) k_rb2(const TileD* __restrict__ tiles, in
     h2n = old_at(e1, nz + 1);
   }
 
+  // x/y neighbours and f of a red cell, loaded one plane ahead so that the
+  // loads are in flight across the barrier and the black phase
+  struct Nb {
+    T xm1, xp1, xm2, xp2, ym1, yp1, ym2, yp2, fv;
+  };
+  auto load_nb = [&](int64_t ec) -> Nb {
+    return Nb{u[ec - 1],  u[ec + 1],      u[ec - 2],      u[ec + 2], u[ec - sy],
+              u[ec + sy], u[ec - 2 * sy], u[ec + 2 * sy], f[ec]};
+  };
+  auto red_of = [&](const Nb& n, T inv, T m2, T m1, T c0, T q1, T q2) -> T {
+    T ls = T(16) * (n.xm1 + n.xp1) - (n.xm2 + n.xp2) + T(16) * (m1 + q1) - (m2 + q2) + T(-30 * 3) * c0;
+    ls += T(16) * (n.ym1 + n.yp1) - (n.ym2 + n.yp2);
+    const T Au = alpha * c0 + beta * ls;
+    return c0 + T(1) * (n.fv - Au) * inv;
+  };
+  Nb nown{}, nring{};
+  T fblk = T(0), r2n = T(0), wn = T(0), vn = T(0);
+  // loads for the step of plane pn: its red inputs, f of the black cell at
+  // pn - 1 (the same lanes), ring values, and plane pn + 2 of the windows
+  auto prefetch = [&](int pn) {
+    if (ok) {
+      const bool red_n = !((par + pn) & 1);  // red at pn, black at pn - 1
+      if (pn <= pb && red_n) nown = load_nb(e0 + (int64_t)pn * sm);
+      if (red_n && pn - 1 >= p0 && pn - 1 < p1) fblk = f[e0 + (int64_t)(pn - 1) * sm];
+      if (pn + 2 < nz) wn = u[e0 + (int64_t)(pn + 2) * sm];
+    }
+    if (pn >= p0 && pn < p1) {
+      if (has1 && !((par1 + pn) & 1)) nring = load_nb(e1 + (int64_t)pn * sm);
+      if (has2) r2n = u[e2 + (int64_t)pn * sm];
+    }
+    if (has1 && pn + 2 < nz) vn = u[e1 + (int64_t)(pn + 2) * sm];
+  };
+  prefetch(pa);
   const int pe = p1;  // black at plane p1 - 1 is done in the step of plane p1
   for (int p = pa; p <= pe; ++p) {
     T (*L)[RB2_W] = pl[p % 3];
     const bool own_plane = p >= p0 && p < p1;
+    const Nb cown = nown, cring = nring;
+    const T cfb = fblk, cr2 = r2n;
     // red phase: plane p
     T v = T(0);
     if (ok && p <= pb) {
-      v = red_val(e0 + (int64_t)p * sm, p, par, dg.at(p, nz), w1, w2, w3, w4, w5);
+      v = ((par + p) & 1) ? w3 : red_of(cown, dg.at(p, nz), w1, w2, w3, w4, w5);
       if (own_plane) {
         L[ly][lx] = v;
         if (!((par + p) & 1)) out[e0 + (int64_t)p * sm] = v;
@@ -657,11 +692,15 @@ __global__ void __launch_bounds__(512) k_rb2(const TileD* __restrict__ tiles, in
       gzh2 = ghost2<T>(czh, r3, r2, r1, r0);
     }
     if (own_plane) {
-      if (has1)
-        L[yr1 - y0 + 2][xr1 - x0 + 2] = red_val(e1 + (int64_t)p * sm, p, par1, dr.at(p, nz), v0, v1, v2, v3, v4);
-      if (has2) L[yr2 - y0 + 2][xr2 - x0 + 2] = u[e2 + (int64_t)p * sm];
+      if (has1) L[yr1 - y0 + 2][xr1 - x0 + 2] = ((par1 + p) & 1) ? v2 : red_of(cring, dr.at(p, nz), v0, v1, v2, v3, v4);
+      if (has2) L[yr2 - y0 + 2][xr2 - x0 + 2] = cr2;
     }
-    __syncthreads();
+    if (p + 1 <= pe) prefetch(p + 1);  // (wn, vn: plane p + 3, entering the windows below)
+    // the LDS plane is complete: only LDS needs ordering here, so the global
+    // loads just issued stay in flight
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     // black phase: plane q = p - 1
     const int q = p - 1;
     if (ok && q >= p0 && q < p1 && ((par + q) & 1)) {
@@ -701,15 +740,15 @@ __global__ void __launch_bounds__(512) k_rb2(const TileD* __restrict__ tiles, in
       T ls = T(16) * (xm1 + xp1) - (xm2 + xp2) + T(16) * (zm1 + zp1) - (zm2 + zp2) + T(-30 * 3) * c0;
       ls += T(16) * (ym1 + yp1) - (ym2 + yp2);
       const T Au = alpha * c0 + beta * ls;
-      const int64_t eq = e0 + (int64_t)q * sm;
-      out[eq] = c0 + T(1) * (f[eq] - Au) * dg.at(q, nz);
+      out[e0 + (int64_t)q * sm] = c0 + T(1) * (cfb - Au) * dg.at(q, nz);
     }
-    // advance the old windows to plane p + 1
+    // advance the old windows to plane p + 1 (plane p + 3 enters; its load
+    // was issued with the prefetch)
     if (ok) {
       T nw;
       const int r = p + 3;
       if (r < nz) {
-        nw = u[e0 + (int64_t)r * sm];
+        nw = wn;
       } else if (r == nz) {  // w2..w5 hold planes nz-4 .. nz-1
         nw = ghost1<T>(czh, w5, w4, w3, w2);
         g2n = ghost2<T>(czh, w5, w4, w3, w2);
@@ -727,7 +766,7 @@ __global__ void __launch_bounds__(512) k_rb2(const TileD* __restrict__ tiles, in
       T nv;
       const int r = p + 3;
       if (r < nz) {
-        nv = u[e1 + (int64_t)r * sm];
+        nv = vn;
       } else if (r == nz) {  // v1..v4 hold planes nz-4 .. nz-1
         nv = ghost1<T>(czh, v4, v3, v2, v1);
         h2n = ghost2<T>(czh, v4, v3, v2, v1);
