@@ -46,6 +46,10 @@ def parse():
     p.add_argument("--plain", action="store_true",
                    help="batched workload: the plain FP64 solver (every box solved on its own, its kernels "
                         "launched directly, no graph) instead of the batched solve")
+    p.add_argument("--omega-rb", default="1.0,1.3",
+                   help="single-level workloads: red-black relaxation factor of the Helmholtz and the Poisson "
+                        "solve (1: plain red-black; 1.3 takes the Neumann Poisson solve from 13 to 8 V(1,3) cycles "
+                        "in 3D)")
     p.add_argument("--bottom-cells", type=int, default=512,
                    help="single-level workloads: exact bottom solve once a depth has at most this many cells "
                         "(0: coarsen as far as the layout allows)")
@@ -107,10 +111,10 @@ def single_level_problems(dim, n, nu):
     return h, c, [("helmholtz", "D", helm), ("poisson", "N", pois)]
 
 
-def cpu_baseline(dim, n, nu, smoother, nu1=2, nu2=2, bottom_cells=0):
+def cpu_baseline(dim, n, nu, smoother, nu1=2, nu2=2, bottom_cells=0, omega_rb=None):
     """The FP64 oracle on a bounded sample of the same workload (same recipe,
-    same smoother, V-cycle and bottom size, smaller grid), single-threaded,
-    timed on the host."""
+    same smoother, relaxation, V-cycle and bottom size, smaller grid),
+    single-threaded, timed on the host."""
     import numpy as np
 
     from oracle import mg
@@ -123,13 +127,14 @@ def cpu_baseline(dim, n, nu, smoother, nu1=2, nu2=2, bottom_cells=0):
         fa = lev.zeros()
         fa[lev.inner] = f
         x, st = mg.solve(lev, fa, op, c, tol_rel=1e-10, max_cycles=100, smoother=smoother, nu1=nu1, nu2=nu2,
-                         bottom_cells=bottom_cells)
+                         bottom_cells=bottom_cells, omega_rb=(omega_rb or {}).get(op, 1.0))
         assert st["converged"]
         dof += lev.ncells
     dt = time.perf_counter() - t0
     return {"value": dof / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
             "sample": f"{dim}D {n}^{dim}: Helmholtz (Dirichlet) + Neumann Poisson solves to 1e-10, "
-                      f"same recipe, smoother ({smoother}), V({nu1},{nu2}) and bottom size ({bottom_cells}) "
+                      f"same recipe, smoother ({smoother}, omega_rb {omega_rb}), V({nu1},{nu2}) and bottom size "
+                      f"({bottom_cells}) "
                       f"as the timed workload, {dt:.1f} s"}
 
 
@@ -155,7 +160,9 @@ def main():
     base = None
     if not args.no_cpu_baseline:
         # before the GPU is touched: single-threaded numpy
-        base = cpu_baseline(*sample, args.smoother, nu1, nu2, args.bottom_cells)
+        w_rb = dict(zip(("helmholtz", "poisson"), map(float, args.omega_rb.split(","))))
+        base = cpu_baseline(*sample, args.smoother, nu1, nu2, args.bottom_cells,
+                            w_rb if args.smoother == "rb" else None)
 
     import torch
     if args.copy_probe:
@@ -166,8 +173,10 @@ def main():
     h, c, probs = single_level_problems(dim, n, nu)
     prec = A.MIXED if args.precision == "mixed" else A.FP64
     sm = A.SMOOTH_JACOBI if args.smoother == "jacobi" else A.SMOOTH_RB
-    opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100, nu1=nu1, nu2=nu2,
-                          use_graph=0 if args.no_graph else 1)
+    w_rb = dict(zip(("helmholtz", "poisson"), map(float, args.omega_rb.split(","))))
+    opts = {op: A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100, nu1=nu1, nu2=nu2,
+                               use_graph=0 if args.no_graph else 1, omega_rb=w_rb[op])
+            for op in ("helmholtz", "poisson")}
     systems = []
     march = None
     for op, bc, f in probs:
@@ -196,7 +205,7 @@ def main():
     def step():
         for op, H, x, fd in systems:
             x.zero_()
-            st = H.solve(0, x, fd, None, opts)
+            st = H.solve(0, x, fd, None, opts[op])
             if st["status"] != 0 or not st["converged"]:
                 raise RuntimeError(f"{op} solve did not converge: {st}")
             cycles[op] = st["cycles"]
@@ -243,7 +252,8 @@ def main():
         "config": {"workload": f"{dim}D single level {n}^{dim}, Helmholtz (Dirichlet, nu={nu}) + Neumann Poisson",
                    "cells": n ** dim, "dof_per_step": dof_step, "tol_rel": 1e-10,
                    "cycles": cycles, "smoother": args.smoother, "precision": args.precision,
-                   "graph": not args.no_graph, "vcycle": f"V({nu1},{nu2})", "march": march, "bottom_cells": args.bottom_cells,
+                   "graph": not args.no_graph, "vcycle": f"V({nu1},{nu2})",
+                   "omega_rb": w_rb if args.smoother == "rb" else None, "march": march, "bottom_cells": args.bottom_cells,
                    "depths": systems[0][1].level_info(0).depths},
     }
     if not args.no_timing:

@@ -143,6 +143,8 @@ typedef struct {
   double tol_abs;
   int32_t use_graph;     /* 1: capture the outer cycle once into a HIP graph and replay it */
   int32_t pad_;
+  double omega_rb;       /* red-black: each half-sweep adds omega_rb times its correction
+                            (1: plain red-black; over-relaxation > 1), 0 < omega_rb < 2 */
 } amg_solve_opts;
 
 typedef struct {
@@ -278,7 +280,8 @@ int amg_residual(amg_hier* h, int level, int depth, int dtype, const void* u, co
 
 /* nsweeps homogeneous sweeps of the chosen smoother on u (ghosts refilled
  * before each sweep and half-sweep); tmp is a second buffer of the same
- * layout.  The result is in u. */
+ * layout.  omega: the Jacobi weight, or the red-black relaxation factor of
+ * each half-sweep (1: plain).  The result is in u. */
 int amg_smooth(amg_hier* h, int level, int depth, int dtype, int smoother, int nsweeps, double omega,
                void* u, const void* f, void* tmp, void* stream);
 

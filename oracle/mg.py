@@ -70,14 +70,17 @@ def jacobi(lev, e, f, op, c, D, omega, nsweeps, transpose=False):
     return e
 
 
-def red_black(lev, e, f, op, c, D, nsweeps, transpose=False):
+def red_black(lev, e, f, op, c, D, nsweeps, transpose=False, omega=1.0):
+    """Red-black half-sweeps (reading R-4): each colour in turn takes omega
+    times its Jacobi correction from the current iterate (omega = 1: plain;
+    > 1 over-relaxed)."""
     red = lev.colour() & lev.mask
     black = ~lev.colour() & lev.mask
     for _ in range(nsweeps):
         for sel in (red, black):
             r = f - _A(lev, e, op, c, transpose)
             e = e.copy()
-            e[sel] += r[sel] / D[sel]
+            e[sel] += omega * r[sel] / D[sel]
     return e
 
 
@@ -131,11 +134,11 @@ class MG:
     matrix."""
 
     def __init__(self, lev, op, c, nu1=2, nu2=2, smoother="jacobi", omega=2.0 / 3.0, transpose=False,
-                 bottom_cells=0):
+                 bottom_cells=0, omega_rb=1.0):
         self.levels = lev.hierarchy(bottom_cells)
         self.op, self.c = op, c
         self.transpose = transpose
-        self.nu1, self.nu2, self.smoother, self.omega = nu1, nu2, smoother, omega
+        self.nu1, self.nu2, self.smoother, self.omega, self.omega_rb = nu1, nu2, smoother, omega, omega_rb
         self.D = [l.diagonal(op, c) for l in self.levels]
         self.sing = [l.singular_components(op) for l in self.levels]
         self.bottom = Bottom(self.levels[-1], op, c, transpose)
@@ -144,7 +147,7 @@ class MG:
         lev = self.levels[k]
         if self.smoother == "jacobi":
             return jacobi(lev, e, f, self.op, self.c, self.D[k], self.omega, n, self.transpose)
-        return red_black(lev, e, f, self.op, self.c, self.D[k], n, self.transpose)
+        return red_black(lev, e, f, self.op, self.c, self.D[k], n, self.transpose, self.omega_rb)
 
     def vcycle(self, f, k=0):
         """Correction e with A_hom e ~= f on depth k (homogeneous ghosts)."""
@@ -223,7 +226,7 @@ def norm_inf(lev, a):
 
 def solve(lev, f, op, c, fd=None, cfv=None, x0=None, nu1=2, nu2=2, smoother="jacobi",
           omega=2.0 / 3.0, tol_rel=1e-10, tol_abs=0.0, max_cycles=50, shift=True, mg=None, transpose=False,
-          cf_delta=False, bottom_cells=0):
+          cf_delta=False, bottom_cells=0, omega_rb=1.0):
     """Outer residual-correction loop in FP64:
     r = f - A(x); s = ||r||_inf; e = V(r / s); x += s e; remove the mean of x
     on every singular component; stop by the max-norm criterion above.
@@ -233,7 +236,7 @@ def solve(lev, f, op, c, fd=None, cfv=None, x0=None, nu1=2, nu2=2, smoother="jac
     mean-free, which is the RHS shift with zero face data."""
     if transpose and (fd is not None or cfv is not None):
         raise ValueError("the adjoint system is homogeneous")
-    mg = mg or MG(lev, op, c, nu1, nu2, smoother, omega, transpose, bottom_cells)
+    mg = mg or MG(lev, op, c, nu1, nu2, smoother, omega, transpose, bottom_cells, omega_rb)
     sing = mg.sing[0]
     defects = []
     if shift and sing and cf_delta:

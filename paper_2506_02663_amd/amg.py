@@ -40,7 +40,8 @@ class BoxDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("smoother", C.c_int32), ("precision", C.c_int32),
                 ("solvability", C.c_int32), ("max_cycles", C.c_int32), ("omega", C.c_double),
-                ("tol_rel", C.c_double), ("tol_abs", C.c_double), ("use_graph", C.c_int32), ("pad_", C.c_int32)]
+                ("tol_rel", C.c_double), ("tol_abs", C.c_double), ("use_graph", C.c_int32), ("pad_", C.c_int32),
+                ("omega_rb", C.c_double)]
 
 
 class SolveStats(C.Structure):
@@ -373,7 +374,11 @@ class Hierarchy:
             self._need(t, level, depth, nm, (u.dtype,))
         self._check(lib().amg_residual(self.h, level, depth, self._dt(u), _ptr(u), _ptr(f), _ptr(r), _stream()))
 
-    def smooth(self, level, depth, u, f, tmp, smoother=SMOOTH_JACOBI, nsweeps=1, omega=2.0 / 3.0):
+    def smooth(self, level, depth, u, f, tmp, smoother=SMOOTH_JACOBI, nsweeps=1, omega=None):
+        """omega: the Jacobi weight (default 2/3) or the red-black relaxation
+        factor (default 1)."""
+        if omega is None:
+            omega = 2.0 / 3.0 if smoother == SMOOTH_JACOBI else 1.0
         for t, nm in ((u, "u"), (f, "f"), (tmp, "tmp")):
             self._need(t, level, depth, nm, (u.dtype,))
         self._check(lib().amg_smooth(self.h, level, depth, self._dt(u), smoother, nsweeps, float(omega), _ptr(u),

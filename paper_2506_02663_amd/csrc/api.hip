@@ -225,14 +225,14 @@ void smooth(const Run& R, int k, int smoother, int nsweeps, double omega, bool f
         }
         {
           Timed tm(R, AMG_T_SWEEP, k);
-          launch_rb2<T>(D, cur, f, oth, alpha, beta, R.st);
+          launch_rb2<T>(D, cur, f, oth, alpha, beta, (T)omega, R.st);
         }
         std::swap(cur, oth);
         continue;
       }
       for (int col = 0; col < 2; ++col) {
         if (s == 0 && col == 0 && from_zero) {
-          launch_rb<T>(R.dim, D, nullptr, f, cur, alpha, beta, 0, true, R.st);
+          launch_rb<T>(R.dim, D, nullptr, f, cur, alpha, beta, (T)omega, 0, true, R.st);
           continue;
         }
         if (fill) {
@@ -241,14 +241,18 @@ void smooth(const Run& R, int k, int smoother, int nsweeps, double omega, bool f
         }
         {
           Timed tm(R, AMG_T_SWEEP, k);
-          launch_rb<T>(R.dim, D, cur, f, oth, alpha, beta, col, false, R.st, gr);
+          launch_rb<T>(R.dim, D, cur, f, oth, alpha, beta, (T)omega, col, false, R.st, gr);
         }
-        if (R.tr) launch_band<T>(R.dim, D, 2, cur, oth, alpha, beta, -beta, col, R.st);
+        if (R.tr) launch_band<T>(R.dim, D, 2, cur, oth, alpha, beta, -(T)omega * beta, col, R.st);
         std::swap(cur, oth);
       }
     }
   }
 }
+
+// relaxation factor of the chosen smoother: the Jacobi weight, or the
+// red-black half-sweeps' factor
+inline double relax(const amg_solve_opts& o) { return o.smoother == AMG_SMOOTH_RB ? o.omega_rb : o.omega; }
 
 // One homogeneous V-cycle from e = 0; f0 is the depth-0 right-hand side, e0
 // and t0 the two depth-0 buffers.  Returns the buffer that holds e.
@@ -268,7 +272,7 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0) {
     // boxes that end here: exact solve, written to both buffers of the depth
     if (!D.groups.empty()) launch_bottom<T>(D, L.d_mat, L.d_idx, f[k], cur[k], R.tr, R.st, oth[k]);
     if (k + 1 >= K || D.stiles.empty()) break;
-    smooth<T>(R, k, o.smoother, o.nu1, o.omega, true, cur[k], oth[k], f[k]);
+    smooth<T>(R, k, o.smoother, o.nu1, relax(o), true, cur[k], oth[k], f[k]);
     T alpha, beta;
     coefs<T>(R.H, D, alpha, beta);
     {
@@ -295,7 +299,7 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0) {
       Timed tm(R, AMG_T_PROLONG, k);
       launch_prolong<T>(R.dim, D, L.depths[k + 1], cur[k + 1], cur[k], R.st);
     }
-    smooth<T>(R, k, o.smoother, o.nu2, o.omega, false, cur[k], oth[k], f[k]);
+    smooth<T>(R, k, o.smoother, o.nu2, relax(o), false, cur[k], oth[k], f[k]);
   }
   return cur[0];
 }
@@ -565,6 +569,8 @@ void amg_default_opts(amg_solve_opts* o) {
   o->tol_rel = 1e-10;
   o->tol_abs = 0.0;
   o->use_graph = 1;
+  o->pad_ = 0;
+  o->omega_rb = 1.0;
 }
 
 int amg_create(int dim, const int32_t* base_cells, double h0, int ratio, int nlevels, amg_hier** out) {
@@ -980,6 +986,7 @@ static int check_opts(amg_hier* H, const amg_solve_opts& o) {
   if (o.nu1 < 0 || o.nu2 < 0 || o.max_cycles < 0 || o.max_cycles > 100000 ||
       (o.smoother != AMG_SMOOTH_JACOBI && o.smoother != AMG_SMOOTH_RB) ||
       (o.precision != AMG_FP64 && o.precision != AMG_MIXED) || !(o.omega > 0) ||
+      !(o.omega_rb > 0 && o.omega_rb < 2) ||
       (o.solvability != AMG_SOLV_RHS_SHIFT && o.solvability != AMG_SOLV_OFF && o.solvability != AMG_SOLV_CF_DELTA))
     return fail(H, AMG_EINVAL, "bad solve options");
   return AMG_OK;
@@ -1234,6 +1241,8 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
                                 o.smoother, o.nu1, o.nu2, (int64_t)H->timer.on};
     int64_t ob;
     memcpy(&ob, &o.omega, sizeof ob);
+    key.push_back(ob);
+    memcpy(&ob, &o.omega_rb, sizeof ob);
     key.push_back(ob);
     if (!G.exec || G.key != key) {
       G.release();
@@ -1663,9 +1672,9 @@ int amg_time_sweep(amg_hier* H, int level, int dtype, int smoother, int n, void*
       if (smoother == AMG_SMOOTH_JACOBI)
         launch_jacobi<T>(H->dim, D, cur, ff, oth, a, b, T(2.0 / 3.0), false, st, gr);
       else if (sizeof(T) == 4 && D.fuse_rb && H->fuse_rb)
-        launch_rb2<T>(D, cur, ff, oth, a, b, st);  // one launch = both colours
+        launch_rb2<T>(D, cur, ff, oth, a, b, T(1), st);  // one launch = both colours
       else
-        launch_rb<T>(H->dim, D, cur, ff, oth, a, b, i & 1, false, st, gr);
+        launch_rb<T>(H->dim, D, cur, ff, oth, a, b, T(1), i & 1, false, st, gr);
       std::swap(cur, oth);
     }
     (void)hipEventRecord(e1, st);

@@ -37,9 +37,9 @@ void launch_jacobi(int dim, const Depth& D, const T* u, const T* f, T* out, T al
 // both colours of one red-black sweep in one launch (FP32 3D, depths with
 // D.fuse_rb); out receives the whole swept array
 template <typename T>
-void launch_rb2(const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, hipStream_t st);
+void launch_rb2(const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, T omega, hipStream_t st);
 template <typename T>
-void launch_rb(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, int col, bool zero,
+void launch_rb(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, T omega, int col, bool zero,
                hipStream_t st, int gr = 0);
 template <typename T>
 void launch_resid_restrict(int dim, const Depth& F, const Depth& C, const T* u, const T* f, T* fc, T alpha, T beta,

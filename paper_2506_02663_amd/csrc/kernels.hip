@@ -342,7 +342,7 @@ __device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __
 
 // OP_RESID : out = f - A u (f == NULL: out = A u); PART: per-tile max |out|
 // OP_JACOBI: out = u + omega (f - A u) / diag
-// OP_RB    : out = u + (f - A u) / diag on cells of colour `col`, else u
+// OP_RB    : out = u + omega (f - A u) / diag on cells of colour `col`, else u (omega = 1: plain)
 // with A u = alpha u + beta * (sum of the 1-D stencils of eq. discreteOps c).
 // Along the march direction the neighbours come from the thread's register
 // queue; across it they are re-read through the L1/L2 caches (the
@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
           vsum += (double)v;
         }
       } else if (OP == OP_JACOBI || (((par0 + p) & 1) == col)) {
-        out[c] = q2 + (OP == OP_JACOBI ? omega : T(1)) * (f[c] - Au) *
+        out[c] = q2 + omega * (f[c] - Au) *
                           dg.inv(b, codes, p, C.x, DIM == 2 ? p : C.y, DIM == 2 ? 0 : p);
       } else {
         out[c] = q2;
@@ -495,7 +495,7 @@ template <typename T>
 __global__ void __launch_bounds__(512) k_rb2(const TileD* __restrict__ tiles, int ntiles,
                                              const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
                                              const T* u, const T* __restrict__ f, T* __restrict__ out, T alpha,
-                                             T beta) {
+                                             T beta, T omega) {
   __shared__ T pl[3][RB2_H][RB2_W];
   const int ti = tile_of_block(ntiles);
   if (ti < 0) return;
@@ -542,7 +542,7 @@ __global__ void __launch_bounds__(512) k_rb2(const TileD* __restrict__ tiles, in
            T(-30 * 3) * c0;
     ls += T(16) * (u[ec - sy] + u[ec + sy]) - (u[ec - 2 * sy] + u[ec + 2 * sy]);
     const T Au = alpha * c0 + beta * ls;
-    return c0 + T(1) * (f[ec] - Au) * inv;
+    return c0 + omega * (f[ec] - Au) * inv;
   };
   // inverse diagonals of a column at planes 0, 1, the middle, nz - 2, nz - 1
   // (the faces across the march carry one code each, so nothing else varies)
@@ -648,7 +648,7 @@ __global__ void __launch_bounds__(512) k_rb2(const TileD* __restrict__ tiles, in
     T ls = T(16) * (n.xm1 + n.xp1) - (n.xm2 + n.xp2) + T(16) * (m1 + q1) - (m2 + q2) + T(-30 * 3) * c0;
     ls += T(16) * (n.ym1 + n.yp1) - (n.ym2 + n.yp2);
     const T Au = alpha * c0 + beta * ls;
-    return c0 + T(1) * (n.fv - Au) * inv;
+    return c0 + omega * (n.fv - Au) * inv;
   };
   Nb nown{}, nring{};
   T fblk = T(0), r2n = T(0), wn = T(0), vn = T(0);
@@ -740,7 +740,7 @@ __global__ void __launch_bounds__(512) k_rb2(const TileD* __restrict__ tiles, in
       T ls = T(16) * (xm1 + xp1) - (xm2 + xp2) + T(16) * (zm1 + zp1) - (zm2 + zp2) + T(-30 * 3) * c0;
       ls += T(16) * (ym1 + yp1) - (ym2 + yp2);
       const T Au = alpha * c0 + beta * ls;
-      out[e0 + (int64_t)q * sm] = c0 + T(1) * (cfb - Au) * dg.at(q, nz);
+      out[e0 + (int64_t)q * sm] = c0 + omega * (cfb - Au) * dg.at(q, nz);
     }
     // advance the old windows to plane p + 1 (plane p + 3 enters; its load
     // was issued with the prefetch)
@@ -861,7 +861,7 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
         const int cy = DIM == 2 ? p : C.y, cz = DIM == 2 ? 0 : p;
         const bool u0 = OP == OP_JACOBI || (((par0 + p) & 1) == col);
         const bool u1 = OP == OP_JACOBI || (((par0 + p + 1) & 1) == col);
-        const T wgt = OP == OP_JACOBI ? omega : T(1);
+        const T wgt = omega;
         o0 = u0 ? q2.a + wgt * (fv.a - A0) * d0.inv(b, codes, p, C.x, cy, cz) : q2.a;
         o1 = u1 ? q2.b + wgt * (fv.b - A1) * d1.inv(b, codes, p, C.x + 1, cy, cz) : q2.b;
       }
@@ -918,7 +918,7 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
     for (int p = C.p0; p < C.p1; ++p)
 
 // first sweep from a zero iterate: Jacobi out = omega f / diag; red-black
-// (red half) out = f / diag on red cells, 0 on black ones
+// (red half) out = omega f / diag on red cells, 0 on black ones
 template <typename T, int DIM, bool RB>
 __global__ void __launch_bounds__(256) k_sweep0(const TileD* __restrict__ tiles, int ntiles,
                                                 const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
@@ -934,7 +934,7 @@ __global__ void __launch_bounds__(256) k_sweep0(const TileD* __restrict__ tiles,
   d0.init(b, codes, C.x, C.y, alpha, beta, true);
   d1.init(b, codes, C.x + 1, C.y, alpha, beta, C.ok1);
   const int par0 = (b.lo[0] + C.x + (DIM == 3 ? b.lo[1] + C.y : 0) + b.lo[DIM - 1]) & 1;
-  const T w = RB ? T(1) : omega;
+  const T w = omega;
   for (int p = C.p0; p < C.p1; ++p) {
     const int cy = DIM == 2 ? p : C.y, cz = DIM == 2 ? 0 : p;
     const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
@@ -1960,11 +1960,11 @@ void launch_residual(int dim, const Depth& D, bool all, const T* u, const T* f, 
 }
 
 template <typename T>
-void launch_rb2(const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, hipStream_t st) {
+void launch_rb2(const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, T omega, hipStream_t st) {
   const size_t n = D.stiles.size();
   if (!n) return;
   hipLaunchKernelGGL((k_rb2<T>), grid8(n), dim3(512), 0, st, D.d_stiles, (int)n, D.d_box, D.d_codes, u, f, out, alpha,
-                     beta);
+                     beta, omega);
 }
 
 template <typename T>
@@ -1985,20 +1985,20 @@ void launch_jacobi(int dim, const Depth& D, const T* u, const T* f, T* out, T al
 }
 
 template <typename T>
-void launch_rb(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, int col, bool zero,
+void launch_rb(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, T omega, int col, bool zero,
                hipStream_t st, int gr) {
   const size_t n = D.stiles.size();
   if (!n) return;
   if (zero) {
     if (dim == 2)
       hipLaunchKernelGGL((k_sweep0<T, 2, true>), grid8(n), threads<2>(), 0, st, D.d_stiles, (int)n, D.d_box, D.d_codes,
-                         f, out, alpha, beta, T(1));
+                         f, out, alpha, beta, omega);
     else
       hipLaunchKernelGGL((k_sweep0<T, 3, true>), grid8(n), threads<3>(), 0, st, D.d_stiles, (int)n, D.d_box, D.d_codes,
-                         f, out, alpha, beta, T(1));
+                         f, out, alpha, beta, omega);
     return;
   }
-  march<T, OP_RB, false>(dim, D.d_stiles, n, D, u, f, out, alpha, beta, T(1), col, nullptr, st, nullptr, gr);
+  march<T, OP_RB, false>(dim, D.d_stiles, n, D, u, f, out, alpha, beta, omega, col, nullptr, st, nullptr, gr);
 }
 
 template <typename T>
@@ -2295,8 +2295,8 @@ void launch_zero(T* a, int64_t n, hipStream_t st) {
   template void launch_band<T>(int, const Depth&, int, const T*, T*, T, T, T, int, hipStream_t);                  \
   template void launch_residual<T>(int, const Depth&, bool, const T*, const T*, T*, T, T, double*, hipStream_t);  \
   template void launch_jacobi<T>(int, const Depth&, const T*, const T*, T*, T, T, T, bool, hipStream_t, int);     \
-  template void launch_rb<T>(int, const Depth&, const T*, const T*, T*, T, T, int, bool, hipStream_t, int);       \
-  template void launch_rb2<T>(const Depth&, const T*, const T*, T*, T, T, hipStream_t);                            \
+  template void launch_rb<T>(int, const Depth&, const T*, const T*, T*, T, T, T, int, bool, hipStream_t, int);    \
+  template void launch_rb2<T>(const Depth&, const T*, const T*, T*, T, T, T, hipStream_t);                         \
   template void launch_resid_restrict<T>(int, const Depth&, const Depth&, const T*, const T*, T*, T, T,           \
                                          hipStream_t);                                                            \
   template void launch_restrict<T>(int, const Depth&, const Depth&, const T*, T*, hipStream_t);                   \

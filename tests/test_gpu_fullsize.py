@@ -1,5 +1,6 @@
 """The benchmark workloads at full size, in the configuration the benchmark
-times (mixed precision, red-black V(1,3) in 3D and V(2,2) for the batch, 1e-10): the GPU solutions satisfy
+times (mixed precision, red-black V(1,3) in 3D with the Poisson solve
+over-relaxed by 1.3, V(2,2) for the batch, 1e-10): the GPU solutions satisfy
 the oracle's discrete systems, checked by evaluating the oracle's operator
 on the GPU solution everywhere (3D 256^3) or on a sample of boxes (the batch
 of 1024 boxes), and one operator application agrees with the oracle element
@@ -54,7 +55,8 @@ def test_3d_256_solution_satisfies_oracle_system(op, bc, bottom):
     assert H.level_info(0).depths == (6 if bottom else 7)
     fd = torch.tensor(H.pack(0, 0, lambda i, b: f), device="cuda")
     x = torch.zeros_like(fd)
-    st = H.solve(0, x, fd, None, A.default_opts(**OPTS3))
+    # the benchmark's red-black relaxation: 1.3 for the Poisson solve
+    st = H.solve(0, x, fd, None, A.default_opts(**OPTS3, omega_rb=1.3 if op == "poisson" else 1.0))
     assert st["status"] == 0 and st["converged"], st
     lev = Level(shape, h, [((0,) * 3, (n - 1,) * 3)], {(d, s): bc for d in range(3) for s in (0, 1)})
     xs = lev.zeros()
