@@ -38,6 +38,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-timing", action="store_true", help="skip the per-kernel event timing")
     p.add_argument("--no-autotune", action="store_true", help="keep the default tile march length")
+    p.add_argument("--march", type=int, default=0,
+                   help="single-level workloads: this tile march length instead of the autotuner's choice")
     p.add_argument("--nu", default=None,
                    help="pre,post smoothing steps of the V-cycle (default: 1,3 for the 3D single level, "
                         "whose 1e-10 solve it reaches fastest of V(0..2, 1..4); 2,2 otherwise)")
@@ -186,7 +188,10 @@ def main():
             for s in (0, 1):
                 H.set_physical_bc(d, s, A.DIRICHLET if bc == "D" else A.NEUMANN)
         H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c)
-        if not args.no_autotune:
+        if args.march:
+            march = args.march
+            H.set_tuning(A.TUNE_MARCH2 if dim == 2 else A.TUNE_MARCH3, march)
+        elif not args.no_autotune:
             # tile march length of the finest sweep, timed once (setup, untimed)
             if march is None:
                 march, _ = H.autotune(0, A.F32 if prec == A.MIXED else A.F64, sm)
