@@ -339,8 +339,10 @@ def bench_amr(args):
     from paper_2506_02663_amd import amg as A
     prec = A.MIXED if args.precision == "mixed" else A.FP64
     sm = A.SMOOTH_JACOBI if args.smoother == "jacobi" else A.SMOOTH_RB
-    opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100,
-                          use_graph=0 if args.no_graph else 1)
+    w_rb = dict(zip(("helmholtz", "poisson"), map(float, args.omega_rb.split(","))))
+    opts = {op: A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100,
+                               use_graph=0 if args.no_graph else 1, omega_rb=w_rb[op])
+            for op in ("helmholtz", "poisson")}
     systems = []
     for op, bc in (("helmholtz", "D"), ("poisson", "N")):
         H = A.Hierarchy(2, (256, 256), 1.0 / 256, 2)
@@ -367,7 +369,7 @@ def bench_amr(args):
         for op, H, xs, fs in systems:
             for x in xs:
                 x.zero_()
-            st = H.solve_composite(xs, fs, None, opts)
+            st = H.solve_composite(xs, fs, None, opts[op])
             if st["status"] != 0 or not st["converged"]:
                 raise RuntimeError(f"{op} composite solve did not converge: {st}")
             cycles[op] = st["cycles"]
@@ -387,7 +389,8 @@ def bench_amr(args):
         "vs_baseline": None, "dtype": "f32-in-f64" if prec == A.MIXED else "f64", "data": "synthetic",
         "config": {"workload": "2D two-level AMR 256^2 + 56 boxes of 32^2 (ratio 2), composite Helmholtz + "
                                "composite Neumann Poisson", "dof_per_step": 2 * nvalid, "tol_rel": 1e-10,
-                   "cycles": cycles, "smoother": args.smoother, "precision": args.precision},
+                   "cycles": cycles, "smoother": args.smoother, "precision": args.precision,
+                   "omega_rb": w_rb if args.smoother == "rb" else None},
     }
     if base is not None:
         out["cpu_baseline"] = base

@@ -327,9 +327,10 @@ def correct_level(H, U, f, op, c, fd, MGl, l, sing):
 
 
 def composite_solve(H, f, op, c, fd=None, tol_rel=1e-10, tol_abs=0.0, max_cycles=100, nu1=2, nu2=2,
-                    smoother="jacobi", shift=True):
-    """The composite cycle described in the module docstring, from U = 0."""
-    MG = [mg.MG(lev, op, c, nu1, nu2, smoother) for lev in H.levels]
+                    smoother="jacobi", shift=True, omega_rb=1.0):
+    """The composite cycle described in the module docstring, from U = 0
+    (omega_rb: the red-black relaxation factor of the level cycles)."""
+    MG = [mg.MG(lev, op, c, nu1, nu2, smoother, omega_rb=omega_rb) for lev in H.levels]
     sing = H.singular(op)
     defect = 0.0
     if sing and shift:

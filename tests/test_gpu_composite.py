@@ -121,3 +121,24 @@ def test_composite_solve(name, bc, op, c):
             assert np.allclose(hist[:k], ho[:k], rtol=1e-5, atol=1e-14 * ho[0])
         if OH.singular(op):
             assert np.isclose(st["defects"][0], sto["defect"], rtol=1e-9, atol=1e-13)
+
+
+@pytest.mark.parametrize("name,bc,op,c", [cs for cs in CASES if cs[2] == "poisson"][:2] + [CASES[0]])
+def test_composite_solve_over_relaxed_red_black(name, bc, op, c):
+    """The composite cycle with over-relaxed red-black level cycles (omega_rb
+    1.3) against the oracle's composite solve with the same factor."""
+    OH, base, h0, boxes = make_oracle(name, bc)
+    H = make_gpu(base, h0, boxes, bc, op, c)
+    F = random_levels(OH, 6)
+    Uo, sto = amr.composite_solve(OH, F, op, c, None, tol_rel=1e-12, max_cycles=200, smoother="rb", omega_rb=1.3)
+    assert sto["converged"]
+    fs = [to_dev(H, l, 0, F[l]) for l in range(OH.nlev)]
+    for prec, tol in ((A.FP64, 1e-11), (A.MIXED, 1e-9)):
+        xs = [torch.zeros_like(f) for f in fs]
+        st = H.solve_composite(xs, fs, None, A.default_opts(precision=prec, smoother=A.SMOOTH_RB, omega_rb=1.3,
+                                                            tol_rel=1e-12, max_cycles=200))
+        assert st["status"] == 0 and st["converged"], st
+        got = [from_dev(H, l, 0, xs[l], OH.levels[l]) for l in range(OH.nlev)]
+        assert relmax(got, Uo, OH.valid) < tol, (prec, st["cycles"], sto["cycles"])
+        if prec == A.FP64:
+            assert abs(st["cycles"] - sto["cycles"]) <= 1
