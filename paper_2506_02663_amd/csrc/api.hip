@@ -1170,6 +1170,10 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
   double* Rb = mixed ? L.r64 : D0.f64;
   double alpha, beta;
   coefs<double>(H, D0, alpha, beta);
+  // mixed precision: the residual kernel stores r in FP32 directly (the
+  // conversion then scales it in place), unless its size is outside the
+  // range where FP32 holds it comfortably
+  bool direct32 = mixed && !tr;
   auto residual_norm = [&]() {
     if (tr) {
       launch_fill_tr<double>(D0, X, R.st);
@@ -1179,7 +1183,10 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
     } else {
       launch_fill<double>(D0, X, FD, R.st);
       Timed tm(R, AMG_T_RESIDUAL, 0);
-      launch_residual<double>(dim, D0, true, X, frhs, Rb, alpha, beta, L.partial, R.st);
+      if (direct32)
+        launch_residual32(dim, D0, X, frhs, D0.f32, alpha, beta, L.partial, R.st);
+      else
+        launch_residual<double>(dim, D0, true, X, frhs, Rb, alpha, beta, L.partial, R.st);
     }
     global_max(R, D0, L.scal + S_NORM);
   };
@@ -1193,6 +1200,11 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
   HIPCHK(hipGetLastError());
   double r0 = 0;
   TRY(read_norm(r0));
+  if (direct32 && std::isfinite(r0) && !(r0 > 1e-20 && r0 < 1e30)) {
+    direct32 = false;
+    residual_norm();
+    TRY(read_norm(r0));
+  }
   if (!std::isfinite(r0)) return fail(H, AMG_ENONFINITE, "non-finite initial residual");
   const double target = std::max(o.tol_rel * r0, o.tol_abs);
   double rn = r0;
@@ -1221,7 +1233,10 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
     if (L.nsingular) residual_mean();
     if (mixed) {
       // the mean removal fused into the FP32 conversion
-      launch_to32(dim, D0, Rb, D0.f32, L.scal + S_NORM, R.st, L.nsingular ? L.d_delta : nullptr);
+      if (direct32)
+        launch_scale32(dim, D0, D0.f32, L.scal + S_NORM, R.st, L.nsingular ? L.d_delta : nullptr);
+      else
+        launch_to32(dim, D0, Rb, D0.f32, L.scal + S_NORM, R.st, L.nsingular ? L.d_delta : nullptr);
       float* e = vcycle<float>(R, o, D0.f32, D0.e32, D0.t32);
       launch_update<float>(dim, D0, X, e, L.scal + S_NORM, R.st);
     } else {
@@ -1237,7 +1252,8 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
   // provide: with timing on, the cycle runs as direct launches
   bool use_graph = o.use_graph != 0 && !G.broken && !H->timer.on;
   if (use_graph) {
-    std::vector<int64_t> key = {(int64_t)(intptr_t)X, (int64_t)(intptr_t)frhs, (int64_t)(intptr_t)FD, o.precision,
+    std::vector<int64_t> key = {(int64_t)direct32, (int64_t)(intptr_t)X, (int64_t)(intptr_t)frhs,
+                                (int64_t)(intptr_t)FD, o.precision,
                                 o.smoother, o.nu1, o.nu2, (int64_t)H->timer.on};
     int64_t ob;
     memcpy(&ob, &o.omega, sizeof ob);

@@ -96,6 +96,12 @@ void launch_update2(int dim, const Depth& D, double* x, double* E, const T* e, c
 template <typename T>
 void launch_update(int dim, const Depth& D, double* x, const T* e, const double* scal, hipStream_t st);
 // r32 = (r - delta[component]) / scal[0] (delta may be NULL)
+// the FP64 residual of all tiles stored unscaled in FP32 (r = f - A u, with
+// the per-tile max and sum partials), and its in-place conversion
+// r32 = (r32 - delta[comp]) / scal[0]
+void launch_residual32(int dim, const Depth& D, const double* u, const double* f, float* r, double alpha, double beta,
+                       double* part, hipStream_t st);
+void launch_scale32(int dim, const Depth& D, float* r32, const double* scal, hipStream_t st, const double* delta);
 void launch_to32(int dim, const Depth& D, const double* r, float* r32, const double* scal, hipStream_t st,
                  const double* delta = nullptr);
 void launch_shift_copy(int dim, const Depth& D, const double* f, double* out, const double* delta, hipStream_t st);

@@ -788,11 +788,12 @@ __global__ void __launch_bounds__(512) k_rb2(const TileD* __restrict__ tiles, in
 // the caches.  OP_RESTRICT computes the residual like OP_RESID and averages
 // it over the 2^DIM children of each coarse cell on the fly (x pairs inside
 // the thread, z or y pairs over two steps, y pairs in 3D through LDS), so the
-// fine residual is never stored: out is the coarse right-hand side.
-template <typename T, int DIM, int OP, bool PART>
+// fine residual is never stored: out is the coarse right-hand side.  TO:
+// the element type of out (an FP64 residual may be stored in FP32).
+template <typename T, int DIM, int OP, bool PART, typename TO = T>
 __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, int ntiles,
                                                const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
-                                               const T* __restrict__ u, const T* __restrict__ f, T* __restrict__ out,
+                                               const T* __restrict__ u, const T* __restrict__ f, TO* __restrict__ out,
                                                T alpha, T beta, T omega, int col, double* __restrict__ part,
                                                const BoxD* __restrict__ cboxes) {
   __shared__ double sh[4];
@@ -867,9 +868,9 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
       }
       if (OP != OP_RESTRICT) {
         if (C.ok1)
-          st2(out + c, o0, o1);
+          st2<TO>(out + c, (TO)o0, (TO)o1);
         else
-          out[c] = o0;
+          out[c] = (TO)o0;
       }
     }
     if (OP == OP_RESTRICT) {
@@ -880,12 +881,12 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
           __syncthreads();
           if (!(w & 1) && C.ok) {
             const BoxD cb = cboxes[b.coarse];
-            out[cell_index<DIM>(cb, C.x >> 1, C.y >> 1, p >> 1)] = (acc + R[w >> 1][lane]) * T(0.125);
+            out[cell_index<DIM>(cb, C.x >> 1, C.y >> 1, p >> 1)] = (TO)((acc + R[w >> 1][lane]) * T(0.125));
           }
           __syncthreads();
         } else if (C.ok) {
           const BoxD cb = cboxes[b.coarse];
-          out[cell_index<DIM>(cb, C.x >> 1, p >> 1, 0)] = acc * T(0.25);
+          out[cell_index<DIM>(cb, C.x >> 1, p >> 1, 0)] = (TO)(acc * T(0.25));
         }
         acc = T(0);
       }
@@ -982,6 +983,25 @@ __global__ void __launch_bounds__(256) k_to32(const TileD* __restrict__ tiles, i
       st2(r32 + c, (float)((rv.a - dv) * inv), (float)((rv.b - dv) * inv));
     } else {
       r32[c] = (float)((r[c] - dv) * inv);
+    }
+  }
+}
+
+// r32 = (r32 - delta[comp]) / scal[0] in place (the FP64 residual stored
+// unscaled in FP32 by the residual kernel; arithmetic in FP64)
+template <int DIM>
+__global__ void __launch_bounds__(256) k_scale32(const TileD* __restrict__ tiles, int ntiles,
+                                                 const BoxD* __restrict__ boxes, float* __restrict__ r32,
+                                                 const double* __restrict__ scal, const double* __restrict__ delta) {
+  const double inv = 1.0 / scal[0];
+  FOR_COLUMN(DIM) {
+    const double dv = delta ? delta[b.comp] : 0.0;
+    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+    if (C.ok1) {
+      const Pair<float> rv = ld2(r32 + c);
+      st2(r32 + c, (float)(((double)rv.a - dv) * inv), (float)(((double)rv.b - dv) * inv));
+    } else {
+      r32[c] = (float)(((double)r32[c] - dv) * inv);
     }
   }
 }
@@ -2267,6 +2287,24 @@ void launch_to32(int dim, const Depth& D, const double* r, float* r32, const dou
   const size_t n = D.tiles.size();
   if (!n) return;
   DISPATCH_DIM(dim, k_to32, D.d_tiles, (int)n, D.d_box, r, r32, scal, delta);
+}
+
+void launch_scale32(int dim, const Depth& D, float* r32, const double* scal, hipStream_t st, const double* delta) {
+  const size_t n = D.tiles.size();
+  if (!n) return;
+  DISPATCH_DIM(dim, k_scale32, D.d_tiles, (int)n, D.d_box, r32, scal, delta);
+}
+
+void launch_residual32(int dim, const Depth& D, const double* u, const double* f, float* r, double alpha, double beta,
+                       double* part, hipStream_t st) {
+  const size_t n = D.tiles.size();
+  if (!n) return;
+  if (dim == 2)
+    hipLaunchKernelGGL((k_march<double, 2, OP_RESID, true, float>), grid8(n), threads<2>(), 0, st, D.d_tiles, (int)n,
+                       D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr);
+  else
+    hipLaunchKernelGGL((k_march<double, 3, OP_RESID, true, float>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n,
+                       D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr);
 }
 
 void launch_shift_copy(int dim, const Depth& D, const double* f, double* out, const double* delta, hipStream_t st) {
