@@ -174,9 +174,7 @@ void remove_mean(const Run& R, int k, T* a) {
     return;
   }
   launch_tile_sum<T>(R.dim, D, a, L.partial, R.st);
-  comp_sums(R, D, L.comp_sum);
-  launch_comp_delta(L.comp_sum, nullptr, L.d_comp_flag, L.d_comp_cnt + (size_t)k * L.ncomp, L.ncomp, 1.0, 0.0,
-                    L.d_delta, nullptr, R.st);
+  launch_comp_mean_delta(D, L.partial, L.d_comp_flag, L.d_comp_cnt + (size_t)k * L.ncomp, L.ncomp, L.d_delta, R.st);
   launch_comp_shift<T>(R.dim, D, a, L.d_delta, R.st);
 }
 
@@ -1221,10 +1219,11 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
     if (tr) {
       launch_tile_sum<double>(dim, D0, Rb, L.partial, R.st);
       comp_sums(R, D0, L.comp_sum);
+      launch_comp_delta(L.comp_sum, nullptr, L.d_comp_flag, L.d_comp_cnt, L.ncomp, 1.0, 0.0, L.d_delta, nullptr,
+                        R.st);
     } else {
-      comp_sums(R, D0, L.comp_sum, L.partial + D0.tiles.size());
+      launch_comp_mean_delta(D0, L.partial + D0.tiles.size(), L.d_comp_flag, L.d_comp_cnt, L.ncomp, L.d_delta, R.st);
     }
-    launch_comp_delta(L.comp_sum, nullptr, L.d_comp_flag, L.d_comp_cnt, L.ncomp, 1.0, 0.0, L.d_delta, nullptr, R.st);
   };
   // The solution's mean on singular components does not change the
   // residual (the operator annihilates constants), so it is removed once

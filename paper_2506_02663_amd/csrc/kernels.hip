@@ -1031,17 +1031,14 @@ __global__ void __launch_bounds__(1024) k_comp_mean_small(int nboxes, const BoxD
   __shared__ double mean;
   const int comp = blockIdx.x;
   if (!flag[comp]) return;
-  // rows of the box's cells: wavefront w takes rows w, w + 16, ..., its
-  // lanes the cells of the row (no per-cell index division)
-  const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
   double v = 0.0;
   for (int bi = 0; bi < nboxes; ++bi) {
     const BoxD b = boxes[bi];
     if (b.comp != comp) continue;
-    const int nrow = b.n[1] * (DIM == 3 ? b.n[2] : 1);
-    for (int r = w; r < nrow; r += 16) {
-      const int64_t c0 = cell_index<DIM>(b, 0, DIM == 3 ? r % b.n[1] : r, DIM == 3 ? r / b.n[1] : 0);
-      for (int x = lane; x < b.n[0]; x += 64) v += (double)a[c0 + x];
+    const int n = b.n[0] * b.n[1] * (DIM == 3 ? b.n[2] : 1);
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) {
+      const int x = i % b.n[0], r = i / b.n[0];
+      v += (double)a[cell_index<DIM>(b, x, DIM == 3 ? r % b.n[1] : r, DIM == 3 ? r / b.n[1] : 0)];
     }
   }
   v = block_sum<double>(v, sh);
@@ -1051,10 +1048,11 @@ __global__ void __launch_bounds__(1024) k_comp_mean_small(int nboxes, const BoxD
   for (int bi = 0; bi < nboxes; ++bi) {
     const BoxD b = boxes[bi];
     if (b.comp != comp) continue;
-    const int nrow = b.n[1] * (DIM == 3 ? b.n[2] : 1);
-    for (int r = w; r < nrow; r += 16) {
-      const int64_t c0 = cell_index<DIM>(b, 0, DIM == 3 ? r % b.n[1] : r, DIM == 3 ? r / b.n[1] : 0);
-      for (int x = lane; x < b.n[0]; x += 64) a[c0 + x] = (T)((double)a[c0 + x] - m);
+    const int n = b.n[0] * b.n[1] * (DIM == 3 ? b.n[2] : 1);
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) {
+      const int x = i % b.n[0], r = i / b.n[0];
+      const int64_t c = cell_index<DIM>(b, x, DIM == 3 ? r % b.n[1] : r, DIM == 3 ? r / b.n[1] : 0);
+      a[c] = (T)((double)a[c] - m);
     }
   }
 }
@@ -1440,6 +1438,27 @@ __global__ void __launch_bounds__(256) k_comp_sum(const double* __restrict__ par
   for (int j = ptr[c] + threadIdx.x; j < ptr[c + 1]; j += 256) v += part[ids[j]];
   v = block_sum<double>(v, sh);
   if (threadIdx.x == 0) out[c] = v;
+}
+
+// per-component means of tile partials in one launch: block c sums the
+// partials of component c's tiles (a contiguous range) in a fixed order and
+// writes delta[c] = flag[c] ? sum / cnt[c] : 0
+__global__ void __launch_bounds__(256) k_comp_mean_delta(const double* __restrict__ part,
+                                                         const int32_t* __restrict__ seg,
+                                                         const int32_t* __restrict__ cseg,
+                                                         const int32_t* __restrict__ flag,
+                                                         const double* __restrict__ cnt, double* __restrict__ delta) {
+  __shared__ double sh[4];
+  const int c = blockIdx.x;
+  if (!flag[c]) {  // block-uniform
+    if (threadIdx.x == 0) delta[c] = 0.0;
+    return;
+  }
+  const int a = seg[cseg[c]], b = seg[cseg[c + 1]];
+  double v = 0.0;
+  for (int j = a + (int)threadIdx.x; j < b; j += 256) v += part[j];
+  v = block_sum<double>(v, sh);
+  if (threadIdx.x == 0) delta[c] = v / (cnt[c] * 1.0);
 }
 
 // per-component deltas: delta[c] = flag[c] ? (sum[c] - bsum[c]) * scale / cnt[c] : 0
@@ -2089,6 +2108,12 @@ void launch_seg_reduce(const double* in, const int32_t* ptr, int nseg, int n, do
     hipLaunchKernelGGL(k_seg_reduce<true>, dim3(nseg), dim3(256), 0, st, in, ptr, n, out);
   else
     hipLaunchKernelGGL(k_seg_reduce<false>, dim3(nseg), dim3(256), 0, st, in, ptr, n, out);
+}
+
+void launch_comp_mean_delta(const Depth& D, const double* part, const int32_t* flag, const double* cnt, int ncomp,
+                            double* delta, hipStream_t st) {
+  if (ncomp <= 0) return;
+  hipLaunchKernelGGL(k_comp_mean_delta, dim3(ncomp), dim3(256), 0, st, part, D.d_seg, D.d_cseg, flag, cnt, delta);
 }
 
 void launch_comp_sum(const double* part, const int32_t* ptr, const int32_t* ids, int ncomp, double* out,
