@@ -156,6 +156,11 @@ void comp_sums(const Run& R, const Depth& D, double* out, const double* in = nul
 void global_max(const Run& R, const Depth& D, double* out) {
   Level& L = *R.L;
   const int nseg = (int)D.seg_ptr.size() - 1;
+  const int nt = (int)D.tiles.size();
+  if (nt <= 16384) {  // one block over all tile partials
+    launch_seg_reduce(L.partial, nullptr, 1, nt, out, true, R.st);
+    return;
+  }
   launch_seg_reduce(L.partial, D.d_seg, nseg, 0, L.partial2, true, R.st);
   launch_seg_reduce(L.partial2, nullptr, 1, nseg, out, true, R.st);
 }
