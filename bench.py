@@ -43,6 +43,8 @@ def parse():
     p.add_argument("--nu", default=None,
                    help="pre,post smoothing steps of the V-cycle (default: 1,3 for the 3D single level, "
                         "whose 1e-10 solve it reaches fastest of V(0..2, 1..4); 2,2 otherwise)")
+    p.add_argument("--no-split", action="store_true",
+                   help="3D mixed precision: keep the finest depth in interleaved storage during post-smoothing")
     p.add_argument("--no-graph", action="store_true",
                    help="launch every kernel of a cycle directly instead of replaying its HIP graph")
     p.add_argument("--plain", action="store_true",
@@ -198,6 +200,8 @@ def main():
             H.set_tuning(A.TUNE_MARCH2 if dim == 2 else A.TUNE_MARCH3, march)
         if args.bottom_cells:
             H.set_bottom_cells(args.bottom_cells)
+        if args.no_split:
+            H.set_tuning(A.TUNE_SPLIT_RB, 0)
         H.finalize()
         fd = torch.tensor(H.pack(0, 0, lambda i, b: f), device="cuda")
         x = torch.zeros_like(fd)
@@ -259,19 +263,22 @@ def main():
                    "cycles": cycles, "smoother": args.smoother, "precision": args.precision,
                    "graph": not args.no_graph, "vcycle": f"V({nu1},{nu2})",
                    "omega_rb": w_rb if args.smoother == "rb" else None, "march": march, "bottom_cells": args.bottom_cells,
-                   "depths": systems[0][1].level_info(0).depths},
+                   "depths": systems[0][1].level_info(0).depths,
+                   "split_storage": bool(systems[0][1].level_info(0).split_rb) and prec == A.MIXED and
+                   args.smoother == "rb"},
     }
     if not args.no_timing:
-        # dominant kernel: the smoothing sweep on the finest depth
-        cnt, tot = 0, 0.0
+        # dominant kernel: the smoothing half-sweep on the finest depth (in
+        # colour-split storage where the solves use it)
+        split_on = out["config"]["split_storage"]
         kinds = {}
         for _, H, _, _ in systems:
-            for k, name in enumerate(("sweep", "fill", "resid_restrict", "prolong", "residual64")):
+            for k, name in enumerate(("sweep", "fill", "resid_restrict", "prolong", "residual64", "sweep_split")):
                 c_, t_ = H.timing_read(k, reset=False)
                 a = kinds.setdefault(name, [0, 0.0])
                 a[0] += c_
                 a[1] += t_
-        cnt, tot = kinds["sweep"]
+        cnt, tot = kinds["sweep_split" if split_on else "sweep"]
         avg_s = tot / cnt / 1e3
         word = 4 if prec == A.MIXED else 8
         if args.smoother == "jacobi":
@@ -279,14 +286,14 @@ def main():
         else:
             # one half-sweep: read u, read f on one colour, write that colour
             bytes_launch = 2 * word * n ** dim
-        ach = bytes_launch / avg_s / 1e9
         traffic = None
         if dim == 3 and n == 256 and word == 4:
-            traffic = measured_traffic(f"{args.smoother}_sweep_fp32_256cubed_counters.txt")
-        # the same kernel launched 50 times back to back by the library
-        # (amg_time_sweep, HIP events on its stream around the batch): the
-        # events bracket the kernels, not the fills and launch gaps between
-        # them inside a solve
+            traffic = measured_traffic(f"{args.smoother}_sweep{'_split' if split_on else ''}_fp32_256cubed_counters.txt")
+        # `achieved` is taken from the launches inside the timed solves (the
+        # event pass); for reference, the same kernel launched 50 times back
+        # to back by the library (amg_time_sweep, HIP events on its stream
+        # around the batch), where its arrays stay in the caches between
+        # launches
         _, H0, x0, f0 = systems[0]
         dt_ = torch.float32 if word == 4 else torch.float64
         u_ = (f0 * 1e-3).to(dt_)
@@ -296,13 +303,14 @@ def main():
         bcnt = 50
         bavg_s = H0.time_sweep(0, u_, f_, t_, smoother=sm, n=bcnt) / 1e3
         del u_, f_, t_
-        ach = bytes_launch / bavg_s / 1e9
+        ach = bytes_launch / avg_s / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                            "kernel": f"{args.smoother} {'half-' if args.smoother == 'rb' else ''}sweep, finest depth, "
-                                     f"{'FP32' if word == 4 else 'FP64'}",
-                           "avg_us": bavg_s * 1e6, "launches": bcnt, "bytes_per_launch": bytes_launch,
-                           "avg_us_inside_solves": avg_s * 1e6, "launches_inside_solves": cnt}
+                                     f"{'FP32' if word == 4 else 'FP64'}"
+                                     f"{', colour-split storage' if split_on else ''}",
+                           "avg_us": avg_s * 1e6, "launches": cnt, "bytes_per_launch": bytes_launch,
+                           "avg_us_back_to_back": bavg_s * 1e6, "launches_back_to_back": bcnt}
         out["kernel_ms_per_step"] = {k: v[1] / args.steps for k, v in kinds.items()}
         out["ms_per_step_event_pass"] = timed_ms
     if base is not None:

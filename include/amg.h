@@ -99,12 +99,13 @@ extern "C" {
 #define AMG_SOLV_CF_DELTA 2
 
 /* kernel kinds of the optional event timing (finest multigrid depth) */
-#define AMG_T_SWEEP 0     /* one smoothing sweep or half-sweep */
+#define AMG_T_SWEEP 0     /* one smoothing sweep or half-sweep (except the kind below) */
 #define AMG_T_FILL 1      /* one ghost fill */
 #define AMG_T_RESTRICT 2  /* fused residual and restriction */
 #define AMG_T_PROLONG 3   /* prolongation and correction */
 #define AMG_T_RESIDUAL 4  /* outer FP64 residual with its norm partials */
-#define AMG_T_KINDS 5
+#define AMG_T_SWEEP_SPLIT 5 /* one red-black half-sweep in colour-split storage (not the first two from zero) */
+#define AMG_T_KINDS 6
 
 #define AMG_MAX_HISTORY 128
 #define AMG_MAX_COMP 64
@@ -120,7 +121,7 @@ typedef struct {
   int64_t nstored;     /* elements of the packed buffer */
   int64_t nface;       /* elements of the face-data buffer */
   int32_t fused_rb;    /* bit k set: FP32 red-black sweeps at depth k run both colours in one launch */
-  int32_t pad_;
+  int32_t split_rb;    /* bit k set: mixed-precision solves post-smooth depth k in colour-split storage */
 } amg_level_desc;
 
 typedef struct {
@@ -210,6 +211,14 @@ int amg_set_operator(amg_hier* h, int kind, double c);
  * planes); 0 (default) keeps two launches per sweep, the faster form on
  * gfx950 as measured.  The two forms agree to rounding. */
 #define AMG_TUNE_FUSED_RB 3
+/* AMG_TUNE_SPLIT_RB: 1 (default) lets the mixed-precision solve keep the
+ * finest depth's correction and right-hand side in colour-split storage
+ * during the red-black post-smoothing (each colour in its own half array, so
+ * a half-sweep moves only the cells it reads and writes), on 3D depths
+ * whose faces are all filled uniformly with both ghost layers from their own
+ * rows and whose boxes have an even number of cells along x; 0 keeps the
+ * interleaved storage.  The two forms give the same results. */
+#define AMG_TUNE_SPLIT_RB 4
 int amg_set_tuning(amg_hier* h, int key, int value);
 
 /* Size of the exactly solved coarsest systems (Section 6.5 leaves the bottom
@@ -421,8 +430,11 @@ int amg_timing_enable(amg_hier* h, int on);
  * `level` (one Jacobi sweep, or one red-black half-sweep alternating the
  * colours) launched n times back to back on the stream, u and tmp swapping
  * roles, with no ghost fill in between, bracketed by two HIP events;
- * *avg_ms = elapsed / n.  The values written are not a smoothing result
- * (ghosts are not refilled): for timing only.  u != tmp. */
+ * *avg_ms = elapsed / n.  FP32 red-black on a depth whose mixed-precision
+ * post-smoothing runs in colour-split storage (AMG_TUNE_SPLIT_RB) times that
+ * split half-sweep, u, f and tmp taken as split arrays.  The values written
+ * are not a smoothing result (ghosts are not refilled): for timing only.
+ * u != tmp. */
 int amg_time_sweep(amg_hier* h, int level, int dtype, int smoother, int n, void* u, const void* f, void* tmp,
                    double* avg_ms, void* stream);
 

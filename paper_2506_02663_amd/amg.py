@@ -21,15 +21,15 @@ SMOOTH_JACOBI, SMOOTH_RB = 0, 1
 FP64, MIXED = 0, 1
 F64, F32 = 0, 1
 SOLV_RHS_SHIFT, SOLV_OFF, SOLV_CF_DELTA = 0, 1, 2
-T_SWEEP, T_FILL, T_RESTRICT, T_PROLONG, T_RESIDUAL, T_KINDS = range(6)
-TUNE_MARCH2, TUNE_MARCH3, TUNE_ROW_ALIGN, TUNE_FUSED_RB = range(4)
+T_SWEEP, T_FILL, T_RESTRICT, T_PROLONG, T_RESIDUAL, T_SWEEP_SPLIT, T_KINDS = range(7)
+TUNE_MARCH2, TUNE_MARCH3, TUNE_ROW_ALIGN, TUNE_FUSED_RB, TUNE_SPLIT_RB = range(5)
 MAX_HISTORY, MAX_COMP = 128, 64
 
 
 class LevelDesc(C.Structure):
     _fields_ = [("nboxes", C.c_int32), ("depths", C.c_int32), ("ncomp", C.c_int32), ("nsingular", C.c_int32),
                 ("ncells", C.c_int64), ("nstored", C.c_int64), ("nface", C.c_int64), ("fused_rb", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("split_rb", C.c_int32)]
 
 
 class BoxDesc(C.Structure):

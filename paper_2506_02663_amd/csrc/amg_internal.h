@@ -188,6 +188,7 @@ struct Depth {
   int64_t nstored = 0;
   bool fill_only = false;  // every ghost column is filled from its own row (no exchange or interpolated ghosts)
   bool fuse_rb = false;    // the fused red-black sweep (k_rb2) applies to this depth
+  bool split_rb = false;   // colour-split storage (k_rbs) applies to this depth
   int march = 2;  // cells each tile marches along the last direction
   // device copies
   BoxD* d_box = nullptr;
@@ -201,6 +202,7 @@ struct Depth {
   // work buffers (FP64 and FP32): correction, right-hand side, second buffer
   double *e64 = nullptr, *f64 = nullptr, *t64 = nullptr;
   float *e32 = nullptr, *f32 = nullptr, *t32 = nullptr;
+  float* fs32 = nullptr;  // right-hand side in colour-split storage (depth 0 with split_rb)
 };
 
 struct GraphCache {  // the captured outer cycle of one level
@@ -283,6 +285,7 @@ struct amg_hier {
   int row_align = ROW_ALIGN_DEFAULT;                       // row alignment of the packed layout (elements)
   int bottom_cells = 0;  // coarsening stops once every component has at most this many cells (0: off)
   int fuse_rb = 0;       // FP32 red-black sweeps in one launch where the depth allows it (opt-in)
+  int split_rb = 1;      // mixed-precision post-smoothing of depth 0 in colour-split storage where allowed
   int dim = 2;
   int32_t base[3] = {1, 1, 1};
   double h0 = 1;

@@ -257,10 +257,64 @@ void smooth(const Run& R, int k, int smoother, int nsweeps, double omega, bool f
 // red-black half-sweeps' factor
 inline double relax(const amg_solve_opts& o) { return o.smoother == AMG_SMOOTH_RB ? o.omega_rb : o.omega; }
 
+// nsweeps red-black sweeps of a depth in colour-split storage: the iterate
+// starts in buffer a (both halves), b is the second buffer; each half-sweep
+// writes its colour's half into the buffer that does not hold it.  Returns
+// the buffer that holds the final iterate (both halves).
+float* smooth_split(const Run* R, hipStream_t st, const Depth& D, int k, int nsweeps, float alpha, float beta,
+                    float omega, const float* fs, float* a, float* b) {
+  const int64_t hs = D.nstored / 2;
+  const float* h[2] = {a, a + hs};
+  for (int s = 0; s < nsweeps; ++s)
+    for (int col = 0; col < 2; ++col) {
+      float* dst = (h[col] == a + col * hs ? b : a) + col * hs;
+      if (R) {
+        Timed tm(*R, AMG_T_SWEEP_SPLIT, k);
+        launch_rbs(D, 0, h[0], h[1], fs + col * hs, dst, alpha, beta, omega, col, st);
+      } else {
+        launch_rbs(D, 0, h[0], h[1], fs + col * hs, dst, alpha, beta, omega, col, st);
+      }
+      h[col] = dst;
+    }
+  return const_cast<float*>(h[0]);
+}
+
+// Pre-smoothing of depth 0 in colour-split storage from e = 0: nsweeps
+// red-black sweeps into buffer a (b: the second buffer).  The first
+// half-sweep starts from zero and writes the red half; the second reads only
+// the red half (its own colour is still zero) and writes the black half of
+// the same buffer.  Returns the buffer that holds the iterate.
+float* presmooth_split(const Run& R, const Depth& D, int nsweeps, float alpha, float beta, float omega,
+                       const float* fs, float* a, float* b) {
+  if (nsweeps <= 0) {
+    launch_zero<float>(a, D.nstored, R.st);
+    return a;
+  }
+  const int64_t hs = D.nstored / 2;
+  {
+    Timed tm(R, AMG_T_SWEEP, 0);
+    launch_rbs(D, 2, nullptr, nullptr, fs, a, alpha, beta, omega, 0, R.st);
+  }
+  {
+    Timed tm(R, AMG_T_SWEEP, 0);
+    launch_rbs(D, 1, a, a + hs, fs + hs, a + hs, alpha, beta, omega, 1, R.st);
+  }
+  return smooth_split(&R, R.st, D, 0, nsweeps - 1, alpha, beta, omega, fs, a, b);
+}
+
+// whether a mixed-precision solve runs depth 0 in colour-split storage (its
+// right-hand side is then written split)
+inline bool use_split(const amg_hier* H, const Depth& D0, const amg_solve_opts& o) {
+  return D0.split_rb && D0.fs32 && o.smoother == AMG_SMOOTH_RB && o.nu2 > 0 && !(H->fuse_rb && D0.fuse_rb);
+}
+
 // One homogeneous V-cycle from e = 0; f0 is the depth-0 right-hand side, e0
-// and t0 the two depth-0 buffers.  Returns the buffer that holds e.
+// and t0 the two depth-0 buffers.  Returns the buffer that holds e.  With
+// fs0 (FP32: the depth-0 right-hand side in colour-split storage, depth 0
+// with split_rb; f0 is then not read) every depth-0 step runs in split
+// storage and the returned e is split.
 template <typename T>
-T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0) {
+T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, const float* fs0 = nullptr) {
   Level& L = *R.L;
   const int K = (int)L.depths.size();
   std::vector<T*> cur(K), oth(K);
@@ -275,6 +329,21 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0) {
     // boxes that end here: exact solve, written to both buffers of the depth
     if (!D.groups.empty()) launch_bottom<T>(D, L.d_mat, L.d_idx, f[k], cur[k], R.tr, R.st, oth[k]);
     if (k + 1 >= K || D.stiles.empty()) break;
+    if constexpr (sizeof(T) == 4) {
+      if (k == 0 && fs0) {
+        T alpha, beta;
+        coefs<T>(R.H, D, alpha, beta);
+        float* s = presmooth_split(R, D, o.nu1, alpha, beta, (float)relax(o), fs0, cur[0], oth[0]);
+        if (s != cur[0]) std::swap(cur[0], oth[0]);
+        {
+          // the kernel writes the ghosts it reads itself: no fill launch
+          Timed tm(R, AMG_T_RESTRICT, 0);
+          launch_resid_restrict_s(D, L.depths[1], cur[0], fs0, Bufs<T>::f(L.depths[1]), alpha, beta, R.st);
+        }
+        remove_mean<T>(R, 1, Bufs<T>::f(L.depths[1]));
+        continue;
+      }
+    }
     smooth<T>(R, k, o.smoother, o.nu1, relax(o), true, cur[k], oth[k], f[k]);
     T alpha, beta;
     coefs<T>(R.H, D, alpha, beta);
@@ -298,6 +367,18 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0) {
     Depth& D = L.depths[k];
     if (D.stiles.empty()) continue;
     launch_fill<T>(L.depths[k + 1], cur[k + 1], nullptr, R.st);
+    if constexpr (sizeof(T) == 4) {
+      if (k == 0 && fs0) {
+        // the prolongation writes the corrected iterate into the free buffer
+        {
+          Timed tm(R, AMG_T_PROLONG, k);
+          launch_prolong_s(D, L.depths[1], cur[1], cur[0], oth[0], R.st);
+        }
+        T alpha, beta;
+        coefs<T>(R.H, D, alpha, beta);
+        return smooth_split(&R, R.st, D, 0, o.nu2, alpha, beta, (float)relax(o), fs0, oth[0], cur[0]);
+      }
+    }
     {
       Timed tm(R, AMG_T_PROLONG, k);
       launch_prolong<T>(R.dim, D, L.depths[k + 1], cur[k + 1], cur[k], R.st);
@@ -326,7 +407,7 @@ void free_level(amg::Level& L) {
   for (auto& D : L.depths) {
     for (void* p : {(void*)D.d_box, (void*)D.d_codes, (void*)D.d_chunks, (void*)D.d_tiles, (void*)D.d_stiles,
                     (void*)D.d_seg, (void*)D.d_cseg, (void*)D.d_cc_ptr, (void*)D.d_cc_idx, (void*)D.d_groups, (void*)D.d_band,
-                    (void*)D.e64, (void*)D.f64, (void*)D.t64, (void*)D.e32, (void*)D.f32, (void*)D.t32})
+                    (void*)D.e64, (void*)D.f64, (void*)D.t64, (void*)D.e32, (void*)D.f32, (void*)D.t32, (void*)D.fs32})
       if (p) (void)hipFree(p);
   }
   for (void* p : {(void*)L.d_mat, (void*)L.d_idx, (void*)L.r64, (void*)L.fsh, (void*)L.partial, (void*)L.partial2, (void*)L.comp_sum,
@@ -670,6 +751,10 @@ int amg_set_tuning(amg_hier* H, int key, int value) {
       if (value != 0 && value != 1) return fail(H, AMG_EINVAL, "fused red-black switch must be 0 or 1");
       H->fuse_rb = value;
       return AMG_OK;
+    case AMG_TUNE_SPLIT_RB:
+      if (value != 0 && value != 1) return fail(H, AMG_EINVAL, "split red-black switch must be 0 or 1");
+      H->split_rb = value;
+      return AMG_OK;
     case AMG_TUNE_ROW_ALIGN:
       if (value < 2 || value > 256 || (value & (value - 1)))
         return fail(H, AMG_EINVAL, "alignment must be a power of two of at least 2");
@@ -723,6 +808,7 @@ int amg_finalize(amg_hier* H) {
       TRY(zalloc(H, &D.e32, D.nstored));
       TRY(zalloc(H, &D.f32, D.nstored));
       TRY(zalloc(H, &D.t32, D.nstored));
+      if (D.split_rb) TRY(zalloc(H, &D.fs32, D.nstored));
       maxpart = std::max(maxpart, std::max(D.tiles.size(), D.chunks.size()));
       maxseg = std::max(maxseg, D.seg_ptr.size());
     }
@@ -810,7 +896,7 @@ int amg_level_info(const amg_hier* Hc, int level, amg_level_desc* out) {
   out->fused_rb = 0;
   for (size_t k = 0; k < L.depths.size() && k < 31; ++k)
     if (H->fuse_rb && L.depths[k].fuse_rb) out->fused_rb |= 1 << k;
-  out->pad_ = 0;
+  out->split_rb = L.depths[0].split_rb ? 1 : 0;
   return AMG_OK;
 }
 
@@ -1177,6 +1263,7 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
   // conversion then scales it in place), unless its size is outside the
   // range where FP32 holds it comfortably
   bool direct32 = mixed && !tr;
+  const bool split = mixed && !tr && use_split(H, D0, o);
   auto residual_norm = [&]() {
     if (tr) {
       launch_fill_tr<double>(D0, X, R.st);
@@ -1237,12 +1324,17 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
     if (L.nsingular) residual_mean();
     if (mixed) {
       // the mean removal fused into the FP32 conversion
+      // with depth 0 in split storage the conversion writes f split
+      float* fs = split ? D0.fs32 : nullptr;
       if (direct32)
-        launch_scale32(dim, D0, D0.f32, L.scal + S_NORM, R.st, L.nsingular ? L.d_delta : nullptr);
+        launch_scale32(dim, D0, D0.f32, L.scal + S_NORM, R.st, L.nsingular ? L.d_delta : nullptr, fs);
       else
-        launch_to32(dim, D0, Rb, D0.f32, L.scal + S_NORM, R.st, L.nsingular ? L.d_delta : nullptr);
-      float* e = vcycle<float>(R, o, D0.f32, D0.e32, D0.t32);
-      launch_update<float>(dim, D0, X, e, L.scal + S_NORM, R.st);
+        launch_to32(dim, D0, Rb, D0.f32, L.scal + S_NORM, R.st, L.nsingular ? L.d_delta : nullptr, fs);
+      float* e = vcycle<float>(R, o, D0.f32, D0.e32, D0.t32, fs);
+      if (split)
+        launch_update_s(D0, X, e, L.scal + S_NORM, R.st);
+      else
+        launch_update<float>(dim, D0, X, e, L.scal + S_NORM, R.st);
     } else {
       if (L.nsingular) launch_comp_shift<double>(dim, D0, Rb, L.d_delta, R.st);
       double* e = vcycle<double>(R, o, D0.f64, D0.e64, D0.t64);
@@ -1687,6 +1779,22 @@ int amg_time_sweep(amg_hier* H, int level, int dtype, int smoother, int n, void*
     T a, b;
     coefs<T>(H, D, a, b);
     (void)hipEventRecord(e0, st);
+    if constexpr (sizeof(T) == 4) {
+      // the form the mixed-precision solve post-smooths in: n half-sweeps
+      // in colour-split storage (u, f and tmp taken as split arrays)
+      if (smoother == AMG_SMOOTH_RB && D.split_rb && !(H->fuse_rb && D.fuse_rb)) {
+        const int64_t hs = D.nstored / 2;
+        const float* h[2] = {cur, cur + hs};
+        for (int i = 0; i < n; ++i) {
+          const int col = i & 1;
+          float* dst = (h[col] == cur + col * hs ? oth : cur) + col * hs;
+          launch_rbs(D, 0, h[0], h[1], ff + col * hs, dst, a, b, 1.0f, col, st);
+          h[col] = dst;
+        }
+        (void)hipEventRecord(e1, st);
+        return;
+      }
+    }
     for (int i = 0; i < n; ++i) {
       const int gr = sizeof(T) == 4 ? 1 : 0;  // the form the FP32 V-cycle launches
       if (smoother == AMG_SMOOTH_JACOBI)
@@ -1737,6 +1845,7 @@ int amg_autotune(amg_hier* H, int level, int dtype, int smoother, int nreps, int
     T->row_align = H->row_align;
     T->bottom_cells = H->bottom_cells;
     T->fuse_rb = H->fuse_rb;
+    T->split_rb = H->split_rb;
     T->march2 = T->march3 = m;
     rc = amg_finalize(T);
     if (rc != AMG_OK) {

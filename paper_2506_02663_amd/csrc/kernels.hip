@@ -127,6 +127,11 @@ __device__ __forceinline__ int64_t cell_index(const BoxD& b, int x, int y, int z
   return b.off + (x + 2) + (int64_t)(y + 2) * b.s[1] + (DIM == 3 ? (int64_t)(z + 2) * b.s[2] : 0);
 }
 
+// red-black colour of cell (x, y, z) of a 3D box
+__device__ __forceinline__ int colour_of(const BoxD& b, int x, int y, int z) {
+  return (b.lo[0] + b.lo[1] + b.lo[2] + x + y + z) & 1;
+}
+
 // folded diagonal increments of the faces within two cells of (x, y, z)
 template <typename T, int DIM>
 __device__ __forceinline__ T fold_at(const BoxD& b, const uint8_t* __restrict__ codes, int x, int y, int z) {
@@ -968,19 +973,34 @@ __global__ void __launch_bounds__(256) k_update(const TileD* __restrict__ tiles,
   }
 }
 
-// r32 = fp32(r / s), s = scal[0]
+// the pair of cells (x, x + 1) at element c (x even) of a 3D box stored
+// into split halves fs0, fs1
+__device__ __forceinline__ void split_pair(float* __restrict__ fs0, float* __restrict__ fs1, const BoxD& b, int x,
+                                           int y, int z, int64_t c, float a, float a1) {
+  const int cx = colour_of(b, x, y, z);
+  (cx ? fs1 : fs0)[c >> 1] = a;
+  (cx ? fs0 : fs1)[c >> 1] = a1;
+}
+
+// r32 = fp32(r / s), s = scal[0]; with fs0, fs1 (3D) the result goes to
+// split storage instead
 template <int DIM>
 __global__ void __launch_bounds__(256) k_to32(const TileD* __restrict__ tiles, int ntiles,
                                               const BoxD* __restrict__ boxes, const double* __restrict__ r,
                                               float* __restrict__ r32, const double* __restrict__ scal,
-                                              const double* __restrict__ delta) {
+                                              const double* __restrict__ delta, float* __restrict__ fs0,
+                                              float* __restrict__ fs1) {
   const double inv = 1.0 / scal[0];
   FOR_COLUMN(DIM) {
     const double dv = delta ? delta[b.comp] : 0.0;
     const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
     if (C.ok1) {
       const Pair<double> rv = ld2(r + c);
-      st2(r32 + c, (float)((rv.a - dv) * inv), (float)((rv.b - dv) * inv));
+      const float a = (float)((rv.a - dv) * inv), a1 = (float)((rv.b - dv) * inv);
+      if (DIM == 3 && fs0)
+        split_pair(fs0, fs1, b, C.x, C.y, p, c, a, a1);
+      else
+        st2(r32 + c, a, a1);
     } else {
       r32[c] = (float)((r[c] - dv) * inv);
     }
@@ -988,18 +1008,24 @@ __global__ void __launch_bounds__(256) k_to32(const TileD* __restrict__ tiles, i
 }
 
 // r32 = (r32 - delta[comp]) / scal[0] in place (the FP64 residual stored
-// unscaled in FP32 by the residual kernel; arithmetic in FP64)
+// unscaled in FP32 by the residual kernel; arithmetic in FP64); with fs0,
+// fs1 (3D) the result goes to split storage instead
 template <int DIM>
 __global__ void __launch_bounds__(256) k_scale32(const TileD* __restrict__ tiles, int ntiles,
                                                  const BoxD* __restrict__ boxes, float* __restrict__ r32,
-                                                 const double* __restrict__ scal, const double* __restrict__ delta) {
+                                                 const double* __restrict__ scal, const double* __restrict__ delta,
+                                                 float* __restrict__ fs0, float* __restrict__ fs1) {
   const double inv = 1.0 / scal[0];
   FOR_COLUMN(DIM) {
     const double dv = delta ? delta[b.comp] : 0.0;
     const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
     if (C.ok1) {
       const Pair<float> rv = ld2(r32 + c);
-      st2(r32 + c, (float)(((double)rv.a - dv) * inv), (float)(((double)rv.b - dv) * inv));
+      const float a = (float)(((double)rv.a - dv) * inv), a1 = (float)(((double)rv.b - dv) * inv);
+      if (DIM == 3 && fs0)
+        split_pair(fs0, fs1, b, C.x, C.y, p, c, a, a1);
+      else
+        st2(r32 + c, a, a1);
     } else {
       r32[c] = (float)(((double)r32[c] - dv) * inv);
     }
@@ -1166,6 +1192,309 @@ __global__ void __launch_bounds__(256) k_prolong(const TileD* __restrict__ tiles
     const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
     u[c] += common + T(0.25) * ec[q - 1];
     if (C.ok1) u[c + 1] += common + T(0.25) * ec[q + 1];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Colour-split storage (3D, FP32).  An array of a depth is kept as two halves
+// of nstored / 2 elements: element e (of the interleaved layout) of colour c,
+// c = (lo + x + y + z) mod 2, lives at index e >> 1 of half c.  Box offsets,
+// row lengths and plane sizes are even and every row starts on an even
+// element, so the two cells of each aligned pair (e even, e + 1) have
+// different colours and share the index e >> 1, and a cell's neighbours at
+// distance 1 along y or z (the other colour) and at distance 2 (its own
+// colour) keep its index shifted by half the stride.  A red-black half-sweep
+// of colour c then streams half c (the cell and its same-colour neighbours),
+// the other half (its neighbours at distance 1) and half c of f, and writes
+// only half c: two words per cell of the depth instead of the three of the
+// interleaved out-of-place form, whose cache lines carry both colours.
+
+// cell (x, y, z) (ghosts included) of a split array with halves h0, h1;
+// zc: a colour whose interior cells are taken as zero (not read), -1: none
+__device__ __forceinline__ float split_ld(const float* h0, const float* h1, const BoxD& b, int x, int y, int z,
+                                          int zc) {
+  const int k = colour_of(b, x, y, z);
+  return k == zc ? 0.0f : (k ? h1 : h0)[cell_index<3>(b, x, y, z) >> 1];
+}
+__device__ __forceinline__ void split_st(float* h0, float* h1, const BoxD& b, int x, int y, int z, float v) {
+  (colour_of(b, x, y, z) ? h1 : h0)[cell_index<3>(b, x, y, z) >> 1] = v;
+}
+
+// Read-time fill in split storage: the two ghost layers of every face of the
+// box that the tile's cells read (every face filled uniformly, both layers
+// from its own row), written into the input halves before the march; one
+// thread per face row of the tile.  zc >= 0: the interior cells of colour zc
+// are zero (their half is not read); the ghosts of both colours are written.  Each of these ghosts is read only by
+// this tile (smoothed boxes have even sizes and marches are even, so the
+// last tile of every row, column and march has at least 2 cells).
+__device__ __forceinline__ void split_ghosts(const TileD& t, const BoxD& b, float* h0, float* h1, int zc) {
+  const int lo[3] = {t.x0, t.y0, t.z0};
+  const int nn[3] = {min(TILE_X, b.n[0] - t.x0), min(TILE3_Y, b.n[1] - t.y0), min(t.len, b.n[2] - t.z0)};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
+    for (int side = 0; side < 2; ++side) {
+      if (side == 0 ? lo[d] != 0 : lo[d] + nn[d] != b.n[d]) continue;
+      const uint8_t cd = b.ucode[d][side];
+      const int in = side ? -1 : 1, e = side ? b.n[d] - 1 : 0;
+      for (int r = (int)threadIdx.x; r < nn[d1] * nn[d2]; r += (int)blockDim.x) {
+        const int a1 = lo[d1] + r % nn[d1], a2 = lo[d2] + r / nn[d1];
+        // (x, y, z) of the cell at distance m from the face cell along d
+        auto at = [&](int m, int& x, int& y, int& z) {
+          x = d == 0 ? e + m * in : (d1 == 0 ? a1 : a2);
+          y = d == 1 ? e + m * in : (d1 == 1 ? a1 : a2);
+          z = d == 2 ? e + m * in : a2;
+        };
+        float u[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          int x, y, z;
+          at(m, x, y, z);
+          u[m] = split_ld(h0, h1, b, x, y, z, zc);
+        }
+        int x, y, z;
+        at(-1, x, y, z);
+        split_st(h0, h1, b, x, y, z, ghost1<float>(cd, u[0], u[1], u[2], u[3]));
+        at(-2, x, y, z);
+        split_st(h0, h1, b, x, y, z, ghost2<float>(cd, u[0], u[1], u[2], u[3]));
+      }
+    }
+  }
+}
+
+// Sum of the folded diagonal increments of the x and y faces at (x, y),
+// added in the order of DiagColumn (uniformly filled faces).
+__device__ __forceinline__ float split_sfix(const BoxD& b, int x, int y) {
+  float S = -90.0f;
+  const int q[2] = {x, y};
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    const int lo = q[d], hi = b.n[d] - 1 - q[d];
+    if (lo < 2) S += fold<float>(b.ucode[d][0], lo);
+    if (hi < 2) S += fold<float>(b.ucode[d][1], hi);
+  }
+  return S;
+}
+
+// true if the tile touches a face of its box (its block writes ghosts)
+__device__ __forceinline__ bool tile_at_face(const TileD& t, const BoxD& b) {
+  return t.x0 == 0 || t.x0 + TILE_X >= b.n[0] || t.y0 == 0 || t.y0 + TILE3_Y >= b.n[1] || t.z0 == 0 ||
+         t.z0 + t.len >= b.n[2];
+}
+
+// One red-black half-sweep of colour `col` in split storage (the arithmetic
+// of k_march1<OP_RB>): out_c = u_c + omega (f_c - A u)_c / diag on the cells
+// of colour col, u given by its halves h0, h1; fc and out are half col of f
+// and of the output.  MODE 1: the interior cells of colour col are zero (the
+// second half-sweep after a first one from zero; only the ghosts of colour
+// col are read from half col, which may be the output half); MODE 2: u is
+// zero (the first half-sweep from zero, out_c = omega f_c / diag; h0, h1
+// unused).  Blocks of
+// 4 wavefronts over the sweep tiles (128 x 4 columns): lane i of wavefront w
+// takes the colour-col cell of row (y0 + w, z) in the i-th aligned pair from
+// x0, whose x alternates between x0 + 2i and x0 + 2i + 1 from plane to
+// plane while its split index moves by one plane stride.  Along z the thread
+// keeps both halves at planes -2..+2 in registers; x and y neighbours are
+// re-read through the caches.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_rbs(const TileD* __restrict__ tiles, int ntiles,
+                                             const BoxD* __restrict__ boxes, const float* h0, const float* h1,
+                                             const float* __restrict__ fc, float* __restrict__ out, float alpha,
+                                             float beta, float omega, int col) {
+  const int ti = tile_of_block(ntiles);
+  if (ti < 0) return;
+  const TileD t = tiles[ti];
+  const BoxD b = boxes[t.box];
+  if (MODE != 2 && tile_at_face(t, b)) {  // block-uniform
+    split_ghosts(t, b, const_cast<float*>(h0), const_cast<float*>(h1), MODE == 1 ? col : -1);
+    __syncthreads();
+  }
+  const int i = threadIdx.x & 63, y = t.y0 + (int)(threadIdx.x >> 6);
+  const int nxh = min(TILE_X, b.n[0] - t.x0) >> 1;
+  if (i >= nxh || y >= b.n[1]) return;
+  const float* __restrict__ self = col ? h1 : h0;
+  const float* __restrict__ oth = col ? h0 : h1;
+  const int64_t sy = b.s[1] >> 1, sz = b.s[2] >> 1;
+  const int z0 = t.z0, z1 = min(t.z0 + t.len, b.n[2]), nz = b.n[2];
+  // split index of the thread's cell at plane z0 (x = x0 + 2i + parity)
+  int64_t c = (b.off >> 1) + 1 + (t.x0 >> 1) + i + (int64_t)(y + 2) * sy + (int64_t)(z0 + 2) * sz;
+  // x parity of the colour-col cell of the pair: (col + lo + x + y + z) even
+  int par = (col + b.lo[0] + b.lo[1] + b.lo[2] + t.x0 + y + z0) & 1;
+  const int xa = t.x0 + 2 * i;
+  const float SfA = split_sfix(b, xa, y), SfB = split_sfix(b, xa + 1, y);
+  const float imA = 1.0f / (alpha + beta * SfA), imB = 1.0f / (alpha + beta * SfB);
+  const uint8_t zl = b.ucode[2][0], zh = b.ucode[2][1];
+  const float flo0 = fold<float>(zl, 0), flo1 = fold<float>(zl, 1);
+  const float fhi0 = fold<float>(zh, 0), fhi1 = fold<float>(zh, 1);
+  // own colour at plane q / at a neighbour: MODE 1 reads only ghosts
+  auto own = [&](int64_t j, bool ghost) { return (MODE == 0 || (MODE == 1 && ghost)) ? self[j] : 0.0f; };
+  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f, o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
+  if (MODE != 2) {
+    s0 = own(c - 2 * sz, z0 - 2 < 0);
+    s1 = own(c - sz, z0 - 1 < 0);
+    s2 = own(c, false);
+    s3 = own(c + sz, z0 + 1 >= nz);
+  }
+  if (MODE != 2) {
+    o0 = oth[c - 2 * sz];
+    o1 = oth[c - sz];
+    o2 = oth[c];
+    o3 = oth[c + sz];
+  }
+  for (int z = z0; z < z1; ++z, c += sz, par ^= 1) {
+    float inv;
+    if (z >= 2 && z <= nz - 3) {
+      inv = par ? imB : imA;
+    } else {
+      float S = par ? SfB : SfA;
+      if (z < 2) S += z == 0 ? flo0 : flo1;
+      if (z > nz - 3) S += z == nz - 1 ? fhi0 : fhi1;
+      inv = 1.0f / (alpha + beta * S);
+    }
+    if (MODE == 2) {
+      out[c] = omega * fc[c] * inv;
+      continue;
+    }
+    const int x = xa + par;
+    const float s4 = own(c + 2 * sz, z + 2 >= nz), o4 = oth[c + 2 * sz];
+    const float on = oth[c + (par ? 1 : -1)];
+    const float xm1 = par ? o2 : on, xp1 = par ? on : o2;
+    const float xm2 = own(c - 1, x < 2), xp2 = own(c + 1, x + 2 >= b.n[0]);
+    const float ym2 = own(c - 2 * sy, y < 2), yp2 = own(c + 2 * sy, y + 2 >= b.n[1]);
+    float ls = 16.0f * (xm1 + xp1) - (xm2 + xp2) + 16.0f * (o1 + o3) - (s0 + s4) + -90.0f * s2;
+    ls += 16.0f * (oth[c - sy] + oth[c + sy]) - (ym2 + yp2);
+    const float Au = alpha * s2 + beta * ls;
+    out[c] = s2 + omega * (fc[c] - Au) * inv;
+    s0 = s1;
+    s1 = s2;
+    s2 = s3;
+    s3 = s4;
+    o0 = o1;
+    o1 = o2;
+    o2 = o3;
+    o3 = o4;
+  }
+  (void)o0;
+}
+
+// the pair of cells (x, x + 1) at element e (x even) of a split array whose
+// cell x has colour cx, in x order
+__device__ __forceinline__ Pair<float> split_pair_ld(const float* h0, const float* h1, int64_t e, int cx) {
+  return Pair<float>{(cx ? h1 : h0)[e >> 1], (cx ? h0 : h1)[e >> 1]};
+}
+
+// Residual fused with restriction on a split iterate (halves h0, h1) and a
+// split right-hand side (halves f0, f1): the arithmetic of
+// k_march<OP_RESTRICT>, after the block has written the ghosts of its tile
+// into the iterate (read-time fill, as in k_rbs).  Output: the coarse
+// right-hand side, interleaved.
+__global__ void __launch_bounds__(256) k_resid_restrict_s(const TileD* __restrict__ tiles, int ntiles,
+                                                          const BoxD* __restrict__ boxes, const float* h0,
+                                                          const float* h1, const float* __restrict__ f0,
+                                                          const float* __restrict__ f1, float* __restrict__ out,
+                                                          float alpha, float beta,
+                                                          const BoxD* __restrict__ cboxes) {
+  __shared__ float R[2][64];
+  const int ti = tile_of_block(ntiles);
+  if (ti < 0) return;
+  const TileD t = tiles[ti];
+  const BoxD b = boxes[t.box];
+  if (tile_at_face(t, b)) {  // block-uniform
+    split_ghosts(t, b, const_cast<float*>(h0), const_cast<float*>(h1), -1);
+    __syncthreads();
+  }
+  const Column C = column_of<3>(t, b);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // lanes up to two cells past the box feed the x-neighbours of the last cells
+  const bool has = C.x < b.n[0] + 2 && C.y < b.n[1];
+  const int64_t sm = C.sm, sy = b.s[1];
+  int64_t c = C.base + (int64_t)(C.p0 + 2) * sm;
+  int cx = colour_of(b, C.x, C.y, C.p0);  // colour of cell x at plane p
+  Pair<float> q0{}, q1{}, q2{}, q3{}, q4{};
+  if (has) {
+    q0 = split_pair_ld(h0, h1, c - 2 * sm, cx);
+    q1 = split_pair_ld(h0, h1, c - sm, cx ^ 1);
+    q2 = split_pair_ld(h0, h1, c, cx);
+    q3 = split_pair_ld(h0, h1, c + sm, cx ^ 1);
+  }
+  float acc = 0.0f;
+  for (int p = C.p0; p < C.p1; ++p, c += sm, cx ^= 1) {
+    if (has) q4 = split_pair_ld(h0, h1, c + 2 * sm, cx);
+    float La = __shfl_up(q2.a, 1, 64), Lb = __shfl_up(q2.b, 1, 64);
+    float Ra = __shfl_down(q2.a, 1, 64), Rb = __shfl_down(q2.b, 1, 64);
+    float o0 = 0.0f, o1 = 0.0f;
+    if (C.ok) {
+      if (lane == 0) {
+        const Pair<float> l = split_pair_ld(h0, h1, c - 2, cx);
+        La = l.a;
+        Lb = l.b;
+      }
+      if (lane == 63) {
+        const Pair<float> r = split_pair_ld(h0, h1, c + 2, cx);
+        Ra = r.a;
+        Rb = r.b;
+      }
+      float s0 = 16.0f * (Lb + q2.b) - (La + Ra) + 16.0f * (q1.a + q3.a) - (q0.a + q4.a) + -90.0f * q2.a;
+      float s1 = 16.0f * (q2.a + Ra) - (Lb + Rb) + 16.0f * (q1.b + q3.b) - (q0.b + q4.b) + -90.0f * q2.b;
+      const Pair<float> ym1 = split_pair_ld(h0, h1, c - sy, cx ^ 1), yp1 = split_pair_ld(h0, h1, c + sy, cx ^ 1),
+                        ym2 = split_pair_ld(h0, h1, c - 2 * sy, cx), yp2 = split_pair_ld(h0, h1, c + 2 * sy, cx);
+      s0 += 16.0f * (ym1.a + yp1.a) - (ym2.a + yp2.a);
+      s1 += 16.0f * (ym1.b + yp1.b) - (ym2.b + yp2.b);
+      const float A0 = alpha * q2.a + beta * s0, A1 = alpha * q2.b + beta * s1;
+      const Pair<float> fv = split_pair_ld(f0, f1, c, cx);
+      o0 = fv.a - A0;
+      o1 = fv.b - A1;
+    }
+    acc += o0 + o1;  // x pair (fine sizes are even, so both cells exist)
+    if ((p - C.p0) & 1) {
+      if (w & 1) R[w >> 1][lane] = acc;
+      __syncthreads();
+      if (!(w & 1) && C.ok) {
+        const BoxD cb = cboxes[b.coarse];
+        out[cell_index<3>(cb, C.x >> 1, C.y >> 1, p >> 1)] = (acc + R[w >> 1][lane]) * 0.125f;
+      }
+      __syncthreads();
+      acc = 0.0f;
+    }
+    q0 = q1;
+    q1 = q2;
+    q2 = q3;
+    q3 = q4;
+  }
+}
+
+// Prolongation in split storage: out = u + P ec (the arithmetic of
+// k_prolong), u and out split (halves u0, u1 and o0, o1)
+__global__ void __launch_bounds__(256) k_prolong_s(const TileD* __restrict__ tiles, int ntiles,
+                                                   const BoxD* __restrict__ boxes, const BoxD* __restrict__ cboxes,
+                                                   const float* __restrict__ ec, const float* __restrict__ u0,
+                                                   const float* __restrict__ u1, float* __restrict__ o0,
+                                                   float* __restrict__ o1) {
+  FOR_COLUMN(3) {
+    const BoxD cb = cboxes[b.coarse];
+    const int64_t q = cell_index<3>(cb, C.x >> 1, C.y >> 1, p >> 1);
+    float common = 0.25f * ec[q] + 0.25f * ec[q + ((C.y & 1) ? cb.s[1] : -cb.s[1])];
+    common += 0.25f * ec[q + ((p & 1) ? cb.s[2] : -cb.s[2])];
+    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+    const int cx = colour_of(b, C.x, C.y, p);
+    const Pair<float> uv = split_pair_ld(u0, u1, c, cx);
+    (cx ? o1 : o0)[c >> 1] = uv.a + (common + 0.25f * ec[q - 1]);
+    (cx ? o0 : o1)[c >> 1] = uv.b + (common + 0.25f * ec[q + 1]);
+  }
+}
+
+// x += s e with e in split storage (halves e0, e1), s = scal[0]
+__global__ void __launch_bounds__(256) k_update_s(const TileD* __restrict__ tiles, int ntiles,
+                                                  const BoxD* __restrict__ boxes, double* __restrict__ x,
+                                                  const float* __restrict__ e0, const float* __restrict__ e1,
+                                                  const double* __restrict__ scal) {
+  const double s = scal[0];
+  FOR_COLUMN(3) {
+    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+    const int cx = colour_of(b, C.x, C.y, p);
+    const float ea = (cx ? e1 : e0)[c >> 1], eb = (cx ? e0 : e1)[c >> 1];
+    const Pair<double> xv = ld2(x + c);
+    st2(x + c, xv.a + s * (double)ea, xv.b + s * (double)eb);
   }
 }
 
@@ -2308,16 +2637,58 @@ void launch_update(int dim, const Depth& D, double* x, const T* e, const double*
 }
 
 void launch_to32(int dim, const Depth& D, const double* r, float* r32, const double* scal, hipStream_t st,
-                 const double* delta) {
+                 const double* delta, float* fs) {
   const size_t n = D.tiles.size();
   if (!n) return;
-  DISPATCH_DIM(dim, k_to32, D.d_tiles, (int)n, D.d_box, r, r32, scal, delta);
+  float* fs1 = fs ? fs + D.nstored / 2 : nullptr;
+  DISPATCH_DIM(dim, k_to32, D.d_tiles, (int)n, D.d_box, r, r32, scal, delta, fs, fs1);
 }
 
-void launch_scale32(int dim, const Depth& D, float* r32, const double* scal, hipStream_t st, const double* delta) {
+void launch_scale32(int dim, const Depth& D, float* r32, const double* scal, hipStream_t st, const double* delta,
+                    float* fs) {
   const size_t n = D.tiles.size();
   if (!n) return;
-  DISPATCH_DIM(dim, k_scale32, D.d_tiles, (int)n, D.d_box, r32, scal, delta);
+  float* fs1 = fs ? fs + D.nstored / 2 : nullptr;
+  DISPATCH_DIM(dim, k_scale32, D.d_tiles, (int)n, D.d_box, r32, scal, delta, fs, fs1);
+}
+
+void launch_rbs(const Depth& D, int mode, const float* h0, const float* h1, const float* fc, float* out,
+                float alpha, float beta, float omega, int col, hipStream_t st) {
+  const size_t n = D.stiles.size();
+  if (!n) return;
+  if (mode == 0)
+    hipLaunchKernelGGL(k_rbs<0>, grid8(n), dim3(256), 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
+                       beta, omega, col);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_rbs<1>, grid8(n), dim3(256), 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
+                       beta, omega, col);
+  else
+    hipLaunchKernelGGL(k_rbs<2>, grid8(n), dim3(256), 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
+                       beta, omega, col);
+}
+
+void launch_resid_restrict_s(const Depth& F, const Depth& C, const float* u, const float* f, float* fc, float alpha,
+                             float beta, hipStream_t st) {
+  const size_t n = F.stiles.size();
+  if (!n) return;
+  const int64_t hs = F.nstored / 2;
+  hipLaunchKernelGGL(k_resid_restrict_s, grid8(n), threads<3>(), 0, st, F.d_stiles, (int)n, F.d_box, u, u + hs, f,
+                     f + hs, fc, alpha, beta, C.d_box);
+}
+
+void launch_prolong_s(const Depth& F, const Depth& C, const float* ec, const float* u, float* out, hipStream_t st) {
+  const size_t n = F.stiles.size();
+  if (!n) return;
+  const int64_t hs = F.nstored / 2;
+  hipLaunchKernelGGL(k_prolong_s, grid8(n), threads<3>(), 0, st, F.d_stiles, (int)n, F.d_box, C.d_box, ec, u,
+                     u + hs, out, out + hs);
+}
+
+void launch_update_s(const Depth& D, double* x, const float* e, const double* scal, hipStream_t st) {
+  const size_t n = D.tiles.size();
+  if (!n) return;
+  hipLaunchKernelGGL(k_update_s, grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, x, e,
+                     e + D.nstored / 2, scal);
 }
 
 void launch_residual32(int dim, const Depth& D, const double* u, const double* f, float* r, double alpha, double beta,
