@@ -189,6 +189,7 @@ struct Depth {
   bool fill_only = false;  // every ghost column is filled from its own row (no exchange or interpolated ghosts)
   bool fuse_rb = false;    // the fused red-black sweep (k_rb2) applies to this depth
   bool split_rb = false;   // colour-split storage (k_rbs) applies to this depth
+  bool uniform_fill = false;  // every face of every box filled uniformly from its own rows, both ghost layers
   int march = 2;  // cells each tile marches along the last direction
   // device copies
   BoxD* d_box = nullptr;

@@ -347,7 +347,10 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, cons
     smooth<T>(R, k, o.smoother, o.nu1, relax(o), true, cur[k], oth[k], f[k]);
     T alpha, beta;
     coefs<T>(R.H, D, alpha, beta);
-    {
+    // below the finest depth the FP32 restriction writes the ghosts it reads
+    // itself where every face is filled uniformly (no fill launch)
+    const int rgr = (sizeof(T) == 4 && !R.tr && k > 0 && D.uniform_fill) ? 1 : 0;
+    if (!rgr) {
       Timed tm(R, AMG_T_FILL, k);
       fill_op<T>(R, D, cur[k]);
     }
@@ -359,14 +362,17 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, cons
     } else {
       Timed tm(R, AMG_T_RESTRICT, k);
       launch_resid_restrict<T>(R.dim, D, L.depths[k + 1], cur[k], f[k], Bufs<T>::f(L.depths[k + 1]), alpha, beta,
-                               R.st);
+                               R.st, rgr);
     }
     remove_mean<T>(R, k + 1, Bufs<T>::f(L.depths[k + 1]));
   }
   for (int k = K - 2; k >= 0; --k) {
     Depth& D = L.depths[k];
     if (D.stiles.empty()) continue;
-    launch_fill<T>(L.depths[k + 1], cur[k + 1], nullptr, R.st);
+    // the FP32 prolongation into depths below the finest forms the coarse
+    // ghosts it reads where the coarse faces are filled uniformly
+    const int pgr = (sizeof(T) == 4 && !R.tr && k > 0 && L.depths[k + 1].uniform_fill) ? 1 : 0;
+    if (!pgr) launch_fill<T>(L.depths[k + 1], cur[k + 1], nullptr, R.st);
     if constexpr (sizeof(T) == 4) {
       if (k == 0 && fs0) {
         // the prolongation writes the corrected iterate into the free buffer
@@ -381,7 +387,7 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, cons
     }
     {
       Timed tm(R, AMG_T_PROLONG, k);
-      launch_prolong<T>(R.dim, D, L.depths[k + 1], cur[k + 1], cur[k], R.st);
+      launch_prolong<T>(R.dim, D, L.depths[k + 1], cur[k + 1], cur[k], R.st, pgr);
     }
     smooth<T>(R, k, o.smoother, o.nu2, relax(o), false, cur[k], oth[k], f[k]);
   }

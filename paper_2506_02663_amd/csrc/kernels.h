@@ -42,12 +42,16 @@ template <typename T>
 void launch_rb(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, T omega, int col, bool zero,
                hipStream_t st, int gr = 0);
 template <typename T>
+// gr != 0 (F.uniform_fill): the kernel writes the ghosts it reads itself
+// (no fill launch before it)
 void launch_resid_restrict(int dim, const Depth& F, const Depth& C, const T* u, const T* f, T* fc, T alpha, T beta,
-                           hipStream_t st);
+                           hipStream_t st, int gr = 0);
 template <typename T>
 void launch_restrict(int dim, const Depth& F, const Depth& C, const T* r, T* fc, hipStream_t st);
 template <typename T>
-void launch_prolong(int dim, const Depth& F, const Depth& C, const T* ec, T* u, hipStream_t st);
+// gr != 0 (C.uniform_fill): the coarse ghosts it reads are formed from the
+// coarse rows (no fill launch on C before it)
+void launch_prolong(int dim, const Depth& F, const Depth& C, const T* ec, T* u, hipStream_t st, int gr = 0);
 template <typename T>
 void launch_bottom(const Depth& D, const double* mats, const int64_t* idx, const T* f, T* e, bool tr, hipStream_t st,
                    T* e2 = nullptr);

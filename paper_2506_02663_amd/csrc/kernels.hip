@@ -337,6 +337,31 @@ __device__ __forceinline__ void face_ghosts(const BoxD& b, T* __restrict__ u, in
   }
 }
 
+// Ghosts along the march direction of the tile's columns (the faces at the
+// ends of the march), from each column's own code, on the faces the tile
+// reaches; written by the block before its march like face_ghosts.
+template <typename T, int DIM>
+__device__ __forceinline__ void march_ghosts(const TileD& t, const BoxD& b, const uint8_t* __restrict__ codes,
+                                             T* __restrict__ u) {
+  constexpr int M = DIM - 1;
+  const int p0 = DIM == 2 ? t.y0 : t.z0, len = min(t.len, b.n[M] - p0);
+  const int nx = min(TILE_X, b.n[0] - t.x0), ny = DIM == 3 ? min(TILE3_Y, b.n[1] - t.y0) : 1;
+  for (int side = 0; side < 2; ++side) {
+    if (side == 0 ? p0 != 0 : p0 + len != b.n[M]) continue;
+    for (int r = (int)threadIdx.x; r < nx * ny; r += (int)blockDim.x) {
+      const int x = t.x0 + r % nx, y = DIM == 3 ? t.y0 + r / nx : 0;
+      const uint8_t cd = codes[b.code_off[M][side] + (DIM == 2 ? x : x + b.n[0] * y)];
+      if (!(cd & 3)) continue;
+      const int pe = side ? b.n[M] - 1 : 0;
+      const int64_t e0 = DIM == 3 ? cell_index<3>(b, x, y, pe) : cell_index<2>(b, x, pe, 0);
+      const int64_t in = (side ? -1 : 1) * (int64_t)b.s[M];
+      const T u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
+      u[e0 - in] = ghost1<T>(cd, u0, u1, u2, u3);
+      if (cd & 4) u[e0 - 2 * in] = ghost2<T>(cd, u0, u1, u2, u3);
+    }
+  }
+}
+
 // the same for the cells of one column tile
 template <typename T, int DIM>
 __device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __restrict__ u) {
@@ -800,13 +825,25 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
                                                const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
                                                const T* __restrict__ u, const T* __restrict__ f, TO* __restrict__ out,
                                                T alpha, T beta, T omega, int col, double* __restrict__ part,
-                                               const BoxD* __restrict__ cboxes) {
+                                               const BoxD* __restrict__ cboxes, int gr) {
   __shared__ double sh[4];
   __shared__ T R[2][64];
   const int ti = tile_of_block(ntiles);
   if (ti < 0) return;
   const TileD t = tiles[ti];
   const BoxD b = boxes[t.box];
+  // gr != 0 (every face filled uniformly from its own rows, both layers): a
+  // block whose tile touches a face writes the ghosts its cells read there
+  // first, so no fill launch is needed before the kernel
+  if (gr) {
+    const int p0 = DIM == 2 ? t.y0 : t.z0, nm = b.n[DIM - 1];
+    if (t.x0 == 0 || t.x0 + TILE_X >= b.n[0] || (DIM == 3 && (t.y0 == 0 || t.y0 + TILE3_Y >= b.n[1])) || p0 == 0 ||
+        p0 + t.len >= nm) {  // block-uniform
+      tile_ghosts<T, DIM>(t, b, const_cast<T*>(u));
+      march_ghosts<T, DIM>(t, b, codes, const_cast<T*>(u));
+      __syncthreads();
+    }
+  }
   const Column C = column_of<DIM>(t, b);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   // lanes up to two cells past the box feed the x-neighbours of the last cells
@@ -1179,19 +1216,33 @@ __global__ void __launch_bounds__(256) k_restrict(const TileD* __restrict__ tile
 // u += face-neighbour linear interpolation of the coarse correction:
 // (1 - DIM/4) e_P + 1/4 sum_d e_{P + s_d e_d}, s_d the child's side;
 // marched over fine tiles.  The thread's two cells x, x+1 share the parent.
+// Neighbour of coarse cell q (coordinate pd along direction d) on side s
+// (-1, +1); with gr != 0 (the coarse faces filled uniformly from their own
+// rows) a neighbour beyond the box is its first ghost, formed from the row.
+template <typename T>
+__device__ __forceinline__ T coarse_nb(const T* __restrict__ ec, const BoxD& cb, int64_t q, int d, int pd, int s,
+                                       int gr) {
+  const int64_t st = d == 0 ? 1 : cb.s[d];
+  if (gr && s < 0 && pd == 0) return ghost1<T>(cb.ucode[d][0], ec[q], ec[q + st], ec[q + 2 * st], ec[q + 3 * st]);
+  if (gr && s > 0 && pd == cb.n[d] - 1)
+    return ghost1<T>(cb.ucode[d][1], ec[q], ec[q - st], ec[q - 2 * st], ec[q - 3 * st]);
+  return ec[q + s * st];
+}
+
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_prolong(const TileD* __restrict__ tiles, int ntiles,
                                                  const BoxD* __restrict__ boxes, const BoxD* __restrict__ cboxes,
-                                                 const T* __restrict__ ec, T* __restrict__ u) {
+                                                 const T* __restrict__ ec, T* __restrict__ u, int gr) {
   FOR_COLUMN(DIM) {
     const int cy = DIM == 2 ? p : C.y, cz = DIM == 2 ? 0 : p;
     const BoxD cb = cboxes[b.coarse];
-    const int64_t q = cell_index<DIM>(cb, C.x >> 1, cy >> 1, cz >> 1);
-    T common = T(1.0 - DIM * 0.25) * ec[q] + T(0.25) * ec[q + ((cy & 1) ? cb.s[1] : -cb.s[1])];
-    if (DIM == 3) common += T(0.25) * ec[q + ((cz & 1) ? cb.s[2] : -cb.s[2])];
+    const int px = C.x >> 1, py = cy >> 1, pz = cz >> 1;
+    const int64_t q = cell_index<DIM>(cb, px, py, pz);
+    T common = T(1.0 - DIM * 0.25) * ec[q] + T(0.25) * coarse_nb<T>(ec, cb, q, 1, py, (cy & 1) ? 1 : -1, gr);
+    if (DIM == 3) common += T(0.25) * coarse_nb<T>(ec, cb, q, 2, pz, (cz & 1) ? 1 : -1, gr);
     const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
-    u[c] += common + T(0.25) * ec[q - 1];
-    if (C.ok1) u[c + 1] += common + T(0.25) * ec[q + 1];
+    u[c] += common + T(0.25) * coarse_nb<T>(ec, cb, q, 0, px, -1, gr);
+    if (C.ok1) u[c + 1] += common + T(0.25) * coarse_nb<T>(ec, cb, q, 0, px, 1, gr);
   }
 }
 
@@ -2302,7 +2353,7 @@ struct MarchK {
                          D.d_box, D.d_codes, u, f, out, a, b, w, col, part, gr);
     else
       hipLaunchKernelGGL((k_march<T, DIM, OP, PART>), grid8(n), threads<DIM>(), 0, st, tl, (int)n, D.d_box, D.d_codes,
-                         u, f, out, a, b, w, col, part, cboxes);
+                         u, f, out, a, b, w, col, part, cboxes, gr);
   }
 };
 
@@ -2371,10 +2422,10 @@ void launch_rb(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha,
 
 template <typename T>
 void launch_resid_restrict(int dim, const Depth& F, const Depth& C, const T* u, const T* f, T* fc, T alpha, T beta,
-                           hipStream_t st) {
+                           hipStream_t st, int gr) {
   // marched over the fine tiles of the boxes that continue to depth+1
   march<T, OP_RESTRICT, false>(dim, F.d_stiles, F.stiles.size(), F, u, f, fc, alpha, beta, T(0), 0, nullptr, st,
-                               C.d_box);
+                               C.d_box, gr);
 }
 
 template <typename T>
@@ -2388,13 +2439,15 @@ void launch_restrict(int dim, const Depth& F, const Depth& C, const T* r, T* fc,
 }
 
 template <typename T>
-void launch_prolong(int dim, const Depth& F, const Depth& C, const T* ec, T* u, hipStream_t st) {
+void launch_prolong(int dim, const Depth& F, const Depth& C, const T* ec, T* u, hipStream_t st, int gr) {
   const size_t n = F.stiles.size();
   if (!n) return;
   if (dim == 2)
-    hipLaunchKernelGGL((k_prolong<T, 2>), grid8(n), threads<2>(), 0, st, F.d_stiles, (int)n, F.d_box, C.d_box, ec, u);
+    hipLaunchKernelGGL((k_prolong<T, 2>), grid8(n), threads<2>(), 0, st, F.d_stiles, (int)n, F.d_box, C.d_box, ec, u,
+                       gr);
   else
-    hipLaunchKernelGGL((k_prolong<T, 3>), grid8(n), threads<3>(), 0, st, F.d_stiles, (int)n, F.d_box, C.d_box, ec, u);
+    hipLaunchKernelGGL((k_prolong<T, 3>), grid8(n), threads<3>(), 0, st, F.d_stiles, (int)n, F.d_box, C.d_box, ec, u,
+                       gr);
 }
 
 template <typename T>
@@ -2697,10 +2750,10 @@ void launch_residual32(int dim, const Depth& D, const double* u, const double* f
   if (!n) return;
   if (dim == 2)
     hipLaunchKernelGGL((k_march<double, 2, OP_RESID, true, float>), grid8(n), threads<2>(), 0, st, D.d_tiles, (int)n,
-                       D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr);
+                       D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr, 0);
   else
     hipLaunchKernelGGL((k_march<double, 3, OP_RESID, true, float>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n,
-                       D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr);
+                       D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr, 0);
 }
 
 void launch_shift_copy(int dim, const Depth& D, const double* f, double* out, const double* delta, hipStream_t st) {
@@ -2732,9 +2785,9 @@ void launch_zero(T* a, int64_t n, hipStream_t st) {
   template void launch_rb<T>(int, const Depth&, const T*, const T*, T*, T, T, T, int, bool, hipStream_t, int);    \
   template void launch_rb2<T>(const Depth&, const T*, const T*, T*, T, T, T, hipStream_t);                         \
   template void launch_resid_restrict<T>(int, const Depth&, const Depth&, const T*, const T*, T*, T, T,           \
-                                         hipStream_t);                                                            \
+                                         hipStream_t, int);                                                       \
   template void launch_restrict<T>(int, const Depth&, const Depth&, const T*, T*, hipStream_t);                   \
-  template void launch_prolong<T>(int, const Depth&, const Depth&, const T*, T*, hipStream_t);                    \
+  template void launch_prolong<T>(int, const Depth&, const Depth&, const T*, T*, hipStream_t, int);               \
   template void launch_bottom<T>(const Depth&, const double*, const int64_t*, const T*, T*, bool, hipStream_t, T*); \
   template void launch_tile_sum<T>(int, const Depth&, const T*, double*, hipStream_t);                            \
   template void launch_tile_absmax<T>(int, const Depth&, const T*, double*, hipStream_t);                         \

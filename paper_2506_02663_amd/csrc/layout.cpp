@@ -522,6 +522,11 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       D.comp_seg_ptr.push_back((int32_t)D.seg_ptr.size() - 1);
     }
     D.fuse_rb = fuse_ok && !D.stiles.empty();
+    D.uniform_fill = D.fill_only;
+    for (const BoxD& X : D.boxd)
+      for (int d = 0; d < dim; ++d)
+        for (int s = 0; s < 2; ++s)
+          if (X.ucode[d][s] != 5 && X.ucode[d][s] != 6) D.uniform_fill = false;
     // colour-split storage (depth 0, 3D): every face filled uniformly with
     // both layers from its own row (the sweep computes all ghosts it reads),
     // even offsets, row lengths and plane sizes (each aligned pair of
