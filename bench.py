@@ -190,6 +190,8 @@ def main():
             for s in (0, 1):
                 H.set_physical_bc(d, s, A.DIRICHLET if bc == "D" else A.NEUMANN)
         H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c)
+        if args.no_split:  # before the autotuner, which times the sweep the solves will run
+            H.set_tuning(A.TUNE_SPLIT_RB, 0)
         if args.march:
             march = args.march
             H.set_tuning(A.TUNE_MARCH2 if dim == 2 else A.TUNE_MARCH3, march)
@@ -200,8 +202,6 @@ def main():
             H.set_tuning(A.TUNE_MARCH2 if dim == 2 else A.TUNE_MARCH3, march)
         if args.bottom_cells:
             H.set_bottom_cells(args.bottom_cells)
-        if args.no_split:
-            H.set_tuning(A.TUNE_SPLIT_RB, 0)
         H.finalize()
         fd = torch.tensor(H.pack(0, 0, lambda i, b: f), device="cuda")
         x = torch.zeros_like(fd)

@@ -440,7 +440,8 @@ int amg_time_sweep(amg_hier* h, int level, int dtype, int smoother, int n, void*
 
 /* Autotuning of the tile march length (cells a tile marches along the last
  * direction, AMG_TUNE_MARCH2/3) before amg_finalize: for each candidate
- * (8, 16, 32, 64, 128) a finalized copy of the layout times the finest-depth
+ * (4, 6, 8, 16, 32, 64, 128; from 8 for 3D sweeps in interleaved storage)
+ * a finalized copy of the layout times the finest-depth
  * smoothing kernel of `level` (amg_time_sweep, nreps launches, zero data);
  * the fastest candidate is set on h.  *best, *best_ms (may be NULL) receive
  * it and its time per launch.  Allocates and frees device memory. */

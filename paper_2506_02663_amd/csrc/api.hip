@@ -1832,7 +1832,7 @@ int amg_autotune(amg_hier* H, int level, int dtype, int smoother, int nreps, int
   if (!H) return AMG_EINVAL;
   if (H->finalized) return fail(H, AMG_EINVAL, "autotuning runs before amg_finalize");
   if (level < 0 || level >= H->nlevels || nreps < 1) return fail(H, AMG_EINVAL, "bad arguments");
-  const int cands[] = {8, 16, 32, 64, 128};
+  const int cands[] = {4, 6, 8, 16, 32, 64, 128};
   int arg = H->dim == 2 ? H->march2 : H->march3;
   double tbest = 1e300;
   for (int m : cands) {
@@ -1858,6 +1858,14 @@ int amg_autotune(amg_hier* H, int level, int dtype, int smoother, int nreps, int
       const std::string e = T->err;
       amg_destroy(T);
       return fail(H, rc, "autotune: " + e);
+    }
+    // marches below 8 are not tried for 3D sweeps in interleaved storage:
+    // they time well back to back there but not inside the solves (the
+    // colour-split sweep and 2D sweeps gain from them in the solves too)
+    const bool split = dtype == AMG_F32 && smoother == AMG_SMOOTH_RB && T->levels[level].depths[0].split_rb;
+    if (m < 8 && H->dim == 3 && !split) {
+      amg_destroy(T);
+      continue;
     }
     const size_t bytes = T->levels[level].depths[0].nstored * (dtype == AMG_F64 ? 8 : 4);
     void *u = nullptr, *f = nullptr, *t = nullptr;

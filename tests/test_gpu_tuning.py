@@ -52,7 +52,7 @@ def test_autotune_picks_a_candidate():
     H.set_level_boxes(0, [((0,) * 3, (63,) * 3)])
     H.set_operator(A.HELMHOLTZ, 1e-4)
     best, ms = H.autotune(0, A.F32, A.SMOOTH_RB, nreps=5)
-    assert best in (8, 16, 32, 64, 128) and ms > 0
+    assert best in (4, 6, 8, 16, 32, 64, 128) and ms > 0
     H.finalize()
     f = torch.ones(H.depth_size(0, 0)[0], dtype=torch.float64, device="cuda")
     x = torch.zeros_like(f)
