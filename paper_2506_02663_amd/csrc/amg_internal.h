@@ -40,6 +40,7 @@ struct BoxD {              // one box at one multigrid depth
   int32_t coarse;          // index at depth+1, -1 if the box ends here
   uint8_t ucode[3][2];     // column code shared by a whole face, 0xFF if the face mixes codes
   uint8_t pad[2];
+  int64_t xg;              // colour-split depths: first element of the box's x-face ghost rows in Depth::xg32
 };
 
 struct TileD {             // a column block of one box, marched along the last direction
@@ -204,6 +205,11 @@ struct Depth {
   double *e64 = nullptr, *f64 = nullptr, *t64 = nullptr;
   float *e32 = nullptr, *f32 = nullptr, *t32 = nullptr;
   float* fs32 = nullptr;  // right-hand side in colour-split storage (depth 0 with split_rb)
+  // x-face ghosts of split depths, outside the split halves: per box, rows
+  // (y, z) of the low face (2 layers) then of the high face; written by the
+  // tiles at the x faces and read by their edge lanes
+  float* xg32 = nullptr;
+  int64_t nxg = 0;
 };
 
 struct GraphCache {  // the captured outer cycle of one level

@@ -413,7 +413,7 @@ void free_level(amg::Level& L) {
   for (auto& D : L.depths) {
     for (void* p : {(void*)D.d_box, (void*)D.d_codes, (void*)D.d_chunks, (void*)D.d_tiles, (void*)D.d_stiles,
                     (void*)D.d_seg, (void*)D.d_cseg, (void*)D.d_cc_ptr, (void*)D.d_cc_idx, (void*)D.d_groups, (void*)D.d_band,
-                    (void*)D.e64, (void*)D.f64, (void*)D.t64, (void*)D.e32, (void*)D.f32, (void*)D.t32, (void*)D.fs32})
+                    (void*)D.e64, (void*)D.f64, (void*)D.t64, (void*)D.e32, (void*)D.f32, (void*)D.t32, (void*)D.fs32, (void*)D.xg32})
       if (p) (void)hipFree(p);
   }
   for (void* p : {(void*)L.d_mat, (void*)L.d_idx, (void*)L.r64, (void*)L.fsh, (void*)L.partial, (void*)L.partial2, (void*)L.comp_sum,
@@ -815,6 +815,7 @@ int amg_finalize(amg_hier* H) {
       TRY(zalloc(H, &D.f32, D.nstored));
       TRY(zalloc(H, &D.t32, D.nstored));
       if (D.split_rb) TRY(zalloc(H, &D.fs32, D.nstored));
+      if (D.split_rb) TRY(zalloc(H, &D.xg32, std::max<int64_t>(D.nxg, 1)));
       maxpart = std::max(maxpart, std::max(D.tiles.size(), D.chunks.size()));
       maxseg = std::max(maxseg, D.seg_ptr.size());
     }

@@ -1271,14 +1271,24 @@ __device__ __forceinline__ void split_st(float* h0, float* h1, const BoxD& b, in
   (colour_of(b, x, y, z) ? h1 : h0)[cell_index<3>(b, x, y, z) >> 1] = v;
 }
 
+// x-face ghost of row (y, z) of box b on side `side` (0 low, 1 high),
+// layer 1 or 2, in the side buffer xg: the rows of a face are contiguous
+__device__ __forceinline__ float* x_ghost(float* xg, const BoxD& b, int side, int y, int z, int layer) {
+  return xg + b.xg + (int64_t)side * 2 * b.n[1] * b.n[2] + ((int64_t)z * b.n[1] + y) * 2 + (layer - 1);
+}
+
 // Read-time fill in split storage: the two ghost layers of every face of the
 // box that the tile's cells read (every face filled uniformly, both layers
-// from its own row), written into the input halves before the march; one
-// thread per face row of the tile.  zc >= 0: the interior cells of colour zc
-// are zero (their half is not read); the ghosts of both colours are written.  Each of these ghosts is read only by
+// from its own row), written before the march: the y and z faces into the
+// input halves, the x faces into the side buffer xg (in the halves an x-face
+// ghost is one word per row and half, which would dirty a cache line each);
+// one thread per face row of the tile.  Each of these ghosts is read only by
 // this tile (smoothed boxes have even sizes and marches are even, so the
-// last tile of every row, column and march has at least 2 cells).
-__device__ __forceinline__ void split_ghosts(const TileD& t, const BoxD& b, float* h0, float* h1, int zc) {
+// last tile of every row, column and march has at least 2 cells).  zc >= 0:
+// the interior cells of colour zc are zero (their half is not read); the
+// ghosts of both colours are written.
+__device__ __forceinline__ void split_ghosts(const TileD& t, const BoxD& b, float* h0, float* h1, float* xg,
+                                             int zc) {
   const int lo[3] = {t.x0, t.y0, t.z0};
   const int nn[3] = {min(TILE_X, b.n[0] - t.x0), min(TILE3_Y, b.n[1] - t.y0), min(t.len, b.n[2] - t.z0)};
 #pragma unroll
@@ -1303,11 +1313,17 @@ __device__ __forceinline__ void split_ghosts(const TileD& t, const BoxD& b, floa
           at(m, x, y, z);
           u[m] = split_ld(h0, h1, b, x, y, z, zc);
         }
-        int x, y, z;
-        at(-1, x, y, z);
-        split_st(h0, h1, b, x, y, z, ghost1<float>(cd, u[0], u[1], u[2], u[3]));
-        at(-2, x, y, z);
-        split_st(h0, h1, b, x, y, z, ghost2<float>(cd, u[0], u[1], u[2], u[3]));
+        const float g1 = ghost1<float>(cd, u[0], u[1], u[2], u[3]), g2 = ghost2<float>(cd, u[0], u[1], u[2], u[3]);
+        if (d == 0) {
+          *x_ghost(xg, b, side, a1, a2, 1) = g1;
+          *x_ghost(xg, b, side, a1, a2, 2) = g2;
+        } else {
+          int x, y, z;
+          at(-1, x, y, z);
+          split_st(h0, h1, b, x, y, z, g1);
+          at(-2, x, y, z);
+          split_st(h0, h1, b, x, y, z, g2);
+        }
       }
     }
   }
@@ -1351,13 +1367,13 @@ template <int MODE>
 __global__ void __launch_bounds__(256) k_rbs(const TileD* __restrict__ tiles, int ntiles,
                                              const BoxD* __restrict__ boxes, const float* h0, const float* h1,
                                              const float* __restrict__ fc, float* __restrict__ out, float alpha,
-                                             float beta, float omega, int col) {
+                                             float beta, float omega, int col, float* xg) {
   const int ti = tile_of_block(ntiles);
   if (ti < 0) return;
   const TileD t = tiles[ti];
   const BoxD b = boxes[t.box];
   if (MODE != 2 && tile_at_face(t, b)) {  // block-uniform
-    split_ghosts(t, b, const_cast<float*>(h0), const_cast<float*>(h1), MODE == 1 ? col : -1);
+    split_ghosts(t, b, const_cast<float*>(h0), const_cast<float*>(h1), xg, MODE == 1 ? col : -1);
     __syncthreads();
   }
   const int i = threadIdx.x & 63, y = t.y0 + (int)(threadIdx.x >> 6);
@@ -1406,11 +1422,18 @@ __global__ void __launch_bounds__(256) k_rbs(const TileD* __restrict__ tiles, in
       out[c] = omega * fc[c] * inv;
       continue;
     }
-    const int x = xa + par;
+    const int x = xa + par, nx0 = b.n[0];
     const float s4 = own(c + 2 * sz, z + 2 >= nz), o4 = oth[c + 2 * sz];
-    const float on = oth[c + (par ? 1 : -1)];
+    // x neighbours beyond the box come from the side buffer: one load each,
+    // its address chosen per lane
+    const float* a_on = par ? (x + 1 >= nx0 ? x_ghost(xg, b, 1, y, z, 1) : oth + c + 1)
+                            : (x < 1 ? x_ghost(xg, b, 0, y, z, 1) : oth + c - 1);
+    const float on = *a_on;
     const float xm1 = par ? o2 : on, xp1 = par ? on : o2;
-    const float xm2 = own(c - 1, x < 2), xp2 = own(c + 1, x + 2 >= b.n[0]);
+    const float* a_m2 = x < 2 ? x_ghost(xg, b, 0, y, z, 2 - x) : self + c - 1;
+    const float* a_p2 = x + 2 >= nx0 ? x_ghost(xg, b, 1, y, z, x + 3 - nx0) : self + c + 1;
+    const float xm2 = (MODE == 0 || x < 2) ? *a_m2 : 0.0f;
+    const float xp2 = (MODE == 0 || x + 2 >= nx0) ? *a_p2 : 0.0f;
     const float ym2 = own(c - 2 * sy, y < 2), yp2 = own(c + 2 * sy, y + 2 >= b.n[1]);
     float ls = 16.0f * (xm1 + xp1) - (xm2 + xp2) + 16.0f * (o1 + o3) - (s0 + s4) + -90.0f * s2;
     ls += 16.0f * (oth[c - sy] + oth[c + sy]) - (ym2 + yp2);
@@ -1444,14 +1467,14 @@ __global__ void __launch_bounds__(256) k_resid_restrict_s(const TileD* __restric
                                                           const float* h1, const float* __restrict__ f0,
                                                           const float* __restrict__ f1, float* __restrict__ out,
                                                           float alpha, float beta,
-                                                          const BoxD* __restrict__ cboxes) {
+                                                          const BoxD* __restrict__ cboxes, float* xg) {
   __shared__ float R[2][64];
   const int ti = tile_of_block(ntiles);
   if (ti < 0) return;
   const TileD t = tiles[ti];
   const BoxD b = boxes[t.box];
   if (tile_at_face(t, b)) {  // block-uniform
-    split_ghosts(t, b, const_cast<float*>(h0), const_cast<float*>(h1), -1);
+    split_ghosts(t, b, const_cast<float*>(h0), const_cast<float*>(h1), xg, -1);
     __syncthreads();
   }
   const Column C = column_of<3>(t, b);
@@ -1471,19 +1494,33 @@ __global__ void __launch_bounds__(256) k_resid_restrict_s(const TileD* __restric
   float acc = 0.0f;
   for (int p = C.p0; p < C.p1; ++p, c += sm, cx ^= 1) {
     if (has) q4 = split_pair_ld(h0, h1, c + 2 * sm, cx);
-    float La = __shfl_up(q2.a, 1, 64), Lb = __shfl_up(q2.b, 1, 64);
-    float Ra = __shfl_down(q2.a, 1, 64), Rb = __shfl_down(q2.b, 1, 64);
+    // the lane whose pair is the x-high ghost pair feeds its left neighbour
+    // from the side buffer
+    Pair<float> sq = q2;
+    if (C.x == b.n[0] && C.y < b.n[1]) sq = Pair<float>{*x_ghost(xg, b, 1, C.y, p, 1), *x_ghost(xg, b, 1, C.y, p, 2)};
+    float La = __shfl_up(sq.a, 1, 64), Lb = __shfl_up(sq.b, 1, 64);
+    float Ra = __shfl_down(sq.a, 1, 64), Rb = __shfl_down(sq.b, 1, 64);
     float o0 = 0.0f, o1 = 0.0f;
     if (C.ok) {
       if (lane == 0) {
-        const Pair<float> l = split_pair_ld(h0, h1, c - 2, cx);
-        La = l.a;
-        Lb = l.b;
+        if (C.x == 0) {
+          La = *x_ghost(xg, b, 0, C.y, p, 2);
+          Lb = *x_ghost(xg, b, 0, C.y, p, 1);
+        } else {
+          const Pair<float> l = split_pair_ld(h0, h1, c - 2, cx);
+          La = l.a;
+          Lb = l.b;
+        }
       }
       if (lane == 63) {
-        const Pair<float> r = split_pair_ld(h0, h1, c + 2, cx);
-        Ra = r.a;
-        Rb = r.b;
+        if (C.x + 2 == b.n[0]) {
+          Ra = *x_ghost(xg, b, 1, C.y, p, 1);
+          Rb = *x_ghost(xg, b, 1, C.y, p, 2);
+        } else {
+          const Pair<float> r = split_pair_ld(h0, h1, c + 2, cx);
+          Ra = r.a;
+          Rb = r.b;
+        }
       }
       float s0 = 16.0f * (Lb + q2.b) - (La + Ra) + 16.0f * (q1.a + q3.a) - (q0.a + q4.a) + -90.0f * q2.a;
       float s1 = 16.0f * (q2.a + Ra) - (Lb + Rb) + 16.0f * (q1.b + q3.b) - (q0.b + q4.b) + -90.0f * q2.b;
@@ -2711,13 +2748,13 @@ void launch_rbs(const Depth& D, int mode, const float* h0, const float* h1, cons
   if (!n) return;
   if (mode == 0)
     hipLaunchKernelGGL(k_rbs<0>, grid8(n), dim3(256), 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
-                       beta, omega, col);
+                       beta, omega, col, D.xg32);
   else if (mode == 1)
     hipLaunchKernelGGL(k_rbs<1>, grid8(n), dim3(256), 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
-                       beta, omega, col);
+                       beta, omega, col, D.xg32);
   else
     hipLaunchKernelGGL(k_rbs<2>, grid8(n), dim3(256), 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
-                       beta, omega, col);
+                       beta, omega, col, D.xg32);
 }
 
 void launch_resid_restrict_s(const Depth& F, const Depth& C, const float* u, const float* f, float* fc, float alpha,
@@ -2726,7 +2763,7 @@ void launch_resid_restrict_s(const Depth& F, const Depth& C, const float* u, con
   if (!n) return;
   const int64_t hs = F.nstored / 2;
   hipLaunchKernelGGL(k_resid_restrict_s, grid8(n), threads<3>(), 0, st, F.d_stiles, (int)n, F.d_box, u, u + hs, f,
-                     f + hs, fc, alpha, beta, C.d_box);
+                     f + hs, fc, alpha, beta, C.d_box, F.xg32);
 }
 
 void launch_prolong_s(const Depth& F, const Depth& C, const float* ec, const float* u, float* out, hipStream_t st) {

@@ -547,6 +547,12 @@ int plan_level(amg_hier* H, int l, std::string& err) {
         split_ok = false;
     }
     D.split_rb = split_ok;
+    D.nxg = 0;
+    if (split_ok)
+      for (BoxD& X : D.boxd) {
+        X.xg = D.nxg;
+        D.nxg += 4 * (int64_t)X.n[1] * X.n[2];
+      }
     for (const TileD& T : D.stiles)
       if (T.len < 4) D.fuse_rb = false;
     prev_index = cur_index;
