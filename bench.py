@@ -513,9 +513,12 @@ def bench_batched(args):
         for sd in (0, 1):
             H.set_physical_bc(d, sd, A.DIRICHLET)
     H.set_operator(A.HELMHOLTZ, c)
+    if args.no_split:
+        H.set_tuning(A.TUNE_SPLIT_RB, 0)
     t0 = time.perf_counter()
     H.finalize()
     setup_s = time.perf_counter() - t0
+    split_on = bool(H.level_info(0).split_rb) and args.precision == "mixed" and args.smoother == "rb"
     fd = torch.tensor(H.pack(0, 0, lambda i, b: fs[i]), device="cuda")
     x = torch.zeros_like(fd)
     ncell = int(sum(s * s for s in sides))
@@ -543,7 +546,7 @@ def bench_batched(args):
         "dtype": "f32-in-f64" if prec == A.MIXED else "f64", "data": "synthetic",
         "config": {"workload": "batch of 1024 independent 2D boxes, sides 8m, m~U{2..32}, Dirichlet Helmholtz",
                    "cells": ncell, "tol_rel": 1e-10, "cycles": info["cycles"], "smoother": args.smoother,
-                   "precision": args.precision, "vcycle": "V(2,2)", "setup_s": setup_s},
+                   "precision": args.precision, "vcycle": "V(2,2)", "setup_s": setup_s, "split_storage": split_on},
     }
     if not args.no_timing:
         # the finest sweep over all 1024 boxes, 50 launches back to back
@@ -561,7 +564,8 @@ def bench_batched(args):
         ach = bytes_launch / avg_s / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                           "kernel": f"{args.smoother} {'half-' if args.smoother == 'rb' else ''}sweep, finest depth, all 1024 boxes in one launch",
+                           "kernel": f"{args.smoother} {'half-' if args.smoother == 'rb' else ''}sweep, finest depth, all 1024 boxes in one launch"
+                                     f"{', colour-split storage' if split_on else ''}",
                            "avg_us": avg_s * 1e6, "launches": cnt, "bytes_per_launch": bytes_launch}
     if base is not None:
         out["cpu_baseline"] = base

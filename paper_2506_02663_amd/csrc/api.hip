@@ -261,8 +261,8 @@ inline double relax(const amg_solve_opts& o) { return o.smoother == AMG_SMOOTH_R
 // starts in buffer a (both halves), b is the second buffer; each half-sweep
 // writes its colour's half into the buffer that does not hold it.  Returns
 // the buffer that holds the final iterate (both halves).
-float* smooth_split(const Run* R, hipStream_t st, const Depth& D, int k, int nsweeps, float alpha, float beta,
-                    float omega, const float* fs, float* a, float* b) {
+float* smooth_split(const Run* R, hipStream_t st, int dim, const Depth& D, int k, int nsweeps, float alpha,
+                    float beta, float omega, const float* fs, float* a, float* b) {
   const int64_t hs = D.nstored / 2;
   const float* h[2] = {a, a + hs};
   for (int s = 0; s < nsweeps; ++s)
@@ -270,9 +270,9 @@ float* smooth_split(const Run* R, hipStream_t st, const Depth& D, int k, int nsw
       float* dst = (h[col] == a + col * hs ? b : a) + col * hs;
       if (R) {
         Timed tm(*R, AMG_T_SWEEP_SPLIT, k);
-        launch_rbs(D, 0, h[0], h[1], fs + col * hs, dst, alpha, beta, omega, col, st);
+        launch_rbs(dim, D, 0, h[0], h[1], fs + col * hs, dst, alpha, beta, omega, col, st);
       } else {
-        launch_rbs(D, 0, h[0], h[1], fs + col * hs, dst, alpha, beta, omega, col, st);
+        launch_rbs(dim, D, 0, h[0], h[1], fs + col * hs, dst, alpha, beta, omega, col, st);
       }
       h[col] = dst;
     }
@@ -293,13 +293,13 @@ float* presmooth_split(const Run& R, const Depth& D, int nsweeps, float alpha, f
   const int64_t hs = D.nstored / 2;
   {
     Timed tm(R, AMG_T_SWEEP, 0);
-    launch_rbs(D, 2, nullptr, nullptr, fs, a, alpha, beta, omega, 0, R.st);
+    launch_rbs(R.dim, D, 2, nullptr, nullptr, fs, a, alpha, beta, omega, 0, R.st);
   }
   {
     Timed tm(R, AMG_T_SWEEP, 0);
-    launch_rbs(D, 1, a, a + hs, fs + hs, a + hs, alpha, beta, omega, 1, R.st);
+    launch_rbs(R.dim, D, 1, a, a + hs, fs + hs, a + hs, alpha, beta, omega, 1, R.st);
   }
-  return smooth_split(&R, R.st, D, 0, nsweeps - 1, alpha, beta, omega, fs, a, b);
+  return smooth_split(&R, R.st, R.dim, D, 0, nsweeps - 1, alpha, beta, omega, fs, a, b);
 }
 
 // whether a mixed-precision solve runs depth 0 in colour-split storage (its
@@ -338,7 +338,7 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, cons
         {
           // the kernel writes the ghosts it reads itself: no fill launch
           Timed tm(R, AMG_T_RESTRICT, 0);
-          launch_resid_restrict_s(D, L.depths[1], cur[0], fs0, Bufs<T>::f(L.depths[1]), alpha, beta, R.st);
+          launch_resid_restrict_s(R.dim, D, L.depths[1], cur[0], fs0, Bufs<T>::f(L.depths[1]), alpha, beta, R.st);
         }
         remove_mean<T>(R, 1, Bufs<T>::f(L.depths[1]));
         continue;
@@ -378,11 +378,11 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, cons
         // the prolongation writes the corrected iterate into the free buffer
         {
           Timed tm(R, AMG_T_PROLONG, k);
-          launch_prolong_s(D, L.depths[1], cur[1], cur[0], oth[0], R.st);
+          launch_prolong_s(R.dim, D, L.depths[1], cur[1], cur[0], oth[0], R.st);
         }
         T alpha, beta;
         coefs<T>(R.H, D, alpha, beta);
-        return smooth_split(&R, R.st, D, 0, o.nu2, alpha, beta, (float)relax(o), fs0, oth[0], cur[0]);
+        return smooth_split(&R, R.st, R.dim, D, 0, o.nu2, alpha, beta, (float)relax(o), fs0, oth[0], cur[0]);
       }
     }
     {
@@ -1339,7 +1339,7 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
         launch_to32(dim, D0, Rb, D0.f32, L.scal + S_NORM, R.st, L.nsingular ? L.d_delta : nullptr, fs);
       float* e = vcycle<float>(R, o, D0.f32, D0.e32, D0.t32, fs);
       if (split)
-        launch_update_s(D0, X, e, L.scal + S_NORM, R.st);
+        launch_update_s(dim, D0, X, e, L.scal + S_NORM, R.st);
       else
         launch_update<float>(dim, D0, X, e, L.scal + S_NORM, R.st);
     } else {
@@ -1795,7 +1795,7 @@ int amg_time_sweep(amg_hier* H, int level, int dtype, int smoother, int n, void*
         for (int i = 0; i < n; ++i) {
           const int col = i & 1;
           float* dst = (h[col] == cur + col * hs ? oth : cur) + col * hs;
-          launch_rbs(D, 0, h[0], h[1], ff + col * hs, dst, a, b, 1.0f, col, st);
+          launch_rbs(H->dim, D, 0, h[0], h[1], ff + col * hs, dst, a, b, 1.0f, col, st);
           h[col] = dst;
         }
         (void)hipEventRecord(e1, st);

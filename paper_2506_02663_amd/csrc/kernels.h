@@ -108,25 +108,26 @@ void launch_update(int dim, const Depth& D, double* x, const T* e, const double*
 // r32 = (r32 - delta[comp]) / scal[0]
 void launch_residual32(int dim, const Depth& D, const double* u, const double* f, float* r, double alpha, double beta,
                        double* part, hipStream_t st);
-// fs (3D, may be null): the result in colour-split storage instead of r32
+// fs (may be null): the result in colour-split storage instead of r32
 // (two halves of D.nstored / 2 elements, element e of colour c at index
 // e >> 1 of half c)
 void launch_scale32(int dim, const Depth& D, float* r32, const double* scal, hipStream_t st, const double* delta,
                     float* fs = nullptr);
 void launch_to32(int dim, const Depth& D, const double* r, float* r32, const double* scal, hipStream_t st,
                  const double* delta = nullptr, float* fs = nullptr);
-// colour-split storage (3D FP32 depths with split_rb): red-black half-sweep
+// colour-split storage (FP32 depths with split_rb): red-black half-sweep
 // of colour col of the iterate with halves h0, h1 into the half `out` (fc:
 // half col of f; mode 0: plain, 1: half col of the iterate is zero, 2: the
 // iterate is zero); residual fused with restriction from split u and f into
 // the coarse f (interleaved); prolongation out = u + P ec (u, out split);
 // x += scal[0] e with e split
-void launch_rbs(const Depth& D, int mode, const float* h0, const float* h1, const float* fc, float* out,
+void launch_rbs(int dim, const Depth& D, int mode, const float* h0, const float* h1, const float* fc, float* out,
                 float alpha, float beta, float omega, int col, hipStream_t st);
-void launch_resid_restrict_s(const Depth& F, const Depth& C, const float* u, const float* f, float* fc, float alpha,
-                             float beta, hipStream_t st);
-void launch_prolong_s(const Depth& F, const Depth& C, const float* ec, const float* u, float* out, hipStream_t st);
-void launch_update_s(const Depth& D, double* x, const float* e, const double* scal, hipStream_t st);
+void launch_resid_restrict_s(int dim, const Depth& F, const Depth& C, const float* u, const float* f, float* fc,
+                             float alpha, float beta, hipStream_t st);
+void launch_prolong_s(int dim, const Depth& F, const Depth& C, const float* ec, const float* u, float* out,
+                      hipStream_t st);
+void launch_update_s(int dim, const Depth& D, double* x, const float* e, const double* scal, hipStream_t st);
 void launch_shift_copy(int dim, const Depth& D, const double* f, double* out, const double* delta, hipStream_t st);
 void launch_set_scale(const double* src, double* dst, hipStream_t st);
 void launch_set_scaled(const double* src, double f, double* dst, hipStream_t st);

@@ -1010,8 +1010,8 @@ __global__ void __launch_bounds__(256) k_update(const TileD* __restrict__ tiles,
   }
 }
 
-// the pair of cells (x, x + 1) at element c (x even) of a 3D box stored
-// into split halves fs0, fs1
+// the pair of cells (x, x + 1) at element c (x even; (x, y, z) with z = 0 in
+// 2D) stored into split halves fs0, fs1
 __device__ __forceinline__ void split_pair(float* __restrict__ fs0, float* __restrict__ fs1, const BoxD& b, int x,
                                            int y, int z, int64_t c, float a, float a1) {
   const int cx = colour_of(b, x, y, z);
@@ -1019,8 +1019,8 @@ __device__ __forceinline__ void split_pair(float* __restrict__ fs0, float* __res
   (cx ? fs0 : fs1)[c >> 1] = a1;
 }
 
-// r32 = fp32(r / s), s = scal[0]; with fs0, fs1 (3D) the result goes to
-// split storage instead
+// r32 = fp32(r / s), s = scal[0]; with fs0, fs1 the result goes to split
+// storage instead
 template <int DIM>
 __global__ void __launch_bounds__(256) k_to32(const TileD* __restrict__ tiles, int ntiles,
                                               const BoxD* __restrict__ boxes, const double* __restrict__ r,
@@ -1034,8 +1034,8 @@ __global__ void __launch_bounds__(256) k_to32(const TileD* __restrict__ tiles, i
     if (C.ok1) {
       const Pair<double> rv = ld2(r + c);
       const float a = (float)((rv.a - dv) * inv), a1 = (float)((rv.b - dv) * inv);
-      if (DIM == 3 && fs0)
-        split_pair(fs0, fs1, b, C.x, C.y, p, c, a, a1);
+      if (fs0)
+        split_pair(fs0, fs1, b, C.x, DIM == 3 ? C.y : p, DIM == 3 ? p : 0, c, a, a1);
       else
         st2(r32 + c, a, a1);
     } else {
@@ -1046,7 +1046,7 @@ __global__ void __launch_bounds__(256) k_to32(const TileD* __restrict__ tiles, i
 
 // r32 = (r32 - delta[comp]) / scal[0] in place (the FP64 residual stored
 // unscaled in FP32 by the residual kernel; arithmetic in FP64); with fs0,
-// fs1 (3D) the result goes to split storage instead
+// fs1 the result goes to split storage instead
 template <int DIM>
 __global__ void __launch_bounds__(256) k_scale32(const TileD* __restrict__ tiles, int ntiles,
                                                  const BoxD* __restrict__ boxes, float* __restrict__ r32,
@@ -1059,8 +1059,8 @@ __global__ void __launch_bounds__(256) k_scale32(const TileD* __restrict__ tiles
     if (C.ok1) {
       const Pair<float> rv = ld2(r32 + c);
       const float a = (float)(((double)rv.a - dv) * inv), a1 = (float)(((double)rv.b - dv) * inv);
-      if (DIM == 3 && fs0)
-        split_pair(fs0, fs1, b, C.x, C.y, p, c, a, a1);
+      if (fs0)
+        split_pair(fs0, fs1, b, C.x, DIM == 3 ? C.y : p, DIM == 3 ? p : 0, c, a, a1);
       else
         st2(r32 + c, a, a1);
     } else {
@@ -1262,13 +1262,15 @@ __global__ void __launch_bounds__(256) k_prolong(const TileD* __restrict__ tiles
 
 // cell (x, y, z) (ghosts included) of a split array with halves h0, h1;
 // zc: a colour whose interior cells are taken as zero (not read), -1: none
+template <int DIM>
 __device__ __forceinline__ float split_ld(const float* h0, const float* h1, const BoxD& b, int x, int y, int z,
                                           int zc) {
   const int k = colour_of(b, x, y, z);
-  return k == zc ? 0.0f : (k ? h1 : h0)[cell_index<3>(b, x, y, z) >> 1];
+  return k == zc ? 0.0f : (k ? h1 : h0)[cell_index<DIM>(b, x, y, z) >> 1];
 }
+template <int DIM>
 __device__ __forceinline__ void split_st(float* h0, float* h1, const BoxD& b, int x, int y, int z, float v) {
-  (colour_of(b, x, y, z) ? h1 : h0)[cell_index<3>(b, x, y, z) >> 1] = v;
+  (colour_of(b, x, y, z) ? h1 : h0)[cell_index<DIM>(b, x, y, z) >> 1] = v;
 }
 
 // x-face ghost of row (y, z) of box b on side `side` (0 low, 1 high),
@@ -1287,12 +1289,15 @@ __device__ __forceinline__ float* x_ghost(float* xg, const BoxD& b, int side, in
 // last tile of every row, column and march has at least 2 cells).  zc >= 0:
 // the interior cells of colour zc are zero (their half is not read); the
 // ghosts of both colours are written.
+template <int DIM>
 __device__ __forceinline__ void split_ghosts(const TileD& t, const BoxD& b, float* h0, float* h1, float* xg,
                                              int zc) {
-  const int lo[3] = {t.x0, t.y0, t.z0};
-  const int nn[3] = {min(TILE_X, b.n[0] - t.x0), min(TILE3_Y, b.n[1] - t.y0), min(t.len, b.n[2] - t.z0)};
+  // the tile's cells: x, then (3D) its rows and planes, (2D) its rows
+  const int lo[3] = {t.x0, t.y0, DIM == 3 ? t.z0 : 0};
+  const int nn[3] = {min(TILE_X, b.n[0] - t.x0), DIM == 3 ? min(TILE3_Y, b.n[1] - t.y0) : min(t.len, b.n[1] - t.y0),
+                     DIM == 3 ? min(t.len, b.n[2] - t.z0) : 1};
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
+  for (int d = 0; d < DIM; ++d) {
     const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
     for (int side = 0; side < 2; ++side) {
       if (side == 0 ? lo[d] != 0 : lo[d] + nn[d] != b.n[d]) continue;
@@ -1311,7 +1316,7 @@ __device__ __forceinline__ void split_ghosts(const TileD& t, const BoxD& b, floa
         for (int m = 0; m < 4; ++m) {
           int x, y, z;
           at(m, x, y, z);
-          u[m] = split_ld(h0, h1, b, x, y, z, zc);
+          u[m] = split_ld<DIM>(h0, h1, b, x, y, z, zc);
         }
         const float g1 = ghost1<float>(cd, u[0], u[1], u[2], u[3]), g2 = ghost2<float>(cd, u[0], u[1], u[2], u[3]);
         if (d == 0) {
@@ -1320,22 +1325,24 @@ __device__ __forceinline__ void split_ghosts(const TileD& t, const BoxD& b, floa
         } else {
           int x, y, z;
           at(-1, x, y, z);
-          split_st(h0, h1, b, x, y, z, g1);
+          split_st<DIM>(h0, h1, b, x, y, z, g1);
           at(-2, x, y, z);
-          split_st(h0, h1, b, x, y, z, g2);
+          split_st<DIM>(h0, h1, b, x, y, z, g2);
         }
       }
     }
   }
 }
 
-// Sum of the folded diagonal increments of the x and y faces at (x, y),
-// added in the order of DiagColumn (uniformly filled faces).
+// -30 D plus the folded diagonal increments of the faces across the march
+// at (x, y) (3D: x and y faces; 2D: x faces), added in the order of
+// DiagColumn (uniformly filled faces).
+template <int DIM>
 __device__ __forceinline__ float split_sfix(const BoxD& b, int x, int y) {
-  float S = -90.0f;
+  float S = float(-30 * DIM);
   const int q[2] = {x, y};
 #pragma unroll
-  for (int d = 0; d < 2; ++d) {
+  for (int d = 0; d < DIM - 1; ++d) {
     const int lo = q[d], hi = b.n[d] - 1 - q[d];
     if (lo < 2) S += fold<float>(b.ucode[d][0], lo);
     if (hi < 2) S += fold<float>(b.ucode[d][1], hi);
@@ -1344,7 +1351,9 @@ __device__ __forceinline__ float split_sfix(const BoxD& b, int x, int y) {
 }
 
 // true if the tile touches a face of its box (its block writes ghosts)
+template <int DIM>
 __device__ __forceinline__ bool tile_at_face(const TileD& t, const BoxD& b) {
+  if (DIM == 2) return t.x0 == 0 || t.x0 + TILE_X >= b.n[0] || t.y0 == 0 || t.y0 + t.len >= b.n[1];
   return t.x0 == 0 || t.x0 + TILE_X >= b.n[0] || t.y0 == 0 || t.y0 + TILE3_Y >= b.n[1] || t.z0 == 0 ||
          t.z0 + t.len >= b.n[2];
 }
@@ -1356,41 +1365,43 @@ __device__ __forceinline__ bool tile_at_face(const TileD& t, const BoxD& b) {
 // second half-sweep after a first one from zero; only the ghosts of colour
 // col are read from half col, which may be the output half); MODE 2: u is
 // zero (the first half-sweep from zero, out_c = omega f_c / diag; h0, h1
-// unused).  Blocks of
-// 4 wavefronts over the sweep tiles (128 x 4 columns): lane i of wavefront w
-// takes the colour-col cell of row (y0 + w, z) in the i-th aligned pair from
-// x0, whose x alternates between x0 + 2i and x0 + 2i + 1 from plane to
-// plane while its split index moves by one plane stride.  Along z the thread
-// keeps both halves at planes -2..+2 in registers; x and y neighbours are
-// re-read through the caches.
-template <int MODE>
+// unused).  3D: blocks of 4 wavefronts over the sweep tiles (128 x 4
+// columns), lane i of wavefront w taking the colour-col cell of row
+// (y0 + w, z) in the i-th aligned pair from x0; 2D: one wavefront per tile
+// (128 columns, marched along y).  The cell's x alternates between x0 + 2i
+// and x0 + 2i + 1 from plane to plane while its split index moves by one
+// plane stride.  Along the march the thread keeps both halves at planes
+// -2..+2 in registers; x (and y) neighbours are re-read through the caches.
+template <int DIM, int MODE>
 __global__ void __launch_bounds__(256) k_rbs(const TileD* __restrict__ tiles, int ntiles,
                                              const BoxD* __restrict__ boxes, const float* h0, const float* h1,
                                              const float* __restrict__ fc, float* __restrict__ out, float alpha,
                                              float beta, float omega, int col, float* xg) {
+  constexpr int M = DIM - 1;  // march direction
   const int ti = tile_of_block(ntiles);
   if (ti < 0) return;
   const TileD t = tiles[ti];
   const BoxD b = boxes[t.box];
-  if (MODE != 2 && tile_at_face(t, b)) {  // block-uniform
-    split_ghosts(t, b, const_cast<float*>(h0), const_cast<float*>(h1), xg, MODE == 1 ? col : -1);
+  if (MODE != 2 && tile_at_face<DIM>(t, b)) {  // block-uniform
+    split_ghosts<DIM>(t, b, const_cast<float*>(h0), const_cast<float*>(h1), xg, MODE == 1 ? col : -1);
     __syncthreads();
   }
-  const int i = threadIdx.x & 63, y = t.y0 + (int)(threadIdx.x >> 6);
+  // 3D: wavefront w takes row y0 + w of the tile; 2D: one wavefront per tile
+  const int i = threadIdx.x & 63, y = DIM == 3 ? t.y0 + (int)(threadIdx.x >> 6) : 0;
   const int nxh = min(TILE_X, b.n[0] - t.x0) >> 1;
-  if (i >= nxh || y >= b.n[1]) return;
+  if (i >= nxh || (DIM == 3 && y >= b.n[1])) return;
   const float* __restrict__ self = col ? h1 : h0;
   const float* __restrict__ oth = col ? h0 : h1;
-  const int64_t sy = b.s[1] >> 1, sz = b.s[2] >> 1;
-  const int z0 = t.z0, z1 = min(t.z0 + t.len, b.n[2]), nz = b.n[2];
-  // split index of the thread's cell at plane z0 (x = x0 + 2i + parity)
-  int64_t c = (b.off >> 1) + 1 + (t.x0 >> 1) + i + (int64_t)(y + 2) * sy + (int64_t)(z0 + 2) * sz;
+  const int64_t sy = b.s[1] >> 1, sz = b.s[M] >> 1;
+  const int z0 = DIM == 3 ? t.z0 : t.y0, z1 = min(z0 + t.len, b.n[M]), nz = b.n[M];
+  // split index of the thread's cell at march plane z0 (x = x0 + 2i + parity)
+  int64_t c = (b.off >> 1) + 1 + (t.x0 >> 1) + i + (DIM == 3 ? (int64_t)(y + 2) * sy : 0) + (int64_t)(z0 + 2) * sz;
   // x parity of the colour-col cell of the pair: (col + lo + x + y + z) even
   int par = (col + b.lo[0] + b.lo[1] + b.lo[2] + t.x0 + y + z0) & 1;
   const int xa = t.x0 + 2 * i;
-  const float SfA = split_sfix(b, xa, y), SfB = split_sfix(b, xa + 1, y);
+  const float SfA = split_sfix<DIM>(b, xa, y), SfB = split_sfix<DIM>(b, xa + 1, y);
   const float imA = 1.0f / (alpha + beta * SfA), imB = 1.0f / (alpha + beta * SfB);
-  const uint8_t zl = b.ucode[2][0], zh = b.ucode[2][1];
+  const uint8_t zl = b.ucode[M][0], zh = b.ucode[M][1];
   const float flo0 = fold<float>(zl, 0), flo1 = fold<float>(zl, 1);
   const float fhi0 = fold<float>(zh, 0), fhi1 = fold<float>(zh, 1);
   // own colour at plane q / at a neighbour: MODE 1 reads only ghosts
@@ -1401,8 +1412,6 @@ __global__ void __launch_bounds__(256) k_rbs(const TileD* __restrict__ tiles, in
     s1 = own(c - sz, z0 - 1 < 0);
     s2 = own(c, false);
     s3 = own(c + sz, z0 + 1 >= nz);
-  }
-  if (MODE != 2) {
     o0 = oth[c - 2 * sz];
     o1 = oth[c - sz];
     o2 = oth[c];
@@ -1423,20 +1432,24 @@ __global__ void __launch_bounds__(256) k_rbs(const TileD* __restrict__ tiles, in
       continue;
     }
     const int x = xa + par, nx0 = b.n[0];
+    // the row of the side buffer: (y, z) in 3D, (z, 0) in 2D
+    const int gy = DIM == 3 ? y : z, gz = DIM == 3 ? z : 0;
     const float s4 = own(c + 2 * sz, z + 2 >= nz), o4 = oth[c + 2 * sz];
     // x neighbours beyond the box come from the side buffer: one load each,
     // its address chosen per lane
-    const float* a_on = par ? (x + 1 >= nx0 ? x_ghost(xg, b, 1, y, z, 1) : oth + c + 1)
-                            : (x < 1 ? x_ghost(xg, b, 0, y, z, 1) : oth + c - 1);
+    const float* a_on = par ? (x + 1 >= nx0 ? x_ghost(xg, b, 1, gy, gz, 1) : oth + c + 1)
+                            : (x < 1 ? x_ghost(xg, b, 0, gy, gz, 1) : oth + c - 1);
     const float on = *a_on;
     const float xm1 = par ? o2 : on, xp1 = par ? on : o2;
-    const float* a_m2 = x < 2 ? x_ghost(xg, b, 0, y, z, 2 - x) : self + c - 1;
-    const float* a_p2 = x + 2 >= nx0 ? x_ghost(xg, b, 1, y, z, x + 3 - nx0) : self + c + 1;
+    const float* a_m2 = x < 2 ? x_ghost(xg, b, 0, gy, gz, 2 - x) : self + c - 1;
+    const float* a_p2 = x + 2 >= nx0 ? x_ghost(xg, b, 1, gy, gz, x + 3 - nx0) : self + c + 1;
     const float xm2 = (MODE == 0 || x < 2) ? *a_m2 : 0.0f;
     const float xp2 = (MODE == 0 || x + 2 >= nx0) ? *a_p2 : 0.0f;
-    const float ym2 = own(c - 2 * sy, y < 2), yp2 = own(c + 2 * sy, y + 2 >= b.n[1]);
-    float ls = 16.0f * (xm1 + xp1) - (xm2 + xp2) + 16.0f * (o1 + o3) - (s0 + s4) + -90.0f * s2;
-    ls += 16.0f * (oth[c - sy] + oth[c + sy]) - (ym2 + yp2);
+    float ls = 16.0f * (xm1 + xp1) - (xm2 + xp2) + 16.0f * (o1 + o3) - (s0 + s4) + float(-30 * DIM) * s2;
+    if (DIM == 3) {
+      const float ym2 = own(c - 2 * sy, y < 2), yp2 = own(c + 2 * sy, y + 2 >= b.n[1]);
+      ls += 16.0f * (oth[c - sy] + oth[c + sy]) - (ym2 + yp2);
+    }
     const float Au = alpha * s2 + beta * ls;
     out[c] = s2 + omega * (fc[c] - Au) * inv;
     s0 = s1;
@@ -1460,8 +1473,9 @@ __device__ __forceinline__ Pair<float> split_pair_ld(const float* h0, const floa
 // Residual fused with restriction on a split iterate (halves h0, h1) and a
 // split right-hand side (halves f0, f1): the arithmetic of
 // k_march<OP_RESTRICT>, after the block has written the ghosts of its tile
-// into the iterate (read-time fill, as in k_rbs).  Output: the coarse
-// right-hand side, interleaved.
+// (read-time fill, as in k_rbs: y/z faces into the iterate's halves, x faces
+// into the side buffer).  Output: the coarse right-hand side, interleaved.
+template <int DIM>
 __global__ void __launch_bounds__(256) k_resid_restrict_s(const TileD* __restrict__ tiles, int ntiles,
                                                           const BoxD* __restrict__ boxes, const float* h0,
                                                           const float* h1, const float* __restrict__ f0,
@@ -1473,17 +1487,21 @@ __global__ void __launch_bounds__(256) k_resid_restrict_s(const TileD* __restric
   if (ti < 0) return;
   const TileD t = tiles[ti];
   const BoxD b = boxes[t.box];
-  if (tile_at_face(t, b)) {  // block-uniform
-    split_ghosts(t, b, const_cast<float*>(h0), const_cast<float*>(h1), xg, -1);
+  if (tile_at_face<DIM>(t, b)) {  // block-uniform
+    split_ghosts<DIM>(t, b, const_cast<float*>(h0), const_cast<float*>(h1), xg, -1);
     __syncthreads();
   }
-  const Column C = column_of<3>(t, b);
+  const Column C = column_of<DIM>(t, b);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   // lanes up to two cells past the box feed the x-neighbours of the last cells
-  const bool has = C.x < b.n[0] + 2 && C.y < b.n[1];
+  const bool has = C.x < b.n[0] + 2 && (DIM == 2 || C.y < b.n[1]);
   const int64_t sm = C.sm, sy = b.s[1];
   int64_t c = C.base + (int64_t)(C.p0 + 2) * sm;
-  int cx = colour_of(b, C.x, C.y, C.p0);  // colour of cell x at plane p
+  // colour of cell x at plane p; the row of the side buffer at plane p
+  int cx = DIM == 3 ? colour_of(b, C.x, C.y, C.p0) : colour_of(b, C.x, C.p0, 0);
+  auto xgh = [&](int side, int p, int layer) {
+    return *x_ghost(xg, b, side, DIM == 3 ? C.y : p, DIM == 3 ? p : 0, layer);
+  };
   Pair<float> q0{}, q1{}, q2{}, q3{}, q4{};
   if (has) {
     q0 = split_pair_ld(h0, h1, c - 2 * sm, cx);
@@ -1497,15 +1515,15 @@ __global__ void __launch_bounds__(256) k_resid_restrict_s(const TileD* __restric
     // the lane whose pair is the x-high ghost pair feeds its left neighbour
     // from the side buffer
     Pair<float> sq = q2;
-    if (C.x == b.n[0] && C.y < b.n[1]) sq = Pair<float>{*x_ghost(xg, b, 1, C.y, p, 1), *x_ghost(xg, b, 1, C.y, p, 2)};
+    if (C.x == b.n[0] && (DIM == 2 || C.y < b.n[1])) sq = Pair<float>{xgh(1, p, 1), xgh(1, p, 2)};
     float La = __shfl_up(sq.a, 1, 64), Lb = __shfl_up(sq.b, 1, 64);
     float Ra = __shfl_down(sq.a, 1, 64), Rb = __shfl_down(sq.b, 1, 64);
     float o0 = 0.0f, o1 = 0.0f;
     if (C.ok) {
       if (lane == 0) {
         if (C.x == 0) {
-          La = *x_ghost(xg, b, 0, C.y, p, 2);
-          Lb = *x_ghost(xg, b, 0, C.y, p, 1);
+          La = xgh(0, p, 2);
+          Lb = xgh(0, p, 1);
         } else {
           const Pair<float> l = split_pair_ld(h0, h1, c - 2, cx);
           La = l.a;
@@ -1514,20 +1532,22 @@ __global__ void __launch_bounds__(256) k_resid_restrict_s(const TileD* __restric
       }
       if (lane == 63) {
         if (C.x + 2 == b.n[0]) {
-          Ra = *x_ghost(xg, b, 1, C.y, p, 1);
-          Rb = *x_ghost(xg, b, 1, C.y, p, 2);
+          Ra = xgh(1, p, 1);
+          Rb = xgh(1, p, 2);
         } else {
           const Pair<float> r = split_pair_ld(h0, h1, c + 2, cx);
           Ra = r.a;
           Rb = r.b;
         }
       }
-      float s0 = 16.0f * (Lb + q2.b) - (La + Ra) + 16.0f * (q1.a + q3.a) - (q0.a + q4.a) + -90.0f * q2.a;
-      float s1 = 16.0f * (q2.a + Ra) - (Lb + Rb) + 16.0f * (q1.b + q3.b) - (q0.b + q4.b) + -90.0f * q2.b;
-      const Pair<float> ym1 = split_pair_ld(h0, h1, c - sy, cx ^ 1), yp1 = split_pair_ld(h0, h1, c + sy, cx ^ 1),
-                        ym2 = split_pair_ld(h0, h1, c - 2 * sy, cx), yp2 = split_pair_ld(h0, h1, c + 2 * sy, cx);
-      s0 += 16.0f * (ym1.a + yp1.a) - (ym2.a + yp2.a);
-      s1 += 16.0f * (ym1.b + yp1.b) - (ym2.b + yp2.b);
+      float s0 = 16.0f * (Lb + q2.b) - (La + Ra) + 16.0f * (q1.a + q3.a) - (q0.a + q4.a) + float(-30 * DIM) * q2.a;
+      float s1 = 16.0f * (q2.a + Ra) - (Lb + Rb) + 16.0f * (q1.b + q3.b) - (q0.b + q4.b) + float(-30 * DIM) * q2.b;
+      if (DIM == 3) {
+        const Pair<float> ym1 = split_pair_ld(h0, h1, c - sy, cx ^ 1), yp1 = split_pair_ld(h0, h1, c + sy, cx ^ 1),
+                          ym2 = split_pair_ld(h0, h1, c - 2 * sy, cx), yp2 = split_pair_ld(h0, h1, c + 2 * sy, cx);
+        s0 += 16.0f * (ym1.a + yp1.a) - (ym2.a + yp2.a);
+        s1 += 16.0f * (ym1.b + yp1.b) - (ym2.b + yp2.b);
+      }
       const float A0 = alpha * q2.a + beta * s0, A1 = alpha * q2.b + beta * s1;
       const Pair<float> fv = split_pair_ld(f0, f1, c, cx);
       o0 = fv.a - A0;
@@ -1535,13 +1555,18 @@ __global__ void __launch_bounds__(256) k_resid_restrict_s(const TileD* __restric
     }
     acc += o0 + o1;  // x pair (fine sizes are even, so both cells exist)
     if ((p - C.p0) & 1) {
-      if (w & 1) R[w >> 1][lane] = acc;
-      __syncthreads();
-      if (!(w & 1) && C.ok) {
+      if (DIM == 3) {
+        if (w & 1) R[w >> 1][lane] = acc;
+        __syncthreads();
+        if (!(w & 1) && C.ok) {
+          const BoxD cb = cboxes[b.coarse];
+          out[cell_index<3>(cb, C.x >> 1, C.y >> 1, p >> 1)] = (acc + R[w >> 1][lane]) * 0.125f;
+        }
+        __syncthreads();
+      } else if (C.ok) {
         const BoxD cb = cboxes[b.coarse];
-        out[cell_index<3>(cb, C.x >> 1, C.y >> 1, p >> 1)] = (acc + R[w >> 1][lane]) * 0.125f;
+        out[cell_index<2>(cb, C.x >> 1, p >> 1, 0)] = acc * 0.25f;
       }
-      __syncthreads();
       acc = 0.0f;
     }
     q0 = q1;
@@ -1553,18 +1578,20 @@ __global__ void __launch_bounds__(256) k_resid_restrict_s(const TileD* __restric
 
 // Prolongation in split storage: out = u + P ec (the arithmetic of
 // k_prolong), u and out split (halves u0, u1 and o0, o1)
+template <int DIM>
 __global__ void __launch_bounds__(256) k_prolong_s(const TileD* __restrict__ tiles, int ntiles,
                                                    const BoxD* __restrict__ boxes, const BoxD* __restrict__ cboxes,
                                                    const float* __restrict__ ec, const float* __restrict__ u0,
                                                    const float* __restrict__ u1, float* __restrict__ o0,
                                                    float* __restrict__ o1) {
-  FOR_COLUMN(3) {
+  FOR_COLUMN(DIM) {
+    const int cy = DIM == 2 ? p : C.y, cz = DIM == 2 ? 0 : p;
     const BoxD cb = cboxes[b.coarse];
-    const int64_t q = cell_index<3>(cb, C.x >> 1, C.y >> 1, p >> 1);
-    float common = 0.25f * ec[q] + 0.25f * ec[q + ((C.y & 1) ? cb.s[1] : -cb.s[1])];
-    common += 0.25f * ec[q + ((p & 1) ? cb.s[2] : -cb.s[2])];
+    const int64_t q = cell_index<DIM>(cb, C.x >> 1, cy >> 1, cz >> 1);
+    float common = float(1.0 - DIM * 0.25) * ec[q] + 0.25f * ec[q + ((cy & 1) ? cb.s[1] : -cb.s[1])];
+    if (DIM == 3) common += 0.25f * ec[q + ((cz & 1) ? cb.s[2] : -cb.s[2])];
     const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
-    const int cx = colour_of(b, C.x, C.y, p);
+    const int cx = colour_of(b, C.x, cy, cz);
     const Pair<float> uv = split_pair_ld(u0, u1, c, cx);
     (cx ? o1 : o0)[c >> 1] = uv.a + (common + 0.25f * ec[q - 1]);
     (cx ? o0 : o1)[c >> 1] = uv.b + (common + 0.25f * ec[q + 1]);
@@ -1572,14 +1599,15 @@ __global__ void __launch_bounds__(256) k_prolong_s(const TileD* __restrict__ til
 }
 
 // x += s e with e in split storage (halves e0, e1), s = scal[0]
+template <int DIM>
 __global__ void __launch_bounds__(256) k_update_s(const TileD* __restrict__ tiles, int ntiles,
                                                   const BoxD* __restrict__ boxes, double* __restrict__ x,
                                                   const float* __restrict__ e0, const float* __restrict__ e1,
                                                   const double* __restrict__ scal) {
   const double s = scal[0];
-  FOR_COLUMN(3) {
+  FOR_COLUMN(DIM) {
     const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
-    const int cx = colour_of(b, C.x, C.y, p);
+    const int cx = DIM == 3 ? colour_of(b, C.x, C.y, p) : colour_of(b, C.x, p, 0);
     const float ea = (cx ? e1 : e0)[c >> 1], eb = (cx ? e0 : e1)[c >> 1];
     const Pair<double> xv = ld2(x + c);
     st2(x + c, xv.a + s * (double)ea, xv.b + s * (double)eb);
@@ -2742,43 +2770,66 @@ void launch_scale32(int dim, const Depth& D, float* r32, const double* scal, hip
   DISPATCH_DIM(dim, k_scale32, D.d_tiles, (int)n, D.d_box, r32, scal, delta, fs, fs1);
 }
 
-void launch_rbs(const Depth& D, int mode, const float* h0, const float* h1, const float* fc, float* out,
-                float alpha, float beta, float omega, int col, hipStream_t st) {
+template <int DIM>
+void launch_rbs_d(const Depth& D, int mode, const float* h0, const float* h1, const float* fc, float* out,
+                  float alpha, float beta, float omega, int col, hipStream_t st) {
   const size_t n = D.stiles.size();
-  if (!n) return;
+  const dim3 bs(DIM == 3 ? 256 : 64);
   if (mode == 0)
-    hipLaunchKernelGGL(k_rbs<0>, grid8(n), dim3(256), 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
+    hipLaunchKernelGGL((k_rbs<DIM, 0>), grid8(n), bs, 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
                        beta, omega, col, D.xg32);
   else if (mode == 1)
-    hipLaunchKernelGGL(k_rbs<1>, grid8(n), dim3(256), 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
+    hipLaunchKernelGGL((k_rbs<DIM, 1>), grid8(n), bs, 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
                        beta, omega, col, D.xg32);
   else
-    hipLaunchKernelGGL(k_rbs<2>, grid8(n), dim3(256), 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
+    hipLaunchKernelGGL((k_rbs<DIM, 2>), grid8(n), bs, 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
                        beta, omega, col, D.xg32);
 }
 
-void launch_resid_restrict_s(const Depth& F, const Depth& C, const float* u, const float* f, float* fc, float alpha,
-                             float beta, hipStream_t st) {
+void launch_rbs(int dim, const Depth& D, int mode, const float* h0, const float* h1, const float* fc, float* out,
+                float alpha, float beta, float omega, int col, hipStream_t st) {
+  if (D.stiles.empty()) return;
+  if (dim == 2)
+    launch_rbs_d<2>(D, mode, h0, h1, fc, out, alpha, beta, omega, col, st);
+  else
+    launch_rbs_d<3>(D, mode, h0, h1, fc, out, alpha, beta, omega, col, st);
+}
+
+void launch_resid_restrict_s(int dim, const Depth& F, const Depth& C, const float* u, const float* f, float* fc,
+                             float alpha, float beta, hipStream_t st) {
   const size_t n = F.stiles.size();
   if (!n) return;
   const int64_t hs = F.nstored / 2;
-  hipLaunchKernelGGL(k_resid_restrict_s, grid8(n), threads<3>(), 0, st, F.d_stiles, (int)n, F.d_box, u, u + hs, f,
-                     f + hs, fc, alpha, beta, C.d_box, F.xg32);
+  if (dim == 2)
+    hipLaunchKernelGGL(k_resid_restrict_s<2>, grid8(n), threads<2>(), 0, st, F.d_stiles, (int)n, F.d_box, u, u + hs,
+                       f, f + hs, fc, alpha, beta, C.d_box, F.xg32);
+  else
+    hipLaunchKernelGGL(k_resid_restrict_s<3>, grid8(n), threads<3>(), 0, st, F.d_stiles, (int)n, F.d_box, u, u + hs,
+                       f, f + hs, fc, alpha, beta, C.d_box, F.xg32);
 }
 
-void launch_prolong_s(const Depth& F, const Depth& C, const float* ec, const float* u, float* out, hipStream_t st) {
+void launch_prolong_s(int dim, const Depth& F, const Depth& C, const float* ec, const float* u, float* out,
+                      hipStream_t st) {
   const size_t n = F.stiles.size();
   if (!n) return;
   const int64_t hs = F.nstored / 2;
-  hipLaunchKernelGGL(k_prolong_s, grid8(n), threads<3>(), 0, st, F.d_stiles, (int)n, F.d_box, C.d_box, ec, u,
-                     u + hs, out, out + hs);
+  if (dim == 2)
+    hipLaunchKernelGGL(k_prolong_s<2>, grid8(n), threads<2>(), 0, st, F.d_stiles, (int)n, F.d_box, C.d_box, ec, u,
+                       u + hs, out, out + hs);
+  else
+    hipLaunchKernelGGL(k_prolong_s<3>, grid8(n), threads<3>(), 0, st, F.d_stiles, (int)n, F.d_box, C.d_box, ec, u,
+                       u + hs, out, out + hs);
 }
 
-void launch_update_s(const Depth& D, double* x, const float* e, const double* scal, hipStream_t st) {
+void launch_update_s(int dim, const Depth& D, double* x, const float* e, const double* scal, hipStream_t st) {
   const size_t n = D.tiles.size();
   if (!n) return;
-  hipLaunchKernelGGL(k_update_s, grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, x, e,
-                     e + D.nstored / 2, scal);
+  if (dim == 2)
+    hipLaunchKernelGGL(k_update_s<2>, grid8(n), threads<2>(), 0, st, D.d_tiles, (int)n, D.d_box, x, e,
+                       e + D.nstored / 2, scal);
+  else
+    hipLaunchKernelGGL(k_update_s<3>, grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, x, e,
+                       e + D.nstored / 2, scal);
 }
 
 void launch_residual32(int dim, const Depth& D, const double* u, const double* f, float* r, double alpha, double beta,

@@ -527,23 +527,23 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       for (int d = 0; d < dim; ++d)
         for (int s = 0; s < 2; ++s)
           if (X.ucode[d][s] != 5 && X.ucode[d][s] != 6) D.uniform_fill = false;
-    // colour-split storage (depth 0, 3D): every face filled uniformly with
+    // colour-split storage (depth 0): every face filled uniformly with
     // both layers from its own row (the sweep computes all ghosts it reads),
     // even offsets, row lengths and plane sizes (each aligned pair of
     // elements holds one cell of each colour) and rows of an even number of
     // cells (a tile's columns pair up)
     // no box solved exactly at this depth (the bottom solve writes interleaved)
-    bool split_ok = H->split_rb && k == 0 && dim == 3 && D.fill_only && !D.stiles.empty() &&
-                    D.bottom_boxes.empty() && (D.nstored % 2) == 0;
+    bool split_ok = H->split_rb && k == 0 && D.fill_only && !D.stiles.empty() && D.bottom_boxes.empty() &&
+                    (D.nstored % 2) == 0;
     for (const BoxD& X : D.boxd) {
-      for (int d = 0; d < 3; ++d)
+      for (int d = 0; d < dim; ++d)
         for (int s = 0; s < 2; ++s)
           if (X.ucode[d][s] != 5 && X.ucode[d][s] != 6) split_ok = false;
       // even sizes (true of every box that is smoothed, since it coarsens)
       // with an even march give every last tile of a row, column or march at
       // least 2 cells, so no tile's stencil reaches a ghost another tile writes
       if ((X.off % 2) != 0 || (X.s[1] % 2) != 0 || (X.s[2] % 2) != 0 || (X.n[0] % 2) != 0 || (X.n[1] % 2) != 0 ||
-          (X.n[2] % 2) != 0)
+          (dim == 3 && (X.n[2] % 2) != 0))
         split_ok = false;
     }
     D.split_rb = split_ok;

@@ -30,11 +30,12 @@ MIXED3 = {(0, 0): "D", (0, 1): "N", (1, 0): "N", (1, 1): "D", (2, 0): "D", (2, 1
 
 def build(shape, boxes, bc, split, isolated=False, op="helmholtz", c=None):
     n = max(shape)
-    H = A.Hierarchy(3, shape, 1.0 / n, 1)
+    dim = len(shape)
+    H = A.Hierarchy(dim, shape, 1.0 / n, 1)
     if isolated:
         H.set_isolated(0)
     H.set_level_boxes(0, boxes)
-    for d in range(3):
+    for d in range(dim):
         for s in (0, 1):
             kind = bc[(d, s)] if isinstance(bc, dict) else bc
             H.set_physical_bc(d, s, A.DIRICHLET if kind == "D" else A.NEUMANN)
@@ -53,6 +54,13 @@ CASES = {
     "wide_130x8x8": ((130, 8, 8), [((0, 0, 0), (129, 7, 7))], "N", False),  # last x-tile 2 wide
     "rows_264x16x16": ((264, 16, 16), [((0, 0, 0), (263, 15, 15))], MIXED3, False),
     "isolated": ((64, 64, 64), [((0, 0, 0), (15, 15, 15)), ((32, 0, 0), (55, 23, 31))], "N", True),
+    # 2D: one wavefront per tile, marched along y
+    "sq2d_64_D": ((64, 64), [((0, 0), (63, 63))], "D", False),
+    "rect2d_96x64_N": ((96, 64), [((0, 0), (95, 63))], "N", False),
+    "mixed2d_136x40": ((136, 40), [((0, 0), (135, 39))], MIXED3, False),
+    "wide2d_130x16": ((130, 16), [((0, 0), (129, 15))], "D", False),  # last x-tile 2 wide
+    "iso2d": ((512, 64), [((0, 0), (15, 23)), ((32, 0), (63, 31)), ((96, 0), (231, 47)), ((256, 0), (511, 63))],
+              "D", True),
 }
 
 
@@ -74,12 +82,7 @@ def test_split_layout_bits(name):
     assert build(shape, boxes, bc, False, iso).level_info(0).split_rb == 0
 
 
-def test_split_not_taken_in_2d_or_on_interpolated_faces():
-    H = A.Hierarchy(2, (64, 64), 1.0 / 64, 1)
-    H.set_level_boxes(0, [((0, 0), (63, 63))])
-    H.set_operator(A.POISSON, 0.0)
-    H.finalize()
-    assert H.level_info(0).split_rb == 0
+def test_split_not_taken_on_interpolated_faces():
     # a refined patch: its faces inside the domain are coarse-fine faces,
     # filled from their own rows in the Dirichlet and Neumann modes (like
     # physical faces) and interpolated from the coarse level in the other
