@@ -516,6 +516,15 @@ def bench_batched(args):
     if args.no_split:
         H.set_tuning(A.TUNE_SPLIT_RB, 0)
     t0 = time.perf_counter()
+    if args.march:
+        march = args.march
+    elif not args.no_autotune:
+        # tile march length of the finest sweep, timed on copies of the layout
+        march, _ = H.autotune(0, A.F32 if prec == A.MIXED else A.F64, sm)
+    else:
+        march = None
+    if march:
+        H.set_tuning(A.TUNE_MARCH2, march)
     H.finalize()
     setup_s = time.perf_counter() - t0
     split_on = bool(H.level_info(0).split_rb) and args.precision == "mixed" and args.smoother == "rb"
@@ -546,7 +555,8 @@ def bench_batched(args):
         "dtype": "f32-in-f64" if prec == A.MIXED else "f64", "data": "synthetic",
         "config": {"workload": "batch of 1024 independent 2D boxes, sides 8m, m~U{2..32}, Dirichlet Helmholtz",
                    "cells": ncell, "tol_rel": 1e-10, "cycles": info["cycles"], "smoother": args.smoother,
-                   "precision": args.precision, "vcycle": "V(2,2)", "setup_s": setup_s, "split_storage": split_on},
+                   "precision": args.precision, "vcycle": "V(2,2)", "setup_s": setup_s, "march": march,
+                   "split_storage": split_on},
     }
     if not args.no_timing:
         # the finest sweep over all 1024 boxes, 50 launches back to back
