@@ -213,11 +213,12 @@ int amg_set_operator(amg_hier* h, int kind, double c);
 #define AMG_TUNE_FUSED_RB 3
 /* AMG_TUNE_SPLIT_RB: 1 (default) lets the mixed-precision solve keep the
  * finest depth's correction and right-hand side in colour-split storage
- * during the red-black post-smoothing (each colour in its own half array, so
- * a half-sweep moves only the cells it reads and writes), on 3D depths
- * whose faces are all filled uniformly with both ghost layers from their own
- * rows and whose boxes have an even number of cells along x; 0 keeps the
- * interleaved storage.  The two forms give the same results. */
+ * (each colour in its own half array, so a red-black half-sweep moves only
+ * the cells it reads and writes), in 2D and 3D, on depths whose faces are
+ * all filled uniformly with both ghost layers from their own rows, whose
+ * boxes have even sizes and where no box is solved exactly; 0 keeps the
+ * interleaved storage.  The two forms give the same results (to the
+ * rounding of FP32 sums). */
 #define AMG_TUNE_SPLIT_RB 4
 int amg_set_tuning(amg_hier* h, int key, int value);
 
