@@ -261,6 +261,7 @@ struct Level {
   int32_t* d_comp_flag = nullptr;  // 1 on singular components
   double* d_comp_cnt = nullptr;    // cells per component at each depth [depth*ncomp + c]
   double* d_delta = nullptr;       // per-component shift
+  double* d_delta0 = nullptr;      // per-component mean of the outer residual (kept through the V-cycle)
   double* d_bsum = nullptr;        // per-component sum of Neumann face data
   double* d_defect = nullptr;      // per-component solvability defect
   double* d_comp_ncf = nullptr;    // comp_ncf on the device

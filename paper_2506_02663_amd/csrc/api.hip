@@ -260,9 +260,11 @@ inline double relax(const amg_solve_opts& o) { return o.smoother == AMG_SMOOTH_R
 // nsweeps red-black sweeps of a depth in colour-split storage: the iterate
 // starts in buffer a (both halves), b is the second buffer; each half-sweep
 // writes its colour's half into the buffer that does not hold it.  Returns
-// the buffer that holds the final iterate (both halves).
+// the buffer that holds the final iterate (both halves).  fsc (may be null):
+// fs holds the unscaled residual, read as (fs - fdl[comp]) / fsc[0].
 float* smooth_split(const Run* R, hipStream_t st, int dim, const Depth& D, int k, int nsweeps, float alpha,
-                    float beta, float omega, const float* fs, float* a, float* b) {
+                    float beta, float omega, const float* fs, float* a, float* b, const double* fsc = nullptr,
+                    const double* fdl = nullptr) {
   const int64_t hs = D.nstored / 2;
   const float* h[2] = {a, a + hs};
   for (int s = 0; s < nsweeps; ++s)
@@ -270,9 +272,9 @@ float* smooth_split(const Run* R, hipStream_t st, int dim, const Depth& D, int k
       float* dst = (h[col] == a + col * hs ? b : a) + col * hs;
       if (R) {
         Timed tm(*R, AMG_T_SWEEP_SPLIT, k);
-        launch_rbs(dim, D, 0, h[0], h[1], fs + col * hs, dst, alpha, beta, omega, col, st);
+        launch_rbs(dim, D, 0, h[0], h[1], fs + col * hs, dst, alpha, beta, omega, col, st, fsc, fdl);
       } else {
-        launch_rbs(dim, D, 0, h[0], h[1], fs + col * hs, dst, alpha, beta, omega, col, st);
+        launch_rbs(dim, D, 0, h[0], h[1], fs + col * hs, dst, alpha, beta, omega, col, st, fsc, fdl);
       }
       h[col] = dst;
     }
@@ -285,7 +287,7 @@ float* smooth_split(const Run* R, hipStream_t st, int dim, const Depth& D, int k
 // the red half (its own colour is still zero) and writes the black half of
 // the same buffer.  Returns the buffer that holds the iterate.
 float* presmooth_split(const Run& R, const Depth& D, int nsweeps, float alpha, float beta, float omega,
-                       const float* fs, float* a, float* b) {
+                       const float* fs, float* a, float* b, const double* fsc, const double* fdl) {
   if (nsweeps <= 0) {
     launch_zero<float>(a, D.nstored, R.st);
     return a;
@@ -293,13 +295,13 @@ float* presmooth_split(const Run& R, const Depth& D, int nsweeps, float alpha, f
   const int64_t hs = D.nstored / 2;
   {
     Timed tm(R, AMG_T_SWEEP, 0);
-    launch_rbs(R.dim, D, 2, nullptr, nullptr, fs, a, alpha, beta, omega, 0, R.st);
+    launch_rbs(R.dim, D, 2, nullptr, nullptr, fs, a, alpha, beta, omega, 0, R.st, fsc, fdl);
   }
   {
     Timed tm(R, AMG_T_SWEEP, 0);
-    launch_rbs(R.dim, D, 1, a, a + hs, fs + hs, a + hs, alpha, beta, omega, 1, R.st);
+    launch_rbs(R.dim, D, 1, a, a + hs, fs + hs, a + hs, alpha, beta, omega, 1, R.st, fsc, fdl);
   }
-  return smooth_split(&R, R.st, R.dim, D, 0, nsweeps - 1, alpha, beta, omega, fs, a, b);
+  return smooth_split(&R, R.st, R.dim, D, 0, nsweeps - 1, alpha, beta, omega, fs, a, b, fsc, fdl);
 }
 
 // whether a mixed-precision solve runs depth 0 in colour-split storage (its
@@ -312,9 +314,11 @@ inline bool use_split(const amg_hier* H, const Depth& D0, const amg_solve_opts& 
 // and t0 the two depth-0 buffers.  Returns the buffer that holds e.  With
 // fs0 (FP32: the depth-0 right-hand side in colour-split storage, depth 0
 // with split_rb; f0 is then not read) every depth-0 step runs in split
-// storage and the returned e is split.
+// storage and the returned e is split; with fsc0 fs0 holds the unscaled
+// residual, which the split kernels read as (fs0 - fdl0[comp]) / fsc0[0].
 template <typename T>
-T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, const float* fs0 = nullptr) {
+T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, const float* fs0 = nullptr,
+          const double* fsc0 = nullptr, const double* fdl0 = nullptr) {
   Level& L = *R.L;
   const int K = (int)L.depths.size();
   std::vector<T*> cur(K), oth(K);
@@ -333,12 +337,13 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, cons
       if (k == 0 && fs0) {
         T alpha, beta;
         coefs<T>(R.H, D, alpha, beta);
-        float* s = presmooth_split(R, D, o.nu1, alpha, beta, (float)relax(o), fs0, cur[0], oth[0]);
+        float* s = presmooth_split(R, D, o.nu1, alpha, beta, (float)relax(o), fs0, cur[0], oth[0], fsc0, fdl0);
         if (s != cur[0]) std::swap(cur[0], oth[0]);
         {
           // the kernel writes the ghosts it reads itself: no fill launch
           Timed tm(R, AMG_T_RESTRICT, 0);
-          launch_resid_restrict_s(R.dim, D, L.depths[1], cur[0], fs0, Bufs<T>::f(L.depths[1]), alpha, beta, R.st);
+          launch_resid_restrict_s(R.dim, D, L.depths[1], cur[0], fs0, Bufs<T>::f(L.depths[1]), alpha, beta, R.st,
+                                  fsc0, fdl0);
         }
         remove_mean<T>(R, 1, Bufs<T>::f(L.depths[1]));
         continue;
@@ -382,7 +387,8 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, cons
         }
         T alpha, beta;
         coefs<T>(R.H, D, alpha, beta);
-        return smooth_split(&R, R.st, R.dim, D, 0, o.nu2, alpha, beta, (float)relax(o), fs0, oth[0], cur[0]);
+        return smooth_split(&R, R.st, R.dim, D, 0, o.nu2, alpha, beta, (float)relax(o), fs0, oth[0], cur[0], fsc0,
+                            fdl0);
       }
     }
     {
@@ -417,7 +423,7 @@ void free_level(amg::Level& L) {
       if (p) (void)hipFree(p);
   }
   for (void* p : {(void*)L.d_mat, (void*)L.d_idx, (void*)L.r64, (void*)L.fsh, (void*)L.partial, (void*)L.partial2, (void*)L.comp_sum,
-                  (void*)L.scal, (void*)L.d_comp_flag, (void*)L.d_comp_cnt, (void*)L.d_delta, (void*)L.d_bsum,
+                  (void*)L.scal, (void*)L.d_comp_flag, (void*)L.d_comp_cnt, (void*)L.d_delta, (void*)L.d_delta0, (void*)L.d_bsum,
                   (void*)L.d_defect, (void*)L.d_dfd, (void*)L.fdc, (void*)L.d_comp_ncf})
     if (p) (void)hipFree(p);
   if (L.h_scal) (void)hipHostFree(L.h_scal);
@@ -825,6 +831,7 @@ int amg_finalize(amg_hier* H) {
     TRY(zalloc(H, &L.partial2, maxseg));
     TRY(zalloc(H, &L.comp_sum, L.ncomp));
     TRY(zalloc(H, &L.d_delta, L.ncomp));
+    TRY(zalloc(H, &L.d_delta0, L.ncomp));
     TRY(zalloc(H, &L.d_bsum, L.ncomp));
     TRY(zalloc(H, &L.d_defect, L.ncomp));
     TRY(zalloc(H, &L.d_dfd, L.ncomp));
@@ -1281,7 +1288,7 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
       launch_fill<double>(D0, X, FD, R.st);
       Timed tm(R, AMG_T_RESIDUAL, 0);
       if (direct32)
-        launch_residual32(dim, D0, X, frhs, D0.f32, alpha, beta, L.partial, R.st);
+        launch_residual32(dim, D0, X, frhs, split ? D0.fs32 : D0.f32, alpha, beta, L.partial, R.st, split);
       else
         launch_residual<double>(dim, D0, true, X, frhs, Rb, alpha, beta, L.partial, R.st);
     }
@@ -1318,10 +1325,10 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
     if (tr) {
       launch_tile_sum<double>(dim, D0, Rb, L.partial, R.st);
       comp_sums(R, D0, L.comp_sum);
-      launch_comp_delta(L.comp_sum, nullptr, L.d_comp_flag, L.d_comp_cnt, L.ncomp, 1.0, 0.0, L.d_delta, nullptr,
+      launch_comp_delta(L.comp_sum, nullptr, L.d_comp_flag, L.d_comp_cnt, L.ncomp, 1.0, 0.0, L.d_delta0, nullptr,
                         R.st);
     } else {
-      launch_comp_mean_delta(D0, L.partial + D0.tiles.size(), L.d_comp_flag, L.d_comp_cnt, L.ncomp, L.d_delta, R.st);
+      launch_comp_mean_delta(D0, L.partial + D0.tiles.size(), L.d_comp_flag, L.d_comp_cnt, L.ncomp, L.d_delta0, R.st);
     }
   };
   // The solution's mean on singular components does not change the
@@ -1331,19 +1338,27 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
     if (L.nsingular) residual_mean();
     if (mixed) {
       // the mean removal fused into the FP32 conversion
-      // with depth 0 in split storage the conversion writes f split
+      // with depth 0 in split storage the residual kernel has stored r split
+      // and the split kernels scale it as they read it (no conversion pass);
+      // from the FP64 residual the conversion writes f split, scaled
       float* fs = split ? D0.fs32 : nullptr;
-      if (direct32)
-        launch_scale32(dim, D0, D0.f32, L.scal + S_NORM, R.st, L.nsingular ? L.d_delta : nullptr, fs);
-      else
-        launch_to32(dim, D0, Rb, D0.f32, L.scal + S_NORM, R.st, L.nsingular ? L.d_delta : nullptr, fs);
-      float* e = vcycle<float>(R, o, D0.f32, D0.e32, D0.t32, fs);
+      const double* fsc = nullptr;
+      const double* fdl = nullptr;
+      if (direct32 && split) {
+        fsc = L.scal + S_NORM;
+        fdl = L.nsingular ? L.d_delta0 : nullptr;
+      } else if (direct32) {
+        launch_scale32(dim, D0, D0.f32, L.scal + S_NORM, R.st, L.nsingular ? L.d_delta0 : nullptr);
+      } else {
+        launch_to32(dim, D0, Rb, D0.f32, L.scal + S_NORM, R.st, L.nsingular ? L.d_delta0 : nullptr, fs);
+      }
+      float* e = vcycle<float>(R, o, D0.f32, D0.e32, D0.t32, fs, fsc, fdl);
       if (split)
         launch_update_s(dim, D0, X, e, L.scal + S_NORM, R.st);
       else
         launch_update<float>(dim, D0, X, e, L.scal + S_NORM, R.st);
     } else {
-      if (L.nsingular) launch_comp_shift<double>(dim, D0, Rb, L.d_delta, R.st);
+      if (L.nsingular) launch_comp_shift<double>(dim, D0, Rb, L.d_delta0, R.st);
       double* e = vcycle<double>(R, o, D0.f64, D0.e64, D0.t64);
       launch_update<double>(dim, D0, X, e, L.scal + S_ONE, R.st);
     }

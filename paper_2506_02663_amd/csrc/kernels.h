@@ -106,8 +106,9 @@ void launch_update(int dim, const Depth& D, double* x, const T* e, const double*
 // the FP64 residual of all tiles stored unscaled in FP32 (r = f - A u, with
 // the per-tile max and sum partials), and its in-place conversion
 // r32 = (r32 - delta[comp]) / scal[0]
+// split: r in colour-split storage (halves D.nstored / 2 apart)
 void launch_residual32(int dim, const Depth& D, const double* u, const double* f, float* r, double alpha, double beta,
-                       double* part, hipStream_t st);
+                       double* part, hipStream_t st, bool split = false);
 // fs (may be null): the result in colour-split storage instead of r32
 // (two halves of D.nstored / 2 elements, element e of colour c at index
 // e >> 1 of half c)
@@ -120,11 +121,14 @@ void launch_to32(int dim, const Depth& D, const double* r, float* r32, const dou
 // half col of f; mode 0: plain, 1: half col of the iterate is zero, 2: the
 // iterate is zero); residual fused with restriction from split u and f into
 // the coarse f (interleaved); prolongation out = u + P ec (u, out split);
-// x += scal[0] e with e split
+// x += scal[0] e with e split.  scal (may be null): f is the unscaled
+// residual, read as (f - delta[comp]) / scal[0] (delta may be null)
 void launch_rbs(int dim, const Depth& D, int mode, const float* h0, const float* h1, const float* fc, float* out,
-                float alpha, float beta, float omega, int col, hipStream_t st);
+                float alpha, float beta, float omega, int col, hipStream_t st, const double* scal = nullptr,
+                const double* delta = nullptr);
 void launch_resid_restrict_s(int dim, const Depth& F, const Depth& C, const float* u, const float* f, float* fc,
-                             float alpha, float beta, hipStream_t st);
+                             float alpha, float beta, hipStream_t st, const double* scal = nullptr,
+                             const double* delta = nullptr);
 void launch_prolong_s(int dim, const Depth& F, const Depth& C, const float* ec, const float* u, float* out,
                       hipStream_t st);
 void launch_update_s(int dim, const Depth& D, double* x, const float* e, const double* scal, hipStream_t st);

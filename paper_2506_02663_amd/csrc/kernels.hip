@@ -825,7 +825,7 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
                                                const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
                                                const T* __restrict__ u, const T* __restrict__ f, TO* __restrict__ out,
                                                T alpha, T beta, T omega, int col, double* __restrict__ part,
-                                               const BoxD* __restrict__ cboxes, int gr) {
+                                               const BoxD* __restrict__ cboxes, int gr, int64_t shalf) {
   __shared__ double sh[4];
   __shared__ T R[2][64];
   const int ti = tile_of_block(ntiles);
@@ -909,10 +909,15 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
         o1 = u1 ? q2.b + wgt * (fv.b - A1) * d1.inv(b, codes, p, C.x + 1, cy, cz) : q2.b;
       }
       if (OP != OP_RESTRICT) {
-        if (C.ok1)
+        if (OP == OP_RESID && shalf) {  // colour-split output, halves shalf apart
+          const int cxo = DIM == 3 ? colour_of(b, C.x, C.y, p) : colour_of(b, C.x, p, 0);
+          out[(cxo ? shalf : 0) + (c >> 1)] = (TO)o0;
+          out[(cxo ? 0 : shalf) + (c >> 1)] = (TO)o1;
+        } else if (C.ok1) {
           st2<TO>(out + c, (TO)o0, (TO)o1);
-        else
+        } else {
           out[c] = (TO)o0;
+        }
       }
     }
     if (OP == OP_RESTRICT) {
@@ -1376,7 +1381,8 @@ template <int DIM, int MODE>
 __global__ void __launch_bounds__(256) k_rbs(const TileD* __restrict__ tiles, int ntiles,
                                              const BoxD* __restrict__ boxes, const float* h0, const float* h1,
                                              const float* __restrict__ fc, float* __restrict__ out, float alpha,
-                                             float beta, float omega, int col, float* xg) {
+                                             float beta, float omega, int col, float* xg,
+                                             const double* __restrict__ scal, const double* __restrict__ delta) {
   constexpr int M = DIM - 1;  // march direction
   const int ti = tile_of_block(ntiles);
   if (ti < 0) return;
@@ -1406,6 +1412,10 @@ __global__ void __launch_bounds__(256) k_rbs(const TileD* __restrict__ tiles, in
   const float fhi0 = fold<float>(zh, 0), fhi1 = fold<float>(zh, 1);
   // own colour at plane q / at a neighbour: MODE 1 reads only ghosts
   auto own = [&](int64_t j, bool ghost) { return (MODE == 0 || (MODE == 1 && ghost)) ? self[j] : 0.0f; };
+  // scal != null: fc holds the unscaled residual; f = (r - delta) / scal[0],
+  // evaluated in FP64 as the conversion kernel (k_scale32) would
+  const double finv = scal ? 1.0 / scal[0] : 1.0, fdv = (scal && delta) ? delta[b.comp] : 0.0;
+  auto fval = [&](int64_t j) { return scal ? (float)(((double)fc[j] - fdv) * finv) : fc[j]; };
   float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f, o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
   if (MODE != 2) {
     s0 = own(c - 2 * sz, z0 - 2 < 0);
@@ -1428,7 +1438,7 @@ __global__ void __launch_bounds__(256) k_rbs(const TileD* __restrict__ tiles, in
       inv = 1.0f / (alpha + beta * S);
     }
     if (MODE == 2) {
-      out[c] = omega * fc[c] * inv;
+      out[c] = omega * fval(c) * inv;
       continue;
     }
     const int x = xa + par, nx0 = b.n[0];
@@ -1451,7 +1461,7 @@ __global__ void __launch_bounds__(256) k_rbs(const TileD* __restrict__ tiles, in
       ls += 16.0f * (oth[c - sy] + oth[c + sy]) - (ym2 + yp2);
     }
     const float Au = alpha * s2 + beta * ls;
-    out[c] = s2 + omega * (fc[c] - Au) * inv;
+    out[c] = s2 + omega * (fval(c) - Au) * inv;
     s0 = s1;
     s1 = s2;
     s2 = s3;
@@ -1481,7 +1491,9 @@ __global__ void __launch_bounds__(256) k_resid_restrict_s(const TileD* __restric
                                                           const float* h1, const float* __restrict__ f0,
                                                           const float* __restrict__ f1, float* __restrict__ out,
                                                           float alpha, float beta,
-                                                          const BoxD* __restrict__ cboxes, float* xg) {
+                                                          const BoxD* __restrict__ cboxes, float* xg,
+                                                          const double* __restrict__ scal,
+                                                          const double* __restrict__ delta) {
   __shared__ float R[2][64];
   const int ti = tile_of_block(ntiles);
   if (ti < 0) return;
@@ -1549,7 +1561,11 @@ __global__ void __launch_bounds__(256) k_resid_restrict_s(const TileD* __restric
         s1 += 16.0f * (ym1.b + yp1.b) - (ym2.b + yp2.b);
       }
       const float A0 = alpha * q2.a + beta * s0, A1 = alpha * q2.b + beta * s1;
-      const Pair<float> fv = split_pair_ld(f0, f1, c, cx);
+      Pair<float> fv = split_pair_ld(f0, f1, c, cx);
+      if (scal) {  // unscaled residual: f = (r - delta) / scal[0] in FP64, as k_scale32
+        const double inv = 1.0 / scal[0], dv = delta ? delta[b.comp] : 0.0;
+        fv = Pair<float>{(float)(((double)fv.a - dv) * inv), (float)(((double)fv.b - dv) * inv)};
+      }
       o0 = fv.a - A0;
       o1 = fv.b - A1;
     }
@@ -2418,7 +2434,7 @@ struct MarchK {
                          D.d_box, D.d_codes, u, f, out, a, b, w, col, part, gr);
     else
       hipLaunchKernelGGL((k_march<T, DIM, OP, PART>), grid8(n), threads<DIM>(), 0, st, tl, (int)n, D.d_box, D.d_codes,
-                         u, f, out, a, b, w, col, part, cboxes, gr);
+                         u, f, out, a, b, w, col, part, cboxes, gr, (int64_t)0);
   }
 };
 
@@ -2772,40 +2788,42 @@ void launch_scale32(int dim, const Depth& D, float* r32, const double* scal, hip
 
 template <int DIM>
 void launch_rbs_d(const Depth& D, int mode, const float* h0, const float* h1, const float* fc, float* out,
-                  float alpha, float beta, float omega, int col, hipStream_t st) {
+                  float alpha, float beta, float omega, int col, hipStream_t st, const double* scal,
+                  const double* delta) {
   const size_t n = D.stiles.size();
   const dim3 bs(DIM == 3 ? 256 : 64);
   if (mode == 0)
     hipLaunchKernelGGL((k_rbs<DIM, 0>), grid8(n), bs, 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
-                       beta, omega, col, D.xg32);
+                       beta, omega, col, D.xg32, scal, delta);
   else if (mode == 1)
     hipLaunchKernelGGL((k_rbs<DIM, 1>), grid8(n), bs, 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
-                       beta, omega, col, D.xg32);
+                       beta, omega, col, D.xg32, scal, delta);
   else
     hipLaunchKernelGGL((k_rbs<DIM, 2>), grid8(n), bs, 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
-                       beta, omega, col, D.xg32);
+                       beta, omega, col, D.xg32, scal, delta);
 }
 
 void launch_rbs(int dim, const Depth& D, int mode, const float* h0, const float* h1, const float* fc, float* out,
-                float alpha, float beta, float omega, int col, hipStream_t st) {
+                float alpha, float beta, float omega, int col, hipStream_t st, const double* scal,
+                const double* delta) {
   if (D.stiles.empty()) return;
   if (dim == 2)
-    launch_rbs_d<2>(D, mode, h0, h1, fc, out, alpha, beta, omega, col, st);
+    launch_rbs_d<2>(D, mode, h0, h1, fc, out, alpha, beta, omega, col, st, scal, delta);
   else
-    launch_rbs_d<3>(D, mode, h0, h1, fc, out, alpha, beta, omega, col, st);
+    launch_rbs_d<3>(D, mode, h0, h1, fc, out, alpha, beta, omega, col, st, scal, delta);
 }
 
 void launch_resid_restrict_s(int dim, const Depth& F, const Depth& C, const float* u, const float* f, float* fc,
-                             float alpha, float beta, hipStream_t st) {
+                             float alpha, float beta, hipStream_t st, const double* scal, const double* delta) {
   const size_t n = F.stiles.size();
   if (!n) return;
   const int64_t hs = F.nstored / 2;
   if (dim == 2)
     hipLaunchKernelGGL(k_resid_restrict_s<2>, grid8(n), threads<2>(), 0, st, F.d_stiles, (int)n, F.d_box, u, u + hs,
-                       f, f + hs, fc, alpha, beta, C.d_box, F.xg32);
+                       f, f + hs, fc, alpha, beta, C.d_box, F.xg32, scal, delta);
   else
     hipLaunchKernelGGL(k_resid_restrict_s<3>, grid8(n), threads<3>(), 0, st, F.d_stiles, (int)n, F.d_box, u, u + hs,
-                       f, f + hs, fc, alpha, beta, C.d_box, F.xg32);
+                       f, f + hs, fc, alpha, beta, C.d_box, F.xg32, scal, delta);
 }
 
 void launch_prolong_s(int dim, const Depth& F, const Depth& C, const float* ec, const float* u, float* out,
@@ -2833,15 +2851,16 @@ void launch_update_s(int dim, const Depth& D, double* x, const float* e, const d
 }
 
 void launch_residual32(int dim, const Depth& D, const double* u, const double* f, float* r, double alpha, double beta,
-                       double* part, hipStream_t st) {
+                       double* part, hipStream_t st, bool split) {
   const size_t n = D.tiles.size();
   if (!n) return;
+  const int64_t sh = split ? D.nstored / 2 : 0;
   if (dim == 2)
     hipLaunchKernelGGL((k_march<double, 2, OP_RESID, true, float>), grid8(n), threads<2>(), 0, st, D.d_tiles, (int)n,
-                       D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr, 0);
+                       D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr, 0, sh);
   else
     hipLaunchKernelGGL((k_march<double, 3, OP_RESID, true, float>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n,
-                       D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr, 0);
+                       D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr, 0, sh);
 }
 
 void launch_shift_copy(int dim, const Depth& D, const double* f, double* out, const double* delta, hipStream_t st) {
