@@ -215,8 +215,10 @@ def test_time_sweep_on_split_depth():
 def test_split_poisson_keeps_outer_mean_shift(shape):
     """A right-hand side with a large mean: the split kernels subtract the
     outer residual's per-component mean as they read it, through the whole
-    V-cycle (the coarse depths' own mean removals must not replace it), so
-    the split solve equals the interleaved one to rounding."""
+    V-cycle (the coarse depths' own mean removals must not replace it).  The
+    two storages evaluate the same expressions in the same order, so the
+    solves agree bitwise (the shift of a coarse depth in its place changed
+    the solution by a few 1e-12)."""
     box = [((0,) * len(shape), tuple(n - 1 for n in shape))]
     res = []
     for split in (True, False):
@@ -229,4 +231,4 @@ def test_split_poisson_keeps_outer_mean_shift(shape):
         assert st["converged"], st
         res.append((st["cycles"], H.unpack(0, 0, x.cpu().numpy())[0]))
     assert res[0][0] == res[1][0]
-    assert np.abs(res[0][1] - res[1][1]).max() <= 1e-12 * np.abs(res[1][1]).max()
+    assert np.array_equal(res[0][1], res[1][1]), np.abs(res[0][1] - res[1][1]).max() / np.abs(res[1][1]).max()
