@@ -261,15 +261,27 @@ inline double relax(const amg_solve_opts& o) { return o.smoother == AMG_SMOOTH_R
 // starts in buffer a (both halves), b is the second buffer; each half-sweep
 // writes its colour's half into the buffer that does not hold it.  Returns
 // the buffer that holds the final iterate (both halves).  fsc (may be null):
-// fs holds the unscaled residual, read as (fs - fdl[comp]) / fsc[0].
+// fs holds the unscaled residual, read as (fs - fdl[comp]) / fsc[0].  xu
+// (may be null): the last half-sweep adds su[0] times the final iterate to
+// the FP64 array xu instead of storing it (the outer update fused into it),
+// and the function returns null.
 float* smooth_split(const Run* R, hipStream_t st, int dim, const Depth& D, int k, int nsweeps, float alpha,
                     float beta, float omega, const float* fs, float* a, float* b, const double* fsc = nullptr,
-                    const double* fdl = nullptr) {
+                    const double* fdl = nullptr, double* xu = nullptr, const double* su = nullptr) {
   const int64_t hs = D.nstored / 2;
   const float* h[2] = {a, a + hs};
   for (int s = 0; s < nsweeps; ++s)
     for (int col = 0; col < 2; ++col) {
       float* dst = (h[col] == a + col * hs ? b : a) + col * hs;
+      if (xu && s == nsweeps - 1 && col == 1) {
+        if (R) {
+          Timed tm(*R, AMG_T_SWEEP, k);
+          launch_rbs(dim, D, 3, h[0], h[1], fs + col * hs, dst, alpha, beta, omega, col, st, fsc, fdl, xu, su);
+        } else {
+          launch_rbs(dim, D, 3, h[0], h[1], fs + col * hs, dst, alpha, beta, omega, col, st, fsc, fdl, xu, su);
+        }
+        return nullptr;
+      }
       if (R) {
         Timed tm(*R, AMG_T_SWEEP_SPLIT, k);
         launch_rbs(dim, D, 0, h[0], h[1], fs + col * hs, dst, alpha, beta, omega, col, st, fsc, fdl);
@@ -315,10 +327,13 @@ inline bool use_split(const amg_hier* H, const Depth& D0, const amg_solve_opts& 
 // fs0 (FP32: the depth-0 right-hand side in colour-split storage, depth 0
 // with split_rb; f0 is then not read) every depth-0 step runs in split
 // storage and the returned e is split; with fsc0 fs0 holds the unscaled
-// residual, which the split kernels read as (fs0 - fdl0[comp]) / fsc0[0].
+// residual, which the split kernels read as (fs0 - fdl0[comp]) / fsc0[0];
+// with xu (split only) the last half-sweep adds su[0] e to xu itself and
+// the function returns null.
 template <typename T>
 T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, const float* fs0 = nullptr,
-          const double* fsc0 = nullptr, const double* fdl0 = nullptr) {
+          const double* fsc0 = nullptr, const double* fdl0 = nullptr, double* xu = nullptr,
+          const double* su = nullptr) {
   Level& L = *R.L;
   const int K = (int)L.depths.size();
   std::vector<T*> cur(K), oth(K);
@@ -388,7 +403,7 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, cons
         T alpha, beta;
         coefs<T>(R.H, D, alpha, beta);
         return smooth_split(&R, R.st, R.dim, D, 0, o.nu2, alpha, beta, (float)relax(o), fs0, oth[0], cur[0], fsc0,
-                            fdl0);
+                            fdl0, xu, su);
       }
     }
     {
@@ -1352,11 +1367,10 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
       } else {
         launch_to32(dim, D0, Rb, D0.f32, L.scal + S_NORM, R.st, L.nsingular ? L.d_delta0 : nullptr, fs);
       }
-      float* e = vcycle<float>(R, o, D0.f32, D0.e32, D0.t32, fs, fsc, fdl);
-      if (split)
-        launch_update_s(dim, D0, X, e, L.scal + S_NORM, R.st);
-      else
-        launch_update<float>(dim, D0, X, e, L.scal + S_NORM, R.st);
+      // in split storage the V-cycle's last half-sweep applies x += s e
+      float* e = vcycle<float>(R, o, D0.f32, D0.e32, D0.t32, fs, fsc, fdl, split ? X : nullptr,
+                               split ? L.scal + S_NORM : nullptr);
+      if (e) launch_update<float>(dim, D0, X, e, L.scal + S_NORM, R.st);
     } else {
       if (L.nsingular) launch_comp_shift<double>(dim, D0, Rb, L.d_delta0, R.st);
       double* e = vcycle<double>(R, o, D0.f64, D0.e64, D0.t64);

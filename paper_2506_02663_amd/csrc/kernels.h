@@ -120,18 +120,19 @@ void launch_to32(int dim, const Depth& D, const double* r, float* r32, const dou
 // of colour col of the iterate with halves h0, h1 into the half `out` (fc:
 // half col of f; mode 0: plain, 1: half col of the iterate is zero, 2: the
 // iterate is zero); residual fused with restriction from split u and f into
-// the coarse f (interleaved); prolongation out = u + P ec (u, out split);
-// x += scal[0] e with e split.  scal (may be null): f is the unscaled
-// residual, read as (f - delta[comp]) / scal[0] (delta may be null)
+// the coarse f (interleaved); prolongation out = u + P ec (u, out split).  scal (may be null): f is the unscaled
+// residual, read as (f - delta[comp]) / scal[0] (delta may be null).  Mode 3
+// of the half-sweep: mode 0 with xu += su[0] * (the pair of the new value and
+// the other colour) instead of writing `out` (the last half-sweep fused with
+// the outer update; xu FP64 in the depth's interleaved layout).
 void launch_rbs(int dim, const Depth& D, int mode, const float* h0, const float* h1, const float* fc, float* out,
                 float alpha, float beta, float omega, int col, hipStream_t st, const double* scal = nullptr,
-                const double* delta = nullptr);
+                const double* delta = nullptr, double* xu = nullptr, const double* su = nullptr);
 void launch_resid_restrict_s(int dim, const Depth& F, const Depth& C, const float* u, const float* f, float* fc,
                              float alpha, float beta, hipStream_t st, const double* scal = nullptr,
                              const double* delta = nullptr);
 void launch_prolong_s(int dim, const Depth& F, const Depth& C, const float* ec, const float* u, float* out,
                       hipStream_t st);
-void launch_update_s(int dim, const Depth& D, double* x, const float* e, const double* scal, hipStream_t st);
 void launch_shift_copy(int dim, const Depth& D, const double* f, double* out, const double* delta, hipStream_t st);
 void launch_set_scale(const double* src, double* dst, hipStream_t st);
 void launch_set_scaled(const double* src, double f, double* dst, hipStream_t st);

@@ -1370,7 +1370,10 @@ __device__ __forceinline__ bool tile_at_face(const TileD& t, const BoxD& b) {
 // second half-sweep after a first one from zero; only the ghosts of colour
 // col are read from half col, which may be the output half); MODE 2: u is
 // zero (the first half-sweep from zero, out_c = omega f_c / diag; h0, h1
-// unused).  3D: blocks of 4 wavefronts over the sweep tiles (128 x 4
+// unused); MODE 3: as MODE 0, but instead of writing half col the kernel
+// adds su[0] times both cells of every aligned pair (its own new value and
+// the other colour's, which it reads anyway) to the FP64 array xu of the
+// same layout: the last half-sweep of a V-cycle fused with the outer update.  3D: blocks of 4 wavefronts over the sweep tiles (128 x 4
 // columns), lane i of wavefront w taking the colour-col cell of row
 // (y0 + w, z) in the i-th aligned pair from x0; 2D: one wavefront per tile
 // (128 columns, marched along y).  The cell's x alternates between x0 + 2i
@@ -1382,7 +1385,8 @@ __global__ void __launch_bounds__(256) k_rbs(const TileD* __restrict__ tiles, in
                                              const BoxD* __restrict__ boxes, const float* h0, const float* h1,
                                              const float* __restrict__ fc, float* __restrict__ out, float alpha,
                                              float beta, float omega, int col, float* xg,
-                                             const double* __restrict__ scal, const double* __restrict__ delta) {
+                                             const double* __restrict__ scal, const double* __restrict__ delta,
+                                             double* __restrict__ xu, const double* __restrict__ su) {
   constexpr int M = DIM - 1;  // march direction
   const int ti = tile_of_block(ntiles);
   if (ti < 0) return;
@@ -1411,11 +1415,13 @@ __global__ void __launch_bounds__(256) k_rbs(const TileD* __restrict__ tiles, in
   const float flo0 = fold<float>(zl, 0), flo1 = fold<float>(zl, 1);
   const float fhi0 = fold<float>(zh, 0), fhi1 = fold<float>(zh, 1);
   // own colour at plane q / at a neighbour: MODE 1 reads only ghosts
-  auto own = [&](int64_t j, bool ghost) { return (MODE == 0 || (MODE == 1 && ghost)) ? self[j] : 0.0f; };
+  constexpr bool FULL = MODE == 0 || MODE == 3;  // reads both halves in full
+  auto own = [&](int64_t j, bool ghost) { return (FULL || (MODE == 1 && ghost)) ? self[j] : 0.0f; };
   // scal != null: fc holds the unscaled residual; f = (r - delta) / scal[0],
   // evaluated in FP64 as the conversion kernel (k_scale32) would
   const double finv = scal ? 1.0 / scal[0] : 1.0, fdv = (scal && delta) ? delta[b.comp] : 0.0;
   auto fval = [&](int64_t j) { return scal ? (float)(((double)fc[j] - fdv) * finv) : fc[j]; };
+  const double ssc = MODE == 3 ? su[0] : 0.0;
   float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f, o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
   if (MODE != 2) {
     s0 = own(c - 2 * sz, z0 - 2 < 0);
@@ -1453,15 +1459,25 @@ __global__ void __launch_bounds__(256) k_rbs(const TileD* __restrict__ tiles, in
     const float xm1 = par ? o2 : on, xp1 = par ? on : o2;
     const float* a_m2 = x < 2 ? x_ghost(xg, b, 0, gy, gz, 2 - x) : self + c - 1;
     const float* a_p2 = x + 2 >= nx0 ? x_ghost(xg, b, 1, gy, gz, x + 3 - nx0) : self + c + 1;
-    const float xm2 = (MODE == 0 || x < 2) ? *a_m2 : 0.0f;
-    const float xp2 = (MODE == 0 || x + 2 >= nx0) ? *a_p2 : 0.0f;
+    const float xm2 = (FULL || x < 2) ? *a_m2 : 0.0f;
+    const float xp2 = (FULL || x + 2 >= nx0) ? *a_p2 : 0.0f;
     float ls = 16.0f * (xm1 + xp1) - (xm2 + xp2) + 16.0f * (o1 + o3) - (s0 + s4) + float(-30 * DIM) * s2;
     if (DIM == 3) {
       const float ym2 = own(c - 2 * sy, y < 2), yp2 = own(c + 2 * sy, y + 2 >= b.n[1]);
       ls += 16.0f * (oth[c - sy] + oth[c + sy]) - (ym2 + yp2);
     }
     const float Au = alpha * s2 + beta * ls;
-    out[c] = s2 + omega * (fval(c) - Au) * inv;
+    const float v = s2 + omega * (fval(c) - Au) * inv;
+    if (MODE == 3) {
+      // the pair (elements 2c, 2c + 1) holds this cell and the other
+      // colour's final value o2: x += s e for both, as k_update
+      double* xp = xu + 2 * c;
+      const Pair<double> xv = ld2(xp);
+      const float ea = par ? o2 : v, eb = par ? v : o2;
+      st2(xp, xv.a + ssc * (double)ea, xv.b + ssc * (double)eb);
+    } else {
+      out[c] = v;
+    }
     s0 = s1;
     s1 = s2;
     s2 = s3;
@@ -1611,22 +1627,6 @@ __global__ void __launch_bounds__(256) k_prolong_s(const TileD* __restrict__ til
     const Pair<float> uv = split_pair_ld(u0, u1, c, cx);
     (cx ? o1 : o0)[c >> 1] = uv.a + (common + 0.25f * ec[q - 1]);
     (cx ? o0 : o1)[c >> 1] = uv.b + (common + 0.25f * ec[q + 1]);
-  }
-}
-
-// x += s e with e in split storage (halves e0, e1), s = scal[0]
-template <int DIM>
-__global__ void __launch_bounds__(256) k_update_s(const TileD* __restrict__ tiles, int ntiles,
-                                                  const BoxD* __restrict__ boxes, double* __restrict__ x,
-                                                  const float* __restrict__ e0, const float* __restrict__ e1,
-                                                  const double* __restrict__ scal) {
-  const double s = scal[0];
-  FOR_COLUMN(DIM) {
-    const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
-    const int cx = DIM == 3 ? colour_of(b, C.x, C.y, p) : colour_of(b, C.x, p, 0);
-    const float ea = (cx ? e1 : e0)[c >> 1], eb = (cx ? e0 : e1)[c >> 1];
-    const Pair<double> xv = ld2(x + c);
-    st2(x + c, xv.a + s * (double)ea, xv.b + s * (double)eb);
   }
 }
 
@@ -2789,28 +2789,31 @@ void launch_scale32(int dim, const Depth& D, float* r32, const double* scal, hip
 template <int DIM>
 void launch_rbs_d(const Depth& D, int mode, const float* h0, const float* h1, const float* fc, float* out,
                   float alpha, float beta, float omega, int col, hipStream_t st, const double* scal,
-                  const double* delta) {
+                  const double* delta, double* xu, const double* su) {
   const size_t n = D.stiles.size();
   const dim3 bs(DIM == 3 ? 256 : 64);
+#define RBS_LAUNCH(MD)                                                                                         \
+  hipLaunchKernelGGL((k_rbs<DIM, MD>), grid8(n), bs, 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha, \
+                     beta, omega, col, D.xg32, scal, delta, xu, su)
   if (mode == 0)
-    hipLaunchKernelGGL((k_rbs<DIM, 0>), grid8(n), bs, 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
-                       beta, omega, col, D.xg32, scal, delta);
+    RBS_LAUNCH(0);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_rbs<DIM, 1>), grid8(n), bs, 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
-                       beta, omega, col, D.xg32, scal, delta);
+    RBS_LAUNCH(1);
+  else if (mode == 2)
+    RBS_LAUNCH(2);
   else
-    hipLaunchKernelGGL((k_rbs<DIM, 2>), grid8(n), bs, 0, st, D.d_stiles, (int)n, D.d_box, h0, h1, fc, out, alpha,
-                       beta, omega, col, D.xg32, scal, delta);
+    RBS_LAUNCH(3);
+#undef RBS_LAUNCH
 }
 
 void launch_rbs(int dim, const Depth& D, int mode, const float* h0, const float* h1, const float* fc, float* out,
                 float alpha, float beta, float omega, int col, hipStream_t st, const double* scal,
-                const double* delta) {
+                const double* delta, double* xu, const double* su) {
   if (D.stiles.empty()) return;
   if (dim == 2)
-    launch_rbs_d<2>(D, mode, h0, h1, fc, out, alpha, beta, omega, col, st, scal, delta);
+    launch_rbs_d<2>(D, mode, h0, h1, fc, out, alpha, beta, omega, col, st, scal, delta, xu, su);
   else
-    launch_rbs_d<3>(D, mode, h0, h1, fc, out, alpha, beta, omega, col, st, scal, delta);
+    launch_rbs_d<3>(D, mode, h0, h1, fc, out, alpha, beta, omega, col, st, scal, delta, xu, su);
 }
 
 void launch_resid_restrict_s(int dim, const Depth& F, const Depth& C, const float* u, const float* f, float* fc,
@@ -2837,17 +2840,6 @@ void launch_prolong_s(int dim, const Depth& F, const Depth& C, const float* ec, 
   else
     hipLaunchKernelGGL(k_prolong_s<3>, grid8(n), threads<3>(), 0, st, F.d_stiles, (int)n, F.d_box, C.d_box, ec, u,
                        u + hs, out, out + hs);
-}
-
-void launch_update_s(int dim, const Depth& D, double* x, const float* e, const double* scal, hipStream_t st) {
-  const size_t n = D.tiles.size();
-  if (!n) return;
-  if (dim == 2)
-    hipLaunchKernelGGL(k_update_s<2>, grid8(n), threads<2>(), 0, st, D.d_tiles, (int)n, D.d_box, x, e,
-                       e + D.nstored / 2, scal);
-  else
-    hipLaunchKernelGGL(k_update_s<3>, grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, x, e,
-                       e + D.nstored / 2, scal);
 }
 
 void launch_residual32(int dim, const Depth& D, const double* u, const double* f, float* r, double alpha, double beta,
