@@ -1300,10 +1300,13 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
       launch_band<double>(dim, D0, 0, X, Rb, alpha, beta, -beta, 0, R.st);
       launch_tile_absmax<double>(dim, D0, Rb, L.partial, R.st);
     } else {
-      launch_fill<double>(D0, X, FD, R.st);
+      // without face data on uniformly filled faces the residual kernel
+      // writes the (homogeneous) ghosts of x it reads itself
+      const int rgr = (direct32 && !FD && D0.uniform_fill) ? 1 : 0;
+      if (!rgr) launch_fill<double>(D0, X, FD, R.st);
       Timed tm(R, AMG_T_RESIDUAL, 0);
       if (direct32)
-        launch_residual32(dim, D0, X, frhs, split ? D0.fs32 : D0.f32, alpha, beta, L.partial, R.st, split);
+        launch_residual32(dim, D0, X, frhs, split ? D0.fs32 : D0.f32, alpha, beta, L.partial, R.st, split, rgr);
       else
         launch_residual<double>(dim, D0, true, X, frhs, Rb, alpha, beta, L.partial, R.st);
     }

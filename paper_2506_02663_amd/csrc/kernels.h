@@ -106,9 +106,11 @@ void launch_update(int dim, const Depth& D, double* x, const T* e, const double*
 // the FP64 residual of all tiles stored unscaled in FP32 (r = f - A u, with
 // the per-tile max and sum partials), and its in-place conversion
 // r32 = (r32 - delta[comp]) / scal[0]
-// split: r in colour-split storage (halves D.nstored / 2 apart)
+// split: r in colour-split storage (halves D.nstored / 2 apart); gr != 0
+// (D.uniform_fill, homogeneous conditions): the kernel writes the ghosts of
+// u it reads itself, so no fill launch is needed before it
 void launch_residual32(int dim, const Depth& D, const double* u, const double* f, float* r, double alpha, double beta,
-                       double* part, hipStream_t st, bool split = false);
+                       double* part, hipStream_t st, bool split = false, int gr = 0);
 // fs (may be null): the result in colour-split storage instead of r32
 // (two halves of D.nstored / 2 elements, element e of colour c at index
 // e >> 1 of half c)

@@ -2843,16 +2843,16 @@ void launch_prolong_s(int dim, const Depth& F, const Depth& C, const float* ec, 
 }
 
 void launch_residual32(int dim, const Depth& D, const double* u, const double* f, float* r, double alpha, double beta,
-                       double* part, hipStream_t st, bool split) {
+                       double* part, hipStream_t st, bool split, int gr) {
   const size_t n = D.tiles.size();
   if (!n) return;
   const int64_t sh = split ? D.nstored / 2 : 0;
   if (dim == 2)
     hipLaunchKernelGGL((k_march<double, 2, OP_RESID, true, float>), grid8(n), threads<2>(), 0, st, D.d_tiles, (int)n,
-                       D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr, 0, sh);
+                       D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr, gr, sh);
   else
     hipLaunchKernelGGL((k_march<double, 3, OP_RESID, true, float>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n,
-                       D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr, 0, sh);
+                       D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr, gr, sh);
 }
 
 void launch_shift_copy(int dim, const Depth& D, const double* f, double* out, const double* delta, hipStream_t st) {
