@@ -1252,18 +1252,19 @@ __global__ void __launch_bounds__(256) k_prolong(const TileD* __restrict__ tiles
 }
 
 // ---------------------------------------------------------------------------
-// Colour-split storage (3D, FP32).  An array of a depth is kept as two halves
-// of nstored / 2 elements: element e (of the interleaved layout) of colour c,
-// c = (lo + x + y + z) mod 2, lives at index e >> 1 of half c.  Box offsets,
-// row lengths and plane sizes are even and every row starts on an even
-// element, so the two cells of each aligned pair (e even, e + 1) have
-// different colours and share the index e >> 1, and a cell's neighbours at
-// distance 1 along y or z (the other colour) and at distance 2 (its own
-// colour) keep its index shifted by half the stride.  A red-black half-sweep
-// of colour c then streams half c (the cell and its same-colour neighbours),
-// the other half (its neighbours at distance 1) and half c of f, and writes
-// only half c: two words per cell of the depth instead of the three of the
-// interleaved out-of-place form, whose cache lines carry both colours.
+// Colour-split storage (FP32, 2D and 3D).  An array of a depth is kept as
+// two halves of nstored / 2 elements: element e (of the interleaved layout)
+// of colour c, c = (lo + x + y + z) mod 2, lives at index e >> 1 of half c.
+// Box offsets, row lengths and plane sizes are even and every row starts on
+// an even element, so the two cells of each aligned pair (e even, e + 1)
+// have different colours and share the index e >> 1, and a cell's
+// neighbours at distance 1 along y or z (the other colour) and at distance 2
+// (its own colour) keep its index shifted by half the stride.  A red-black
+// half-sweep of colour c then streams half c (the cell and its same-colour
+// neighbours), the other half (its neighbours at distance 1) and half c of
+// f, and writes only half c: two words per cell of the depth instead of the
+// three of the interleaved out-of-place form, whose cache lines carry both
+// colours.
 
 // cell (x, y, z) (ghosts included) of a split array with halves h0, h1;
 // zc: a colour whose interior cells are taken as zero (not read), -1: none
