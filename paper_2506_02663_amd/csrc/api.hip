@@ -1445,10 +1445,12 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
   }
   if (H->timer.on) collect_timing(H->timer);
   remove_mean<double>(R, 0, X);
-  if (tr) {  // the adjoint solution as a gradient: zero outside the cells
+  if (tr)  // the adjoint solution as a gradient: zero outside the cells
     launch_fill_zero<double>(D0, X, R.st);
-    HIPCHK(hipGetLastError());
-  }
+  else  // the residual kernels need not leave every ghost of x written, and
+        // the mean shift moves the cells: ghosts of the returned solution
+    launch_fill<double>(D0, X, FD, R.st);
+  HIPCHK(hipGetLastError());
   if (rn > target) return fail(H, AMG_ENOTCONVERGED, "max_cycles reached");
   return AMG_OK;
 }

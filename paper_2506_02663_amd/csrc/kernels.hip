@@ -305,9 +305,9 @@ __device__ __forceinline__ T ghost2(uint8_t cd, T u0, T u1, T u2, T u3) {
 // block that writes it.
 template <typename T, int DIM>
 __device__ __forceinline__ void face_ghosts(const BoxD& b, T* __restrict__ u, int x0, int nx, int y0, int ny, int p0,
-                                            int len) {
+                                            int len, bool xfaces = true) {
   // x faces: one thread per (row, side)
-  for (int side = 0; side < 2; ++side) {
+  for (int side = 0; side < 2 && xfaces; ++side) {
     const uint8_t cd = b.ucode[0][side];
     if (cd == 0xFF || !(cd & 3)) continue;
     if (side == 0 ? x0 != 0 : x0 + nx != b.n[0]) continue;
@@ -362,12 +362,12 @@ __device__ __forceinline__ void march_ghosts(const TileD& t, const BoxD& b, cons
   }
 }
 
-// the same for the cells of one column tile
+// the same for the cells of one column tile (xfaces false: y faces only)
 template <typename T, int DIM>
-__device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __restrict__ u) {
+__device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __restrict__ u, bool xfaces = true) {
   const int p0 = DIM == 2 ? t.y0 : t.z0;
   face_ghosts<T, DIM>(b, u, t.x0, min(TILE_X, b.n[0] - t.x0), DIM == 3 ? t.y0 : 0,
-                      DIM == 3 ? min(TILE3_Y, b.n[1] - t.y0) : 1, p0, min(t.len, b.n[DIM - 1] - p0));
+                      DIM == 3 ? min(TILE3_Y, b.n[1] - t.y0) : 1, p0, min(t.len, b.n[DIM - 1] - p0), xfaces);
 }
 
 // OP_RESID : out = f - A u (f == NULL: out = A u); PART: per-tile max |out|
@@ -832,18 +832,25 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
   if (ti < 0) return;
   const TileD t = tiles[ti];
   const BoxD b = boxes[t.box];
-  // gr != 0 (every face filled uniformly from its own rows, both layers): a
-  // block whose tile touches a face writes the ghosts its cells read there
-  // first, so no fill launch is needed before the kernel
+  // gr != 0 (every face filled uniformly from its own rows, both layers):
+  // no fill launch is needed before the kernel.  A block whose tile touches
+  // a y face or an end of the march writes the ghosts its cells read there
+  // first; the x-face ghosts are formed in registers by the lanes next to
+  // the x faces from the cells the lanes exchange (below), except at the
+  // high x face of a row of odd length (its last lane holds one cell), which
+  // the block writes too.
+  const bool xodd = gr && (b.n[0] & 1) && t.x0 + TILE_X >= b.n[0];
   if (gr) {
     const int p0 = DIM == 2 ? t.y0 : t.z0, nm = b.n[DIM - 1];
-    if (t.x0 == 0 || t.x0 + TILE_X >= b.n[0] || (DIM == 3 && (t.y0 == 0 || t.y0 + TILE3_Y >= b.n[1])) || p0 == 0 ||
-        p0 + t.len >= nm) {  // block-uniform
-      tile_ghosts<T, DIM>(t, b, const_cast<T*>(u));
+    if (xodd || (DIM == 3 && (t.y0 == 0 || t.y0 + TILE3_Y >= b.n[1])) || p0 == 0 || p0 + t.len >= nm) {
+      tile_ghosts<T, DIM>(t, b, const_cast<T*>(u), xodd);  // block-uniform branch
       march_ghosts<T, DIM>(t, b, codes, const_cast<T*>(u));
       __syncthreads();
     }
   }
+  // lanes whose pair ends at an x face (gr only)
+  const bool gxlo = gr && t.x0 == 0, gxhi = gr && !(b.n[0] & 1);
+  const uint8_t cxl = b.ucode[0][0], cxh = b.ucode[0][1];
   const Column C = column_of<DIM>(t, b);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   // lanes up to two cells past the box feed the x-neighbours of the last cells
@@ -871,13 +878,23 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
     T Ra = __shfl_down(q2.a, 1, 64), Rb = __shfl_down(q2.b, 1, 64);
     T o0 = T(0), o1 = T(0);
     if (C.ok) {
-      if (lane == 0) {
+      const bool xlo = gxlo && C.x == 0, xhi = gxhi && C.x + 2 == b.n[0];
+      if (lane == 0 && !xlo) {
         La = u[c - 2];
         Lb = u[c - 1];
       }
-      if (lane == 63) {
+      if (lane == 63 && !xhi) {
         Ra = u[c + 2];
         Rb = u[c + 3];
+      }
+      if (xlo) {  // cells -2, -1 from cells 0..3 (the next lane's pair)
+        La = ghost2<T>(cxl, q2.a, q2.b, Ra, Rb);
+        Lb = ghost1<T>(cxl, q2.a, q2.b, Ra, Rb);
+      }
+      if (xhi) {  // cells n, n + 1 from cells n - 1 .. n - 4 (the previous pair)
+        const T g1 = ghost1<T>(cxh, q2.b, q2.a, Lb, La), g2 = ghost2<T>(cxh, q2.b, q2.a, Lb, La);
+        Ra = g1;
+        Rb = g2;
       }
       T s0 = T(16) * (Lb + q2.b) - (La + Ra) + T(16) * (q1.a + q3.a) - (q0.a + q4.a) + T(-30 * DIM) * q2.a;
       T s1 = T(16) * (q2.a + Ra) - (Lb + Rb) + T(16) * (q1.b + q3.b) - (q0.b + q4.b) + T(-30 * DIM) * q2.b;
