@@ -198,7 +198,7 @@ int amg_set_operator(amg_hier* h, int kind, double c);
 /* Tuning knobs of the kernels' work layout, set before amg_finalize:
  * AMG_TUNE_MARCH2 / AMG_TUNE_MARCH3: the longest march (cells a tile walks
  * along the last direction) in 2D / 3D, even, 2..4096; each multigrid depth
- * uses the longest even march up to it that still gives about 1024 tiles; AMG_TUNE_ROW_ALIGN: rows of the packed
+ * uses the longest even march up to it that still gives about 512 tiles; AMG_TUNE_ROW_ALIGN: rows of the packed
  * layout are padded so that every box row starts on a multiple of this many
  * elements (power of two, 2..256).  They change speed, not results. */
 #define AMG_TUNE_MARCH2 0

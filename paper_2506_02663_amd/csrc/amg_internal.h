@@ -79,7 +79,7 @@ struct BandChunkD {
 };
 
 constexpr int kSeg = 2048;          // tiles per first-stage reduction segment
-constexpr int64_t kTargetTiles = 1024;  // tiles a depth should offer the 256 CUs
+constexpr int64_t kTargetTiles = 512;  // tiles a depth should offer the 256 CUs (two each)
 
 struct BottomGroupD {      // systems sharing one dense inverse
   int64_t mat;             // offset of the n x n inverse (column-major) in the matrix pool
