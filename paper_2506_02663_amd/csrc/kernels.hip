@@ -1548,6 +1548,8 @@ __global__ void __launch_bounds__(256) k_resid_restrict_s(const TileD* __restric
   auto xgh = [&](int side, int p, int layer) {
     return *x_ghost(xg, b, side, DIM == 3 ? C.y : p, DIM == 3 ? p : 0, layer);
   };
+  // unscaled residual: f = (r - delta) / scal[0] in FP64, as k_scale32
+  const double finv = scal ? 1.0 / scal[0] : 1.0, fdv = scal && delta ? delta[b.comp] : 0.0;
   Pair<float> q0{}, q1{}, q2{}, q3{}, q4{};
   if (has) {
     q0 = split_pair_ld(h0, h1, c - 2 * sm, cx);
@@ -1596,10 +1598,7 @@ __global__ void __launch_bounds__(256) k_resid_restrict_s(const TileD* __restric
       }
       const float A0 = alpha * q2.a + beta * s0, A1 = alpha * q2.b + beta * s1;
       Pair<float> fv = split_pair_ld(f0, f1, c, cx);
-      if (scal) {  // unscaled residual: f = (r - delta) / scal[0] in FP64, as k_scale32
-        const double inv = 1.0 / scal[0], dv = delta ? delta[b.comp] : 0.0;
-        fv = Pair<float>{(float)(((double)fv.a - dv) * inv), (float)(((double)fv.b - dv) * inv)};
-      }
+      if (scal) fv = Pair<float>{(float)(((double)fv.a - fdv) * finv), (float)(((double)fv.b - fdv) * finv)};
       o0 = fv.a - A0;
       o1 = fv.b - A1;
     }
@@ -1929,11 +1928,12 @@ __global__ void __launch_bounds__(256) k_comp_mean_delta(const double* __restric
                                                          const double* __restrict__ cnt, double* __restrict__ delta) {
   __shared__ double sh[4];
   const int c = blockIdx.x;
-  if (!flag[c]) {  // block-uniform
+  // the flag and the segment range are loaded together (one round trip less)
+  const int32_t fl = flag[c], a = seg[cseg[c]], b = seg[cseg[c + 1]];
+  if (!fl) {  // block-uniform
     if (threadIdx.x == 0) delta[c] = 0.0;
     return;
   }
-  const int a = seg[cseg[c]], b = seg[cseg[c + 1]];
   double v = 0.0;
   for (int j = a + (int)threadIdx.x; j < b; j += 256) v += part[j];
   v = block_sum<double>(v, sh);
