@@ -179,6 +179,10 @@ void remove_mean(const Run& R, int k, T* a) {
     return;
   }
   launch_tile_sum<T>(R.dim, D, a, L.partial, R.st);
+  if (D.tiles.size() <= 1024) {  // every block re-sums at most 1024 tile sums
+    launch_comp_mean_shift<T>(R.dim, D, L.partial, L.d_comp_flag, L.d_comp_cnt + (size_t)k * L.ncomp, a, R.st);
+    return;
+  }
   launch_comp_mean_delta(D, L.partial, L.d_comp_flag, L.d_comp_cnt + (size_t)k * L.ncomp, L.ncomp, L.d_delta, R.st);
   launch_comp_shift<T>(R.dim, D, a, L.d_delta, R.st);
 }

@@ -72,6 +72,11 @@ void launch_comp_delta(const double* sum, const double* bsum, const int32_t* fla
 template <typename T>
 void launch_comp_shift(int dim, const Depth& D, T* a, const double* delta, hipStream_t st);
 void launch_chunk_fdsum(const Depth& D, const double* fd, const uint8_t* valid, double* part, hipStream_t st);
+// mean removal from the per-tile sums in one launch (each block re-sums its
+// component's tile sums)
+template <typename T>
+void launch_comp_mean_shift(int dim, const Depth& D, const double* part, const int32_t* flag, const double* cnt, T* a,
+                            hipStream_t st);
 // per-component mean removal of a small depth in one launch (one block per component)
 template <typename T>
 void launch_comp_mean_small(int dim, const Depth& D, int ncomp, const int32_t* flag, const double* cnt, T* a,

@@ -1105,6 +1105,44 @@ __global__ void __launch_bounds__(256) k_comp_shift(const TileD* __restrict__ ti
   }
 }
 
+// Per-component mean removal from the per-tile sums in part (k_tile_reduce)
+// in one launch: every block sums its component's tile sums itself, in the
+// order k_comp_mean_delta uses, so all blocks of a component subtract the
+// same mean, then shifts its own tile (for depths of few tiles, where the
+// repeated sums are cheap and the launch saved is not).
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_comp_mean_shift(const TileD* __restrict__ tiles, int ntiles,
+                                                         const BoxD* __restrict__ boxes,
+                                                         const double* __restrict__ part,
+                                                         const int32_t* __restrict__ seg,
+                                                         const int32_t* __restrict__ cseg,
+                                                         const int32_t* __restrict__ flag,
+                                                         const double* __restrict__ cnt, T* __restrict__ a) {
+  __shared__ double sh[4];
+  __shared__ double mean;
+  const int ti = tile_of_block(ntiles);
+  if (ti < 0) return;
+  const TileD t = tiles[ti];
+  const BoxD b = boxes[t.box];
+  const int comp = b.comp;
+  const int32_t fl = flag[comp], j0 = seg[cseg[comp]], j1 = seg[cseg[comp + 1]];
+  if (!fl) return;  // block-uniform
+  double v = 0.0;
+  for (int j = j0 + (int)threadIdx.x; j < j1; j += (int)blockDim.x) v += part[j];
+  v = block_sum<double>(v, sh);
+  if (threadIdx.x == 0) mean = v / (cnt[comp] * 1.0);
+  __syncthreads();
+  const double d = mean;
+  if (d == 0.0) return;
+  const Column C = column_of<DIM>(t, b);
+  if (C.ok)
+    for (int p = C.p0; p < C.p1; ++p) {
+      const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
+      a[c] = (T)((double)a[c] - d);
+      if (C.ok1) a[c + 1] = (T)((double)a[c + 1] - d);
+    }
+}
+
 // Per-component mean removal of a small depth in one launch: one block per
 // component walks the cells of the component's boxes in a fixed order,
 // sums, and subtracts sum / cells on singular components.
@@ -2617,6 +2655,23 @@ void launch_comp_shift(int dim, const Depth& D, T* a, const double* delta, hipSt
   else
     hipLaunchKernelGGL((k_comp_shift<T, 3>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, a, delta);
 }
+
+template <typename T>
+void launch_comp_mean_shift(int dim, const Depth& D, const double* part, const int32_t* flag, const double* cnt, T* a,
+                            hipStream_t st) {
+  const size_t n = D.tiles.size();
+  if (!n) return;
+  if (dim == 2)
+    hipLaunchKernelGGL((k_comp_mean_shift<T, 2>), grid8(n), threads<2>(), 0, st, D.d_tiles, (int)n, D.d_box, part,
+                       D.d_seg, D.d_cseg, flag, cnt, a);
+  else
+    hipLaunchKernelGGL((k_comp_mean_shift<T, 3>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n, D.d_box, part,
+                       D.d_seg, D.d_cseg, flag, cnt, a);
+}
+template void launch_comp_mean_shift<float>(int, const Depth&, const double*, const int32_t*, const double*, float*,
+                                            hipStream_t);
+template void launch_comp_mean_shift<double>(int, const Depth&, const double*, const int32_t*, const double*, double*,
+                                             hipStream_t);
 
 template <typename T>
 void launch_comp_mean_small(int dim, const Depth& D, int ncomp, const int32_t* flag, const double* cnt, T* a,
