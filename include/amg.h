@@ -17,7 +17,7 @@
  * Conventions shared by every call.
  *   Index space.  Level l has cell size h_l = h0 / ratio^l.  A box is given by
  *   its inclusive corners lo/hi in level-l indices (eq. AMRHier); cell i spans
- *   [i h_l, (i+1) h_l] in each direction.
+ *   [x_lo + i h_l, x_lo + (i+1) h_l] in each direction (amg_create).
  *   Packed level buffer.  Every array of cell averages of a level (solution,
  *   right-hand side, output of an operator) is ONE device buffer holding all
  *   boxes of the level, each stored with two ghost layers on every side, x
@@ -61,7 +61,7 @@ extern "C" {
 #define AMG_EUNSUPPORTED 3    /* valid but not supported (e.g. box too small) */
 #define AMG_ENOTCONVERGED 4   /* max_cycles reached; x holds the last iterate */
 #define AMG_ENONFINITE 5      /* NaN or Inf in a residual */
-#define AMG_ESOLVABILITY 6    /* Neumann defect above tolerance with enforcement off */
+#define AMG_ESOLVABILITY 6    /* Neumann defect above the stopping target with enforcement off */
 #define AMG_EDEVICE 7         /* HIP runtime error */
 
 /* operator kinds (Section 6.5) */
@@ -91,7 +91,13 @@ extern "C" {
 
 /* solvability modes for components with a constant null vector */
 #define AMG_SOLV_RHS_SHIFT 0 /* shift the right-hand side to satisfy the discrete condition */
-#define AMG_SOLV_OFF 1       /* do nothing; report the defect */
+/* AMG_SOLV_OFF: do nothing; report the defect.  The residual of a singular
+ * component has the mean defect / (|cells| h^D) whatever x is (the operator
+ * maps every x to data of zero sum there, eq. velocity_disc_solvabilityCond),
+ * so if that mean exceeds the stopping target max(tol_rel r0, tol_abs) the
+ * solve cannot converge: it returns AMG_ESOLVABILITY before any cycle, x
+ * unchanged, stats holding r0 and the defects. */
+#define AMG_SOLV_OFF 1
 /* eq. (correctingFaceAvg): add one constant delta to the Neumann face data of
  * every coarse-fine face of the component (|faces| delta h^(D-1) = defect);
  * a component without coarse-fine Neumann faces takes the RHS shift.  Level
@@ -120,7 +126,6 @@ typedef struct {
   int64_t ncells;      /* interior cells */
   int64_t nstored;     /* elements of the packed buffer */
   int64_t nface;       /* elements of the face-data buffer */
-  int32_t fused_rb;    /* bit k set: FP32 red-black sweeps at depth k run both colours in one launch */
   int32_t split_rb;    /* bit k set: mixed-precision solves post-smooth depth k in colour-split storage */
 } amg_level_desc;
 
@@ -164,10 +169,17 @@ typedef struct {
  * precision, RHS shift, tol_rel 1e-10, tol_abs 0, 100 cycles. */
 void amg_default_opts(amg_solve_opts* opts);
 
-/* Creates a hierarchy of nlevels levels over the grid of base_cells[d] cells
- * of size h0 in dimension dim (2 or 3) with refinement ratio `ratio` (2),
- * eq. (grids).  *out receives the handle.  Errors: AMG_EINVAL. */
-int amg_create(int dim, const int32_t* base_cells, double h0, int ratio, int nlevels, amg_hier** out);
+/* Creates a hierarchy of nlevels levels over the box [x_lo, x_hi] (dim
+ * entries each) of the physical domain, cut into base_cells[d] cells along
+ * direction d at level 0, in dimension dim (2 or 3) with refinement ratio
+ * `ratio` (2), eq. (grids) of Section 5.1: cells are cubes, so
+ * (x_hi[d] - x_lo[d]) / base_cells[d] must be the same h0 in every direction
+ * (to 1e-12 relative), and level l has h0 / ratio^l.  Cell i of level l spans
+ * [x_lo + i h_l, x_lo + (i+1) h_l].  *out receives the handle.
+ * Errors: AMG_EINVAL (dim, ratio, nlevels outside 1..16, fewer than 4 cells,
+ * an empty or non-finite extent, cells that are not cubes). */
+int amg_create(int dim, const double* x_lo, const double* x_hi, const int32_t* base_cells, int ratio, int nlevels,
+               amg_hier** out);
 
 /* Frees the hierarchy and all its device workspace.  NULL is a no-op. */
 int amg_destroy(amg_hier* h);
@@ -186,13 +198,32 @@ int amg_set_level_boxes(amg_hier* h, int level, int nboxes, const int32_t* lo, c
  * share one launch per multigrid step). */
 int amg_set_isolated_boxes(amg_hier* h, int level, int isolated);
 
-/* Physical condition on the domain face (d, side), side 0 = low, 1 = high. */
+/* Physical condition on the domain face (d, side), side 0 = low, 1 = high:
+ * AMG_DIRICHLET (face averages of the value, eq. velBCHomoDiri5th) or
+ * AMG_NEUMANN (face averages of the outward normal derivative, eq.
+ * Neumann5), the assignment of the boundary conditions to the velocity and
+ * pressure systems in Section 4 (default Dirichlet on every face).  Set
+ * before amg_finalize.  Errors: AMG_EINVAL (d, side or type out of range,
+ * layout final). */
 int amg_set_physical_bc(amg_hier* h, int d, int side, int type);
 
-/* Coarse-fine mode of a level > 0 (default AMG_CF_DIRICHLET). */
+/* Coarse-fine mode of a level > 0 (default AMG_CF_DIRICHLET): the condition
+ * its ghosts take on the coarse-fine interface.  AMG_CF_DIRICHLET /
+ * AMG_CF_NEUMANN: the level is solved on its own with face data on the
+ * interface (Definition 6.1 and the interface conditions of Section 6.3,
+ * filled by eqs. velBCHomoDiri5th / Neumann5 like a physical face);
+ * AMG_CF_INTERP: ghosts interpolated from level l-1 (the AMRCFI of Section
+ * 5.2), for composite solves (COH-1..4 of Section 5.3).  Set before
+ * amg_finalize.  Errors: AMG_EINVAL (level 0, mode out of range, final). */
 int amg_set_cf_mode(amg_hier* h, int level, int mode);
 
-/* Operator: AMG_HELMHOLTZ (I - c L), c > 0, or AMG_POISSON L (c ignored). */
+/* Operator of every level: AMG_HELMHOLTZ (I - c L), c > 0, the implicit
+ * stage operator of eq. GePUP-IMEX with c = gamma nu k ((TLS-2) of Section
+ * 6.5; the caller computes c, since the tableau is not printed), or
+ * AMG_POISSON L ((TLS-1) and (TLS-3); c ignored), with L the fourth-order
+ * Laplacian of eq. discreteOps c.  Set before amg_finalize (a new c after it:
+ * amg_set_coefficient).  Errors: AMG_EINVAL (kind, c <= 0 for Helmholtz,
+ * layout final). */
 int amg_set_operator(amg_hier* h, int kind, double c);
 
 /* Tuning knobs of the kernels' work layout, set before amg_finalize:
@@ -204,13 +235,6 @@ int amg_set_operator(amg_hier* h, int kind, double c);
 #define AMG_TUNE_MARCH2 0
 #define AMG_TUNE_MARCH3 1
 #define AMG_TUNE_ROW_ALIGN 2
-/* AMG_TUNE_FUSED_RB: 1 lets FP32 red-black sweeps run both colours in one
- * launch on depths whose faces are all filled uniformly (single or isolated
- * boxes with physical conditions, rows of 128 m or 128 m + (>= 4) cells,
- * rows per plane a multiple of 4; such depths then use tiles of >= 4
- * planes); 0 (default) keeps two launches per sweep, the faster form on
- * gfx950 as measured.  The two forms agree to rounding. */
-#define AMG_TUNE_FUSED_RB 3
 /* AMG_TUNE_SPLIT_RB: 1 (default) lets the mixed-precision solve keep the
  * finest depth's correction and right-hand side in colour-split storage
  * (each colour in its own half array, so a red-black half-sweep moves only
@@ -219,7 +243,7 @@ int amg_set_operator(amg_hier* h, int kind, double c);
  * boxes have even sizes and where no box is solved exactly; 0 keeps the
  * interleaved storage.  The two forms give the same results (to the
  * rounding of FP32 sums). */
-#define AMG_TUNE_SPLIT_RB 4
+#define AMG_TUNE_SPLIT_RB 3
 int amg_set_tuning(amg_hier* h, int key, int value);
 
 /* Size of the exactly solved coarsest systems (Section 6.5 leaves the bottom
@@ -242,11 +266,28 @@ int amg_set_bottom_cells(amg_hier* h, int cells);
  * Errors: AMG_ELAYOUT, AMG_EUNSUPPORTED, AMG_EDEVICE. */
 int amg_finalize(amg_hier* h);
 
+/* Summary of level `level` after amg_finalize: its boxes (eq. AMRHier), the
+ * multigrid depths the planner built (Section 6.5: a level is halved while
+ * every box has even corners and even sides of at least 8), the
+ * face-connected components and how many of them are singular (pure
+ * Neumann: the constant null vector behind the solvability condition of
+ * Section 6.4), cells, and the sizes of the packed level buffer and of the
+ * face-data buffer.  *out is written by the call.  Errors: AMG_EINVAL (not
+ * finalized, level out of range, out NULL). */
 int amg_level_info(const amg_hier* h, int level, amg_level_desc* out);
 
 /* Layout of box `box` of level `level` at multigrid depth `depth` (depth 0 is
- * the level itself; deeper layouts serve the step-level entry points). */
+ * the level itself; deeper layouts serve the step-level entry points): its
+ * inclusive corners in that depth's index space (eq. AMRHier; depth k halves
+ * the corners of depth k-1: lo / 2, (hi + 1) / 2 - 1), where it sits in the
+ * packed buffer, where its face data sit, and its component.  Box order is
+ * the order of amg_set_level_boxes at every depth.  *out is written by the
+ * call.  A box of an isolated level (amg_set_isolated_boxes) is its own
+ * domain: its corners are given in its own index space (lo = 0), and at depth
+ * k the table lists, in order, only the boxes that coarsen that far.
+ * Errors: AMG_EINVAL (not finalized, an index out of range). */
 int amg_box_info(const amg_hier* h, int level, int depth, int box, amg_box_desc* out);
+/* Elements of the packed buffer of (level, depth) and boxes at that depth. */
 int amg_depth_size(const amg_hier* h, int level, int depth, int64_t* nstored, int32_t* nboxes);
 
 /* Solves the level system A x = f on level `level` (lev_lo == lev_hi; the

@@ -22,14 +22,13 @@ FP64, MIXED = 0, 1
 F64, F32 = 0, 1
 SOLV_RHS_SHIFT, SOLV_OFF, SOLV_CF_DELTA = 0, 1, 2
 T_SWEEP, T_FILL, T_RESTRICT, T_PROLONG, T_RESIDUAL, T_SWEEP_SPLIT, T_KINDS = range(7)
-TUNE_MARCH2, TUNE_MARCH3, TUNE_ROW_ALIGN, TUNE_FUSED_RB, TUNE_SPLIT_RB = range(5)
+TUNE_MARCH2, TUNE_MARCH3, TUNE_ROW_ALIGN, TUNE_SPLIT_RB = range(4)
 MAX_HISTORY, MAX_COMP = 128, 64
 
 
 class LevelDesc(C.Structure):
     _fields_ = [("nboxes", C.c_int32), ("depths", C.c_int32), ("ncomp", C.c_int32), ("nsingular", C.c_int32),
-                ("ncells", C.c_int64), ("nstored", C.c_int64), ("nface", C.c_int64), ("fused_rb", C.c_int32),
-                ("split_rb", C.c_int32)]
+                ("ncells", C.c_int64), ("nstored", C.c_int64), ("nface", C.c_int64), ("split_rb", C.c_int32)]
 
 
 class BoxDesc(C.Structure):
@@ -67,7 +66,8 @@ def lib():
             raise RuntimeError("libamg.so is not built: run __graft_entry__.build() (hipcc, gfx950)")
         L = C.CDLL(LIB_PATH)
         vp, i32, dbl = C.c_void_p, C.c_int, C.c_double
-        L.amg_create.argtypes = [i32, C.POINTER(C.c_int32), dbl, i32, i32, C.POINTER(vp)]
+        L.amg_create.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32), i32, i32,
+                                 C.POINTER(vp)]
         L.amg_destroy.argtypes = [vp]
         L.amg_last_error.argtypes = [vp]
         L.amg_last_error.restype = C.c_char_p
@@ -142,11 +142,15 @@ def default_opts(**kw):
 class Hierarchy:
     """A box layout and operator; owns the library handle."""
 
-    def __init__(self, dim, base_cells, h0, nlevels=1, ratio=2):
+    def __init__(self, dim, base_cells, h0, nlevels=1, ratio=2, x_lo=None):
+        """Level 0 has base_cells[d] cells of size h0 from x_lo (default 0)."""
         self.dim = dim
         h = C.c_void_p()
         base = (C.c_int32 * dim)(*base_cells)
-        rc = lib().amg_create(dim, base, float(h0), ratio, nlevels, C.byref(h))
+        lo = [0.0] * dim if x_lo is None else [float(v) for v in x_lo]
+        xlo = (C.c_double * dim)(*lo)
+        xhi = (C.c_double * dim)(*[lo[d] + base_cells[d] * float(h0) for d in range(dim)])
+        rc = lib().amg_create(dim, xlo, xhi, base, ratio, nlevels, C.byref(h))
         if rc:
             raise AmgError(rc, "amg_create")
         self.h = h

@@ -26,6 +26,25 @@ import torch
 from . import amg as A
 
 
+class _coefficient:
+    """Runs a backward with the Helmholtz coefficient of its forward solve
+    (another forward on the same hierarchy may have changed it since) and
+    puts the hierarchy's coefficient back afterwards."""
+
+    def __init__(self, H, c):
+        self.H, self.c, self.prev = H, c, None
+
+    def __enter__(self):
+        if self.H.op_kind == A.HELMHOLTZ and self.H.c != self.c:
+            self.prev = self.H.c
+            self.H.set_coefficient(self.c)
+
+    def __exit__(self, *exc):
+        if self.prev is not None:
+            self.H.set_coefficient(self.prev)
+        return False
+
+
 class LevelSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, f, c, H, level, face_data, opts):
@@ -38,6 +57,7 @@ class LevelSolve(torch.autograd.Function):
         if st["status"] != 0:
             raise A.AmgError(st["status"], f"level solve did not converge: {st}")
         ctx.H, ctx.level, ctx.face_data, ctx.opts = H, level, face_data, opts
+        ctx.c_fwd = H.c  # the coefficient this solve used (the hierarchy may change it before backward)
         ctx.c_is_tensor = torch.is_tensor(c)
         ctx.c_meta = (c.dtype, c.device) if ctx.c_is_tensor else None
         ctx.save_for_backward(x)
@@ -47,16 +67,17 @@ class LevelSolve(torch.autograd.Function):
     def backward(ctx, gx):
         (x,) = ctx.saved_tensors
         H, level = ctx.H, ctx.level
-        lam = torch.zeros_like(x)
-        st = H.solve_adjoint(level, lam, gx.contiguous(), ctx.opts)
-        if st["status"] != 0:
-            raise A.AmgError(st["status"], f"adjoint solve did not converge: {st}")
-        gc = None
-        if ctx.c_is_tensor and ctx.needs_input_grad[1] and H.op_kind == A.HELMHOLTZ:
-            xx = x.clone()
-            y = torch.zeros_like(x)
-            H.apply_laplacian(level, xx, y, ctx.face_data)
-            gc = torch.tensor(H.dot(level, lam, y), dtype=ctx.c_meta[0], device=ctx.c_meta[1])
+        with _coefficient(H, ctx.c_fwd):
+            lam = torch.zeros_like(x)
+            st = H.solve_adjoint(level, lam, gx.contiguous(), ctx.opts)
+            if st["status"] != 0:
+                raise A.AmgError(st["status"], f"adjoint solve did not converge: {st}")
+            gc = None
+            if ctx.c_is_tensor and ctx.needs_input_grad[1] and H.op_kind == A.HELMHOLTZ:
+                xx = x.clone()
+                y = torch.zeros_like(x)
+                H.apply_laplacian(level, xx, y, ctx.face_data)
+                gc = torch.tensor(H.dot(level, lam, y), dtype=ctx.c_meta[0], device=ctx.c_meta[1])
         return lam, gc, None, None, None, None
 
 
@@ -77,6 +98,7 @@ class CompositeSolve(torch.autograd.Function):
         if st["status"] != 0:
             raise A.AmgError(st["status"], f"composite solve did not converge: {st}")
         ctx.H, ctx.face_data, ctx.opts = H, face_data, opts
+        ctx.c_fwd = H.c
         ctx.c_meta = (c.dtype, c.device) if torch.is_tensor(c) else None
         ctx.save_for_backward(*xs)
         return tuple(xs)
@@ -85,18 +107,19 @@ class CompositeSolve(torch.autograd.Function):
     def backward(ctx, *gxs):
         xs = ctx.saved_tensors
         H = ctx.H
-        lams = [torch.zeros_like(x) for x in xs]
-        gs = [g.contiguous() if g is not None else torch.zeros_like(x) for g, x in zip(gxs, xs)]
-        st = H.solve_adjoint_composite(lams, gs, ctx.opts)
-        if st["status"] != 0:
-            raise A.AmgError(st["status"], f"composite adjoint solve did not converge: {st}")
-        gc = None
-        if ctx.c_meta is not None and ctx.needs_input_grad[0] and H.op_kind == A.HELMHOLTZ:
-            xx = [x.clone() for x in xs]
-            ys = [torch.zeros_like(x) for x in xs]
-            H.composite_laplacian(xx, ys, ctx.face_data)
-            tot = sum(H.dot(l, lams[l], ys[l]) for l in range(len(xs)))
-            gc = torch.tensor(tot, dtype=ctx.c_meta[0], device=ctx.c_meta[1])
+        with _coefficient(H, ctx.c_fwd):
+            lams = [torch.zeros_like(x) for x in xs]
+            gs = [g.contiguous() if g is not None else torch.zeros_like(x) for g, x in zip(gxs, xs)]
+            st = H.solve_adjoint_composite(lams, gs, ctx.opts)
+            if st["status"] != 0:
+                raise A.AmgError(st["status"], f"composite adjoint solve did not converge: {st}")
+            gc = None
+            if ctx.c_meta is not None and ctx.needs_input_grad[0] and H.op_kind == A.HELMHOLTZ:
+                xx = [x.clone() for x in xs]
+                ys = [torch.zeros_like(x) for x in xs]
+                H.composite_laplacian(xx, ys, ctx.face_data)
+                tot = sum(H.dot(l, lams[l], ys[l]) for l in range(len(xs)))
+                gc = torch.tensor(tot, dtype=ctx.c_meta[0], device=ctx.c_meta[1])
         return (gc, None, None, None, *lams)
 
 

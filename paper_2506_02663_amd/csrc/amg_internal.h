@@ -188,7 +188,6 @@ struct Depth {
   std::vector<BottomGroupD> groups;
   int64_t nstored = 0;
   bool fill_only = false;  // every ghost column is filled from its own row (no exchange or interpolated ghosts)
-  bool fuse_rb = false;    // the fused red-black sweep (k_rb2) applies to this depth
   bool split_rb = false;   // colour-split storage (k_rbs) applies to this depth
   bool uniform_fill = false;  // every face of every box filled uniformly from its own rows, both ghost layers
   int march = 2;  // cells each tile marches along the last direction
@@ -292,11 +291,11 @@ struct amg_hier {
   int march2 = MARCH2_DEFAULT, march3 = MARCH3_DEFAULT;  // tile march lengths
   int row_align = ROW_ALIGN_DEFAULT;                       // row alignment of the packed layout (elements)
   int bottom_cells = 0;  // coarsening stops once every component has at most this many cells (0: off)
-  int fuse_rb = 0;       // FP32 red-black sweeps in one launch where the depth allows it (opt-in)
   int split_rb = 1;      // mixed-precision post-smoothing of depth 0 in colour-split storage where allowed
   int dim = 2;
   int32_t base[3] = {1, 1, 1};
-  double h0 = 1;
+  double h0 = 1;         // cell size of level 0
+  double x_lo[3] = {0, 0, 0};  // physical corner of the grid of level 0
   int ratio = 2;
   int nlevels = 1;
   int phys_bc[3][2] = {{0, 0}, {0, 0}, {0, 0}};

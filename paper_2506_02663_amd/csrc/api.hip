@@ -221,22 +221,7 @@ void smooth(const Run& R, int k, int smoother, int nsweeps, double omega, bool f
       std::swap(cur, oth);
     }
   } else {
-    // FP32 forward sweeps after the first run both colours in one launch
-    // where the depth allows it
-    const bool fused = sizeof(T) == 4 && !R.tr && D.fuse_rb && R.H->fuse_rb;
     for (int s = 0; s < nsweeps; ++s) {
-      if (fused && !(s == 0 && from_zero)) {
-        if (fill) {
-          Timed tm(R, AMG_T_FILL, k);
-          fill_op<T>(R, D, cur);
-        }
-        {
-          Timed tm(R, AMG_T_SWEEP, k);
-          launch_rb2<T>(D, cur, f, oth, alpha, beta, (T)omega, R.st);
-        }
-        std::swap(cur, oth);
-        continue;
-      }
       for (int col = 0; col < 2; ++col) {
         if (s == 0 && col == 0 && from_zero) {
           launch_rb<T>(R.dim, D, nullptr, f, cur, alpha, beta, (T)omega, 0, true, R.st);
@@ -323,7 +308,7 @@ float* presmooth_split(const Run& R, const Depth& D, int nsweeps, float alpha, f
 // whether a mixed-precision solve runs depth 0 in colour-split storage (its
 // right-hand side is then written split)
 inline bool use_split(const amg_hier* H, const Depth& D0, const amg_solve_opts& o) {
-  return D0.split_rb && D0.fs32 && o.smoother == AMG_SMOOTH_RB && o.nu2 > 0 && !(H->fuse_rb && D0.fuse_rb);
+  return D0.split_rb && D0.fs32 && o.smoother == AMG_SMOOTH_RB && o.nu2 > 0;
 }
 
 // One homogeneous V-cycle from e = 0; f0 is the depth-0 right-hand side, e0
@@ -688,16 +673,27 @@ void amg_default_opts(amg_solve_opts* o) {
   o->omega_rb = 1.0;
 }
 
-int amg_create(int dim, const int32_t* base_cells, double h0, int ratio, int nlevels, amg_hier** out) {
+int amg_create(int dim, const double* x_lo, const double* x_hi, const int32_t* base_cells, int ratio, int nlevels,
+               amg_hier** out) {
   if (!out) return AMG_EINVAL;
   *out = nullptr;
-  if ((dim != 2 && dim != 3) || !base_cells || !(h0 > 0) || ratio != 2 || nlevels < 1 || nlevels > 16)
+  if ((dim != 2 && dim != 3) || !x_lo || !x_hi || !base_cells || ratio != 2 || nlevels < 1 || nlevels > 16)
     return AMG_EINVAL;
-  for (int d = 0; d < dim; ++d)
-    if (base_cells[d] < 4) return AMG_EINVAL;
+  double h0 = 0;
+  for (int d = 0; d < dim; ++d) {
+    if (base_cells[d] < 4 || !std::isfinite(x_lo[d]) || !std::isfinite(x_hi[d]) || !(x_hi[d] > x_lo[d]))
+      return AMG_EINVAL;
+    const double h = (x_hi[d] - x_lo[d]) / base_cells[d];
+    if (d == 0) h0 = h;
+    // cells are cubes (eq. grids): one h for every direction
+    if (std::fabs(h - h0) > 1e-12 * h0) return AMG_EINVAL;
+  }
   amg_hier* H = new amg_hier();
   H->dim = dim;
-  for (int d = 0; d < dim; ++d) H->base[d] = base_cells[d];
+  for (int d = 0; d < dim; ++d) {
+    H->base[d] = base_cells[d];
+    H->x_lo[d] = x_lo[d];
+  }
   H->h0 = h0;
   H->ratio = ratio;
   H->nlevels = nlevels;
@@ -778,10 +774,6 @@ int amg_set_tuning(amg_hier* H, int key, int value) {
       if (value < 2 || value > 4096 || (value & 1)) return fail(H, AMG_EINVAL, "march length must be even, 2..4096");
       (key == AMG_TUNE_MARCH2 ? H->march2 : H->march3) = value;
       return AMG_OK;
-    case AMG_TUNE_FUSED_RB:
-      if (value != 0 && value != 1) return fail(H, AMG_EINVAL, "fused red-black switch must be 0 or 1");
-      H->fuse_rb = value;
-      return AMG_OK;
     case AMG_TUNE_SPLIT_RB:
       if (value != 0 && value != 1) return fail(H, AMG_EINVAL, "split red-black switch must be 0 or 1");
       H->split_rb = value;
@@ -806,19 +798,33 @@ int amg_set_bottom_cells(amg_hier* H, int cells) {
 int amg_finalize(amg_hier* H) {
   if (!H) return AMG_EINVAL;
   if (H->finalized) return fail(H, AMG_EINVAL, "already final");
-  HIPCHK(hipStreamCreate(&H->own));
+  // Host planning first (validation, tables, bottom factors, composite
+  // tables), so a rejected layout is reported before any device call.
+  std::vector<std::vector<double>> mats(H->nlevels);
+  std::vector<std::vector<int64_t>> idxs(H->nlevels);
   for (int l = 0; l < H->nlevels; ++l) {
     Level& L = H->levels[l];
     if (L.boxes.empty()) return fail(H, AMG_ELAYOUT, "level " + std::to_string(l) + " has no boxes");
     std::string err;
     int rc = plan_level(H, l, err);
     if (rc != AMG_OK) return fail(H, rc, err);
-    std::vector<double> mats;
-    std::vector<int64_t> idx;
-    rc = build_bottom(H, l, err, mats, idx);
+    rc = build_bottom(H, l, err, mats[l], idxs[l]);
     if (rc != AMG_OK) return fail(H, rc, err);
-    TRY(upload(H, &L.d_mat, mats));
-    L.nmat = mats.size();
+    L.face_valid.assign((size_t)std::max<int64_t>(L.nface, 1), 1);  // build_composite marks covered faces
+  }
+  for (int l = 1; l < H->nlevels; ++l) {
+    if (H->levels[l].cf_mode != AMG_CF_INTERP) continue;
+    std::string err;
+    int rc = build_composite(H, l, err);
+    if (rc != AMG_OK) return fail(H, rc, err);
+  }
+  HIPCHK(hipStreamCreate(&H->own));
+  for (int l = 0; l < H->nlevels; ++l) {
+    Level& L = H->levels[l];
+    const std::vector<double>& mats_l = mats[l];
+    const std::vector<int64_t>& idx = idxs[l];
+    TRY(upload(H, &L.d_mat, mats_l));
+    L.nmat = mats_l.size();
     TRY(upload(H, &L.d_idx, idx));
     size_t maxpart = 1, maxseg = 1;
     for (auto& D : L.depths) {
@@ -874,15 +880,11 @@ int amg_finalize(amg_hier* H) {
       TRY(upload(H, &D0.d_exT_slot, D0.exT_slot));
       TRY(upload(H, &D0.d_exT_ptr, D0.exT_ptr));
     }
-    L.face_valid.assign((size_t)std::max<int64_t>(L.nface, 1), 1);
   }
   // composite tables of every interpolated level against the one below
   for (int l = 1; l < H->nlevels; ++l) {
     Level& L = H->levels[l];
     if (L.cf_mode != AMG_CF_INTERP) continue;
-    std::string err;
-    int rc = build_composite(H, l, err);
-    if (rc != AMG_OK) return fail(H, rc, err);
     Composite& X = L.cmp;
     std::vector<double> w(&X.w[0][0], &X.w[0][0] + 50);
     TRY(upload(H, &X.d_w, w));
@@ -926,9 +928,6 @@ int amg_level_info(const amg_hier* Hc, int level, amg_level_desc* out) {
   out->ncells = L.ncells;
   out->nstored = L.depths[0].nstored;
   out->nface = L.nface;
-  out->fused_rb = 0;
-  for (size_t k = 0; k < L.depths.size() && k < 31; ++k)
-    if (H->fuse_rb && L.depths[k].fuse_rb) out->fused_rb |= 1 << k;
   out->split_rb = L.depths[0].split_rb ? 1 : 0;
   return AMG_OK;
 }
@@ -1146,6 +1145,7 @@ static int composite_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x
   const int dim = H->dim;
   Level& L0 = H->levels[0];
   if (stats) memset(stats, 0, sizeof *stats);
+  double comp_defect_mean = 0.0;
   // solvability of the pure-Neumann composite problem: one constant shift of
   // the right-hand side on every level (sums over valid cells and over the
   // physical faces of valid cells)
@@ -1179,6 +1179,7 @@ static int composite_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x
       stats->ncomp = 1;
       stats->defect[0] = defect;
     }
+    comp_defect_mean = std::fabs(defect) / vol;
     if (o.solvability != AMG_SOLV_OFF) {
       L0.h_scal[0] = defect / vol;
       HIPCHK(hipMemcpyAsync(L0.scal + S_DELTA, L0.h_scal, sizeof(double), hipMemcpyHostToDevice, C.st));
@@ -1207,6 +1208,13 @@ static int composite_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x
   if (stats) {
     stats->r0 = r0;
     stats->history[0] = r0;
+  }
+  // unenforced solvability: the volume-weighted mean of the composite
+  // residual is defect / volume whatever x is (see level_solve)
+  if (L0.nsingular && o.solvability == AMG_SOLV_OFF && comp_defect_mean > target) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "mean defect %.3e exceeds the stopping target %.3e", comp_defect_mean, target);
+    return fail(H, AMG_ESOLVABILITY, buf);
   }
   while (rn > target && cycles < o.max_cycles) {
     comp_cycle(C, o);
@@ -1338,6 +1346,24 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
   if (stats) {
     stats->r0 = r0;
     stats->history[0] = r0;
+  }
+  // Without enforcement the residual keeps the mean defect / (|c| h^D) on a
+  // singular component c whatever x is (the discrete divergence theorem of
+  // eq. velocity_disc_solvabilityCond), so a mean above the target can never
+  // be reached.
+  if (!tr && L.nsingular && o.solvability == AMG_SOLV_OFF) {
+    std::vector<double> df(L.ncomp);
+    HIPCHK(hipMemcpyAsync(df.data(), L.d_defect, L.ncomp * sizeof(double), hipMemcpyDeviceToHost, R.st));
+    HIPCHK(hipStreamSynchronize(R.st));
+    for (int c = 0; c < L.ncomp; ++c) {
+      if (!L.comp_singular[c]) continue;
+      const double m = std::fabs(df[c]) / ((double)L.comp_cells[c] * hD);
+      if (m > target) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "component %d: mean defect %.3e exceeds the stopping target %.3e", c, m, target);
+        return fail(H, AMG_ESOLVABILITY, buf);
+      }
+    }
   }
   // one outer cycle: r -> V-cycle -> x += s e -> new residual and its norm
   // per-component means of the residual: from the per-tile sums the
@@ -1827,7 +1853,7 @@ int amg_time_sweep(amg_hier* H, int level, int dtype, int smoother, int n, void*
     if constexpr (sizeof(T) == 4) {
       // the form the mixed-precision solve post-smooths in: n half-sweeps
       // in colour-split storage (u, f and tmp taken as split arrays)
-      if (smoother == AMG_SMOOTH_RB && D.split_rb && !(H->fuse_rb && D.fuse_rb)) {
+      if (smoother == AMG_SMOOTH_RB && D.split_rb) {
         const int64_t hs = D.nstored / 2;
         const float* h[2] = {cur, cur + hs};
         for (int i = 0; i < n; ++i) {
@@ -1844,8 +1870,6 @@ int amg_time_sweep(amg_hier* H, int level, int dtype, int smoother, int n, void*
       const int gr = sizeof(T) == 4 ? 1 : 0;  // the form the FP32 V-cycle launches
       if (smoother == AMG_SMOOTH_JACOBI)
         launch_jacobi<T>(H->dim, D, cur, ff, oth, a, b, T(2.0 / 3.0), false, st, gr);
-      else if (sizeof(T) == 4 && D.fuse_rb && H->fuse_rb)
-        launch_rb2<T>(D, cur, ff, oth, a, b, T(1), st);  // one launch = both colours
       else
         launch_rb<T>(H->dim, D, cur, ff, oth, a, b, T(1), i & 1, false, st, gr);
       std::swap(cur, oth);
@@ -1877,7 +1901,9 @@ int amg_autotune(amg_hier* H, int level, int dtype, int smoother, int nreps, int
   for (int m : cands) {
     // a finalized copy of the layout with march length m
     amg_hier* T = nullptr;
-    int rc = amg_create(H->dim, H->base, H->h0, H->ratio, H->nlevels, &T);
+    double xhi[3];
+    for (int d = 0; d < H->dim; ++d) xhi[d] = H->x_lo[d] + H->base[d] * H->h0;
+    int rc = amg_create(H->dim, H->x_lo, xhi, H->base, H->ratio, H->nlevels, &T);
     if (rc != AMG_OK) return fail(H, rc, "autotune: amg_create failed");
     for (int l = 0; l < H->nlevels && rc == AMG_OK; ++l) {
       T->levels[l].boxes = H->levels[l].boxes;
@@ -1889,7 +1915,6 @@ int amg_autotune(amg_hier* H, int level, int dtype, int smoother, int nreps, int
     T->c = H->c;
     T->row_align = H->row_align;
     T->bottom_cells = H->bottom_cells;
-    T->fuse_rb = H->fuse_rb;
     T->split_rb = H->split_rb;
     T->march2 = T->march3 = m;
     rc = amg_finalize(T);

@@ -34,10 +34,6 @@ void launch_residual(int dim, const Depth& D, bool all, const T* u, const T* f, 
 template <typename T>
 void launch_jacobi(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, T omega, bool zero,
                    hipStream_t st, int gr = 0);
-// both colours of one red-black sweep in one launch (FP32 3D, depths with
-// D.fuse_rb); out receives the whole swept array
-template <typename T>
-void launch_rb2(const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, T omega, hipStream_t st);
 template <typename T>
 void launch_rb(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, T omega, int col, bool zero,
                hipStream_t st, int gr = 0);

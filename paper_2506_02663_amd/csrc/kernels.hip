@@ -500,318 +500,6 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
   }
 }
 
-// Fused red-black sweep (FP32, 3D): the red half-sweep and then the black
-// half-sweep of k_march1<OP_RB> in one launch, with the same arithmetic, for
-// depths whose faces are all filled uniformly (both ghost layers from the
-// row).  The march computes red at plane p and black at plane p - 1:
-// - red cells need only the input; own columns keep their z neighbours in a
-//   register window, x and y neighbours come through the caches as in
-//   k_march1;
-// - the post-red state of plane p (red cells new, black cells old) of the
-//   tile and of a one-cell ring around it is staged in LDS, plus the old
-//   values two cells out, so the black update of plane p - 1 reads its x and
-//   y neighbours from LDS (triple-buffered planes, one barrier per plane); the
-//   ring's red cells are recomputed by this block;
-// - z neighbours of black cells come from the registers (post-red window for
-//   the red cells at distance 1, old window at distance 2);
-// - ghosts of the post-red state at the box faces are formed from the post-red
-//   cells they depend on (LDS rows across the march, registers along it, the
-//   four lowest planes computed ahead at the low face).
-// Each cell of the tile is written once.  Tiles need at least 4 planes; boxes
-// need rows of 128 m or 128 m + (>= 4) cells and a multiple of 4 rows.
-constexpr int RB2_W = TILE_X + 4, RB2_H = TILE3_Y + 4;
-
-template <typename T>
-__global__ void __launch_bounds__(512) k_rb2(const TileD* __restrict__ tiles, int ntiles,
-                                             const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
-                                             const T* u, const T* __restrict__ f, T* __restrict__ out, T alpha,
-                                             T beta, T omega) {
-  __shared__ T pl[3][RB2_H][RB2_W];
-  const int ti = tile_of_block(ntiles);
-  if (ti < 0) return;
-  const TileD t = tiles[ti];
-  const BoxD b = boxes[t.box];
-  const int nx = b.n[0], ny = b.n[1], nz = b.n[2];
-  const int x0 = t.x0, y0 = t.y0;
-  const int ntx = min(TILE_X, nx - x0), nty = min(TILE3_Y, ny - y0);
-  const int p0 = t.z0, p1 = min(t.z0 + t.len, nz);
-  const int64_t sy = b.s[1], sm = b.s[2];
-  const int pa = p0 > 0 ? p0 - 1 : 0;  // first red plane of the own columns
-  const int pb = min(p1, nz - 1);      // last red plane of the own columns
-  const uint8_t czl = b.ucode[2][0], czh = b.ucode[2][1];
-  // old-state ghosts across the march for the tile and its ring, on every
-  // plane a red update reads here (each value is the same whichever block
-  // writes it)
-  {
-    const int xa = max(x0 - 1, 0), xb = min(x0 + ntx + 1, nx);
-    const int ya = max(y0 - 1, 0), yb = min(y0 + nty + 1, ny);
-    const int za = pa, zb = min(nz, max(pb + 1, p0 == 0 ? 4 : 0));
-    face_ghosts<T, 3>(b, const_cast<T*>(u), xa, xb - xa, ya, yb - ya, za, zb - za);
-    __syncthreads();
-  }
-  // old value of plane r of the column whose plane-0 element is e (ghosts of
-  // the z faces from the fill of the column)
-  auto old_at = [&](int64_t e, int r) -> T {
-    if (r >= 0 && r < nz) return u[e + (int64_t)r * sm];
-    T g1 = T(0), g2 = T(0);
-    if (r == -1 || r == -2) {
-      gfill<T>(czl, u, e, sm, g1, g2);
-      return r == -1 ? g1 : g2;
-    }
-    if (r == nz || r == nz + 1) {
-      gfill<T>(czh, u, e + (int64_t)(nz - 1) * sm, -sm, g1, g2);
-      return r == nz ? g1 : g2;
-    }
-    return T(0);
-  };
-  // post-red value at plane r of a column with element ec at plane r; m2..q2
-  // its old values at planes r - 2 .. r + 2, inv its inverse diagonal there
-  auto red_val = [&](int64_t ec, int r, int par, T inv, T m2, T m1, T c0, T q1, T q2) -> T {
-    if ((par + r) & 1) return c0;  // black: unchanged by the red half-sweep
-    T ls = T(16) * (u[ec - 1] + u[ec + 1]) - (u[ec - 2] + u[ec + 2]) + T(16) * (m1 + q1) - (m2 + q2) +
-           T(-30 * 3) * c0;
-    ls += T(16) * (u[ec - sy] + u[ec + sy]) - (u[ec - 2 * sy] + u[ec + 2 * sy]);
-    const T Au = alpha * c0 + beta * ls;
-    return c0 + omega * (f[ec] - Au) * inv;
-  };
-  // inverse diagonals of a column at planes 0, 1, the middle, nz - 2, nz - 1
-  // (the faces across the march carry one code each, so nothing else varies)
-  struct Inv5 {
-    T lo0, lo1, mid, hi1, hi0;
-    __device__ __forceinline__ T at(int r, int n) const {
-      return r == 0 ? lo0 : r == 1 ? lo1 : r == n - 2 ? hi1 : r == n - 1 ? hi0 : mid;
-    }
-  };
-  auto inv5 = [&](int xx, int yy) -> Inv5 {
-    DiagColumn<T, 3> dg;
-    dg.init(b, codes, xx, yy, alpha, beta, true);
-    Inv5 v{dg.inv(b, codes, 0, xx, yy, 0), dg.inv(b, codes, 1, xx, yy, 1), dg.inv_mid,
-           dg.inv(b, codes, nz - 2, xx, yy, nz - 2), dg.inv(b, codes, nz - 1, xx, yy, nz - 1)};
-    // kept in registers: otherwise the divisions are redone per cell in the march
-    asm volatile("" : "+v"(v.lo0), "+v"(v.lo1), "+v"(v.mid), "+v"(v.hi1), "+v"(v.hi0));
-    return v;
-  };
-
-  // ---- own column ----
-  const Column C = column1_of<3>(t, b);
-  const bool ok = C.ok;
-  const int x = C.x, y = C.y, lx = x - x0 + 2, ly = y - y0 + 2;
-  const int par = (b.lo[0] + x + b.lo[1] + y + b.lo[2]) & 1;  // red where (par + z) is even
-  const int64_t e0 = C.base + 2 * sm;                          // element of plane 0
-  Inv5 dg{T(0), T(0), T(0), T(0), T(0)};
-  T w0 = T(0), w1 = T(0), w2 = T(0), w3 = T(0), w4 = T(0), w5 = T(0);  // old, planes p-3 .. p+2
-  T r0 = T(0), r1 = T(0), r2 = T(0), r3 = T(0);                        // post-red, planes p-3 .. p
-  T gzl1 = T(0), gzl2 = T(0), gzh1 = T(0), gzh2 = T(0);                // post-red z ghosts
-  T g2n = T(0);
-  if (ok) {
-    dg = inv5(x, y);
-    w0 = old_at(e0, pa - 3);
-    w1 = old_at(e0, pa - 2);
-    w2 = old_at(e0, pa - 1);
-    w3 = old_at(e0, pa);
-    w4 = old_at(e0, pa + 1);
-    w5 = old_at(e0, pa + 2);
-    g2n = old_at(e0, nz + 1);
-    if (p0 == 0) {
-      // post-red planes 0..3 of this column, for the low-face ghosts
-      const T o[8] = {old_at(e0, -2), old_at(e0, -1), old_at(e0, 0), old_at(e0, 1),
-                      old_at(e0, 2),  old_at(e0, 3),  old_at(e0, 4), old_at(e0, 5)};
-      T v[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        v[r] = red_val(e0 + (int64_t)r * sm, r, par, dg.at(r, nz), o[r], o[r + 1], o[r + 2], o[r + 3], o[r + 4]);
-      gzl1 = ghost1<T>(czl, v[0], v[1], v[2], v[3]);
-      gzl2 = ghost2<T>(czl, v[0], v[1], v[2], v[3]);
-    }
-  }
-
-  // ---- ring: one red-updated cell out (post-red state), two cells out (old) ----
-  auto ring_pos = [&](int j, int dist, int& xr, int& yr) -> bool {
-    const bool ylo = y0 - dist >= 0, yhi = y0 + nty - 1 + dist < ny;
-    const bool xlo = x0 - dist >= 0, xhi = x0 + ntx - 1 + dist < nx;
-    if (ylo) {
-      if (j < ntx) { xr = x0 + j; yr = y0 - dist; return true; }
-      j -= ntx;
-    }
-    if (yhi) {
-      if (j < ntx) { xr = x0 + j; yr = y0 + nty - 1 + dist; return true; }
-      j -= ntx;
-    }
-    if (xlo) {
-      if (j < nty) { xr = x0 - dist; yr = y0 + j; return true; }
-      j -= nty;
-    }
-    if (xhi) {
-      if (j < nty) { xr = x0 + ntx - 1 + dist; yr = y0 + j; return true; }
-    }
-    return false;
-  };
-  int xr1 = 0, yr1 = 0, xr2 = 0, yr2 = 0;
-  const bool has1 = ring_pos((int)threadIdx.x, 1, xr1, yr1);
-  const bool has2 = ring_pos((int)threadIdx.x, 2, xr2, yr2);
-  const int64_t e1 = b.off + (xr1 + 2) + (int64_t)(yr1 + 2) * sy + 2 * sm;
-  const int64_t e2 = b.off + (xr2 + 2) + (int64_t)(yr2 + 2) * sy + 2 * sm;
-  const int par1 = (b.lo[0] + xr1 + b.lo[1] + yr1 + b.lo[2]) & 1;
-  Inv5 dr{T(0), T(0), T(0), T(0), T(0)};
-  T v0 = T(0), v1 = T(0), v2 = T(0), v3 = T(0), v4 = T(0);  // ring column, old, planes p-2 .. p+2
-  T h2n = T(0);
-  if (has1) {
-    dr = inv5(xr1, yr1);
-    v0 = old_at(e1, pa - 2);
-    v1 = old_at(e1, pa - 1);
-    v2 = old_at(e1, pa);
-    v3 = old_at(e1, pa + 1);
-    v4 = old_at(e1, pa + 2);
-    h2n = old_at(e1, nz + 1);
-  }
-
-  // x/y neighbours and f of a red cell, loaded one plane ahead so that the
-  // loads are in flight across the barrier and the black phase
-  struct Nb {
-    T xm1, xp1, xm2, xp2, ym1, yp1, ym2, yp2, fv;
-  };
-  auto load_nb = [&](int64_t ec) -> Nb {
-    return Nb{u[ec - 1],  u[ec + 1],      u[ec - 2],      u[ec + 2], u[ec - sy],
-              u[ec + sy], u[ec - 2 * sy], u[ec + 2 * sy], f[ec]};
-  };
-  auto red_of = [&](const Nb& n, T inv, T m2, T m1, T c0, T q1, T q2) -> T {
-    T ls = T(16) * (n.xm1 + n.xp1) - (n.xm2 + n.xp2) + T(16) * (m1 + q1) - (m2 + q2) + T(-30 * 3) * c0;
-    ls += T(16) * (n.ym1 + n.yp1) - (n.ym2 + n.yp2);
-    const T Au = alpha * c0 + beta * ls;
-    return c0 + omega * (n.fv - Au) * inv;
-  };
-  Nb nown{}, nring{};
-  T fblk = T(0), r2n = T(0), wn = T(0), vn = T(0);
-  // loads for the step of plane pn: its red inputs, f of the black cell at
-  // pn - 1 (the same lanes), ring values, and plane pn + 2 of the windows
-  auto prefetch = [&](int pn) {
-    if (ok) {
-      const bool red_n = !((par + pn) & 1);  // red at pn, black at pn - 1
-      if (pn <= pb && red_n) nown = load_nb(e0 + (int64_t)pn * sm);
-      if (red_n && pn - 1 >= p0 && pn - 1 < p1) fblk = f[e0 + (int64_t)(pn - 1) * sm];
-      if (pn + 2 < nz) wn = u[e0 + (int64_t)(pn + 2) * sm];
-    }
-    if (pn >= p0 && pn < p1) {
-      if (has1 && !((par1 + pn) & 1)) nring = load_nb(e1 + (int64_t)pn * sm);
-      if (has2) r2n = u[e2 + (int64_t)pn * sm];
-    }
-    if (has1 && pn + 2 < nz) vn = u[e1 + (int64_t)(pn + 2) * sm];
-  };
-  prefetch(pa);
-  const int pe = p1;  // black at plane p1 - 1 is done in the step of plane p1
-  for (int p = pa; p <= pe; ++p) {
-    T (*L)[RB2_W] = pl[p % 3];
-    const bool own_plane = p >= p0 && p < p1;
-    const Nb cown = nown, cring = nring;
-    const T cfb = fblk, cr2 = r2n;
-    // red phase: plane p
-    T v = T(0);
-    if (ok && p <= pb) {
-      v = ((par + p) & 1) ? w3 : red_of(cown, dg.at(p, nz), w1, w2, w3, w4, w5);
-      if (own_plane) {
-        L[ly][lx] = v;
-        if (!((par + p) & 1)) out[e0 + (int64_t)p * sm] = v;
-      }
-    }
-    r0 = r1;  // post-red window: planes p - 3 .. p
-    r1 = r2;
-    r2 = r3;
-    r3 = v;
-    if (ok && p == nz - 1) {  // post-red planes nz-4 .. nz-1 are r0..r3
-      gzh1 = ghost1<T>(czh, r3, r2, r1, r0);
-      gzh2 = ghost2<T>(czh, r3, r2, r1, r0);
-    }
-    if (own_plane) {
-      if (has1) L[yr1 - y0 + 2][xr1 - x0 + 2] = ((par1 + p) & 1) ? v2 : red_of(cring, dr.at(p, nz), v0, v1, v2, v3, v4);
-      if (has2) L[yr2 - y0 + 2][xr2 - x0 + 2] = cr2;
-    }
-    if (p + 1 <= pe) prefetch(p + 1);  // (wn, vn: plane p + 3, entering the windows below)
-    // the LDS plane is complete: only LDS needs ordering here, so the global
-    // loads just issued stay in flight
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-    // black phase: plane q = p - 1
-    const int q = p - 1;
-    if (ok && q >= p0 && q < p1 && ((par + q) & 1)) {
-      const T (*B)[RB2_W] = pl[(p + 2) % 3];
-      const T c0 = w2;  // old value at plane q (black: also its post-red value)
-      // post-red ghosts of the x and y faces near this cell
-      T gx1 = T(0), gx2 = T(0), gy1 = T(0), gy2 = T(0);
-      if (x < 2) {
-        gx1 = ghost1<T>(b.ucode[0][0], B[ly][2], B[ly][3], B[ly][4], B[ly][5]);
-        gx2 = ghost2<T>(b.ucode[0][0], B[ly][2], B[ly][3], B[ly][4], B[ly][5]);
-      } else if (x > nx - 3) {
-        const int le = nx - 1 - x0 + 2;
-        gx1 = ghost1<T>(b.ucode[0][1], B[ly][le], B[ly][le - 1], B[ly][le - 2], B[ly][le - 3]);
-        gx2 = ghost2<T>(b.ucode[0][1], B[ly][le], B[ly][le - 1], B[ly][le - 2], B[ly][le - 3]);
-      }
-      if (y < 2) {
-        gy1 = ghost1<T>(b.ucode[1][0], B[2][lx], B[3][lx], B[4][lx], B[5][lx]);
-        gy2 = ghost2<T>(b.ucode[1][0], B[2][lx], B[3][lx], B[4][lx], B[5][lx]);
-      } else if (y > ny - 3) {
-        const int le = ny - 1 - y0 + 2;
-        gy1 = ghost1<T>(b.ucode[1][1], B[le][lx], B[le - 1][lx], B[le - 2][lx], B[le - 3][lx]);
-        gy2 = ghost2<T>(b.ucode[1][1], B[le][lx], B[le - 1][lx], B[le - 2][lx], B[le - 3][lx]);
-      }
-      const T xm1 = x >= 1 ? B[ly][lx - 1] : gx1;
-      const T xm2 = x >= 2 ? B[ly][lx - 2] : (x == 1 ? gx1 : gx2);
-      const T xp1 = x <= nx - 2 ? B[ly][lx + 1] : gx1;
-      const T xp2 = x <= nx - 3 ? B[ly][lx + 2] : (x == nx - 2 ? gx1 : gx2);
-      const T ym1 = y >= 1 ? B[ly - 1][lx] : gy1;
-      const T ym2 = y >= 2 ? B[ly - 2][lx] : (y == 1 ? gy1 : gy2);
-      const T yp1 = y <= ny - 2 ? B[ly + 1][lx] : gy1;
-      const T yp2 = y <= ny - 3 ? B[ly + 2][lx] : (y == ny - 2 ? gy1 : gy2);
-      // z: post-red at q -+ 1 (r1, r3: planes p - 2, p), old at q -+ 2 (w0, w4)
-      const T zm1 = q >= 1 ? r1 : gzl1;
-      const T zm2 = q >= 2 ? w0 : (q == 1 ? gzl1 : gzl2);
-      const T zp1 = q <= nz - 2 ? r3 : gzh1;
-      const T zp2 = q <= nz - 3 ? w4 : (q == nz - 2 ? gzh1 : gzh2);
-      T ls = T(16) * (xm1 + xp1) - (xm2 + xp2) + T(16) * (zm1 + zp1) - (zm2 + zp2) + T(-30 * 3) * c0;
-      ls += T(16) * (ym1 + yp1) - (ym2 + yp2);
-      const T Au = alpha * c0 + beta * ls;
-      out[e0 + (int64_t)q * sm] = c0 + omega * (cfb - Au) * dg.at(q, nz);
-    }
-    // advance the old windows to plane p + 1 (plane p + 3 enters; its load
-    // was issued with the prefetch)
-    if (ok) {
-      T nw;
-      const int r = p + 3;
-      if (r < nz) {
-        nw = wn;
-      } else if (r == nz) {  // w2..w5 hold planes nz-4 .. nz-1
-        nw = ghost1<T>(czh, w5, w4, w3, w2);
-        g2n = ghost2<T>(czh, w5, w4, w3, w2);
-      } else {
-        nw = r == nz + 1 ? g2n : T(0);
-      }
-      w0 = w1;
-      w1 = w2;
-      w2 = w3;
-      w3 = w4;
-      w4 = w5;
-      w5 = nw;
-    }
-    if (has1) {
-      T nv;
-      const int r = p + 3;
-      if (r < nz) {
-        nv = vn;
-      } else if (r == nz) {  // v1..v4 hold planes nz-4 .. nz-1
-        nv = ghost1<T>(czh, v4, v3, v2, v1);
-        h2n = ghost2<T>(czh, v4, v3, v2, v1);
-      } else {
-        nv = r == nz + 1 ? h2n : T(0);
-      }
-      v0 = v1;
-      v1 = v2;
-      v2 = v3;
-      v3 = v4;
-      v4 = nv;
-    }
-  }
-}
-
 // Two cells (x, x+1) per thread and step.  x neighbours: the two cells on
 // each side come from the adjacent lanes (shuffles); the end lanes of the
 // wavefront read them from memory.  y neighbours (3D): vector loads through
@@ -1106,10 +794,13 @@ __global__ void __launch_bounds__(256) k_comp_shift(const TileD* __restrict__ ti
 }
 
 // Per-component mean removal from the per-tile sums in part (k_tile_reduce)
-// in one launch: every block sums its component's tile sums itself, in the
-// order k_comp_mean_delta uses, so all blocks of a component subtract the
-// same mean, then shifts its own tile (for depths of few tiles, where the
-// repeated sums are cheap and the launch saved is not).
+// in one launch: every block sums its component's tile sums itself, in one
+// fixed order (a block-size stride, the same in every block of the launch),
+// so all blocks of a component subtract the same mean, then shifts its own
+// tile (for depths of few tiles, where the repeated sums are cheap and the
+// launch saved is not).  In 3D the blocks have the 256 threads of
+// k_comp_mean_delta and sum in its order; the 64-thread blocks of 2D sum in
+// another order, so the two mean paths agree there to rounding only.
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_comp_mean_shift(const TileD* __restrict__ tiles, int ntiles,
                                                          const BoxD* __restrict__ boxes,
@@ -1208,7 +899,12 @@ __global__ void __launch_bounds__(256) k_tile_reduce(const TileD* __restrict__ t
     for (int p = C.p0; p < C.p1; ++p) {
       const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
       const double x0 = (double)a[c], x1 = C.ok1 ? (double)a[c + 1] : 0.0;
-      v = MAX ? fmax(v, fmax(fabs(x0), fabs(x1))) : v + (x0 + x1);
+      if (MAX) {
+        const double m = fmax(fabs(x0), fabs(x1));
+        v = fmax(v, (x0 == x0 && x1 == x1) ? m : (double)INFINITY);  // a NaN must not vanish in fmax
+      } else {
+        v += x0 + x1;
+      }
     }
   v = MAX ? block_max<double>(v, sh) : block_sum<double>(v, sh);
   if (threadIdx.x == 0) part[ti] = v;
@@ -2516,14 +2212,6 @@ void launch_residual(int dim, const Depth& D, bool all, const T* u, const T* f, 
 }
 
 template <typename T>
-void launch_rb2(const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, T omega, hipStream_t st) {
-  const size_t n = D.stiles.size();
-  if (!n) return;
-  hipLaunchKernelGGL((k_rb2<T>), grid8(n), dim3(512), 0, st, D.d_stiles, (int)n, D.d_box, D.d_codes, u, f, out, alpha,
-                     beta, omega);
-}
-
-template <typename T>
 void launch_jacobi(int dim, const Depth& D, const T* u, const T* f, T* out, T alpha, T beta, T omega, bool zero,
                    hipStream_t st, int gr) {
   const size_t n = D.stiles.size();
@@ -2955,7 +2643,6 @@ void launch_zero(T* a, int64_t n, hipStream_t st) {
   template void launch_residual<T>(int, const Depth&, bool, const T*, const T*, T*, T, T, double*, hipStream_t);  \
   template void launch_jacobi<T>(int, const Depth&, const T*, const T*, T*, T, T, T, bool, hipStream_t, int);     \
   template void launch_rb<T>(int, const Depth&, const T*, const T*, T*, T, T, T, int, bool, hipStream_t, int);    \
-  template void launch_rb2<T>(const Depth&, const T*, const T*, T*, T, T, T, hipStream_t);                         \
   template void launch_resid_restrict<T>(int, const Depth&, const Depth&, const T*, const T*, T*, T, T,           \
                                          hipStream_t, int);                                                       \
   template void launch_restrict<T>(int, const Depth&, const Depth&, const T*, T*, hipStream_t);                   \

@@ -119,6 +119,31 @@ int plan_level(amg_hier* H, int l, std::string& err) {
         return AMG_ELAYOUT;
       }
     }
+    // nesting (Section 5.1): the parents of every cell of level l are cells
+    // of level l-1, i.e. each coarsened box is covered by the (disjoint)
+    // boxes of level l-1
+    if (l > 0 && !H->levels[l - 1].isolated) {
+      const std::vector<Box>& CB = H->levels[l - 1].boxes;
+      for (int b = 0; b < nb; ++b) {
+        Box P;
+        int64_t need = 1, got = 0;
+        for (int d = 0; d < 3; ++d) {
+          P.lo[d] = d < dim ? L.boxes[b].lo[d] / H->ratio : 0;
+          P.hi[d] = d < dim ? (L.boxes[b].hi[d] + 1) / H->ratio - 1 : 0;
+          if (d < dim) need *= P.n(d);
+        }
+        for (const Box& Q : CB) {
+          int64_t v = 1;
+          for (int d = 0; d < dim; ++d) v *= std::max(0, std::min(P.hi[d], Q.hi[d]) - std::max(P.lo[d], Q.lo[d]) + 1);
+          got += v;
+        }
+        if (got != need) {
+          snprintf(buf, sizeof buf, "level %d is not nested in level %d (box %d)", l, l - 1, b);
+          err = buf;
+          return AMG_ELAYOUT;
+        }
+      }
+    }
   }
   L.ncells = vol;
 
@@ -457,17 +482,6 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       for (int d = 0; d + 1 < dim; ++d)
         if (X.ucode[d][0] == 0xFF || X.ucode[d][1] == 0xFF) D.fill_only = false;
 
-    // the fused red-black sweep (3D) needs every face filled uniformly with
-    // both layers from its row, a last x-tile at least 4 wide, whole 4-row
-    // tiles and tiles of at least 4 planes
-    bool fuse_ok = H->fuse_rb && dim == 3 && D.fill_only && H->march3 >= 4;
-    for (const BoxD& X : D.boxd) {
-      for (int d = 0; d < 3; ++d)
-        for (int s = 0; s < 2; ++s)
-          if (X.ucode[d][s] != 5 && X.ucode[d][s] != 6) fuse_ok = false;
-      if ((X.n[0] % TILE_X != 0 && X.n[0] % TILE_X < 4) || X.n[1] % TILE3_Y != 0) fuse_ok = false;
-    }
-
     // ---- tiles (grouped by component, so each component is one range) ----
     D.tiles.clear();
     D.stiles.clear();
@@ -484,7 +498,7 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       }
       const int cap = dim == 2 ? H->march2 : H->march3;
       int64_t m = R / kTargetTiles;
-      m = std::max<int64_t>(fuse_ok ? 4 : 2, std::min<int64_t>(cap, m));
+      m = std::max<int64_t>(2, std::min<int64_t>(cap, m));
       CH = (int)(m & ~int64_t(1));
     }
     D.march = CH;
@@ -521,7 +535,6 @@ int plan_level(amg_hier* H, int l, std::string& err) {
         D.seg_ptr.push_back((int32_t)std::min(D.tiles.size(), a + kSeg));
       D.comp_seg_ptr.push_back((int32_t)D.seg_ptr.size() - 1);
     }
-    D.fuse_rb = fuse_ok && !D.stiles.empty();
     D.uniform_fill = D.fill_only;
     for (const BoxD& X : D.boxd)
       for (int d = 0; d < dim; ++d)
@@ -553,8 +566,6 @@ int plan_level(amg_hier* H, int l, std::string& err) {
         X.xg = D.nxg;
         D.nxg += 4 * (int64_t)X.n[1] * X.n[2];
       }
-    for (const TileD& T : D.stiles)
-      if (T.len < 4) D.fuse_rb = false;
     prev_index = cur_index;
   }
 

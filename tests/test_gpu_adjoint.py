@@ -150,6 +150,32 @@ def test_autograd_against_oracle(name):
     assert abs(cdev.grad.item() - gc) < 1e-8 * abs(gc)
 
 
+def test_backward_uses_the_coefficient_of_its_forward():
+    # two forward solves at different c on one hierarchy, then the backward of
+    # the first: its gradients are the oracle's at the first c, and the
+    # hierarchy keeps the coefficient it had before the backward
+    lev = unit_level(32, 2, "D")
+    c1, c2 = 0.3 * lev.h, 0.8 * lev.h
+    H, L = make_hier(lev, "helmholtz", c1)
+    f, t = random_field(lev, 21), random_field(lev, 22)
+    fdev, tdev = to_dev(H, L, 0, f).requires_grad_(True), to_dev(H, L, 0, t)
+    mask = to_dev(H, L, 0, lev.mask.astype(float))
+    opts = A.default_opts(precision=A.FP64, smoother=A.SMOOTH_RB, tol_rel=1e-13, max_cycles=200)
+    cdev = torch.tensor(c1, dtype=torch.float64, requires_grad=True)
+    x1 = level_solve(fdev, cdev, H, L, None, opts)
+    x2 = level_solve(fdev.detach(), c2, H, L, None, opts)
+    assert H.c == c2
+    J = 0.5 * (((x1 - tdev) * mask) ** 2).sum()
+    J.backward()
+    assert H.c == c2
+    u, _ = mg.solve(lev, f, "helmholtz", c1, tol_rel=1e-13, max_cycles=200)
+    lam, _ = mg.solve(lev, u - t, "helmholtz", c1, tol_rel=1e-13, max_cycles=200, transpose=True)
+    assert relerr(from_dev(H, L, 0, fdev.grad, lev), lam, lev.mask) < 1e-9
+    gc = mg.grad_c(lev, lam, u)
+    assert abs(cdev.grad.item() - gc) < 1e-8 * abs(gc)
+    del x2
+
+
 def test_autograd_finite_differences_and_nu_chain():
     # dJ/dnu through c = gamma nu k by autograd, against central differences
     # of GPU solves (step 1e-6 relative); the hierarchy's coefficient is

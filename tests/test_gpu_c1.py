@@ -1,0 +1,55 @@
+"""The 2D single-level workload at its own recipe: the unit square, one
+128^2 level, h = 1/128, Helmholtz (I - cL) with c = 0.5 nu k, nu = 1e-3,
+k = 1/128, homogeneous Dirichlet, and the Neumann pressure Poisson system
+with a mean-zero right-hand side; both from the manufactured field
+sin(2 pi x) sin(2 pi y) plus seeded N(0, 1e-3^2) noise; V(2,2) cycles to a
+relative residual of 1e-12.  Both smoothers (the paper's weighted Jacobi
+and red-black).  FP64 solves follow the oracle's iterations (<= 1e-11, the
+same cycle count to one), mixed-precision solves reach the oracle's
+solution to <= 1e-9."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import mg  # noqa: E402
+from paper_2506_02663_amd import amg as A  # noqa: E402
+from paper_2506_02663_amd import workloads as W  # noqa: E402
+from tests.gpuhelp import from_dev, make_hier, relerr, to_dev, unit_level  # noqa: E402
+
+N = 128
+H0 = 1.0 / N
+C = 0.5 * 1e-3 * H0
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "rb"])
+@pytest.mark.parametrize("op,bc", [("helmholtz", "D"), ("poisson", "N")])
+def test_c1_recipe(op, bc, smoother):
+    lev = unit_level(N, 2, bc)
+    c = C if op == "helmholtz" else 0.0
+    f = lev.zeros()
+    f[lev.inner] = W.single_level_rhs((N, N), H0, op, c, seed=0)
+    sing = lev.singular_components(op)
+    x_or, st_or = mg.solve(lev, f, op, c, nu1=2, nu2=2, smoother=smoother, tol_rel=1e-12, max_cycles=200)
+    assert st_or["converged"]
+    H, L = make_hier(lev, op, c)
+    fd = to_dev(H, L, 0, f)
+    sm = A.SMOOTH_JACOBI if smoother == "jacobi" else A.SMOOTH_RB
+    want = lev.comp_mean(x_or, sing)
+    for prec, tol in ((A.FP64, 1e-11), (A.MIXED, 1e-9)):
+        x = torch.zeros_like(fd)
+        st = H.solve(L, x, fd, None, A.default_opts(precision=prec, smoother=sm, nu1=2, nu2=2, tol_rel=1e-12,
+                                                    max_cycles=200))
+        torch.cuda.synchronize()
+        assert st["status"] == 0 and st["converged"], st
+        err = relerr(lev.comp_mean(from_dev(H, L, 0, x, lev), sing), want, lev.mask)
+        assert err < tol, (prec, err)
+        if prec == A.FP64:
+            assert abs(st["cycles"] - st_or["cycles"]) <= 1, (st["cycles"], st_or["cycles"])
+            k = min(len(st["history"]), len(st_or["history"]))
+            assert np.allclose(st["history"][:k], st_or["history"][:k], rtol=1e-6,
+                               atol=1e-13 * st_or["history"][0])

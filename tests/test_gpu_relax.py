@@ -1,7 +1,7 @@
 """Parity of the over-relaxed red-black smoother (solve option omega_rb, the
 step entry point's omega for red-black) with the oracle: single sweeps in
 FP64 and FP32, whole V-cycles forward and adjoint, FP64 and mixed solves (the
-FP64 solve takes the oracle's cycles), the fused red-black form, and the
+FP64 solve takes the oracle's cycles), and the
 option's range check."""
 import numpy as np
 import pytest
@@ -78,29 +78,6 @@ def test_over_relaxed_solves(name):
         assert relerr(from_dev(H, L, 0, x, lev), x_or, lev.mask) < tol, prec
         if prec == A.FP64:
             assert s["cycles"] == st["cycles"]
-
-
-def test_over_relaxed_fused_sweep_matches_half_sweeps():
-    n = 32
-    outs = []
-    for fused in (1, 0):
-        H = A.Hierarchy(3, (n,) * 3, 1.0 / n, 1)
-        H.set_level_boxes(0, [((0,) * 3, (n - 1,) * 3)])
-        for d in range(3):
-            for s in (0, 1):
-                H.set_physical_bc(d, s, A.NEUMANN)
-        H.set_operator(A.POISSON, 0.0)
-        H.set_tuning(A.TUNE_FUSED_RB, fused)
-        H.finalize()
-        assert (H.level_info(0).fused_rb & 1) == fused
-        N, _ = H.depth_size(0, 0)
-        g = torch.Generator(device="cpu").manual_seed(5)
-        u = torch.randn(N, generator=g).float().cuda()
-        f = torch.randn(N, generator=g).float().cuda()
-        H.smooth(0, 0, u, f, torch.zeros_like(u), A.SMOOTH_RB, 3, W)
-        torch.cuda.synchronize()
-        outs.append(H.unpack(0, 0, u.double().cpu().numpy())[0])
-    assert np.abs(outs[0] - outs[1]).max() <= 2e-6 * np.abs(outs[1]).max()
 
 
 def test_relaxation_range_checked():
