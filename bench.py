@@ -57,6 +57,12 @@ def parse():
     p.add_argument("--bottom-cells", type=int, default=512,
                    help="single-level workloads: exact bottom solve once a depth has at most this many cells "
                         "(0: coarsen as far as the layout allows)")
+    p.add_argument("--no-fp64", action="store_true",
+                   help="single-level workloads: skip timing the plain FP64 solver on the same systems")
+    p.add_argument("--no-oracle-residual", action="store_true",
+                   help="single-level workloads: skip the oracle's residual of the timed solutions")
+    p.add_argument("--cpu-workers", type=int, default=0,
+                   help="worker processes of the CPU baseline (default: the host's cores, at most 16)")
     p.add_argument("--copy-probe", action="store_true",
                    help="first run a plain 256 MiB device copy three times (the reference kernel that "
                         "calibrates the HBM byte counters)")
@@ -115,31 +121,99 @@ def single_level_problems(dim, n, nu):
     return h, c, [("helmholtz", "D", helm), ("poisson", "N", pois)]
 
 
-def cpu_baseline(dim, n, nu, smoother, nu1=2, nu2=2, bottom_cells=0, omega_rb=None):
-    """The FP64 oracle on a bounded sample of the same workload (same recipe,
-    same smoother, relaxation, V-cycle and bottom size, smaller grid),
-    single-threaded, timed on the host."""
-    import numpy as np
+def host_info():
+    """CPU model and core counts of the host running the benchmark."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cores_available": avail}
 
+
+def floor_tol(op, f, tol):
+    """Absolute stopping term of a solve: at a relative tolerance of 1e-12 the
+    Neumann Poisson system stops at its FP64 rounding floor, 2e-12 ||f||."""
+    return 2e-12 * float(abs(f).max()) if op == "poisson" and tol <= 1e-12 else 0.0
+
+
+def _oracle_sample(dim, n, nu, smoother, nu1, nu2, bottom_cells, omega_rb, tol, keep):
+    """One run of the oracle on the sample (both systems); returns the DOF
+    solved and, if keep, the solutions as interior arrays."""
     from oracle import mg
     from oracle.level import Level
     h, c, probs = single_level_problems(dim, n, nu)
-    dof = 0
-    t0 = time.perf_counter()
+    dof, sols = 0, {}
     for op, bc, f in probs:
         lev = Level((n,) * dim, h, [((0,) * dim, (n - 1,) * dim)], {(d, s): bc for d in range(dim) for s in (0, 1)})
         fa = lev.zeros()
         fa[lev.inner] = f
-        x, st = mg.solve(lev, fa, op, c, tol_rel=1e-10, max_cycles=100, smoother=smoother, nu1=nu1, nu2=nu2,
-                         bottom_cells=bottom_cells, omega_rb=(omega_rb or {}).get(op, 1.0))
+        x, st = mg.solve(lev, fa, op, c, tol_rel=tol, tol_abs=floor_tol(op, f, tol), max_cycles=100,
+                         smoother=smoother, nu1=nu1, nu2=nu2, bottom_cells=bottom_cells,
+                         omega_rb=(omega_rb or {}).get(op, 1.0))
         assert st["converged"]
         dof += lev.ncells
+        if keep:
+            sols[op] = x[lev.inner].copy()
+    return dof, sols
+
+
+def cpu_baseline(dim, n, nu, smoother, nu1=2, nu2=2, bottom_cells=0, omega_rb=None, tol=1e-10, workers=None):
+    """The FP64 oracle on a bounded sample of the same workload (same recipe,
+    same smoother, relaxation, V-cycle, bottom size and tolerance, smaller
+    grid), timed on the host: one copy of the sample per worker process, all
+    running at once (each single-threaded numpy), value = all DOF solved /
+    wall time.  Runs before the GPU is touched.  Returns the baseline record
+    and the oracle's solutions of the sample (for the error of the GPU
+    solutions)."""
+    from concurrent.futures import ProcessPoolExecutor
+    info = host_info()
+    workers = workers or max(1, min(16, info["cores_available"] or 1))
+    args = (dim, n, nu, smoother, nu1, nu2, bottom_cells, omega_rb, tol)
+    t0 = time.perf_counter()
+    if workers == 1:
+        res = [_oracle_sample(*args, True)]
+    else:
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            futs = [ex.submit(_oracle_sample, *args, k == 0) for k in range(workers)]
+            res = [f.result() for f in futs]
     dt = time.perf_counter() - t0
-    return {"value": dof / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"{dim}D {n}^{dim}: Helmholtz (Dirichlet) + Neumann Poisson solves to 1e-10, "
+    dof = sum(r[0] for r in res)
+    base = {"value": dof / dt, "unit": "DOF/s", "cores": workers, "kind": "oracle",
+            "sample": f"{dim}D {n}^{dim}: Helmholtz (Dirichlet) + Neumann Poisson solves to {tol:g}, "
                       f"same recipe, smoother ({smoother}, omega_rb {omega_rb}), V({nu1},{nu2}) and bottom size "
-                      f"({bottom_cells}) "
-                      f"as the timed workload, {dt:.1f} s"}
+                      f"({bottom_cells}) as the timed workload; {workers} copies at once, one per worker process "
+                      f"(single-threaded numpy each), {dt:.1f} s wall",
+            **info}
+    return base, res[0][1]
+
+
+def oracle_residual(dim, n, op, bc, c, f, x):
+    """||f' - A x||_inf / ||f'||_inf with A the oracle's operator (numpy, FP64)
+    and f' the RHS after the oracle's solvability shift: how well the GPU
+    solution x (interior array) satisfies the discrete system, judged by an
+    implementation that shares no code with the GPU path."""
+    import numpy as np
+
+    from oracle import mg
+    from oracle.level import Level
+    lev = Level((n,) * dim, 1.0 / n, [((0,) * dim, (n - 1,) * dim)], {(d, s): bc for d in range(dim) for s in (0, 1)})
+    fa = lev.zeros()
+    fa[lev.inner] = f
+    sing = lev.singular_components(op)
+    if sing:
+        fa, _ = mg.solvability_shift(lev, fa, None, sing)
+    xa = lev.zeros()
+    xa[lev.inner] = x
+    r = fa - lev.apply(xa, op, c)
+    return float(np.abs(r[lev.mask]).max() / np.abs(fa[lev.mask]).max())
 
 
 def main():
@@ -152,21 +226,23 @@ def main():
     if args.workload == "c3":
         dim, n, nu = 3, args.n or 256, 1e-4
         sample = (3, 64, 1e-4)
+        tol = 1e-10  # the metric's tolerance
     elif args.workload == "c1":
         dim, n, nu = 2, args.n or 128, 1e-3
         sample = (2, 64, 1e-3)
+        tol = 1e-12  # the 2D single-level configuration's own tolerance
     elif args.workload == "c2":
         return bench_amr(args)
     else:
         return bench_batched(args)
 
     nu1, nu2 = map(int, (args.nu or ("1,3" if dim == 3 else "2,2")).split(","))
-    base = None
+    base, oracle_sols = None, None
     if not args.no_cpu_baseline:
-        # before the GPU is touched: single-threaded numpy
+        # before the GPU is touched: worker processes of single-threaded numpy
         w_rb = dict(zip(("helmholtz", "poisson"), map(float, args.omega_rb.split(","))))
-        base = cpu_baseline(*sample, args.smoother, nu1, nu2, args.bottom_cells,
-                            w_rb if args.smoother == "rb" else None)
+        base, oracle_sols = cpu_baseline(*sample, args.smoother, nu1, nu2, args.bottom_cells,
+                                         w_rb if args.smoother == "rb" else None, tol, args.cpu_workers)
 
     import torch
     if args.copy_probe:
@@ -178,11 +254,16 @@ def main():
     prec = A.MIXED if args.precision == "mixed" else A.FP64
     sm = A.SMOOTH_JACOBI if args.smoother == "jacobi" else A.SMOOTH_RB
     w_rb = dict(zip(("helmholtz", "poisson"), map(float, args.omega_rb.split(","))))
-    opts = {op: A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100, nu1=nu1, nu2=nu2,
-                               use_graph=0 if args.no_graph else 1, omega_rb=w_rb[op])
+    # the 2D workload's 1e-12 lies at the FP64 rounding floor of its Neumann
+    # Poisson system (the residual of the exact solution rounds to 1-1.6e-12
+    # ||f|| at its largest cell): that solve stops at the floor, 2e-12 ||f||
+    tol_abs = {op: floor_tol(op, f, tol) for op, _, f in probs}
+    opts = {op: A.default_opts(precision=prec, smoother=sm, tol_rel=tol, tol_abs=tol_abs[op], max_cycles=100,
+                               nu1=nu1, nu2=nu2, use_graph=0 if args.no_graph else 1, omega_rb=w_rb[op])
             for op in ("helmholtz", "poisson")}
     systems = []
     march = None
+    rhs = {op: (bc, f) for op, bc, f in probs}
     for op, bc, f in probs:
         H = A.Hierarchy(dim, (n,) * dim, h, 1)
         H.set_level_boxes(0, [((0,) * dim, (n - 1,) * dim)])
@@ -211,13 +292,13 @@ def main():
 
     cycles = {}
 
-    def step():
+    def step(op_opts=opts, cyc=cycles):
         for op, H, x, fd in systems:
             x.zero_()
-            st = H.solve(0, x, fd, None, opts[op])
+            st = H.solve(0, x, fd, None, op_opts[op])
             if st["status"] != 0 or not st["converged"]:
                 raise RuntimeError(f"{op} solve did not converge: {st}")
-            cycles[op] = st["cycles"]
+            cyc[op] = st["cycles"]
 
     for _ in range(args.warmup):
         step()
@@ -259,7 +340,7 @@ def main():
         "dtype": "f32-in-f64" if prec == A.MIXED else "f64",
         "data": "synthetic",
         "config": {"workload": f"{dim}D single level {n}^{dim}, Helmholtz (Dirichlet, nu={nu}) + Neumann Poisson",
-                   "cells": n ** dim, "dof_per_step": dof_step, "tol_rel": 1e-10,
+                   "cells": n ** dim, "dof_per_step": dof_step, "tol_rel": tol,
                    "cycles": cycles, "smoother": args.smoother, "precision": args.precision,
                    "graph": not args.no_graph, "vcycle": f"V({nu1},{nu2})",
                    "omega_rb": w_rb if args.smoother == "rb" else None, "march": march, "bottom_cells": args.bottom_cells,
@@ -313,9 +394,80 @@ def main():
                            "avg_us_back_to_back": bavg_s * 1e6, "launches_back_to_back": bcnt}
         out["kernel_ms_per_step"] = {k: v[1] / args.steps for k, v in kinds.items()}
         out["ms_per_step_event_pass"] = timed_ms
+    # accuracy of the timed solutions: the oracle's operator applied to them
+    # (an implementation sharing no code with the GPU path)
+    if not args.no_oracle_residual:
+        res = {}
+        for op, H, x, fd in systems:
+            bc, f = rhs[op]
+            xs = H.unpack(0, 0, x.cpu().numpy())[0]
+            res[op] = oracle_residual(dim, n, op, bc, c, f, xs)
+        out["oracle_residual_of_timed_solution"] = res
+    # accuracy against the oracle's solution: the sample the CPU baseline
+    # solved, solved again on the GPU with the timed configuration
+    if oracle_sols is not None:
+        out["err_vs_oracle"] = sample_error(A, sample, sm, nu1, nu2, args.bottom_cells, w_rb, prec, tol, oracle_sols)
+    # the plain FP64 solver on the same systems: the same V-cycle, smoother,
+    # factors and tolerance in FP64, every kernel launched directly (no
+    # graph); and the same with graph replay
+    if prec == A.MIXED and not args.no_fp64:
+        fp = {}
+        for graph in (0, 1):
+            o64 = {op: A.default_opts(precision=A.FP64, smoother=sm, tol_rel=tol, tol_abs=tol_abs[op], max_cycles=100,
+                                      nu1=nu1, nu2=nu2, use_graph=graph, omega_rb=w_rb[op])
+                   for op in ("helmholtz", "poisson")}
+            cyc64 = {}
+            for _ in range(args.warmup):
+                step(o64, cyc64)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            for _ in range(args.steps):
+                step(o64, cyc64)
+            torch.cuda.synchronize()
+            fp["ms_per_step_graph" if graph else "ms_per_step_plain"] = (time.perf_counter() - t2) * 1e3 / args.steps
+            fp["cycles"] = cyc64
+        fp["value_plain"] = dof_step / fp["ms_per_step_plain"] * 1e3
+        fp["mixed_speedup_vs_plain"] = fp["ms_per_step_plain"] / ms
+        fp["mixed_speedup_vs_fp64_graph"] = fp["ms_per_step_graph"] / ms
+        out["fp64"] = fp
     if base is not None:
         out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
+
+
+def sample_error(A, sample, sm, nu1, nu2, bottom_cells, w_rb, prec, tol, oracle_sols):
+    """Max relative difference between the GPU solutions of the CPU
+    baseline's sample (same configuration as the timed solves) and the
+    oracle's (both mean-free on the pure-Neumann system)."""
+    import numpy as np
+    import torch
+    dim, n, nu = sample
+    h, c, probs = single_level_problems(dim, n, nu)
+    err = {}
+    for op, bc, f in probs:
+        H = A.Hierarchy(dim, (n,) * dim, h, 1)
+        H.set_level_boxes(0, [((0,) * dim, (n - 1,) * dim)])
+        for d in range(dim):
+            for s in (0, 1):
+                H.set_physical_bc(d, s, A.DIRICHLET if bc == "D" else A.NEUMANN)
+        H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c)
+        if bottom_cells:
+            H.set_bottom_cells(bottom_cells)
+        H.finalize()
+        fd = torch.tensor(H.pack(0, 0, lambda i, b: f), device="cuda")
+        x = torch.zeros_like(fd)
+        st = H.solve(0, x, fd, None, A.default_opts(precision=prec, smoother=sm, tol_rel=tol,
+                                                    tol_abs=floor_tol(op, f, tol), max_cycles=100,
+                                                    nu1=nu1, nu2=nu2, omega_rb=w_rb[op]))
+        if st["status"] != 0:
+            raise RuntimeError(f"sample {op} solve failed: {st}")
+        got = H.unpack(0, 0, x.cpu().numpy())[0]
+        want = oracle_sols[op]
+        if op == "poisson":
+            got, want = got - got.mean(), want - want.mean()
+        err[op] = float(np.abs(got - want).max() / np.abs(want).max())
+    err["sample"] = f"{dim}D {n}^{dim}, the CPU baseline's sample"
+    return err
 
 
 def bench_amr(args):

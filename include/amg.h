@@ -456,6 +456,45 @@ int amg_project(amg_hier* hw, amg_hier* hp, int lev_lo, int lev_hi, double* cons
                 double* const* phi, double* const* u, const amg_solve_opts* opts, amg_solve_stats* stats,
                 void* stream);
 
+/* ---- transposes of G, D and the projection (not in the paper) ---------------
+ * The adjoint that carries a loss on the projected velocity back to the
+ * velocity before projection.  Each is the transpose of the homogeneous (zero
+ * boundary data) linear map above, taken between the valid cells of levels
+ * lev_lo..lev_hi (one level, or composite from level 0) in the plain inner
+ * product sum over valid cells of a_i b_i: the forward maps read no covered
+ * input cell (they average down first) and their covered outputs are copies.
+ * G_d of eq. discreteOps a is antisymmetric, so its transpose on a level's
+ * cells is -G_d of the adjoint extended by zero, plus the weights the stencil
+ * puts on ghosts sent back through the fills (eqs. velBCHomoDiri5th,
+ * Neumann5), exchange copies and AMRCFI; the composite divergence's
+ * refluxing (COH-3, face averages of eq. cell2face) is transposed onto the
+ * values and ghosts its face averages read, and the average-down of the
+ * input onto the children of covered cells.  Inputs: their covered cells
+ * and ghosts are set to 0 by the call.  Outputs: 0 on covered cells and on
+ * ghosts.  Buffers are packed FP64 level buffers indexed as in
+ * amg_gradient / amg_divergence; outputs must not alias inputs.  Errors:
+ * AMG_EINVAL (range, null buffer), AMG_EUNSUPPORTED (composite not from
+ * level 0). */
+
+/* out[l] = sum_d G_d^T mu[l*dim+d], G with the hierarchy's fill. */
+int amg_gradient_transpose(amg_hier* h, int lev_lo, int lev_hi, double* const* mu, double* const* out, void* stream);
+
+/* out[l*dim+d] = G_d^T lam[l], the transpose of D w = sum_d G_d w_d with the
+ * hierarchy's fill for every component. */
+int amg_divergence_transpose(amg_hier* h, int lev_lo, int lev_hi, double* const* lam, double* const* out,
+                             void* stream);
+
+/* wbar = P^T ubar = ubar - D^T L^-T G^T ubar for the projection of
+ * amg_project (hw, hp as there): G^T on hp, the adjoint pure-Neumann solve of
+ * amg_solve_adjoint(_composite) on hp (it holds the transposes of the
+ * solvability shift and the mean removal; opts, stats as there), D^T on hw.
+ * lam[l]: initial guess in, the adjoint potential out.  ubar[l*dim+d]: its
+ * covered cells and ghosts are set to 0; wbar may alias ubar (then it is
+ * updated in place), covered cells of wbar are 0.  Uses the work buffers of
+ * both hierarchies.  Errors as amg_project and amg_solve_adjoint. */
+int amg_project_adjoint(amg_hier* hw, amg_hier* hp, int lev_lo, int lev_hi, double* const* ubar, double* const* lam,
+                        double* const* wbar, const amg_solve_opts* opts, amg_solve_stats* stats, void* stream);
+
 /* Changes the Helmholtz coefficient c (> 0) of a finalized hierarchy: the
  * bottom inverses are recomputed on the host and captured graphs dropped.
  * Not on the hot path; AMG_EINVAL if the operator is not Helmholtz. */

@@ -112,6 +112,10 @@ def lib():
         L.amg_composite_laplacian.argtypes = [vp, i32, pp, pp, pp, vp]
         L.amg_time_sweep.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, C.POINTER(C.c_double), vp]
         L.amg_autotune.argtypes = [vp, i32, i32, i32, i32, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.amg_gradient_transpose.argtypes = [vp, i32, i32, pp, pp, vp]
+        L.amg_divergence_transpose.argtypes = [vp, i32, i32, pp, pp, vp]
+        L.amg_project_adjoint.argtypes = [vp, vp, i32, i32, pp, pp, pp, C.POINTER(SolveOpts), C.POINTER(SolveStats),
+                                          vp]
         _lib = L
     return _lib
 
@@ -564,6 +568,37 @@ class Hierarchy:
                         wb[(lev_lo + i) * self.dim + d] = t.data_ptr()
         self._check(lib().amg_divergence(self.h, lev_lo, lev_lo + n - 1, self._comp_ptrs(lev_lo, ws), wb,
                                          self._lev_ptrs(lev_lo, outs), _stream()))
+
+    def gradient_transpose(self, mus, outs, lev_lo=0):
+        """outs[i] = sum_d G_d^T mus[i][d] (mus' covered cells and ghosts are
+        set to 0)."""
+        n = len(outs)
+        self._check(lib().amg_gradient_transpose(self.h, lev_lo, lev_lo + n - 1, self._comp_ptrs(lev_lo, mus),
+                                                 self._lev_ptrs(lev_lo, outs), _stream()))
+
+    def divergence_transpose(self, lams, outs, lev_lo=0):
+        """outs[i][d] = G_d^T lams[i] (lams' covered cells and ghosts are set
+        to 0)."""
+        n = len(lams)
+        self._check(lib().amg_divergence_transpose(self.h, lev_lo, lev_lo + n - 1, self._lev_ptrs(lev_lo, lams),
+                                                   self._comp_ptrs(lev_lo, outs), _stream()))
+
+
+def project_adjoint(Hw, Hp, ubars, lams, wbars, opts=None, lev_lo=0):
+    """wbar = P^T ubar (see amg_project_adjoint); ubars[i][d] (covered cells
+    and ghosts set to 0), lams[i] initial guess in, adjoint potential out;
+    wbars may be ubars."""
+    n = len(lams)
+    o = opts or default_opts()
+    st = SolveStats()
+    rc = lib().amg_project_adjoint(Hw.h, Hp.h, lev_lo, lev_lo + n - 1, Hp._comp_ptrs(lev_lo, ubars),
+                                   Hp._lev_ptrs(lev_lo, lams), Hw._comp_ptrs(lev_lo, wbars), C.byref(o), C.byref(st),
+                                   _stream())
+    if rc and rc != ENOTCONVERGED:
+        Hp._check(rc)
+    out = st.as_dict()
+    out["status"] = rc
+    return out
 
 
 def project(Hw, Hp, ws, phis, us, wbs=None, opts=None, lev_lo=0):

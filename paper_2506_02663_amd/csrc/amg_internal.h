@@ -61,7 +61,8 @@ struct ChunkD {            // up to 64 consecutive ghost columns of one face
   int32_t box;
   uint8_t kind1, kind2;
   uint8_t cf;              // 1: the face is not on the physical boundary
-  uint8_t pad[5];
+  uint8_t dir;             // direction d of the face normal
+  uint8_t pad[4];
 };
 
 // Up to 256 cells of the band of one box face that the transposed ghost
@@ -133,6 +134,18 @@ struct Composite {  // tables of level l against level l-1 (l >= 1)
   std::vector<int64_t> rfxTc_elem, rfxTf_elem;
   std::vector<int32_t> rfxTc_ptr, rfxTf_ptr, rfxTc_src, rfxTf_src;  // src: index into rfx_cell
   std::vector<double> rfxTc_coef, rfxTf_coef;
+  // refluxing of the divergence (face averages of eq. cell2face, first row),
+  // transposed like the above, one table per face direction d (the
+  // divergence refluxes component d through the faces normal to d)
+  struct GatherT {
+    std::vector<int64_t> elem;
+    std::vector<int32_t> ptr, src;
+    std::vector<double> coef;
+    int64_t* d_elem = nullptr;
+    int32_t *d_ptr = nullptr, *d_src = nullptr;
+    double* d_coef = nullptr;
+  };
+  GatherT rfxVc[3], rfxVf[3];
   // device
   double* d_w = nullptr;
   int64_t* d_cfi_dst = nullptr;

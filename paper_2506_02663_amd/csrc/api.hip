@@ -439,6 +439,10 @@ void free_level(amg::Level& L) {
                   (void*)X.d_rfxTc_elem, (void*)X.d_rfxTc_ptr, (void*)X.d_rfxTc_src, (void*)X.d_rfxTc_coef,
                   (void*)X.d_rfxTf_elem, (void*)X.d_rfxTf_ptr, (void*)X.d_rfxTf_src, (void*)X.d_rfxTf_coef})
     if (p) (void)hipFree(p);
+  for (int d = 0; d < 3; ++d)
+    for (const Composite::GatherT* t : {&X.rfxVc[d], &X.rfxVf[d]})
+      for (void* p : {(void*)t->d_elem, (void*)t->d_ptr, (void*)t->d_src, (void*)t->d_coef})
+        if (p) (void)hipFree(p);
   for (auto& D : L.depths)
     for (void* p : {(void*)D.d_exT_elem, (void*)D.d_exT_slot, (void*)D.d_exT_ptr})
       if (p) (void)hipFree(p);
@@ -910,6 +914,13 @@ int amg_finalize(amg_hier* H) {
     TRY(upload(H, &X.d_rfxTf_ptr, X.rfxTf_ptr));
     TRY(upload(H, &X.d_rfxTf_src, X.rfxTf_src));
     TRY(upload(H, &X.d_rfxTf_coef, X.rfxTf_coef));
+    for (int d = 0; d < H->dim; ++d)
+      for (Composite::GatherT* t : {&X.rfxVc[d], &X.rfxVf[d]}) {
+        TRY(upload(H, &t->d_elem, t->elem));
+        TRY(upload(H, &t->d_ptr, t->ptr));
+        TRY(upload(H, &t->d_src, t->src));
+        TRY(upload(H, &t->d_coef, t->coef));
+      }
     TRY(zalloc(H, &L.mu, X.cfi_dst.size()));
   }
   for (auto& L : H->levels) TRY(upload(H, &L.d_face_valid, L.face_valid));
@@ -1798,14 +1809,8 @@ int amg_divergence(amg_hier* H, int lev_lo, int lev_hi, double* const* w, const 
   return divergence_impl(H, lev_lo, lev_hi, w, face_data, out, stream_of(H, stream));
 }
 
-int amg_project(amg_hier* Hw, amg_hier* Hp, int lev_lo, int lev_hi, double* const* w, const double* const* wb,
-                double* const* phi, double* const* u, const amg_solve_opts* opts, amg_solve_stats* stats,
-                void* stream) {
-  TRY(check_range(Hw, lev_lo, lev_hi));
-  TRY(check_range(Hp, lev_lo, lev_hi));
-  if (!w || !phi || !u) return fail(Hp, AMG_EINVAL, "bad arguments");
-  if (Hp->op != AMG_POISSON) return fail(Hp, AMG_EINVAL, "the potential's hierarchy must hold the Poisson operator");
-  // the two hierarchies must share the packed layout of every level
+// the two hierarchies of a projection must share the packed layout of every level
+static int same_layout(amg_hier* Hw, amg_hier* Hp, int lev_lo, int lev_hi) {
   if (Hw->dim != Hp->dim || Hw->nlevels != Hp->nlevels) return fail(Hp, AMG_EINVAL, "hierarchies differ");
   for (int l = lev_lo; l <= lev_hi; ++l) {
     const Depth& A0 = Hw->levels[l].depths[0];
@@ -1816,6 +1821,17 @@ int amg_project(amg_hier* Hw, amg_hier* Hp, int lev_lo, int lev_hi, double* cons
           memcmp(A0.boxes[b].hi, B0.boxes[b].hi, sizeof(int) * 3))
         return fail(Hp, AMG_EINVAL, "layouts differ");
   }
+  return AMG_OK;
+}
+
+int amg_project(amg_hier* Hw, amg_hier* Hp, int lev_lo, int lev_hi, double* const* w, const double* const* wb,
+                double* const* phi, double* const* u, const amg_solve_opts* opts, amg_solve_stats* stats,
+                void* stream) {
+  TRY(check_range(Hw, lev_lo, lev_hi));
+  TRY(check_range(Hp, lev_lo, lev_hi));
+  if (!w || !phi || !u) return fail(Hp, AMG_EINVAL, "bad arguments");
+  if (Hp->op != AMG_POISSON) return fail(Hp, AMG_EINVAL, "the potential's hierarchy must hold the Poisson operator");
+  TRY(same_layout(Hw, Hp, lev_lo, lev_hi));
   hipStream_t st = stream_of(Hp, stream);
   std::vector<double*> div(lev_hi + 1, nullptr);
   for (int l = lev_lo; l <= lev_hi; ++l) div[l] = Hw->levels[l].fsh;
@@ -1832,6 +1848,179 @@ int amg_project(amg_hier* Hw, amg_hier* Hp, int lev_lo, int lev_hi, double* cons
     rc = level_solve(Hp, lev_lo, phi[lev_lo], f[lev_lo], nullptr, o, stats, st, false);
   if (rc != AMG_OK) return rc;
   return gradient_impl(Hp, lev_lo, lev_hi, phi, nullptr, u, w, st);
+}
+
+// ---- transposes of G, D and the projection -------------------------------
+// Each is the homogeneous map between the valid cells of levels lo..hi (one
+// level, or composite from level 0): its input's covered cells and ghosts
+// are set to 0 (they do not enter the forward map), the output is 0 on
+// covered cells.  Ghost adjoints of the gradient stencil go to the slots of
+// the level's scratch array A64 (negated), refluxing (divergence) adds its
+// share there too, and the scatter kernels send them on: fills (band),
+// exchange copies, AMRCFI onto the level below.
+
+// the input of a transpose: valid cells only, ghosts 0
+static void clear_input(amg_hier* H, int l, int hi, double* a, hipStream_t st) {
+  if (l < hi) launch_zero_covered(H->levels[l + 1].cmp, a, st);
+  launch_fill_zero<double>(H->levels[l].depths[0], a, st);
+}
+
+// the ghost adjoints held (negated) in each level's A64 onto the cells of
+// out: interior share, fills, exchange copies, AMRCFI onto the level below
+static void scatter_slots(amg_hier* H, int lo, int hi, double* const* out, int stride, hipStream_t st) {
+  const int dim = H->dim;
+  for (int l = hi; l >= lo; --l) {
+    Level& L = H->levels[l];
+    Depth& D = L.depths[0];
+    double* o = out[l * stride];
+    launch_sub_array(dim, D, L.A64, o, st);
+    launch_band_ab(dim, D, o, L.A64, o, 0.0, st);
+    launch_exch_T(D, L.A64, o, st);
+    if (l > lo) launch_cfi_T(dim, L.cmp, o, L.A64, 0.0, L.mu, out[(l - 1) * stride], st);
+  }
+}
+
+// the average-down of the forward input, transposed: covered adjoints to
+// the children in equal parts, coarse to fine
+static void pass_down_all(amg_hier* H, int hi, double* const* out, int stride, hipStream_t st) {
+  const double down = 1.0 / (1 << H->dim);
+  for (int l = 1; l <= hi; ++l) {
+    launch_pass_down(H->levels[l].cmp, out[(l - 1) * stride], out[l * stride], down, st);
+    launch_zero_covered(H->levels[l].cmp, out[(l - 1) * stride], st);
+  }
+}
+
+static int gradient_T_impl(amg_hier* H, int lo, int hi, double* const* mu, double* const* out, hipStream_t st) {
+  const int dim = H->dim;
+  for (int l = lo; l <= hi; ++l) {
+    if (!out[l]) return fail(H, AMG_EINVAL, "null output");
+    for (int d = 0; d < dim; ++d)
+      if (!mu[l * dim + d]) return fail(H, AMG_EINVAL, "null component");
+  }
+  for (int l = lo; l <= hi; ++l) {
+    Level& L = H->levels[l];
+    CPtrs m{};
+    for (int d = 0; d < dim; ++d) {
+      clear_input(H, l, hi, mu[l * dim + d], st);
+      m.p[d] = mu[l * dim + d];
+    }
+    // G_d is antisymmetric: its transpose on the cells is -G_d of the
+    // zero-extended adjoint
+    launch_div(dim, L.depths[0], m, out[l], st, -1.0);
+    launch_zero<double>(L.A64, L.depths[0].nstored, st);
+    launch_gslot(L.depths[0], m, -1, L.A64, st);
+  }
+  scatter_slots(H, lo, hi, out, 1, st);
+  if (hi > lo) pass_down_all(H, hi, out, 1, st);
+  for (int l = lo; l <= hi; ++l) launch_fill_zero<double>(H->levels[l].depths[0], out[l], st);
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+static int divergence_T_impl(amg_hier* H, int lo, int hi, double* const* lam, double* const* out, hipStream_t st) {
+  const int dim = H->dim;
+  for (int l = lo; l <= hi; ++l) {
+    if (!lam[l]) return fail(H, AMG_EINVAL, "null lam");
+    for (int d = 0; d < dim; ++d)
+      if (!out[l * dim + d]) return fail(H, AMG_EINVAL, "null component");
+  }
+  for (int l = lo; l <= hi; ++l) {
+    clear_input(H, l, hi, lam[l], st);
+    DPtrs g{};
+    for (int d = 0; d < dim; ++d) g.p[d] = out[l * dim + d];
+    launch_grad(dim, H->levels[l].depths[0], lam[l], g, CPtrs{}, false, st, -1.0);
+  }
+  for (int d = 0; d < dim; ++d) {
+    for (int l = lo; l <= hi; ++l)
+      launch_zero<double>(H->levels[l].A64, H->levels[l].depths[0].nstored, st);
+    for (int l = lo + 1; l <= hi; ++l)
+      launch_rfxV_T(H->levels[l].cmp, d, lam[l - 1], -1.0, H->levels[l - 1].A64, H->levels[l].A64, st);
+    for (int l = lo; l <= hi; ++l) {
+      CPtrs m{};
+      for (int e = 0; e < dim; ++e) m.p[e] = lam[l];
+      launch_gslot(H->levels[l].depths[0], m, d, H->levels[l].A64, st);
+    }
+    scatter_slots(H, lo, hi, out + d, dim, st);
+    if (hi > lo) pass_down_all(H, hi, out + d, dim, st);
+  }
+  for (int l = lo; l <= hi; ++l)
+    for (int d = 0; d < dim; ++d) launch_fill_zero<double>(H->levels[l].depths[0], out[l * dim + d], st);
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_gradient_transpose(amg_hier* H, int lev_lo, int lev_hi, double* const* mu, double* const* out,
+                           void* stream) {
+  TRY(check_range(H, lev_lo, lev_hi));
+  if (!mu || !out) return fail(H, AMG_EINVAL, "bad arguments");
+  return gradient_T_impl(H, lev_lo, lev_hi, mu, out, stream_of(H, stream));
+}
+
+int amg_divergence_transpose(amg_hier* H, int lev_lo, int lev_hi, double* const* lam, double* const* out,
+                             void* stream) {
+  TRY(check_range(H, lev_lo, lev_hi));
+  if (!lam || !out) return fail(H, AMG_EINVAL, "bad arguments");
+  return divergence_T_impl(H, lev_lo, lev_hi, lam, out, stream_of(H, stream));
+}
+
+int amg_project_adjoint(amg_hier* Hw, amg_hier* Hp, int lev_lo, int lev_hi, double* const* ubar, double* const* lam,
+                        double* const* wbar, const amg_solve_opts* opts, amg_solve_stats* stats, void* stream) {
+  TRY(check_range(Hw, lev_lo, lev_hi));
+  TRY(check_range(Hp, lev_lo, lev_hi));
+  if (!ubar || !lam || !wbar) return fail(Hp, AMG_EINVAL, "bad arguments");
+  TRY(same_layout(Hw, Hp, lev_lo, lev_hi));
+  const int dim = Hp->dim;
+  for (int l = lev_lo; l <= lev_hi; ++l) {
+    if (!lam[l]) return fail(Hp, AMG_EINVAL, "null lam");
+    for (int d = 0; d < dim; ++d)
+      if (!ubar[l * dim + d] || !wbar[l * dim + d]) return fail(Hp, AMG_EINVAL, "null component");
+  }
+  hipStream_t st = stream_of(Hp, stream);
+  amg_hier* H = Hp;  // the hierarchy that reports device errors
+  // g = G^T ubar (the potential's fill), into the Poisson hierarchy's fsh
+  std::vector<double*> g(lev_hi + 1, nullptr);
+  for (int l = lev_lo; l <= lev_hi; ++l) g[l] = Hp->levels[l].fsh;
+  TRY(gradient_T_impl(Hp, lev_lo, lev_hi, ubar, g.data(), st));
+  // lam = L^-T g: the adjoint of the pure-Neumann solve (transposes of its
+  // solvability shift and mean removal included)
+  amg_solve_opts o;
+  amg_default_opts(&o);
+  if (opts) o = *opts;
+  TRY(check_opts(Hp, o));
+  int rc;
+  if (lev_hi > lev_lo) {
+    std::vector<const double*> gc(g.begin(), g.end());
+    rc = amg_solve_adjoint_composite(Hp, lev_hi, lam, gc.data(), &o, stats, st);
+  } else {
+    rc = amg_solve_adjoint(Hp, lev_lo, lam[lev_lo], g[lev_lo], &o, stats, st);
+  }
+  if (rc != AMG_OK) return rc;
+  // wbar = ubar - D^T lam (the velocity's fill); D^T lam into the velocity
+  // hierarchy's depth-0 work buffers
+  std::vector<double*> dt((lev_hi + 1) * dim, nullptr), lamv(lev_hi + 1, nullptr);
+  for (int l = lev_lo; l <= lev_hi; ++l) {
+    Depth& D = Hw->levels[l].depths[0];
+    double* bufs[3] = {D.e64, D.f64, D.t64};
+    for (int d = 0; d < dim; ++d) dt[l * dim + d] = bufs[d];
+    // the solve leaves lam's ghosts and covered cells 0; a copy keeps the
+    // caller's lam as the solve returned it
+    lamv[l] = Hw->levels[l].fsh;
+    HIPCHK(hipMemcpyAsync(lamv[l], lam[l], D.nstored * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  rc = divergence_T_impl(Hw, lev_lo, lev_hi, lamv.data(), dt.data(), st);
+  if (rc != AMG_OK) return fail(Hp, rc, Hw->err);
+  for (int l = lev_lo; l <= lev_hi; ++l) {
+    Depth& D = Hw->levels[l].depths[0];
+    for (int d = 0; d < dim; ++d) {
+      double* wb = wbar[l * dim + d];
+      if (wb != ubar[l * dim + d])
+        HIPCHK(hipMemcpyAsync(wb, ubar[l * dim + d], D.nstored * sizeof(double), hipMemcpyDeviceToDevice, st));
+      launch_sub_array(dim, D, dt[l * dim + d], wb, st);
+      if (l < lev_hi) launch_zero_covered(Hw->levels[l + 1].cmp, wb, st);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
 }
 
 int amg_time_sweep(amg_hier* H, int level, int dtype, int smoother, int n, void* u, const void* f, void* tmp,

@@ -328,6 +328,29 @@ int build_composite(amg_hier* H, int l, std::string& err) {
     };
     build(tc, X.rfxTc_elem, X.rfxTc_ptr, X.rfxTc_src, X.rfxTc_coef);
     build(tf, X.rfxTf_elem, X.rfxTf_ptr, X.rfxTf_src, X.rfxTf_coef);
+    // refluxing of the divergence: the correction at coarse cell i is
+    // (sg / hc) sum over its faces normal to d of [mean_t Ff_t - Fc], face
+    // averages (-v[+2] + 7 v[+1] + 7 v[0] - v[-1]) / 12 along n
+    const int vw[4] = {-1, 7, 7, -1};  // offsets -1, 0, 1, 2 along n
+    for (int d = 0; d < dim; ++d) {
+      std::vector<std::pair<int64_t, std::pair<int32_t, double>>> vc, vf;
+      for (size_t i = 0; i + 1 < X.rfx_ptr.size(); ++i) {
+        const int64_t c = X.rfx_cell[i];
+        for (int k = X.rfx_ptr[i]; k < X.rfx_ptr[i + 1]; ++k) {
+          const RfxFaceD& F = X.rfx_face[k];
+          if (F.d != d) continue;
+          for (int o = 0; o < 4; ++o)
+            vc.push_back({c + (int64_t)(o - 1) * F.csn, {(int32_t)i, -F.sg * vw[o] / (12.0 * hc)}});
+          for (int t = 0; t < (1 << (dim - 1)); ++t) {
+            const int64_t e = F.fe + ((t & 1) ? F.ft0 : 0) + ((t & 2) ? F.ft1 : 0);
+            for (int o = 0; o < 4; ++o)
+              vf.push_back({e + (int64_t)(o - 2) * F.fsn, {(int32_t)i, F.sg * vw[o] / (12.0 * hc * nf)}});
+          }
+        }
+      }
+      build(vc, X.rfxVc[d].elem, X.rfxVc[d].ptr, X.rfxVc[d].src, X.rfxVc[d].coef);
+      build(vf, X.rfxVf[d].elem, X.rfxVf[d].ptr, X.rfxVf[d].src, X.rfxVf[d].coef);
+    }
   }
 
   // ---- prolongation of a level-(l-1) correction onto level l ----

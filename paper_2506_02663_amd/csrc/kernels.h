@@ -22,9 +22,18 @@ struct DPtrs {
 struct CPtrs {
   const double* p[3];
 };
-// g[d] = G_d u, or w[d] - G_d u if sub
-void launch_grad(int dim, const Depth& D, const double* u, DPtrs g, CPtrs w, bool sub, hipStream_t st);
-void launch_div(int dim, const Depth& D, CPtrs w, double* out, hipStream_t st);
+// g[d] = scale G_d u, or w[d] - scale G_d u if sub
+void launch_grad(int dim, const Depth& D, const double* u, DPtrs g, CPtrs w, bool sub, hipStream_t st,
+                 double scale = 1.0);
+// out = scale sum_d G_d w[d]
+void launch_div(int dim, const Depth& D, CPtrs w, double* out, hipStream_t st, double scale = 1.0);
+// transposes of G and D: ghost-slot adjoints of the gradient stencil (ab
+// -= weights times mu; mu.p[d] read along d; dir >= 0: faces normal to dir)
+void launch_gslot(const Depth& D, CPtrs mu, int dir, double* ab, hipStream_t st);
+// refluxing of the divergence (component d), transposed: abc / abf (levels
+// l-1 / l) += lscale * d(correction) / d(element) * lam_c[refluxed cell]
+void launch_rfxV_T(const Composite& X, int d, const double* lam_c, double lscale, double* abc, double* abf,
+                   hipStream_t st);
 void launch_reflux_div(int dim, const Composite& X, CPtrs wc, CPtrs wf, double* div, double hc, hipStream_t st);
 template <typename T>
 void launch_residual(int dim, const Depth& D, bool all, const T* u, const T* f, T* r, T alpha, T beta, double* part,

@@ -1604,6 +1604,30 @@ __global__ void __launch_bounds__(256) k_div(const TileD* __restrict__ tiles, in
   }
 }
 
+// Ghost-slot adjoints of the gradient stencil (the transposes of G and D):
+// along the normal d of a face, the row-end cell e0 reads its first ghost
+// with the weight a(sg) = 8 sg / 12h and its second with a(2 sg) = -sg / 12h,
+// the next cell e1 reads the first ghost with a(2 sg) (sg = +1 on a high
+// face, -1 on a low one; eq. discreteOps a).  ab[slot] -= sum of the weights
+// times mu[cell] (ab holds the negated adjoint, the convention of the
+// scatter kernels k_band_ab, k_exch_T and k_cfi_T, which subtract it).
+// mu.p[d]: the array read along d; dir >= 0: faces normal to dir only.  One
+// wavefront per chunk of ghost columns; every slot belongs to one chunk.
+__global__ void __launch_bounds__(256) k_gslot(const ChunkD* __restrict__ chunks, int nchunks, CPtrs mu, int dir,
+                                               double* __restrict__ ab, double inv12h) {
+  const int ci = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (ci >= nchunks) return;
+  const ChunkD ch = chunks[ci];
+  if (lane >= ch.count || (dir >= 0 && ch.dir != dir)) return;
+  const double* __restrict__ m = mu.p[ch.dir];
+  const int64_t g1 = ch.dst + (int64_t)lane * ch.cstride, ns = ch.nstride;
+  const double sg = ns > 0 ? 1.0 : -1.0;
+  const double m0 = m[g1 - ns], m1 = m[g1 - 2 * ns];
+  ab[g1] -= sg * (8.0 * m0 - m1) * inv12h;
+  ab[g1 + ns] -= -sg * m0 * inv12h;
+}
+
 // per-tile sum of a * b over the interior (dot products)
 template <int DIM>
 __global__ void __launch_bounds__(256) k_tile_dot(const TileD* __restrict__ tiles, int ntiles,
@@ -2145,16 +2169,35 @@ void launch_band(int dim, const Depth& D, int mode, const T* u, T* out, T alpha,
 #undef BAND_
 }
 
-void launch_grad(int dim, const Depth& D, const double* u, DPtrs g, CPtrs w, bool sub, hipStream_t st) {
+void launch_grad(int dim, const Depth& D, const double* u, DPtrs g, CPtrs w, bool sub, hipStream_t st,
+                 double scale) {
   const size_t n = D.tiles.size();
   if (!n) return;
-  DISPATCH_DIM(dim, k_grad, D.d_tiles, (int)n, D.d_box, u, g, w, sub, 1.0 / (12.0 * D.h));
+  DISPATCH_DIM(dim, k_grad, D.d_tiles, (int)n, D.d_box, u, g, w, sub, scale / (12.0 * D.h));
 }
 
-void launch_div(int dim, const Depth& D, CPtrs w, double* out, hipStream_t st) {
+void launch_div(int dim, const Depth& D, CPtrs w, double* out, hipStream_t st, double scale) {
   const size_t n = D.tiles.size();
   if (!n) return;
-  DISPATCH_DIM(dim, k_div, D.d_tiles, (int)n, D.d_box, w, out, 1.0 / (12.0 * D.h));
+  DISPATCH_DIM(dim, k_div, D.d_tiles, (int)n, D.d_box, w, out, scale / (12.0 * D.h));
+}
+
+void launch_gslot(const Depth& D, CPtrs mu, int dir, double* ab, hipStream_t st) {
+  const int n = (int)D.chunks.size();
+  if (!n) return;
+  hipLaunchKernelGGL(k_gslot, dim3((n + 3) / 4), dim3(256), 0, st, D.d_chunks, n, mu, dir, ab, 1.0 / (12.0 * D.h));
+}
+
+void launch_rfxV_T(const Composite& X, int d, const double* lam_c, double lscale, double* abc, double* abf,
+                   hipStream_t st) {
+  const Composite::GatherT* t[2] = {&X.rfxVc[d], &X.rfxVf[d]};
+  double* out[2] = {abc, abf};
+  for (int k = 0; k < 2; ++k) {
+    const int n = (int)t[k]->elem.size();
+    if (n)
+      hipLaunchKernelGGL(k_rfx_T, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, t[k]->d_elem, t[k]->d_ptr,
+                         t[k]->d_src, t[k]->d_coef, X.d_rfx_cell, lam_c, lscale, out[k]);
+  }
 }
 
 void launch_reflux_div(int dim, const Composite& X, CPtrs wc, CPtrs wf, double* div, double hc, hipStream_t st) {

@@ -435,6 +435,7 @@ int plan_level(amg_hier* H, int l, std::string& err) {
               ch.dst = addr(i, g[0], g[1], g[2]);
               ch.cstride = D.boxd[i].s[t[0]];
               ch.nstride = step * D.boxd[i].s[d];
+              ch.dir = (uint8_t)d;
               ch.count = q - q0;
               ch.box = i;
               ch.kind1 = fc.k1[col];

@@ -6,7 +6,16 @@ sin(2 pi x) sin(2 pi y) plus seeded N(0, 1e-3^2) noise; V(2,2) cycles to a
 relative residual of 1e-12.  Both smoothers (the paper's weighted Jacobi
 and red-black).  FP64 solves follow the oracle's iterations (<= 1e-11, the
 same cycle count to one), mixed-precision solves reach the oracle's
-solution to <= 1e-9."""
+solution to <= 1e-9.
+
+The Neumann Poisson system's FP64 rounding floor lies at the target: the
+residual of an exact solution rounds to about eps ||A|| ||x|| per cell, and
+its max over the 16384 cells comes to 1-1.6e-12 ||f||.  Measured on the GPU,
+every solver variant (FP64 and mixed, both smoothers) levels off at
+1.2-1.6e-12 ||r0|| after 20-30 cycles; the oracle reaches 8.6e-13 in its
+last cycle while its reduction per cycle collapses from 6 to 2.3.  The
+Poisson solves therefore take the stopping test's absolute term at that
+floor, tol_abs = 2e-12 ||f||, on both sides."""
 import numpy as np
 import pytest
 
@@ -34,7 +43,9 @@ def test_c1_recipe(op, bc, smoother):
     f = lev.zeros()
     f[lev.inner] = W.single_level_rhs((N, N), H0, op, c, seed=0)
     sing = lev.singular_components(op)
-    x_or, st_or = mg.solve(lev, f, op, c, nu1=2, nu2=2, smoother=smoother, tol_rel=1e-12, max_cycles=200)
+    tol_abs = 2e-12 * np.abs(f[lev.mask]).max() if op == "poisson" else 0.0
+    x_or, st_or = mg.solve(lev, f, op, c, nu1=2, nu2=2, smoother=smoother, tol_rel=1e-12, tol_abs=tol_abs,
+                           max_cycles=200)
     assert st_or["converged"]
     H, L = make_hier(lev, op, c)
     fd = to_dev(H, L, 0, f)
@@ -43,7 +54,7 @@ def test_c1_recipe(op, bc, smoother):
     for prec, tol in ((A.FP64, 1e-11), (A.MIXED, 1e-9)):
         x = torch.zeros_like(fd)
         st = H.solve(L, x, fd, None, A.default_opts(precision=prec, smoother=sm, nu1=2, nu2=2, tol_rel=1e-12,
-                                                    max_cycles=200))
+                                                    tol_abs=tol_abs, max_cycles=200))
         torch.cuda.synchronize()
         assert st["status"] == 0 and st["converged"], st
         err = relerr(lev.comp_mean(from_dev(H, L, 0, x, lev), sing), want, lev.mask)
@@ -51,5 +62,6 @@ def test_c1_recipe(op, bc, smoother):
         if prec == A.FP64:
             assert abs(st["cycles"] - st_or["cycles"]) <= 1, (st["cycles"], st_or["cycles"])
             k = min(len(st["history"]), len(st_or["history"]))
+            # histories agree until rounding noise takes over at the floor
             assert np.allclose(st["history"][:k], st_or["history"][:k], rtol=1e-6,
-                               atol=1e-13 * st_or["history"][0])
+                               atol=max(1e-13 * st_or["history"][0], tol_abs))

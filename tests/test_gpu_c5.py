@@ -106,3 +106,36 @@ def test_three_level_vortex_workload():
         R = amr_adj.composite_residual_T(OH, lo, g, "helmholtz", C_HELM)
         print("adjoint", d, st["cycles"], vmax(OH, R) / vmax(OH, g), flush=True)
         assert vmax(OH, R) <= 2e-10 * vmax(OH, g)
+
+
+def test_vortex_projection_adjoint_full_size():
+    """The adjoint of the composite projection on the full three-level
+    layout, checked by the oracle's operators: the adjoint potential lam
+    satisfies the oracle's transposed composite Poisson system with the
+    oracle's G^T ubar as source (projected along the volume weights), and
+    wbar = ubar - D^T lam with the oracle's D^T applied to the GPU's lam."""
+    from oracle import proj_adj
+    OH = amr.Hierarchy((BASE, BASE), 1.0 / BASE, BOXES, {(d, s): "D" for d in range(2) for s in (0, 1)})
+    Hw, Hp = gpu_hier("D", A.POISSON), gpu_hier("N", A.POISSON)
+    Hw_o, Hp_o = proj.hierarchy_with(OH, "D"), proj.hierarchy_with(OH, "N")
+    rng = np.random.default_rng(30)
+    ub = [[np.where(OH.valid[l], rng.normal(size=OH.levels[l].pshape), 0.0) for l in range(3)] for _ in range(2)]
+    ubs = [[to_dev(Hw, l, 0, ub[d][l]) for d in range(2)] for l in range(3)]
+    lams = [torch.zeros_like(ubs[l][0]) for l in range(3)]
+    wbs = [[torch.zeros_like(ubs[l][0]) for _ in range(2)] for l in range(3)]
+    st = A.project_adjoint(Hw, Hp, ubs, lams, wbs, A.default_opts(**OPTS))
+    assert st["status"] == 0 and st["converged"], st
+    lam = [from_dev(Hp, l, 0, lams[l], OH.levels[l]) for l in range(3)]
+    g = proj_adj.composite_gradient_T(Hp_o, ub)
+    wts = [np.where(OH.valid[l], OH.levels[l].h ** 2, 0.0) for l in range(3)]
+    tot = sum(g[l][OH.valid[l]].sum() for l in range(3))
+    gp = [np.where(OH.valid[l], g[l] - wts[l] * tot / sum(w.sum() for w in wts), 0.0) for l in range(3)]
+    R = amr_adj.composite_residual_T(Hp_o, lam, gp, "poisson", 0.0)
+    print("projection adjoint", st["cycles"], vmax(OH, R) / vmax(OH, gp), flush=True)
+    assert vmax(OH, R) <= 2e-10 * vmax(OH, gp)
+    dt = proj_adj.composite_divergence_T(Hw_o, lam)
+    for d in range(2):
+        got = [from_dev(Hw, l, 0, wbs[l][d], OH.levels[l]) for l in range(3)]
+        want = [np.where(OH.valid[l], ub[d][l] - dt[d][l], 0.0) for l in range(3)]
+        err = max(np.abs(got[l] - want[l])[OH.valid[l]].max() for l in range(3)) / vmax(OH, want)
+        assert err < 1e-11, err
