@@ -423,6 +423,18 @@ int amg_apply_laplacian(amg_hier* h, int level, double* x, const double* face_da
  * bitwise reproducible); synchronises the stream. */
 int amg_dot(amg_hier* h, int level, const double* a, const double* b, double* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): amg_dot
+ * without any allocation, host transfer or synchronisation.  *out (ONE
+ * DEVICE double, written on the stream) = sum over the level's cells of
+ * a_i b_i, bitwise equal to amg_dot's value (same kernels, same order).  The
+ * per-tile partials live in a static 256 KiB device array that every GPU
+ * holds until the process ends, so the level may have at most 32768 tiles
+ * (AMG_EUNSUPPORTED beyond); every call fully overwrites what it reads, and
+ * calls that overlap on one GPU (two streams, two threads) race on that
+ * array.  Errors: AMG_EINVAL, AMG_EUNSUPPORTED, AMG_EDEVICE. */
+int amg_dot_noalloc(amg_hier* h, int level, const double* a, const double* b, double* out, void* stream);
+
 /* ---- gradient, divergence and the approximate projection --------------------
  * Eqs. (discreteOps a-b) on one level (lev_lo == lev_hi) or in composite form
  * over levels 0..lev_hi (COH-1..4 of Section 5.3: ghosts by the hierarchy's

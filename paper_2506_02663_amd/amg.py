@@ -112,6 +112,7 @@ def lib():
         L.amg_composite_laplacian.argtypes = [vp, i32, pp, pp, pp, vp]
         L.amg_time_sweep.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, C.POINTER(C.c_double), vp]
         L.amg_autotune.argtypes = [vp, i32, i32, i32, i32, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.amg_dot_noalloc.argtypes = [vp, i32, vp, vp, vp, vp]
         L.amg_gradient_transpose.argtypes = [vp, i32, i32, pp, pp, vp]
         L.amg_divergence_transpose.argtypes = [vp, i32, i32, pp, pp, vp]
         L.amg_project_adjoint.argtypes = [vp, vp, i32, i32, pp, pp, pp, C.POINTER(SolveOpts), C.POINTER(SolveStats),
@@ -511,6 +512,16 @@ class Hierarchy:
         out = C.c_double()
         self._check(lib().amg_dot(self.h, level, _ptr(a), _ptr(b), C.byref(out), _stream()))
         return out.value
+
+    def dot_noalloc(self, level, a, b, out):
+        """out[0] = sum over the level's cells of a b, into the device tensor
+        out (no allocation, no synchronisation)."""
+        import torch
+        self._need(a, level, 0, "a", (torch.float64,))
+        self._need(b, level, 0, "b", (torch.float64,))
+        if not out.is_cuda or out.dtype != torch.float64 or out.numel() < 1:
+            raise ValueError("out must be a float64 device tensor of at least one element")
+        self._check(lib().amg_dot_noalloc(self.h, level, _ptr(a), _ptr(b), _ptr(out), _stream()))
 
     def set_coefficient(self, c):
         self._check(lib().amg_set_coefficient(self.h, float(c)))

@@ -36,6 +36,35 @@ int fail(amg_hier* H, int code, const std::string& msg) {
   return code;
 }
 
+// ---- static scratch of the allocation-free entry point ----------------------
+// kNoAllocDoubles FP64 words of device memory that every GPU holds from the
+// load of the library to the end of the process; amg_dot_noalloc keeps its
+// per-tile partial sums there instead of in the level's partial buffer.  In
+// host code the array's name is only a stand-in: its device address is looked
+// up once per device (hipGetSymbolAddress) and that address is what kernels
+// receive.
+constexpr int64_t kNoAllocDoubles = 32768;  // 256 KiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+constexpr int kMaxDevices = 64;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device (looked up once per
+// device, at amg_finalize or at the first allocation-free call there)
+hipError_t scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 template <typename T>
 int upload(amg_hier* H, T** dst, const std::vector<T>& v) {
   size_t n = std::max<size_t>(v.size(), 1);
@@ -823,6 +852,10 @@ int amg_finalize(amg_hier* H) {
     if (rc != AMG_OK) return fail(H, rc, err);
   }
   HIPCHK(hipStreamCreate(&H->own));
+  {
+    double* sp = nullptr;  // the allocation-free entry point's scratch on this device
+    HIPCHK(scratch_address(&sp));
+  }
   for (int l = 0; l < H->nlevels; ++l) {
     Level& L = H->levels[l];
     const std::vector<double>& mats_l = mats[l];
@@ -1683,6 +1716,26 @@ int amg_dot(amg_hier* H, int level, const double* a, const double* b, double* ou
   HIPCHK(hipMemcpyAsync(L.h_scal + S_DOT, L.scal + S_DOT, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   *out = L.h_scal[S_DOT];
+  return AMG_OK;
+}
+
+int amg_dot_noalloc(amg_hier* H, int level, const double* a, const double* b, double* out, void* stream) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  if (!a || !b || !out) return fail(H, AMG_EINVAL, "bad arguments");
+  Level& L = H->levels[level];
+  Depth& D = L.depths[0];
+  const int64_t nt = (int64_t)D.tiles.size();
+  if (nt > kNoAllocDoubles)
+    return fail(H, AMG_EUNSUPPORTED, "amg_dot_noalloc: the level has " + std::to_string(nt) +
+                                         " tiles, the static scratch holds " + std::to_string(kNoAllocDoubles));
+  double* sp = nullptr;
+  HIPCHK(scratch_address(&sp));
+  hipStream_t st = stream_of(H, stream);
+  // every tile writes its own partial before the reduction reads it: nothing
+  // of an earlier call's contents is read
+  launch_tile_dot(H->dim, D, a, b, sp, st);
+  launch_seg_reduce(sp, nullptr, 1, (int)nt, out, false, st);
+  HIPCHK(hipGetLastError());
   return AMG_OK;
 }
 
