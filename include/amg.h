@@ -507,6 +507,52 @@ int amg_divergence_transpose(amg_hier* h, int lev_lo, int lev_hi, double* const*
 int amg_project_adjoint(amg_hier* hw, amg_hier* hp, int lev_lo, int lev_hi, double* const* ubar, double* const* lam,
                         double* const* wbar, const amg_solve_opts* opts, amg_solve_stats* stats, void* stream);
 
+/* ---- coarse-fine interface conditions (CIC-1..3 of Section 6.3) -------------
+ * The face data a refined level solved on its own (AMG_CF_DIRICHLET or
+ * AMG_CF_NEUMANN) takes on its coarse-fine faces, from the data of level-1
+ * at four earlier coarse times t_-i = t_-0 - i k (the history kept by the
+ * subcycled time stepping, eq. vel_slicing):
+ *   CIC-1 the face between a row-end cell e and the position beyond it has
+ *         two fine cells on each side along the normal (e - n, e, e + n,
+ *         e + 2n, n the outward unit step);
+ *   CIC-2 their averages are interpolated from the coarse data by AMRCFI
+ *         (Section 5.2, the tensor-product conservative quartic of the
+ *         composite operators) and combined by eq. cell2face: the face
+ *         average (AMG_CIC_VALUE, first row) or the face average of the
+ *         outward normal derivative (AMG_CIC_NORMAL_DERIVATIVE, second row);
+ *   CIC-3 eq. timeInterp takes them to t* = t_-1 + eta.
+ * Readings of the printed time matrix: its columns belong to t_-3, t_-2,
+ * t_-1, t_-0 (it puts weight 1 on t_-1 at eta = 0 and on t_-0 at eta = k),
+ * and with the printed prefactor 1/(6k^3) its second row gives d/dt itself.
+ * Every step is linear: the kernels combine the coarse data in time first,
+ * which agrees with the paper's order to rounding. */
+#define AMG_CIC_VALUE 0
+#define AMG_CIC_NORMAL_DERIVATIVE 1
+
+/* coarse[i] (i = 0..3): packed FP64 buffers of level-1 with the data at t_-i
+ * (covered cells included: the history of level-1 itself); k > 0 the coarse
+ * step, eta the offset of t* from t_-1.  Writes the entries of face_data
+ * (the level's face-data layout) on its coarse-fine faces, and those of
+ * face_data_dt (may be NULL) with the time derivative at t*; other entries
+ * (physical faces) are left alone.  Errors: AMG_EINVAL (level 0, an
+ * interpolated or isolated level, bad arguments), AMG_EUNSUPPORTED (a
+ * coarse window of the interpolation leaves level-1; amg_finalize records
+ * this instead of rejecting the layout), AMG_EDEVICE. */
+int amg_cic_face_data(amg_hier* h, int level, const double* const* coarse, double k, double eta, int kind,
+                      double* face_data, double* face_data_dt, void* stream);
+
+/* Eq. correctingFaceAvg on the face data of a velocity of the level:
+ * face_data[d] is the face-data buffer of velocity component d.  Per
+ * face-connected component c, the outward normal face averages of its
+ * coarse-fine and physical faces must sum to zero (eq.
+ * velocity_disc_solvabilityCond; the faces of a level have one area); one
+ * constant delta_c, -delta_c (coarse-fine faces of c) = that sum, is added
+ * to the outward normal average of each of its coarse-fine faces (component
+ * d on faces normal to d, with the outward sign).  delta (host, ncomp
+ * values, may be NULL) receives the constants (the call then synchronises
+ * the stream).  Errors as amg_cic_face_data. */
+int amg_cic_correct(amg_hier* h, int level, double* const* face_data, double* delta, void* stream);
+
 /* Changes the Helmholtz coefficient c (> 0) of a finalized hierarchy: the
  * bottom inverses are recomputed on the host and captured graphs dropped.
  * Not on the hot path; AMG_EINVAL if the operator is not Helmholtz. */

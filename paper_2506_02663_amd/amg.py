@@ -21,6 +21,7 @@ SMOOTH_JACOBI, SMOOTH_RB = 0, 1
 FP64, MIXED = 0, 1
 F64, F32 = 0, 1
 SOLV_RHS_SHIFT, SOLV_OFF, SOLV_CF_DELTA = 0, 1, 2
+CIC_VALUE, CIC_NORMAL_DERIVATIVE = 0, 1
 T_SWEEP, T_FILL, T_RESTRICT, T_PROLONG, T_RESIDUAL, T_SWEEP_SPLIT, T_KINDS = range(7)
 TUNE_MARCH2, TUNE_MARCH3, TUNE_ROW_ALIGN, TUNE_SPLIT_RB = range(4)
 MAX_HISTORY, MAX_COMP = 128, 64
@@ -113,6 +114,8 @@ def lib():
         L.amg_time_sweep.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, C.POINTER(C.c_double), vp]
         L.amg_autotune.argtypes = [vp, i32, i32, i32, i32, C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.amg_dot_noalloc.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.amg_cic_face_data.argtypes = [vp, i32, C.POINTER(vp), dbl, dbl, i32, vp, vp, vp]
+        L.amg_cic_correct.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(C.c_double), vp]
         L.amg_gradient_transpose.argtypes = [vp, i32, i32, pp, pp, vp]
         L.amg_divergence_transpose.argtypes = [vp, i32, i32, pp, pp, vp]
         L.amg_project_adjoint.argtypes = [vp, vp, i32, i32, pp, pp, pp, C.POINTER(SolveOpts), C.POINTER(SolveStats),
@@ -522,6 +525,35 @@ class Hierarchy:
         if not out.is_cuda or out.dtype != torch.float64 or out.numel() < 1:
             raise ValueError("out must be a float64 device tensor of at least one element")
         self._check(lib().amg_dot_noalloc(self.h, level, _ptr(a), _ptr(b), _ptr(out), _stream()))
+
+    def cic_face_data(self, level, coarse_hist, k, eta, face_data, face_data_dt=None, kind=CIC_VALUE):
+        """Coarse-fine face data of `level` at t* = t_-1 + eta from
+        coarse_hist[i] = the level-1 data at t_-i (i = 0..3) into face_data
+        (and the time derivative into face_data_dt)."""
+        import torch
+        if len(coarse_hist) != 4:
+            raise ValueError("four coarse time levels")
+        for t in coarse_hist:
+            self._need(t, level - 1, 0, "coarse data", (torch.float64,))
+        self._need_faces(face_data, level)
+        if face_data_dt is not None:
+            self._need_faces(face_data_dt, level)
+        arr = (C.c_void_p * 4)(*[t.data_ptr() for t in coarse_hist])
+        self._check(lib().amg_cic_face_data(self.h, level, arr, float(k), float(eta), kind, _ptr(face_data),
+                                            _ptr(face_data_dt), _stream()))
+
+    def cic_correct(self, level, face_data):
+        """Eq. correctingFaceAvg on the velocity face data (one buffer per
+        component, corrected in place); returns the per-component deltas."""
+        if len(face_data) != self.dim:
+            raise ValueError("one face-data buffer per velocity component")
+        for t in face_data:
+            self._need_faces(t, level)
+        arr = (C.c_void_p * self.dim)(*[t.data_ptr() for t in face_data])
+        n = self.level_info(level).ncomp
+        out = (C.c_double * max(n, 1))()
+        self._check(lib().amg_cic_correct(self.h, level, arr, out, _stream()))
+        return list(out[:n])
 
     def set_coefficient(self, c):
         self._check(lib().amg_set_coefficient(self.h, float(c)))

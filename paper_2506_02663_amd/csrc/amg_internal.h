@@ -240,7 +240,27 @@ struct GraphCache {  // the captured outer cycle of one level
   }
 };
 
+// Coarse-fine interface conditions of a level solved with face data (CIC-1..3
+// of Section 6.3): per face-data entry on a coarse-fine face, the four fine
+// cells across the face along the outward normal (two inside, two outside)
+// and, for each, the 5^D window of coarse cells AMRCFI interpolates it from.
+struct CicTable {
+  std::vector<int64_t> fd;     // face-data entry
+  std::vector<int32_t> src;    // [entry * 4 + cell] * 5^D coarse elements
+  std::vector<uint8_t> wsel;   // [entry * 4 + cell] * D weight sets (of Composite::w)
+  std::vector<double> ncf;     // coarse-fine face entries per component
+  double w[10][5];
+  int64_t* d_fd = nullptr;
+  int32_t* d_src = nullptr;
+  uint8_t* d_wsel = nullptr;
+  double* d_w = nullptr;
+  double* d_ncf = nullptr;
+  double* d_sum = nullptr;     // per-component compatibility sums, then deltas
+  std::string err;             // why the table could not be built (empty: built)
+};
+
 struct Level {
+  CicTable cic;                     // coarse-fine interface conditions (face-data levels)
   GraphCache graph;                 // captured outer cycle of the level solve
   GraphCache graphT;                // the same for the adjoint solve
   Composite cmp;                    // against level l-1 (l >= 1)
@@ -325,6 +345,8 @@ namespace amg {
 int plan_level(amg_hier* H, int l, std::string& err);
 // composite tables of level l against level l-1 (composite.cpp)
 int build_composite(amg_hier* H, int l, std::string& err);
+// interface-condition table of a level solved with face data (composite.cpp)
+int build_cic(amg_hier* H, int l, std::string& err);
 // host assembly of the coarsest operator and its inverse (bottom.cpp)
 int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats, std::vector<int64_t>& idx);
 }  // namespace amg

@@ -475,6 +475,9 @@ void free_level(amg::Level& L) {
   for (auto& D : L.depths)
     for (void* p : {(void*)D.d_exT_elem, (void*)D.d_exT_slot, (void*)D.d_exT_ptr})
       if (p) (void)hipFree(p);
+  const CicTable& T = L.cic;
+  for (void* p : {(void*)T.d_fd, (void*)T.d_src, (void*)T.d_wsel, (void*)T.d_w, (void*)T.d_ncf, (void*)T.d_sum})
+    if (p) (void)hipFree(p);
 }
 
 // ---- composite (multi-level) solve -------------------------------------------
@@ -846,9 +849,17 @@ int amg_finalize(amg_hier* H) {
     L.face_valid.assign((size_t)std::max<int64_t>(L.nface, 1), 1);  // build_composite marks covered faces
   }
   for (int l = 1; l < H->nlevels; ++l) {
-    if (H->levels[l].cf_mode != AMG_CF_INTERP) continue;
+    Level& L = H->levels[l];
     std::string err;
-    int rc = build_composite(H, l, err);
+    int rc = AMG_OK;
+    if (L.cf_mode == AMG_CF_INTERP)
+      rc = build_composite(H, l, err);
+    else if (!L.isolated && !H->levels[l - 1].isolated && build_cic(H, l, err) != AMG_OK) {
+      // the interface conditions its face data may come from: a window off
+      // the coarse level makes only amg_cic_face_data unavailable
+      L.cic = CicTable();
+      L.cic.err = err;
+    }
     if (rc != AMG_OK) return fail(H, rc, err);
   }
   HIPCHK(hipStreamCreate(&H->own));
@@ -917,6 +928,18 @@ int amg_finalize(amg_hier* H) {
       TRY(upload(H, &D0.d_exT_slot, D0.exT_slot));
       TRY(upload(H, &D0.d_exT_ptr, D0.exT_ptr));
     }
+  }
+  // interface-condition tables of the face-data levels
+  for (int l = 1; l < H->nlevels; ++l) {
+    CicTable& T = H->levels[l].cic;
+    if (T.fd.empty()) continue;
+    std::vector<double> w(&T.w[0][0], &T.w[0][0] + 50);
+    TRY(upload(H, &T.d_w, w));
+    TRY(upload(H, &T.d_fd, T.fd));
+    TRY(upload(H, &T.d_src, T.src));
+    TRY(upload(H, &T.d_wsel, T.wsel));
+    TRY(upload(H, &T.d_ncf, T.ncf));
+    TRY(zalloc(H, &T.d_sum, (size_t)H->levels[l].ncomp));
   }
   // composite tables of every interpolated level against the one below
   for (int l = 1; l < H->nlevels; ++l) {
@@ -1735,6 +1758,65 @@ int amg_dot_noalloc(amg_hier* H, int level, const double* a, const double* b, do
   // of an earlier call's contents is read
   launch_tile_dot(H->dim, D, a, b, sp, st);
   launch_seg_reduce(sp, nullptr, 1, (int)nt, out, false, st);
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+static int check_cic(amg_hier* H, int level) {
+  if (!check_level(H, level)) return AMG_EINVAL;
+  const Level& L = H->levels[level];
+  if (level < 1 || L.cf_mode == AMG_CF_INTERP || L.isolated || H->levels[level - 1].isolated)
+    return fail(H, AMG_EINVAL, "interface conditions are for a refined level solved with face data");
+  return AMG_OK;
+}
+
+int amg_cic_face_data(amg_hier* H, int level, const double* const* coarse, double k, double eta, int kind,
+                      double* face_data, double* face_data_dt, void* stream) {
+  TRY(check_cic(H, level));
+  if (!coarse || !face_data || (kind != AMG_CIC_VALUE && kind != AMG_CIC_NORMAL_DERIVATIVE) || !(k > 0) ||
+      !std::isfinite(eta))
+    return fail(H, AMG_EINVAL, "bad arguments");
+  for (int i = 0; i < 4; ++i)
+    if (!coarse[i]) return fail(H, AMG_EINVAL, "null coarse data");
+  // eq. timeInterp: the printed rows divided by 6 k^3; its columns belong to
+  // t_-3, t_-2, t_-1, t_-0 (t* = t_-1 + eta), coarse[i] holds t_-i
+  const double e = eta, e2 = eta * eta, e3 = e2 * eta, k2 = k * k, k3 = k2 * k, s = 1.0 / (6.0 * k3);
+  const double r0[4] = {-e3 + k2 * e, 3 * e3 + 3 * k * e2 - 6 * k2 * e, -3 * e3 - 6 * k * e2 + 3 * k2 * e + 6 * k3,
+                        e3 + 3 * k * e2 + 2 * k2 * e};
+  const double r1[4] = {-3 * e2 + k2, 9 * e2 + 6 * k * e - 6 * k2, -9 * e2 - 12 * k * e + 3 * k2,
+                        3 * e2 + 6 * k * e + 2 * k2};
+  double tv[4], td[4];
+  for (int i = 0; i < 4; ++i) {
+    tv[i] = r0[3 - i] * s;
+    td[i] = r1[3 - i] * s;
+  }
+  Level& L = H->levels[level];
+  if (!L.cic.err.empty()) return fail(H, AMG_EUNSUPPORTED, L.cic.err);
+  launch_cic(H->dim, L.cic, coarse, tv, td, kind, L.depths[0].h, face_data, face_data_dt, stream_of(H, stream));
+  HIPCHK(hipGetLastError());
+  return AMG_OK;
+}
+
+int amg_cic_correct(amg_hier* H, int level, double* const* face_data, double* delta, void* stream) {
+  TRY(check_cic(H, level));
+  if (!face_data) return fail(H, AMG_EINVAL, "bad arguments");
+  DPtrs fdv{};
+  for (int d = 0; d < H->dim; ++d) {
+    if (!face_data[d]) return fail(H, AMG_EINVAL, "null face data");
+    fdv.p[d] = face_data[d];
+  }
+  Level& L = H->levels[level];
+  hipStream_t st = stream_of(H, stream);
+  if (L.cic.fd.empty()) {  // no coarse-fine face: nothing to correct
+    if (delta)
+      for (int c = 0; c < L.ncomp; ++c) delta[c] = 0.0;
+    return AMG_OK;
+  }
+  launch_cic_correct(L.depths[0], L.ncomp, L.cic, fdv, st);
+  if (delta) {
+    HIPCHK(hipMemcpyAsync(delta, L.cic.d_sum, L.ncomp * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   HIPCHK(hipGetLastError());
   return AMG_OK;
 }

@@ -398,4 +398,81 @@ int build_composite(amg_hier* H, int l, std::string& err) {
   return AMG_OK;
 }
 
+int build_cic(amg_hier* H, int l, std::string& err) {
+  Level& F = H->levels[l];
+  Level& C = H->levels[l - 1];
+  CicTable& T = F.cic;
+  const int dim = H->dim;
+  const int nwin = dim == 2 ? 25 : 125;
+  char buf[256];
+  cfi_weights(T.w);
+  const Owner oc = make_owner(H, C, l - 1);
+  const Depth& DF = F.depths[0];
+  const Depth& DC = C.depths[0];
+  T.fd.clear();
+  T.src.clear();
+  T.wsel.clear();
+  T.ncf.assign(F.ncomp, 0.0);
+  int64_t gn[3] = {1, 1, 1};  // cells of level l's grid
+  for (int d = 0; d < dim; ++d) gn[d] = oc.n[d] * H->ratio;
+  for (size_t b = 0; b < DF.boxes.size(); ++b) {
+    const Box& B = DF.boxes[b];
+    for (int d = 0; d < dim; ++d) {
+      int t[2] = {-1, -1}, k = 0;
+      for (int e = 0; e < dim; ++e)
+        if (e != d) t[k++] = e;
+      const int n0 = B.n(t[0]);
+      const int n1 = dim == 3 ? B.n(t[1]) : 1;
+      for (int s = 0; s < 2; ++s) {
+        const int sg = s ? 1 : -1;
+        const int p1 = s ? B.hi[d] + 1 : B.lo[d] - 1;
+        if (p1 < 0 || p1 >= gn[d]) continue;  // physical face
+        const FaceCols& fc = DF.faces[b * 6 + d * 2 + s];
+        for (int q1 = 0; q1 < n1; ++q1)
+          for (int q0 = 0; q0 < n0; ++q0) {
+            const size_t col = (size_t)q0 + (size_t)n0 * q1;
+            if (fc.k1[col] != G_FILL_D && fc.k1[col] != G_FILL_N) continue;  // another box of the level
+            T.fd.push_back(F.face_off[b * 6 + d * 2 + s] + (int64_t)q0 + (int64_t)n0 * q1);
+            T.ncf[DF.boxd[b].comp] += 1.0;
+            // the row-end cell and the cells at -1, +1, +2 along the outward normal
+            int e0[3] = {0, 0, 0};
+            e0[d] = s ? B.hi[d] : B.lo[d];
+            e0[t[0]] = B.lo[t[0]] + q0;
+            if (dim == 3) e0[t[1]] = B.lo[t[1]] + q1;
+            for (int m = -1; m <= 2; ++m) {
+              int g[3] = {e0[0], e0[1], e0[2]};
+              g[d] += m * sg;
+              int lo[3] = {0, 0, 0};
+              for (int e = 0; e < dim; ++e) {
+                const int P = floordiv2(g[e]);
+                const int N = (int)oc.n[e];
+                int sh = 0;
+                if (P < 2) sh = 2 - P;
+                if (P > N - 3) sh = (N - 3) - P;
+                lo[e] = P + sh - 2;
+                T.wsel.push_back((uint8_t)((sh + 2) * 2 + (g[e] - 2 * P)));
+              }
+              for (int w = 0; w < nwin; ++w) {
+                int q[3] = {lo[0] + w % 5, lo[1] + (w / 5) % 5, dim == 3 ? lo[2] + w / 25 : 0};
+                const int cb = oc.at(q);
+                if (cb < 0) {
+                  snprintf(buf, sizeof buf, "interface-condition window of level %d leaves level %d", l, l - 1);
+                  err = buf;
+                  return AMG_EUNSUPPORTED;
+                }
+                const int64_t e = elem(DC, cb, q, dim);
+                if (e > INT32_MAX) {
+                  err = "coarse level too large for 32-bit interpolation indices";
+                  return AMG_EUNSUPPORTED;
+                }
+                T.src.push_back((int32_t)e);
+              }
+            }
+          }
+      }
+    }
+  }
+  return AMG_OK;
+}
+
 }  // namespace amg

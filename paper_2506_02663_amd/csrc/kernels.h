@@ -27,6 +27,15 @@ void launch_grad(int dim, const Depth& D, const double* u, DPtrs g, CPtrs w, boo
                  double scale = 1.0);
 // out = scale sum_d G_d w[d]
 void launch_div(int dim, const Depth& D, CPtrs w, double* out, hipStream_t st, double scale = 1.0);
+// coarse-fine interface conditions of a face-data level: fd (dfd may be
+// null) at the table's entries from the coarse data hist[i] = phi(t_-i) with
+// time weights tv (value) and td (derivative); kind 0 face averages, 1
+// outward normal derivatives (h: the level's cell size)
+void launch_cic(int dim, const CicTable& T, const double* const* hist, const double tv[4], const double td[4], int kind,
+                double h, double* fd, double* dfd, hipStream_t st);
+// eq. correctingFaceAvg on the velocity face data fdv.p[d] (T.d_sum receives
+// the per-component deltas)
+void launch_cic_correct(const Depth& D, int ncomp, const CicTable& T, DPtrs fdv, hipStream_t st);
 // transposes of G and D: ghost-slot adjoints of the gradient stencil (ab
 // -= weights times mu; mu.p[d] read along d; dir >= 0: faces normal to dir)
 void launch_gslot(const Depth& D, CPtrs mu, int dir, double* ab, hipStream_t st);

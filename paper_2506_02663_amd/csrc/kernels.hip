@@ -1628,6 +1628,95 @@ __global__ void __launch_bounds__(256) k_gslot(const ChunkD* __restrict__ chunks
   ab[g1 + ns] -= -sg * m0 * inv12h;
 }
 
+// ---------------------------------------------------------------------------
+// coarse-fine interface conditions (CIC-1..3 of Section 6.3).  One thread per
+// face-data entry of a coarse-fine face: the four fine cells across the face
+// along the outward normal are interpolated (AMRCFI) from the coarse data of
+// four earlier times, combined by eq. cell2face into the face average (kind
+// 0, weights (-1, 7, 7, -1) / 12) or the outward normal derivative (kind 1,
+// (1, -15, 15, -1) / 12h), and taken to the time t* by the two rows tw0, tw1
+// of eq. timeInterp; every step is linear, so the coarse data are combined
+// in time first.  fd[entry] = value at t*, dfd[entry] (may be null) = its
+// time derivative.
+struct CoarseHist {
+  const double* p[4];  // phi(t_-i), i = 0..3
+};
+struct TimeW {
+  double v[4], d[4];  // weights of phi(t_-i) for the value and the derivative
+};
+template <int DIM>
+__global__ void __launch_bounds__(256) k_cic(int n, const int64_t* __restrict__ fdi, const int32_t* __restrict__ src,
+                                             const uint8_t* __restrict__ wsel, const double* __restrict__ W,
+                                             CoarseHist hist, TimeW tw, int kind, double inv12h,
+                                             double* __restrict__ fd, double* __restrict__ dfd) {
+  constexpr int NW = DIM == 2 ? 25 : 125;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  const double cv[4] = {-1.0 / 12.0, 7.0 / 12.0, 7.0 / 12.0, -1.0 / 12.0};
+  const double cd[4] = {inv12h, -15.0 * inv12h, 15.0 * inv12h, -inv12h};
+  double a0 = 0.0, a1 = 0.0;
+  for (int p = 0; p < 4; ++p) {
+    const int q = j * 4 + p;
+    const uint8_t* ws = wsel + (size_t)q * DIM;
+    const int32_t* sr = src + (size_t)q * NW;
+    double b0 = 0.0, b1 = 0.0;
+    for (int m = 0; m < NW; ++m) {
+      double w = W[5 * ws[0] + m % 5] * W[5 * ws[1] + (m / 5) % 5];
+      if (DIM == 3) w *= W[5 * ws[2] + m / 25];
+      const int32_t e = sr[m];
+      double v = 0.0, dv = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double c = hist.p[i][e];
+        v += tw.v[i] * c;
+        dv += tw.d[i] * c;
+      }
+      b0 += w * v;
+      b1 += w * dv;
+    }
+    const double cf = kind == 0 ? cv[p] : cd[p];
+    a0 += cf * b0;
+    a1 += cf * b1;
+  }
+  fd[fdi[j]] = a0;
+  if (dfd) dfd[fdi[j]] = a1;
+}
+
+// eq. correctingFaceAvg on a velocity's face data (fdv.p[d]: component d):
+// per component c, sum over its faces with face data (coarse-fine and
+// physical) of the outward normal component, sign(outward) * fdv[normal
+// direction]; then delta[c] = -sum / (coarse-fine entries of c), 0 without
+// any.  One block per component, the component's chunks in list order.
+__global__ void __launch_bounds__(256) k_cic_sum(const ChunkD* __restrict__ chunks, const int32_t* __restrict__ ptr,
+                                                 const int32_t* __restrict__ idx, DPtrs fdv,
+                                                 const double* __restrict__ ncf, double* __restrict__ delta) {
+  __shared__ double sh[4];
+  const int c = blockIdx.x;
+  const int a = ptr[c], b = ptr[c + 1];
+  double v = 0.0;
+  for (int k = a * 64 + (int)threadIdx.x; k < b * 64; k += 256) {
+    const ChunkD ch = chunks[idx[k >> 6]];
+    const int lane = k & 63;
+    if (lane >= ch.count || ch.fd < 0 || (ch.kind1 != G_FILL_D && ch.kind1 != G_FILL_N)) continue;
+    v += (ch.nstride > 0 ? 1.0 : -1.0) * fdv.p[ch.dir][ch.fd + lane];
+  }
+  v = block_sum<double>(v, sh);
+  if (threadIdx.x == 0) delta[c] = ncf[c] > 0.0 ? -v / ncf[c] : 0.0;
+}
+
+// the correction: fdv[d] += sign(outward) * delta[component] on the
+// coarse-fine face entries of faces normal to d
+__global__ void __launch_bounds__(256) k_cic_fix(const ChunkD* __restrict__ chunks, int nchunks,
+                                                 const BoxD* __restrict__ boxes, DPtrs fdv,
+                                                 const double* __restrict__ delta) {
+  const int ci = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (ci >= nchunks) return;
+  const ChunkD ch = chunks[ci];
+  if (lane >= ch.count || !ch.cf || ch.fd < 0 || (ch.kind1 != G_FILL_D && ch.kind1 != G_FILL_N)) return;
+  fdv.p[ch.dir][ch.fd + lane] += (ch.nstride > 0 ? 1.0 : -1.0) * delta[boxes[ch.box].comp];
+}
+
 // per-tile sum of a * b over the interior (dot products)
 template <int DIM>
 __global__ void __launch_bounds__(256) k_tile_dot(const TileD* __restrict__ tiles, int ntiles,
@@ -2180,6 +2269,34 @@ void launch_div(int dim, const Depth& D, CPtrs w, double* out, hipStream_t st, d
   const size_t n = D.tiles.size();
   if (!n) return;
   DISPATCH_DIM(dim, k_div, D.d_tiles, (int)n, D.d_box, w, out, scale / (12.0 * D.h));
+}
+
+void launch_cic(int dim, const CicTable& T, const double* const* hist, const double tv[4], const double td[4], int kind,
+                double h, double* fd, double* dfd, hipStream_t st) {
+  const int n = (int)T.fd.size();
+  if (!n) return;
+  CoarseHist ch;
+  TimeW tw;
+  for (int i = 0; i < 4; ++i) {
+    ch.p[i] = hist[i];
+    tw.v[i] = tv[i];
+    tw.d[i] = td[i];
+  }
+  const dim3 g((unsigned)((n + 255) / 256)), b(256);
+  if (dim == 2)
+    hipLaunchKernelGGL(k_cic<2>, g, b, 0, st, n, T.d_fd, T.d_src, T.d_wsel, T.d_w, ch, tw, kind, 1.0 / (12.0 * h), fd,
+                       dfd);
+  else
+    hipLaunchKernelGGL(k_cic<3>, g, b, 0, st, n, T.d_fd, T.d_src, T.d_wsel, T.d_w, ch, tw, kind, 1.0 / (12.0 * h), fd,
+                       dfd);
+}
+
+void launch_cic_correct(const Depth& D, int ncomp, const CicTable& T, DPtrs fdv, hipStream_t st) {
+  if (D.chunks.empty() || ncomp <= 0) return;
+  hipLaunchKernelGGL(k_cic_sum, dim3(ncomp), dim3(256), 0, st, D.d_chunks, D.d_cc_ptr, D.d_cc_idx, fdv, T.d_ncf,
+                     T.d_sum);
+  const int n = (int)D.chunks.size();
+  hipLaunchKernelGGL(k_cic_fix, dim3((n + 3) / 4), dim3(256), 0, st, D.d_chunks, n, D.d_box, fdv, T.d_sum);
 }
 
 void launch_gslot(const Depth& D, CPtrs mu, int dir, double* ab, hipStream_t st) {

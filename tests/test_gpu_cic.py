@@ -1,0 +1,170 @@
+"""The coarse-fine interface conditions on the GPU against the oracle
+(oracle/cic.py, pinned by the printed time matrix and by exactness on
+polynomial data): face averages and outward normal derivatives at t* and
+their time derivatives, entry by entry on the coarse-fine faces of 2D and 3D
+levels (physical entries left alone); the compatibility correction of a
+velocity's face data; and the pipeline feeding its consumer: a refined
+level's Helmholtz solve with coarse-fine face data from a polynomial
+coarse field reproduces the polynomial's cell averages."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import amr, cic, mg  # noqa: E402
+from oracle.level import PAD, Level  # noqa: E402
+from paper_2506_02663_amd import amg as A  # noqa: E402
+from tests.gpuhelp import faces_to_dev, from_dev, relerr, to_dev  # noqa: E402
+from tests.polyfix import Poly1  # noqa: E402
+
+LAYOUTS = {
+    "2d": ((16, 16), [[((0, 0), (15, 15))],
+                      [((0, 8), (15, 15)), ((16, 8), (23, 23)), ((8, 24), (15, 31))]], "N"),
+    "2d_dir": ((16, 16), [[((0, 0), (15, 15))], [((6, 4), (21, 11))]], "D"),
+    "3d": ((8, 8, 8), [[((0, 0, 0), (7, 7, 7))], [((4, 4, 4), (11, 11, 15)), ((0, 4, 4), (3, 11, 11))]], "D"),
+}
+
+
+def build(name, cf_mode=A.CF_DIRICHLET, op=A.HELMHOLTZ, c=1e-3):
+    base, boxes, bc = LAYOUTS[name]
+    D = len(base)
+    OH = amr.Hierarchy(base, 1.0 / base[0], boxes, {(d, s): bc for d in range(D) for s in (0, 1)})
+    H = A.Hierarchy(D, base, 1.0 / base[0], 2)
+    for l, bl in enumerate(boxes):
+        H.set_level_boxes(l, bl)
+    H.set_cf_mode(1, cf_mode)
+    for d in range(D):
+        for s in (0, 1):
+            H.set_physical_bc(d, s, A.DIRICHLET if bc == "D" else A.NEUMANN)
+    H.set_operator(op, c)
+    H.finalize()
+    return OH, H
+
+
+def faces_from_dev(H, level, lev, t):
+    """Face data buffer -> {(d, s): padded array at the row-end cells}."""
+    flat = t.detach().cpu().numpy()
+    out = lev.zero_face_data()
+    D = lev.dim
+    for b in H.boxes(level, 0):
+        n = [hi - lo + 1 for lo, hi in zip(b["lo"], b["hi"])]
+        for d in range(D):
+            trans = [e for e in range(D) if e != d]
+            shape = [n[e] for e in trans]
+            for s in (0, 1):
+                off = b["face_offset"][d][s]
+                vals = flat[off: off + int(np.prod(shape))].reshape(shape[::-1]).T
+                sl = [slice(PAD + lo, PAD + hi + 1) for lo, hi in zip(b["lo"], b["hi"])]
+                sl[d] = PAD + (b["hi"][d] if s else b["lo"][d])
+                out[(d, s)][tuple(sl)] = vals
+    return out
+
+
+@pytest.mark.parametrize("name", sorted(LAYOUTS))
+@pytest.mark.parametrize("kind", ["value", "normal_derivative"])
+def test_face_data_against_oracle(name, kind):
+    OH, H = build(name)
+    coarse, fine = OH.levels
+    rng = np.random.default_rng(3)
+    hist = [np.where(coarse.mask, rng.normal(size=coarse.pshape), 0.0) for _ in range(4)]
+    k, eta = 0.07, 0.031
+    want, wantd = cic.cic_face_data(OH, 1, hist, k, eta, kind)
+    nface = H.level_info(1).nface
+    fd = torch.full((nface,), 123.0, dtype=torch.float64, device="cuda")
+    dfd = torch.full((nface,), 123.0, dtype=torch.float64, device="cuda")
+    H.cic_face_data(1, [to_dev(H, 0, 0, a) for a in hist], k, eta, fd, dfd,
+                    kind=A.CIC_VALUE if kind == "value" else A.CIC_NORMAL_DERIVATIVE)
+    torch.cuda.synchronize()
+    got, gotd = faces_from_dev(H, 1, fine, fd), faces_from_dev(H, 1, fine, dfd)
+    n = 0
+    for key in want:
+        cf = fine.row_end(*key) & ~fine.end_is_physical(*key)
+        phys = fine.end_is_physical(*key)
+        scale = max(1.0, np.abs(want[key][cf]).max()) if cf.any() else 1.0
+        assert np.abs(got[key][cf] - want[key][cf]).max(initial=0.0) <= 1e-12 * scale, key
+        scd = max(1.0, np.abs(wantd[key][cf]).max()) if cf.any() else 1.0
+        assert np.abs(gotd[key][cf] - wantd[key][cf]).max(initial=0.0) <= 1e-11 * scd, key
+        assert np.all(got[key][phys] == 123.0) and np.all(gotd[key][phys] == 123.0), key
+        n += int(cf.sum())
+    assert n > 20
+
+
+@pytest.mark.parametrize("name", ["2d", "3d"])
+def test_correction_against_oracle(name):
+    OH, H = build(name)
+    fine = OH.levels[1]
+    D = fine.dim
+    rng = np.random.default_rng(4)
+    fdv = []
+    for d in range(D):
+        per = fine.zero_face_data()
+        for key in per:
+            e = fine.row_end(*key)
+            per[key][e] = rng.normal(size=int(e.sum()))
+        fdv.append(per)
+    want, wdelta = cic.cic_correct(fine, fdv)
+    devs = [faces_to_dev(H, 1, fine, fdv[d]) for d in range(D)]
+    delta = H.cic_correct(1, devs)
+    torch.cuda.synchronize()
+    # component ids: the library's box table against the oracle's labels
+    lab = {}
+    for b in H.boxes(1, 0):
+        sl = tuple(slice(PAD + lo, PAD + hi + 1) for lo, hi in zip(b["lo"], b["hi"]))
+        lab[b["comp"]] = int(np.unique(fine.labels[sl])[0])
+    for cg, co in lab.items():
+        assert abs(delta[cg] - wdelta[co]) <= 1e-13 * max(1.0, abs(wdelta[co])), (cg, delta, wdelta)
+    for d in range(D):
+        got = faces_from_dev(H, 1, fine, devs[d])
+        for key in got:
+            e = fine.row_end(*key)
+            assert np.abs(got[key][e] - want[d][key][e]).max() <= 1e-13 * (1 + np.abs(want[d][key][e]).max())
+    # the corrected data satisfy the compatibility condition
+    after = cic.compatibility_defects(fine, [faces_from_dev(H, 1, fine, devs[d]) for d in range(D)])
+    assert np.abs(after).max() < 1e-12
+
+
+def test_interface_conditions_feed_the_level_solve():
+    """A refined level's Helmholtz solve with coarse-fine face data computed
+    by the pipeline from the coarse cell averages of a polynomial (degree <= 3
+    per direction, steady in time): the face data are exact, so the solve
+    reproduces the polynomial's cell averages."""
+    c = 0.01
+    OH, H = build("2d_dir", op=A.HELMHOLTZ, c=c)
+    coarse, fine = OH.levels
+    P, Q = Poly1([0.3, -0.8, 1.2, 0.5]), Poly1([-0.2, 0.6, 0.9, -0.7])
+
+    def avgs(lev, p, q):
+        a = lev.zeros()
+        a[lev.inner] = np.multiply.outer(p.avg(0.0, lev.h, lev.shape[0]), q.avg(0.0, lev.h, lev.shape[1]))
+        return np.where(lev.mask, a, 0.0)
+
+    u = avgs(fine, P, Q)
+    f = u - c * (avgs(fine, P.d2(), Q) + avgs(fine, P, Q.d2()))
+    hist = [to_dev(H, 0, 0, avgs(coarse, P, Q)) for _ in range(4)]
+    nface = H.level_info(1).nface
+    fd = torch.zeros(nface, dtype=torch.float64, device="cuda")
+    H.cic_face_data(1, hist, 0.1, 0.05, fd)
+    # physical faces of the fine level: face averages of the same polynomial
+    lvl = Level(fine.shape, fine.h, fine.boxes, fine.phys_bc, "D")
+    fdict = faces_from_dev(H, 1, lvl, fd)
+    for d in range(2):
+        for s in (0, 1):
+            for pos in np.argwhere(lvl.end_is_physical(d, s)):
+                e = pos - PAD
+                xf = (e[d] + s) * lvl.h
+                along, across = (P, Q) if d == 0 else (Q, P)
+                fdict[(d, s)][tuple(pos)] = along.val(xf) * float(across.avg(e[1 - d] * lvl.h, lvl.h, 1)[0])
+    fdd = faces_to_dev(H, 1, lvl, fdict)
+    fdev = to_dev(H, 1, 0, f)
+    x = torch.zeros_like(fdev)
+    st = H.solve(1, x, fdev, fdd, A.default_opts(precision=A.FP64, tol_rel=1e-13, max_cycles=100))
+    assert st["status"] == 0 and st["converged"], st
+    got = from_dev(H, 1, 0, x, lvl)
+    assert relerr(got, u, lvl.mask) < 1e-10
+    # and the oracle's level solve with the same face data agrees
+    x_or, _ = mg.solve(lvl, f, "helmholtz", c, fdict, tol_rel=1e-13, max_cycles=100)
+    assert relerr(got, x_or, lvl.mask) < 1e-11
