@@ -98,7 +98,8 @@ class Hierarchy:
 
     base_shape : cells of level 0 per direction; h0 its cell size
     boxes      : list per level of (lo, hi) boxes (level 0 covers the grid)
-    phys_bc    : {(d, s): 'D' | 'N'}
+    phys_bc    : {(d, s): 'D' | 'N' | 'P'} (a level above 0 may not touch a
+                 periodic side)
     """
 
     def __init__(self, base_shape, h0, boxes, phys_bc):
@@ -277,7 +278,7 @@ class Hierarchy:
         return tot / vol
 
     def singular(self, op):
-        return op == "poisson" and all(v == "N" for v in self.levels[0].phys_bc.values())
+        return op == "poisson" and all(v in ("N", "P") for v in self.levels[0].phys_bc.values())
 
     def solvability_shift(self, f, fd):
         """Shift every level's right-hand side by one constant so that the
@@ -289,7 +290,7 @@ class Hierarchy:
                 break
             for d in range(D):
                 for s in (0, 1):
-                    phys = lev.end_is_physical(d, s)
+                    phys = lev.end_is_physical(d, s) & (lev.end_kind(d, s) != "P")
                     bsum += fd[l][(d, s)][phys & self.valid[l]].sum() * lev.h ** (D - 1)
         vol = sum(self.valid[l].sum() * self.levels[l].h ** D for l in range(self.nlev))
         tot = sum(f[l][self.valid[l]].sum() * self.levels[l].h ** D for l in range(self.nlev))

@@ -33,7 +33,7 @@ import numpy as np
 
 from . import fv, mg
 from .amr import _W, window_shift
-from .level import NEUMANN, DIRICHLET, PAD, _shift
+from .level import NEUMANN, DIRICHLET, PAD, PERIODIC, _shift, _wrap
 
 
 def _scatter_fill(lev, Gbar, back):
@@ -58,6 +58,11 @@ def _scatter_fill(lev, Gbar, back):
                     continue
                 for j in range(4):
                     back += _shift(np.where(sel, w[j][0] * mu1 + w[j][1] * mu2, 0.0), d, j * step)
+            # periodic ghosts copy the cells one and two steps on (mod n)
+            sel = end & (kinds == PERIODIC)
+            if sel.any():
+                back += _wrap(np.where(sel, mu1, 0.0), d, -step)
+                back += _wrap(np.where(sel, mu2, 0.0), d, -2 * step)
 
 
 def _interp_ghost_adjoint(lev, Gbar):

@@ -21,6 +21,12 @@ directly from the array (the exchange ghosts of Figure 1(c)).
 Face data ``fd[(d, s)]`` holds, at the row-end cell e, the face average on
 the face between e and e + s*e_d: the Dirichlet value, or the derivative
 along the outward normal for Neumann (eqs. velBCHomoDiri5th, Neumann5).
+
+Periodic boundaries (the domains of Section 7.3) pair the two sides of a
+direction: a row end on such a side is kind 'P', and its first and second
+ghosts are the cells of the level at e + s*e_d and e + 2s*e_d taken modulo
+the grid size (cells of the level there are required); components connect
+across the periodic boundary.
 """
 import numpy as np
 from scipy import ndimage
@@ -28,7 +34,7 @@ from scipy import ndimage
 from . import fv
 
 PAD = 2
-DIRICHLET, NEUMANN, INTERP = "D", "N", "I"
+DIRICHLET, NEUMANN, INTERP, PERIODIC = "D", "N", "I", "P"
 
 
 def _shift(a, d, k):
@@ -37,13 +43,23 @@ def _shift(a, d, k):
     return np.roll(a, -k, axis=d)
 
 
+def _wrap(a, d, k):
+    """b[i] = a[(i + k e_d) mod n] on the domain part of a padded array (the
+    pad stays zero): the periodic neighbour."""
+    inner = tuple(slice(PAD, -PAD) for _ in range(a.ndim))
+    out = np.zeros_like(a)
+    out[inner] = np.roll(a[inner], -k, axis=d)
+    return out
+
+
 class Level:
     """One level of the hierarchy, or one multigrid depth of one level.
 
     shape   : cells per direction of the level's whole grid (the domain)
     h       : cell size
     boxes   : list of (lo, hi) inclusive index tuples, eq. (AMRHier)
-    phys_bc : {(d, s): 'D' | 'N'} for the physical boundary, s = 0 low, 1 high
+    phys_bc : {(d, s): 'D' | 'N' | 'P'} for the physical boundary, s = 0 low,
+              1 high; 'P' (periodic) on both sides of a direction or neither
     cf_kind : 'D' | 'N' (face data on the coarse-fine interface, Definition
               6.1) or 'I' (ghosts from coarse-fine interpolation)
     """
@@ -54,6 +70,10 @@ class Level:
         self.h = float(h)
         self.boxes = [(tuple(int(v) for v in lo), tuple(int(v) for v in hi)) for lo, hi in boxes]
         self.phys_bc = dict(phys_bc)
+        self.periodic = [d for d in range(self.dim) if self.phys_bc[(d, 0)] == PERIODIC]
+        for d in range(self.dim):
+            if (self.phys_bc[(d, 0)] == PERIODIC) != (self.phys_bc[(d, 1)] == PERIODIC):
+                raise ValueError("periodic on one side of direction %d only" % d)
         self.cf_kind = cf_kind
         self.pshape = tuple(n + 2 * PAD for n in self.shape)
         self.inner = tuple(slice(PAD, PAD + n) for n in self.shape)
@@ -69,6 +89,41 @@ class Level:
         self._check_rows()
         self.labels, self.ncomp = ndimage.label(self.mask)  # face connectivity
         self.labels = self.labels - 1  # -1 outside the level, else 0..ncomp-1
+        if self.periodic:
+            self._join_periodic()
+            for d in self.periodic:
+                for s in (0, 1):
+                    step = 1 if s else -1
+                    pend = self.end_is_physical(d, s)
+                    for k in (1, 2):
+                        if np.any(pend & ~_wrap(self.mask, d, k * step)):
+                            raise ValueError("a periodic ghost of direction %d is not a cell of the level" % d)
+
+    def _join_periodic(self):
+        """Merge the labels of cells that face each other across a periodic
+        boundary (first and last cell of a row along that direction)."""
+        par = list(range(self.ncomp))
+
+        def find(x):
+            while par[x] != x:
+                x = par[x]
+            return x
+
+        for d in self.periodic:
+            lo = [slice(None)] * self.dim
+            hi = [slice(None)] * self.dim
+            lo[d], hi[d] = PAD, PAD + self.shape[d] - 1
+            a, b = self.labels[tuple(lo)], self.labels[tuple(hi)]
+            both = (a >= 0) & (b >= 0)
+            for x, y in zip(a[both], b[both]):
+                rx, ry = find(int(x)), find(int(y))
+                if rx != ry:
+                    par[max(rx, ry)] = min(rx, ry)
+        roots = sorted({find(c) for c in range(self.ncomp)})
+        new = {r: i for i, r in enumerate(roots)}
+        remap = np.array([new[find(c)] for c in range(self.ncomp)] + [-1])
+        self.labels = remap[self.labels]  # -1 indexes the trailing -1
+        self.ncomp = len(roots)
 
     # ------------------------------------------------------------------
     # bookkeeping
@@ -94,7 +149,8 @@ class Level:
                         raise ValueError("a row of cells is shorter than 4")
 
     def end_kind(self, d, s):
-        """Array of fill kinds at row ends: 'D', 'N' or 'I' (None elsewhere)."""
+        """Array of fill kinds at row ends: 'D', 'N', 'P' or 'I' (None
+        elsewhere)."""
         phys = self.end_is_physical(d, s)
         end = self.row_end(d, s)
         kinds = np.full(self.pshape, None, dtype=object)
@@ -124,13 +180,14 @@ class Level:
 
     # ------------------------------------------------------------------
     # ghost fill (Section 3, eqs. velBCHomoDiri5th and Neumann5)
-    def ghosts(self, u, fd=None, cfv=None):
+    def ghosts(self, u, fd=None, cfv=None, wrap=True):
         """Ghost arrays G[(d, s)] for the padded level array u.
 
-        fd  : face data as described in the module docstring (None = zero,
-              the homogeneous fill used for corrections)
-        cfv : padded array of coarse-fine interpolated ghost values for
-              row ends of kind 'I' (None = zero)
+        fd   : face data as described in the module docstring (None = zero,
+               the homogeneous fill used for corrections)
+        cfv  : padded array of coarse-fine interpolated ghost values for
+               row ends of kind 'I' (None = zero)
+        wrap : False leaves the ghosts of periodic row ends at zero
         """
         G = {}
         for d in range(self.dim):
@@ -151,6 +208,10 @@ class Level:
                 isn = end & (kinds == NEUMANN)
                 first[isd], second[isd] = gd1[isd], gd2[isd]
                 first[isn], second[isn] = gn1[isn], gn2[isn]
+                isp = end & (kinds == PERIODIC)
+                if wrap and isp.any():
+                    first[isp] = _wrap(u, d, step)[isp]
+                    second[isp] = _wrap(u, d, 2 * step)[isp]
                 Gs = _shift(first, d, -step) + _shift(second, d, -2 * step)
                 isi = end & (kinds == INTERP)
                 if cfv is not None and isi.any():
@@ -238,6 +299,12 @@ class Level:
                     for j in range(4):
                         contrib = np.where(sel, w[j][0] * mu1 + w[j][1] * mu2, 0.0)
                         back += _shift(contrib, d, j * step)
+                # a periodic ghost copies the cell one or two steps on,
+                # modulo the grid: its adjoint goes back to that cell
+                sel = end & (kinds == PERIODIC)
+                if sel.any():
+                    back += _wrap(np.where(sel, mu1, 0.0), d, -step)
+                    back += _wrap(np.where(sel, mu2, 0.0), d, -2 * step)
         back[~self.mask] = 0.0
         if op == "helmholtz":
             out = lam - c * (Ltl + back)
@@ -252,13 +319,15 @@ class Level:
         """Coefficient of u_i in (A u)_i with the homogeneous ghost fill
         folded in.  Obtained by probing: along direction d the folded 1-D
         operator couples cells at most 3 apart, so unit vectors on every 7th
-        cell of a row cannot disturb each other's diagonal entries."""
+        cell of a row cannot disturb each other's diagonal entries.  A
+        periodic ghost is a copy of another cell (rows have at least 4
+        cells), so it carries no diagonal part and is left at zero."""
         idx = np.indices(self.pshape)
         Ldiag = self.zeros()
         for d in range(self.dim):
             for colour in range(7):
                 probe = (self.mask & (idx[d] % 7 == colour)).astype(float)
-                G = self.ghosts(probe)
+                G = self.ghosts(probe, wrap=False)
                 col = self.laplacian(probe, G, dirs=[d])
                 sel = probe > 0
                 Ldiag[sel] += col[sel]

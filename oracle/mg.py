@@ -174,7 +174,7 @@ def solvability_shift(lev, f, fd, comps):
     bsum = np.zeros(lev.ncomp)
     for d in range(lev.dim):
         for s in (0, 1):
-            end = lev.row_end(d, s)
+            end = lev.row_end(d, s) & (lev.end_kind(d, s) != "P")  # periodic ends take no data
             if fd is not None:
                 np.add.at(bsum, lev.labels[end], fd[(d, s)][end] * lev.h ** (lev.dim - 1))
     out = f.copy()

@@ -54,15 +54,20 @@ def divergence(lev, W, wb=None, cfvs=None):
     return np.where(lev.mask, out, 0.0)
 
 
+def _keep_periodic(bc, kind):
+    return {k: ("P" if v == "P" else kind) for k, v in bc.items()}
+
+
 def velocity_level(lev):
-    """The same boxes with Dirichlet conditions everywhere (the velocity's
-    fill)."""
-    return Level(lev.shape, lev.h, lev.boxes, {k: "D" for k in lev.phys_bc}, "D")
+    """The same boxes with Dirichlet conditions on every non-periodic side
+    (the velocity's fill)."""
+    return Level(lev.shape, lev.h, lev.boxes, _keep_periodic(lev.phys_bc, "D"), "D")
 
 
 def pressure_level(lev):
-    """The same boxes with Neumann conditions everywhere (phi's fill)."""
-    return Level(lev.shape, lev.h, lev.boxes, {k: "N" for k in lev.phys_bc}, "N")
+    """The same boxes with Neumann conditions on every non-periodic side
+    (phi's fill)."""
+    return Level(lev.shape, lev.h, lev.boxes, _keep_periodic(lev.phys_bc, "N"), "N")
 
 
 def project(lev, W, wb=None, tol_rel=1e-12, max_cycles=200, smoother="jacobi"):
@@ -78,10 +83,10 @@ def project(lev, W, wb=None, tol_rel=1e-12, max_cycles=200, smoother="jacobi"):
 # ---------------------------------------------------------------------------
 # composite (hierarchy) forms
 def hierarchy_with(H, kind):
-    """A hierarchy with H's boxes and every physical condition set to kind."""
+    """A hierarchy with H's boxes and every non-periodic physical condition
+    set to kind."""
     boxes = [lev.boxes for lev in H.levels]
-    return amr.Hierarchy(H.levels[0].shape, H.levels[0].h, boxes,
-                         {k: kind for k in H.levels[0].phys_bc})
+    return amr.Hierarchy(H.levels[0].shape, H.levels[0].h, boxes, _keep_periodic(H.levels[0].phys_bc, kind))
 
 
 def composite_gradient(Hp, Phi):
