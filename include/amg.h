@@ -71,6 +71,7 @@ extern "C" {
 /* boundary condition types */
 #define AMG_DIRICHLET 0
 #define AMG_NEUMANN 1
+#define AMG_PERIODIC 2 /* both sides of a direction; the domains of Section 7.3 */
 
 /* coarse-fine modes of a level */
 #define AMG_CF_DIRICHLET 0 /* face averages given on the coarse-fine interface */
@@ -199,12 +200,16 @@ int amg_set_level_boxes(amg_hier* h, int level, int nboxes, const int32_t* lo, c
 int amg_set_isolated_boxes(amg_hier* h, int level, int isolated);
 
 /* Physical condition on the domain face (d, side), side 0 = low, 1 = high:
- * AMG_DIRICHLET (face averages of the value, eq. velBCHomoDiri5th) or
+ * AMG_DIRICHLET (face averages of the value, eq. velBCHomoDiri5th),
  * AMG_NEUMANN (face averages of the outward normal derivative, eq.
  * Neumann5), the assignment of the boundary conditions to the velocity and
- * pressure systems in Section 4 (default Dirichlet on every face).  Set
- * before amg_finalize.  Errors: AMG_EINVAL (d, side or type out of range,
- * layout final). */
+ * pressure systems in Section 4, or AMG_PERIODIC (the periodic domains of
+ * Section 7.3: a ghost beyond the side is the cell at its index modulo the
+ * grid size, no face data).  Default Dirichlet on every face.  Set before
+ * amg_finalize.  Errors: AMG_EINVAL (d, side or type out of range, layout
+ * final); amg_finalize returns AMG_EINVAL when a direction is periodic on
+ * one side only, and AMG_EUNSUPPORTED when a level above 0 touches a
+ * periodic side or a level of isolated boxes has a periodic direction. */
 int amg_set_physical_bc(amg_hier* h, int d, int side, int type);
 
 /* Coarse-fine mode of a level > 0 (default AMG_CF_DIRICHLET): the condition

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libamg.so")
 
 OK, EINVAL, ELAYOUT, EUNSUPPORTED, ENOTCONVERGED, ENONFINITE, ESOLVABILITY, EDEVICE = range(8)
 HELMHOLTZ, POISSON = 0, 1
-DIRICHLET, NEUMANN = 0, 1
+DIRICHLET, NEUMANN, PERIODIC = 0, 1, 2
 CF_DIRICHLET, CF_NEUMANN, CF_INTERP = 0, 1, 2
 SMOOTH_JACOBI, SMOOTH_RB = 0, 1
 FP64, MIXED = 0, 1

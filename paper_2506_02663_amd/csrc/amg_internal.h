@@ -204,6 +204,8 @@ struct Depth {
   bool split_rb = false;   // colour-split storage (k_rbs) applies to this depth
   bool uniform_fill = false;  // every face of every box filled uniformly from its own rows, both ghost layers
   int march = 2;  // cells each tile marches along the last direction
+  int32_t dn[3] = {1, 1, 1};  // cells of the grid per direction at this depth
+  bool periodic[3] = {false, false, false};
   // device copies
   BoxD* d_box = nullptr;
   uint8_t* d_codes = nullptr;

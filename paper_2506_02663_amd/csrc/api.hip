@@ -776,7 +776,7 @@ int amg_set_isolated_boxes(amg_hier* H, int level, int isolated) {
 int amg_set_physical_bc(amg_hier* H, int d, int side, int type) {
   if (!H) return AMG_EINVAL;
   if (H->finalized) return fail(H, AMG_EINVAL, "layout is final");
-  if (d < 0 || d >= H->dim || side < 0 || side > 1 || (type != AMG_DIRICHLET && type != AMG_NEUMANN))
+  if (d < 0 || d >= H->dim || side < 0 || side > 1 || (type != AMG_DIRICHLET && type != AMG_NEUMANN && type != AMG_PERIODIC))
     return fail(H, AMG_EINVAL, "bad boundary condition");
   H->phys_bc[d][side] = type;
   return AMG_OK;

@@ -177,6 +177,7 @@ int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats
                     const Box& C = D.boxes[j];
                     int g[3] = {B.lo[0] + x, B.lo[1] + y, B.lo[2] + z};
                     g[d] = B.lo[d] + p;
+                    if (D.periodic[d]) g[d] = ((g[d] % D.dn[d]) + D.dn[d]) % D.dn[d];
                     if (start[j] < 0) {
                       err = "exchange source outside the bottom system";
                       return AMG_EUNSUPPORTED;

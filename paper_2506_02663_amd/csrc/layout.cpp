@@ -10,6 +10,12 @@
 // has even corners and even sides of at least 8 (an isolated box: even sides
 // of at least 8) and, with a bottom size B set, while some component (an
 // isolated box) has more than B cells.
+//
+// Periodic directions (the domains of Section 7.3) pair the two sides of the
+// grid: a ghost beyond a periodic side is an exchange ghost whose source is
+// the cell at its index modulo the grid size, and boxes touching across the
+// side are face-connected.  Level 0 covers its grid, so every such source is
+// a cell; a finer level may not touch a periodic side.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -44,6 +50,18 @@ bool touch(const Box& a, const Box& b, int dim) {
   return false;
 }
 
+// face contact across a periodic side of direction d (grid size n): a ends
+// at the last cell, b starts at cell 0 (or the other way round), overlapping
+// with positive extent in all other directions
+bool touch_periodic(const Box& a, const Box& b, int dim, int d, int64_t n) {
+  if (!((a.hi[d] == n - 1 && b.lo[d] == 0) || (b.hi[d] == n - 1 && a.lo[d] == 0))) return false;
+  for (int e = 0; e < dim; ++e)
+    if (e != d && std::max(a.lo[e], b.lo[e]) > std::min(a.hi[e], b.hi[e])) return false;
+  return true;
+}
+
+int64_t wrap(int64_t p, int64_t n) { return ((p % n) + n) % n; }
+
 bool overlap(const Box& a, const Box& b, int dim) {
   for (int d = 0; d < dim; ++d)
     if (std::max(a.lo[d], b.lo[d]) > std::min(a.hi[d], b.hi[d])) return false;
@@ -76,6 +94,20 @@ int plan_level(amg_hier* H, int l, std::string& err) {
   }
   int64_t gn[3] = {1, 1, 1};
   for (int d = 0; d < dim; ++d) gn[d] = grid_cells(H, l, d);
+  bool per[3] = {false, false, false};
+  for (int d = 0; d < dim; ++d) {
+    const bool p0 = H->phys_bc[d][0] == AMG_PERIODIC, p1 = H->phys_bc[d][1] == AMG_PERIODIC;
+    if (p0 != p1) {
+      snprintf(buf, sizeof buf, "direction %d is periodic on one side only", d);
+      err = buf;
+      return AMG_EINVAL;
+    }
+    per[d] = p0;
+    if (per[d] && L.isolated) {
+      err = "isolated boxes with periodic conditions are not supported";
+      return AMG_EUNSUPPORTED;
+    }
+  }
 
   // ---- validation -----------------------------------------------------------
   int64_t vol = 0;
@@ -92,6 +124,11 @@ int plan_level(amg_hier* H, int l, std::string& err) {
         snprintf(buf, sizeof buf, "box %d leaves the grid of level %d", b, l);
         err = buf;
         return AMG_ELAYOUT;
+      }
+      if (l > 0 && per[d] && (B.lo[d] == 0 || B.hi[d] == gn[d] - 1)) {
+        snprintf(buf, sizeof buf, "box %d of level %d touches the periodic side of direction %d", b, l, d);
+        err = buf;
+        return AMG_EUNSUPPORTED;
       }
       if (l > 0 && !L.isolated && (B.lo[d] % H->ratio || (B.hi[d] + 1) % H->ratio)) {
         snprintf(buf, sizeof buf, "box %d of level %d is not properly refined (corners not multiples of %d)", b, l,
@@ -154,6 +191,11 @@ int plan_level(amg_hier* H, int l, std::string& err) {
     for (int a = 0; a < nb; ++a)
       for (int b = a + 1; b < nb; ++b)
         if (touch(L.boxes[a], L.boxes[b], dim)) par[find(par, a)] = find(par, b);
+  for (int d = 0; d < dim; ++d)
+    if (per[d])
+      for (int a = 0; a < nb; ++a)
+        for (int b = a + 1; b < nb; ++b)
+          if (touch_periodic(L.boxes[a], L.boxes[b], dim, d, gn[d])) par[find(par, a)] = find(par, b);
   std::vector<int> root_id(nb, -1);
   L.box_comp.assign(nb, 0);
   L.ncomp = 0;
@@ -298,6 +340,10 @@ int plan_level(amg_hier* H, int l, std::string& err) {
     // domain at this depth
     int64_t dn[3] = {1, 1, 1};
     for (int d = 0; d < dim; ++d) dn[d] = gn[d] >> k;
+    for (int d = 0; d < 3; ++d) {
+      D.dn[d] = (int32_t)dn[d];
+      D.periodic[d] = per[d];
+    }
 
     // ---- ghost-column classification ----
     D.faces.assign((size_t)nbk * 6, FaceCols());
@@ -312,7 +358,7 @@ int plan_level(amg_hier* H, int l, std::string& err) {
           FaceCols& fc = D.faces[i * 6 + d * 2 + s];
           size_t area = (size_t)n0 * n1;
           int p1 = s ? B.hi[d] + 1 : B.lo[d] - 1;
-          bool phys = L.isolated ? true : (p1 < 0 || p1 >= dn[d]);
+          bool phys = L.isolated ? true : ((p1 < 0 || p1 >= dn[d]) && !per[d]);
           uint8_t kk = phys ? ((H->phys_bc[d][s] == AMG_DIRICHLET) ? G_FILL_D : G_FILL_N) : gk1;
           fc.k1.assign(area, kk);
           fc.k2.assign(area, kk);
@@ -321,8 +367,10 @@ int plan_level(amg_hier* H, int l, std::string& err) {
           if (L.isolated || phys) continue;
           for (int layer = 1; layer <= 2; ++layer) {
             int p = s ? B.hi[d] + layer : B.lo[d] - layer;
+            const bool wrapped = p < 0 || p >= dn[d];  // beyond a periodic side
+            if (wrapped) p = (int)wrap(p, dn[d]);
             for (int j = 0; j < nbk; ++j) {
-              if (j == i) continue;
+              if (j == i && !wrapped) continue;
               const Box& C = D.boxes[j];
               if (p < C.lo[d] || p > C.hi[d]) continue;
               int a0 = std::max(B.lo[t[0]], C.lo[t[0]]), b0 = std::min(B.hi[t[0]], C.hi[t[0]]);
@@ -442,12 +490,14 @@ int plan_level(amg_hier* H, int l, std::string& err) {
               ch.kind2 = fc.k2[col];
               ch.src1 = ch.src2 = -1;
               if (fc.src1[col] >= 0) {
-                ch.src1 = addr(fc.src1[col], g[0], g[1], g[2]);
+                int g1[3] = {g[0], g[1], g[2]};
+                g1[d] = (int)wrap(g1[d], dn[d]);
+                ch.src1 = addr(fc.src1[col], g1[0], g1[1], g1[2]);
                 ch.sstride1 = D.boxd[fc.src1[col]].s[t[0]];
               }
               if (fc.src2[col] >= 0) {
                 int g2[3] = {g[0], g[1], g[2]};
-                g2[d] += step;
+                g2[d] = (int)wrap(g2[d] + step, dn[d]);
                 ch.src2 = addr(fc.src2[col], g2[0], g2[1], g2[2]);
                 ch.sstride2 = D.boxd[fc.src2[col]].s[t[0]];
               }

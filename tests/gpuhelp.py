@@ -29,7 +29,7 @@ def make_hier(lev, op, c, cf_mode=None, bottom_cells=0):
         H.set_cf_mode(1, mode)
     H.set_level_boxes(index, lev.boxes)
     for (d, s), kind in lev.phys_bc.items():
-        H.set_physical_bc(d, s, A.DIRICHLET if kind == "D" else A.NEUMANN)
+        H.set_physical_bc(d, s, {"D": A.DIRICHLET, "N": A.NEUMANN, "P": A.PERIODIC}[kind])
     H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c)
     if bottom_cells:
         H.set_bottom_cells(bottom_cells)
@@ -117,6 +117,7 @@ def unit_level(n, D, bc):
 
 
 MIXED_BC = {(0, 0): "D", (0, 1): "N", (1, 0): "N", (1, 1): "D"}
+PERIODIC_X_BC = {(0, 0): "P", (0, 1): "P", (1, 0): "D", (1, 1): "N"}
 
 
 def tiled_level(n=32, D=2, bc="D"):

@@ -114,6 +114,9 @@ def _finalize_code(L, h):
     ("not_nested", "ELAYOUT", "not nested"),
     ("cfi_window_off_coarse", "EUNSUPPORTED", "interpolation window"),
     ("empty_level", "ELAYOUT", "no boxes"),
+    ("periodic_one_side", "EINVAL", "periodic on one side only"),
+    ("periodic_fine_touches_side", "EUNSUPPORTED", "touches the periodic side"),
+    ("periodic_isolated", "EUNSUPPORTED", "isolated boxes with periodic"),
 ])
 def test_layout_rejected_before_any_device_call(lib, case, want, text):
     from paper_2506_02663_amd import amg as A
@@ -138,6 +141,14 @@ def test_layout_rejected_before_any_device_call(lib, case, want, text):
         h = _layout(L, 2, 32, [full, [((16, 16), (47, 47))], [((34, 34), (61, 61))]], cf=A.CF_INTERP)
     elif case == "empty_level":
         h = _layout(L, 2, 32, [full, []])
+    elif case == "periodic_one_side":
+        h = _layout(L, 2, 32, [full])
+        assert L.amg_set_physical_bc(h, 1, 0, A.PERIODIC) == A.OK
+    elif case == "periodic_fine_touches_side":
+        h = _layout(L, 2, 32, [full, [((0, 16), (15, 31))]], bc=A.PERIODIC)
+    elif case == "periodic_isolated":
+        h = _layout(L, 2, 32, [full], bc=A.PERIODIC)
+        assert L.amg_set_isolated_boxes(h, 0, 1) == A.OK
     rc, msg = _finalize_code(L, h)
     assert rc == getattr(A, want), (case, rc, msg)
     assert text in msg, (case, msg)

@@ -4,7 +4,8 @@ operator element by element on every kind of ghost, one adjoint V-cycle
 and mixed precision, the Laplacian and dot product behind dJ/dc, the
 autograd binding against the oracle's gradients and against finite
 differences of GPU solves, batched isolated boxes, and a coefficient change
-on a finalized hierarchy."""
+on a finalized hierarchy.  Layouts include periodic ones (the transposed
+wrapped exchange)."""
 import numpy as np
 import pytest
 
@@ -18,7 +19,7 @@ from oracle import mg  # noqa: E402
 from oracle.level import Level  # noqa: E402
 from paper_2506_02663_amd import amg as A  # noqa: E402
 from paper_2506_02663_amd.autograd import level_solve  # noqa: E402
-from tests.gpuhelp import (MIXED_BC, cf_level, faces_to_dev, from_dev, gap_level, make_hier,  # noqa: E402
+from tests.gpuhelp import (MIXED_BC, PERIODIC_X_BC, cf_level, faces_to_dev, from_dev, gap_level, make_hier,  # noqa: E402
                            random_faces, random_field, relerr, tiled_level, to_dev, unit_level)
 
 TOL64 = 1e-11
@@ -38,6 +39,8 @@ LAYOUTS = {
     "3d_neu_tiled": lambda: tiled_level(16, 3, "N"),
     "3d_mixed": lambda: Level((16, 16, 16), 1 / 16, [((0, 0, 0), (15, 15, 15))],
                               {(0, 0): "D", (0, 1): "N", (1, 0): "N", (1, 1): "D", (2, 0): "N", (2, 1): "D"}),
+    "2d_periodic_tiled": lambda: tiled_level(32, 2, "P"),
+    "2d_periodic_x": lambda: unit_level(32, 2, PERIODIC_X_BC),
 }
 OPS = [("helmholtz", 0.37), ("poisson", 0.0)]
 
@@ -61,7 +64,7 @@ def test_apply_transpose(name, op, c0):
 
 
 @pytest.mark.parametrize("name", ["2d_dir", "2d_neu", "2d_mixed", "2d_small", "2d_cf_neu", "2d_gap", "3d_dir",
-                                  "3d_mixed"])
+                                  "3d_mixed", "2d_periodic_tiled", "2d_periodic_x"])
 @pytest.mark.parametrize("op,c0", OPS)
 @pytest.mark.parametrize("smoother", ["jacobi", "rb"])
 def test_adjoint_vcycle(name, op, c0, smoother):
@@ -79,7 +82,7 @@ def test_adjoint_vcycle(name, op, c0, smoother):
 
 
 @pytest.mark.parametrize("name", ["2d_dir", "2d_neu", "2d_mixed", "2d_tiled", "2d_cf_dir", "2d_cf_neu", "2d_gap",
-                                  "2d_ragged", "3d_dir", "3d_neu_tiled"])
+                                  "2d_ragged", "3d_dir", "3d_neu_tiled", "2d_periodic_tiled", "2d_periodic_x"])
 @pytest.mark.parametrize("op,c0", OPS)
 def test_adjoint_solve(name, op, c0):
     lev = LAYOUTS[name]()

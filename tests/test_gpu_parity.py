@@ -2,7 +2,9 @@
 element, through the C ABI (one multigrid step at a time, then whole
 V-cycles and solves).  Layouts span single boxes, box-to-box exchange,
 coarse-fine faces with two components, a one-cell gap between boxes one
-depth down, 2D and 3D, Dirichlet, Neumann and mixed conditions."""
+depth down, 2D and 3D, Dirichlet, Neumann, mixed and periodic conditions
+(wrapped exchange within a box and between boxes; the fully periodic
+Poisson system is singular)."""
 import numpy as np
 import pytest
 
@@ -14,7 +16,7 @@ if not torch.cuda.is_available():  # pragma: no cover
 
 from oracle import mg  # noqa: E402
 from paper_2506_02663_amd import amg as A  # noqa: E402
-from tests.gpuhelp import (MIXED_BC, cf_level, faces_to_dev, from_dev, gap_level, ghost_values,  # noqa: E402
+from tests.gpuhelp import (MIXED_BC, PERIODIC_X_BC, cf_level, faces_to_dev, from_dev, gap_level, ghost_values,  # noqa: E402
                            make_hier, random_faces, random_field, relerr, tiled_level, unit_level, to_dev)
 
 TOL64 = 1e-11
@@ -29,6 +31,10 @@ LAYOUTS = {
     "2d_gap": lambda: gap_level("D"),
     "3d_dir": lambda: unit_level(16, 3, "D"),
     "3d_neu_tiled": lambda: tiled_level(16, 3, "N"),
+    "2d_periodic": lambda: unit_level(32, 2, "P"),
+    "2d_periodic_tiled": lambda: tiled_level(32, 2, "P"),
+    "2d_periodic_x": lambda: unit_level(32, 2, PERIODIC_X_BC),
+    "3d_periodic_tiled": lambda: tiled_level(16, 3, "P"),
 }
 OPS = [("helmholtz", 0.37), ("poisson", 0.0)]
 
@@ -112,7 +118,8 @@ def test_residual_restriction_prolongation(name, op, c0):
     assert relerr(from_dev(H, L, 0, ud, lev), u + mg.prolong(coarse, ec, lev), lev.mask) < TOL64
 
 
-@pytest.mark.parametrize("name", ["2d_dir", "2d_neu", "2d_cf_neu", "3d_dir", "3d_neu_tiled"])
+@pytest.mark.parametrize("name", ["2d_dir", "2d_neu", "2d_cf_neu", "3d_dir", "3d_neu_tiled", "2d_periodic_tiled",
+                                  "2d_periodic_x", "3d_periodic_tiled"])
 @pytest.mark.parametrize("op,c0", OPS)
 def test_bottom_and_vcycle(name, op, c0):
     lev = LAYOUTS[name]()
@@ -143,7 +150,8 @@ def test_bottom_and_vcycle(name, op, c0):
 
 
 @pytest.mark.parametrize("name", ["2d_dir", "2d_neu", "2d_mixed", "2d_cf_dir", "2d_cf_neu", "2d_gap", "3d_dir",
-                                  "3d_neu_tiled"])
+                                  "3d_neu_tiled", "2d_periodic", "2d_periodic_tiled", "2d_periodic_x",
+                                  "3d_periodic_tiled"])
 @pytest.mark.parametrize("op,c0", OPS)
 def test_solve_fp64_and_mixed(name, op, c0):
     lev = LAYOUTS[name]()
@@ -175,7 +183,7 @@ def test_solve_fp64_and_mixed(name, op, c0):
             assert np.allclose(st["defects"], st_or["defects"], rtol=1e-9, atol=1e-12)
 
 
-@pytest.mark.parametrize("name", ["2d_cf_neu", "3d_dir"])
+@pytest.mark.parametrize("name", ["2d_cf_neu", "3d_dir", "2d_periodic_tiled"])
 def test_graph_replays_match_direct_launches_bitwise(name):
     """The captured outer cycle, replayed many times (with eager host work
     and synchronisations between solves), gives bit-identical iterates to
