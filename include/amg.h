@@ -558,6 +558,54 @@ int amg_cic_face_data(amg_hier* h, int level, const double* const* coarse, doubl
  * the stream).  Errors as amg_cic_face_data. */
 int amg_cic_correct(amg_hier* h, int level, double* const* face_data, double* delta, void* stream);
 
+/* ---- the IMEX time step on one periodic level (Section 4) -------------------
+ * One step of eq. GePUP-IMEX with the ERK-ESDIRK pair ARK4(3)6L[2]SA of
+ * Kennedy and Carpenter (2003, the scheme the paper cites; six stages,
+ * gamma = 1/4, stiffly accurate) for the system eq. ODE-MOL on a level that
+ * is one box covering a grid periodic in every direction (the domains of
+ * Section 7.3, where no boundary data enter).  Per stage s = 2..6: X of
+ * the previous stage from its velocity (convection eq. convOp, pressure
+ * from L q = D(g - Div<uu>), TLS-1), the Helmholtz systems
+ * (I - dt nu gamma L) w = w^n + dt sum A_E X + dt nu sum A_I L w per
+ * component (TLS-2), then u = P w (eq. appProj, TLS-3); after the last
+ * stage one more X, w* = w^(6) + dt sum (b - A_E[6]) X and u^(n+1) = P w*.
+ * hv: Helmholtz hierarchy of the velocity (its coefficient is set to
+ * dt nu / 4 by the call when it differs: bottom inverses are rebuilt on
+ * the host, see amg_set_coefficient); hp: Poisson hierarchy with the same
+ * box; both one level, periodic in every direction.  u[d]: packed FP64
+ * level buffers, u^n on entry (taken as w^n), u^(n+1) on return.  g: NULL
+ * (no forcing) or g[j*dim+d], the forcing's cell averages at t_n + c_j dt,
+ * j = 0..5 (c = 0, 1/2, 83/250, 31/50, 17/20, 1).  opts: every linear
+ * solve, each from a zero initial guess (its stopping test is then
+ * relative to its right-hand side).
+ * The library keeps (15 dim + 4) level buffers of stage storage in hv,
+ * allocated on the first call.  Not graph-capturable (it allocates on its
+ * first call and the solves synchronise).  Errors: AMG_EINVAL (null
+ * argument, dt <= 0, nu < 0, operators or layouts that differ),
+ * AMG_EUNSUPPORTED (not one periodic box on one level), errors of the
+ * solves; AMG_ENOTCONVERGED if a solve did not converge (u still holds the
+ * step's result). */
+/* out[d] = (Div<uu>)_d, the convection of eq. convOp: per direction the
+ * difference across the cell of the face averages of the product u_d u_e,
+ * each the product of the face averages (eq. cell2face) plus h^2/12 times
+ * the products of their centred transverse differences.  h: one level of
+ * one box on a grid periodic in every direction (neighbours wrap; ghosts
+ * are not read).  u[d], out[d]: packed FP64 level buffers, out not aliasing
+ * u; only cells are written.  Errors: AMG_EINVAL (null), AMG_EUNSUPPORTED
+ * (layout). */
+int amg_convection(amg_hier* h, double* const* u, double* const* out, void* stream);
+
+typedef struct {
+  int32_t solves;           /* linear solves run (TLS-1, TLS-2 per component, TLS-3) */
+  int32_t cycles;           /* outer cycles over all of them */
+  int32_t max_cycles;       /* most cycles of one solve */
+  int32_t converged;        /* 1 if every solve converged */
+  double max_rel_residual;  /* max over the solves of ||r||/||r0|| at return */
+} amg_imex_stats;
+
+int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, double* const* u, const double* const* g,
+                  const amg_solve_opts* opts, amg_imex_stats* stats, void* stream);
+
 /* Changes the Helmholtz coefficient c (> 0) of a finalized hierarchy: the
  * bottom inverses are recomputed on the host and captured graphs dropped.
  * Not on the hot path; AMG_EINVAL if the operator is not Helmholtz. */

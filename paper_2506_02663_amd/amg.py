@@ -56,6 +56,17 @@ class SolveStats(C.Structure):
                 "graph": bool(self.used_graph)}
 
 
+class ImexStats(C.Structure):
+    _fields_ = [("solves", C.c_int32), ("cycles", C.c_int32), ("max_cycles", C.c_int32), ("converged", C.c_int32),
+                ("max_rel_residual", C.c_double)]
+
+    def as_dict(self):
+        return {"solves": self.solves, "cycles": self.cycles, "max_cycles": self.max_cycles,
+                "converged": bool(self.converged), "max_rel_residual": self.max_rel_residual}
+
+
+IMEX_C = (0.0, 1 / 2, 83 / 250, 31 / 50, 17 / 20, 1.0)  # stage nodes of ARK4(3)6L[2]SA
+
 _lib = None
 
 
@@ -120,6 +131,8 @@ def lib():
         L.amg_divergence_transpose.argtypes = [vp, i32, i32, pp, pp, vp]
         L.amg_project_adjoint.argtypes = [vp, vp, i32, i32, pp, pp, pp, C.POINTER(SolveOpts), C.POINTER(SolveStats),
                                           vp]
+        L.amg_imex_step.argtypes = [vp, vp, dbl, dbl, pp, pp, C.POINTER(SolveOpts), C.POINTER(ImexStats), vp]
+        L.amg_convection.argtypes = [vp, pp, pp, vp]
         _lib = L
     return _lib
 
@@ -666,3 +679,35 @@ def project(Hw, Hp, ws, phis, us, wbs=None, opts=None, lev_lo=0):
     out = st.as_dict()
     out["status"] = rc
     return out
+
+
+def imex_step(Hv, Hp, dt, nu, us, gs=None, opts=None):
+    """One step of eq. GePUP-IMEX on one periodic box (see amg_imex_step):
+    us[d] holds u^n on entry and u^(n+1) on return; gs: None or gs[j][d],
+    the forcing at t_n + IMEX_C[j] dt.  Returns the stats and status."""
+    import torch
+    arr = Hv._comp_ptrs(0, [us])
+    g = None
+    if gs is not None:
+        if len(gs) != len(IMEX_C):
+            raise ValueError("the forcing needs one entry per stage")
+        g = (C.c_void_p * (len(IMEX_C) * Hv.dim))()
+        for j, per in enumerate(gs):
+            for d in range(Hv.dim):
+                Hv._need(per[d], 0, 0, "forcing", (torch.float64,))
+                g[j * Hv.dim + d] = per[d].data_ptr()
+    o = opts or default_opts()
+    st = ImexStats()
+    rc = lib().amg_imex_step(Hv.h, Hp.h, float(dt), float(nu), arr, g, C.byref(o), C.byref(st), _stream())
+    if rc and rc != ENOTCONVERGED:
+        Hv._check(rc)
+    out = st.as_dict()
+    out["status"] = rc
+    return out
+
+
+
+def convection(H, us, outs):
+    """outs[d] = (Div<uu>)_d of eq. convOp on one periodic box (see
+    amg_convection)."""
+    H._check(lib().amg_convection(H.h, H._comp_ptrs(0, [us]), H._comp_ptrs(0, [outs]), _stream()))
