@@ -11,7 +11,8 @@ cos(2 pi x) cos(2 pi y) cos(2 pi z) through L, plus seeded N(0, 1e-3^2)
 noise (the Poisson one made mean-free).  DOF per step = 2 * 256^3.
 
 Prints one JSON line.  --workload c1 runs the 2D 128^2 workload instead;
---workload c4 the batch of 1024 independent 2D boxes.
+--workload c4 the batch of 1024 independent 2D boxes; --workload imex one
+IMEX time step of the four-way vortex flow on a periodic 1024^2 level.
 """
 import argparse
 import json
@@ -31,7 +32,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
+    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "imex"])
     p.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     p.add_argument("--smoother", default="rb", choices=["jacobi", "rb"])
     p.add_argument("--n", type=int, default=0, help="cells per direction (default: the workload's)")
@@ -219,7 +220,7 @@ def oracle_residual(dim, n, op, bc, c, f, x):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the solver has no multi-GPU path in this build "
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
@@ -233,6 +234,8 @@ def main():
         tol = 1e-12  # the 2D single-level configuration's own tolerance
     elif args.workload == "c2":
         return bench_amr(args)
+    elif args.workload == "imex":
+        return bench_imex(args)
     else:
         return bench_batched(args)
 
@@ -551,6 +554,88 @@ def bench_amr(args):
                                "composite Neumann Poisson", "dof_per_step": 2 * nvalid, "tol_rel": 1e-10,
                    "cycles": cycles, "smoother": args.smoother, "precision": args.precision,
                    "omega_rb": w_rb if args.smoother == "rb" else None},
+    }
+    if base is not None:
+        out["cpu_baseline"] = base
+    print(json.dumps(out), flush=True)
+
+
+def bench_imex(args):
+    """The IMEX time step of eq. GePUP-IMEX on one periodic level: the
+    four-way vortex merging of Section 7.3 (periodic unit square, Re = 1000,
+    i.e. nu = 1e-3, Courant number 0.5) on n^2 cells, n = 1024 by default.
+    One step = 6 pressure solves, 10 Helmholtz solves and 6 projections
+    (tol_rel 1e-10, mixed precision unless --precision fp64); value = cell
+    updates per second (n^2 / step time)."""
+    import numpy as np
+    import torch
+
+    from paper_2506_02663_amd import amg as A
+    from paper_2506_02663_amd import workloads as W
+    n = args.n or 1024
+    nu, cr = 1e-3, 0.5
+    u, v = W.four_vortex_velocity(n)
+    h = 1.0 / n
+    dt = cr * h / max(np.abs(u).max(), np.abs(v).max())
+    base = None
+    if not args.no_cpu_baseline:
+        from oracle import imex
+        from oracle.level import Level
+        m = 64
+        lev = Level((m, m), 1.0 / m, [((0, 0), (m - 1, m - 1))], {(d, s): "P" for d in range(2) for s in (0, 1)})
+        us_, vs_ = W.four_vortex_velocity(m)
+        U = [lev.zeros(), lev.zeros()]
+        U[0][lev.inner], U[1][lev.inner] = us_, vs_
+        t0 = time.perf_counter()
+        imex.imex_step(lev, U, cr / m / max(np.abs(us_).max(), np.abs(vs_).max()), nu, tol_rel=1e-10)
+        el = time.perf_counter() - t0
+        base = {"value": m * m / el, "unit": "cell updates/s", "cores": 1, "kind": "oracle",
+                "sample": f"one IMEX step of the same flow on 64^2 cells, {el:.1f} s"}
+    prec = A.MIXED if args.precision == "mixed" else A.FP64
+    sm = A.SMOOTH_JACOBI if args.smoother == "jacobi" else A.SMOOTH_RB
+    opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100,
+                          use_graph=0 if args.no_graph else 1)
+    hs = []
+    for op in (A.HELMHOLTZ, A.POISSON):
+        H = A.Hierarchy(2, (n, n), h, 1)
+        H.set_level_boxes(0, [((0, 0), (n - 1, n - 1))])
+        for d in range(2):
+            for s in (0, 1):
+                H.set_physical_bc(d, s, A.PERIODIC)
+        H.set_operator(op, dt * nu / 4 if op == A.HELMHOLTZ else 0.0)
+        if args.bottom_cells:
+            H.set_bottom_cells(args.bottom_cells)
+        H.finalize()
+        hs.append(H)
+    Hv, Hp = hs
+    u0 = [torch.tensor(Hv.pack(0, 0, lambda i, b, a=a: a), device="cuda") for a in (u, v)]
+    us = [t.clone() for t in u0]
+    stats = {}
+
+    def step():
+        for t, t0_ in zip(us, u0):
+            t.copy_(t0_)
+        st = A.imex_step(Hv, Hp, dt, nu, us, None, opts)
+        if st["status"] != 0 or not st["converged"]:
+            raise RuntimeError(f"IMEX step failed: {st}")
+        stats.update(st)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {
+        "metric": "IMEX step cell updates/s (eq. GePUP-IMEX, ARK4(3)6L[2]SA, solves to 1e-10)",
+        "value": n * n * args.steps / el, "unit": "cell updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32-in-f64" if prec == A.MIXED else "f64", "data": "synthetic",
+        "config": {"workload": f"four-way vortex merging, periodic {n}^2, Re 1000, Cr 0.5, one IMEX step",
+                   "dt": dt, "solves": stats.get("solves"), "cycles": stats.get("cycles"),
+                   "max_cycles": stats.get("max_cycles"), "precision": args.precision, "smoother": args.smoother},
     }
     if base is not None:
         out["cpu_baseline"] = base

@@ -338,6 +338,8 @@ struct amg_hier {
   double c = 0;
   bool finalized = false;
   hipStream_t own = nullptr;  // used when the caller passes no stream
+  amg::GraphCache comp_graph;   // captured cycle of the composite solve
+  amg::GraphCache comp_graphT;  // the same for the composite adjoint solve
   double* imex_ws = nullptr;  // stage storage of the IMEX step (allocated on its first call)
   int64_t imex_len = 0;
   std::vector<amg::Level> levels;

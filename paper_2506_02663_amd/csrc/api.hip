@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -741,6 +742,9 @@ int amg_create(int dim, const double* x_lo, const double* x_hi, const int32_t* b
 int amg_destroy(amg_hier* H) {
   if (!H) return AMG_OK;
   for (auto& L : H->levels) L.graph.release();
+  for (auto& L : H->levels) L.graphT.release();
+  H->comp_graph.release();
+  H->comp_graphT.release();
   for (auto& e : H->timer.pool) (void)hipEventDestroy(e);
   for (auto& L : H->levels) free_level(L);
   if (H->imex_ws) (void)hipFree(H->imex_ws);
@@ -1201,6 +1205,48 @@ static int make_comp(amg_hier* H, int lev_lo, int lev_hi, double* const* x, cons
   return AMG_OK;
 }
 
+// Prepares the replay of one composite cycle (body) from a HIP graph
+// captured on C.st, keyed on everything its launches bake in: the levels'
+// buffers and the options (the coefficient and the timer release the graph
+// when they change).  Returns false when the cycle is to run as direct
+// launches (graphs off, timing on, or a capture that failed once).
+static bool comp_graph_ready(amg_hier* H, GraphCache& G, const Comp& C, const amg_solve_opts& o,
+                             const std::function<void()>& body) {
+  if (o.use_graph == 0 || G.broken || H->timer.on) return false;
+  std::vector<int64_t> key = {(int64_t)C.hi, o.precision, o.smoother, o.nu1, o.nu2, (int64_t)C.tr};
+  int64_t ob;
+  memcpy(&ob, &o.omega, sizeof ob);
+  key.push_back(ob);
+  memcpy(&ob, &o.omega_rb, sizeof ob);
+  key.push_back(ob);
+  for (int l = 0; l <= C.hi; ++l) {
+    key.push_back((int64_t)(intptr_t)C.X[l]);
+    key.push_back((int64_t)(intptr_t)C.R[l]);
+    key.push_back((int64_t)(intptr_t)C.F[l]);
+    key.push_back((int64_t)(intptr_t)C.FD[l]);
+  }
+  if (G.exec && G.key == key) return true;
+  G.release();
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(C.st, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    body();
+    e = hipStreamEndCapture(C.st, &g);
+  }
+  hipGraphExec_t ex = nullptr;
+  if (e == hipSuccess && g) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess || !ex) {
+    (void)hipGetLastError();
+    if (g) (void)hipGraphDestroy(g);
+    G.broken = true;  // direct launches from now on
+    return false;
+  }
+  G.graph = g;
+  G.exec = ex;
+  G.key = key;
+  return true;
+}
+
 static int composite_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x, const double* const* f,
                            const double* const* face_data, const amg_solve_opts* opts, amg_solve_stats* stats,
                            void* stream) {
@@ -1284,8 +1330,13 @@ static int composite_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x
     snprintf(buf, sizeof buf, "mean defect %.3e exceeds the stopping target %.3e", comp_defect_mean, target);
     return fail(H, AMG_ESOLVABILITY, buf);
   }
+  // the cycle is captured once into a HIP graph and replayed
+  const bool use_graph = comp_graph_ready(H, H->comp_graph, C, o, [&]() { comp_cycle(C, o); });
   while (rn > target && cycles < o.max_cycles) {
-    comp_cycle(C, o);
+    if (use_graph)
+      HIPCHK(hipGraphLaunch(H->comp_graph.exec, C.st));
+    else
+      comp_cycle(C, o);
     HIPCHK(hipGetLastError());
     TRY(read_norm(rn));
     ++cycles;
@@ -1296,6 +1347,7 @@ static int composite_solve(amg_hier* H, int lev_lo, int lev_hi, double* const* x
     stats->cycles = cycles;
     stats->rfinal = rn;
     stats->converged = rn <= target;
+    stats->used_graph = use_graph && cycles > 0;
   }
   if (rn > target) return fail(H, AMG_ENOTCONVERGED, "max_cycles reached");
   return AMG_OK;
@@ -1657,8 +1709,12 @@ int amg_solve_adjoint_composite(amg_hier* H, int lev_hi, double* const* lam, con
     stats->r0 = r0;
     stats->history[0] = r0;
   }
+  const bool use_graph = comp_graph_ready(H, H->comp_graphT, C, o, [&]() { comp_cycle_T(C, o); });
   while (rn > target && cycles < o.max_cycles) {
-    comp_cycle_T(C, o);
+    if (use_graph)
+      HIPCHK(hipGraphLaunch(H->comp_graphT.exec, C.st));
+    else
+      comp_cycle_T(C, o);
     HIPCHK(hipGetLastError());
     TRY(read_norm(rn));
     ++cycles;
@@ -1675,6 +1731,7 @@ int amg_solve_adjoint_composite(amg_hier* H, int lev_hi, double* const* lam, con
     stats->cycles = cycles;
     stats->rfinal = rn;
     stats->converged = rn <= target;
+    stats->used_graph = use_graph && cycles > 0;
   }
   if (rn > target) return fail(H, AMG_ENOTCONVERGED, "max_cycles reached");
   return AMG_OK;
@@ -1840,6 +1897,8 @@ int amg_set_coefficient(amg_hier* H, double c) {
     L.graph.release();
     L.graphT.release();
   }
+  H->comp_graph.release();
+  H->comp_graphT.release();
   return AMG_OK;
 }
 
@@ -2289,6 +2348,7 @@ int amg_timing_enable(amg_hier* H, int on) {
   if (!H) return AMG_EINVAL;
   H->timer.on = on != 0;
   for (auto& L : H->levels) L.graph.release();  // recapture with or without events
+  H->comp_graph.release();  // composite cycles run as direct launches while timing is on
   H->timer.pending.clear();
   H->timer.next = H->timer.base = 0;
   if (H->timer.on && H->timer.pool.empty()) {

@@ -192,3 +192,26 @@ def smooth_field_avg(lo, n, h, seed, nmodes=4):
         a = rng.normal()
         out += a * outer(avg_sin(p * math.pi, s, lo[0] * h, h, n[0]), avg_sin(q * math.pi, t, lo[1] * h, h, n[1]))
     return out
+
+
+def four_vortex_velocity(n):
+    """Initial velocity of the four-way vortex merging of Section 7.3 on the
+    periodic unit square, as values at the n^2 cell centres: the vorticity is
+    the sum of four tanh-profiled vortices (strengths -150, 50, 50, 50), the
+    stream function solves the periodic Poisson equation Delta psi = -omega
+    (by FFT of the point values: synthetic input data, not the method), and
+    u = (psi_y, -psi_x).  Returns (u, v) as n x n arrays indexed [x, y]."""
+    x = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    gam = [-150.0, 50.0, 50.0, 50.0]
+    ctr = [(0.5, 0.5), (0.59, 0.5), (0.455, 0.5 + 0.045 * math.sqrt(3)), (0.455, 0.5 - 0.045 * math.sqrt(3))]
+    om = sum(0.5 * g * (1 + np.tanh(3 - 100 * np.hypot(X - cx, Y - cy))) for g, (cx, cy) in zip(gam, ctr))
+    k = 2 * math.pi * np.fft.fftfreq(n, 1.0 / n)
+    KX, KY = np.meshgrid(k, k, indexing="ij")
+    k2 = KX ** 2 + KY ** 2
+    k2[0, 0] = 1.0
+    ph = np.fft.fft2(om) / k2
+    ph[0, 0] = 0.0
+    u = np.real(np.fft.ifft2(1j * KY * ph))
+    v = np.real(np.fft.ifft2(-1j * KX * ph))
+    return u, v

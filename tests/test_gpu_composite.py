@@ -142,3 +142,31 @@ def test_composite_solve_over_relaxed_red_black(name, bc, op, c):
         assert relmax(got, Uo, OH.valid) < tol, (prec, st["cycles"], sto["cycles"])
         if prec == A.FP64:
             assert abs(st["cycles"] - sto["cycles"]) <= 1
+
+
+@pytest.mark.parametrize("name,bc,op,c", [("two_level", "D", "helmholtz", 0.01), ("three_level", "N", "poisson", 0.0),
+                                          ("boundary", "N", "poisson", 0.0)])
+@pytest.mark.parametrize("prec", [A.FP64, A.MIXED])
+def test_composite_graph_replays_match_direct_launches_bitwise(name, bc, op, c, prec):
+    """The captured composite cycle, replayed (with eager host work and
+    synchronisations between solves), gives bit-identical iterates and
+    residual histories to direct launches, forward and adjoint."""
+    OH, base, h0, boxes = make_oracle(name, bc)
+    H = make_gpu(base, h0, boxes, bc, op, c)
+    f = random_levels(OH, 21)
+    fs = [to_dev(H, l, 0, f[l]) for l in range(OH.nlev)]
+    for adjoint in (False, True):
+        results = []
+        for graph in (0, 1, 1, 0, 1):
+            xs = [torch.zeros_like(t) for t in fs]
+            o = A.default_opts(precision=prec, use_graph=graph, tol_rel=1e-11, max_cycles=100)
+            st = H.solve_adjoint_composite(xs, fs, o) if adjoint else H.solve_composite(xs, fs, None, o)
+            torch.cuda.synchronize()
+            assert st["status"] == 0 and st["converged"], st
+            assert st["graph"] == bool(graph), st
+            results.append(([x.cpu().numpy().copy() for x in xs], st["history"]))
+            _ = (fs[0] * 3).sum().item()  # unrelated eager work between solves
+        for xs, hist in results[1:]:
+            for a, b in zip(xs, results[0][0]):
+                assert np.array_equal(a, b)
+            assert hist == results[0][1]

@@ -23,6 +23,7 @@ if not torch.cuda.is_available():  # pragma: no cover
 from oracle import imex, proj  # noqa: E402
 from oracle.level import Level  # noqa: E402
 from paper_2506_02663_amd import amg as A  # noqa: E402
+from paper_2506_02663_amd import workloads as W  # noqa: E402
 from tests.gpuhelp import from_dev, relerr, to_dev  # noqa: E402
 
 TWO_PI = 2 * np.pi
@@ -147,31 +148,11 @@ def test_shear_flow_at_256_is_the_closed_form(prec, tol):
     assert np.abs(from_dev(Hv, 0, 0, us[1], lev)[lev.inner]).max() < tol
 
 
-def four_vortex_velocity(n):
-    """Section 7.3's initial data: vorticity of four vortices, stream function
-    from the periodic Poisson equation (FFT of the exact point values, the
-    data are synthetic), velocity (psi_y, -psi_x), as cell values."""
-    x = (np.arange(n) + 0.5) / n
-    X, Y = np.meshgrid(x, x, indexing="ij")
-    gam = [-150.0, 50.0, 50.0, 50.0]
-    ctr = [(0.5, 0.5), (0.59, 0.5), (0.455, 0.5 + 0.045 * np.sqrt(3)), (0.455, 0.5 - 0.045 * np.sqrt(3))]
-    om = sum(0.5 * g * (1 + np.tanh(3 - 100 * np.hypot(X - cx, Y - cy))) for g, (cx, cy) in zip(gam, ctr))
-    k = TWO_PI * np.fft.fftfreq(n, 1.0 / n)
-    KX, KY = np.meshgrid(k, k, indexing="ij")
-    k2 = KX ** 2 + KY ** 2
-    k2[0, 0] = 1.0
-    ph = np.fft.fft2(om) / k2  # Delta psi = -omega
-    ph[0, 0] = 0.0
-    u = np.real(np.fft.ifft2(1j * KY * ph))
-    v = np.real(np.fft.ifft2(-1j * KX * ph))
-    return u, v
-
-
 def test_four_vortex_steps_at_256():
     n = 256
     lev = plevel((n, n))
     Hv, Hp = hiers(lev)
-    u, v = four_vortex_velocity(n)
+    u, v = W.four_vortex_velocity(n)
     U = [lev.zeros(), lev.zeros()]
     U[0][lev.inner], U[1][lev.inner] = u, v
     us = [to_dev(Hv, 0, 0, a) for a in U]
