@@ -19,7 +19,8 @@ Readings taken where the paper points to other papers:
   face derivative of eq. (cell2face), fine ones taken with the interpolated
   ghosts.
 * Average-down (COH-4, eq. AMR_avergingDownToCrse) puts on every coarse cell
-  covered by the next level the mean of its 2^D children.
+  covered by the next level the mean of its r^D children (r the refinement
+  ratio, 2 or 4).
 * Composite solve (the paper cites an adaptive multigrid for the inverse of
   the composite operator): multiplicative correction by levels in V order,
   finest to level 1, then level 0, then level 1 to finest.  Each correction
@@ -62,16 +63,16 @@ def _solve_fraction(A, b):
     return [M[r][n] / M[r][r] for r in range(n)]
 
 
-def cfi_weights_1d(shift, child):
+def cfi_weights_1d(shift, child, ratio=2):
     """Weights on the five window cells (left to right) giving the average,
-    over child `child` (0 = low half, 1 = high half) of the parent, of the
+    over child `child` (0 .. ratio-1 from the low end) of the parent, of the
     quartic with the given cell averages.  The window is the parent's cell
     moved by `shift` cells: window cell m = 0..4 covers [m, m+1] and the
     parent is window cell 2 - shift."""
     M = _moment_matrix()
     mp = 2 - shift
-    x0 = Fr(mp) + Fr(child, 2)
-    x1 = x0 + Fr(1, 2)
+    x0 = Fr(mp) + Fr(child, ratio)
+    x1 = x0 + Fr(1, ratio)
     # average of x^k over [x0, x1]
     c = [(x1 ** (k + 1) - x0 ** (k + 1)) / (k + 1) / (x1 - x0) for k in range(5)]
     # child average = c . a, with M a = U  =>  weights w = M^-T c
@@ -79,7 +80,53 @@ def cfi_weights_1d(shift, child):
     return _solve_fraction(MT, c)
 
 
-_W = {(s, a): np.array([float(v) for v in cfi_weights_1d(s, a)]) for s in range(-2, 3) for a in (0, 1)}
+_WR = {}
+
+
+def weights(ratio):
+    """{(shift, child): the five AMRCFI weights} for refinement ratio `ratio`."""
+    if ratio not in _WR:
+        _WR[ratio] = {(s, a): np.array([float(v) for v in cfi_weights_1d(s, a, ratio)])
+                      for s in range(-2, 3) for a in range(ratio)}
+    return _WR[ratio]
+
+
+_W = weights(2)
+
+
+def restrict_ratio(fine, r, coarse, ratio):
+    """Mean of the ratio^D children of every coarse cell (average-down)."""
+    rin = r[fine.inner]
+    acc = np.zeros(coarse.shape)
+    for corner in np.ndindex(*(ratio,) * fine.dim):
+        acc += rin[tuple(slice(a, None, ratio) for a in corner)]
+    out = coarse.zeros()
+    out[coarse.inner] = acc / ratio ** fine.dim
+    out[~coarse.mask] = 0.0
+    return out
+
+
+def prolong_ratio(coarse, ec, fine, ratio):
+    """Face-neighbour linear interpolation of a coarse correction onto the
+    children of a refinement by `ratio`: a child whose centre lies delta_d
+    (in parent widths) from the parent's centre along d takes
+    (1 - sum_d |delta_d|) e_P + sum_d |delta_d| e_(P + sign(delta_d) e_d)
+    (ratio 2: delta = +-1/4, the multigrid prolongation)."""
+    if ratio == 2:
+        return mg.prolong(coarse, ec, fine)
+    G = coarse.ghosts(ec)
+    D = fine.dim
+    out = fine.zeros()
+    fin = out[fine.inner]
+    nb = {(d, k): coarse.neighbour(ec, G, d, k) for d in range(D) for k in (-1, 1)}
+    for corner in np.ndindex(*(ratio,) * D):
+        delta = [(a + 0.5) / ratio - 0.5 for a in corner]
+        val = (1.0 - sum(abs(t) for t in delta)) * ec
+        for d in range(D):
+            val = val + abs(delta[d]) * nb[(d, 1 if delta[d] > 0 else -1)]
+        fin[tuple(slice(a, None, ratio) for a in corner)] = val[coarse.inner]
+    out[~fine.mask] = 0.0
+    return out
 
 
 def window_shift(P, n):
@@ -94,7 +141,8 @@ def window_shift(P, n):
 
 # ---------------------------------------------------------------------------
 class Hierarchy:
-    """Levels 0..lmax of a block-structured hierarchy with ratio 2.
+    """Levels 0..lmax of a block-structured hierarchy with refinement ratio
+    `ratio` (2 or 4, eq. grids) between consecutive levels.
 
     base_shape : cells of level 0 per direction; h0 its cell size
     boxes      : list per level of (lo, hi) boxes (level 0 covers the grid)
@@ -102,11 +150,12 @@ class Hierarchy:
                  periodic side)
     """
 
-    def __init__(self, base_shape, h0, boxes, phys_bc):
+    def __init__(self, base_shape, h0, boxes, phys_bc, ratio=2):
+        r = self.ratio = int(ratio)
         self.levels = []
         for l, bl in enumerate(boxes):
-            shape = tuple(n * 2 ** l for n in base_shape)
-            self.levels.append(Level(shape, h0 / 2 ** l, bl, phys_bc, "I" if l else "D"))
+            shape = tuple(n * r ** l for n in base_shape)
+            self.levels.append(Level(shape, h0 / r ** l, bl, phys_bc, "I" if l else "D"))
         self.dim = len(base_shape)
         self.nlev = len(self.levels)
         # covered[l]: cells of level l under level l+1
@@ -115,7 +164,7 @@ class Hierarchy:
             cov = np.zeros(self.levels[l].pshape, bool)
             if l + 1 < self.nlev:
                 for lo, hi in self.levels[l + 1].boxes:
-                    sl = tuple(slice(PAD + a // 2, PAD + (b + 1) // 2) for a, b in zip(lo, hi))
+                    sl = tuple(slice(PAD + a // r, PAD + (b + 1) // r) for a, b in zip(lo, hi))
                     cov[sl] = True
             self.covered.append(cov)
         self.valid = [self.levels[l].mask & ~self.covered[l] for l in range(self.nlev)]
@@ -124,13 +173,14 @@ class Hierarchy:
     def _check_nesting(self):
         for l in range(1, self.nlev):
             fine, coarse = self.levels[l], self.levels[l - 1]
+            r = self.ratio
             for lo, hi in fine.boxes:
-                if any(v % 2 for v in lo) or any((v + 1) % 2 for v in hi):
+                if any(v % r for v in lo) or any((v + 1) % r for v in hi):
                     raise ValueError("level %d is not properly refined" % l)
             # every fine cell's parent is a cell of the coarse level
             par = np.zeros(coarse.pshape, bool)
             for lo, hi in fine.boxes:
-                par[tuple(slice(PAD + a // 2, PAD + (b + 1) // 2) for a, b in zip(lo, hi))] = True
+                par[tuple(slice(PAD + a // r, PAD + (b + 1) // r) for a, b in zip(lo, hi))] = True
             if np.any(par & ~coarse.mask):
                 raise ValueError("level %d is not nested in level %d" % (l, l - 1))
 
@@ -155,8 +205,8 @@ class Hierarchy:
         D = fine.dim
         for pos in np.argwhere(self.cf_positions(l)):
             g = pos - PAD
-            P = g // 2
-            a = g % 2
+            P = g // self.ratio
+            a = g % self.ratio
             shifts = [window_shift(int(P[d]), coarse.shape[d]) for d in range(D)]
             lo = [int(P[d]) + shifts[d] - 2 for d in range(D)]
             win = Uc[tuple(slice(PAD + lo[d], PAD + lo[d] + 5) for d in range(D))]
@@ -165,7 +215,7 @@ class Hierarchy:
                 raise ValueError("interpolation window leaves level %d" % (l - 1))
             val = win
             for d in range(D):
-                w = _W[(shifts[d], int(a[d]))]
+                w = weights(self.ratio)[(shifts[d], int(a[d]))]
                 val = np.tensordot(w, val, axes=([0], [0]))
             out[tuple(pos)] = float(val)
         return out
@@ -174,7 +224,7 @@ class Hierarchy:
     def average_down(self, U, l):
         """Covered cells of level l-1 := mean of their children on level l."""
         fine, coarse = self.levels[l], self.levels[l - 1]
-        avg = mg.restrict(fine, np.where(fine.mask, U[l], 0.0), coarse)
+        avg = restrict_ratio(fine, np.where(fine.mask, U[l], 0.0), coarse, self.ratio)
         cov = self.covered[l - 1]
         U[l - 1] = np.where(cov, avg, U[l - 1])
 
@@ -243,20 +293,21 @@ class Hierarchy:
             else:  # face i - 1/2
                 Fc = fv.face_derivative(cval(-2), cval(-1), cval(0), cval(1), hc)
             # fine faces covering it
-            jd = 2 * i[d] + (2 if s else 0)  # fine index of the first cell past the face (+e_d side)
+            r = self.ratio
+            jd = r * i[d] + (r if s else 0)  # fine index of the first cell past the face (+e_d side)
             tot = 0.0
             nf = 0
             trans = [e for e in range(D) if e != d]
-            for off in np.ndindex(*(2,) * (D - 1)):
+            for off in np.ndindex(*(r,) * (D - 1)):
                 q = np.zeros(D, int)
                 q[d] = jd
                 for e, o in zip(trans, off):
-                    q[e] = 2 * i[e] + o
+                    q[e] = r * i[e] + o
 
                 def fval(delta):
-                    r = q.copy()
-                    r[d] += delta
-                    t = tuple(r + PAD)
+                    qq = q.copy()
+                    qq[d] += delta
+                    t = tuple(qq + PAD)
                     if fine.mask[t]:
                         return U[l][t]
                     side = 1 if delta >= 0 else 0
@@ -321,7 +372,7 @@ def correct_level(H, U, f, op, c, fd, MGl, l, sing):
     U[l] = U[l] + e
     E = e
     for m in range(l + 1, H.nlev):
-        dU = mg.prolong(H.levels[m - 1], E, H.levels[m])
+        dU = prolong_ratio(H.levels[m - 1], E, H.levels[m], H.ratio)
         U[m] = U[m] + dU
         E = dU
     return U

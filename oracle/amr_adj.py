@@ -32,7 +32,7 @@ prolongation, the cycle diverges on a three-level hierarchy.)
 import numpy as np
 
 from . import fv, mg
-from .amr import _W, window_shift
+from .amr import prolong_ratio, weights, window_shift
 from .level import NEUMANN, DIRICHLET, PAD, PERIODIC, _shift, _wrap
 
 
@@ -91,13 +91,13 @@ def _amrcfi_T(H, l, cbar):
         if v == 0.0:
             continue
         g = pos - PAD
-        P = g // 2
-        a = g % 2
+        P = g // H.ratio
+        a = g % H.ratio
         shifts = [window_shift(int(P[d]), coarse.shape[d]) for d in range(D)]
         lo = [int(P[d]) + shifts[d] - 2 for d in range(D)]
         w = np.array(1.0)
         for d in range(D):
-            w = np.multiply.outer(w, np.array([float(x) for x in _W[(shifts[d], int(a[d]))]]))
+            w = np.multiply.outer(w, np.array([float(x) for x in weights(H.ratio)[(shifts[d], int(a[d]))]]))
         sl = tuple(slice(PAD + lo[d], PAD + lo[d] + 5) for d in range(D))
         out[sl] += v * w
     return out
@@ -142,14 +142,15 @@ def composite_apply_T(H, Lam, op, c):
             offs = [-1, 0, 1, 2] if s else [-2, -1, 0, 1]
             for o, wv in zip(offs, cw):
                 add_c(o, -t * wv / (12 * hc))
-            jd = 2 * i[d] + (2 if s else 0)
+            rr = H.ratio
+            jd = rr * i[d] + (rr if s else 0)
             trans = [e for e in range(D) if e != d]
-            nf = 2 ** (D - 1)
-            for off in np.ndindex(*(2,) * (D - 1)):
+            nf = rr ** (D - 1)
+            for off in np.ndindex(*(rr,) * (D - 1)):
                 q = np.zeros(D, int)
                 q[d] = jd
                 for e, o in zip(trans, off):
-                    q[e] = 2 * i[e] + o
+                    q[e] = rr * i[e] + o
                 for delta, wv in zip((-2, -1, 0, 1), cw):
                     r = q.copy()
                     r[d] += delta
@@ -184,19 +185,19 @@ def composite_apply_T(H, Lam, op, c):
     for l in range(1, nl):
         fine, coarse = H.levels[l], H.levels[l - 1]
         cov = np.where(H.covered[l - 1], Ubar[l - 1], 0.0)
-        Ubar[l] += np.where(fine.mask, _children(fine, coarse, cov), 0.0)
+        Ubar[l] += np.where(fine.mask, _children(fine, coarse, cov, H.ratio), 0.0)
         Ubar[l - 1] = np.where(H.covered[l - 1], 0.0, Ubar[l - 1])
     return [np.where(H.valid[l], Ubar[l], 0.0) for l in range(nl)]
 
 
-def _children(fine, coarse, a):
-    """Fine array whose every cell holds 1/2^D of its parent's value in a."""
+def _children(fine, coarse, a, ratio=2):
+    """Fine array whose every cell holds 1/ratio^D of its parent's value in a."""
     out = fine.zeros()
     D = fine.dim
     ain = a[coarse.inner]
     fin = out[fine.inner]
-    for corner in np.ndindex(*(2,) * D):
-        fin[tuple(slice(k, None, 2) for k in corner)] = ain / 2 ** D
+    for corner in np.ndindex(*(ratio,) * D):
+        fin[tuple(slice(k, None, ratio) for k in corner)] = ain / ratio ** D
     return out
 
 
@@ -207,7 +208,7 @@ def composite_residual_T(H, Lam, g, op, c):
     R = [np.where(H.valid[l], g[l] - AT[l], 0.0) for l in range(H.nlev)]
     for l in range(H.nlev - 1, 0, -1):
         H.average_down(R, l)
-        R[l - 1] = np.where(H.covered[l - 1], R[l - 1] * 2 ** H.dim, R[l - 1])
+        R[l - 1] = np.where(H.covered[l - 1], R[l - 1] * H.ratio ** H.dim, R[l - 1])
     return R
 
 
@@ -252,7 +253,7 @@ def composite_solve_T(H, g, op, c, tol_rel=1e-10, tol_abs=0.0, max_cycles=100, n
             lam[l] = lam[l] + np.where(H.valid[l], e, 0.0)
             E = e
             for m in range(l + 1, H.nlev):
-                dU = mg.prolong(H.levels[m - 1], E, H.levels[m]) / 2 ** H.dim
+                dU = prolong_ratio(H.levels[m - 1], E, H.levels[m], H.ratio) / H.ratio ** H.dim
                 lam[m] = lam[m] + np.where(H.valid[m], dU, 0.0)
                 E = dU
         if sing:

@@ -36,7 +36,7 @@ from the newest, hist[i] = phi(t_(-i)).
 import numpy as np
 
 from . import fv
-from .amr import _W, window_shift
+from .amr import weights, window_shift
 from .level import PAD
 
 
@@ -59,8 +59,8 @@ def fine_average(H, l, Uc, g):
     whose averages over the 5^D window around its parent equal Uc."""
     coarse = H.levels[l - 1]
     D = coarse.dim
-    P = [gi // 2 for gi in g]
-    a = [gi % 2 for gi in g]
+    P = [gi // H.ratio for gi in g]
+    a = [gi % H.ratio for gi in g]
     shifts = [window_shift(P[d], coarse.shape[d]) for d in range(D)]
     lo = [P[d] + shifts[d] - 2 for d in range(D)]
     sl = tuple(slice(PAD + lo[d], PAD + lo[d] + 5) for d in range(D))
@@ -68,7 +68,7 @@ def fine_average(H, l, Uc, g):
         raise ValueError("interpolation window leaves level %d" % (l - 1))
     val = Uc[sl]
     for d in range(D):
-        val = np.tensordot(_W[(shifts[d], a[d])], val, axes=([0], [0]))
+        val = np.tensordot(weights(H.ratio)[(shifts[d], a[d])], val, axes=([0], [0]))
     return float(val)
 
 

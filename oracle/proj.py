@@ -86,7 +86,8 @@ def hierarchy_with(H, kind):
     """A hierarchy with H's boxes and every non-periodic physical condition
     set to kind."""
     boxes = [lev.boxes for lev in H.levels]
-    return amr.Hierarchy(H.levels[0].shape, H.levels[0].h, boxes, _keep_periodic(H.levels[0].phys_bc, kind))
+    return amr.Hierarchy(H.levels[0].shape, H.levels[0].h, boxes, _keep_periodic(H.levels[0].phys_bc, kind),
+                         H.ratio)
 
 
 def composite_gradient(Hp, Phi):
@@ -139,19 +140,20 @@ def composite_divergence(Hw, W, wb=None):
             # coarse face average of w_d on the face (d, s) of the cell
             Fc = fv.face_value(cval(-1), cval(0), cval(1), cval(2)) if s else \
                 fv.face_value(cval(-2), cval(-1), cval(0), cval(1))
-            jd = 2 * i[d] + (2 if s else 0)
+            rr = Hw.ratio
+            jd = rr * i[d] + (rr if s else 0)
             trans = [e for e in range(D) if e != d]
             tot, nf = 0.0, 0
-            for off in np.ndindex(*(2,) * (D - 1)):
+            for off in np.ndindex(*(rr,) * (D - 1)):
                 q = np.zeros(D, int)
                 q[d] = jd
                 for e, o in zip(trans, off):
-                    q[e] = 2 * i[e] + o
+                    q[e] = rr * i[e] + o
 
                 def fval(delta):
-                    r = q.copy()
-                    r[d] += delta
-                    t = tuple(r + PAD)
+                    qq = q.copy()
+                    qq[d] += delta
+                    t = tuple(qq + PAD)
                     if fine.mask[t]:
                         return Wf[t]
                     return Gf[(d, 1 if delta >= 0 else 0)][t]

@@ -110,7 +110,7 @@ def _down_T(H, Ubar):
     for l in range(1, H.nlev):
         fine, coarse = H.levels[l], H.levels[l - 1]
         cov = np.where(H.covered[l - 1], Ubar[l - 1], 0.0)
-        Ubar[l] += np.where(fine.mask, amr_adj._children(fine, coarse, cov), 0.0)
+        Ubar[l] += np.where(fine.mask, amr_adj._children(fine, coarse, cov, H.ratio), 0.0)
         Ubar[l - 1] = np.where(H.covered[l - 1], 0.0, Ubar[l - 1])
     return [np.where(H.valid[l], Ubar[l], 0.0) for l in range(H.nlev)]
 
@@ -176,14 +176,15 @@ def composite_divergence_T(Hw, Lam):
                 q = np.array(pos)
                 q[d] += o
                 add(l - 1, coarse, q, 1 if o > 0 else 0, -t * wv / 12.0)
-            jd = 2 * i[d] + (2 if s else 0)
+            rr = Hw.ratio
+            jd = rr * i[d] + (rr if s else 0)
             trans = [e for e in range(D) if e != d]
-            nf = 2 ** (D - 1)
-            for off in np.ndindex(*(2,) * (D - 1)):
+            nf = rr ** (D - 1)
+            for off in np.ndindex(*(rr,) * (D - 1)):
                 q = np.zeros(D, int)
                 q[d] = jd
                 for e, o in zip(trans, off):
-                    q[e] = 2 * i[e] + o
+                    q[e] = rr * i[e] + o
                 for delta, wv in zip((-2, -1, 0, 1), fw):
                     r = q.copy()
                     r[d] += delta

@@ -1,7 +1,8 @@
 """Pins of the oracle's composite (multi-level) operators: coarse-fine
 interpolation weights in exact arithmetic, polynomial reproduction of the
 composite operator and solve, conservation of the refluxed operator, and the
-directly solved composite system as referee."""
+directly solved composite system as referee; refinement ratios 2 and 4
+(eq. grids), the prolongation of corrections exact on linear functions."""
 from fractions import Fraction as Fr
 
 import numpy as np
@@ -41,6 +42,51 @@ def test_weights_are_conservative(shift):
     assert mean == [Fr(1) if m == 2 - shift else Fr(0) for m in range(5)]
 
 
+@pytest.mark.parametrize("shift", range(-2, 3))
+@pytest.mark.parametrize("child", range(4))
+def test_ratio4_weights_exact_to_degree_4_and_not_5(shift, child):
+    w = amr.cfi_weights_1d(shift, child, 4)
+    x0 = Fr(2 - shift) + Fr(child, 4)
+    for k in range(6):
+        data = [avg_mono(k, m, m + 1) for m in range(5)]
+        got = sum(wi * di for wi, di in zip(w, data))
+        assert (got == avg_mono(k, x0, x0 + Fr(1, 4))) == (k <= 4)
+
+
+@pytest.mark.parametrize("shift", range(-2, 3))
+def test_ratio4_weights_are_conservative_and_mirror(shift):
+    ws = [amr.cfi_weights_1d(shift, a, 4) for a in range(4)]
+    mean = [sum(col) / 4 for col in zip(*ws)]
+    assert mean == [Fr(1) if m == 2 - shift else Fr(0) for m in range(5)]
+    if shift == 0:  # the centred window is symmetric: child a mirrors child 3 - a
+        for a in range(4):
+            assert ws[a] == ws[3 - a][::-1]
+
+
+@pytest.mark.parametrize("ratio", [2, 4])
+def test_prolongation_exact_on_linear_functions(ratio):
+    """The correction prolongation reproduces a linear function's cell
+    averages at every child whose coarse neighbours are cells (a linear
+    function's cell average is its value at the centre)."""
+    from oracle.level import Level
+    D = 2
+    coarse = Level((8, 8), 1 / 8, [((0, 0), (7, 7))], {(d, s): "D" for d in range(D) for s in (0, 1)})
+    n = 8 * ratio
+    fine = Level((n, n), 1 / n, [((0, 0), (n - 1, n - 1))], {(d, s): "D" for d in range(D) for s in (0, 1)})
+    lin = lambda x, y: 0.3 + 1.7 * x - 0.6 * y  # noqa: E731
+    xc = (np.arange(8) + 0.5) / 8
+    ec = coarse.zeros()
+    ec[coarse.inner] = lin(xc[:, None], xc[None, :])
+    got = amr.prolong_ratio(coarse, ec, fine, ratio)[fine.inner]
+    xf = (np.arange(n) + 0.5) / n
+    want = lin(xf[:, None], xf[None, :])
+    inner = (slice(ratio, n - ratio), slice(ratio, n - ratio))  # children whose neighbours are cells
+    assert np.abs(got[inner] - want[inner]).max() < 1e-13
+    if ratio == 2:
+        from oracle import mg
+        assert np.array_equal(amr.prolong_ratio(coarse, ec, fine, 2), mg.prolong(coarse, ec, fine))
+
+
 P4a = Poly1([0.3, -1.0, 0.5, 2.0, -1.5])
 P4b = Poly1([1.0, 0.7, -2.0, 0.25, 1.0])
 P3 = Poly1([-0.2, 1.1, 0.4, -0.9])
@@ -55,6 +101,17 @@ def three_level(bc):
     return amr.Hierarchy((16, 16), 1.0 / 16,
                          [[((0, 0), (15, 15))], [((4, 4), (27, 27))], [((16, 16), (31, 31))]],
                          {(d, s): bc for d in range(2) for s in (0, 1)})
+
+
+def two_level_r4(bc):
+    # ratio 4: level 1 on the 64^2 grid, an L of two boxes
+    return amr.Hierarchy((16, 16), 1.0 / 16, [[((0, 0), (15, 15))], [((16, 16), (39, 47)), ((40, 16), (47, 31))]],
+                         {(d, s): bc for d in range(2) for s in (0, 1)}, ratio=4)
+
+
+def three_level_r4(bc):
+    return amr.Hierarchy((8, 8), 1.0 / 8, [[((0, 0), (7, 7))], [((8, 8), (23, 23))], [((48, 48), (79, 79))]],
+                         {(d, s): bc for d in range(2) for s in (0, 1)}, ratio=4)
 
 
 def poly_data(H, op, c):
@@ -72,7 +129,7 @@ def rel(U, V, H):
     return num / max(np.abs(V[l][H.valid[l]]).max() for l in range(H.nlev))
 
 
-@pytest.mark.parametrize("make", [two_level, three_level])
+@pytest.mark.parametrize("make", [two_level, three_level, two_level_r4, three_level_r4])
 @pytest.mark.parametrize("op,bc,c", [("helmholtz", "D", 0.5 / 16), ("poisson", "N", 0.0), ("poisson", "D", 0.0)])
 def test_composite_reproduces_polynomials(make, op, bc, c):
     H = make(bc)
@@ -88,8 +145,9 @@ def test_composite_reproduces_polynomials(make, op, bc, c):
     assert rel(U, us, H) < 1e-9
 
 
-def test_refluxed_operator_is_conservative():
-    H = two_level("N")
+@pytest.mark.parametrize("make", [two_level, two_level_r4, three_level_r4])
+def test_refluxed_operator_is_conservative(make):
+    H = make("N")
     rng = np.random.default_rng(0)
     U = []
     for l, lev in enumerate(H.levels):
@@ -119,7 +177,12 @@ def corner(bc):
                          {(d, s): bc for d in range(2) for s in (0, 1)})
 
 
-@pytest.mark.parametrize("make", [two_level, corner])
+def corner_r4(bc):
+    return amr.Hierarchy((8, 8), 1.0 / 8, [[((0, 0), (7, 7))], [((0, 0), (15, 15))]],
+                         {(d, s): bc for d in range(2) for s in (0, 1)}, ratio=4)
+
+
+@pytest.mark.parametrize("make", [two_level, corner, corner_r4])
 @pytest.mark.parametrize("op,bc,c", [("helmholtz", "D", 0.3 / 16), ("poisson", "N", 0.0), ("poisson", "D", 0.0)])
 def test_composite_solve_equals_direct_solve(make, op, bc, c):
     H = make(bc)
@@ -135,6 +198,9 @@ def test_composite_solve_equals_direct_solve(make, op, bc, c):
 
 
 def test_nesting_is_checked():
+    with pytest.raises(ValueError):  # not properly refined for ratio 4
+        amr.Hierarchy((16, 16), 1.0 / 16, [[((0, 0), (15, 15))], [((18, 16), (41, 47))]],
+                      {(d, s): "D" for d in range(2) for s in (0, 1)}, ratio=4)
     with pytest.raises(ValueError):
         amr.Hierarchy((16, 16), 1.0 / 16, [[((0, 0), (15, 15))], [((4, 4), (11, 11))], [((2, 2), (9, 9))]],
                       {(d, s): "D" for d in range(2) for s in (0, 1)})

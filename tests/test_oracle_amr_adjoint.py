@@ -16,13 +16,15 @@ LAYOUTS = {
     "corner": ((16, 8), 1 / 16, [[((0, 0), (15, 7))], [((0, 0), (7, 7))]]),
     "boundary": ((32, 16), 1 / 32, [[((0, 0), (15, 15)), ((16, 0), (31, 15))],
                                    [((0, 0), (15, 15)), ((16, 0), (23, 11))]]),
+    "two_level_r4": ((16, 16), 1 / 16, [[((0, 0), (15, 15))], [((16, 16), (39, 47)), ((40, 16), (47, 31))]], 4),
+    "three_level_r4": ((8, 8), 1 / 8, [[((0, 0), (7, 7))], [((8, 8), (23, 23))], [((48, 48), (79, 79))]], 4),
 }
 CASES = [("D", "helmholtz", 0.3), ("N", "poisson", 0.0), ("D", "poisson", 0.0), ("N", "helmholtz", 0.5)]
 
 
 def hier(name, bc):
-    base, h0, boxes = LAYOUTS[name]
-    return amr.Hierarchy(base, h0, boxes, {(d, s): bc for d in range(2) for s in (0, 1)})
+    base, h0, boxes, *ratio = LAYOUTS[name]
+    return amr.Hierarchy(base, h0, boxes, {(d, s): bc for d in range(2) for s in (0, 1)}, *ratio)
 
 
 def rand_valid(H, rng):
@@ -71,6 +73,7 @@ def test_transpose_equals_probed_matrix_transpose():
 
 
 @pytest.mark.parametrize("name,bc,op,c0", [("two_level", "D", "helmholtz", 0.3), ("three_level", "N", "poisson", 0.0),
+                                           ("two_level_r4", "N", "poisson", 0.0), ("three_level_r4", "D", "helmholtz", 0.3),
                                           ("three_level", "D", "helmholtz", 0.3), ("corner", "D", "poisson", 0.0),
                                           ("boundary", "N", "poisson", 0.0)])
 def test_adjoint_solve_identity(name, bc, op, c0):

@@ -89,9 +89,13 @@ def test_time_matrix_reproduces_cubics(k, eta):
 
 
 # ---------------------------------------------------------------------------
-def hierarchy():
-    # level 1: two boxes of a 32^2 grid (an L-shaped component) and a
-    # separate box; coarse-fine faces on every side, physical faces too
+def hierarchy(ratio=2):
+    # level 1: two boxes (an L-shaped component) and a separate box;
+    # coarse-fine faces on every side, physical faces too
+    if ratio == 4:
+        boxes = [[((0, 0), (15, 15))],
+                 [((0, 16), (31, 31)), ((32, 16), (47, 47)), ((16, 48), (31, 63))]]
+        return amr.Hierarchy((16, 16), 1.0 / 16, boxes, {(d, s): "D" for d in range(2) for s in (0, 1)}, ratio=4)
     boxes = [[((0, 0), (15, 15))],
              [((0, 8), (15, 15)), ((16, 8), (23, 23)), ((8, 24), (15, 31))]]
     return amr.Hierarchy((16, 16), 1.0 / 16, boxes, {(d, s): "D" for d in range(2) for s in (0, 1)})
@@ -117,8 +121,9 @@ def dqt(t):
 
 
 @pytest.mark.parametrize("kind", ["value", "normal_derivative"])
-def test_face_data_exact_on_polynomials(kind):
-    H = hierarchy()
+@pytest.mark.parametrize("ratio", [2, 4])
+def test_face_data_exact_on_polynomials(kind, ratio):
+    H = hierarchy(ratio)
     coarse, fine = H.levels
     k, eta, t0 = 0.05, 0.02, 0.4  # t_(-0) = t0, t_(-i) = t0 - i k, t* = t_(-1) + eta
     hist = [cell_avgs(coarse, PX, PY, qt(t0 - i * k)) for i in range(4)]

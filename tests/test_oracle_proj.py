@@ -122,7 +122,12 @@ def three_level(kind):
                          {(d, s): kind for d in range(2) for s in (0, 1)})
 
 
-@pytest.mark.parametrize("make", [two_level, three_level])
+def two_level_r4(kind):
+    return amr.Hierarchy((16, 16), 1.0 / 16, [[((0, 0), (15, 15))], [((16, 16), (39, 47)), ((40, 16), (47, 31))]],
+                         {(d, s): kind for d in range(2) for s in (0, 1)}, ratio=4)
+
+
+@pytest.mark.parametrize("make", [two_level, three_level, two_level_r4])
 def test_composite_projection_on_polynomials(make):
     H = make("D")
     Hw = proj.hierarchy_with(H, "D")
@@ -152,8 +157,9 @@ def test_composite_projection_on_polynomials(make):
             assert np.abs(U[d][l] - want[d][l])[H.valid[l]].max() < 1e-9
 
 
-def test_composite_divergence_is_conservative():
-    Hw = two_level("D")
+@pytest.mark.parametrize("make", [two_level, two_level_r4])
+def test_composite_divergence_is_conservative(make):
+    Hw = make("D")
     rng = np.random.default_rng(3)
     W = [[np.where(lev.mask, rng.normal(size=lev.pshape), 0.0) for lev in Hw.levels] for _ in range(2)]
     wb = []

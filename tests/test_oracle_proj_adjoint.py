@@ -118,12 +118,13 @@ HIERS = {
     "two_level": ((16, 16), 1 / 16, [[((0, 0), (15, 15))], [((8, 8), (15, 23)), ((16, 8), (23, 15))]]),
     "three_level": ((16, 16), 1 / 16, [[((0, 0), (15, 15))], [((4, 4), (27, 27))], [((16, 16), (31, 31))]]),
     "boundary": ((16, 16), 1 / 16, [[((0, 0), (15, 15))], [((0, 0), (15, 15)), ((16, 0), (23, 11))]]),
+    "two_level_r4": ((16, 16), 1 / 16, [[((0, 0), (15, 15))], [((16, 16), (39, 47)), ((40, 16), (47, 31))]], 4),
 }
 
 
 def hier(name, kind):
-    base, h0, boxes = HIERS[name]
-    return amr.Hierarchy(base, h0, boxes, {(d, s): kind for d in range(2) for s in (0, 1)})
+    base, h0, boxes, *ratio = HIERS[name]
+    return amr.Hierarchy(base, h0, boxes, {(d, s): kind for d in range(2) for s in (0, 1)}, *ratio)
 
 
 def rand_levels(H, rng, valid=True):
@@ -156,7 +157,7 @@ def test_composite_gradient_and_divergence_transposes(name):
             assert np.all(DT[d][l][~Hw.valid[l]] == 0.0)
 
 
-@pytest.mark.parametrize("name", ["two_level", "three_level"])
+@pytest.mark.parametrize("name", ["two_level", "three_level", "two_level_r4"])
 def test_composite_projection_transpose(name):
     rng = np.random.default_rng(4)
     H = hier(name, "D")
