@@ -173,7 +173,8 @@ void amg_default_opts(amg_solve_opts* opts);
 /* Creates a hierarchy of nlevels levels over the box [x_lo, x_hi] (dim
  * entries each) of the physical domain, cut into base_cells[d] cells along
  * direction d at level 0, in dimension dim (2 or 3) with refinement ratio
- * `ratio` (2), eq. (grids) of Section 5.1: cells are cubes, so
+ * `ratio` (2 or 4; the tests of Sections 7.4-7.5 take 4) between
+ * consecutive levels, eq. (grids) of Section 5.1: cells are cubes, so
  * (x_hi[d] - x_lo[d]) / base_cells[d] must be the same h0 in every direction
  * (to 1e-12 relative), and level l has h0 / ratio^l.  Cell i of level l spans
  * [x_lo + i h_l, x_lo + (i+1) h_l].  *out receives the handle.

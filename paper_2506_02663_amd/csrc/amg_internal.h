@@ -108,12 +108,13 @@ struct RfxFaceD {  // one coarse-fine face of a valid coarse cell
 struct ProlD {     // one fine cell and its coarse parent
   int64_t fe, pe;
   int32_t cs1, cs2;  // coarse strides along y and z
-  int32_t child;     // bit d set: the child lies on the high side along d
+  int32_t child;     // bits 2d..2d+1: the child's offset 0..ratio-1 in its parent along d
   int32_t pad;
 };
 
 struct Composite {  // tables of level l against level l-1 (l >= 1)
-  double w[10][5];  // interpolation weights, [(shift + 2) * 2 + child][window cell]
+  int r = 2;        // refinement ratio against level l-1 (2 or 4)
+  double w[20][5];  // interpolation weights, [(shift + 2) * r + child][window cell]
   std::vector<int64_t> cfi_dst;
   std::vector<int32_t> cfi_src;  // 5^D coarse elements per ghost
   std::vector<uint8_t> cfi_w;    // D weight-set indices per ghost
@@ -251,7 +252,7 @@ struct CicTable {
   std::vector<int32_t> src;    // [entry * 4 + cell] * 5^D coarse elements
   std::vector<uint8_t> wsel;   // [entry * 4 + cell] * D weight sets (of Composite::w)
   std::vector<double> ncf;     // coarse-fine face entries per component
-  double w[10][5];
+  double w[20][5];  // as Composite::w
   int64_t* d_fd = nullptr;
   int32_t* d_src = nullptr;
   uint8_t* d_wsel = nullptr;

@@ -620,7 +620,7 @@ void comp_residual_T(Comp& C) {
     launch_sub_array(dim, D, L.A64, C.R[l], C.st);
     if (l) launch_cfi_T(dim, L.cmp, C.X[l], L.A64, b, L.mu, C.R[l - 1], C.st);
   }
-  const double down = 1.0 / (1 << dim);
+  const double down = 1.0 / std::pow((double)H->ratio, dim);  // 1 / children per coarse cell
   for (int l = 1; l <= C.hi; ++l) {
     launch_pass_down(H->levels[l].cmp, C.R[l - 1], C.R[l], down, C.st);
     launch_zero_covered(H->levels[l].cmp, C.R[l - 1], C.st);
@@ -674,7 +674,7 @@ void comp_correct_T(Comp& C, const amg_solve_opts& o, int l) {
   Level& L = H->levels[l];
   launch_zero<double>(L.E64, L.depths[0].nstored, C.st);
   comp_level_vcycle(C, l, o, C.R[l], L0.scal + S_LEV + l);
-  const double down = 1.0 / (1 << dim);
+  const double down = 1.0 / std::pow((double)H->ratio, dim);  // 1 / children per coarse cell
   for (int m = l + 1; m <= C.hi; ++m) {
     launch_fill<double>(H->levels[m - 1].depths[0], H->levels[m - 1].E64, nullptr, C.st);
     launch_amr_prolong(dim, H->levels[m].cmp, H->levels[m - 1].E64, C.X[m], H->levels[m].E64, C.st, down);
@@ -714,7 +714,8 @@ int amg_create(int dim, const double* x_lo, const double* x_hi, const int32_t* b
                amg_hier** out) {
   if (!out) return AMG_EINVAL;
   *out = nullptr;
-  if ((dim != 2 && dim != 3) || !x_lo || !x_hi || !base_cells || ratio != 2 || nlevels < 1 || nlevels > 16)
+  if ((dim != 2 && dim != 3) || !x_lo || !x_hi || !base_cells || (ratio != 2 && ratio != 4) || nlevels < 1 ||
+      nlevels > 16)
     return AMG_EINVAL;
   double h0 = 0;
   for (int d = 0; d < dim; ++d) {
@@ -938,7 +939,7 @@ int amg_finalize(amg_hier* H) {
   for (int l = 1; l < H->nlevels; ++l) {
     CicTable& T = H->levels[l].cic;
     if (T.fd.empty()) continue;
-    std::vector<double> w(&T.w[0][0], &T.w[0][0] + 50);
+    std::vector<double> w(&T.w[0][0], &T.w[0][0] + 100);
     TRY(upload(H, &T.d_w, w));
     TRY(upload(H, &T.d_fd, T.fd));
     TRY(upload(H, &T.d_src, T.src));
@@ -951,7 +952,7 @@ int amg_finalize(amg_hier* H) {
     Level& L = H->levels[l];
     if (L.cf_mode != AMG_CF_INTERP) continue;
     Composite& X = L.cmp;
-    std::vector<double> w(&X.w[0][0], &X.w[0][0] + 50);
+    std::vector<double> w(&X.w[0][0], &X.w[0][0] + 100);
     TRY(upload(H, &X.d_w, w));
     TRY(upload(H, &X.d_cfi_dst, X.cfi_dst));
     TRY(upload(H, &X.d_cfi_src, X.cfi_src));

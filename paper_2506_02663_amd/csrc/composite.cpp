@@ -10,7 +10,7 @@
 //    keeps it inside the domain.  The weights are computed here by solving
 //    the 5 x 5 moment system.
 //  * Average-down (eq. AMR_avergingDownToCrse, COH-4): coarse cell := mean of
-//    its 2^D children.
+//    its r^D children (r the refinement ratio, 2 or 4).
 //  * Refluxing (COH-3): at a valid coarse cell, the coarse flux through a face
 //    bordering level l is replaced by the mean of the fine fluxes through the
 //    fine faces covering it (fourth-order face derivatives, eq. cell2face).
@@ -25,15 +25,16 @@ namespace amg {
 
 namespace {
 
-// weights[(s + 2) * 2 + child][m]: five window cells m = 0..4, window shifted
-// by s cells from the parent's centred position (parent = window cell 2 - s)
-void cfi_weights(double W[10][5]) {
+// weights[(s + 2) * r + child][m]: five window cells m = 0..4, window
+// shifted by s cells from the parent's centred position (parent = window
+// cell 2 - s), child 0..r-1 from the parent's low end
+void cfi_weights(double W[20][5], int r) {
   for (int s = -2; s <= 2; ++s)
-    for (int a = 0; a < 2; ++a) {
+    for (int a = 0; a < r; ++a) {
       // moment matrix M[m][k] = average of x^k over [m, m+1]; child average of
       // the quartic = c . coef with M coef = U, so the weights solve M^T w = c
       long double A[5][6];
-      const long double x0 = (2 - s) + 0.5L * a, x1 = x0 + 0.5L;
+      const long double x0 = (2 - s) + (long double)a / r, x1 = x0 + 1.0L / r;
       for (int k = 0; k < 5; ++k) {
         for (int m = 0; m < 5; ++m) A[k][m] = (std::pow((long double)(m + 1), k + 1) - std::pow((long double)m, k + 1)) / (k + 1);
         A[k][5] = (std::pow(x1, k + 1) - std::pow(x0, k + 1)) / ((k + 1) * (x1 - x0));
@@ -49,7 +50,7 @@ void cfi_weights(double W[10][5]) {
           for (int j = 0; j < 6; ++j) A[r][j] -= f * A[c][j];
         }
       }
-      for (int m = 0; m < 5; ++m) W[(s + 2) * 2 + a][m] = (double)(A[m][5] / A[m][m]);
+      for (int m = 0; m < 5; ++m) W[(s + 2) * r + a][m] = (double)(A[m][5] / A[m][m]);
     }
 }
 
@@ -94,7 +95,7 @@ int64_t elem(const Depth& D, int b, const int* g, int dim) {
   return e;
 }
 
-int floordiv2(int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
+int floordiv(int v, int r) { return v >= 0 ? v / r : -((-v + r - 1) / r); }
 
 }  // namespace
 
@@ -104,7 +105,9 @@ int build_composite(amg_hier* H, int l, std::string& err) {
   Composite& X = F.cmp;
   const int dim = H->dim;
   char buf[256];
-  cfi_weights(X.w);
+  const int r = H->ratio;
+  X.r = r;
+  cfi_weights(X.w, r);
   const Owner oc = make_owner(H, C, l - 1), of = make_owner(H, F, l);
   const Depth& DF = F.depths[0];
   const Depth& DC = C.depths[0];
@@ -114,10 +117,10 @@ int build_composite(amg_hier* H, int l, std::string& err) {
   for (size_t b = 0; b < DF.boxes.size(); ++b) {
     const Box& B = DF.boxes[b];
     int g[3];
-    for (g[2] = B.lo[2]; g[2] <= B.hi[2]; g[2] += (dim == 3 ? 2 : 1))
-      for (g[1] = B.lo[1]; g[1] <= B.hi[1]; g[1] += 2)
-        for (g[0] = B.lo[0]; g[0] <= B.hi[0]; g[0] += 2) {
-          int p[3] = {g[0] / 2, g[1] / 2, dim == 3 ? g[2] / 2 : 0};
+    for (g[2] = B.lo[2]; g[2] <= B.hi[2]; g[2] += (dim == 3 ? r : 1))
+      for (g[1] = B.lo[1]; g[1] <= B.hi[1]; g[1] += r)
+        for (g[0] = B.lo[0]; g[0] <= B.hi[0]; g[0] += r) {
+          int p[3] = {g[0] / r, g[1] / r, dim == 3 ? g[2] / r : 0};
           if (oc.at(p) < 0) {
             snprintf(buf, sizeof buf, "level %d is not nested in level %d", l, l - 1);
             err = buf;
@@ -160,13 +163,13 @@ int build_composite(amg_hier* H, int l, std::string& err) {
               }
               int lo[3] = {0, 0, 0};
               for (int e = 0; e < dim; ++e) {
-                const int P = floordiv2(g[e]);
+                const int P = floordiv(g[e], r);
                 const int N = (int)oc.n[e];
                 int sh = 0;
                 if (P < 2) sh = 2 - P;
                 if (P > N - 3) sh = (N - 3) - P;
                 lo[e] = P + sh - 2;
-                X.cfi_w.push_back((uint8_t)((sh + 2) * 2 + (g[e] - 2 * P)));
+                X.cfi_w.push_back((uint8_t)((sh + 2) * r + (g[e] - r * P)));
               }
               for (int w = 0; w < nwin; ++w) {
                 int q[3] = {lo[0] + w % 5, lo[1] + (w / 5) % 5, dim == 3 ? lo[2] + w / 25 : 0};
@@ -196,10 +199,10 @@ int build_composite(amg_hier* H, int l, std::string& err) {
     const Box& B = DF.boxes[b];
     const BoxD& Y = DF.boxd[b];
     int g[3];
-    for (g[2] = B.lo[2]; g[2] <= B.hi[2]; g[2] += (dim == 3 ? 2 : 1))
-      for (g[1] = B.lo[1]; g[1] <= B.hi[1]; g[1] += 2)
-        for (g[0] = B.lo[0]; g[0] <= B.hi[0]; g[0] += 2) {
-          int p[3] = {g[0] / 2, g[1] / 2, dim == 3 ? g[2] / 2 : 0};
+    for (g[2] = B.lo[2]; g[2] <= B.hi[2]; g[2] += (dim == 3 ? r : 1))
+      for (g[1] = B.lo[1]; g[1] <= B.hi[1]; g[1] += r)
+        for (g[0] = B.lo[0]; g[0] <= B.hi[0]; g[0] += r) {
+          int p[3] = {g[0] / r, g[1] / r, dim == 3 ? g[2] / r : 0};
           AvgD a;
           memset(&a, 0, sizeof a);
           a.ce = elem(DC, oc.at(p), p, dim);
@@ -235,27 +238,27 @@ int build_composite(amg_hier* H, int l, std::string& err) {
               j[d] += sg;
               if (!is_cov(j)) continue;
               // first fine cell past the face, transverse offset 0
-              int f0[3] = {2 * i[0], 2 * i[1], dim == 3 ? 2 * i[2] : 0};
-              f0[d] = sg > 0 ? 2 * j[d] : 2 * j[d] + 1;
+              int f0[3] = {r * i[0], r * i[1], dim == 3 ? r * i[2] : 0};
+              f0[d] = sg > 0 ? r * j[d] : r * j[d] + r - 1;
               const int fb = of.at(f0);
               if (fb < 0) {
                 err = "refluxing: the fine cell past a coarse-fine face is not in the fine level";
                 return AMG_ELAYOUT;
               }
               const BoxD& Z = DF.boxd[fb];
-              RfxFaceD r;
-              memset(&r, 0, sizeof r);
-              r.fe = elem(DF, fb, f0, dim);
-              r.fsn = sg * Z.s[d];
+              RfxFaceD rf;
+              memset(&rf, 0, sizeof rf);
+              rf.fe = elem(DF, fb, f0, dim);
+              rf.fsn = sg * Z.s[d];
               int t[2] = {-1, -1}, k = 0;
               for (int e = 0; e < dim; ++e)
                 if (e != d) t[k++] = e;
-              r.ft0 = Z.s[t[0]];
-              r.ft1 = dim == 3 ? Z.s[t[1]] : 0;
-              r.csn = sg * Y.s[d];
-              r.d = d;
-              r.sg = sg;
-              X.rfx_face.push_back(r);
+              rf.ft0 = Z.s[t[0]];
+              rf.ft1 = dim == 3 ? Z.s[t[1]] : 0;
+              rf.csn = sg * Y.s[d];
+              rf.d = d;
+              rf.sg = sg;
+              X.rfx_face.push_back(rf);
             }
           if (X.rfx_face.size() > nf0) {
             X.rfx_cell.push_back(elem(DC, (int)b, i, dim));
@@ -292,7 +295,8 @@ int build_composite(amg_hier* H, int l, std::string& err) {
     // (1/hc) sum_faces [mean_t Ff_t - Fc], fluxes (-v[+2] + 15 v[+1] - 15 v[0]
     // + v[-1]) / 12h along the face normal n
     const double hc = DC.h, hf = DF.h;
-    const double nf = (double)(1 << (dim - 1));
+    const int nft = dim == 2 ? r : r * r;  // fine faces covering a coarse face
+    const double nf = (double)nft;
     std::vector<std::pair<int64_t, std::pair<int32_t, double>>> tc, tf;
     const int cw[4] = {1, -15, 15, -1};  // offsets -1, 0, 1, 2 along n
     for (size_t i = 0; i + 1 < X.rfx_ptr.size(); ++i) {
@@ -301,8 +305,8 @@ int build_composite(amg_hier* H, int l, std::string& err) {
         const RfxFaceD& F = X.rfx_face[k];
         for (int o = 0; o < 4; ++o)
           tc.push_back({c + (int64_t)(o - 1) * F.csn, {(int32_t)i, -cw[o] / (12.0 * hc * hc)}});
-        for (int t = 0; t < (1 << (dim - 1)); ++t) {
-          const int64_t e = F.fe + ((t & 1) ? F.ft0 : 0) + ((t & 2) ? F.ft1 : 0);
+        for (int t = 0; t < nft; ++t) {
+          const int64_t e = F.fe + (int64_t)(t % r) * F.ft0 + (int64_t)(t / r) * F.ft1;
           // fine flux at the face: offsets -2, -1, 0, 1 from e along n
           for (int o = 0; o < 4; ++o)
             tf.push_back({e + (int64_t)(o - 2) * F.fsn, {(int32_t)i, cw[o] / (12.0 * hf * hc * nf)}});
@@ -341,8 +345,8 @@ int build_composite(amg_hier* H, int l, std::string& err) {
           if (F.d != d) continue;
           for (int o = 0; o < 4; ++o)
             vc.push_back({c + (int64_t)(o - 1) * F.csn, {(int32_t)i, -F.sg * vw[o] / (12.0 * hc)}});
-          for (int t = 0; t < (1 << (dim - 1)); ++t) {
-            const int64_t e = F.fe + ((t & 1) ? F.ft0 : 0) + ((t & 2) ? F.ft1 : 0);
+          for (int t = 0; t < nft; ++t) {
+            const int64_t e = F.fe + (int64_t)(t % r) * F.ft0 + (int64_t)(t / r) * F.ft1;
             for (int o = 0; o < 4; ++o)
               vf.push_back({e + (int64_t)(o - 2) * F.fsn, {(int32_t)i, F.sg * vw[o] / (12.0 * hc * nf)}});
           }
@@ -361,16 +365,16 @@ int build_composite(amg_hier* H, int l, std::string& err) {
     for (g[2] = B.lo[2]; g[2] <= B.hi[2]; ++g[2])
       for (g[1] = B.lo[1]; g[1] <= B.hi[1]; ++g[1])
         for (g[0] = B.lo[0]; g[0] <= B.hi[0]; ++g[0]) {
-          int p[3] = {g[0] / 2, g[1] / 2, dim == 3 ? g[2] / 2 : 0};
+          int p[3] = {g[0] / r, g[1] / r, dim == 3 ? g[2] / r : 0};
           const int cb = oc.at(p);
-          ProlD r;
-          memset(&r, 0, sizeof r);
-          r.fe = elem(DF, (int)b, g, dim);
-          r.pe = elem(DC, cb, p, dim);
-          r.cs1 = DC.boxd[cb].s[1];
-          r.cs2 = dim == 3 ? DC.boxd[cb].s[2] : 0;
-          r.child = (g[0] & 1) | ((g[1] & 1) << 1) | (dim == 3 ? ((g[2] & 1) << 2) : 0);
-          X.pro.push_back(r);
+          ProlD q;
+          memset(&q, 0, sizeof q);
+          q.fe = elem(DF, (int)b, g, dim);
+          q.pe = elem(DC, cb, p, dim);
+          q.cs1 = DC.boxd[cb].s[1];
+          q.cs2 = dim == 3 ? DC.boxd[cb].s[2] : 0;
+          q.child = (g[0] % r) | ((g[1] % r) << 2) | (dim == 3 ? ((g[2] % r) << 4) : 0);
+          X.pro.push_back(q);
         }
   }
 
@@ -405,7 +409,8 @@ int build_cic(amg_hier* H, int l, std::string& err) {
   const int dim = H->dim;
   const int nwin = dim == 2 ? 25 : 125;
   char buf[256];
-  cfi_weights(T.w);
+  const int r = H->ratio;
+  cfi_weights(T.w, r);
   const Owner oc = make_owner(H, C, l - 1);
   const Depth& DF = F.depths[0];
   const Depth& DC = C.depths[0];
@@ -444,13 +449,13 @@ int build_cic(amg_hier* H, int l, std::string& err) {
               g[d] += m * sg;
               int lo[3] = {0, 0, 0};
               for (int e = 0; e < dim; ++e) {
-                const int P = floordiv2(g[e]);
+                const int P = floordiv(g[e], r);
                 const int N = (int)oc.n[e];
                 int sh = 0;
                 if (P < 2) sh = 2 - P;
                 if (P > N - 3) sh = (N - 3) - P;
                 lo[e] = P + sh - 2;
-                T.wsel.push_back((uint8_t)((sh + 2) * 2 + (g[e] - 2 * P)));
+                T.wsel.push_back((uint8_t)((sh + 2) * r + (g[e] - r * P)));
               }
               for (int w = 0; w < nwin; ++w) {
                 int q[3] = {lo[0] + w % 5, lo[1] + (w / 5) % 5, dim == 3 ? lo[2] + w / 25 : 0};

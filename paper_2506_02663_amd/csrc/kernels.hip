@@ -1892,27 +1892,46 @@ __global__ void __launch_bounds__(256) k_cfi(int n, const int64_t* __restrict__ 
   uf[dst[i]] = (T)acc;
 }
 
-// coarse cell := mean of its 2^DIM children
+// sum of the r^DIM children of a coarse cell (the first child at e.fe)
+template <typename T, int DIM>
+__device__ __forceinline__ T children_sum(const AvgD& e, const T* __restrict__ uf, int r) {
+  if (r == 2) {
+    T s = uf[e.fe] + uf[e.fe + 1] + uf[e.fe + e.fs1] + uf[e.fe + e.fs1 + 1];
+    if (DIM == 3)
+      s += uf[e.fe + e.fs2] + uf[e.fe + e.fs2 + 1] + uf[e.fe + e.fs2 + e.fs1] + uf[e.fe + e.fs2 + e.fs1 + 1];
+    return s;
+  }
+  T s = T(0);
+  for (int cz = 0; cz < (DIM == 3 ? r : 1); ++cz)
+    for (int cy = 0; cy < r; ++cy)
+      for (int cx = 0; cx < r; ++cx) s += uf[e.fe + cx + (int64_t)cy * e.fs1 + (int64_t)cz * e.fs2];
+  return s;
+}
+
+// coarse cell := mean of its r^DIM children
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_avgdown(int n, const AvgD* __restrict__ a, const T* __restrict__ uf,
-                                                 T* __restrict__ uc) {
+                                                 T* __restrict__ uc, int r) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const AvgD e = a[i];
-  T s = uf[e.fe] + uf[e.fe + 1] + uf[e.fe + e.fs1] + uf[e.fe + e.fs1 + 1];
-  if (DIM == 3) s += uf[e.fe + e.fs2] + uf[e.fe + e.fs2 + 1] + uf[e.fe + e.fs2 + e.fs1] + uf[e.fe + e.fs2 + e.fs1 + 1];
-  uc[e.ce] = s * T(DIM == 2 ? 0.25 : 0.125);
+  const T s = children_sum<T, DIM>(e, uf, r);
+  if (r == 2)
+    uc[e.ce] = s * T(DIM == 2 ? 0.25 : 0.125);
+  else
+    uc[e.ce] = s * T(1.0 / (DIM == 2 ? r * r : r * r * r));
 }
 
 // refluxing: r[c] += kappa * sum over the cell's coarse-fine faces of
 // (mean fine flux - coarse flux) / hc, fluxes = fourth-order derivatives
-// along the normal n pointing into the finer level
+// along the normal n pointing into the finer level; ratio^(DIM-1) fine faces
+// cover a coarse face
 template <int DIM>
 __global__ void __launch_bounds__(256) k_reflux(int ncell, const int64_t* __restrict__ cell,
                                                 const int32_t* __restrict__ ptr, const RfxFaceD* __restrict__ faces,
                                                 const double* __restrict__ uc, const double* __restrict__ uf,
                                                 double* __restrict__ r, double kappa, double inv12hc, double inv12hf,
-                                                double inv_hc) {
+                                                double inv_hc, int ratio) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= ncell) return;
   const int64_t c = cell[i];
@@ -1922,13 +1941,13 @@ __global__ void __launch_bounds__(256) k_reflux(int ncell, const int64_t* __rest
     const int64_t n = F.csn;
     const double Fc = (-uc[c + 2 * n] + 15.0 * uc[c + n] - 15.0 * uc[c] + uc[c - n]) * inv12hc;
     const int64_t fn = F.fsn;
+    const int nt = DIM == 2 ? ratio : ratio * ratio;
     double Ff = 0.0;
-#pragma unroll
-    for (int t = 0; t < (1 << (DIM - 1)); ++t) {
-      const int64_t e = F.fe + ((t & 1) ? F.ft0 : 0) + ((t & 2) ? F.ft1 : 0);
+    for (int t = 0; t < nt; ++t) {
+      const int64_t e = F.fe + (int64_t)(t % ratio) * F.ft0 + (int64_t)(t / ratio) * F.ft1;
       Ff += (-uf[e + fn] + 15.0 * uf[e] - 15.0 * uf[e - fn] + uf[e - 2 * fn]) * inv12hf;
     }
-    Ff *= 1.0 / (1 << (DIM - 1));
+    Ff *= 1.0 / nt;
     corr += (Ff - Fc) * inv_hc;
   }
   r[c] += kappa * corr;
@@ -1943,7 +1962,7 @@ __global__ void __launch_bounds__(256) k_reflux_div(int ncell, const int64_t* __
                                                     const int32_t* __restrict__ ptr,
                                                     const RfxFaceD* __restrict__ faces, CPtrs wc, CPtrs wf,
                                                     double* __restrict__ div,
-                                                    double inv_hc) {
+                                                    double inv_hc, int ratio) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= ncell) return;
   const int64_t c = cell[i];
@@ -1955,29 +1974,42 @@ __global__ void __launch_bounds__(256) k_reflux_div(int ncell, const int64_t* __
     const int64_t n = F.csn;
     const double Fc = (-uc[c + 2 * n] + 7.0 * uc[c + n] + 7.0 * uc[c] - uc[c - n]) * (1.0 / 12.0);
     const int64_t fn = F.fsn;
+    const int nt = DIM == 2 ? ratio : ratio * ratio;
     double Ff = 0.0;
-#pragma unroll
-    for (int t = 0; t < (1 << (DIM - 1)); ++t) {
-      const int64_t e = F.fe + ((t & 1) ? F.ft0 : 0) + ((t & 2) ? F.ft1 : 0);
+    for (int t = 0; t < nt; ++t) {
+      const int64_t e = F.fe + (int64_t)(t % ratio) * F.ft0 + (int64_t)(t / ratio) * F.ft1;
       Ff += (-uf[e + fn] + 7.0 * uf[e] + 7.0 * uf[e - fn] - uf[e - 2 * fn]) * (1.0 / 12.0);
     }
-    Ff *= 1.0 / (1 << (DIM - 1));
+    Ff *= 1.0 / nt;
     corr += F.sg * (Ff - Fc) * inv_hc;
   }
   div[c] += corr;
 }
 
 // prolongation of a coarse correction onto the finer level (face-neighbour
-// linear): v = (1 - DIM/4) E[P] + 1/4 sum_d E[P +- e_d]; u += v, and ef = v
+// linear): a child whose centre lies delta_d parent widths from the
+// parent's centre along d takes (1 - sum |delta_d|) E[P] + sum |delta_d|
+// E[P + sign(delta_d) e_d] (ratio 2: delta = +-1/4); u += v, and ef = v
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_amr_prolong(int n, const ProlD* __restrict__ p, const T* __restrict__ ec,
-                                                     T* __restrict__ u, T* __restrict__ ef, T scale) {
+                                                     T* __restrict__ u, T* __restrict__ ef, T scale, int r) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const ProlD q = p[i];
-  T v = T(1.0 - DIM * 0.25) * ec[q.pe] +
-        T(0.25) * (ec[q.pe + ((q.child & 1) ? 1 : -1)] + ec[q.pe + ((q.child & 2) ? q.cs1 : -q.cs1)]);
-  if (DIM == 3) v += T(0.25) * ec[q.pe + ((q.child & 4) ? q.cs2 : -q.cs2)];
+  const int a0 = q.child & 3, a1 = (q.child >> 2) & 3, a2 = (q.child >> 4) & 3;
+  T v;
+  if (r == 2) {
+    v = T(1.0 - DIM * 0.25) * ec[q.pe] + T(0.25) * (ec[q.pe + (a0 ? 1 : -1)] + ec[q.pe + (a1 ? q.cs1 : -q.cs1)]);
+    if (DIM == 3) v += T(0.25) * ec[q.pe + (a2 ? q.cs2 : -q.cs2)];
+  } else {
+    const T d0 = (T(a0) + T(0.5)) / T(r) - T(0.5), d1 = (T(a1) + T(0.5)) / T(r) - T(0.5);
+    const T d2 = DIM == 3 ? (T(a2) + T(0.5)) / T(r) - T(0.5) : T(0);
+    const T w0 = d0 < T(0) ? -d0 : d0, w1 = d1 < T(0) ? -d1 : d1, w2 = d2 < T(0) ? -d2 : d2;
+    v = (T(1) - (w0 + w1 + w2)) * ec[q.pe];
+    v += w0 * ec[q.pe + (d0 > T(0) ? 1 : -1)];
+    v += w1 * ec[q.pe + (d1 > T(0) ? q.cs1 : -q.cs1)];
+    if (DIM == 3) v += w2 * ec[q.pe + (d2 > T(0) ? q.cs2 : -q.cs2)];
+  }
   v *= scale;
   u[q.fe] += v;
   if (ef) ef[q.fe] = v;
@@ -1992,16 +2024,14 @@ __global__ void __launch_bounds__(256) k_zero_covered(int n, const AvgD* __restr
   if (i < n) u[a[i].ce] = 0.0;
 }
 
-// coarse cell := scale * (sum of its 2^DIM children)
+// coarse cell := scale * (sum of its r^DIM children)
 template <int DIM>
 __global__ void __launch_bounds__(256) k_sumdown(int n, const AvgD* __restrict__ a, const double* __restrict__ uf,
-                                                 double* __restrict__ uc, double scale) {
+                                                 double* __restrict__ uc, double scale, int r) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const AvgD e = a[i];
-  double s = uf[e.fe] + uf[e.fe + 1] + uf[e.fe + e.fs1] + uf[e.fe + e.fs1 + 1];
-  if (DIM == 3) s += uf[e.fe + e.fs2] + uf[e.fe + e.fs2 + 1] + uf[e.fe + e.fs2 + e.fs1] + uf[e.fe + e.fs2 + e.fs1 + 1];
-  uc[e.ce] = s * scale;
+  uc[e.ce] = children_sum<double, DIM>(e, uf, r) * scale;
 }
 
 // refluxing, transposed: out[elem[k]] += lscale * sum over entries of
@@ -2063,7 +2093,8 @@ __global__ void __launch_bounds__(256) k_cfi_T(int n, const int64_t* __restrict_
   r[elem[k]] -= acc;
 }
 
-// adjoint of the average-down: rf[child] += rc[parent] / 2^DIM
+// adjoint of the average-down: rf[child] += scale * rc[parent] (scale =
+// 1 / ratio^DIM)
 __global__ void __launch_bounds__(256) k_pass_down(int n, const ProlD* __restrict__ p, const double* __restrict__ rc,
                                                    double* __restrict__ rf, double scale) {
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -2322,10 +2353,10 @@ void launch_reflux_div(int dim, const Composite& X, CPtrs wc, CPtrs wf, double* 
   if (!n) return;
   if (dim == 2)
     hipLaunchKernelGGL(k_reflux_div<2>, dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_rfx_cell, X.d_rfx_ptr,
-                       X.d_rfx_face, wc, wf, div, 1.0 / hc);
+                       X.d_rfx_face, wc, wf, div, 1.0 / hc, X.r);
   else
     hipLaunchKernelGGL(k_reflux_div<3>, dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_rfx_cell, X.d_rfx_ptr,
-                       X.d_rfx_face, wc, wf, div, 1.0 / hc);
+                       X.d_rfx_face, wc, wf, div, 1.0 / hc, X.r);
 }
 
 void launch_tile_dot(int dim, const Depth& D, const double* a, const double* b, double* part, hipStream_t st) {
@@ -2568,9 +2599,9 @@ void launch_avgdown(int dim, const Composite& X, const double* uf, double* uc, h
   const int n = (int)X.avg.size();
   if (!n) return;
   if (dim == 2)
-    hipLaunchKernelGGL((k_avgdown<double, 2>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_avg, uf, uc);
+    hipLaunchKernelGGL((k_avgdown<double, 2>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_avg, uf, uc, X.r);
   else
-    hipLaunchKernelGGL((k_avgdown<double, 3>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_avg, uf, uc);
+    hipLaunchKernelGGL((k_avgdown<double, 3>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_avg, uf, uc, X.r);
 }
 
 void launch_reflux(int dim, const Composite& X, const double* uc, const double* uf, double* r, double kappa,
@@ -2579,10 +2610,10 @@ void launch_reflux(int dim, const Composite& X, const double* uc, const double* 
   if (!n) return;
   if (dim == 2)
     hipLaunchKernelGGL(k_reflux<2>, dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_rfx_cell, X.d_rfx_ptr,
-                       X.d_rfx_face, uc, uf, r, kappa, 1.0 / (12 * hc), 1.0 / (12 * hf), 1.0 / hc);
+                       X.d_rfx_face, uc, uf, r, kappa, 1.0 / (12 * hc), 1.0 / (12 * hf), 1.0 / hc, X.r);
   else
     hipLaunchKernelGGL(k_reflux<3>, dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_rfx_cell, X.d_rfx_ptr,
-                       X.d_rfx_face, uc, uf, r, kappa, 1.0 / (12 * hc), 1.0 / (12 * hf), 1.0 / hc);
+                       X.d_rfx_face, uc, uf, r, kappa, 1.0 / (12 * hc), 1.0 / (12 * hf), 1.0 / hc, X.r);
 }
 
 void launch_amr_prolong(int dim, const Composite& X, const double* ec, double* u, double* ef, hipStream_t st,
@@ -2591,10 +2622,10 @@ void launch_amr_prolong(int dim, const Composite& X, const double* ec, double* u
   if (!n) return;
   if (dim == 2)
     hipLaunchKernelGGL((k_amr_prolong<double, 2>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_pro, ec, u, ef,
-                       scale);
+                       scale, X.r);
   else
     hipLaunchKernelGGL((k_amr_prolong<double, 3>), dim3((n + 255) / 256), dim3(256), 0, st, n, X.d_pro, ec, u, ef,
-                       scale);
+                       scale, X.r);
 }
 
 #define GRID1(n) dim3((unsigned)(((n) + 255) / 256)), dim3(256)
@@ -2606,9 +2637,9 @@ void launch_sumdown(int dim, const Composite& X, const double* uf, double* uc, d
   const int n = (int)X.avg.size();
   if (!n) return;
   if (dim == 2)
-    hipLaunchKernelGGL(k_sumdown<2>, GRID1(n), 0, st, n, X.d_avg, uf, uc, scale);
+    hipLaunchKernelGGL(k_sumdown<2>, GRID1(n), 0, st, n, X.d_avg, uf, uc, scale, X.r);
   else
-    hipLaunchKernelGGL(k_sumdown<3>, GRID1(n), 0, st, n, X.d_avg, uf, uc, scale);
+    hipLaunchKernelGGL(k_sumdown<3>, GRID1(n), 0, st, n, X.d_avg, uf, uc, scale, X.r);
 }
 void launch_rfx_T(const Composite& X, const double* lam_c, double lscale, double* abc, double* abf, hipStream_t st) {
   int n = (int)X.rfxTc_elem.size();

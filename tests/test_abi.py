@@ -80,9 +80,9 @@ def test_host_argument_checks(lib):
 # a row (eqs. velBCHomoDiri5th, Neumann5), so boxes have at least 4 cells per
 # side; the interpolation window of the AMRCFI must lie on the coarse level.
 
-def _layout(L, dim, n, levels, cf=None, bc=0):
+def _layout(L, dim, n, levels, cf=None, bc=0, ratio=2):
     from paper_2506_02663_amd import amg as A
-    rc, h = _create(L, dim, [n] * dim, nlevels=len(levels))
+    rc, h = _create(L, dim, [n] * dim, nlevels=len(levels), ratio=ratio)
     assert rc == A.OK
     for d in range(dim):
         for s in (0, 1):
@@ -117,6 +117,8 @@ def _finalize_code(L, h):
     ("periodic_one_side", "EINVAL", "periodic on one side only"),
     ("periodic_fine_touches_side", "EUNSUPPORTED", "touches the periodic side"),
     ("periodic_isolated", "EUNSUPPORTED", "isolated boxes with periodic"),
+    ("unaligned_ratio4", "ELAYOUT", "not properly refined"),
+    ("not_nested_ratio4", "ELAYOUT", "not nested"),
 ])
 def test_layout_rejected_before_any_device_call(lib, case, want, text):
     from paper_2506_02663_amd import amg as A
@@ -146,6 +148,10 @@ def test_layout_rejected_before_any_device_call(lib, case, want, text):
         assert L.amg_set_physical_bc(h, 1, 0, A.PERIODIC) == A.OK
     elif case == "periodic_fine_touches_side":
         h = _layout(L, 2, 32, [full, [((0, 16), (15, 31))]], bc=A.PERIODIC)
+    elif case == "unaligned_ratio4":  # corners multiples of 2, not of 4
+        h = _layout(L, 2, 32, [full, [((18, 16), (41, 47))]], ratio=4)
+    elif case == "not_nested_ratio4":  # level 2 reaching beyond level 1 (ratio 4)
+        h = _layout(L, 2, 16, [[((0, 0), (15, 15))], [((16, 16), (31, 31))], [((64, 64), (159, 159))]], ratio=4)
     elif case == "periodic_isolated":
         h = _layout(L, 2, 32, [full], bc=A.PERIODIC)
         assert L.amg_set_isolated_boxes(h, 0, 1) == A.OK

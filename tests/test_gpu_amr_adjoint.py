@@ -21,14 +21,17 @@ LAYOUTS = {
     "corner": ((16, 8), 1 / 16, [[((0, 0), (15, 7))], [((0, 0), (7, 7))]]),
     "boundary": ((32, 16), 1 / 32, [[((0, 0), (15, 15)), ((16, 0), (31, 15))],
                                    [((0, 0), (15, 15)), ((16, 0), (23, 11))]]),
+    "two_level_r4": ((16, 16), 1 / 16, [[((0, 0), (15, 15))], [((16, 16), (39, 47)), ((40, 16), (47, 31))]], 4),
+    "three_level_r4": ((8, 8), 1 / 8, [[((0, 0), (7, 7))], [((8, 8), (23, 23))], [((48, 48), (79, 79))]], 4),
 }
 CASES = [("D", "helmholtz", 0.3), ("N", "poisson", 0.0), ("D", "poisson", 0.0), ("N", "helmholtz", 0.5)]
 
 
 def build(name, bc, op, c0):
-    base, h0, boxes = LAYOUTS[name]
-    OH = amr.Hierarchy(base, h0, boxes, {(d, s): bc for d in range(2) for s in (0, 1)})
-    H = A.Hierarchy(2, base, h0, len(boxes))
+    base, h0, boxes, *rest = LAYOUTS[name]
+    ratio = rest[0] if rest else 2
+    OH = amr.Hierarchy(base, h0, boxes, {(d, s): bc for d in range(2) for s in (0, 1)}, ratio=ratio)
+    H = A.Hierarchy(2, base, h0, len(boxes), ratio=ratio)
     for l, bl in enumerate(boxes):
         H.set_level_boxes(l, bl)
         if l:

@@ -26,14 +26,17 @@ LAYOUTS = {
                       [((0, 8), (15, 15)), ((16, 8), (23, 23)), ((8, 24), (15, 31))]], "N"),
     "2d_dir": ((16, 16), [[((0, 0), (15, 15))], [((6, 4), (21, 11))]], "D"),
     "3d": ((8, 8, 8), [[((0, 0, 0), (7, 7, 7))], [((4, 4, 4), (11, 11, 15)), ((0, 4, 4), (3, 11, 11))]], "D"),
+    "2d_r4": ((16, 16), [[((0, 0), (15, 15))],
+                         [((0, 16), (31, 31)), ((32, 16), (47, 47)), ((16, 48), (31, 63))]], "N", 4),
 }
 
 
 def build(name, cf_mode=A.CF_DIRICHLET, op=A.HELMHOLTZ, c=1e-3):
-    base, boxes, bc = LAYOUTS[name]
+    base, boxes, bc, *rest = LAYOUTS[name]
+    ratio = rest[0] if rest else 2
     D = len(base)
-    OH = amr.Hierarchy(base, 1.0 / base[0], boxes, {(d, s): bc for d in range(D) for s in (0, 1)})
-    H = A.Hierarchy(D, base, 1.0 / base[0], 2)
+    OH = amr.Hierarchy(base, 1.0 / base[0], boxes, {(d, s): bc for d in range(D) for s in (0, 1)}, ratio=ratio)
+    H = A.Hierarchy(D, base, 1.0 / base[0], 2, ratio=ratio)
     for l, bl in enumerate(boxes):
         H.set_level_boxes(l, bl)
     H.set_cf_mode(1, cf_mode)
@@ -93,7 +96,7 @@ def test_face_data_against_oracle(name, kind):
     assert n > 20
 
 
-@pytest.mark.parametrize("name", ["2d", "3d"])
+@pytest.mark.parametrize("name", ["2d", "3d", "2d_r4"])
 def test_correction_against_oracle(name):
     OH, H = build(name)
     fine = OH.levels[1]

@@ -1,7 +1,7 @@
 """Composite (multi-level) path on the GPU against the oracle: the composite
 residual (interpolated coarse-fine ghosts, refluxing, average-down) element
 by element, and whole composite solves in FP64 (same cycle, same residual
-history) and mixed precision."""
+history) and mixed precision; refinement ratios 2 and 4."""
 import numpy as np
 import pytest
 
@@ -30,11 +30,20 @@ def make_oracle(name, bc):
     if name == "boundary":  # fine boxes touching the physical boundary, two of them face to face
         boxes = [[((0, 0), (15, 15)), ((16, 0), (31, 15))], [((0, 0), (15, 15)), ((16, 0), (23, 11))]]
         return amr.Hierarchy((32, 16), 1.0 / 32, boxes, phys), (32, 16), 1.0 / 32, boxes
+    if name == "two_level_r4":  # refinement ratio 4: an L of two boxes on the 64^2 grid
+        boxes = [[((0, 0), (15, 15))], [((16, 16), (39, 47)), ((40, 16), (47, 31))]]
+        return amr.Hierarchy((16, 16), 1.0 / 16, boxes, phys, ratio=4), (16, 16), 1.0 / 16, boxes
+    if name == "three_level_r4":
+        boxes = [[((0, 0), (7, 7))], [((8, 8), (23, 23))], [((48, 48), (79, 79))]]
+        return amr.Hierarchy((8, 8), 1.0 / 8, boxes, phys, ratio=4), (8, 8), 1.0 / 8, boxes
+    if name == "corner_r4":  # a ratio-4 box in a corner of the domain, touching two physical faces
+        boxes = [[((0, 0), (7, 7))], [((0, 0), (15, 15))]]
+        return amr.Hierarchy((8, 8), 1.0 / 8, boxes, phys, ratio=4), (8, 8), 1.0 / 8, boxes
     raise KeyError(name)
 
 
-def make_gpu(base, h0, boxes, bc, op, c):
-    H = A.Hierarchy(2, base, h0, len(boxes))
+def make_gpu(base, h0, boxes, bc, op, c, ratio=2):
+    H = A.Hierarchy(2, base, h0, len(boxes), ratio=ratio)
     for l, bl in enumerate(boxes):
         H.set_level_boxes(l, bl)
         if l:
@@ -73,13 +82,16 @@ def relmax(G, O, masks):
 CASES = [("corner", "D", "helmholtz", 0.3 / 16), ("corner", "N", "poisson", 0.0),
          ("two_level", "D", "helmholtz", 0.4 / 16), ("two_level", "N", "poisson", 0.0),
          ("three_level", "D", "poisson", 0.0), ("three_level", "N", "helmholtz", 0.2 / 16),
-         ("boundary", "N", "poisson", 0.0), ("boundary", "D", "helmholtz", 0.3 / 32)]
+         ("boundary", "N", "poisson", 0.0), ("boundary", "D", "helmholtz", 0.3 / 32),
+         ("two_level_r4", "D", "helmholtz", 0.4 / 16), ("two_level_r4", "N", "poisson", 0.0),
+         ("three_level_r4", "N", "poisson", 0.0), ("three_level_r4", "D", "helmholtz", 0.2 / 8),
+         ("corner_r4", "D", "poisson", 0.0), ("corner_r4", "N", "helmholtz", 0.3 / 8)]
 
 
 @pytest.mark.parametrize("name,bc,op,c", CASES)
 def test_composite_residual(name, bc, op, c):
     OH, base, h0, boxes = make_oracle(name, bc)
-    H = make_gpu(base, h0, boxes, bc, op, c)
+    H = make_gpu(base, h0, boxes, bc, op, c, OH.ratio)
     U = random_levels(OH, 1)
     F = random_levels(OH, 2)
     FD = random_levels(OH, 3, faces=True)
@@ -101,7 +113,7 @@ def test_composite_residual(name, bc, op, c):
 @pytest.mark.parametrize("name,bc,op,c", CASES)
 def test_composite_solve(name, bc, op, c):
     OH, base, h0, boxes = make_oracle(name, bc)
-    H = make_gpu(base, h0, boxes, bc, op, c)
+    H = make_gpu(base, h0, boxes, bc, op, c, OH.ratio)
     F = random_levels(OH, 4)
     FD = random_levels(OH, 5, faces=True)
     Uo, sto = amr.composite_solve(OH, F, op, c, FD, tol_rel=1e-12, max_cycles=200)
@@ -116,9 +128,13 @@ def test_composite_solve(name, bc, op, c):
         assert relmax(got, Uo, OH.valid) < tol, (prec, st["cycles"], sto["cycles"])
         if prec == A.FP64:
             hist, ho = np.array(st["history"]), np.array(sto["history"])
-            assert abs(len(hist) - len(ho)) <= 1
+            # a slowly converging case (ratio 4, a box in a Dirichlet corner:
+            # about 0.83 per cycle) may cross the target a few cycles apart
+            assert abs(len(hist) - len(ho)) <= max(1, len(ho) // 50)
             k = min(len(hist), len(ho))
-            assert np.allclose(hist[:k], ho[:k], rtol=1e-5, atol=1e-14 * ho[0])
+            # to rounding at the floor: the ratio-4 Neumann composite's last
+            # cycles differ from the oracle's by about 1e-14 r0
+            assert np.allclose(hist[:k], ho[:k], rtol=1e-5, atol=5e-14 * ho[0])
         if OH.singular(op):
             assert np.isclose(st["defects"][0], sto["defect"], rtol=1e-9, atol=1e-13)
 
@@ -128,7 +144,7 @@ def test_composite_solve_over_relaxed_red_black(name, bc, op, c):
     """The composite cycle with over-relaxed red-black level cycles (omega_rb
     1.3) against the oracle's composite solve with the same factor."""
     OH, base, h0, boxes = make_oracle(name, bc)
-    H = make_gpu(base, h0, boxes, bc, op, c)
+    H = make_gpu(base, h0, boxes, bc, op, c, OH.ratio)
     F = random_levels(OH, 6)
     Uo, sto = amr.composite_solve(OH, F, op, c, None, tol_rel=1e-12, max_cycles=200, smoother="rb", omega_rb=1.3)
     assert sto["converged"]
@@ -152,7 +168,7 @@ def test_composite_graph_replays_match_direct_launches_bitwise(name, bc, op, c, 
     synchronisations between solves), gives bit-identical iterates and
     residual histories to direct launches, forward and adjoint."""
     OH, base, h0, boxes = make_oracle(name, bc)
-    H = make_gpu(base, h0, boxes, bc, op, c)
+    H = make_gpu(base, h0, boxes, bc, op, c, OH.ratio)
     f = random_levels(OH, 21)
     fs = [to_dev(H, l, 0, f[l]) for l in range(OH.nlev)]
     for adjoint in (False, True):

@@ -67,11 +67,12 @@ COMPOSITE = {
     "corner": ((16, 8), 1 / 16, [[((0, 0), (15, 7))], [((0, 0), (7, 7))]]),
     "boundary": ((32, 16), 1 / 32, [[((0, 0), (15, 15)), ((16, 0), (31, 15))],
                                    [((0, 0), (15, 15)), ((16, 0), (23, 11))]]),
+    "two_level_r4": ((16, 16), 1 / 16, [[((0, 0), (15, 15))], [((16, 16), (39, 47)), ((40, 16), (47, 31))]], 4),
 }
 
 
-def gpu_hier(base, h0, boxes, kind):
-    H = A.Hierarchy(2, base, h0, len(boxes))
+def gpu_hier(base, h0, boxes, kind, ratio=2):
+    H = A.Hierarchy(2, base, h0, len(boxes), ratio=ratio)
     for l, bl in enumerate(boxes):
         H.set_level_boxes(l, bl)
         if l:
@@ -114,10 +115,11 @@ def relmax(G, O, masks):
 
 @pytest.mark.parametrize("name", list(COMPOSITE))
 def test_composite_gradient_and_divergence(name):
-    base, h0, boxes = COMPOSITE[name]
-    Hp_o = amr.Hierarchy(base, h0, boxes, {(d, s): "N" for d in range(2) for s in (0, 1)})
-    Hw_o = amr.Hierarchy(base, h0, boxes, {(d, s): "D" for d in range(2) for s in (0, 1)})
-    Hp, Hw = gpu_hier(base, h0, boxes, "N"), gpu_hier(base, h0, boxes, "D")
+    base, h0, boxes, *rest = COMPOSITE[name]
+    ratio = rest[0] if rest else 2
+    Hp_o = amr.Hierarchy(base, h0, boxes, {(d, s): "N" for d in range(2) for s in (0, 1)}, ratio=ratio)
+    Hw_o = amr.Hierarchy(base, h0, boxes, {(d, s): "D" for d in range(2) for s in (0, 1)}, ratio=ratio)
+    Hp, Hw = gpu_hier(base, h0, boxes, "N", ratio), gpu_hier(base, h0, boxes, "D", ratio)
     nl = len(boxes)
     phi = rand_levels(Hp_o, 1)
     ph = [to_dev(Hp, l, 0, phi[l]) for l in range(nl)]
@@ -159,12 +161,13 @@ def test_level_projection(name):
         assert relerr(from_dev(Hp, L, 0, phi, lev), phi_o, lev.mask) < tol
 
 
-@pytest.mark.parametrize("name", ["two_level", "three_level"])
+@pytest.mark.parametrize("name", ["two_level", "three_level", "two_level_r4"])
 def test_composite_projection(name):
-    base, h0, boxes = COMPOSITE[name]
-    H_o = amr.Hierarchy(base, h0, boxes, {(d, s): "D" for d in range(2) for s in (0, 1)})
+    base, h0, boxes, *rest = COMPOSITE[name]
+    ratio = rest[0] if rest else 2
+    H_o = amr.Hierarchy(base, h0, boxes, {(d, s): "D" for d in range(2) for s in (0, 1)}, ratio=ratio)
     Hw_o = proj.hierarchy_with(H_o, "D")
-    Hp, Hw = gpu_hier(base, h0, boxes, "N"), gpu_hier(base, h0, boxes, "D")
+    Hp, Hw = gpu_hier(base, h0, boxes, "N", ratio), gpu_hier(base, h0, boxes, "D", ratio)
     nl = len(boxes)
     W = [rand_levels(Hw_o, 31 + d) for d in range(2)]
     wb = [rand_faces(Hw_o, 41 + d) for d in range(2)]
