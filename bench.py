@@ -33,6 +33,8 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "imex"])
+    p.add_argument("--ratio", type=int, default=2, choices=[2, 4],
+                   help="two-level AMR workload: refinement ratio (4: the same patches at h = 1/1024)")
     p.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     p.add_argument("--smoother", default="rb", choices=["jacobi", "rb"])
     p.add_argument("--n", type=int, default=0, help="cells per direction (default: the workload's)")
@@ -480,13 +482,14 @@ def bench_amr(args):
     and the composite pure-Neumann Poisson solve, each from 0 to 1e-10;
     DOF = valid cells of the composite (108,544) per solve."""
     from paper_2506_02663_amd import workloads as W
-    boxes = W.amr_two_level_boxes()
+    ratio = args.ratio
+    boxes = W.amr_two_level_boxes(ratio)
     c = 0.5e-3 / 256
     base = None
     if not args.no_cpu_baseline:
         from oracle import amr
         t0 = time.perf_counter()
-        OH = amr.Hierarchy((256, 256), 1.0 / 256, boxes, {(d, s): "D" for d in range(2) for s in (0, 1)})
+        OH = amr.Hierarchy((256, 256), 1.0 / 256, boxes, {(d, s): "D" for d in range(2) for s in (0, 1)}, ratio=ratio)
         F = []
         for l, lev in enumerate(OH.levels):
             f = lev.zeros()
@@ -508,7 +511,7 @@ def bench_amr(args):
             for op in ("helmholtz", "poisson")}
     systems = []
     for op, bc in (("helmholtz", "D"), ("poisson", "N")):
-        H = A.Hierarchy(2, (256, 256), 1.0 / 256, 2)
+        H = A.Hierarchy(2, (256, 256), 1.0 / 256, 2, ratio=ratio)
         for l, bl in enumerate(boxes):
             H.set_level_boxes(l, bl)
         H.set_cf_mode(1, A.CF_INTERP)
@@ -519,13 +522,14 @@ def bench_amr(args):
         H.finalize()
         fs = []
         for l in range(2):
-            n = 256 * 2 ** l
+            n = 256 * ratio ** l
             f = W.single_level_rhs((n, n), 1.0 / n, op, c if op == "helmholtz" else 0.0, seed=l)
             fs.append(torch.tensor(H.pack(l, 0, lambda i, b, f=f: f[b["lo"][0]:b["hi"][0] + 1,
                                                                     b["lo"][1]:b["hi"][1] + 1]), device="cuda"))
         xs = [torch.zeros_like(f) for f in fs]
         systems.append((op, H, xs, fs))
-    nvalid = 256 * 256 - 57344 // 4 + 57344
+    nfine = sum((hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) for lo, hi in boxes[1])
+    nvalid = 256 * 256 - nfine // ratio ** 2 + nfine
     cycles = {}
 
     def step():
@@ -550,8 +554,9 @@ def bench_amr(args):
         "value": 2 * nvalid * args.steps / dt, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32-in-f64" if prec == A.MIXED else "f64", "data": "synthetic",
-        "config": {"workload": "2D two-level AMR 256^2 + 56 boxes of 32^2 (ratio 2), composite Helmholtz + "
-                               "composite Neumann Poisson", "dof_per_step": 2 * nvalid, "tol_rel": 1e-10,
+        "config": {"workload": f"2D two-level AMR 256^2 + {len(boxes[1])} boxes of {16 * ratio}^2 (ratio {ratio}), "
+                               "composite Helmholtz + composite Neumann Poisson", "dof_per_step": 2 * nvalid,
+                   "tol_rel": 1e-10,
                    "cycles": cycles, "smoother": args.smoother, "precision": args.precision,
                    "omega_rb": w_rb if args.smoother == "rb" else None},
     }

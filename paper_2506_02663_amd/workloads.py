@@ -107,12 +107,14 @@ def disk_boxes(centres_radii, nfine, bs):
     return boxes
 
 
-def amr_two_level_boxes():
+def amr_two_level_boxes(ratio=2):
     """Two-level layout: level 0 one 256^2 box on [0,1]^2; level 1 the 32^2
     boxes of the 512^2 grid whose centres lie inside the disk of radius 0.25
     at (0.5, 0.5) or the disk of radius 0.08 at (0.8, 0.2) (56 boxes, two
-    face-connected components)."""
-    return [[((0, 0), (255, 255))], disk_boxes([((0.5, 0.5), 0.25), ((0.8, 0.2), 0.08)], 512, 32)]
+    face-connected components).  ratio 4: the same patches as 64^2 boxes of
+    the 1024^2 grid."""
+    n = 256 * ratio
+    return [[((0, 0), (255, 255))], disk_boxes([((0.5, 0.5), 0.25), ((0.8, 0.2), 0.08)], n, 16 * ratio)]
 
 
 # ----------------------------------------------------------------------------
