@@ -125,6 +125,114 @@ class Bottom:
         return e
 
 
+def ilu0(K, drop=1e-12):
+    """ILU(0) of the square matrix K (dense array) on its own pattern: the
+    diagonal and the entries whose magnitude exceeds drop times the largest
+    of their row (a bordered system's zero corner is a pivot too).
+    Gaussian elimination in the i-k-j order (Saad, Iterative Methods, Alg.
+    10.4) in which only positions of the pattern are ever written.  Returns
+    the combined factors: strictly lower part of L (unit diagonal implied)
+    and U on and above the diagonal, zero off the pattern."""
+    n = K.shape[0]
+    pat = (np.abs(K) > drop * np.abs(K).max(axis=1, keepdims=True)) | np.eye(n, dtype=bool)
+    LU = np.where(pat, K, 0.0).astype(float)
+    for i in range(1, n):
+        for k in range(i):
+            if not pat[i, k]:
+                continue
+            LU[i, k] /= LU[k, k]
+            for j in range(k + 1, n):
+                if pat[i, j]:
+                    LU[i, j] -= LU[i, k] * LU[k, j]
+    return LU
+
+
+def ilu_apply(LU, v):
+    """z = (L U)^-1 v: forward substitution with the unit lower factor, then
+    back substitution with the upper one."""
+    n = LU.shape[0]
+    y = np.zeros(n)
+    for i in range(n):
+        y[i] = v[i] - LU[i, :i] @ y[:i]
+    z = np.zeros(n)
+    for i in range(n - 1, -1, -1):
+        z[i] = (y[i] - LU[i, i + 1:] @ z[i + 1:]) / LU[i, i]
+    return z
+
+
+def gmres_right(K, b, LU, m, breakdown=1e-14):
+    """m steps of GMRES from x0 = 0, preconditioned on the right by the ILU
+    factors (Saad, Alg. 9.5): Arnoldi with modified Gram-Schmidt on
+    K (LU)^-1, the least-squares problem min ||beta e1 - H y||, then
+    x = (LU)^-1 V y.  Stops early when the new Arnoldi vector's norm falls
+    below breakdown times ||b|| (the Krylov space is invariant)."""
+    n = len(b)
+    beta = float(np.linalg.norm(b))
+    if beta == 0.0:
+        return np.zeros(n)
+    V = np.zeros((n, m + 1))
+    H = np.zeros((m + 1, m))
+    V[:, 0] = b / beta
+    k = m
+    for j in range(m):
+        w = K @ ilu_apply(LU, V[:, j])
+        for i in range(j + 1):
+            H[i, j] = w @ V[:, i]
+            w = w - H[i, j] * V[:, i]
+        H[j + 1, j] = float(np.linalg.norm(w))
+        if H[j + 1, j] <= breakdown * beta:
+            k = j + 1
+            break
+        V[:, j + 1] = w / H[j + 1, j]
+    rhs = np.zeros(k + 1)
+    rhs[0] = beta
+    y = np.linalg.lstsq(H[:k + 1, :k], rhs, rcond=None)[0]
+    return ilu_apply(LU, V[:, :k] @ y)
+
+
+class IluGmresBottom:
+    """The paper's bottom solver for the pressure systems (Section 6.5):
+    ILU(0)-preconditioned GMRES(m) at the coarsest depth, m steps from zero
+    per call.  Each face-connected component is its own system (they do not
+    couple), its unknowns ordered box by box in the level's box order, x
+    fastest within a box; a component on which the operator has a constant
+    null vector is bordered with one zero-mean constraint (last unknown)."""
+
+    def __init__(self, lev, op, c, m):
+        self.lev, self.m = lev, m
+        M, cells = assemble(lev, op, c)
+        pos = {tuple(q): i for i, q in enumerate(cells)}
+        sing = set(lev.singular_components(op))
+        self.systems = []
+        for comp in range(lev.ncomp):
+            order = []
+            for lo, hi in lev.boxes:
+                first = tuple(PAD + v for v in lo)
+                if lev.labels[first] != comp:
+                    continue
+                rng = [range(PAD + a, PAD + b + 1) for a, b in zip(lo, hi)]
+                for q in np.ndindex(*[len(r) for r in rng][::-1]):  # last axis slowest
+                    order.append(pos[tuple(r[qi] for r, qi in zip(rng, q[::-1]))])
+            idx = np.array(order)
+            K = M[np.ix_(idx, idx)]
+            if comp in sing:
+                n = len(idx)
+                K = np.block([[K, np.ones((n, 1))], [np.ones((1, n)), np.zeros((1, 1))]])
+            self.systems.append((idx, K, ilu0(K), comp in sing))
+        self.cells = cells
+
+    def solve(self, f):
+        fv = f[self.lev.mask]
+        out = np.zeros(len(fv))
+        for idx, K, LU, sing in self.systems:
+            b = np.concatenate([fv[idx], [0.0]]) if sing else fv[idx]
+            x = gmres_right(K, b, LU, self.m)
+            out[idx] = x[: len(idx)]
+        e = self.lev.zeros()
+        e[self.lev.mask] = out
+        return e
+
+
 class MG:
     """V(nu1, nu2) cycle on the multigrid depths of one level.
 
@@ -134,14 +242,17 @@ class MG:
     matrix."""
 
     def __init__(self, lev, op, c, nu1=2, nu2=2, smoother="jacobi", omega=2.0 / 3.0, transpose=False,
-                 bottom_cells=0, omega_rb=1.0):
+                 bottom_cells=0, omega_rb=1.0, bottom="exact", bottom_iters=5):
         self.levels = lev.hierarchy(bottom_cells)
         self.op, self.c = op, c
         self.transpose = transpose
         self.nu1, self.nu2, self.smoother, self.omega, self.omega_rb = nu1, nu2, smoother, omega, omega_rb
         self.D = [l.diagonal(op, c) for l in self.levels]
         self.sing = [l.singular_components(op) for l in self.levels]
-        self.bottom = Bottom(self.levels[-1], op, c, transpose)
+        if bottom == "ilu_gmres" and not transpose:
+            self.bottom = IluGmresBottom(self.levels[-1], op, c, bottom_iters)
+        else:
+            self.bottom = Bottom(self.levels[-1], op, c, transpose)
 
     def smooth(self, k, e, f, n):
         lev = self.levels[k]
