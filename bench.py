@@ -33,6 +33,10 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "imex"])
+    p.add_argument("--bottom", default="exact", choices=["exact", "ilu_gmres"],
+                   help="single-level workloads: coarsest-depth solver (the paper's ILU(0)-GMRES, or the exact "
+                        "dense inverse)")
+    p.add_argument("--bottom-iters", type=int, default=5, help="GMRES steps per bottom solve (--bottom ilu_gmres)")
     p.add_argument("--ratio", type=int, default=2, choices=[2, 4],
                    help="two-level AMR workload: refinement ratio (4: the same patches at h = 1/1024)")
     p.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
@@ -288,6 +292,8 @@ def main():
             H.set_tuning(A.TUNE_MARCH2 if dim == 2 else A.TUNE_MARCH3, march)
         if args.bottom_cells:
             H.set_bottom_cells(args.bottom_cells)
+        if args.bottom == "ilu_gmres":
+            H.set_bottom_solver(A.BOTTOM_ILU_GMRES, args.bottom_iters)
         H.finalize()
         fd = torch.tensor(H.pack(0, 0, lambda i, b: f), device="cuda")
         x = torch.zeros_like(fd)
@@ -349,6 +355,7 @@ def main():
                    "cycles": cycles, "smoother": args.smoother, "precision": args.precision,
                    "graph": not args.no_graph, "vcycle": f"V({nu1},{nu2})",
                    "omega_rb": w_rb if args.smoother == "rb" else None, "march": march, "bottom_cells": args.bottom_cells,
+                   "bottom": args.bottom if args.bottom == "exact" else f"ilu_gmres({args.bottom_iters})",
                    "depths": systems[0][1].level_info(0).depths,
                    "split_storage": bool(systems[0][1].level_info(0).split_rb) and prec == A.MIXED and
                    args.smoother == "rb"},

@@ -213,6 +213,26 @@ int amg_set_isolated_boxes(amg_hier* h, int level, int isolated);
  * periodic side or a level of isolated boxes has a periodic direction. */
 int amg_set_physical_bc(amg_hier* h, int d, int side, int type);
 
+/* bottom solvers */
+#define AMG_BOTTOM_EXACT 0     /* dense FP64 inverse of each coarsest system (default) */
+#define AMG_BOTTOM_ILU_GMRES 1 /* ILU(0)-preconditioned GMRES(m), Section 6.5 */
+
+/* Solver of the coarsest multigrid depth in forward V-cycles (Section 6.5):
+ * AMG_BOTTOM_EXACT, or the paper's AMG_BOTTOM_ILU_GMRES: iters (1..16)
+ * steps of GMRES from zero per bottom solve, preconditioned on the right by
+ * the ILU(0) factorisation of each coarsest system (a component, or an
+ * isolated box; bordered with the zero-mean constraint when the operator
+ * is singular on it; pattern: the diagonal and the entries above 1e-12 of
+ * their row's largest; unknowns box by box, x fastest).  The factors are
+ * computed once by amg_finalize (and amg_set_coefficient) and kept as one
+ * dense preconditioning matrix per system, so a preconditioning is a
+ * matrix-vector product; the library adds (iters + 1) Krylov vectors per
+ * system instance.  Adjoint solves keep the exact transposed inverse.  Set
+ * before amg_finalize.  Errors: AMG_EINVAL (kind, iters, layout final);
+ * amg_finalize returns AMG_EUNSUPPORTED if an ILU(0) pivot vanishes or a
+ * coarsest system has more than 4096 unknowns. */
+int amg_set_bottom_solver(amg_hier* h, int kind, int iters);
+
 /* Coarse-fine mode of a level > 0 (default AMG_CF_DIRICHLET): the condition
  * its ghosts take on the coarse-fine interface.  AMG_CF_DIRICHLET /
  * AMG_CF_NEUMANN: the level is solved on its own with face data on the

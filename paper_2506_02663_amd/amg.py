@@ -21,6 +21,7 @@ SMOOTH_JACOBI, SMOOTH_RB = 0, 1
 FP64, MIXED = 0, 1
 F64, F32 = 0, 1
 SOLV_RHS_SHIFT, SOLV_OFF, SOLV_CF_DELTA = 0, 1, 2
+BOTTOM_EXACT, BOTTOM_ILU_GMRES = 0, 1
 CIC_VALUE, CIC_NORMAL_DERIVATIVE = 0, 1
 T_SWEEP, T_FILL, T_RESTRICT, T_PROLONG, T_RESIDUAL, T_SWEEP_SPLIT, T_KINDS = range(7)
 TUNE_MARCH2, TUNE_MARCH3, TUNE_ROW_ALIGN, TUNE_SPLIT_RB = range(4)
@@ -88,6 +89,7 @@ def lib():
         L.amg_set_physical_bc.argtypes = [vp, i32, i32, i32]
         L.amg_set_cf_mode.argtypes = [vp, i32, i32]
         L.amg_set_bottom_cells.argtypes = [vp, i32]
+        L.amg_set_bottom_solver.argtypes = [vp, i32, i32]
         L.amg_set_operator.argtypes = [vp, i32, dbl]
         L.amg_finalize.argtypes = [vp]
         L.amg_level_info.argtypes = [vp, i32, C.POINTER(LevelDesc)]
@@ -211,6 +213,10 @@ class Hierarchy:
 
     def set_bottom_cells(self, cells):
         self._check(lib().amg_set_bottom_cells(self.h, int(cells)))
+
+    def set_bottom_solver(self, kind, iters=5):
+        """BOTTOM_EXACT or BOTTOM_ILU_GMRES with iters GMRES steps."""
+        self._check(lib().amg_set_bottom_solver(self.h, int(kind), int(iters)))
 
     def set_operator(self, kind, c=0.0):
         self._check(lib().amg_set_operator(self.h, kind, float(c)))

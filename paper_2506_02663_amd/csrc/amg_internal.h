@@ -87,6 +87,11 @@ struct BottomGroupD {      // systems sharing one dense inverse
   int64_t idx;             // offset of ninst*n element indices in the index pool
   int32_t n, ninst;
   int64_t matT;            // offset of its transpose (column-major) in the matrix pool
+  // ILU(0)-GMRES bottom (amg_set_bottom_solver): the N x N system (N = n, or
+  // n + 1 with the zero-mean border), K P and P = (L U)^-1 column-major in
+  // the matrix pool, and the offset of its instances' Krylov vectors
+  int64_t ilub, ilup, ws;
+  int32_t N, pad;
 };
 
 // ---- composite (multi-level) tables -------------------------------------------
@@ -288,6 +293,8 @@ struct Level {
   double* d_mat = nullptr;
   int64_t* d_idx = nullptr;
   size_t nmat = 0;           // doubles in d_mat
+  double* d_gws = nullptr;   // Krylov vectors of the ILU(0)-GMRES bottom
+  int64_t ngws = 0;          // doubles in d_gws
   double* r64 = nullptr;     // outer residual
   double* fsh = nullptr;     // right-hand side after the solvability shift
   double* partial = nullptr; // tile partials (max over all depths)
@@ -341,6 +348,8 @@ struct amg_hier {
   hipStream_t own = nullptr;  // used when the caller passes no stream
   amg::GraphCache comp_graph;   // captured cycle of the composite solve
   amg::GraphCache comp_graphT;  // the same for the composite adjoint solve
+  int bottom_kind = AMG_BOTTOM_EXACT;  // coarsest-depth solver of forward V-cycles
+  int bottom_iters = 5;                // GMRES steps per bottom solve (AMG_BOTTOM_ILU_GMRES)
   double* imex_ws = nullptr;  // stage storage of the IMEX step (allocated on its first call)
   int64_t imex_len = 0;
   std::vector<amg::Level> levels;

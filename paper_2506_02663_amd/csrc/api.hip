@@ -365,7 +365,12 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, cons
   for (int k = 0; k < K; ++k) {
     Depth& D = L.depths[k];
     // boxes that end here: exact solve, written to both buffers of the depth
-    if (!D.groups.empty()) launch_bottom<T>(D, L.d_mat, L.d_idx, f[k], cur[k], R.tr, R.st, oth[k]);
+    if (!D.groups.empty()) {
+      if (R.H->bottom_kind == AMG_BOTTOM_ILU_GMRES && !R.tr)  // the adjoint keeps the exact transposed inverse
+        launch_bottom_gmres<T>(D, L.d_mat, L.d_idx, f[k], cur[k], R.H->bottom_iters, L.d_gws, R.st, oth[k]);
+      else
+        launch_bottom<T>(D, L.d_mat, L.d_idx, f[k], cur[k], R.tr, R.st, oth[k]);
+    }
     if (k + 1 >= K || D.stiles.empty()) break;
     if constexpr (sizeof(T) == 4) {
       if (k == 0 && fs0) {
@@ -456,6 +461,7 @@ void free_level(amg::Level& L) {
                     (void*)D.e64, (void*)D.f64, (void*)D.t64, (void*)D.e32, (void*)D.f32, (void*)D.t32, (void*)D.fs32, (void*)D.xg32})
       if (p) (void)hipFree(p);
   }
+  if (L.d_gws) (void)hipFree(L.d_gws);
   for (void* p : {(void*)L.d_mat, (void*)L.d_idx, (void*)L.r64, (void*)L.fsh, (void*)L.partial, (void*)L.partial2, (void*)L.comp_sum,
                   (void*)L.scal, (void*)L.d_comp_flag, (void*)L.d_comp_cnt, (void*)L.d_delta, (void*)L.d_delta0, (void*)L.d_bsum,
                   (void*)L.d_defect, (void*)L.d_dfd, (void*)L.fdc, (void*)L.d_comp_ncf})
@@ -837,6 +843,17 @@ int amg_set_bottom_cells(amg_hier* H, int cells) {
   return AMG_OK;
 }
 
+int amg_set_bottom_solver(amg_hier* H, int kind, int iters) {
+  if (!H) return AMG_EINVAL;
+  if (H->finalized) return fail(H, AMG_EINVAL, "layout is final");
+  if (kind != AMG_BOTTOM_EXACT && kind != AMG_BOTTOM_ILU_GMRES) return fail(H, AMG_EINVAL, "unknown bottom solver");
+  if (kind == AMG_BOTTOM_ILU_GMRES && (iters < 1 || iters > 16))
+    return fail(H, AMG_EINVAL, "GMRES steps must be 1..16");
+  H->bottom_kind = kind;
+  if (kind == AMG_BOTTOM_ILU_GMRES) H->bottom_iters = iters;
+  return AMG_OK;
+}
+
 int amg_finalize(amg_hier* H) {
   if (!H) return AMG_EINVAL;
   if (H->finalized) return fail(H, AMG_EINVAL, "already final");
@@ -880,6 +897,7 @@ int amg_finalize(amg_hier* H) {
     TRY(upload(H, &L.d_mat, mats_l));
     L.nmat = mats_l.size();
     TRY(upload(H, &L.d_idx, idx));
+    if (L.ngws > 0) TRY(zalloc(H, &L.d_gws, L.ngws));
     size_t maxpart = 1, maxseg = 1;
     for (auto& D : L.depths) {
       TRY(upload(H, &D.d_box, D.boxd));
@@ -1148,10 +1166,18 @@ int amg_bottom(amg_hier* H, int level, int dtype, const void* f, void* e, void* 
   }
   Depth& D = L.depths.back();
   hipStream_t st = stream_of(H, stream);
-  if (dtype == AMG_F64)
-    launch_bottom<double>(D, L.d_mat, L.d_idx, (const double*)f, (double*)e, false, st);
-  else
-    launch_bottom<float>(D, L.d_mat, L.d_idx, (const float*)f, (float*)e, false, st);
+  const bool gm = H->bottom_kind == AMG_BOTTOM_ILU_GMRES;
+  if (dtype == AMG_F64) {
+    if (gm)
+      launch_bottom_gmres<double>(D, L.d_mat, L.d_idx, (const double*)f, (double*)e, H->bottom_iters, L.d_gws, st);
+    else
+      launch_bottom<double>(D, L.d_mat, L.d_idx, (const double*)f, (double*)e, false, st);
+  } else {
+    if (gm)
+      launch_bottom_gmres<float>(D, L.d_mat, L.d_idx, (const float*)f, (float*)e, H->bottom_iters, L.d_gws, st);
+    else
+      launch_bottom<float>(D, L.d_mat, L.d_idx, (const float*)f, (float*)e, false, st);
+  }
   HIPCHK(hipGetLastError());
   return AMG_OK;
 }
@@ -2300,6 +2326,8 @@ int amg_autotune(amg_hier* H, int level, int dtype, int smoother, int nreps, int
     T->c = H->c;
     T->row_align = H->row_align;
     T->bottom_cells = H->bottom_cells;
+    T->bottom_kind = H->bottom_kind;
+    T->bottom_iters = H->bottom_iters;
     T->split_rb = H->split_rb;
     T->march2 = T->march3 = m;
     rc = amg_finalize(T);

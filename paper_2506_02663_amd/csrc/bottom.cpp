@@ -12,6 +12,15 @@
 // bordered inverse maps a consistent right-hand side to the zero-mean
 // solution.  Identical systems (isolated boxes of equal shape) share one
 // inverse.
+//
+// With the paper's bottom solver selected (amg_set_bottom_solver,
+// ILU(0)-preconditioned GMRES(m), Section 6.5), each system (bordered when
+// singular) is also factorised incompletely: ILU(0) on its pattern (the
+// diagonal and the entries above 1e-12 of their row's largest, elimination
+// in the i-k-j order), and the factors are inverted into one dense
+// preconditioning matrix P = (L U)^-1, so that a preconditioning is one
+// matrix-vector product; B = K P, the right-preconditioned operator, is kept
+// beside it.  Unknowns are ordered box by box, x fastest within a box.
 #include <cmath>
 #include <cstdio>
 #include <map>
@@ -29,6 +38,42 @@ const double kFillD[2][4] = {{-77.0 / 12, 43.0 / 12, -17.0 / 12, 3.0 / 12},
                              {-505.0 / 12, 335.0 / 12, -145.0 / 12, 27.0 / 12}};
 const double kFillN[2][4] = {{5.0 / 10, 9.0 / 10, -5.0 / 10, 1.0 / 10},
                              {-75.0 / 10, 145.0 / 10, -75.0 / 10, 15.0 / 10}};
+
+// ILU(0) of the dense row-major N x N matrix K in place (combined factors:
+// unit lower L strictly below the diagonal, U on and above it); false if a
+// pivot vanishes
+bool ilu0(std::vector<double>& K, int N) {
+  std::vector<std::vector<int>> cols(N);  // pattern per row, increasing
+  for (int i = 0; i < N; ++i) {
+    double mx = 0.0;
+    for (int j = 0; j < N; ++j) mx = std::max(mx, std::fabs(K[(size_t)i * N + j]));
+    for (int j = 0; j < N; ++j) {
+      const double v = K[(size_t)i * N + j];
+      if (j == i || std::fabs(v) > 1e-12 * mx)
+        cols[i].push_back(j);
+      else
+        K[(size_t)i * N + j] = 0.0;
+    }
+  }
+  std::vector<char> in(N, 0);
+  for (int i = 1; i < N; ++i) {
+    double* ri = &K[(size_t)i * N];
+    for (int j : cols[i]) in[j] = 1;
+    for (int k : cols[i]) {
+      if (k >= i) break;
+      const double piv = K[(size_t)k * N + k];
+      if (piv == 0.0) return false;
+      ri[k] /= piv;
+      const double* rk = &K[(size_t)k * N];
+      for (int j : cols[k])
+        if (j > k && in[j]) ri[j] -= ri[k] * rk[j];
+    }
+    for (int j : cols[i]) in[j] = 0;
+  }
+  for (int i = 0; i < N; ++i)
+    if (K[(size_t)i * N + i] == 0.0) return false;
+  return true;
+}
 
 bool invert(std::vector<double>& A, int n) {
   // in-place Gauss-Jordan with partial pivoting, row-major n x n
@@ -76,6 +121,7 @@ bool invert(std::vector<double>& A, int n) {
 int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats, std::vector<int64_t>& idx) {
   Level& L = H->levels[l];
   const int dim = H->dim;
+  L.ngws = 0;
   for (size_t k = 0; k < L.depths.size(); ++k) {
     Depth& D = L.depths[k];
     D.groups.clear();
@@ -132,6 +178,7 @@ int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats
       }
       const int m = (int)n + (sing ? 1 : 0);
       std::vector<double> A((size_t)m * m, 0.0);
+      std::vector<double> Ks;  // the system itself (ILU-GMRES bottom)
       auto lidx = [&](int b, int x, int y, int z) -> int64_t {
         const BoxD& X = D.boxd[b];
         return start[b] + x + (int64_t)X.n[0] * (y + (int64_t)X.n[1] * z);
@@ -198,6 +245,7 @@ int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats
           A[(size_t)n * m + i] = 1.0;
         }
       }
+      if (H->bottom_kind == AMG_BOTTOM_ILU_GMRES) Ks = A;
       if (!invert(A, m)) {
         err = "singular bottom system";
         return AMG_EUNSUPPORTED;
@@ -216,6 +264,50 @@ int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats
           mats[base + (size_t)c * n + r] = A[(size_t)r * m + c];
           mats[G.matT + (size_t)c * n + r] = A[(size_t)c * m + r];
         }
+      G.N = m;
+      G.ilub = G.ilup = G.ws = -1;
+      if (H->bottom_kind == AMG_BOTTOM_ILU_GMRES) {
+        if (m > 4096) {  // the GMRES kernel stages one vector of the system in LDS
+          char b2[160];
+          snprintf(b2, sizeof b2, "coarsest system of level %d has %d unknowns (ILU-GMRES bottom: at most 4096)", l, m);
+          err = b2;
+          return AMG_EUNSUPPORTED;
+        }
+        std::vector<double> LU = Ks;
+        if (!ilu0(LU, m)) {
+          err = "ILU(0) of a bottom system met a zero pivot";
+          return AMG_EUNSUPPORTED;
+        }
+        // P = (L U)^-1 by columns (forward then back substitution), then B = K P
+        std::vector<double> P((size_t)m * m);  // column-major
+        std::vector<double> y(m);
+        for (int c = 0; c < m; ++c) {
+          for (int i = 0; i < m; ++i) {
+            double s = i == c ? 1.0 : 0.0;
+            const double* ri = &LU[(size_t)i * m];
+            for (int j = 0; j < i; ++j) s -= ri[j] * y[j];
+            y[i] = s;
+          }
+          for (int i = m - 1; i >= 0; --i) {
+            double s = y[i];
+            const double* ri = &LU[(size_t)i * m];
+            for (int j = i + 1; j < m; ++j) s -= ri[j] * P[(size_t)c * m + j];
+            P[(size_t)c * m + i] = s / ri[i];
+          }
+        }
+        G.ilub = (int64_t)mats.size();
+        G.ilup = G.ilub + (int64_t)m * m;
+        mats.resize(mats.size() + 2 * (size_t)m * m);
+        for (int c = 0; c < m; ++c)
+          for (int r = 0; r < m; ++r) {
+            double s = 0.0;
+            const double* kr = &Ks[(size_t)r * m];
+            for (int j = 0; j < m; ++j)
+              if (kr[j] != 0.0) s += kr[j] * P[(size_t)c * m + j];
+            mats[G.ilub + (size_t)c * m + r] = s;
+            mats[G.ilup + (size_t)c * m + r] = P[(size_t)c * m + r];
+          }
+      }
       group_elems.push_back(elems);
       if (L.isolated) {
         const BoxD& X = D.boxd[sys[0]];
@@ -227,6 +319,10 @@ int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats
     for (size_t g = 0; g < D.groups.size(); ++g) {
       D.groups[g].idx = (int64_t)idx.size();
       idx.insert(idx.end(), group_elems[g].begin(), group_elems[g].end());
+      if (H->bottom_kind == AMG_BOTTOM_ILU_GMRES) {  // m + 1 Krylov vectors per instance
+        D.groups[g].ws = L.ngws;
+        L.ngws += (int64_t)D.groups[g].ninst * (H->bottom_iters + 1) * D.groups[g].N;
+      }
     }
   }
   return AMG_OK;

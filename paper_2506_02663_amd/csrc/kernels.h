@@ -69,6 +69,11 @@ void launch_prolong(int dim, const Depth& F, const Depth& C, const T* ec, T* u, 
 template <typename T>
 void launch_bottom(const Depth& D, const double* mats, const int64_t* idx, const T* f, T* e, bool tr, hipStream_t st,
                    T* e2 = nullptr);
+// ILU(0)-preconditioned GMRES(iters) on every bottom system of D (tables
+// planned with the ILU-GMRES bottom; ws: the level's Krylov workspace)
+template <typename T>
+void launch_bottom_gmres(const Depth& D, const double* mats, const int64_t* idx, const T* f, T* e, int iters,
+                         double* ws, hipStream_t st, T* e2 = nullptr);
 template <typename T>
 void launch_tile_sum(int dim, const Depth& D, const T* a, double* part, hipStream_t st);
 template <typename T>

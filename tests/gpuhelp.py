@@ -9,7 +9,7 @@ def covers_domain(lev):
     return lev.ncells == int(np.prod(lev.shape))
 
 
-def make_hier(lev, op, c, cf_mode=None, bottom_cells=0):
+def make_hier(lev, op, c, cf_mode=None, bottom_cells=0, bottom=None):
     """Hierarchy whose level `index` has the oracle level's boxes.  A level
     that does not cover its grid becomes level 1 of a two-level hierarchy
     (level 0 one box over the half-resolution grid).  bottom_cells: the
@@ -33,6 +33,8 @@ def make_hier(lev, op, c, cf_mode=None, bottom_cells=0):
     H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c)
     if bottom_cells:
         H.set_bottom_cells(bottom_cells)
+    if bottom is not None:  # (kind, GMRES steps)
+        H.set_bottom_solver(*bottom)
     H.finalize()
     return H, index
 

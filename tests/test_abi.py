@@ -65,6 +65,10 @@ def test_host_argument_checks(lib):
     assert L.amg_set_bottom_cells(h, -1) == A.EINVAL
     assert L.amg_set_bottom_cells(h, 1025) == A.EINVAL                      # host inverse O(n^3)
     assert L.amg_set_bottom_cells(h, 512) == A.OK
+    assert L.amg_set_bottom_solver(h, 2, 5) == A.EINVAL                      # no such bottom solver
+    assert L.amg_set_bottom_solver(h, A.BOTTOM_ILU_GMRES, 0) == A.EINVAL      # GMRES steps 1..16
+    assert L.amg_set_bottom_solver(h, A.BOTTOM_ILU_GMRES, 17) == A.EINVAL
+    assert L.amg_set_bottom_solver(h, A.BOTTOM_ILU_GMRES, 5) == A.OK
     assert L.amg_set_tuning(h, 3, 2) == A.EINVAL                            # split switch is 0 or 1
     assert L.amg_set_tuning(h, 4, 0) == A.EINVAL                            # no such key
     assert L.amg_solve(h, 0, 0, None, None, None, None, None, None) == A.EINVAL  # not finalized
