@@ -10,9 +10,20 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 * RDM-2: tagged cells are grouped into disjoint boxes by the clustering of
   Berger and Rigoutsos (1991), then refined by the ratio.
 * RDM-3: for l = lmax-2 .. 0 the boxes of the new level l+2 are coarsened
-  twice, grown by one cell in every direction (clipped to the domain), and
-  their cells joined to the tags of level l; clustering that set and
-  refining gives the new level l+1.
+  twice, grown by `grow` cells in every direction (clipped to the domain),
+  and their cells joined to the tags of level l; clustering that set and
+  refining gives the new level l+1.  The paper grows by one cell, which
+  gives its nesting (one cell of level l+1 between levels l+2 and l).  The
+  five-cell AMRCFI window (oracle/amr.py, never shifted off the coarser
+  level) reaches three cells of level l+1 beyond the footprint of level
+  l+2, so the default growth is the least g with g * ratio >= 3: one cell
+  at ratio 4 (the paper's), two at ratio 2.
+* Blocking (not in the paper): the fills need rows of at least four cells
+  on every level, which a box around one tagged cell would break; so the
+  tags of level l are clustered on the grid coarsened by a blocking factor
+  b (a block is tagged when any of its cells is), and the boxes refined by
+  b (clipped to the grid) and then by the ratio.  The default is the least
+  b with b * ratio >= 4: two at ratio 2, one at ratio 4.
 * Data migration: cells of the new hierarchy that the old one has on the
   same level take the old values; the others take AMRCFI (the conservative
   tensor quartic of oracle/amr.py) from the new coarser level, which holds
@@ -161,21 +172,51 @@ def _refine(boxes, r):
     return [(tuple(a * r for a in lo), tuple((b + 1) * r - 1 for b in hi)) for lo, hi in boxes]
 
 
-def new_boxes(shapes, tags, ratio, efficiency=0.75, min_side=2):
+def default_growth(ratio):
+    """Cells of level l added around the coarsened boxes in RDM-3: the
+    least g with g * ratio >= 3 (see the module docstring)."""
+    return -(-3 // ratio)
+
+
+def default_blocking(ratio):
+    """Blocking factor of the clustering: the least b with b * ratio >= 4."""
+    return -(-4 // ratio)
+
+
+def blocked_cluster(tags, b, efficiency, min_side):
+    """Boxes over the grid of `tags` from the clustering of its tags
+    coarsened by b (a block tagged when any of its cells is), refined by b
+    and clipped to the grid."""
+    shape = tags.shape
+    nb = [-(-n // b) for n in shape]
+    tb = np.zeros(nb, bool)
+    for pos in np.argwhere(tags):
+        tb[tuple(int(p) // b for p in pos)] = True
+    out = []
+    for lo, hi in cluster(tb, efficiency, min_side):
+        out.append((tuple(a * b for a in lo), tuple(min((c + 1) * b, n) - 1 for c, n in zip(hi, shape))))
+    return out
+
+
+def new_boxes(shapes, tags, ratio, efficiency=0.75, min_side=2, grow=None, block=None):
     """New boxes of levels 1..lmax from the tags of levels 0..lmax-1.
-    shapes[l]: grid of level l; tags[l]: dense booleans over it.  Returns a
-    list per new level l = 1..lmax (an empty list: no boxes)."""
+    shapes[l]: grid of level l; tags[l]: dense booleans over it; grow: cells
+    of RDM-3's expansion (None: default_growth(ratio)); block: blocking
+    factor (None: default_blocking(ratio)).  Returns a list per new level
+    l = 1..lmax (an empty list: no boxes)."""
+    g = default_growth(ratio) if grow is None else grow
+    b = default_blocking(ratio) if block is None else block
     lmax = len(tags)
     new = [None] * (lmax + 1)
-    new[lmax] = _refine(cluster(tags[lmax - 1], efficiency, min_side), ratio)
+    new[lmax] = _refine(blocked_cluster(tags[lmax - 1], b, efficiency, min_side), ratio)
     for l in range(lmax - 2, -1, -1):
         t = tags[l].copy()
         for lo, hi in new[l + 2]:
-            clo = [a // ratio // ratio - 1 for a in lo]
-            chi = [b // ratio // ratio + 1 for b in hi]
+            clo = [a // ratio // ratio - g for a in lo]
+            chi = [b // ratio // ratio + g for b in hi]
             sl = tuple(slice(max(a, 0), min(b, n - 1) + 1) for a, b, n in zip(clo, chi, shapes[l]))
             t[sl] = True
-        new[l + 1] = _refine(cluster(t, efficiency, min_side), ratio)
+        new[l + 1] = _refine(blocked_cluster(t, b, efficiency, min_side), ratio)
     return new[1:]
 
 

@@ -8,8 +8,11 @@ Section 5.4, RDM-1..4):
   or without an admissible cut;
 * RDM-3: the new levels cover the refined tags of the level below and are
   properly nested with a margin (each new level-2 box, coarsened twice and
-  grown by one cell, then refined once, lies in new level 1), and form a
-  valid hierarchy for the composite operators;
+  grown by the default growth, then refined once, lies in new level 1), and
+  form a valid hierarchy on which every AMRCFI window stays on the coarser
+  level (the paper's one-cell growth does not at ratio 2: a pinned
+  counter-example); blocked boxes are aligned to blocks of at least four
+  cells, on random regrids at ratios 2 and 4;
 * migration: the copy on common cells is exact, and cell averages of a
   polynomial of degree <= 4 per direction are reproduced on every new cell
   (AMRCFI is exact to that degree);
@@ -90,14 +93,53 @@ def test_new_hierarchy_is_nested_and_covers_the_tags():
         lev2[lo[0]:hi[0] + 1, lo[1]:hi[1] + 1] = True
     assert lev2[np.kron(t1, np.ones((2, 2), bool))].all()
     # proper nesting with a margin: level-2 boxes coarsened twice and grown by
-    # one cell, refined to level 1, lie in level 1
+    # two cells (the default at ratio 2), refined to level 1, lie in level 1
+    assert regrid.default_growth(2) == 2 and regrid.default_growth(4) == 1
     for lo, hi in new[1]:
-        clo = [max(a // 4 - 1, 0) * 2 for a in lo]
-        chi = [min(b // 4 + 1, 15) * 2 + 1 for b in hi]
+        clo = [max(a // 4 - 2, 0) * 2 for a in lo]
+        chi = [min(b // 4 + 2, 15) * 2 + 1 for b in hi]
         assert lev1[clo[0]:chi[0] + 1, clo[1]:chi[1] + 1].all()
-    # a valid hierarchy (nesting, refinement) for the composite operators
-    amr.Hierarchy((16, 16), 1 / 16, [[((0, 0), (15, 15))], new[0], new[1]],
-                  {(d, s): "D" for d in range(2) for s in (0, 1)})
+    # a valid hierarchy (nesting, refinement) on which every AMRCFI and
+    # refluxing window stays on the coarser level (composite_apply raises
+    # otherwise)
+    H = amr.Hierarchy((16, 16), 1 / 16, [[((0, 0), (15, 15))], new[0], new[1]],
+                      {(d, s): "D" for d in range(2) for s in (0, 1)})
+    H.composite_apply([lev.zeros() for lev in H.levels], "poisson", 0.0)
+
+
+def test_one_cell_growth_leaves_windows_off_the_coarser_level_at_ratio_2():
+    # the paper's one-cell expansion nests the levels with one cell of level
+    # 1 between levels 2 and 0, too little for the five-cell window
+    shapes = [(16, 16), (32, 32)]
+    t0 = np.zeros(shapes[0], bool)
+    t1 = np.zeros(shapes[1], bool)
+    t1[14:18, 14:18] = True
+    new1 = regrid.new_boxes(shapes, [t0, t1], 2, grow=1)
+    H = amr.Hierarchy((16, 16), 1 / 16, [[((0, 0), (15, 15))], new1[0], new1[1]],
+                      {(d, s): "D" for d in range(2) for s in (0, 1)})
+    with pytest.raises(ValueError, match="window leaves"):
+        H.composite_apply([lev.zeros() for lev in H.levels], "poisson", 0.0)
+    new2 = regrid.new_boxes(shapes, [t0, t1], 2)
+    H = amr.Hierarchy((16, 16), 1 / 16, [[((0, 0), (15, 15))], new2[0], new2[1]],
+                      {(d, s): "D" for d in range(2) for s in (0, 1)})
+    H.composite_apply([lev.zeros() for lev in H.levels], "poisson", 0.0)
+
+
+@pytest.mark.parametrize("ratio", [2, 4])
+def test_default_growth_keeps_windows_on_random_regrids(ratio):
+    for seed in range(4):
+        rng = np.random.default_rng(seed)
+        shapes = [(16, 16), (16 * ratio, 16 * ratio)]
+        tags = [rng.random(s) < 0.01 for s in shapes]
+        tags[1][tuple(slice(int(a), int(a) + 3 * ratio) for a in rng.integers(2 * ratio, 12 * ratio, 2))] = True
+        new = regrid.new_boxes(shapes, tags, ratio)
+        q = regrid.default_blocking(ratio) * ratio  # boxes aligned to blocks of q cells
+        assert q >= 4
+        for lo, hi in new[0] + new[1]:
+            assert all(a % q == 0 and (c + 1) % q == 0 for a, c in zip(lo, hi))
+        H = amr.Hierarchy((16, 16), 1 / 16, [[((0, 0), (15, 15))]] + [b for b in new if b],
+                          {(d, s): "D" for d in range(2) for s in (0, 1)}, ratio=ratio)
+        H.composite_apply([lev.zeros() for lev in H.levels], "poisson", 0.0)
 
 
 P = [Poly1([0.3, -1.0, 0.5, 2.0, -1.5]), Poly1([1.0, 0.7, -2.0, 0.25, 1.0])]
