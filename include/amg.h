@@ -627,6 +627,65 @@ typedef struct {
 int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, double* const* u, const double* const* g,
                   const amg_solve_opts* opts, amg_imex_stats* stats, void* stream);
 
+/* ---- regridding and data migration (Section 5.4, RDM-1..4) -----------------
+ * Clustering (RDM-2), as read from Berger and Rigoutsos (1991): a box is
+ * shrunk to the bounding box of its tags and accepted when tags / cells
+ * reaches `efficiency`; otherwise it is cut in two along one direction at
+ * index c (parts [lo, c-1] and [c, hi], each at least min_side long along
+ * the cut): at a slice without tags closest to the box's centre; else at
+ * the strongest inflection of the tag signature (the largest jump of its
+ * second difference where that changes sign between neighbouring slices);
+ * else at the middle of the longest side; ties to the position closer to
+ * the centre, then the lower direction, then the lower index; a box without
+ * an admissible cut is accepted; the low part first.  Host-only: no device
+ * call. */
+
+/* Boxes of the tagged cells of the dense host array tags (shape[d] cells
+ * per direction, x fastest, nonzero = tagged): *nboxes receives their
+ * number, lo/hi (max_boxes * dim entries each) their inclusive corners.
+ * Errors: AMG_EINVAL (dim, shape, efficiency outside (0, 1], min_side < 1,
+ * null pointers), AMG_EUNSUPPORTED (more than max_boxes; *nboxes is still
+ * the count). */
+int amg_cluster(int dim, const int32_t* shape, const uint8_t* tags, double efficiency, int min_side, int max_boxes,
+                int32_t* nboxes, int32_t* lo, int32_t* hi);
+
+/* RDM-2..4: the boxes of new levels 1..ntag from the tags of levels
+ * 0..ntag-1 (tags[l]: dense host array over level l's grid, base_cells
+ * times ratio^l, x fastest): new level ntag clusters the tags of level
+ * ntag-1; for l = ntag-2 .. 0 the boxes of new level l+2 coarsened twice and
+ * grown by `grow` cells of level l (clipped to the grid) join the tags of
+ * level l, and their clustering gives new level l+1; boxes are refined by
+ * the ratio.  Every clustering runs on the level's grid coarsened by the
+ * blocking factor `block` (a block is tagged when any of its cells is;
+ * boxes refined by it and clipped).  grow = 0: the least g with g * ratio
+ * >= 3 (every five-cell AMRCFI window of level l+2 then lies on level l+1;
+ * the paper's one cell is that at ratio 4); block = 0: the least b with
+ * b * ratio >= 4 (every box at least four cells wide, as the fills need).
+ * nboxes[l-1]: boxes of new level l (0: none); lo/hi: per new level
+ * max_boxes * dim entries.  Errors: AMG_EINVAL (arguments, ratio not 2 or
+ * 4, grow < 0, block outside 0..64), AMG_EUNSUPPORTED (a level needs more
+ * than max_boxes). */
+int amg_regrid_boxes(int dim, const int32_t* base_cells, int ratio, int ntag, const uint8_t* const* tags,
+                     double efficiency, int min_side, int grow, int block, int max_boxes, int32_t* nboxes, int32_t* lo, int32_t* hi);
+
+/* RDM-1: tags[l] (device, one byte per cell of level l's grid, x fastest)
+ * := 1 where the vorticity of the velocity u[l*dim+d] reaches eps on a cell
+ * of level l, else 0 (also off the level), levels 0..lev_hi.  Vorticity:
+ * 2D G_x u_1 - G_y u_0, 3D the norm of the curl, from the composite gradient
+ * of each component (amg_gradient: the velocity's ghosts and covered cells
+ * are written).  The library keeps dim^2 level buffers per level of
+ * gradient storage, allocated on the first call.  Errors: AMG_EINVAL. */
+int amg_tag_vorticity(amg_hier* h, int lev_hi, double* const* u, double eps, uint8_t* const* tags, void* stream);
+
+/* Data migration onto a new hierarchy (Section 5.4): u_new[l] on every
+ * cell of new level l := u_old[l] where old level l has the cell, else
+ * AMRCFI from new level l-1 (levels in increasing order; level 0 is
+ * copied).  Both hierarchies final, with the same dimension, grid, cell
+ * size and ratio.  Allocates and frees its lookup tables; synchronises the
+ * stream.  Errors: AMG_EINVAL, AMG_EUNSUPPORTED (an interpolation window
+ * off new level l-1). */
+int amg_migrate(amg_hier* h_old, amg_hier* h_new, double* const* u_old, double* const* u_new, void* stream);
+
 /* Changes the Helmholtz coefficient c (> 0) of a finalized hierarchy: the
  * bottom inverses are recomputed on the host and captured graphs dropped.
  * Not on the hot path; AMG_EINVAL if the operator is not Helmholtz. */

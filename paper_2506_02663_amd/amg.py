@@ -135,6 +135,12 @@ def lib():
                                           vp]
         L.amg_imex_step.argtypes = [vp, vp, dbl, dbl, pp, pp, C.POINTER(SolveOpts), C.POINTER(ImexStats), vp]
         L.amg_convection.argtypes = [vp, pp, pp, vp]
+        i32p = C.POINTER(C.c_int32)
+        L.amg_cluster.argtypes = [i32, i32p, C.POINTER(C.c_uint8), dbl, i32, i32, i32p, i32p, i32p]
+        L.amg_regrid_boxes.argtypes = [i32, i32p, i32, i32, C.POINTER(C.c_void_p), dbl, i32, i32, i32, i32, i32p, i32p,
+                                       i32p]
+        L.amg_tag_vorticity.argtypes = [vp, i32, pp, dbl, C.POINTER(C.c_void_p), vp]
+        L.amg_migrate.argtypes = [vp, vp, pp, pp, vp]
         _lib = L
     return _lib
 
@@ -717,3 +723,61 @@ def convection(H, us, outs):
     """outs[d] = (Div<uu>)_d of eq. convOp on one periodic box (see
     amg_convection)."""
     H._check(lib().amg_convection(H.h, H._comp_ptrs(0, [us]), H._comp_ptrs(0, [outs]), _stream()))
+
+
+def _boxes_out(dim, n, lo, hi):
+    return [(tuple(int(v) for v in lo[i * dim:(i + 1) * dim]), tuple(int(v) for v in hi[i * dim:(i + 1) * dim]))
+            for i in range(n)]
+
+
+def cluster(tags, efficiency=0.75, min_side=2, max_boxes=4096):
+    """Boxes of the tagged cells of a dense boolean array indexed [x, y(, z)]
+    (see amg_cluster)."""
+    import numpy as np
+    t = np.ascontiguousarray(np.asarray(tags, dtype=np.uint8).T)  # x fastest
+    dim = t.ndim
+    shape = (C.c_int32 * dim)(*np.asarray(tags).shape)
+    nb = C.c_int32()
+    lo = (C.c_int32 * (max_boxes * dim))()
+    hi = (C.c_int32 * (max_boxes * dim))()
+    rc = lib().amg_cluster(dim, shape, t.ctypes.data_as(C.POINTER(C.c_uint8)), float(efficiency), int(min_side),
+                           max_boxes, C.byref(nb), lo, hi)
+    if rc:
+        raise AmgError(rc, "amg_cluster failed")
+    return _boxes_out(dim, nb.value, lo, hi)
+
+
+def regrid_boxes(base_cells, ratio, tags, efficiency=0.75, min_side=2, grow=0, block=0, max_boxes=4096):
+    """Boxes of new levels 1..len(tags) from dense boolean tag arrays of
+    levels 0..len(tags)-1, indexed [x, y(, z)] (see amg_regrid_boxes; grow,
+    block = 0: the defaults)."""
+    import numpy as np
+    dim = len(base_cells)
+    arrs = [np.ascontiguousarray(np.asarray(t, dtype=np.uint8).T) for t in tags]
+    ptrs = (C.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+    nt = len(arrs)
+    nb = (C.c_int32 * nt)()
+    lo = (C.c_int32 * (nt * max_boxes * dim))()
+    hi = (C.c_int32 * (nt * max_boxes * dim))()
+    rc = lib().amg_regrid_boxes(dim, (C.c_int32 * dim)(*base_cells), int(ratio), nt, ptrs, float(efficiency),
+                                int(min_side), int(grow), int(block), max_boxes, nb, lo, hi)
+    if rc:
+        raise AmgError(rc, "amg_regrid_boxes failed")
+    out = []
+    for l in range(nt):
+        off = l * max_boxes * dim
+        out.append(_boxes_out(dim, nb[l], lo[off:off + max_boxes * dim], hi[off:off + max_boxes * dim]))
+    return out
+
+
+def tag_vorticity(H, us, eps, tags):
+    """tags[l] (uint8 device tensors, one byte per cell of level l's grid, x
+    fastest) from the velocity us[l][d] (see amg_tag_vorticity)."""
+    n = len(tags)
+    ptrs = (C.c_void_p * n)(*[t.data_ptr() for t in tags])
+    H._check(lib().amg_tag_vorticity(H.h, n - 1, H._comp_ptrs(0, us), float(eps), ptrs, _stream()))
+
+
+def migrate(H_old, H_new, u_old, u_new):
+    """u_new[l] on the new hierarchy from u_old[l] (see amg_migrate)."""
+    H_new._check(lib().amg_migrate(H_old.h, H_new.h, H_old._lev_ptrs(0, u_old), H_new._lev_ptrs(0, u_new), _stream()))

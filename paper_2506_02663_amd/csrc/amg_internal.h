@@ -351,6 +351,8 @@ struct amg_hier {
   int bottom_kind = AMG_BOTTOM_EXACT;  // coarsest-depth solver of forward V-cycles
   int bottom_iters = 5;                // GMRES steps per bottom solve (AMG_BOTTOM_ILU_GMRES)
   double* imex_ws = nullptr;  // stage storage of the IMEX step (allocated on its first call)
+  double* regrid_ws = nullptr;  // gradients of the vorticity tagging (allocated on its first call)
+  int64_t regrid_len = 0;
   int64_t imex_len = 0;
   std::vector<amg::Level> levels;
   std::string err;
@@ -363,6 +365,8 @@ int plan_level(amg_hier* H, int l, std::string& err);
 int build_composite(amg_hier* H, int l, std::string& err);
 // interface-condition table of a level solved with face data (composite.cpp)
 int build_cic(amg_hier* H, int l, std::string& err);
+// AMRCFI weights [(shift + 2) * r + child][window cell] (composite.cpp)
+void cfi_weight_table(double W[20][5], int r);
 // host assembly of the coarsest operator and its inverse (bottom.cpp)
 int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats, std::vector<int64_t>& idx);
 }  // namespace amg

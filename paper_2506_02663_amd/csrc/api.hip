@@ -755,6 +755,7 @@ int amg_destroy(amg_hier* H) {
   for (auto& e : H->timer.pool) (void)hipEventDestroy(e);
   for (auto& L : H->levels) free_level(L);
   if (H->imex_ws) (void)hipFree(H->imex_ws);
+  if (H->regrid_ws) (void)hipFree(H->regrid_ws);
   if (H->own) (void)hipStreamDestroy(H->own);
   delete H;
   return AMG_OK;

@@ -99,6 +99,8 @@ int floordiv(int v, int r) { return v >= 0 ? v / r : -((-v + r - 1) / r); }
 
 }  // namespace
 
+void cfi_weight_table(double W[20][5], int r) { cfi_weights(W, r); }
+
 int build_composite(amg_hier* H, int l, std::string& err) {
   Level& F = H->levels[l];
   Level& C = H->levels[l - 1];

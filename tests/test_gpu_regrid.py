@@ -1,0 +1,204 @@
+"""Regridding on the GPU against the oracle (Section 5.4):
+
+* RDM-1 tags (amg_tag_vorticity) equal the oracle's bit for bit, with the
+  threshold placed in a wide gap of the oracle's vorticity values so that
+  rounding-order differences of the gradient (~1e-12 relative) cannot flip
+  a tag; two- and three-level hierarchies, ratios 2 and 4, 2D and 3D;
+* data migration (amg_migrate): copied cells equal the old values exactly,
+  interpolated cells the oracle's AMRCFI within 1e-13 of the data's scale;
+  new hierarchies with fewer, as many and more levels than the old one;
+  polynomial data of degree <= 4 per direction reproduced exactly;
+* the whole regrid (GPU tags -> amg_regrid_boxes -> new hierarchy ->
+  migration) equals the oracle's chain, boxes bit-exact."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import amr, regrid  # noqa: E402
+from oracle.level import PAD  # noqa: E402
+from paper_2506_02663_amd import amg as A  # noqa: E402
+from tests.gpuhelp import from_dev, to_dev  # noqa: E402
+from tests.polyfix import Poly1  # noqa: E402
+
+
+def both(base, h0, boxes, ratio):
+    dim = len(base)
+    bc = {(d, s): "D" for d in range(dim) for s in (0, 1)}
+    O = amr.Hierarchy(base, h0, boxes, bc, ratio=ratio)
+    H = A.Hierarchy(dim, base, h0, len(boxes), ratio=ratio)
+    for l, bl in enumerate(boxes):
+        H.set_level_boxes(l, bl)
+        if l:
+            H.set_cf_mode(l, A.CF_INTERP)
+    for d in range(dim):
+        for s in (0, 1):
+            H.set_physical_bc(d, s, A.DIRICHLET)
+    H.set_operator(A.POISSON, 0.0)
+    H.finalize()
+    return O, H
+
+
+FULL2 = [((0, 0), (15, 15))]
+LAYOUTS = {
+    "2d_two_level": ((16, 16), 1 / 16, [FULL2, [((8, 8), (15, 23)), ((16, 8), (23, 15))]], 2),
+    "2d_three_level": ((16, 16), 1 / 16, [FULL2, [((4, 4), (27, 27))], [((16, 16), (31, 31))]], 2),
+    "2d_two_level_r4": ((16, 16), 1 / 16, [FULL2, [((16, 16), (39, 47)), ((40, 16), (47, 31))]], 4),
+    "3d_two_level": ((8, 8, 8), 1 / 8, [[((0, 0, 0), (7, 7, 7))], [((4, 4, 4), (11, 13, 11))]], 2),
+}
+
+
+def random_velocity(O, seed):
+    rng = np.random.default_rng(seed)
+    return [[np.where(lev.mask, rng.normal(size=lev.pshape), 0.0) for lev in O.levels] for _ in range(O.dim)]
+
+
+def grid_tags(t, shape):
+    """Device byte array (x fastest) -> boolean array indexed [x, y(, z)]."""
+    return t.cpu().numpy().reshape(tuple(reversed(shape))).T.astype(bool)
+
+
+def gap_threshold(W, masks):
+    v = np.sort(np.concatenate([np.abs(w[m]) for w, m in zip(W, masks)]))
+    lo, hi = int(0.4 * len(v)), int(0.8 * len(v))
+    i = lo + int(np.argmax(np.diff(v[lo:hi + 1])))
+    assert v[i + 1] - v[i] > 1e-8 * v[-1]
+    return 0.5 * (v[i] + v[i + 1])
+
+
+@pytest.mark.parametrize("name", list(LAYOUTS))
+def test_vorticity_tags_match_the_oracle(name):
+    base, h0, boxes, ratio = LAYOUTS[name]
+    O, H = both(base, h0, boxes, ratio)
+    U = random_velocity(O, 3)
+    W = regrid.vorticity(O, U)
+    eps = gap_threshold(W, [lev.mask for lev in O.levels])
+    want = regrid.tag_vorticity(O, U, eps)
+    us = [[to_dev(H, l, 0, U[d][l]) for d in range(O.dim)] for l in range(O.nlev)]
+    tags = [torch.full((int(np.prod(lev.shape)),), 7, dtype=torch.uint8, device="cuda") for lev in O.levels]
+    A.tag_vorticity(H, us, eps, tags)
+    torch.cuda.synchronize()
+    for l, lev in enumerate(O.levels):
+        got = grid_tags(tags[l], lev.shape)
+        assert np.array_equal(got, want[l]), (name, l, int((got != want[l]).sum()))
+        assert want[l].any() and not want[l].all()
+
+
+MIGRATIONS = {
+    # (base, h0, ratio, old boxes, new boxes)
+    "2d_shift": ((16, 16), 1 / 16, 2, [FULL2, [((8, 8), (19, 19))]], [FULL2, [((12, 4), (25, 17))]]),
+    "2d_shift_r4": ((16, 16), 1 / 16, 4, [FULL2, [((16, 16), (39, 39))]], [FULL2, [((24, 8), (51, 31))]]),
+    "2d_three_level": ((16, 16), 1 / 16, 2, [FULL2, [((4, 4), (27, 27))], [((16, 16), (31, 31))]],
+                       [FULL2, [((6, 8), (29, 25))], [((20, 22), (39, 37))]]),
+    "2d_more_levels": ((16, 16), 1 / 16, 2, [FULL2, [((8, 8), (19, 19))]],
+                       [FULL2, [((4, 4), (25, 25))], [((16, 16), (35, 35))]]),
+    "2d_fewer_levels": ((16, 16), 1 / 16, 2, [FULL2, [((4, 4), (27, 27))], [((16, 16), (31, 31))]],
+                        [FULL2, [((12, 6), (31, 21))]]),
+    "3d_shift": ((8, 8, 8), 1 / 8, 2, [[((0, 0, 0), (7, 7, 7))], [((4, 4, 4), (11, 11, 11))]],
+                 [[((0, 0, 0), (7, 7, 7))], [((6, 4, 2), (13, 11, 9))]]),
+}
+
+
+def run_migration(name, U_old_fn):
+    base, h0, ratio, ob, nb = MIGRATIONS[name]
+    Oo, Ho = both(base, h0, ob, ratio)
+    On, Hn = both(base, h0, nb, ratio)
+    U_old = U_old_fn(Oo)
+    want = regrid.migrate(Oo, On, U_old)
+    u_old = [to_dev(Ho, l, 0, U_old[l]) for l in range(Oo.nlev)]
+    u_new = [to_dev(Hn, l, 0, lev.zeros()) for l, lev in enumerate(On.levels)]
+    A.migrate(Ho, Hn, u_old, u_new)
+    got = [from_dev(Hn, l, 0, u_new[l], On.levels[l]) for l in range(On.nlev)]
+    return Oo, On, U_old, want, got
+
+
+@pytest.mark.parametrize("name", list(MIGRATIONS))
+def test_migration_matches_the_oracle(name):
+    def rand(Oo):
+        rng = np.random.default_rng(11)
+        return [np.where(lev.mask, rng.normal(size=lev.pshape), 0.0) for lev in Oo.levels]
+
+    Oo, On, U_old, want, got = run_migration(name, rand)
+    scale = max(np.abs(u).max() for u in U_old)
+    for l, lev in enumerate(On.levels):
+        m = lev.mask
+        common = m & Oo.levels[l].mask if l < Oo.nlev else np.zeros_like(m)
+        assert np.array_equal(got[l][common], want[l][common]), (name, l)
+        assert np.abs(got[l] - want[l])[m].max() <= 1e-13 * scale, (name, l)
+        if l:
+            assert (m & ~common).any()  # the case interpolates somewhere
+
+
+P = [Poly1([0.3, -1.0, 0.5, 2.0, -1.5]), Poly1([1.0, 0.7, -2.0, 0.25, 1.0]), Poly1([-0.5, 0.2, 1.0, -0.75, 0.5])]
+
+
+def poly_avgs(lev):
+    a = lev.zeros()
+    v = P[0].avg(0.0, lev.h, lev.shape[0])
+    for d in range(1, lev.dim):
+        v = np.multiply.outer(v, P[d].avg(0.0, lev.h, lev.shape[d]))
+    a[lev.inner] = v
+    return np.where(lev.mask, a, 0.0)
+
+
+@pytest.mark.parametrize("name", ["2d_shift", "2d_shift_r4", "2d_more_levels", "3d_shift"])
+def test_migration_reproduces_quartic_averages(name):
+    Oo, On, U_old, want, got = run_migration(name, lambda Oo: [poly_avgs(lev) for lev in Oo.levels])
+    for l, lev in enumerate(On.levels):
+        exact = poly_avgs(lev)
+        assert np.abs(got[l] - exact)[lev.mask].max() < 1e-12 * np.abs(exact).max(), (name, l)
+
+
+def test_migration_rejects_mismatched_hierarchies():
+    Oa, Ha = both((16, 16), 1 / 16, [FULL2, [((8, 8), (19, 19))]], 2)
+    Ob, Hb = both((16, 16), 1 / 16, [FULL2, [((16, 16), (39, 39))]], 4)
+    ua = [to_dev(Ha, l, 0, lev.zeros()) for l, lev in enumerate(Oa.levels)]
+    ub = [to_dev(Hb, l, 0, lev.zeros()) for l, lev in enumerate(Ob.levels)]
+    with pytest.raises(A.AmgError, match="ratio"):
+        A.migrate(Ha, Hb, ua, ub)
+
+
+@pytest.mark.parametrize("ratio", [2, 4])
+def test_whole_regrid_matches_the_oracle(ratio):
+    base, h0 = (16, 16), 1 / 16
+    n1 = 16 * ratio
+    old_boxes = [FULL2, [((3 * n1 // 16, 3 * n1 // 16), (11 * n1 // 16 - 1, 11 * n1 // 16 - 1))]]
+    Oo, Ho = both(base, h0, old_boxes, ratio)
+    # a vortex-like velocity: u = (-dpsi/dy, dpsi/dx) of a Gaussian stream
+    # function, cell values (the tags only need a smooth field)
+    U = [[], []]
+    for lev in Oo.levels:
+        x = (np.arange(lev.pshape[0]) - PAD + 0.5) * lev.h
+        y = (np.arange(lev.pshape[1]) - PAD + 0.5) * lev.h
+        X, Y = np.meshgrid(x, y, indexing="ij")
+        g = np.exp(-((X - 0.55) ** 2 + (Y - 0.45) ** 2) / 0.01)
+        U[0].append(np.where(lev.mask, 2 * (Y - 0.45) / 0.01 * g, 0.0))
+        U[1].append(np.where(lev.mask, -2 * (X - 0.55) / 0.01 * g, 0.0))
+    W = regrid.vorticity(Oo, U)
+    eps = gap_threshold(W, [lev.mask for lev in Oo.levels])
+    tags_o = regrid.tag_vorticity(Oo, U, eps)
+    new_o = regrid.new_boxes([lev.shape for lev in Oo.levels], tags_o, ratio)
+
+    us = [[to_dev(Ho, l, 0, U[d][l]) for d in range(2)] for l in range(Oo.nlev)]
+    tags = [torch.zeros(int(np.prod(lev.shape)), dtype=torch.uint8, device="cuda") for lev in Oo.levels]
+    A.tag_vorticity(Ho, us, eps, tags)
+    tags_g = [grid_tags(t, lev.shape) for t, lev in zip(tags, Oo.levels)]
+    for a, b in zip(tags_g, tags_o):
+        assert np.array_equal(a, b)
+    new_g = A.regrid_boxes(base, ratio, tags_g)
+    assert new_g == new_o
+    boxes = [FULL2] + [bl for bl in new_g if bl]
+    On, Hn = both(base, h0, boxes, ratio)
+    want = regrid.migrate(Oo, On, U[0])
+    u_new = [to_dev(Hn, l, 0, lev.zeros()) for l, lev in enumerate(On.levels)]
+    # fresh copies: the gradient of the tagging wrote the velocity's ghosts
+    # and covered cells
+    A.migrate(Ho, Hn, [to_dev(Ho, l, 0, U[0][l]) for l in range(Oo.nlev)], u_new)
+    scale = max(np.abs(u).max() for u in U[0])
+    for l, lev in enumerate(On.levels):
+        got = from_dev(Hn, l, 0, u_new[l], lev)
+        assert np.abs(got - want[l])[lev.mask].max() <= 1e-13 * scale, l
