@@ -12,7 +12,9 @@ noise (the Poisson one made mean-free).  DOF per step = 2 * 256^3.
 
 Prints one JSON line.  --workload c1 runs the 2D 128^2 workload instead;
 --workload c4 the batch of 1024 independent 2D boxes; --workload imex one
-IMEX time step of the four-way vortex flow on a periodic 1024^2 level.
+IMEX time step of the four-way vortex flow on a periodic 1024^2 level;
+--workload regrid one regridding of that flow's two-level hierarchy into
+three levels, with its data migration.
 """
 import argparse
 import json
@@ -32,7 +34,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "imex"])
+    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "imex", "regrid"])
     p.add_argument("--bottom", default="exact", choices=["exact", "ilu_gmres"],
                    help="single-level workloads: coarsest-depth solver (the paper's ILU(0)-GMRES, or the exact "
                         "dense inverse)")
@@ -242,6 +244,8 @@ def main():
         return bench_amr(args)
     elif args.workload == "imex":
         return bench_imex(args)
+    elif args.workload == "regrid":
+        return bench_regrid(args)
     else:
         return bench_batched(args)
 
@@ -648,6 +652,120 @@ def bench_imex(args):
         "config": {"workload": f"four-way vortex merging, periodic {n}^2, Re 1000, Cr 0.5, one IMEX step",
                    "dt": dt, "solves": stats.get("solves"), "cycles": stats.get("cycles"),
                    "max_cycles": stats.get("max_cycles"), "precision": args.precision, "smoother": args.smoother},
+    }
+    if base is not None:
+        out["cpu_baseline"] = base
+    print(json.dumps(out), flush=True)
+
+
+def _regrid_hier(A, n, h, boxes):
+    H = A.Hierarchy(2, (n, n), h, len(boxes))
+    for l, bl in enumerate(boxes):
+        H.set_level_boxes(l, bl)
+        if l:
+            H.set_cf_mode(l, A.CF_INTERP)
+    for d in range(2):
+        for s in (0, 1):
+            H.set_physical_bc(d, s, A.PERIODIC)
+    H.set_operator(A.POISSON, 0.0)
+    H.finalize()
+    return H
+
+
+def bench_regrid(args):
+    """Regridding and data migration (Section 5.4, RDM-1..4) of the four-way
+    vortex flow (Section 7.3) on the periodic unit square: level 0 = n^2
+    cells (n = 512 by default), level 1 from a first regrid of the initial
+    velocity (vorticity threshold 20, ratio 2).  One step regrids that
+    two-level hierarchy into three levels: vorticity tags of levels 0 and 1
+    on the GPU, their copy to the host, the clustering and RDM-3 boxes, the
+    new hierarchy's planning and finalize, and the migration of both
+    velocity components.  value = cells of the new hierarchy per second."""
+    import numpy as np
+    import torch
+
+    from paper_2506_02663_amd import amg as A
+    from paper_2506_02663_amd import workloads as W
+    n, eps, r = args.n or 512, 20.0, 2
+    h = 1.0 / n
+    base = None
+    if not args.no_cpu_baseline:
+        from oracle import amr, regrid
+        from oracle.level import PAD
+        m = 128
+        bc = {(d, s): "P" for d in range(2) for s in (0, 1)}
+        O0 = amr.Hierarchy((m, m), 1.0 / m, [[((0, 0), (m - 1, m - 1))]], bc)
+        us_, vs_ = W.four_vortex_velocity(m)
+        U = [[O0.levels[0].zeros()], [O0.levels[0].zeros()]]
+        U[0][0][PAD:-PAD, PAD:-PAD], U[1][0][PAD:-PAD, PAD:-PAD] = us_, vs_
+        nb = regrid.new_boxes([(m, m)], regrid.tag_vorticity(O0, U, eps), r)
+        O1 = amr.Hierarchy((m, m), 1.0 / m, [[((0, 0), (m - 1, m - 1))], nb[0]], bc)
+        U1 = [regrid.migrate(O0, O1, U[d]) for d in range(2)]
+        t0 = time.perf_counter()
+        tags = regrid.tag_vorticity(O1, U1, eps)
+        nb = regrid.new_boxes([lev.shape for lev in O1.levels], tags, r)
+        O2 = amr.Hierarchy((m, m), 1.0 / m, [[((0, 0), (m - 1, m - 1))]] + [b for b in nb if b], bc)
+        U2 = [regrid.migrate(O1, O2, U1[d]) for d in range(2)]
+        el = time.perf_counter() - t0
+        cells = sum(lev.ncells for lev in O2.levels)
+        base = {"value": cells / el, "unit": "new-hierarchy cells/s", "cores": 1, "kind": "oracle",
+                "sample": f"the same regrid of the flow at level-0 size 128^2 ({cells} new cells), {el:.2f} s"}
+        del U2
+    u, v = W.four_vortex_velocity(n)
+    full = [((0, 0), (n - 1, n - 1))]
+    H0 = _regrid_hier(A, n, h, [full])
+    u0 = [torch.tensor(H0.pack(0, 0, lambda i, b, a=a: a), device="cuda") for a in (u, v)]
+
+    def tags_of(H, us):
+        nl = len(us)
+        t = [torch.zeros((n * r ** l) ** 2, dtype=torch.uint8, device="cuda") for l in range(nl)]
+        A.tag_vorticity(H, [list(x) for x in us], eps, t)
+        return [x.cpu().numpy().reshape((n * r ** l,) * 2).T.astype(bool) for l, x in enumerate(t)]
+
+    def regrid_once(H, us):
+        """-> (new hierarchy, its boxes per level, migrated velocity [l][d],
+        phase times)"""
+        t0 = time.perf_counter()
+        tags = tags_of(H, us)
+        t1 = time.perf_counter()
+        boxes = [full] + [b for b in A.regrid_boxes((n, n), r, tags) if b]
+        t2 = time.perf_counter()
+        Hn = _regrid_hier(A, n, h, boxes)
+        t3 = time.perf_counter()
+        new = [[torch.zeros(Hn.depth_size(l, 0)[0], dtype=torch.float64, device="cuda") for _ in range(2)]
+               for l in range(len(boxes))]
+        for d in range(2):
+            A.migrate(H, Hn, [us[l][d] for l in range(len(us))], [new[l][d] for l in range(len(boxes))])
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        ph = dict(tags_ms=(t1 - t0) * 1e3, boxes_ms=(t2 - t1) * 1e3, finalize_ms=(t3 - t2) * 1e3,
+                  migrate_ms=(t4 - t3) * 1e3)
+        return Hn, boxes, new, ph
+
+    H1, boxes1, us1, _ = regrid_once(H0, [u0])
+    phases, Hs = [], []
+    for i in range(args.warmup + args.steps):
+        if i == args.warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        Hn, boxes, new, ph = regrid_once(H1, us1)
+        if i >= args.warmup:
+            phases.append(ph)
+        Hs.append(Hn)
+        if len(Hs) > 1:
+            Hs.pop(0).close()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    cells = sum(int(np.prod([hi[d] - lo[d] + 1 for d in range(2)])) for bl in boxes for lo, hi in bl)
+    avg = {k: round(sum(p[k] for p in phases) / len(phases), 3) for k in phases[0]}
+    out = {
+        "metric": "regrid throughput: cells of the new hierarchy per second (Section 5.4, RDM-1..4 + migration)",
+        "value": cells * args.steps / el, "unit": "new-hierarchy cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"four-way vortex flow, periodic {n}^2 base, ratio {r}, vorticity >= {eps}: "
+                               f"{len(boxes1)} levels -> {len(boxes)} levels",
+                   "new_cells": cells, "boxes_per_level": [len(bl) for bl in boxes], "phases_ms": avg},
     }
     if base is not None:
         out["cpu_baseline"] = base

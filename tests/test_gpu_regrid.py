@@ -3,7 +3,8 @@
 * RDM-1 tags (amg_tag_vorticity) equal the oracle's bit for bit, with the
   threshold placed in a wide gap of the oracle's vorticity values so that
   rounding-order differences of the gradient (~1e-12 relative) cannot flip
-  a tag; two- and three-level hierarchies, ratios 2 and 4, 2D and 3D;
+  a tag; two- and three-level hierarchies, ratios 2 and 4, 2D and 3D,
+  Dirichlet and periodic boundaries;
 * data migration (amg_migrate): copied cells equal the old values exactly,
   interpolated cells the oracle's AMRCFI within 1e-13 of the data's scale;
   new hierarchies with fewer, as many and more levels than the old one;
@@ -26,9 +27,9 @@ from tests.gpuhelp import from_dev, to_dev  # noqa: E402
 from tests.polyfix import Poly1  # noqa: E402
 
 
-def both(base, h0, boxes, ratio):
+def both(base, h0, boxes, ratio, kind="D"):
     dim = len(base)
-    bc = {(d, s): "D" for d in range(dim) for s in (0, 1)}
+    bc = {(d, s): kind for d in range(dim) for s in (0, 1)}
     O = amr.Hierarchy(base, h0, boxes, bc, ratio=ratio)
     H = A.Hierarchy(dim, base, h0, len(boxes), ratio=ratio)
     for l, bl in enumerate(boxes):
@@ -37,7 +38,7 @@ def both(base, h0, boxes, ratio):
             H.set_cf_mode(l, A.CF_INTERP)
     for d in range(dim):
         for s in (0, 1):
-            H.set_physical_bc(d, s, A.DIRICHLET)
+            H.set_physical_bc(d, s, A.DIRICHLET if kind == "D" else A.PERIODIC)
     H.set_operator(A.POISSON, 0.0)
     H.finalize()
     return O, H
@@ -49,6 +50,7 @@ LAYOUTS = {
     "2d_three_level": ((16, 16), 1 / 16, [FULL2, [((4, 4), (27, 27))], [((16, 16), (31, 31))]], 2),
     "2d_two_level_r4": ((16, 16), 1 / 16, [FULL2, [((16, 16), (39, 47)), ((40, 16), (47, 31))]], 4),
     "3d_two_level": ((8, 8, 8), 1 / 8, [[((0, 0, 0), (7, 7, 7))], [((4, 4, 4), (11, 13, 11))]], 2),
+    "2d_periodic_two_level": ((16, 16), 1 / 16, [FULL2, [((8, 8), (19, 23))]], 2, "P"),
 }
 
 
@@ -72,8 +74,8 @@ def gap_threshold(W, masks):
 
 @pytest.mark.parametrize("name", list(LAYOUTS))
 def test_vorticity_tags_match_the_oracle(name):
-    base, h0, boxes, ratio = LAYOUTS[name]
-    O, H = both(base, h0, boxes, ratio)
+    base, h0, boxes, ratio, *kind = LAYOUTS[name]
+    O, H = both(base, h0, boxes, ratio, *kind)
     U = random_velocity(O, 3)
     W = regrid.vorticity(O, U)
     eps = gap_threshold(W, [lev.mask for lev in O.levels])
