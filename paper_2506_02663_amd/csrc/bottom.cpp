@@ -21,9 +21,15 @@
 // preconditioning matrix P = (L U)^-1, so that a preconditioning is one
 // matrix-vector product; B = K P, the right-preconditioned operator, is kept
 // beside it.  Unknowns are ordered box by box, x fastest within a box.
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
+#include <functional>
 #include <map>
+#include <string>
+#include <thread>
 #include <tuple>
 
 #include "amg_internal.h"
@@ -75,45 +81,136 @@ bool ilu0(std::vector<double>& K, int N) {
   return true;
 }
 
-bool invert(std::vector<double>& A, int n) {
-  // in-place Gauss-Jordan with partial pivoting, row-major n x n
-  std::vector<int> piv(n);
-  std::vector<double> inv((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
-  for (int col = 0; col < n; ++col) {
-    int p = col;
-    double best = std::fabs(A[(size_t)col * n + col]);
-    for (int r = col + 1; r < n; ++r) {
-      double v = std::fabs(A[(size_t)r * n + col]);
-      if (v > best) best = v, p = r;
-    }
-    if (best == 0.0) return false;
-    if (p != col)
-      for (int j = 0; j < n; ++j) {
-        std::swap(A[(size_t)p * n + j], A[(size_t)col * n + j]);
-        std::swap(inv[(size_t)p * n + j], inv[(size_t)col * n + j]);
-      }
-    double d = 1.0 / A[(size_t)col * n + col];
-    for (int j = 0; j < n; ++j) {
-      A[(size_t)col * n + j] *= d;
-      inv[(size_t)col * n + j] *= d;
-    }
-    for (int r = 0; r < n; ++r) {
-      if (r == col) continue;
-      double f = A[(size_t)r * n + col];
-      if (f == 0.0) continue;
-      double* ar = &A[(size_t)r * n];
-      const double* ac = &A[(size_t)col * n];
-      double* ir = &inv[(size_t)r * n];
-      const double* ic = &inv[(size_t)col * n];
-      for (int j = 0; j < n; ++j) {
-        ar[j] -= f * ac[j];
-        ir[j] -= f * ic[j];
-      }
+// barrier for the threads of one inversion (spinning; the waits are short)
+struct SpinBarrier {
+  explicit SpinBarrier(int n) : n_(n) {}
+  void wait() {
+    const int gen = gen_.load(std::memory_order_acquire);
+    if (count_.fetch_add(1, std::memory_order_acq_rel) == n_ - 1) {
+      count_.store(0, std::memory_order_relaxed);
+      gen_.fetch_add(1, std::memory_order_acq_rel);
+    } else {
+      int spins = 0;
+      while (gen_.load(std::memory_order_acquire) == gen)
+        if (++spins > 1024) std::this_thread::yield();
     }
   }
+  int n_;
+  std::atomic<int> count_{0}, gen_{0};
+};
+
+// In-place Gauss-Jordan with partial pivoting of the row-major n x n matrix
+// A into its inverse; false if A is singular.  `threads` > 1 splits each
+// column's row updates over that many threads (the pivot step runs on the
+// first); every row's arithmetic is the same in any split.  Columns of A up
+// to the current one are never read again, so only those right of it are
+// updated.
+bool invert(std::vector<double>& A, int n, int threads = 1) {
+  std::vector<double> inv((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  const int T = std::max(1, std::min(threads, n / 64));
+  SpinBarrier bar(T);
+  std::atomic<bool> singular{false};
+  auto work = [&](int tid) {
+    for (int col = 0; col < n; ++col) {
+      if (tid == 0) {
+        int p = col;
+        double best = std::fabs(A[(size_t)col * n + col]);
+        for (int r = col + 1; r < n; ++r) {
+          const double v = std::fabs(A[(size_t)r * n + col]);
+          if (v > best) best = v, p = r;
+        }
+        if (best == 0.0) {
+          singular.store(true);
+        } else {
+          if (p != col)
+            for (int j = 0; j < n; ++j) {
+              std::swap(A[(size_t)p * n + j], A[(size_t)col * n + j]);
+              std::swap(inv[(size_t)p * n + j], inv[(size_t)col * n + j]);
+            }
+          const double d = 1.0 / A[(size_t)col * n + col];
+          for (int j = col + 1; j < n; ++j) A[(size_t)col * n + j] *= d;
+          for (int j = 0; j < n; ++j) inv[(size_t)col * n + j] *= d;
+        }
+      }
+      if (T > 1) bar.wait();
+      if (singular.load()) return;
+      const double* ac = &A[(size_t)col * n];
+      const double* ic = &inv[(size_t)col * n];
+      for (int r = tid; r < n; r += T) {
+        if (r == col) continue;
+        const double f = A[(size_t)r * n + col];
+        if (f == 0.0) continue;
+        double* ar = &A[(size_t)r * n];
+        double* ir = &inv[(size_t)r * n];
+        for (int j = col + 1; j < n; ++j) ar[j] -= f * ac[j];
+        for (int j = 0; j < n; ++j) ir[j] -= f * ic[j];
+      }
+      if (T > 1) bar.wait();
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < T; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto& t : th) t.join();
+  if (singular.load()) return false;
   A.swap(inv);
   return true;
+}
+
+constexpr size_t kBatch = 8;                      // systems factorised at once
+constexpr size_t kBatchBytes = (size_t)1 << 30;  // their matrices' bytes at once
+
+// one bottom system: the assembled (bordered) matrix, replaced by its
+// inverse; with the ILU-GMRES bottom also B = K P and P = (L U)^-1, both
+// column-major
+struct Job {
+  int group = 0, m = 0, n = 0;
+  std::vector<double> A, K, B, P;
+  bool ok = true;
+  std::string err;
+};
+
+void factorise(Job& J, int kind, int threads) {
+  const int m = J.m;
+  if (!invert(J.A, m, threads)) {
+    J.ok = false;
+    J.err = "singular bottom system";
+    return;
+  }
+  if (kind != AMG_BOTTOM_ILU_GMRES) return;
+  std::vector<double> LU = J.K;
+  if (!ilu0(LU, m)) {
+    J.ok = false;
+    J.err = "ILU(0) of a bottom system met a zero pivot";
+    return;
+  }
+  // P = (L U)^-1 by columns (forward then back substitution), then B = K P
+  J.P.assign((size_t)m * m, 0.0);
+  std::vector<double> y(m);
+  for (int c = 0; c < m; ++c) {
+    for (int i = 0; i < m; ++i) {
+      double s = i == c ? 1.0 : 0.0;
+      const double* ri = &LU[(size_t)i * m];
+      for (int j = 0; j < i; ++j) s -= ri[j] * y[j];
+      y[i] = s;
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      double s = y[i];
+      const double* ri = &LU[(size_t)i * m];
+      for (int j = i + 1; j < m; ++j) s -= ri[j] * J.P[(size_t)c * m + j];
+      J.P[(size_t)c * m + i] = s / ri[i];
+    }
+  }
+  J.B.assign((size_t)m * m, 0.0);
+  for (int c = 0; c < m; ++c)
+    for (int r = 0; r < m; ++r) {
+      double s = 0.0;
+      const double* kr = &J.K[(size_t)r * m];
+      for (int j = 0; j < m; ++j)
+        if (kr[j] != 0.0) s += kr[j] * J.P[(size_t)c * m + j];
+      J.B[(size_t)c * m + r] = s;
+    }
 }
 
 }  // namespace
@@ -139,6 +236,47 @@ int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats
     const double K = 1.0 / (12.0 * D.h * D.h);
     std::map<std::tuple<int, int, int>, int> shared;  // isolated: shape -> group
     std::vector<std::vector<int64_t>> group_elems;
+    // systems waiting for their factorisation, run in parallel batches (at
+    // most kBatch systems and kBatchBytes of matrices at once); results are
+    // appended in the order the systems were met
+    std::vector<Job> jobs;
+    size_t pending = 0;
+    auto flush = [&]() -> int {
+      // kBatch threads in all: one per system, the rest inside the inversions
+      const int inner = jobs.empty() ? 1 : std::max<int>(1, (int)(kBatch / jobs.size()));
+      std::vector<std::thread> th;
+      for (size_t q = 1; q < jobs.size(); ++q)
+        th.emplace_back(factorise, std::ref(jobs[q]), H->bottom_kind, inner);
+      if (!jobs.empty()) factorise(jobs[0], H->bottom_kind, inner);
+      for (auto& t : th) t.join();
+      for (Job& J : jobs) {
+        if (!J.ok) {
+          err = J.err;
+          return AMG_EUNSUPPORTED;
+        }
+        BottomGroupD& G = D.groups[J.group];
+        const int64_t nn = J.n, m = J.m;
+        // column-major top-left n x n block of the inverse, then its transpose
+        const size_t base = mats.size();
+        G.mat = (int64_t)base;
+        G.matT = (int64_t)(base + (size_t)nn * nn);
+        mats.resize(base + 2 * (size_t)nn * nn);
+        for (int64_t c = 0; c < nn; ++c)
+          for (int64_t r = 0; r < nn; ++r) {
+            mats[base + (size_t)c * nn + r] = J.A[(size_t)r * m + c];
+            mats[G.matT + (size_t)c * nn + r] = J.A[(size_t)c * m + r];
+          }
+        if (H->bottom_kind == AMG_BOTTOM_ILU_GMRES) {
+          G.ilub = (int64_t)mats.size();
+          G.ilup = G.ilub + m * m;
+          mats.insert(mats.end(), J.B.begin(), J.B.end());
+          mats.insert(mats.end(), J.P.begin(), J.P.end());
+        }
+      }
+      jobs.clear();
+      pending = 0;
+      return AMG_OK;
+    };
     for (auto& sys : systems) {
       // local numbering
       std::vector<int64_t> start(D.boxes.size(), -1);
@@ -245,27 +383,6 @@ int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats
           A[(size_t)n * m + i] = 1.0;
         }
       }
-      if (H->bottom_kind == AMG_BOTTOM_ILU_GMRES) Ks = A;
-      if (!invert(A, m)) {
-        err = "singular bottom system";
-        return AMG_EUNSUPPORTED;
-      }
-      BottomGroupD G;
-      G.mat = (int64_t)mats.size();
-      G.idx = -1;
-      G.n = (int32_t)n;
-      G.ninst = 1;
-      // column-major top-left n x n block, then its transpose (column-major)
-      size_t base = mats.size();
-      G.matT = (int64_t)(base + (size_t)n * n);
-      mats.resize(base + 2 * (size_t)n * n);
-      for (int64_t c = 0; c < n; ++c)
-        for (int64_t r = 0; r < n; ++r) {
-          mats[base + (size_t)c * n + r] = A[(size_t)r * m + c];
-          mats[G.matT + (size_t)c * n + r] = A[(size_t)c * m + r];
-        }
-      G.N = m;
-      G.ilub = G.ilup = G.ws = -1;
       if (H->bottom_kind == AMG_BOTTOM_ILU_GMRES) {
         if (m > 4096) {  // the GMRES kernel stages one vector of the system in LDS
           char b2[160];
@@ -273,47 +390,39 @@ int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats
           err = b2;
           return AMG_EUNSUPPORTED;
         }
-        std::vector<double> LU = Ks;
-        if (!ilu0(LU, m)) {
-          err = "ILU(0) of a bottom system met a zero pivot";
-          return AMG_EUNSUPPORTED;
-        }
-        // P = (L U)^-1 by columns (forward then back substitution), then B = K P
-        std::vector<double> P((size_t)m * m);  // column-major
-        std::vector<double> y(m);
-        for (int c = 0; c < m; ++c) {
-          for (int i = 0; i < m; ++i) {
-            double s = i == c ? 1.0 : 0.0;
-            const double* ri = &LU[(size_t)i * m];
-            for (int j = 0; j < i; ++j) s -= ri[j] * y[j];
-            y[i] = s;
-          }
-          for (int i = m - 1; i >= 0; --i) {
-            double s = y[i];
-            const double* ri = &LU[(size_t)i * m];
-            for (int j = i + 1; j < m; ++j) s -= ri[j] * P[(size_t)c * m + j];
-            P[(size_t)c * m + i] = s / ri[i];
-          }
-        }
-        G.ilub = (int64_t)mats.size();
-        G.ilup = G.ilub + (int64_t)m * m;
-        mats.resize(mats.size() + 2 * (size_t)m * m);
-        for (int c = 0; c < m; ++c)
-          for (int r = 0; r < m; ++r) {
-            double s = 0.0;
-            const double* kr = &Ks[(size_t)r * m];
-            for (int j = 0; j < m; ++j)
-              if (kr[j] != 0.0) s += kr[j] * P[(size_t)c * m + j];
-            mats[G.ilub + (size_t)c * m + r] = s;
-            mats[G.ilup + (size_t)c * m + r] = P[(size_t)c * m + r];
-          }
+        Ks = A;
       }
+      // the group's place is fixed now; its matrices follow when the batch
+      // of pending systems is factorised
+      const size_t bytes = (H->bottom_kind == AMG_BOTTOM_ILU_GMRES ? 4 : 2) * (size_t)m * m * sizeof(double);
+      if (!jobs.empty() && (jobs.size() >= kBatch || pending + bytes > kBatchBytes)) {
+        const int rc = flush();
+        if (rc != AMG_OK) return rc;
+      }
+      BottomGroupD G;
+      memset(&G, 0, sizeof G);
+      G.mat = G.matT = G.idx = G.ilub = G.ilup = G.ws = -1;
+      G.n = (int32_t)n;
+      G.N = m;
+      G.ninst = 1;
+      Job J;
+      J.group = (int)D.groups.size();
+      J.m = m;
+      J.n = (int)n;
+      J.A.swap(A);
+      J.K.swap(Ks);
+      jobs.push_back(std::move(J));
+      pending += bytes;
       group_elems.push_back(elems);
       if (L.isolated) {
         const BoxD& X = D.boxd[sys[0]];
         shared[std::make_tuple(X.n[0], X.n[1], X.n[2])] = (int)D.groups.size();
       }
       D.groups.push_back(G);
+    }
+    {
+      const int rc = flush();
+      if (rc != AMG_OK) return rc;
     }
     // instances of one group are contiguous in the index pool
     for (size_t g = 0; g < D.groups.size(); ++g) {
