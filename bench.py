@@ -54,6 +54,9 @@ def parse():
                         "whose 1e-10 solve it reaches fastest of V(0..2, 1..4); 2,2 otherwise)")
     p.add_argument("--no-split", action="store_true",
                    help="3D mixed precision: keep the finest depth in interleaved storage during post-smoothing")
+    p.add_argument("--no-tail", action="store_true",
+                   help="mixed precision: launch every operation of the coarse depths instead of running the "
+                        "coarse tail of the V-cycle in one workgroup")
     p.add_argument("--no-graph", action="store_true",
                    help="launch every kernel of a cycle directly instead of replaying its HIP graph")
     p.add_argument("--plain", action="store_true",
@@ -286,6 +289,8 @@ def main():
         H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c)
         if args.no_split:  # before the autotuner, which times the sweep the solves will run
             H.set_tuning(A.TUNE_SPLIT_RB, 0)
+        if args.no_tail:
+            H.set_tuning(A.TUNE_TAIL, 0)
         if args.march:
             march = args.march
             H.set_tuning(A.TUNE_MARCH2 if dim == 2 else A.TUNE_MARCH3, march)
@@ -362,7 +367,8 @@ def main():
                    "bottom": args.bottom if args.bottom == "exact" else f"ilu_gmres({args.bottom_iters})",
                    "depths": systems[0][1].level_info(0).depths,
                    "split_storage": bool(systems[0][1].level_info(0).split_rb) and prec == A.MIXED and
-                   args.smoother == "rb"},
+                   args.smoother == "rb",
+                   "tail_depth": systems[0][1].level_info(0).tail_depth if prec == A.MIXED else -1},
     }
     if not args.no_timing:
         # dominant kernel: the smoothing half-sweep on the finest depth (in
@@ -530,6 +536,8 @@ def bench_amr(args):
             for s in (0, 1):
                 H.set_physical_bc(d, s, A.DIRICHLET if bc == "D" else A.NEUMANN)
         H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c if op == "helmholtz" else 0.0)
+        if args.no_tail:
+            H.set_tuning(A.TUNE_TAIL, 0)
         H.finalize()
         fs = []
         for l in range(2):
@@ -882,6 +890,8 @@ def bench_batched(args):
     H.set_operator(A.HELMHOLTZ, c)
     if args.no_split:
         H.set_tuning(A.TUNE_SPLIT_RB, 0)
+    if args.no_tail:
+        H.set_tuning(A.TUNE_TAIL, 0)
     t0 = time.perf_counter()
     if args.march:
         march = args.march

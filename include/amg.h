@@ -128,6 +128,8 @@ typedef struct {
   int64_t nstored;     /* elements of the packed buffer */
   int64_t nface;       /* elements of the face-data buffer */
   int32_t split_rb;    /* bit k set: mixed-precision solves post-smooth depth k in colour-split storage */
+  int32_t tail_depth;  /* first depth of the FP32 V-cycle's one-workgroup coarse tail (AMG_TUNE_TAIL) in
+                          forward solves, -1: none */
 } amg_level_desc;
 
 typedef struct {
@@ -270,6 +272,15 @@ int amg_set_operator(amg_hier* h, int kind, double c);
  * interleaved storage.  The two forms give the same results (to the
  * rounding of FP32 sums). */
 #define AMG_TUNE_SPLIT_RB 3
+/* AMG_TUNE_TAIL: 1 (default) runs the coarse tail of the FP32 V-cycle of a
+ * forward solve in three launches: from the first depth of at most 4096
+ * cells (16^3, 64^2) down, where every depth holds one box whose faces are
+ * all filled uniformly and the coarsest is one exact system, one workgroup
+ * smooths and restricts depth after depth in LDS, the bottom kernel solves,
+ * and one workgroup prolongs and smooths back up; 0 launches every
+ * operation of every depth.  The two forms give the same results (to the
+ * rounding of FP32 sums). */
+#define AMG_TUNE_TAIL 4
 int amg_set_tuning(amg_hier* h, int key, int value);
 
 /* Size of the exactly solved coarsest systems (Section 6.5 leaves the bottom

@@ -24,13 +24,14 @@ SOLV_RHS_SHIFT, SOLV_OFF, SOLV_CF_DELTA = 0, 1, 2
 BOTTOM_EXACT, BOTTOM_ILU_GMRES = 0, 1
 CIC_VALUE, CIC_NORMAL_DERIVATIVE = 0, 1
 T_SWEEP, T_FILL, T_RESTRICT, T_PROLONG, T_RESIDUAL, T_SWEEP_SPLIT, T_KINDS = range(7)
-TUNE_MARCH2, TUNE_MARCH3, TUNE_ROW_ALIGN, TUNE_SPLIT_RB = range(4)
+TUNE_MARCH2, TUNE_MARCH3, TUNE_ROW_ALIGN, TUNE_SPLIT_RB, TUNE_TAIL = range(5)
 MAX_HISTORY, MAX_COMP = 128, 64
 
 
 class LevelDesc(C.Structure):
     _fields_ = [("nboxes", C.c_int32), ("depths", C.c_int32), ("ncomp", C.c_int32), ("nsingular", C.c_int32),
-                ("ncells", C.c_int64), ("nstored", C.c_int64), ("nface", C.c_int64), ("split_rb", C.c_int32)]
+                ("ncells", C.c_int64), ("nstored", C.c_int64), ("nface", C.c_int64), ("split_rb", C.c_int32),
+                ("tail_depth", C.c_int32)]
 
 
 class BoxDesc(C.Structure):

@@ -335,6 +335,7 @@ struct amg_hier {
   int row_align = ROW_ALIGN_DEFAULT;                       // row alignment of the packed layout (elements)
   int bottom_cells = 0;  // coarsening stops once every component has at most this many cells (0: off)
   int split_rb = 1;      // mixed-precision post-smoothing of depth 0 in colour-split storage where allowed
+  int tail = 1;          // the FP32 V-cycle's coarse tail in one workgroup where allowed
   int dim = 2;
   int32_t base[3] = {1, 1, 1};
   double h0 = 1;         // cell size of level 0

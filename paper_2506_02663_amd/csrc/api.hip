@@ -341,6 +341,66 @@ inline bool use_split(const amg_hier* H, const Depth& D0, const amg_solve_opts& 
   return D0.split_rb && D0.fs32 && o.smoother == AMG_SMOOTH_RB && o.nu2 > 0;
 }
 
+// First depth of the FP32 V-cycle's coarse tail (tail.hip), or -1: the
+// first depth k >= 1 of at most 4096 cells from which every depth holds one
+// box, smooths with every face filled uniformly, and the coarsest is one
+// exact system; at least one depth above the bottom.
+int tail_start(const Run& R, const amg_solve_opts& o) {
+  const Level& L = *R.L;
+  const int K = (int)L.depths.size();
+  if (!R.H->tail || R.tr || L.ncomp != 1 || K < 3) return -1;
+  if (o.smoother != AMG_SMOOTH_RB && o.smoother != AMG_SMOOTH_JACOBI) return -1;
+  const Depth& B = L.depths[K - 1];
+  if (B.boxes.size() != 1 || B.groups.size() != 1 || B.groups[0].ninst != 1 || !B.stiles.empty() ||
+      !B.uniform_fill)
+    return -1;
+  int kt = -1;
+  for (int k = K - 2; k >= 1; --k) {
+    const Depth& D = L.depths[k];
+    if (D.boxes.size() != 1 || !D.uniform_fill || D.stiles.empty() || !D.groups.empty()) break;
+    const BoxD& b = D.boxd[0];
+    if ((int64_t)b.n[0] * b.n[1] * b.n[2] > 4096 || K - k > kTailMaxDepths) break;
+    // LDS of both legs: four arrays of depth k, one of depth k + 1
+    auto padded = [&](const BoxD& x) {
+      return (size_t)(x.n[0] + 4) * (x.n[1] + 4) * (R.dim == 3 ? x.n[2] + 4 : 1) * sizeof(float);
+    };
+    if (4 * padded(b) + padded(L.depths[k + 1].boxd[0]) > tail_lds_limit()) break;
+    kt = k;
+  }
+  return kt;
+}
+
+// The tail's three launches: down-leg (depths kt .. K-2), the bottom solve,
+// up-leg; the result of depth kt lands in its e buffer.
+void run_tail(const Run& R, const amg_solve_opts& o, int kt) {
+  Level& L = *R.L;
+  const int K = (int)L.depths.size();
+  TailArgs A;
+  memset(&A, 0, sizeof A);
+  A.nd = K - kt;
+  A.nu1 = o.nu1;
+  A.nu2 = o.nu2;
+  A.rb = o.smoother == AMG_SMOOTH_RB ? 1 : 0;
+  A.singular = L.comp_singular[0] != 0;
+  A.omega = (float)relax(o);
+  for (int j = 0; j < A.nd; ++j) {
+    Depth& D = L.depths[kt + j];
+    TailDepth& T = A.d[j];
+    T.b = D.boxd[0];
+    T.e = D.e32;
+    T.f = D.f32;
+    coefs<float>(R.H, D, T.alpha, T.beta);
+    T.cnt = (double)L.comp_cells[0] / std::pow(2.0, (double)(R.dim * (kt + j)));
+  }
+  Depth& B = L.depths[K - 1];
+  launch_tail_down(R.dim, A, R.st);
+  if (R.H->bottom_kind == AMG_BOTTOM_ILU_GMRES)
+    launch_bottom_gmres<float>(B, L.d_mat, L.d_idx, B.f32, B.e32, R.H->bottom_iters, L.d_gws, R.st, B.t32);
+  else
+    launch_bottom<float>(B, L.d_mat, L.d_idx, B.f32, B.e32, false, R.st, B.t32);
+  launch_tail_up(R.dim, A, R.st);
+}
+
 // One homogeneous V-cycle from e = 0; f0 is the depth-0 right-hand side, e0
 // and t0 the two depth-0 buffers.  Returns the buffer that holds e.  With
 // fs0 (FP32: the depth-0 right-hand side in colour-split storage, depth 0
@@ -362,8 +422,18 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, cons
     oth[k] = k ? Bufs<T>::t(L.depths[k]) : t0;
     f[k] = k ? Bufs<T>::f(L.depths[k]) : f0;
   }
+  // the coarse tail in three launches (FP32 forward cycles)
+  const int kt = sizeof(T) == 4 ? tail_start(R, o) : -1;
   for (int k = 0; k < K; ++k) {
     Depth& D = L.depths[k];
+    if (k == kt) {
+      if constexpr (sizeof(T) == 4) {
+        Timed tm(R, AMG_T_SWEEP, k);
+        run_tail(R, o, k);
+        cur[k] = D.e32;
+      }
+      break;
+    }
     // boxes that end here: exact solve, written to both buffers of the depth
     if (!D.groups.empty()) {
       if (R.H->bottom_kind == AMG_BOTTOM_ILU_GMRES && !R.tr)  // the adjoint keeps the exact transposed inverse
@@ -410,7 +480,7 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, cons
     }
     remove_mean<T>(R, k + 1, Bufs<T>::f(L.depths[k + 1]));
   }
-  for (int k = K - 2; k >= 0; --k) {
+  for (int k = (kt > 0 ? kt - 1 : K - 2); k >= 0; --k) {
     Depth& D = L.depths[k];
     if (D.stiles.empty()) continue;
     // the FP32 prolongation into depths below the finest forms the coarse
@@ -827,6 +897,10 @@ int amg_set_tuning(amg_hier* H, int key, int value) {
       if (value != 0 && value != 1) return fail(H, AMG_EINVAL, "split red-black switch must be 0 or 1");
       H->split_rb = value;
       return AMG_OK;
+    case AMG_TUNE_TAIL:
+      if (value != 0 && value != 1) return fail(H, AMG_EINVAL, "tail switch must be 0 or 1");
+      H->tail = value;
+      return AMG_OK;
     case AMG_TUNE_ROW_ALIGN:
       if (value < 2 || value > 256 || (value & (value - 1)))
         return fail(H, AMG_EINVAL, "alignment must be a power of two of at least 2");
@@ -887,6 +961,7 @@ int amg_finalize(amg_hier* H) {
     if (rc != AMG_OK) return fail(H, rc, err);
   }
   HIPCHK(hipStreamCreate(&H->own));
+  tail_prepare();
   {
     double* sp = nullptr;  // the allocation-free entry point's scratch on this device
     HIPCHK(scratch_address(&sp));
@@ -1021,6 +1096,12 @@ int amg_level_info(const amg_hier* Hc, int level, amg_level_desc* out) {
   out->nstored = L.depths[0].nstored;
   out->nface = L.nface;
   out->split_rb = L.depths[0].split_rb ? 1 : 0;
+  {
+    Run R{H, const_cast<Level*>(&L), H->dim, H->own};
+    amg_solve_opts o;
+    amg_default_opts(&o);
+    out->tail_depth = tail_start(R, o);
+  }
   return AMG_OK;
 }
 

@@ -5,6 +5,31 @@
 #include "amg_internal.h"
 
 namespace amg {
+// The FP32 V-cycle's coarse tail in one workgroup (tail.hip): depths d[0]
+// (the first tail depth) .. d[nd-1] (the exact bottom system), one box each,
+// every face filled uniformly.  e / f: the depth's iterate and right-hand
+// side buffers; cnt: the component's cells at the depth.
+constexpr int kTailMaxDepths = 8;
+struct TailDepth {
+  BoxD b;
+  float* e;
+  float* f;
+  float alpha, beta;
+  double cnt;
+};
+struct TailArgs {
+  TailDepth d[kTailMaxDepths];
+  int nd, nu1, nu2, rb, singular;
+  float omega;
+};
+// LDS bytes of either leg (four arrays of the first depth, one of the second)
+size_t tail_lds_bytes(int dim, const TailArgs& A);
+// the largest dynamic LDS a tail leg may use on the current device
+size_t tail_lds_limit();
+// raises the tail kernels' dynamic LDS limit to it (before any capture)
+void tail_prepare();
+void launch_tail_down(int dim, const TailArgs& A, hipStream_t st);
+void launch_tail_up(int dim, const TailArgs& A, hipStream_t st);
 template <typename T>
 void launch_fill(const Depth& D, T* u, const double* fd, hipStream_t st);
 template <typename T>

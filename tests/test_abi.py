@@ -70,7 +70,9 @@ def test_host_argument_checks(lib):
     assert L.amg_set_bottom_solver(h, A.BOTTOM_ILU_GMRES, 17) == A.EINVAL
     assert L.amg_set_bottom_solver(h, A.BOTTOM_ILU_GMRES, 5) == A.OK
     assert L.amg_set_tuning(h, 3, 2) == A.EINVAL                            # split switch is 0 or 1
-    assert L.amg_set_tuning(h, 4, 0) == A.EINVAL                            # no such key
+    assert L.amg_set_tuning(h, 4, 2) == A.EINVAL                            # tail switch is 0 or 1
+    assert L.amg_set_tuning(h, 4, 0) == A.OK
+    assert L.amg_set_tuning(h, 5, 0) == A.EINVAL                            # no such key
     assert L.amg_solve(h, 0, 0, None, None, None, None, None, None) == A.EINVAL  # not finalized
     assert b"finalize" in L.amg_last_error(h)
     assert L.amg_destroy(h) == A.OK
