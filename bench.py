@@ -629,6 +629,8 @@ def bench_imex(args):
         H.set_operator(op, dt * nu / 4 if op == A.HELMHOLTZ else 0.0)
         if args.bottom_cells:
             H.set_bottom_cells(args.bottom_cells)
+        if args.no_tail:
+            H.set_tuning(A.TUNE_TAIL, 0)
         H.finalize()
         hs.append(H)
     Hv, Hp = hs

@@ -275,7 +275,8 @@ int amg_set_operator(amg_hier* h, int kind, double c);
 /* AMG_TUNE_TAIL: 1 (default) runs the coarse tail of the FP32 V-cycle of a
  * forward solve in three launches: from the first depth of at most 4096
  * cells (16^3, 64^2) down, where every depth holds one box whose faces are
- * all filled uniformly and the coarsest is one exact system, one workgroup
+ * all filled uniformly or periodic across the whole box, and the coarsest is
+ * one exact system, one workgroup
  * smooths and restricts depth after depth in LDS, the bottom kernel solves,
  * and one workgroup prolongs and smooths back up; 0 launches every
  * operation of every depth.  The two forms give the same results (to the

@@ -343,8 +343,23 @@ inline bool use_split(const amg_hier* H, const Depth& D0, const amg_solve_opts& 
 
 // First depth of the FP32 V-cycle's coarse tail (tail.hip), or -1: the
 // first depth k >= 1 of at most 4096 cells from which every depth holds one
-// box, smooths with every face filled uniformly, and the coarsest is one
-// exact system; at least one depth above the bottom.
+// box whose faces are filled uniformly or wrap onto it, and the coarsest is
+// one exact system; at least one depth above the bottom.
+// direction d of depth D's one box wraps onto the box itself (periodic, and
+// the box spans the grid)
+bool tail_wraps(const Depth& D, int d) { return D.periodic[d] && D.boxd[0].n[d] == D.dn[d]; }
+
+// every face of depth D's one box filled uniformly from its own rows, or
+// wrapping onto the box (an exchange face: column code 0)
+bool tail_faces(const Depth& D, int dim) {
+  for (int d = 0; d < dim; ++d)
+    for (int s = 0; s < 2; ++s) {
+      const uint8_t c = D.boxd[0].ucode[d][s];
+      if (tail_wraps(D, d) ? c != 0 : (c != 5 && c != 6)) return false;
+    }
+  return true;
+}
+
 int tail_start(const Run& R, const amg_solve_opts& o) {
   const Level& L = *R.L;
   const int K = (int)L.depths.size();
@@ -352,12 +367,12 @@ int tail_start(const Run& R, const amg_solve_opts& o) {
   if (o.smoother != AMG_SMOOTH_RB && o.smoother != AMG_SMOOTH_JACOBI) return -1;
   const Depth& B = L.depths[K - 1];
   if (B.boxes.size() != 1 || B.groups.size() != 1 || B.groups[0].ninst != 1 || !B.stiles.empty() ||
-      !B.uniform_fill)
+      !tail_faces(B, R.dim))
     return -1;
   int kt = -1;
   for (int k = K - 2; k >= 1; --k) {
     const Depth& D = L.depths[k];
-    if (D.boxes.size() != 1 || !D.uniform_fill || D.stiles.empty() || !D.groups.empty()) break;
+    if (D.boxes.size() != 1 || !tail_faces(D, R.dim) || D.stiles.empty() || !D.groups.empty()) break;
     const BoxD& b = D.boxd[0];
     if ((int64_t)b.n[0] * b.n[1] * b.n[2] > 4096 || K - k > kTailMaxDepths) break;
     // LDS of both legs: four arrays of depth k, one of depth k + 1
@@ -391,6 +406,7 @@ void run_tail(const Run& R, const amg_solve_opts& o, int kt) {
     T.f = D.f32;
     coefs<float>(R.H, D, T.alpha, T.beta);
     T.cnt = (double)L.comp_cells[0] / std::pow(2.0, (double)(R.dim * (kt + j)));
+    for (int d = 0; d < R.dim; ++d) T.wrap[d] = tail_wraps(D, d) ? 1 : 0;
   }
   Depth& B = L.depths[K - 1];
   launch_tail_down(R.dim, A, R.st);

@@ -7,7 +7,7 @@
 namespace amg {
 // The FP32 V-cycle's coarse tail in one workgroup (tail.hip): depths d[0]
 // (the first tail depth) .. d[nd-1] (the exact bottom system), one box each,
-// every face filled uniformly.  e / f: the depth's iterate and right-hand
+// every face filled uniformly or periodic onto the box itself.  e / f: the depth's iterate and right-hand
 // side buffers; cnt: the component's cells at the depth.
 constexpr int kTailMaxDepths = 8;
 struct TailDepth {
@@ -16,6 +16,7 @@ struct TailDepth {
   float* f;
   float alpha, beta;
   double cnt;
+  int32_t wrap[3];  // direction d periodic with the box spanning the grid: its ghosts wrap onto itself
 };
 struct TailArgs {
   TailDepth d[kTailMaxDepths];

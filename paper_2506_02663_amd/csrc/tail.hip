@@ -2,17 +2,18 @@
 // at most 4096 cells (16^3, 64^2) every multigrid operation is a few
 // microseconds of launch and cache set-up around almost no work, ten of them
 // per depth.  Where every depth from there down holds one box whose faces
-// are all filled uniformly (both ghost layers from its own rows), and the
+// are all filled uniformly (both ghost layers from its own rows) or wrap
+// onto the box itself (a periodic direction that the box spans), and the
 // coarsest is one exact bottom system, one workgroup runs the whole
 // down-leg in LDS (pre-smoothing from zero, residual and restriction, mean
 // removal of a singular problem, depth after depth), the existing bottom
 // kernel solves the coarsest system, and one workgroup runs the up-leg
 // (prolongation, post-smoothing).  Each depth's box is staged in LDS with two
 // ghost layers, filled there before every operator application, with a
-// table of its inverse diagonal.  The
-// arithmetic per cell is the tiled kernels' (the stencil in the same order,
-// the same fills, folded diagonal, prolongation and mean removal), so the
-// two paths agree to the rounding of the diagonal's and the mean's sums.
+// table of its inverse diagonal.  The arithmetic per cell is the tiled
+// kernels' (the stencil in the same order, the same fills, folded diagonal,
+// prolongation and mean removal), so the two paths agree to the rounding of
+// the diagonal's and the mean's sums.
 #include <hip/hip_runtime.h>
 
 #include "amg_internal.h"
@@ -59,9 +60,10 @@ struct Lay {
   }
 };
 
-// both ghost layers of every face from the face rows (uniform fills)
+// both ghost layers of every face: from the face rows (uniform fills), or,
+// in a direction that wraps onto the box, the cells at the other end
 template <int DIM>
-__device__ void fill(const Lay<DIM>& L, const BoxD& b, float* u) {
+__device__ void fill(const Lay<DIM>& L, const BoxD& b, const int32_t* wrap, float* u) {
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
@@ -70,6 +72,7 @@ __device__ void fill(const Lay<DIM>& L, const BoxD& b, float* u) {
     for (int side = 0; side < 2; ++side) {
       const uint8_t cd = b.ucode[d][side];
       const int in = side ? -st : st;
+      const int far = (L.n[d] - 1) * in;  // from the face cell to the other end of its row
       const float rm1 = 1.0f / (float)m1;
       for (int r = (int)threadIdx.x; r < m1 * m2; r += kThreads) {
         int q[3] = {0, 0, 0};
@@ -78,6 +81,11 @@ __device__ void fill(const Lay<DIM>& L, const BoxD& b, float* u) {
         q[d1] = r - r2 * m1;
         if (DIM == 3) q[d2] = r2;
         const int e0 = L.at(q[0], q[1], q[2]);
+        if (wrap[d]) {  // ghost layer g is the cell g from the other end
+          u[e0 - in] = u[e0 + far];
+          u[e0 - 2 * in] = u[e0 + far - in];
+          continue;
+        }
         const float u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
         u[e0 - in] = ghost1<float>(cd, u0, u1, u2, u3);
         u[e0 - 2 * in] = ghost2<float>(cd, u0, u1, u2, u3);
@@ -178,7 +186,7 @@ __device__ float* smooth(const Lay<DIM>& L, const BoxD& b, const TailDepth& D, c
   }
   const int nh = rb ? 2 * nsw : nsw;
   for (; h < nh; ++h) {
-    fill<DIM>(L, b, u);
+    fill<DIM>(L, b, D.wrap, u);
     __syncthreads();
     sweep<DIM>(L, b, D, f, iv, u, o, rb ? (h & 1) : -1, omega);
     __syncthreads();
@@ -234,7 +242,7 @@ __global__ void __launch_bounds__(kThreads) k_tail_down(TailArgs A) {
     __syncthreads();
     float* u = smooth<DIM>(L, D.b, D, f, IV, U, O, A.nu1, true, A.rb, A.omega);
     store<DIM>(L, D.b, u, D.e);
-    fill<DIM>(L, D.b, u);
+    fill<DIM>(L, D.b, D.wrap, u);
     __syncthreads();
     // residual and restriction: the mean of the 2^D children's residuals
 #pragma unroll 4
@@ -299,7 +307,7 @@ __global__ void __launch_bounds__(kThreads) k_tail_up(TailArgs A) {
     load<DIM>(L, D.b, D.e, U);
     load<DIM>(L, D.b, D.f, F);
     diag_table<DIM>(L, D.b, D, IV);
-    fill<DIM>(Lc, C.b, Cb);
+    fill<DIM>(Lc, C.b, C.wrap, Cb);
     __syncthreads();
     // u += (1 - D/4) e_P + 1/4 sum_d e_(P + s_d e_d), s_d the child's side
   #pragma unroll 4

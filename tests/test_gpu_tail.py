@@ -3,7 +3,8 @@ the same solves launching every operation of every depth: the tail engages
 where the layout allows it (level info), and mixed-precision solves with and
 without it take the same number of cycles, with residual histories equal to
 FP32 rounding and solutions equal to the solve tolerance; Dirichlet, Neumann
-(singular: the mean removal inside the tail) and mixed faces, Helmholtz and
+(singular: the mean removal inside the tail), mixed and periodic faces
+(ghosts wrapping onto the box), Helmholtz and
 Poisson, red-black and Jacobi smoothing, 2D and 3D, cubic and ragged boxes,
 with the bottom at the layout's last depth or at a chosen size.  The
 tail-on solves also match the oracle's (the default of every other mixed
@@ -30,6 +31,9 @@ CASES = {
     "2d_128_N": ((128, 128), "N", 0),
     "2d_128_D_bottom256": ((128, 128), "D", 256),
     "2d_64_mixed": ((64, 64), "M", 0),
+    "2d_128_periodic": ((128, 128), "P", 0),
+    "2d_128_periodic_x": ((128, 64), "PX", 0),
+    "3d_32_periodic_xz": ((32, 32, 32), "PXZ", 0),
 }
 
 
@@ -39,6 +43,10 @@ def bcs(D, kind):
         if D == 3:
             b.update({(2, 0): "D", (2, 1): "N"})
         return b
+    if kind == "PX":  # periodic in x, Dirichlet / Neumann in y
+        return {(0, 0): "P", (0, 1): "P", (1, 0): "D", (1, 1): "N"}
+    if kind == "PXZ":  # periodic in x and z, Neumann in y (singular)
+        return {(0, 0): "P", (0, 1): "P", (1, 0): "N", (1, 1): "N", (2, 0): "P", (2, 1): "P"}
     return {(d, s): kind for d in range(D) for s in (0, 1)}
 
 
@@ -47,7 +55,7 @@ def hier(shape, bc, op, c, bottom_cells, tail):
     H = A.Hierarchy(D, shape, 1.0 / shape[0], 1)
     H.set_level_boxes(0, [((0,) * D, tuple(n - 1 for n in shape))])
     for (d, s), k in bc.items():
-        H.set_physical_bc(d, s, A.DIRICHLET if k == "D" else A.NEUMANN)
+        H.set_physical_bc(d, s, {"D": A.DIRICHLET, "N": A.NEUMANN, "P": A.PERIODIC}[k])
     H.set_operator(A.HELMHOLTZ if op == "helmholtz" else A.POISSON, c)
     if bottom_cells:
         H.set_bottom_cells(bottom_cells)
@@ -60,7 +68,7 @@ def rhs(lev, op, seed):
     rng = np.random.default_rng(seed)
     f = lev.zeros()
     f[lev.mask] = rng.normal(size=lev.ncells)
-    if op == "poisson" and all(k == "N" for k in lev.phys_bc.values()):
+    if op == "poisson" and all(k in "NP" for k in lev.phys_bc.values()):
         f[lev.mask] -= f[lev.mask].mean()
     return f
 
@@ -97,7 +105,7 @@ def test_tail_matches_the_launch_per_operation_cycle(name, op, smoother):
     assert np.abs(x_on - x_off)[m].max() <= 1e-6 * scale
 
 
-@pytest.mark.parametrize("shape,kind", [((32, 32), "N"), ((16, 16, 16), "M")])
+@pytest.mark.parametrize("shape,kind", [((32, 32), "N"), ((16, 16, 16), "M"), ((32, 32), "P")])
 def test_tail_solve_matches_the_oracle(shape, kind):
     D = len(shape)
     bc = bcs(D, kind)
@@ -116,7 +124,7 @@ def test_tail_solve_matches_the_oracle(shape, kind):
         want, ost = mg.solve(lev, f, "poisson", 0.0, smoother="rb", tol_rel=1e-13, max_cycles=100)
         assert ost["converged"]
     m = lev.mask
-    if all(k == "N" for k in bc.values()):
+    if all(k in "NP" for k in bc.values()):
         got[m] -= got[m].mean()
         want[m] -= want[m].mean()
     assert np.abs(got - want)[m].max() <= 1e-9 * np.abs(want[m]).max()
