@@ -39,7 +39,9 @@ struct BoxD {              // one box at one multigrid depth
   int32_t fine;            // index of the same box at depth-1 (-1 at depth 0)
   int32_t coarse;          // index at depth+1, -1 if the box ends here
   uint8_t ucode[3][2];     // column code shared by a whole face, 0xFF if the face mixes codes
-  uint8_t pad[2];
+  uint8_t wrap;            // bit d: direction d is periodic and the box spans the grid, so its ghosts
+                           // in d are its own cells at the other end
+  uint8_t pad;
   int64_t xg;              // colour-split depths: first element of the box's x-face ghost rows in Depth::xg32
 };
 

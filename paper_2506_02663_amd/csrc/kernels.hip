@@ -260,29 +260,44 @@ __device__ __forceinline__ bool gfill(uint8_t cd, const T* __restrict__ u, int64
 template <typename T, int DIM>
 __device__ __forceinline__ void face_ghosts(const BoxD& b, T* __restrict__ u, int x0, int nx, int y0, int ny, int p0,
                                             int len, bool xfaces = true) {
-  // x faces: one thread per (row, side)
+  // x faces: one thread per (row, side); a face that wraps onto the box
+  // takes the row's cells at the other end
+  const bool wx = b.wrap & 1;
   for (int side = 0; side < 2 && xfaces; ++side) {
     const uint8_t cd = b.ucode[0][side];
-    if (cd == 0xFF || !(cd & 3)) continue;
+    if (!wx && (cd == 0xFF || !(cd & 3))) continue;
     if (side == 0 ? x0 != 0 : x0 + nx != b.n[0]) continue;
     for (int r = (int)threadIdx.x; r < ny * len; r += (int)blockDim.x) {
       const int y = DIM == 3 ? y0 + r % ny : 0, p = p0 + r / ny;
       const int64_t e0 = cell_index<DIM>(b, side ? b.n[0] - 1 : 0, DIM == 3 ? y : p, DIM == 3 ? p : 0);
       const int64_t in = side ? -1 : 1;
+      if (wx) {
+        const int64_t far = (int64_t)(b.n[0] - 1) * in;
+        u[e0 - in] = u[e0 + far];
+        u[e0 - 2 * in] = u[e0 + far - in];
+        continue;
+      }
       const T u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
       u[e0 - in] = ghost1<T>(cd, u0, u1, u2, u3);
       if (cd & 4) u[e0 - 2 * in] = ghost2<T>(cd, u0, u1, u2, u3);
     }
   }
   if (DIM == 3) {
+    const bool wy = (b.wrap >> 1) & 1;
     for (int side = 0; side < 2; ++side) {
       const uint8_t cd = b.ucode[1][side];
-      if (cd == 0xFF || !(cd & 3)) continue;
+      if (!wy && (cd == 0xFF || !(cd & 3))) continue;
       if (side == 0 ? y0 != 0 : y0 + ny != b.n[1]) continue;
       for (int r = (int)threadIdx.x; r < nx * len; r += (int)blockDim.x) {
         const int x = x0 + r % nx, p = p0 + r / nx;
         const int64_t e0 = cell_index<DIM>(b, x, side ? b.n[1] - 1 : 0, p);
         const int64_t in = (side ? -1 : 1) * (int64_t)b.s[1];
+        if (wy) {
+          const int64_t far = (int64_t)(b.n[1] - 1) * in;
+          u[e0 - in] = u[e0 + far];
+          u[e0 - 2 * in] = u[e0 + far - in];
+          continue;
+        }
         const T u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
         u[e0 - in] = ghost1<T>(cd, u0, u1, u2, u3);
         if (cd & 4) u[e0 - 2 * in] = ghost2<T>(cd, u0, u1, u2, u3);
@@ -337,9 +352,10 @@ __device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __
 // tile and the neighbouring tiles on the same XCD have just fetched them).
 //
 // gr != 0: the ghosts of filled columns (physical and coarse-fine face-data
-// faces, homogeneous) are computed where they are read (gfill), so no fill
-// launch is needed before the sweep for them; ghosts of exchange and
-// interpolated columns still come from memory.
+// faces, homogeneous) are computed where they are read (gfill), and those of
+// a direction that wraps onto the box are read from its other end, so no
+// fill launch is needed before the sweep for them; ghosts of other exchange
+// and interpolated columns still come from memory.
 template <typename T, int DIM, int OP, bool PART>
 __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles, int ntiles,
                                                 const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
@@ -359,7 +375,8 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
   if (gr) {
     const int nx = min(TILE_X, b.n[0] - t.x0);
     const uint8_t ux0 = b.ucode[0][0], ux1 = b.ucode[0][1];
-    const bool xf = (ux0 != 0xFF && (ux0 & 3) && t.x0 == 0) || (ux1 != 0xFF && (ux1 & 3) && t.x0 + nx == b.n[0]);
+    const bool xf = (ux0 != 0xFF && (ux0 & 3) && t.x0 == 0) || (ux1 != 0xFF && (ux1 & 3) && t.x0 + nx == b.n[0]) ||
+                    ((b.wrap & 1) && (t.x0 == 0 || t.x0 + nx == b.n[0]));
     const bool yf = DIM == 3 && (t.y0 == 0 || t.y0 + TILE3_Y >= b.n[1]);
     if (xf || yf) {  // block-uniform
       tile_ghosts<T, DIM>(t, b, const_cast<T*>(u));
@@ -372,7 +389,20 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
     constexpr int M = DIM - 1;
     const int nm = b.n[M];
     int64_t c = C.base + (int64_t)(C.p0 + 2) * sm;
+    // the march direction wraps onto the box: its ghosts are the column's
+    // planes at the other end, read there (c0: plane 0 of the column)
+    const bool wm = gr && ((b.wrap >> M) & 1);
+    const int64_t c0 = c - (int64_t)C.p0 * sm;
     T q0 = u[c - 2 * sm], q1 = u[c - sm], q2 = u[c], q3 = u[c + sm];
+    if (wm) {
+      if (C.p0 == 0) {
+        q0 = u[c0 + (int64_t)(nm - 2) * sm];
+        q1 = u[c0 + (int64_t)(nm - 1) * sm];
+      } else if (C.p0 == 1) {
+        q0 = u[c0 + (int64_t)(nm - 1) * sm];
+      }
+      if (C.p0 + 1 >= nm) q3 = u[c0 + (int64_t)(C.p0 + 1 - nm) * sm];
+    }
     // march-direction ghosts of this column (homogeneous fill, if filled):
     // the low ones once here, the high ones from the register queue
     uint8_t chi = 0;
@@ -413,6 +443,8 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
         }
       } else if (hk && p + 2 == nm + 1) {
         q4 = g2n;
+      } else if (wm && p + 2 >= nm) {
+        q4 = u[c0 + (int64_t)(p + 2 - nm) * sm];
       } else {
         q4 = u[c + 2 * sm];
       }

@@ -344,6 +344,9 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       D.dn[d] = (int32_t)dn[d];
       D.periodic[d] = per[d];
     }
+    for (BoxD& X : D.boxd)
+      for (int d = 0; d < dim; ++d)
+        if (per[d] && X.n[d] == dn[d]) X.wrap |= (uint8_t)(1 << d);
 
     // ---- ghost-column classification ----
     D.faces.assign((size_t)nbk * 6, FaceCols());
@@ -523,10 +526,15 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       D.chunk_comp_ptr.push_back((int32_t)D.chunk_comp_idx.size());
     }
 
+    // (the FP32 sweeps also form the ghosts of a face that wraps onto its own
+    // box where they read them)
     D.fill_only = true;
-    for (const ChunkD& ch : D.chunks)
-      if (!((ch.kind1 == G_FILL_D || ch.kind1 == G_FILL_N) && (ch.kind2 == G_FILL_D || ch.kind2 == G_FILL_N)))
-        D.fill_only = false;
+    for (const ChunkD& ch : D.chunks) {
+      const bool filled =
+          (ch.kind1 == G_FILL_D || ch.kind1 == G_FILL_N) && (ch.kind2 == G_FILL_D || ch.kind2 == G_FILL_N);
+      const bool wraps = ch.kind1 == G_EXCH && ch.kind2 == G_EXCH && ((D.boxd[ch.box].wrap >> ch.dir) & 1);
+      if (!filled && !wraps) D.fill_only = false;
+    }
     // the read-time fill writes the ghosts across the march direction only on
     // faces with one code; a face across it that mixes codes keeps the launch
     for (const BoxD& X : D.boxd)
