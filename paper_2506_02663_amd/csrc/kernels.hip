@@ -257,12 +257,13 @@ __device__ __forceinline__ bool gfill(uint8_t cd, const T* __restrict__ u, int64
 // (read-time fill): x faces for the rows that reach them, y faces (3D) for
 // the columns that reach them.  Each of these ghosts is read only by the
 // block that writes it.
-template <typename T, int DIM>
+template <typename T, int DIM, bool WRAP = false>
 __device__ __forceinline__ void face_ghosts(const BoxD& b, T* __restrict__ u, int x0, int nx, int y0, int ny, int p0,
                                             int len, bool xfaces = true) {
-  // x faces: one thread per (row, side); a face that wraps onto the box
-  // takes the row's cells at the other end
-  const bool wx = b.wrap & 1;
+  // x faces: one thread per (row, side); with WRAP, a face that wraps onto
+  // the box takes the row's cells at the other end (a compile-time switch:
+  // reading the wrap bits costs the other kernels a memory round trip)
+  const bool wx = WRAP && (b.wrap & 1);
   for (int side = 0; side < 2 && xfaces; ++side) {
     const uint8_t cd = b.ucode[0][side];
     if (!wx && (cd == 0xFF || !(cd & 3))) continue;
@@ -283,7 +284,7 @@ __device__ __forceinline__ void face_ghosts(const BoxD& b, T* __restrict__ u, in
     }
   }
   if (DIM == 3) {
-    const bool wy = (b.wrap >> 1) & 1;
+    const bool wy = WRAP && ((b.wrap >> 1) & 1);
     for (int side = 0; side < 2; ++side) {
       const uint8_t cd = b.ucode[1][side];
       if (!wy && (cd == 0xFF || !(cd & 3))) continue;
@@ -332,11 +333,11 @@ __device__ __forceinline__ void march_ghosts(const TileD& t, const BoxD& b, cons
 }
 
 // the same for the cells of one column tile (xfaces false: y faces only)
-template <typename T, int DIM>
+template <typename T, int DIM, bool WRAP = false>
 __device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __restrict__ u, bool xfaces = true) {
   const int p0 = DIM == 2 ? t.y0 : t.z0;
-  face_ghosts<T, DIM>(b, u, t.x0, min(TILE_X, b.n[0] - t.x0), DIM == 3 ? t.y0 : 0,
-                      DIM == 3 ? min(TILE3_Y, b.n[1] - t.y0) : 1, p0, min(t.len, b.n[DIM - 1] - p0), xfaces);
+  face_ghosts<T, DIM, WRAP>(b, u, t.x0, min(TILE_X, b.n[0] - t.x0), DIM == 3 ? t.y0 : 0,
+                            DIM == 3 ? min(TILE3_Y, b.n[1] - t.y0) : 1, p0, min(t.len, b.n[DIM - 1] - p0), xfaces);
 }
 
 // OP_RESID : out = f - A u (f == NULL: out = A u); PART: per-tile max |out|
@@ -356,7 +357,7 @@ __device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __
 // a direction that wraps onto the box are read from its other end, so no
 // fill launch is needed before the sweep for them; ghosts of other exchange
 // and interpolated columns still come from memory.
-template <typename T, int DIM, int OP, bool PART>
+template <typename T, int DIM, int OP, bool PART, bool WRAP>
 __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles, int ntiles,
                                                 const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
                                                 const T* u, const T* __restrict__ f, T* __restrict__ out,
@@ -376,10 +377,10 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
     const int nx = min(TILE_X, b.n[0] - t.x0);
     const uint8_t ux0 = b.ucode[0][0], ux1 = b.ucode[0][1];
     const bool xf = (ux0 != 0xFF && (ux0 & 3) && t.x0 == 0) || (ux1 != 0xFF && (ux1 & 3) && t.x0 + nx == b.n[0]) ||
-                    ((b.wrap & 1) && (t.x0 == 0 || t.x0 + nx == b.n[0]));
+                    (WRAP && (b.wrap & 1) && (t.x0 == 0 || t.x0 + nx == b.n[0]));
     const bool yf = DIM == 3 && (t.y0 == 0 || t.y0 + TILE3_Y >= b.n[1]);
     if (xf || yf) {  // block-uniform
-      tile_ghosts<T, DIM>(t, b, const_cast<T*>(u));
+      tile_ghosts<T, DIM, WRAP>(t, b, const_cast<T*>(u));
       __syncthreads();
     }
   }
@@ -391,7 +392,7 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
     int64_t c = C.base + (int64_t)(C.p0 + 2) * sm;
     // the march direction wraps onto the box: its ghosts are the column's
     // planes at the other end, read there (c0: plane 0 of the column)
-    const bool wm = gr && ((b.wrap >> M) & 1);
+    const bool wm = WRAP && gr && ((b.wrap >> M) & 1);
     const int64_t c0 = c - (int64_t)C.p0 * sm;
     T q0 = u[c - 2 * sm], q1 = u[c - sm], q2 = u[c], q3 = u[c + sm];
     if (wm) {
@@ -2358,10 +2359,15 @@ struct MarchK {
   template <int DIM>
   static void go(const TileD* tl, size_t n, const Depth& D, const T* u, const T* f, T* out, T a, T b, T w, int col,
                  double* part, const BoxD* cboxes, hipStream_t st, int gr) {
-    if (sizeof(T) == 4 && OP != OP_RESTRICT)
-      hipLaunchKernelGGL((k_march1<T, DIM, OP, PART>), grid8(n), dim3(DIM == 2 ? 128 : 512), 0, st, tl, (int)n,
-                         D.d_box, D.d_codes, u, f, out, a, b, w, col, part, gr);
-    else
+    if (sizeof(T) == 4 && OP != OP_RESTRICT) {
+      // the form that reads wrapped ghosts only where a box wraps
+      if (gr && D.wrap)
+        hipLaunchKernelGGL((k_march1<T, DIM, OP, PART, true>), grid8(n), dim3(DIM == 2 ? 128 : 512), 0, st, tl,
+                           (int)n, D.d_box, D.d_codes, u, f, out, a, b, w, col, part, gr);
+      else
+        hipLaunchKernelGGL((k_march1<T, DIM, OP, PART, false>), grid8(n), dim3(DIM == 2 ? 128 : 512), 0, st, tl,
+                           (int)n, D.d_box, D.d_codes, u, f, out, a, b, w, col, part, gr);
+    } else
       hipLaunchKernelGGL((k_march<T, DIM, OP, PART>), grid8(n), threads<DIM>(), 0, st, tl, (int)n, D.d_box, D.d_codes,
                          u, f, out, a, b, w, col, part, cboxes, gr, (int64_t)0);
   }

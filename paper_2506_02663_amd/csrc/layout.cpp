@@ -344,9 +344,13 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       D.dn[d] = (int32_t)dn[d];
       D.periodic[d] = per[d];
     }
+    D.wrap = false;
     for (BoxD& X : D.boxd)
       for (int d = 0; d < dim; ++d)
-        if (per[d] && X.n[d] == dn[d]) X.wrap |= (uint8_t)(1 << d);
+        if (per[d] && X.n[d] == dn[d]) {
+          X.wrap |= (uint8_t)(1 << d);
+          D.wrap = true;
+        }
 
     // ---- ghost-column classification ----
     D.faces.assign((size_t)nbk * 6, FaceCols());
