@@ -211,6 +211,7 @@ struct Depth {
   bool fill_only = false;  // every ghost column is filled from its own row (no exchange or interpolated ghosts)
   bool split_rb = false;   // colour-split storage (k_rbs) applies to this depth
   bool wrap = false;       // some box wraps onto itself in a periodic direction (BoxD::wrap)
+  bool wrap_fill = false;  // every face filled uniformly from its own rows (codes 5, 6) or wrapping onto its box
   bool uniform_fill = false;  // every face of every box filled uniformly from its own rows, both ghost layers
   int march = 2;  // cells each tile marches along the last direction
   int32_t dn[3] = {1, 1, 1};  // cells of the grid per direction at this depth

@@ -501,7 +501,7 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, cons
     if (D.stiles.empty()) continue;
     // the FP32 prolongation into depths below the finest forms the coarse
     // ghosts it reads where the coarse faces are filled uniformly
-    const int pgr = (sizeof(T) == 4 && !R.tr && k > 0 && L.depths[k + 1].uniform_fill) ? 1 : 0;
+    const int pgr = (sizeof(T) == 4 && !R.tr && k > 0 && L.depths[k + 1].wrap_fill) ? 1 : 0;
     if (!pgr) launch_fill<T>(L.depths[k + 1], cur[k + 1], nullptr, R.st);
     if constexpr (sizeof(T) == 4) {
       if (k == 0 && fs0) {

@@ -962,17 +962,24 @@ __global__ void __launch_bounds__(256) k_restrict(const TileD* __restrict__ tile
 // Neighbour of coarse cell q (coordinate pd along direction d) on side s
 // (-1, +1); with gr != 0 (the coarse faces filled uniformly from their own
 // rows) a neighbour beyond the box is its first ghost, formed from the row.
-template <typename T>
+// (WRAP: a direction that wraps onto the coarse box takes the coarse cell at
+// the other end of the row instead)
+template <typename T, bool WRAP = false>
 __device__ __forceinline__ T coarse_nb(const T* __restrict__ ec, const BoxD& cb, int64_t q, int d, int pd, int s,
                                        int gr) {
   const int64_t st = d == 0 ? 1 : cb.s[d];
+  if (WRAP && gr && ((cb.wrap >> d) & 1)) {
+    if (s < 0 && pd == 0) return ec[q + (int64_t)(cb.n[d] - 1) * st];
+    if (s > 0 && pd == cb.n[d] - 1) return ec[q - (int64_t)(cb.n[d] - 1) * st];
+    return ec[q + s * st];
+  }
   if (gr && s < 0 && pd == 0) return ghost1<T>(cb.ucode[d][0], ec[q], ec[q + st], ec[q + 2 * st], ec[q + 3 * st]);
   if (gr && s > 0 && pd == cb.n[d] - 1)
     return ghost1<T>(cb.ucode[d][1], ec[q], ec[q - st], ec[q - 2 * st], ec[q - 3 * st]);
   return ec[q + s * st];
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool WRAP = false>
 __global__ void __launch_bounds__(256) k_prolong(const TileD* __restrict__ tiles, int ntiles,
                                                  const BoxD* __restrict__ boxes, const BoxD* __restrict__ cboxes,
                                                  const T* __restrict__ ec, T* __restrict__ u, int gr) {
@@ -981,11 +988,12 @@ __global__ void __launch_bounds__(256) k_prolong(const TileD* __restrict__ tiles
     const BoxD cb = cboxes[b.coarse];
     const int px = C.x >> 1, py = cy >> 1, pz = cz >> 1;
     const int64_t q = cell_index<DIM>(cb, px, py, pz);
-    T common = T(1.0 - DIM * 0.25) * ec[q] + T(0.25) * coarse_nb<T>(ec, cb, q, 1, py, (cy & 1) ? 1 : -1, gr);
-    if (DIM == 3) common += T(0.25) * coarse_nb<T>(ec, cb, q, 2, pz, (cz & 1) ? 1 : -1, gr);
+    T common =
+        T(1.0 - DIM * 0.25) * ec[q] + T(0.25) * coarse_nb<T, WRAP>(ec, cb, q, 1, py, (cy & 1) ? 1 : -1, gr);
+    if (DIM == 3) common += T(0.25) * coarse_nb<T, WRAP>(ec, cb, q, 2, pz, (cz & 1) ? 1 : -1, gr);
     const int64_t c = C.base + (int64_t)(p + 2) * C.sm;
-    u[c] += common + T(0.25) * coarse_nb<T>(ec, cb, q, 0, px, -1, gr);
-    if (C.ok1) u[c + 1] += common + T(0.25) * coarse_nb<T>(ec, cb, q, 0, px, 1, gr);
+    u[c] += common + T(0.25) * coarse_nb<T, WRAP>(ec, cb, q, 0, px, -1, gr);
+    if (C.ok1) u[c + 1] += common + T(0.25) * coarse_nb<T, WRAP>(ec, cb, q, 0, px, 1, gr);
   }
 }
 
@@ -2450,6 +2458,16 @@ template <typename T>
 void launch_prolong(int dim, const Depth& F, const Depth& C, const T* ec, T* u, hipStream_t st, int gr) {
   const size_t n = F.stiles.size();
   if (!n) return;
+  // the wrapped form only where a coarse box wraps onto itself
+  if (gr && C.wrap) {
+    if (dim == 2)
+      hipLaunchKernelGGL((k_prolong<T, 2, true>), grid8(n), threads<2>(), 0, st, F.d_stiles, (int)n, F.d_box, C.d_box,
+                         ec, u, gr);
+    else
+      hipLaunchKernelGGL((k_prolong<T, 3, true>), grid8(n), threads<3>(), 0, st, F.d_stiles, (int)n, F.d_box, C.d_box,
+                         ec, u, gr);
+    return;
+  }
   if (dim == 2)
     hipLaunchKernelGGL((k_prolong<T, 2>), grid8(n), threads<2>(), 0, st, F.d_stiles, (int)n, F.d_box, C.d_box, ec, u,
                        gr);

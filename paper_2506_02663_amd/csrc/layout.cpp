@@ -603,6 +603,12 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       for (int d = 0; d < dim; ++d)
         for (int s = 0; s < 2; ++s)
           if (X.ucode[d][s] != 5 && X.ucode[d][s] != 6) D.uniform_fill = false;
+    D.wrap_fill = D.fill_only;
+    for (const BoxD& X : D.boxd)
+      for (int d = 0; d < dim; ++d)
+        for (int s = 0; s < 2; ++s)
+          if (((X.wrap >> d) & 1) ? X.ucode[d][s] != 0 : (X.ucode[d][s] != 5 && X.ucode[d][s] != 6))
+            D.wrap_fill = false;
     // colour-split storage (depth 0): every face filled uniformly with
     // both layers from its own row (the sweep computes all ghosts it reads),
     // even offsets, row lengths and plane sizes (each aligned pair of
