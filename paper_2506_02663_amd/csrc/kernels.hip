@@ -104,6 +104,24 @@ template <typename T>
 __device__ __forceinline__ void st2(T* p, T a, T b) {
   *reinterpret_cast<Pair<T>*>(p) = Pair<T>{a, b};
 }
+// Non-temporal forms, for the FP64 arrays of a mixed-precision solve that
+// stream through once per cycle (the outer residual's x and f, the fused
+// update's x): kept from displacing the FP32 cycle's iterate and right-hand
+// side in the caches (the 256 MB Infinity Cache holds those at 256^3).
+template <typename T>
+__device__ __forceinline__ Pair<T> ld2nt(const T* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return Pair<T>{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void st2nt(T* p, T a, T b) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 v;
+  v.x = a;
+  v.y = b;
+  __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+}
 
 
 // red-black colour of cell (x, y, z) of a 3D box
@@ -539,6 +557,8 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
     q2 = ld2(u + c);
     q3 = ld2(u + c + sm);
   }
+  // the outer FP64 residual of a mixed solve (FP32 output): x and f stream
+  constexpr bool NT = OP == OP_RESID && sizeof(T) == 8 && sizeof(TO) == 4;
   DiagColumn<T, DIM> d0, d1;
   if (OP == OP_JACOBI || OP == OP_RB) {
     d0.init(b, codes, C.x, C.y, alpha, beta, C.ok);
@@ -548,7 +568,7 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
   double vmax = 0.0, vsum = 0.0;
   T acc = T(0);
   for (int p = C.p0; p < C.p1; ++p, c += sm) {
-    if (has) q4 = ld2(u + c + 2 * sm);
+    if (has) q4 = NT ? ld2nt(u + c + 2 * sm) : ld2(u + c + 2 * sm);
     T La = __shfl_up(q2.a, 1, 64), Lb = __shfl_up(q2.b, 1, 64);
     T Ra = __shfl_down(q2.a, 1, 64), Rb = __shfl_down(q2.b, 1, 64);
     T o0 = T(0), o1 = T(0);
@@ -581,7 +601,7 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
       }
       const T A0 = alpha * q2.a + beta * s0, A1 = alpha * q2.b + beta * s1;
       Pair<T> fv{};
-      if (OP != OP_RESID || f) fv = ld2(f + c);
+      if (OP != OP_RESID || f) fv = NT ? ld2nt(f + c) : ld2(f + c);
       if (OP == OP_RESID || OP == OP_RESTRICT) {
         o0 = f ? fv.a - A0 : A0;
         o1 = f ? fv.b - A1 : A1;
@@ -1221,7 +1241,7 @@ __global__ void __launch_bounds__(256) k_rbs(const TileD* __restrict__ tiles, in
       double* xp = xu + 2 * c;
       const Pair<double> xv = ld2(xp);
       const float ea = par ? o2 : v, eb = par ? v : o2;
-      st2(xp, xv.a + ssc * (double)ea, xv.b + ssc * (double)eb);
+      st2nt(xp, xv.a + ssc * (double)ea, xv.b + ssc * (double)eb);
     } else {
       out[c] = v;
     }
