@@ -374,12 +374,12 @@ int tail_start(const Run& R, const amg_solve_opts& o) {
     const Depth& D = L.depths[k];
     if (D.boxes.size() != 1 || !tail_faces(D, R.dim) || D.stiles.empty() || !D.groups.empty()) break;
     const BoxD& b = D.boxd[0];
-    if ((int64_t)b.n[0] * b.n[1] * b.n[2] > 4096 || K - k > kTailMaxDepths) break;
-    // LDS of both legs: four arrays of depth k, one of depth k + 1
+    if ((int64_t)b.n[0] * b.n[1] * b.n[2] > kTailMaxCells || K - k > kTailMaxDepths) break;
+    // LDS of both legs: two arrays of depth k, one of depth k + 1
     auto padded = [&](const BoxD& x) {
       return (size_t)(x.n[0] + 4) * (x.n[1] + 4) * (R.dim == 3 ? x.n[2] + 4 : 1) * sizeof(float);
     };
-    if (4 * padded(b) + padded(L.depths[k + 1].boxd[0]) > tail_lds_limit()) break;
+    if (2 * padded(b) + padded(L.depths[k + 1].boxd[0]) > tail_lds_limit()) break;
     kt = k;
   }
   return kt;

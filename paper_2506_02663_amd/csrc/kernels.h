@@ -10,6 +10,7 @@ namespace amg {
 // every face filled uniformly or periodic onto the box itself.  e / f: the depth's iterate and right-hand
 // side buffers; cnt: the component's cells at the depth.
 constexpr int kTailMaxDepths = 8;
+constexpr int kTailMaxCells = 4096;  // cells of a tail depth (four per thread of its workgroup)
 struct TailDepth {
   BoxD b;
   float* e;

@@ -9,8 +9,10 @@
 // removal of a singular problem, depth after depth), the existing bottom
 // kernel solves the coarsest system, and one workgroup runs the up-leg
 // (prolongation, post-smoothing).  Each depth's box is staged in LDS with two
-// ghost layers, filled there before every operator application, with a
-// table of its inverse diagonal.  The arithmetic per cell is the tiled
+// ghost layers, filled there before every operator application; each thread
+// keeps the LDS places, inverse diagonals and colours of its (at most four)
+// cells in registers, and a half-sweep computes its new values before it
+// writes them in place.  The arithmetic per cell is the tiled
 // kernels' (the stencil in the same order, the same fills, folded diagonal,
 // prolongation and mean removal), so the two paths agree to the rounding of
 // the diagonal's and the mean's sums.
@@ -61,36 +63,46 @@ struct Lay {
 };
 
 // both ghost layers of every face: from the face rows (uniform fills), or,
-// in a direction that wraps onto the box, the cells at the other end
+// in a direction that wraps onto the box, the cells at the other end.  The
+// faces' rows are spread over all threads at once (a ghost reads only cells
+// of its own row, so the faces are independent).
 template <int DIM>
 __device__ void fill(const Lay<DIM>& L, const BoxD& b, const int32_t* wrap, float* u) {
+  int rows[3];
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
-    const int m1 = L.n[d1], m2 = DIM == 3 ? L.n[d2] : 1;
-    const int st = L.stride(d);
-    for (int side = 0; side < 2; ++side) {
-      const uint8_t cd = b.ucode[d][side];
-      const int in = side ? -st : st;
-      const int far = (L.n[d] - 1) * in;  // from the face cell to the other end of its row
-      const float rm1 = 1.0f / (float)m1;
-      for (int r = (int)threadIdx.x; r < m1 * m2; r += kThreads) {
-        int q[3] = {0, 0, 0};
-        q[d] = side ? L.n[d] - 1 : 0;
-        const int r2 = DIM == 3 ? (int)(((float)r + 0.5f) * rm1) : 0;
-        q[d1] = r - r2 * m1;
-        if (DIM == 3) q[d2] = r2;
-        const int e0 = L.at(q[0], q[1], q[2]);
-        if (wrap[d]) {  // ghost layer g is the cell g from the other end
-          u[e0 - in] = u[e0 + far];
-          u[e0 - 2 * in] = u[e0 + far - in];
-          continue;
-        }
-        const float u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
-        u[e0 - in] = ghost1<float>(cd, u0, u1, u2, u3);
-        u[e0 - 2 * in] = ghost2<float>(cd, u0, u1, u2, u3);
+  for (int d = 0; d < DIM; ++d) rows[d] = L.n[d == 0 ? 1 : 0] * (DIM == 3 ? L.n[d == 2 ? 1 : 2] : 1);
+  const int total = 2 * (rows[0] + rows[1] + (DIM == 3 ? rows[2] : 0));
+  for (int r = (int)threadIdx.x; r < total; r += kThreads) {
+    // face (d, side) and row j of the item
+    int d = 0, j = r;
+#pragma unroll
+    for (int k = 0; k < DIM - 1; ++k)
+      if (d == k && j >= 2 * rows[k]) {
+        j -= 2 * rows[k];
+        d = k + 1;
       }
+    const int side = j >= rows[d] ? 1 : 0;
+    j -= side * rows[d];
+    const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
+    const int m1 = L.n[d1];
+    const int st = L.stride(d);
+    const int in = side ? -st : st;
+    int q[3] = {0, 0, 0};
+    q[d] = side ? L.n[d] - 1 : 0;
+    const int r2 = DIM == 3 ? (int)(((float)j + 0.5f) / (float)m1) : 0;
+    q[d1] = j - r2 * m1;
+    if (DIM == 3) q[d2] = r2;
+    const int e0 = L.at(q[0], q[1], q[2]);
+    if (wrap[d]) {  // ghost layer g is the cell g from the other end
+      const int far = (L.n[d] - 1) * in;  // from the face cell to the other end of its row
+      u[e0 - in] = u[e0 + far];
+      u[e0 - 2 * in] = u[e0 + far - in];
+      continue;
     }
+    const uint8_t cd = b.ucode[d][side];
+    const float u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
+    u[e0 - in] = ghost1<float>(cd, u0, u1, u2, u3);
+    u[e0 - 2 * in] = ghost2<float>(cd, u0, u1, u2, u3);
   }
 }
 
@@ -123,64 +135,80 @@ __device__ int colour(const BoxD& b, int x, int y, int z) {
   return (b.lo[0] + b.lo[1] + (DIM == 3 ? b.lo[2] : 0) + x + y + z) & 1;
 }
 
-// the inverse folded diagonal of every cell into iv (the sweeps' table)
+// The cells a thread owns in a depth: cell i = threadIdx.x + k kThreads,
+// k < kOwn (a tail depth has at most kOwn kThreads cells), with their LDS
+// elements, inverse folded diagonals and colours kept in registers for the
+// depth's sweeps.
+constexpr int kOwn = 4;
+static_assert(kOwn * kThreads >= kTailMaxCells, "a tail depth's cells exceed its workgroup's share");
+
 template <int DIM>
-__device__ void diag_table(const Lay<DIM>& L, const BoxD& b, const TailDepth& D, float* iv) {
-#pragma unroll 4
-  for (int i = (int)threadIdx.x; i < L.cells(); i += kThreads) {
-    int x, y, z;
-    L.cell(i, x, y, z);
-    iv[L.at(x, y, z)] = inv_diag<DIM>(L, b, x, y, z, D.alpha, D.beta);
+struct Own {
+  int e[kOwn];
+  float iv[kOwn];
+  int col[kOwn];  // red-black colour; -1: no cell
+  __device__ Own(const Lay<DIM>& L, const BoxD& b, const TailDepth& D) {
+#pragma unroll
+    for (int k = 0; k < kOwn; ++k) {
+      const int i = (int)threadIdx.x + k * kThreads;
+      e[k] = 0;
+      iv[k] = 0.0f;
+      col[k] = -1;
+      if (i < L.cells()) {
+        int x, y, z;
+        L.cell(i, x, y, z);
+        e[k] = L.at(x, y, z);
+        iv[k] = inv_diag<DIM>(L, b, x, y, z, D.alpha, D.beta);
+        col[k] = colour<DIM>(b, x, y, z);
+      }
+    }
   }
-}
+};
 
 // the first sweep from zero: red-black (colour 0 only) or Jacobi
 template <int DIM>
-__device__ void sweep_zero(const Lay<DIM>& L, const BoxD& b, const float* f, const float* iv, float* u, int rb,
-                           float omega) {
-#pragma unroll 4
-  for (int i = (int)threadIdx.x; i < L.cells(); i += kThreads) {
-    int x, y, z;
-    L.cell(i, x, y, z);
-    const int e = L.at(x, y, z);
-    u[e] = (!rb || colour<DIM>(b, x, y, z) == 0) ? omega * f[e] * iv[e] : 0.0f;
-  }
+__device__ void sweep_zero(const Own<DIM>& W, const float* f, float* u, int rb, float omega) {
+#pragma unroll
+  for (int k = 0; k < kOwn; ++k)
+    if (W.col[k] >= 0) u[W.e[k]] = (!rb || W.col[k] == 0) ? omega * f[W.e[k]] * W.iv[k] : 0.0f;
 }
 
-// one red-black half-sweep of colour col (col < 0: a Jacobi sweep), u -> o
+// one red-black half-sweep of colour col (col < 0: a Jacobi sweep) in
+// place: every new value is computed from the old iterate first, then
+// written (the same values as a sweep from u into a second buffer)
 template <int DIM>
-__device__ void sweep(const Lay<DIM>& L, const BoxD& b, const TailDepth& D, const float* f, const float* iv,
-                      const float* u, float* o, int col, float omega) {
-#pragma unroll 4
-  for (int i = (int)threadIdx.x; i < L.cells(); i += kThreads) {
-    int x, y, z;
-    L.cell(i, x, y, z);
-    const int e = L.at(x, y, z);
-    if (col < 0 || colour<DIM>(b, x, y, z) == col) {
+__device__ void sweep(const Lay<DIM>& L, const Own<DIM>& W, const TailDepth& D, const float* f, float* u, int col,
+                      float omega) {
+  float nv[kOwn];
+#pragma unroll
+  for (int k = 0; k < kOwn; ++k) {
+    nv[k] = 0.0f;
+    if (W.col[k] >= 0 && (col < 0 || W.col[k] == col)) {
+      const int e = W.e[k];
       const float Au = apply<DIM>(L, u, e, D.alpha, D.beta);
-      o[e] = u[e] + omega * (f[e] - Au) * iv[e];
-    } else {
-      o[e] = u[e];
+      nv[k] = u[e] + omega * (f[e] - Au) * W.iv[k];
     }
   }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kOwn; ++k)
+    if (W.col[k] >= 0 && (col < 0 || W.col[k] == col)) u[W.e[k]] = nv[k];
 }
 
-// nsw sweeps on (u, o) from the iterate in u (from zero: u is written
-// first); iv: the depth's inverse diagonals; returns the buffer that holds
-// the result
+// nsw sweeps on u in place (from zero: u is written first)
 template <int DIM>
-__device__ float* smooth(const Lay<DIM>& L, const BoxD& b, const TailDepth& D, const float* f, const float* iv,
-                         float* u, float* o, int nsw, bool from_zero, int rb, float omega) {
+__device__ void smooth(const Lay<DIM>& L, const BoxD& b, const TailDepth& D, const Own<DIM>& W, const float* f,
+                       float* u, int nsw, bool from_zero, int rb, float omega) {
   if (nsw <= 0) {
     if (from_zero) {
       for (int i = (int)threadIdx.x; i < L.padded(); i += kThreads) u[i] = 0.0f;
       __syncthreads();
     }
-    return u;
+    return;
   }
   int h = 0;
   if (from_zero) {
-    sweep_zero<DIM>(L, b, f, iv, u, rb, omega);
+    sweep_zero<DIM>(W, f, u, rb, omega);
     __syncthreads();
     h = 1;
   }
@@ -188,13 +216,9 @@ __device__ float* smooth(const Lay<DIM>& L, const BoxD& b, const TailDepth& D, c
   for (; h < nh; ++h) {
     fill<DIM>(L, b, D.wrap, u);
     __syncthreads();
-    sweep<DIM>(L, b, D, f, iv, u, o, rb ? (h & 1) : -1, omega);
+    sweep<DIM>(L, W, D, f, u, rb ? (h & 1) : -1, omega);
     __syncthreads();
-    float* t = u;
-    u = o;
-    o = t;
   }
-  return u;
 }
 
 template <int DIM>
@@ -219,8 +243,8 @@ __device__ void store(const Lay<DIM>& L, const BoxD& b, const float* s, float* _
 
 // Down-leg: depth d[0] .. d[nd-2] pre-smoothed from zero, each restricted
 // into the next; the smoothed iterates and the restricted right-hand sides
-// are written to the depths' buffers (e, f).  LDS: u, o, f of the first
-// depth and the next depth's f, alternating.
+// are written to the depths' buffers (e, f).  LDS: the iterate u of the
+// depth and the right-hand sides of the depth and the next, alternating.
 template <int DIM>
 __global__ void __launch_bounds__(kThreads) k_tail_down(TailArgs A) {
   extern __shared__ float lds[];
@@ -228,9 +252,7 @@ __global__ void __launch_bounds__(kThreads) k_tail_down(TailArgs A) {
   __shared__ double mean;
   const Lay<DIM> L0(A.d[0].b);
   float* U = lds;
-  float* O = U + L0.padded();
-  float* IV = O + L0.padded();
-  float* F[2] = {IV + L0.padded(), IV + 2 * L0.padded()};
+  float* F[2] = {U + L0.padded(), U + 2 * L0.padded()};  // F[1] holds odd depths (at most d[1]'s size)
   load<DIM>(L0, A.d[0].b, A.d[0].f, F[0]);
   for (int k = 0; k + 1 < A.nd; ++k) {
     const TailDepth& D = A.d[k];
@@ -238,9 +260,10 @@ __global__ void __launch_bounds__(kThreads) k_tail_down(TailArgs A) {
     const Lay<DIM> L(D.b), Lc(C.b);
     const float* f = F[k & 1];
     float* fc = F[(k + 1) & 1];
-    diag_table<DIM>(L, D.b, D, IV);
-    __syncthreads();
-    float* u = smooth<DIM>(L, D.b, D, f, IV, U, O, A.nu1, true, A.rb, A.omega);
+    const Own<DIM> W(L, D.b, D);
+    __syncthreads();  // the first depth's right-hand side loaded
+    float* u = U;
+    smooth<DIM>(L, D.b, D, W, f, u, A.nu1, true, A.rb, A.omega);
     store<DIM>(L, D.b, u, D.e);
     fill<DIM>(L, D.b, D.wrap, u);
     __syncthreads();
@@ -285,16 +308,14 @@ __global__ void __launch_bounds__(kThreads) k_tail_down(TailArgs A) {
 // Up-leg: from the bottom's solution (in d[nd-1].e), for depth nd-2 .. 0:
 // the iterate saved by the down-leg, plus the prolonged correction, then
 // post-smoothing; the result of depth 0 goes to its buffer e.  LDS: the
-// coarse correction, then u, o, f of the depth.
+// coarse correction, then u and f of the depth.
 template <int DIM>
 __global__ void __launch_bounds__(kThreads) k_tail_up(TailArgs A) {
   extern __shared__ float lds[];
   const Lay<DIM> L0(A.d[0].b), L1(A.d[1].b);
   float* Cb = lds;                // coarse correction (at most the second depth's size)
   float* U = Cb + L1.padded();
-  float* O = U + L0.padded();
-  float* F = O + L0.padded();
-  float* IV = F + L0.padded();
+  float* F = U + L0.padded();
   {
     const TailDepth& B = A.d[A.nd - 1];
     load<DIM>(Lay<DIM>(B.b), B.b, B.e, Cb);
@@ -306,12 +327,12 @@ __global__ void __launch_bounds__(kThreads) k_tail_up(TailArgs A) {
     const Lay<DIM> L(D.b), Lc(C.b);
     load<DIM>(L, D.b, D.e, U);
     load<DIM>(L, D.b, D.f, F);
-    diag_table<DIM>(L, D.b, D, IV);
+    const Own<DIM> W(L, D.b, D);
     fill<DIM>(Lc, C.b, C.wrap, Cb);
     __syncthreads();
     // u += (1 - D/4) e_P + 1/4 sum_d e_(P + s_d e_d), s_d the child's side
-  #pragma unroll 4
-  for (int i = (int)threadIdx.x; i < L.cells(); i += kThreads) {
+#pragma unroll 4
+    for (int i = (int)threadIdx.x; i < L.cells(); i += kThreads) {
       int x, y, z;
       L.cell(i, x, y, z);
       const int q = Lc.at(x >> 1, y >> 1, z >> 1);
@@ -320,11 +341,11 @@ __global__ void __launch_bounds__(kThreads) k_tail_up(TailArgs A) {
       U[L.at(x, y, z)] += common + 0.25f * Cb[q + ((x & 1) ? 1 : -1)];
     }
     __syncthreads();
-    float* u = smooth<DIM>(L, D.b, D, F, IV, U, O, A.nu2, false, A.rb, A.omega);
+    smooth<DIM>(L, D.b, D, W, F, U, A.nu2, false, A.rb, A.omega);
     if (k == 0) {
-      store<DIM>(L, D.b, u, D.e);
+      store<DIM>(L, D.b, U, D.e);
     } else {
-      for (int i = (int)threadIdx.x; i < L.padded(); i += kThreads) Cb[i] = u[i];
+      for (int i = (int)threadIdx.x; i < L.padded(); i += kThreads) Cb[i] = U[i];
       __syncthreads();
     }
   }
@@ -336,7 +357,7 @@ size_t tail_lds_bytes(int dim, const TailArgs& A) {
   auto padded = [&](const BoxD& b) {
     return (size_t)(b.n[0] + 4) * (b.n[1] + 4) * (dim == 3 ? b.n[2] + 4 : 1);
   };
-  return (4 * padded(A.d[0].b) + padded(A.d[1].b)) * sizeof(float);
+  return (2 * padded(A.d[0].b) + padded(A.d[1].b)) * sizeof(float);
 }
 
 size_t tail_lds_limit() {
