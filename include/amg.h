@@ -592,7 +592,27 @@ int amg_cic_face_data(amg_hier* h, int level, const double* const* coarse, doubl
 int amg_cic_correct(amg_hier* h, int level, double* const* face_data, double* delta, void* stream);
 
 /* ---- the IMEX time step on one periodic level (Section 4) -------------------
- * One step of eq. GePUP-IMEX with the ERK-ESDIRK pair ARK4(3)6L[2]SA of
+ * The convection operator and one time step on a periodic box. */
+
+/* out[d] = (Div<uu>)_d, the convection of eq. convOp: per direction the
+ * difference across the cell of the face averages of the product u_d u_e,
+ * each the product of the face averages (eq. cell2face) plus h^2/12 times
+ * the products of their centred transverse differences.  h: one level of
+ * one box on a grid periodic in every direction (neighbours wrap; ghosts
+ * are not read).  u[d], out[d]: packed FP64 level buffers, out not aliasing
+ * u; only cells are written.  Errors: AMG_EINVAL (null), AMG_EUNSUPPORTED
+ * (layout). */
+int amg_convection(amg_hier* h, double* const* u, double* const* out, void* stream);
+
+typedef struct {
+  int32_t solves;           /* linear solves run (TLS-1, TLS-2 per component, TLS-3) */
+  int32_t cycles;           /* outer cycles over all of them */
+  int32_t max_cycles;       /* most cycles of one solve */
+  int32_t converged;        /* 1 if every solve converged */
+  double max_rel_residual;  /* max over the solves of ||r||_inf / ||b||_inf at return */
+} amg_imex_stats;
+
+/* One step of eq. GePUP-IMEX with the ERK-ESDIRK pair ARK4(3)6L[2]SA of
  * Kennedy and Carpenter (2003, the scheme the paper cites; six stages,
  * gamma = 1/4, stiffly accurate) for the system eq. ODE-MOL on a level that
  * is one box covering a grid periodic in every direction (the domains of
@@ -609,33 +629,18 @@ int amg_cic_correct(amg_hier* h, int level, double* const* face_data, double* de
  * level buffers, u^n on entry (taken as w^n), u^(n+1) on return.  g: NULL
  * (no forcing) or g[j*dim+d], the forcing's cell averages at t_n + c_j dt,
  * j = 0..5 (c = 0, 1/2, 83/250, 31/50, 17/20, 1).  opts: every linear
- * solve, each from a zero initial guess (its stopping test is then
- * relative to its right-hand side).
- * The library keeps (15 dim + 4) level buffers of stage storage in hv,
- * allocated on the first call.  Not graph-capturable (it allocates on its
+ * solve.  Each stage system starts from the previous stage's solution of
+ * the same system (the pressure and the potential from zero at the first
+ * stage, the velocity from w^n) and stops when ||r||_inf <= max(tol_rel
+ * ||b||_inf, tol_abs), b its right-hand side: the test of a solve from
+ * zero, whose initial residual is b.
+ * The library keeps (15 dim + 4) level buffers of stage storage and one
+ * word in hv, allocated on the first call.  Not graph-capturable (it allocates on its
  * first call and the solves synchronise).  Errors: AMG_EINVAL (null
  * argument, dt <= 0, nu < 0, operators or layouts that differ),
  * AMG_EUNSUPPORTED (not one periodic box on one level), errors of the
  * solves; AMG_ENOTCONVERGED if a solve did not converge (u still holds the
  * step's result). */
-/* out[d] = (Div<uu>)_d, the convection of eq. convOp: per direction the
- * difference across the cell of the face averages of the product u_d u_e,
- * each the product of the face averages (eq. cell2face) plus h^2/12 times
- * the products of their centred transverse differences.  h: one level of
- * one box on a grid periodic in every direction (neighbours wrap; ghosts
- * are not read).  u[d], out[d]: packed FP64 level buffers, out not aliasing
- * u; only cells are written.  Errors: AMG_EINVAL (null), AMG_EUNSUPPORTED
- * (layout). */
-int amg_convection(amg_hier* h, double* const* u, double* const* out, void* stream);
-
-typedef struct {
-  int32_t solves;           /* linear solves run (TLS-1, TLS-2 per component, TLS-3) */
-  int32_t cycles;           /* outer cycles over all of them */
-  int32_t max_cycles;       /* most cycles of one solve */
-  int32_t converged;        /* 1 if every solve converged */
-  double max_rel_residual;  /* max over the solves of ||r||/||r0|| at return */
-} amg_imex_stats;
-
 int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, double* const* u, const double* const* g,
                   const amg_solve_opts* opts, amg_imex_stats* stats, void* stream);
 

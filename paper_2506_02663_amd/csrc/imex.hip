@@ -10,6 +10,7 @@
 // indices on the one box: no ghosts) and the stage combinations.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <initializer_list>
@@ -134,6 +135,33 @@ __global__ __launch_bounds__(256) void k_combo(Geo G, double* dst, Combo cb) {
   dst[o] = s;
 }
 
+// *out = max over the cells of |v| (out cleared by the caller): per block a
+// max over its cells, then one atomic max on the bit pattern, which orders
+// non-negative doubles (a NaN, positive, lands above infinity)
+__global__ __launch_bounds__(256) void k_maxabs(Geo G, const double* v, unsigned long long* out) {
+  __shared__ double sh[4];
+  const int64_t cells = (int64_t)G.n[0] * G.n[1] * G.n[2];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double m = 0.0;
+  if (i < cells) {
+    const int x = (int)(i % G.n[0]);
+    const int y = (int)((i / G.n[0]) % G.n[1]);
+    const int z = (int)(i / ((int64_t)G.n[0] * G.n[1]));
+    const double a = fabs(v[G.off + (x + 2) + (int64_t)(y + 2) * G.s1 + (int64_t)(z + 2) * G.s2]);
+    m = (a == a) ? a : __longlong_as_double(0x7ff8000000000000LL);
+  }
+  for (int k = 32; k > 0; k >>= 1) {
+    const double o = __shfl_xor(m, k, 64);
+    m = (o > m || o != o) ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = (sh[w] > m || sh[w] != sh[w]) ? sh[w] : m;
+    atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
 int fail(amg_hier* H, int code, const std::string& msg) {
   if (H) H->err = msg;
   return code;
@@ -224,9 +252,10 @@ extern "C" int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, d
   if (N != hp->levels[0].depths[0].nstored) return fail(H, AMG_EINVAL, "the two hierarchies differ");
 
   // workspace: w^n, w, the stage terms X_j and L w^(j), V, G q (D arrays
-  // each), q, phi, the divergence and the stage right-hand side
+  // each), q, phi, the divergence and the stage right-hand side; one word
+  // for the norm of a right-hand side
   const int narr = D * (1 + 1 + kStages + (kStages - 1) + 1 + 1) + 4;
-  const int64_t need = (int64_t)narr * N;
+  const int64_t need = (int64_t)narr * N + 1;
   if (hv->imex_len < need) {
     if (hv->imex_ws) (void)hipFree(hv->imex_ws);
     hv->imex_ws = nullptr;
@@ -253,20 +282,60 @@ extern "C" int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, d
   double* phi = take();
   double* div = take();
   double* rhs = take();
+  unsigned long long* dnorm = reinterpret_cast<unsigned long long*>(ws + (int64_t)narr * N);
 
   const int64_t cells = (int64_t)G.n[0] * G.n[1] * G.n[2];
   const dim3 grid((unsigned)((cells + 255) / 256)), block(256);
   int worst = AMG_OK;
-  auto account = [&](int rc, const amg_solve_stats& s) -> int {
+  // ||b||_inf over the cells (one small reduction and a wait for it)
+  auto rhs_norm = [&](const double* b, double& out) -> int {
+    if (hipMemsetAsync(dnorm, 0, sizeof *dnorm, st) != hipSuccess) return fail(H, AMG_EDEVICE, "norm clear failed");
+    hipLaunchKernelGGL(k_maxabs, grid, block, 0, st, G, b, dnorm);
+    if (hipGetLastError() != hipSuccess) return fail(H, AMG_EDEVICE, "k_maxabs launch failed");
+    unsigned long long bits = 0;
+    if (hipMemcpyAsync(&bits, dnorm, sizeof bits, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return fail(H, AMG_EDEVICE, "norm read failed");
+    memcpy(&out, &bits, sizeof out);
+    return AMG_OK;
+  };
+  // Every stage system starts from the previous stage's solution of the
+  // same system and stops when ||r||_inf <= max(tol_rel ||b||_inf, tol_abs),
+  // b its right-hand side: the test of a solve from zero, whose initial
+  // residual is b.  A zero b has the zero solution (no solve).
+  auto target_opts = [&](double bn, amg_solve_opts& o2) {
+    o2 = *opts;
+    o2.tol_abs = std::max(opts->tol_abs, opts->tol_rel * bn);
+    o2.tol_rel = 0.0;
+  };
+  auto account = [&](int rc, const amg_solve_stats& s, double bn) -> int {
     if (rc != AMG_OK && rc != AMG_ENOTCONVERGED) return rc;
     if (rc == AMG_ENOTCONVERGED) worst = AMG_ENOTCONVERGED;
     if (stats) {
       stats->solves += 1;
       stats->cycles += s.cycles;
       if (s.cycles > stats->max_cycles) stats->max_cycles = s.cycles;
-      const double rel = s.r0 > 0 ? s.rfinal / s.r0 : 0.0;
+      const double rel = bn > 0 ? s.rfinal / bn : 0.0;
       if (rel > stats->max_rel_residual) stats->max_rel_residual = rel;
     }
+    return AMG_OK;
+  };
+  // the solve of (hier) x = b from the x it holds
+  auto stage_solve = [&](amg_hier* hs, double* x, const double* b, const char* what) -> int {
+    double bn = 0.0;
+    int rc = rhs_norm(b, bn);
+    if (rc) return rc;
+    if (bn == 0.0) {
+      if (hipMemsetAsync(x, 0, N * sizeof(double), st) != hipSuccess) return fail(H, AMG_EDEVICE, "clear failed");
+      amg_solve_stats s0;
+      memset(&s0, 0, sizeof s0);
+      return account(AMG_OK, s0, 0.0);
+    }
+    amg_solve_opts o2;
+    target_opts(bn, o2);
+    amg_solve_stats s;
+    rc = account(amg_solve(hs, 0, 0, &x, &b, nullptr, &o2, &s, st), s, bn);
+    if (rc) return fail(H, rc, std::string(what) + amg_last_error(hs));
     return AMG_OK;
   };
   auto combo = [&](double* dst, std::initializer_list<std::pair<const double*, double>> terms) -> int {
@@ -295,29 +364,35 @@ extern "C" int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, d
     if (hipGetLastError() != hipSuccess) return fail(H, AMG_EDEVICE, "k_conv launch failed");
     int rc = amg_divergence(hv, 0, 0, V, nullptr, &div, st);
     if (rc) return rc;
-    if (hipMemsetAsync(q, 0, N * sizeof(double), st) != hipSuccess)
-      return fail(H, AMG_EDEVICE, "clearing the pressure failed");
-    amg_solve_stats s;
-    rc = account(amg_solve(hp, 0, 0, &q, (const double* const*)&div, nullptr, opts, &s, st), s);
-    if (rc) return fail(H, rc, std::string("pressure solve: ") + amg_last_error(hp));
+    if ((rc = stage_solve(hp, q, div, "pressure solve: "))) return rc;
     rc = amg_gradient(hp, 0, 0, &q, nullptr, gq, st);
     if (rc) return fail(H, rc, std::string("pressure gradient: ") + amg_last_error(hp));
     for (int e = 0; e < D; ++e)
       if ((rc = combo(Xs[j][e], {{V[e], 1.0}, {gq[e], -1.0}}))) return rc;
     return AMG_OK;
   };
+  // u = P w, the potential from the previous projection's (D w: the norm of
+  // the potential's right-hand side; zero: u = w)
   auto project = [&]() -> int {
     double* wl[3] = {w[0], w[1], D == 3 ? w[2] : nullptr};
-    if (hipMemsetAsync(phi, 0, N * sizeof(double), st) != hipSuccess)
+    int rc = amg_divergence(hv, 0, 0, wl, nullptr, &div, st);
+    if (rc) return rc;
+    double bn = 0.0;
+    if ((rc = rhs_norm(div, bn))) return rc;
+    if (bn == 0.0 && hipMemsetAsync(phi, 0, N * sizeof(double), st) != hipSuccess)
       return fail(H, AMG_EDEVICE, "clearing the potential failed");
+    amg_solve_opts o2;
+    target_opts(bn, o2);
     amg_solve_stats s;
-    int rc = account(amg_project(hv, hp, 0, 0, wl, nullptr, &phi, u, opts, &s, st), s);
+    rc = account(amg_project(hv, hp, 0, 0, wl, nullptr, &phi, u, &o2, &s, st), s, bn);
     if (rc) return fail(H, rc, std::string("projection: ") + amg_last_error(hp));
     return AMG_OK;
   };
 
-  // stage 1: w = u = w^n; every solve starts from zero, so its stopping
-  // test is relative to its right-hand side
+  // stage 1: w = u = w^n; the pressure and the potential start from zero
+  if (hipMemsetAsync(q, 0, N * sizeof(double), st) != hipSuccess ||
+      hipMemsetAsync(phi, 0, N * sizeof(double), st) != hipSuccess)
+    return fail(H, AMG_EDEVICE, "clearing the pressure failed");
   for (int e = 0; e < D; ++e) {
     if (hipMemcpyAsync(wn[e], u[e], N * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
         hipMemcpyAsync(w[e], u[e], N * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
@@ -347,12 +422,8 @@ extern "C" int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, d
       if (c > 0) {
         hipLaunchKernelGGL(k_combo, grid, block, 0, st, G, rhs, cb);
         if (hipGetLastError() != hipSuccess) return fail(H, AMG_EDEVICE, "k_combo launch failed");
-        // (I - c L) w^(s) = rhs from a zero initial guess
-        if (hipMemsetAsync(w[e], 0, N * sizeof(double), st) != hipSuccess)
-          return fail(H, AMG_EDEVICE, "clearing the stage velocity failed");
-        amg_solve_stats so;
-        rc = account(amg_solve(hv, 0, 0, &w[e], (const double* const*)&rhs, nullptr, opts, &so, st), so);
-        if (rc) return fail(H, rc, std::string("Helmholtz solve: ") + amg_last_error(hv));
+        // (I - c L) w^(s) = rhs from w^(s-1)
+        if ((rc = stage_solve(hv, w[e], rhs, "Helmholtz solve: "))) return rc;
       } else {  // nu = 0: the stage system is the identity
         hipLaunchKernelGGL(k_combo, grid, block, 0, st, G, w[e], cb);
         if (hipGetLastError() != hipSuccess) return fail(H, AMG_EDEVICE, "k_combo launch failed");
