@@ -51,7 +51,8 @@ def parse():
                    help="single-level workloads: this tile march length instead of the autotuner's choice")
     p.add_argument("--nu", default=None,
                    help="pre,post smoothing steps of the V-cycle (default: 1,3 for the 3D single level, "
-                        "whose 1e-10 solve it reaches fastest of V(0..2, 1..4); 2,2 otherwise)")
+                        "whose 1e-10 solve it reaches fastest of V(0..2, 1..4), and for the IMEX step; "
+                        "2,2 otherwise)")
     p.add_argument("--no-split", action="store_true",
                    help="3D mixed precision: keep the finest depth in interleaved storage during post-smoothing")
     p.add_argument("--no-tail", action="store_true",
@@ -617,8 +618,14 @@ def bench_imex(args):
                 "sample": f"one IMEX step of the same flow on 64^2 cells, {el:.1f} s"}
     prec = A.MIXED if args.precision == "mixed" else A.FP64
     sm = A.SMOOTH_JACOBI if args.smoother == "jacobi" else A.SMOOTH_RB
-    opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100,
-                          use_graph=0 if args.no_graph else 1)
+    # the velocity's Helmholtz systems with plain red-black, the pressure and
+    # projection systems over-relaxed
+    w_rb = dict(zip(("helmholtz", "poisson"), map(float, args.omega_rb.split(","))))
+    nu1, nu2 = map(int, (args.nu or "1,3").split(","))
+    opts = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100, nu1=nu1, nu2=nu2,
+                          use_graph=0 if args.no_graph else 1, omega_rb=w_rb["helmholtz"])
+    opts_p = A.default_opts(precision=prec, smoother=sm, tol_rel=1e-10, max_cycles=100, nu1=nu1, nu2=nu2,
+                            use_graph=0 if args.no_graph else 1, omega_rb=w_rb["poisson"])
     hs = []
     for op in (A.HELMHOLTZ, A.POISSON):
         H = A.Hierarchy(2, (n, n), h, 1)
@@ -641,7 +648,7 @@ def bench_imex(args):
     def step():
         for t, t0_ in zip(us, u0):
             t.copy_(t0_)
-        st = A.imex_step(Hv, Hp, dt, nu, us, None, opts)
+        st = A.imex_step(Hv, Hp, dt, nu, us, None, opts, opts_p)
         if st["status"] != 0 or not st["converged"]:
             raise RuntimeError(f"IMEX step failed: {st}")
         stats.update(st)
@@ -661,7 +668,8 @@ def bench_imex(args):
         "vs_baseline": None, "dtype": "f32-in-f64" if prec == A.MIXED else "f64", "data": "synthetic",
         "config": {"workload": f"four-way vortex merging, periodic {n}^2, Re 1000, Cr 0.5, one IMEX step",
                    "dt": dt, "solves": stats.get("solves"), "cycles": stats.get("cycles"),
-                   "max_cycles": stats.get("max_cycles"), "precision": args.precision, "smoother": args.smoother},
+                   "max_cycles": stats.get("max_cycles"), "precision": args.precision, "smoother": args.smoother,
+                   "vcycle": f"V({nu1},{nu2})", "omega_rb": w_rb},
     }
     if base is not None:
         out["cpu_baseline"] = base

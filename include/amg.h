@@ -628,8 +628,9 @@ typedef struct {
  * box; both one level, periodic in every direction.  u[d]: packed FP64
  * level buffers, u^n on entry (taken as w^n), u^(n+1) on return.  g: NULL
  * (no forcing) or g[j*dim+d], the forcing's cell averages at t_n + c_j dt,
- * j = 0..5 (c = 0, 1/2, 83/250, 31/50, 17/20, 1).  opts: every linear
- * solve.  Each stage system starts from the previous stage's solution of
+ * j = 0..5 (c = 0, 1/2, 83/250, 31/50, 17/20, 1).  opts: the Helmholtz
+ * solves; opts_p: the Poisson solves of the pressure and the projection
+ * (NULL: opts).  Each stage system starts from the previous stage's solution of
  * the same system (the pressure and the potential from zero at the first
  * stage, the velocity from w^n) and stops when ||r||_inf <= max(tol_rel
  * ||b||_inf, tol_abs), b its right-hand side: the test of a solve from
@@ -642,7 +643,7 @@ typedef struct {
  * solves; AMG_ENOTCONVERGED if a solve did not converge (u still holds the
  * step's result). */
 int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, double* const* u, const double* const* g,
-                  const amg_solve_opts* opts, amg_imex_stats* stats, void* stream);
+                  const amg_solve_opts* opts, const amg_solve_opts* opts_p, amg_imex_stats* stats, void* stream);
 
 /* ---- regridding and data migration (Section 5.4, RDM-1..4) -----------------
  * Clustering (RDM-2), as read from Berger and Rigoutsos (1991): a box is

@@ -134,7 +134,8 @@ def lib():
         L.amg_divergence_transpose.argtypes = [vp, i32, i32, pp, pp, vp]
         L.amg_project_adjoint.argtypes = [vp, vp, i32, i32, pp, pp, pp, C.POINTER(SolveOpts), C.POINTER(SolveStats),
                                           vp]
-        L.amg_imex_step.argtypes = [vp, vp, dbl, dbl, pp, pp, C.POINTER(SolveOpts), C.POINTER(ImexStats), vp]
+        L.amg_imex_step.argtypes = [vp, vp, dbl, dbl, pp, pp, C.POINTER(SolveOpts), C.POINTER(SolveOpts),
+                                    C.POINTER(ImexStats), vp]
         L.amg_convection.argtypes = [vp, pp, pp, vp]
         i32p = C.POINTER(C.c_int32)
         L.amg_cluster.argtypes = [i32, i32p, C.POINTER(C.c_uint8), dbl, i32, i32, i32p, i32p, i32p]
@@ -694,10 +695,11 @@ def project(Hw, Hp, ws, phis, us, wbs=None, opts=None, lev_lo=0):
     return out
 
 
-def imex_step(Hv, Hp, dt, nu, us, gs=None, opts=None):
+def imex_step(Hv, Hp, dt, nu, us, gs=None, opts=None, opts_p=None):
     """One step of eq. GePUP-IMEX on one periodic box (see amg_imex_step):
     us[d] holds u^n on entry and u^(n+1) on return; gs: None or gs[j][d],
-    the forcing at t_n + IMEX_C[j] dt.  Returns the stats and status."""
+    the forcing at t_n + IMEX_C[j] dt; opts: the Helmholtz solves, opts_p:
+    the Poisson solves (None: opts).  Returns the stats and status."""
     import torch
     arr = Hv._comp_ptrs(0, [us])
     g = None
@@ -710,8 +712,9 @@ def imex_step(Hv, Hp, dt, nu, us, gs=None, opts=None):
                 Hv._need(per[d], 0, 0, "forcing", (torch.float64,))
                 g[j * Hv.dim + d] = per[d].data_ptr()
     o = opts or default_opts()
+    op = C.byref(opts_p) if opts_p is not None else None
     st = ImexStats()
-    rc = lib().amg_imex_step(Hv.h, Hp.h, float(dt), float(nu), arr, g, C.byref(o), C.byref(st), _stream())
+    rc = lib().amg_imex_step(Hv.h, Hp.h, float(dt), float(nu), arr, g, C.byref(o), op, C.byref(st), _stream())
     if rc and rc != ENOTCONVERGED:
         Hv._check(rc)
     out = st.as_dict()

@@ -218,12 +218,14 @@ extern "C" int amg_convection(amg_hier* h, double* const* u, double* const* out,
 }
 
 extern "C" int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, double* const* u,
-                             const double* const* g, const amg_solve_opts* opts, amg_imex_stats* stats,
+                             const double* const* g, const amg_solve_opts* opts,
+                             const amg_solve_opts* opts_p, amg_imex_stats* stats,
                              void* stream) {
   amg_hier* H = hv;
   if (!hv || !hp) return AMG_EINVAL;
   if (stats) memset(stats, 0, sizeof *stats);
   if (!u || !opts) return fail(H, AMG_EINVAL, "null argument");
+  if (!opts_p) opts_p = opts;
   for (int d = 0; d < hv->dim; ++d)
     if (!u[d]) return fail(H, AMG_EINVAL, "null velocity component");
   if (!(dt > 0) || !(nu >= 0) || !std::isfinite(dt) || !std::isfinite(nu))
@@ -303,9 +305,9 @@ extern "C" int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, d
   // same system and stops when ||r||_inf <= max(tol_rel ||b||_inf, tol_abs),
   // b its right-hand side: the test of a solve from zero, whose initial
   // residual is b.  A zero b has the zero solution (no solve).
-  auto target_opts = [&](double bn, amg_solve_opts& o2) {
-    o2 = *opts;
-    o2.tol_abs = std::max(opts->tol_abs, opts->tol_rel * bn);
+  auto target_opts = [&](const amg_solve_opts* base, double bn, amg_solve_opts& o2) {
+    o2 = *base;
+    o2.tol_abs = std::max(base->tol_abs, base->tol_rel * bn);
     o2.tol_rel = 0.0;
   };
   auto account = [&](int rc, const amg_solve_stats& s, double bn) -> int {
@@ -332,7 +334,7 @@ extern "C" int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, d
       return account(AMG_OK, s0, 0.0);
     }
     amg_solve_opts o2;
-    target_opts(bn, o2);
+    target_opts(hs == hp ? opts_p : opts, bn, o2);
     amg_solve_stats s;
     rc = account(amg_solve(hs, 0, 0, &x, &b, nullptr, &o2, &s, st), s, bn);
     if (rc) return fail(H, rc, std::string(what) + amg_last_error(hs));
@@ -382,7 +384,7 @@ extern "C" int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, d
     if (bn == 0.0 && hipMemsetAsync(phi, 0, N * sizeof(double), st) != hipSuccess)
       return fail(H, AMG_EDEVICE, "clearing the potential failed");
     amg_solve_opts o2;
-    target_opts(bn, o2);
+    target_opts(opts_p, bn, o2);
     amg_solve_stats s;
     rc = account(amg_project(hv, hp, 0, 0, wl, nullptr, &phi, u, &o2, &s, st), s, bn);
     if (rc) return fail(H, rc, std::string("projection: ") + amg_last_error(hp));
