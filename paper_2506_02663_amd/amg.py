@@ -78,6 +78,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libamg.so is not built: run __graft_entry__.build() (hipcc, gfx950)")
+        # torch first: its HIP runtime (same soname) then serves the library
+        # too, so the process holds one runtime whichever module loads first
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i32, dbl = C.c_void_p, C.c_int, C.c_double
         L.amg_create.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32), i32, i32,
