@@ -27,6 +27,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <immintrin.h>
 #include <map>
 #include <string>
 #include <thread>
@@ -100,51 +101,215 @@ struct SpinBarrier {
 };
 
 // In-place Gauss-Jordan with partial pivoting of the row-major n x n matrix
-// A into its inverse; false if A is singular.  `threads` > 1 splits each
-// column's row updates over that many threads (the pivot step runs on the
-// first); every row's arithmetic is the same in any split.  Columns of A up
-// to the current one are never read again, so only those right of it are
-// updated.
+// c[i][0..m) -= sum_q a[i][q] B[q][0..m) for R rows at once (B rows ldb
+// apart): eight columns of each row accumulate in registers over q, so every
+// element of B loaded serves R rows.  An AVX2 form where the host has it.
+template <int R>
+void rows_update_plain(double* const* c, const double* const* a, const double* __restrict__ B, int b, size_t ldb,
+                       int m) {
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < R; ++i) {
+      double s = c[i][j];
+      for (int q = 0; q < b; ++q) s -= a[i][q] * B[q * ldb + j];
+      c[i][j] = s;
+    }
+}
+
+template <int R>
+__attribute__((target("avx2,fma"))) void rows_update_avx2(double* const* c, const double* const* a,
+                                                            const double* __restrict__ B, int b, size_t ldb, int m) {
+  int j = 0;
+  for (; j + 8 <= m; j += 8) {
+    __m256d acc[R][2];
+    for (int i = 0; i < R; ++i) {
+      acc[i][0] = _mm256_loadu_pd(c[i] + j);
+      acc[i][1] = _mm256_loadu_pd(c[i] + j + 4);
+    }
+    for (int q = 0; q < b; ++q) {
+      const double* bq = B + q * ldb + j;
+      const __m256d b0 = _mm256_loadu_pd(bq), b1 = _mm256_loadu_pd(bq + 4);
+      for (int i = 0; i < R; ++i) {
+        const __m256d f = _mm256_broadcast_sd(a[i] + q);
+        acc[i][0] = _mm256_fnmadd_pd(f, b0, acc[i][0]);
+        acc[i][1] = _mm256_fnmadd_pd(f, b1, acc[i][1]);
+      }
+    }
+    for (int i = 0; i < R; ++i) {
+      _mm256_storeu_pd(c[i] + j, acc[i][0]);
+      _mm256_storeu_pd(c[i] + j + 4, acc[i][1]);
+    }
+  }
+  if (j < m) {
+    double* cr[R];
+    for (int i = 0; i < R; ++i) cr[i] = c[i] + j;
+    rows_update_plain<R>(cr, a, B + j, b, ldb, m - j);
+  }
+}
+
+// the same over column tiles of 256 (B's tile, b x 256, stays in L2)
+template <int R>
+void rows_update(bool avx2, double* const* c, const double* const* a, const double* B, int b, size_t ldb, int m) {
+  constexpr int kTile = 256;
+  for (int j0 = 0; j0 < m; j0 += kTile) {
+    double* cc[R];
+    for (int i = 0; i < R; ++i) cc[i] = c[i] + j0;
+    if (avx2)
+      rows_update_avx2<R>(cc, a, B + j0, b, ldb, std::min(kTile, m - j0));
+    else
+      rows_update_plain<R>(cc, a, B + j0, b, ldb, std::min(kTile, m - j0));
+  }
+}
+
+// A into its inverse; false if A is singular.  Gauss-Jordan elimination with
+// partial pivoting, in blocks of kPanel columns: the block's pivots come from
+// an LU factorisation of its columns over the rows not yet pivotal (the
+// pivots column-by-column elimination would pick), the same row swaps are
+// applied to A and to X (the inverse being built, initially I), the pivot
+// rows of the trailing columns of A and of X are multiplied by the inverse
+// of the block's pivot block, and every other row subtracts its block
+// entries times those rows (a product of a (n - b) x b and a b x (trailing)
+// matrix).  `threads` > 1 splits the products by rows and columns.
 bool invert(std::vector<double>& A, int n, int threads = 1) {
-  std::vector<double> inv((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  constexpr int kPanel = 64;
+  std::vector<double> X((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) X[(size_t)i * n + i] = 1.0;
   const int T = std::max(1, std::min(threads, n / 64));
+  const bool avx2 = __builtin_cpu_supports("avx2") && __builtin_cpu_supports("fma");
   SpinBarrier bar(T);
   std::atomic<bool> singular{false};
+  // the block's panel (rows k.. x b, LU in place), -A_KK^-1 (b x b), and the
+  // new pivot rows K = A_KK^-1 [A_K,trailing | X_K] (b x (trailing + n))
+  std::vector<double> P((size_t)n * kPanel), W((size_t)kPanel * kPanel), K((size_t)kPanel * 2 * n);
+  std::vector<double> Li((size_t)kPanel * kPanel), Ui((size_t)kPanel * kPanel);
+  std::vector<int> piv(kPanel);
   auto work = [&](int tid) {
-    for (int col = 0; col < n; ++col) {
+    for (int k = 0; k < n; k += kPanel) {
+      const int b = std::min(kPanel, n - k), rows = n - k;
+      const int mt = n - k - b;  // trailing columns of A
+      const int m = mt + n;      // and every column of X
       if (tid == 0) {
-        int p = col;
-        double best = std::fabs(A[(size_t)col * n + col]);
-        for (int r = col + 1; r < n; ++r) {
-          const double v = std::fabs(A[(size_t)r * n + col]);
-          if (v > best) best = v, p = r;
+        for (int r = 0; r < rows; ++r)
+          for (int c = 0; c < b; ++c) P[(size_t)r * b + c] = A[(size_t)(k + r) * n + k + c];
+        for (int c = 0; c < b; ++c) {
+          int p = c;
+          double best = std::fabs(P[(size_t)c * b + c]);
+          for (int r = c + 1; r < rows; ++r) {
+            const double v = std::fabs(P[(size_t)r * b + c]);
+            if (v > best) best = v, p = r;
+          }
+          if (best == 0.0) {
+            singular.store(true);
+            break;
+          }
+          piv[c] = p;
+          if (p != c)
+            for (int j = 0; j < b; ++j) std::swap(P[(size_t)p * b + j], P[(size_t)c * b + j]);
+          const double d = 1.0 / P[(size_t)c * b + c];
+          const double* pc = &P[(size_t)c * b];
+          for (int r = c + 1; r < rows; ++r) {
+            double* pr = &P[(size_t)r * b];
+            const double f = (pr[c] *= d);
+            if (f != 0.0)
+              for (int j = c + 1; j < b; ++j) pr[j] -= f * pc[j];
+          }
         }
-        if (best == 0.0) {
-          singular.store(true);
-        } else {
-          if (p != col)
-            for (int j = 0; j < n; ++j) {
-              std::swap(A[(size_t)p * n + j], A[(size_t)col * n + j]);
-              std::swap(inv[(size_t)p * n + j], inv[(size_t)col * n + j]);
+        if (!singular.load()) {
+          // the swaps on whole rows (A's block columns keep their values
+          // from before the block: they are the multipliers below)
+          for (int c = 0; c < b; ++c)
+            if (piv[c] != c) {
+              std::swap_ranges(&A[(size_t)(k + c) * n], &A[(size_t)(k + c) * n] + n, &A[(size_t)(k + piv[c]) * n]);
+              std::swap_ranges(&X[(size_t)(k + c) * n], &X[(size_t)(k + c) * n] + n, &X[(size_t)(k + piv[c]) * n]);
             }
-          const double d = 1.0 / A[(size_t)col * n + col];
-          for (int j = col + 1; j < n; ++j) A[(size_t)col * n + j] *= d;
-          for (int j = 0; j < n; ++j) inv[(size_t)col * n + j] *= d;
+          // A_KK = L U (unit lower L below the diagonal of the panel's top
+          // block, U on and above it); W = -U^-1 L^-1
+          for (int i = 0; i < b; ++i)
+            for (int j = 0; j < b; ++j) {
+              Li[(size_t)i * b + j] = i == j ? 1.0 : 0.0;
+              Ui[(size_t)i * b + j] = 0.0;
+            }
+          for (int i = 0; i < b; ++i)
+            for (int j = 0; j < i; ++j) {
+              double s = 0.0;
+              for (int q = j; q < i; ++q) s += P[(size_t)i * b + q] * Li[(size_t)q * b + j];
+              Li[(size_t)i * b + j] = -s;
+            }
+          for (int i = b - 1; i >= 0; --i) {
+            const double d = 1.0 / P[(size_t)i * b + i];
+            Ui[(size_t)i * b + i] = d;
+            for (int j = i + 1; j < b; ++j) {
+              double s = 0.0;
+              for (int q = i + 1; q <= j; ++q) s += P[(size_t)i * b + q] * Ui[(size_t)q * b + j];
+              Ui[(size_t)i * b + j] = -s * d;
+            }
+          }
+          for (int i = 0; i < b; ++i)
+            for (int j = 0; j < b; ++j) {
+              double s = 0.0;
+              for (int q = std::max(i, j); q < b; ++q) s += Ui[(size_t)i * b + q] * Li[(size_t)q * b + j];
+              W[(size_t)i * b + j] = -s;
+            }
         }
       }
       if (T > 1) bar.wait();
       if (singular.load()) return;
-      const double* ac = &A[(size_t)col * n];
-      const double* ic = &inv[(size_t)col * n];
-      for (int r = tid; r < n; r += T) {
-        if (r == col) continue;
-        const double f = A[(size_t)r * n + col];
-        if (f == 0.0) continue;
-        double* ar = &A[(size_t)r * n];
-        double* ir = &inv[(size_t)r * n];
-        for (int j = col + 1; j < n; ++j) ar[j] -= f * ac[j];
-        for (int j = 0; j < n; ++j) ir[j] -= f * ic[j];
+      // K = 0 - W [A_K,trailing | X_K], by column ranges
+      {
+        const int per = ((m + T - 1) / T + 7) / 8 * 8, j0 = std::min(m, tid * per), j1 = std::min(m, j0 + per);
+        for (int i = 0; i < b; ++i) std::fill(&K[(size_t)i * m + j0], &K[(size_t)i * m + j1], 0.0);
+        // K columns c0..c1 from the rows k.. of src, starting at its column s0
+        auto part = [&](int c0, int c1, const double* src, int s0) {
+          if (c1 <= c0) return;
+          const double* B = src + (size_t)k * n + s0;
+          for (int i0 = 0; i0 < b; i0 += 4) {
+            double* c[4];
+            const double* a[4];
+            const int R = std::min(4, b - i0);
+            for (int i = 0; i < R; ++i) {
+              c[i] = &K[(size_t)(i0 + i) * m + c0];
+              a[i] = &W[(size_t)(i0 + i) * b];
+            }
+            if (R == 4)
+              rows_update<4>(avx2, c, a, B, b, (size_t)n, c1 - c0);
+            else
+              for (int i = 0; i < R; ++i) rows_update<1>(avx2, c + i, a + i, B, b, (size_t)n, c1 - c0);
+          }
+        };
+        part(j0, std::min(j1, mt), A.data(), k + b + j0);
+        part(std::max(j0, mt), j1, X.data(), std::max(j0, mt) - mt);
+      }
+      if (T > 1) bar.wait();
+      // every other row: [A_r,trailing | X_r] -= A_rK K, four rows at a
+      // time (a group of four lies wholly in the pivot rows or out of them:
+      // k is a multiple of four, and the last block runs to the last row);
+      // the pivot rows take K
+      for (int g = tid; g < (n + 3) / 4; g += T) {
+        const int r0 = 4 * g, r1 = std::min(n, r0 + 4);
+        if (r0 >= k && r0 < k + b) {
+          for (int r = r0; r < r1; ++r) {
+            const double* kr = &K[(size_t)(r - k) * m];
+            std::copy(kr, kr + mt, &A[(size_t)r * n] + k + b);
+            std::copy(kr + mt, kr + m, &X[(size_t)r * n]);
+          }
+          continue;
+        }
+        double* ca[4];
+        double* cx[4];
+        const double* aa[4];
+        for (int r = r0; r < r1; ++r) {
+          ca[r - r0] = &A[(size_t)r * n] + k + b;
+          cx[r - r0] = &X[(size_t)r * n];
+          aa[r - r0] = &A[(size_t)r * n] + k;
+        }
+        if (r1 - r0 == 4) {
+          rows_update<4>(avx2, ca, aa, K.data(), b, (size_t)m, mt);
+          rows_update<4>(avx2, cx, aa, K.data() + mt, b, (size_t)m, n);
+        } else {
+          for (int i = 0; i < r1 - r0; ++i) {
+            rows_update<1>(avx2, ca + i, aa + i, K.data(), b, (size_t)m, mt);
+            rows_update<1>(avx2, cx + i, aa + i, K.data() + mt, b, (size_t)m, n);
+          }
+        }
       }
       if (T > 1) bar.wait();
     }
@@ -154,11 +319,12 @@ bool invert(std::vector<double>& A, int n, int threads = 1) {
   work(0);
   for (auto& t : th) t.join();
   if (singular.load()) return false;
-  A.swap(inv);
+  A.swap(X);
   return true;
 }
 
 constexpr size_t kBatch = 8;                      // systems factorised at once
+constexpr unsigned kHostThreads = 16;             // host threads of a batch at most
 constexpr size_t kBatchBytes = (size_t)1 << 30;  // their matrices' bytes at once
 
 // one bottom system: the assembled (bordered) matrix, replaced by its
@@ -242,8 +408,10 @@ int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats
     std::vector<Job> jobs;
     size_t pending = 0;
     auto flush = [&]() -> int {
-      // kBatch threads in all: one per system, the rest inside the inversions
-      const int inner = jobs.empty() ? 1 : std::max<int>(1, (int)(kBatch / jobs.size()));
+      // one thread per system, the rest of the host's (at most
+      // kHostThreads) inside the inversions
+      const unsigned hw = std::max(1u, std::min(kHostThreads, std::thread::hardware_concurrency()));
+      const int inner = jobs.empty() ? 1 : std::max<int>(1, (int)(hw / jobs.size()));
       std::vector<std::thread> th;
       for (size_t q = 1; q < jobs.size(); ++q)
         th.emplace_back(factorise, std::ref(jobs[q]), H->bottom_kind, inner);
@@ -260,12 +428,17 @@ int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats
         const size_t base = mats.size();
         G.mat = (int64_t)base;
         G.matT = (int64_t)(base + (size_t)nn * nn);
-        mats.resize(base + 2 * (size_t)nn * nn);
-        for (int64_t c = 0; c < nn; ++c)
-          for (int64_t r = 0; r < nn; ++r) {
-            mats[base + (size_t)c * nn + r] = J.A[(size_t)r * m + c];
-            mats[G.matT + (size_t)c * nn + r] = J.A[(size_t)c * m + r];
-          }
+        if (mats.capacity() < base + 2 * (size_t)nn * nn)
+          mats.reserve(std::max(base + 2 * (size_t)nn * nn, 2 * mats.capacity()));
+        mats.resize(base + (size_t)nn * nn);
+        constexpr int64_t kT = 32;  // the block itself: transposed in 32 x 32 tiles
+        for (int64_t c0 = 0; c0 < nn; c0 += kT)
+          for (int64_t r0 = 0; r0 < nn; r0 += kT)
+            for (int64_t r = r0; r < std::min(nn, r0 + kT); ++r)
+              for (int64_t c = c0; c < std::min(nn, c0 + kT); ++c)
+                mats[base + (size_t)c * nn + r] = J.A[(size_t)r * m + c];
+        for (int64_t c = 0; c < nn; ++c)  // its transpose: the rows of A in order
+          mats.insert(mats.end(), &J.A[(size_t)c * m], &J.A[(size_t)c * m] + nn);
         if (H->bottom_kind == AMG_BOTTOM_ILU_GMRES) {
           G.ilub = (int64_t)mats.size();
           G.ilup = G.ilub + m * m;
