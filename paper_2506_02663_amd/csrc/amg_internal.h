@@ -29,6 +29,20 @@ inline uint8_t column_code(uint8_t k1, uint8_t k2) {
   return c;
 }
 
+// Further bits of the stored column code, for the FP32 sweeps that form
+// their ghosts where they read them: kCodeExch, both layers copy cells of
+// another box (their elements in Depth::xsrc); kCodeZero, both layers are
+// zero (the interpolated ghosts of a correction).  A column that copies
+// cells of its own box (a periodic direction the box spans) keeps code 0.
+constexpr uint8_t kCodeExch = 8, kCodeZero = 16;
+inline uint8_t stored_code(uint8_t k1, uint8_t k2, bool own_box) {
+  const uint8_t c = column_code(k1, k2);
+  if (c) return c;
+  if (k1 == G_EXCH && k2 == G_EXCH && !own_box) return kCodeExch;
+  if (k1 == G_ZERO && k2 == G_ZERO) return kCodeZero;
+  return 0;
+}
+
 struct BoxD {              // one box at one multigrid depth
   int64_t off;             // element offset of the stored corner (ghost -2,-2,-2)
   int32_t n[3];            // interior cells per direction (1 for unused dims)
@@ -208,7 +222,8 @@ struct Depth {
   std::vector<int32_t> bottom_boxes; // boxes solved exactly at this depth
   std::vector<BottomGroupD> groups;
   int64_t nstored = 0;
-  bool fill_only = false;  // every ghost column is filled from its own row (no exchange or interpolated ghosts)
+  bool fill_only = false;  // the FP32 sweeps form every ghost they read (fills, wraps, exchanges, zeros)
+  bool xfill = false;      // some column has an exchange or zero code (the sweeps' form that reads them)
   bool split_rb = false;   // colour-split storage (k_rbs) applies to this depth
   bool wrap = false;       // some box wraps onto itself in a periodic direction (BoxD::wrap)
   bool wrap_fill = false;  // every face filled uniformly from its own rows (codes 5, 6) or wrapping onto its box
@@ -216,9 +231,13 @@ struct Depth {
   int march = 2;  // cells each tile marches along the last direction
   int32_t dn[3] = {1, 1, 1};  // cells of the grid per direction at this depth
   bool periodic[3] = {false, false, false};
+  // exchange sources of the columns with kCodeExch: elements of the cells
+  // that ghost layers 1 and 2 copy, at 2 i and 2 i + 1 for the column code i
+  std::vector<int64_t> xsrc;
   // device copies
   BoxD* d_box = nullptr;
   uint8_t* d_codes = nullptr;
+  int64_t* d_xsrc = nullptr;
   ChunkD* d_chunks = nullptr;
   TileD* d_tiles = nullptr;
   TileD* d_stiles = nullptr;

@@ -542,7 +542,7 @@ hipStream_t stream_of(amg_hier* H, void* s) { return s ? (hipStream_t)s : H->own
 
 void free_level(amg::Level& L) {
   for (auto& D : L.depths) {
-    for (void* p : {(void*)D.d_box, (void*)D.d_codes, (void*)D.d_chunks, (void*)D.d_tiles, (void*)D.d_stiles,
+    for (void* p : {(void*)D.d_box, (void*)D.d_codes, (void*)D.d_xsrc, (void*)D.d_chunks, (void*)D.d_tiles, (void*)D.d_stiles,
                     (void*)D.d_seg, (void*)D.d_cseg, (void*)D.d_cc_ptr, (void*)D.d_cc_idx, (void*)D.d_groups, (void*)D.d_band,
                     (void*)D.e64, (void*)D.f64, (void*)D.t64, (void*)D.e32, (void*)D.f32, (void*)D.t32, (void*)D.fs32, (void*)D.xg32})
       if (p) (void)hipFree(p);
@@ -994,6 +994,7 @@ int amg_finalize(amg_hier* H) {
     for (auto& D : L.depths) {
       TRY(upload(H, &D.d_box, D.boxd));
       TRY(upload(H, &D.d_codes, D.codes));
+      TRY(upload(H, &D.d_xsrc, D.xsrc));
       TRY(upload(H, &D.d_chunks, D.chunks));
       TRY(upload(H, &D.d_tiles, D.tiles));
       TRY(upload(H, &D.d_stiles, D.stiles));

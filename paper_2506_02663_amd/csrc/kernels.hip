@@ -277,14 +277,42 @@ __device__ __forceinline__ bool gfill(uint8_t cd, const T* __restrict__ u, int64
 // block that writes it.
 template <typename T, int DIM, bool WRAP = false>
 __device__ __forceinline__ void face_ghosts(const BoxD& b, T* __restrict__ u, int x0, int nx, int y0, int ny, int p0,
-                                            int len, bool xfaces = true) {
+                                            int len, bool xfaces = true, const uint8_t* __restrict__ codes = nullptr,
+                                            const int64_t* __restrict__ xsrc = nullptr) {
+  // the ghosts of one column with code cd (e0: its cell at the face, in:
+  // the inward stride)
+  auto column = [&](uint8_t cd, int64_t e0, int64_t in) {
+    if (cd & 3) {
+      const T u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
+      u[e0 - in] = ghost1<T>(cd, u0, u1, u2, u3);
+      if (cd & 4) u[e0 - 2 * in] = ghost2<T>(cd, u0, u1, u2, u3);
+    }
+  };
+  // the same from the column's stored code at pos, its exchange sources
+  // loaded with the code (-1: not an exchange column)
+  auto column_at = [&](int64_t pos, int64_t e0, int64_t in) {
+    const uint8_t cd = codes[pos];
+    const int64_t s1 = xsrc[2 * pos], s2 = xsrc[2 * pos + 1];
+    if (cd & 3) {
+      column(cd, e0, in);
+    } else if (s1 >= 0) {
+      u[e0 - in] = u[s1];
+      u[e0 - 2 * in] = u[s2];
+    } else if (cd & kCodeZero) {
+      u[e0 - in] = T(0);
+      u[e0 - 2 * in] = T(0);
+    }
+  };
   // x faces: one thread per (row, side); with WRAP, a face that wraps onto
   // the box takes the row's cells at the other end (a compile-time switch:
-  // reading the wrap bits costs the other kernels a memory round trip)
+  // reading the wrap bits costs the other kernels a memory round trip).
+  // With codes, a face of several codes, or of exchange or zero columns,
+  // goes column by column.
   const bool wx = WRAP && (b.wrap & 1);
   for (int side = 0; side < 2 && xfaces; ++side) {
     const uint8_t cd = b.ucode[0][side];
-    if (!wx && (cd == 0xFF || !(cd & 3))) continue;
+    const bool percol = codes && (cd == 0xFF || (cd & (kCodeExch | kCodeZero)));
+    if (!wx && !percol && (cd == 0xFF || !(cd & 3))) continue;
     if (side == 0 ? x0 != 0 : x0 + nx != b.n[0]) continue;
     for (int r = (int)threadIdx.x; r < ny * len; r += (int)blockDim.x) {
       const int y = DIM == 3 ? y0 + r % ny : 0, p = p0 + r / ny;
@@ -296,16 +324,20 @@ __device__ __forceinline__ void face_ghosts(const BoxD& b, T* __restrict__ u, in
         u[e0 - 2 * in] = u[e0 + far - in];
         continue;
       }
-      const T u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
-      u[e0 - in] = ghost1<T>(cd, u0, u1, u2, u3);
-      if (cd & 4) u[e0 - 2 * in] = ghost2<T>(cd, u0, u1, u2, u3);
+      if (percol) {
+        const int64_t pos = (int64_t)b.code_off[0][side] + (DIM == 3 ? y + (int64_t)b.n[1] * p : p);
+        column_at(pos, e0, in);
+        continue;
+      }
+      column(cd, e0, in);
     }
   }
   if (DIM == 3) {
     const bool wy = WRAP && ((b.wrap >> 1) & 1);
     for (int side = 0; side < 2; ++side) {
       const uint8_t cd = b.ucode[1][side];
-      if (!wy && (cd == 0xFF || !(cd & 3))) continue;
+      const bool percol = codes && (cd == 0xFF || (cd & (kCodeExch | kCodeZero)));
+      if (!wy && !percol && (cd == 0xFF || !(cd & 3))) continue;
       if (side == 0 ? y0 != 0 : y0 + ny != b.n[1]) continue;
       for (int r = (int)threadIdx.x; r < nx * len; r += (int)blockDim.x) {
         const int x = x0 + r % nx, p = p0 + r / nx;
@@ -317,9 +349,12 @@ __device__ __forceinline__ void face_ghosts(const BoxD& b, T* __restrict__ u, in
           u[e0 - 2 * in] = u[e0 + far - in];
           continue;
         }
-        const T u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
-        u[e0 - in] = ghost1<T>(cd, u0, u1, u2, u3);
-        if (cd & 4) u[e0 - 2 * in] = ghost2<T>(cd, u0, u1, u2, u3);
+        if (percol) {
+          const int64_t pos = (int64_t)b.code_off[1][side] + x + (int64_t)b.n[0] * p;
+          column_at(pos, e0, in);
+          continue;
+        }
+        column(cd, e0, in);
       }
     }
   }
@@ -352,10 +387,13 @@ __device__ __forceinline__ void march_ghosts(const TileD& t, const BoxD& b, cons
 
 // the same for the cells of one column tile (xfaces false: y faces only)
 template <typename T, int DIM, bool WRAP = false>
-__device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __restrict__ u, bool xfaces = true) {
+__device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __restrict__ u, bool xfaces = true,
+                                            const uint8_t* __restrict__ codes = nullptr,
+                                            const int64_t* __restrict__ xsrc = nullptr) {
   const int p0 = DIM == 2 ? t.y0 : t.z0;
   face_ghosts<T, DIM, WRAP>(b, u, t.x0, min(TILE_X, b.n[0] - t.x0), DIM == 3 ? t.y0 : 0,
-                            DIM == 3 ? min(TILE3_Y, b.n[1] - t.y0) : 1, p0, min(t.len, b.n[DIM - 1] - p0), xfaces);
+                            DIM == 3 ? min(TILE3_Y, b.n[1] - t.y0) : 1, p0, min(t.len, b.n[DIM - 1] - p0), xfaces,
+                            codes, xsrc);
 }
 
 // OP_RESID : out = f - A u (f == NULL: out = A u); PART: per-tile max |out|
@@ -375,12 +413,12 @@ __device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __
 // a direction that wraps onto the box are read from its other end, so no
 // fill launch is needed before the sweep for them; ghosts of other exchange
 // and interpolated columns still come from memory.
-template <typename T, int DIM, int OP, bool PART, bool WRAP>
+template <typename T, int DIM, int OP, bool PART, bool WRAP, bool XF>
 __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles, int ntiles,
                                                 const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
                                                 const T* u, const T* __restrict__ f, T* __restrict__ out,
                                                 T alpha, T beta, T omega, int col, double* __restrict__ part,
-                                                int gr) {
+                                                int gr, const int64_t* __restrict__ xsrc) {
   __shared__ double sh[8];
   const int ti = tile_of_block(ntiles);
   if (ti < 0) return;
@@ -394,11 +432,13 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
   if (gr) {
     const int nx = min(TILE_X, b.n[0] - t.x0);
     const uint8_t ux0 = b.ucode[0][0], ux1 = b.ucode[0][1];
-    const bool xf = (ux0 != 0xFF && (ux0 & 3) && t.x0 == 0) || (ux1 != 0xFF && (ux1 & 3) && t.x0 + nx == b.n[0]) ||
-                    (WRAP && (b.wrap & 1) && (t.x0 == 0 || t.x0 + nx == b.n[0]));
+    // XF: also faces of exchange or zero columns, or of several codes
+    const bool xf = XF ? ((ux0 != 0 && t.x0 == 0) || (ux1 != 0 && t.x0 + nx == b.n[0]))
+                       : ((ux0 != 0xFF && (ux0 & 3) && t.x0 == 0) || (ux1 != 0xFF && (ux1 & 3) && t.x0 + nx == b.n[0]));
+    const bool xw = WRAP && (b.wrap & 1) && (t.x0 == 0 || t.x0 + nx == b.n[0]);
     const bool yf = DIM == 3 && (t.y0 == 0 || t.y0 + TILE3_Y >= b.n[1]);
-    if (xf || yf) {  // block-uniform
-      tile_ghosts<T, DIM, WRAP>(t, b, const_cast<T*>(u));
+    if (xf || xw || yf) {  // block-uniform
+      tile_ghosts<T, DIM, WRAP>(t, b, const_cast<T*>(u), true, XF ? codes : nullptr, XF ? xsrc : nullptr);
       __syncthreads();
     }
   }
@@ -426,26 +466,44 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
     // the low ones once here, the high ones from the register queue
     uint8_t chi = 0;
     T g2n = T(0);  // second high ghost, computed one step ahead
+    T xh1 = T(0), xh2 = T(0);  // high ghosts of an exchange or zero column
     if (gr) {
       const int mcol = DIM == 2 ? C.x : C.x + b.n[0] * C.y;
       T g1, g2;
-      if (C.p0 < 2 && gfill<T>(codes[b.code_off[M][0] + mcol], u, c - (int64_t)C.p0 * sm, sm, g1, g2)) {
-        if (C.p0 == 0) {
-          q0 = g2;
-          q1 = g1;
-        } else {
-          q0 = g1;
+      if (C.p0 < 2) {
+        const int64_t pos = (int64_t)b.code_off[M][0] + mcol;
+        const uint8_t clo = codes[pos];
+        bool got = gfill<T>(clo, u, c - (int64_t)C.p0 * sm, sm, g1, g2);
+        if (XF && !got && (clo & (kCodeExch | kCodeZero))) {
+          g1 = (clo & kCodeExch) ? u[xsrc[2 * pos]] : T(0);
+          g2 = (clo & kCodeExch) ? u[xsrc[2 * pos + 1]] : T(0);
+          got = true;
+        }
+        if (got) {
+          if (C.p0 == 0) {
+            q0 = g2;
+            q1 = g1;
+          } else {
+            q0 = g1;
+          }
         }
       }
       if (C.p1 + 2 > nm) {
-        chi = codes[b.code_off[M][1] + mcol];
+        const int64_t pos = (int64_t)b.code_off[M][1] + mcol;
+        chi = codes[pos];
+        if (XF && (chi & kCodeExch)) {
+          xh1 = u[xsrc[2 * pos]];
+          xh2 = u[xsrc[2 * pos + 1]];
+        }
         if ((chi & 3) && C.p0 + 1 >= nm && gfill<T>(chi, u, c + (int64_t)(nm - 1 - C.p0) * sm, -sm, g1, g2)) {
           q3 = g1;  // a one-cell tile at the end of the column
           g2n = g2;
         }
+        if (XF && (chi & (kCodeExch | kCodeZero)) && C.p0 + 1 >= nm) q3 = xh1;
       }
     }
     const int hk = chi & 3;  // fill kind of the high march-direction face (0: ghosts in memory)
+    const bool hx = XF && (chi & (kCodeExch | kCodeZero)) != 0;  // high ghosts from xh1, xh2
     DiagColumn<T, DIM> dg;
     if (OP != OP_RESID) dg.init(b, codes, C.x, C.y, alpha, beta, true);
     const int par0 = (b.lo[0] + C.x + (DIM == 3 ? b.lo[1] + C.y : 0) + b.lo[DIM - 1]) & 1;
@@ -462,6 +520,8 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
         }
       } else if (hk && p + 2 == nm + 1) {
         q4 = g2n;
+      } else if (hx && p + 2 >= nm) {
+        q4 = p + 2 == nm ? xh1 : xh2;
       } else if (wm && p + 2 >= nm) {
         q4 = u[c0 + (int64_t)(p + 2 - nm) * sm];
       } else {
@@ -2389,12 +2449,22 @@ struct MarchK {
                  double* part, const BoxD* cboxes, hipStream_t st, int gr) {
     if (sizeof(T) == 4 && OP != OP_RESTRICT) {
       // the form that reads wrapped ghosts only where a box wraps
-      if (gr && D.wrap)
-        hipLaunchKernelGGL((k_march1<T, DIM, OP, PART, true>), grid8(n), dim3(DIM == 2 ? 128 : 512), 0, st, tl,
-                           (int)n, D.d_box, D.d_codes, u, f, out, a, b, w, col, part, gr);
+      // the forms that read wrapped ghosts, or form exchange and zero
+      // ghosts, only where a box wraps or such columns exist
+      const dim3 g = grid8(n), bs(DIM == 2 ? 128 : 512);
+      const bool wr = gr && D.wrap, xf = gr && D.xfill;
+      if (wr && xf)
+        hipLaunchKernelGGL((k_march1<T, DIM, OP, PART, true, true>), g, bs, 0, st, tl, (int)n, D.d_box, D.d_codes, u,
+                           f, out, a, b, w, col, part, gr, D.d_xsrc);
+      else if (wr)
+        hipLaunchKernelGGL((k_march1<T, DIM, OP, PART, true, false>), g, bs, 0, st, tl, (int)n, D.d_box, D.d_codes,
+                           u, f, out, a, b, w, col, part, gr, D.d_xsrc);
+      else if (xf)
+        hipLaunchKernelGGL((k_march1<T, DIM, OP, PART, false, true>), g, bs, 0, st, tl, (int)n, D.d_box, D.d_codes,
+                           u, f, out, a, b, w, col, part, gr, D.d_xsrc);
       else
-        hipLaunchKernelGGL((k_march1<T, DIM, OP, PART, false>), grid8(n), dim3(DIM == 2 ? 128 : 512), 0, st, tl,
-                           (int)n, D.d_box, D.d_codes, u, f, out, a, b, w, col, part, gr);
+        hipLaunchKernelGGL((k_march1<T, DIM, OP, PART, false, false>), g, bs, 0, st, tl, (int)n, D.d_box, D.d_codes,
+                           u, f, out, a, b, w, col, part, gr, D.d_xsrc);
     } else
       hipLaunchKernelGGL((k_march<T, DIM, OP, PART>), grid8(n), threads<DIM>(), 0, st, tl, (int)n, D.d_box, D.d_codes,
                          u, f, out, a, b, w, col, part, cboxes, gr, (int64_t)0);

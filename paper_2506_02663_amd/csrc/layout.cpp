@@ -415,15 +415,16 @@ int plan_level(amg_hier* H, int l, std::string& err) {
           }
           FaceCols& fc = D.faces[i * 6 + d * 2 + s];
           D.boxd[i].code_off[d][s] = (int32_t)D.codes.size();
-          uint8_t u0 = column_code(fc.k1[0], fc.k2[0]);
+          uint8_t u0 = stored_code(fc.k1[0], fc.k2[0], fc.src1[0] == i);
           for (size_t c = 0; c < fc.k1.size(); ++c) {
-            const uint8_t cc = column_code(fc.k1[c], fc.k2[c]);
+            const uint8_t cc = stored_code(fc.k1[c], fc.k2[c], fc.src1[c] == i);
             D.codes.push_back(cc);
             if (cc != u0) u0 = 0xFF;
           }
           D.boxd[i].ucode[d][s] = u0;
         }
     if (D.codes.empty()) D.codes.push_back(0);
+    D.xsrc.assign(2 * D.codes.size(), -1);
 
     // ---- band of the transposed fill: 4-deep slabs of faces with filled columns ----
     D.band.clear();
@@ -512,6 +513,13 @@ int plan_level(amg_hier* H, int l, std::string& err) {
                 const int p1 = s ? B.hi[d] + 1 : B.lo[d] - 1;
                 ch.cf = (!L.isolated && p1 >= 0 && p1 < dn[d]) ? 1 : 0;
               }
+              // the sources of exchange columns, for the sweeps' read-time fill
+              for (int l = 0; l < ch.count; ++l) {
+                const size_t pos = (size_t)D.boxd[i].code_off[d][s] + (size_t)(q0 + l) + (size_t)n0 * q1;
+                if (D.codes[pos] != kCodeExch) continue;
+                D.xsrc[2 * pos] = ch.src1 + (int64_t)l * ch.sstride1;
+                D.xsrc[2 * pos + 1] = ch.src2 + (int64_t)l * ch.sstride2;
+              }
               ch.fd = -1;
               if (k == 0 && (ch.kind1 == G_FILL_D || ch.kind1 == G_FILL_N))
                 ch.fd = L.face_off[D.level_box[i] * 6 + d * 2 + s] + (int64_t)q0 + (int64_t)n0 * q1;
@@ -530,20 +538,28 @@ int plan_level(amg_hier* H, int l, std::string& err) {
       D.chunk_comp_ptr.push_back((int32_t)D.chunk_comp_idx.size());
     }
 
-    // (the FP32 sweeps also form the ghosts of a face that wraps onto its own
-    // box where they read them)
-    D.fill_only = true;
+    // (the FP32 sweeps form the ghosts they read: filled columns from their
+    // rows, a face that wraps onto its own box from the box's other end,
+    // exchange columns from their sources, zero columns as zero)
+    // every exchange code has its sources (else the column keeps its ghosts
+    // in memory and the fill launch stays)
+    bool sources = true;
+    for (size_t pos = 0; pos < D.codes.size(); ++pos)
+      if (D.codes[pos] == kCodeExch && (D.xsrc[2 * pos] < 0 || D.xsrc[2 * pos + 1] < 0)) {
+        D.codes[pos] = 0;
+        sources = false;
+      }
+    D.fill_only = sources;
+    D.xfill = false;
+    for (uint8_t c : D.codes)
+      if (c & (kCodeExch | kCodeZero)) D.xfill = true;
     for (const ChunkD& ch : D.chunks) {
       const bool filled =
           (ch.kind1 == G_FILL_D || ch.kind1 == G_FILL_N) && (ch.kind2 == G_FILL_D || ch.kind2 == G_FILL_N);
-      const bool wraps = ch.kind1 == G_EXCH && ch.kind2 == G_EXCH && ((D.boxd[ch.box].wrap >> ch.dir) & 1);
-      if (!filled && !wraps) D.fill_only = false;
+      const bool exch = ch.kind1 == G_EXCH && ch.kind2 == G_EXCH;
+      const bool zero = ch.kind1 == G_ZERO && ch.kind2 == G_ZERO;
+      if (!filled && !exch && !zero) D.fill_only = false;
     }
-    // the read-time fill writes the ghosts across the march direction only on
-    // faces with one code; a face across it that mixes codes keeps the launch
-    for (const BoxD& X : D.boxd)
-      for (int d = 0; d + 1 < dim; ++d)
-        if (X.ucode[d][0] == 0xFF || X.ucode[d][1] == 0xFF) D.fill_only = false;
 
     // ---- tiles (grouped by component, so each component is one range) ----
     D.tiles.clear();
