@@ -478,8 +478,9 @@ T* vcycle(const Run& R, const amg_solve_opts& o, const T* f0, T* e0, T* t0, cons
     T alpha, beta;
     coefs<T>(R.H, D, alpha, beta);
     // below the finest depth the FP32 restriction writes the ghosts it reads
-    // itself where every face is filled uniformly (no fill launch)
-    const int rgr = (sizeof(T) == 4 && !R.tr && k > 0 && D.uniform_fill) ? 1 : 0;
+    // itself where every face is filled uniformly or wraps onto its box (no
+    // fill launch)
+    const int rgr = (sizeof(T) == 4 && !R.tr && k > 0 && D.wrap_fill) ? 1 : 0;
     if (!rgr) {
       Timed tm(R, AMG_T_FILL, k);
       fill_op<T>(R, D, cur[k]);
@@ -1560,7 +1561,7 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
     } else {
       // without face data on uniformly filled faces the residual kernel
       // writes the (homogeneous) ghosts of x it reads itself
-      const int rgr = (direct32 && !FD && D0.uniform_fill) ? 1 : 0;
+      const int rgr = (direct32 && !FD && D0.wrap_fill) ? 1 : 0;
       if (!rgr) launch_fill<double>(D0, X, FD, R.st);
       Timed tm(R, AMG_T_RESIDUAL, 0);
       if (direct32)

@@ -363,21 +363,28 @@ __device__ __forceinline__ void face_ghosts(const BoxD& b, T* __restrict__ u, in
 // Ghosts along the march direction of the tile's columns (the faces at the
 // ends of the march), from each column's own code, on the faces the tile
 // reaches; written by the block before its march like face_ghosts.
-template <typename T, int DIM>
+template <typename T, int DIM, bool WRAP = false>
 __device__ __forceinline__ void march_ghosts(const TileD& t, const BoxD& b, const uint8_t* __restrict__ codes,
                                              T* __restrict__ u) {
   constexpr int M = DIM - 1;
   const int p0 = DIM == 2 ? t.y0 : t.z0, len = min(t.len, b.n[M] - p0);
   const int nx = min(TILE_X, b.n[0] - t.x0), ny = DIM == 3 ? min(TILE3_Y, b.n[1] - t.y0) : 1;
+  const bool wm = WRAP && ((b.wrap >> M) & 1);  // the march direction wraps onto the box
   for (int side = 0; side < 2; ++side) {
     if (side == 0 ? p0 != 0 : p0 + len != b.n[M]) continue;
     for (int r = (int)threadIdx.x; r < nx * ny; r += (int)blockDim.x) {
       const int x = t.x0 + r % nx, y = DIM == 3 ? t.y0 + r / nx : 0;
-      const uint8_t cd = codes[b.code_off[M][side] + (DIM == 2 ? x : x + b.n[0] * y)];
-      if (!(cd & 3)) continue;
       const int pe = side ? b.n[M] - 1 : 0;
       const int64_t e0 = DIM == 3 ? cell_index<3>(b, x, y, pe) : cell_index<2>(b, x, pe, 0);
       const int64_t in = (side ? -1 : 1) * (int64_t)b.s[M];
+      if (wm) {  // ghost layer g is the cell g from the other end of the column
+        const int64_t far = (int64_t)(b.n[M] - 1) * in;
+        u[e0 - in] = u[e0 + far];
+        u[e0 - 2 * in] = u[e0 + far - in];
+        continue;
+      }
+      const uint8_t cd = codes[b.code_off[M][side] + (DIM == 2 ? x : x + b.n[0] * y)];
+      if (!(cd & 3)) continue;
       const T u0 = u[e0], u1 = u[e0 + in], u2 = u[e0 + 2 * in], u3 = u[e0 + 3 * in];
       u[e0 - in] = ghost1<T>(cd, u0, u1, u2, u3);
       if (cd & 4) u[e0 - 2 * in] = ghost2<T>(cd, u0, u1, u2, u3);
@@ -573,7 +580,7 @@ __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles,
 // the thread, z or y pairs over two steps, y pairs in 3D through LDS), so the
 // fine residual is never stored: out is the coarse right-hand side.  TO:
 // the element type of out (an FP64 residual may be stored in FP32).
-template <typename T, int DIM, int OP, bool PART, typename TO = T>
+template <typename T, int DIM, int OP, bool PART, typename TO = T, bool WRAP = false>
 __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, int ntiles,
                                                const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
                                                const T* __restrict__ u, const T* __restrict__ f, TO* __restrict__ out,
@@ -596,8 +603,8 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
   if (gr) {
     const int p0 = DIM == 2 ? t.y0 : t.z0, nm = b.n[DIM - 1];
     if (xodd || (DIM == 3 && (t.y0 == 0 || t.y0 + TILE3_Y >= b.n[1])) || p0 == 0 || p0 + t.len >= nm) {
-      tile_ghosts<T, DIM>(t, b, const_cast<T*>(u), xodd);  // block-uniform branch
-      march_ghosts<T, DIM>(t, b, codes, const_cast<T*>(u));
+      tile_ghosts<T, DIM, WRAP>(t, b, const_cast<T*>(u), xodd);  // block-uniform branch
+      march_ghosts<T, DIM, WRAP>(t, b, codes, const_cast<T*>(u));
       __syncthreads();
     }
   }
@@ -642,11 +649,20 @@ __global__ void __launch_bounds__(256) k_march(const TileD* __restrict__ tiles, 
         Ra = u[c + 2];
         Rb = u[c + 3];
       }
-      if (xlo) {  // cells -2, -1 from cells 0..3 (the next lane's pair)
+      // WRAP: an x direction that wraps onto the box takes the row's cells
+      // at the other end
+      const bool wx = WRAP && (b.wrap & 1);
+      if (xlo && wx) {
+        La = u[c + b.n[0] - 2];
+        Lb = u[c + b.n[0] - 1];
+      } else if (xlo) {  // cells -2, -1 from cells 0..3 (the next lane's pair)
         La = ghost2<T>(cxl, q2.a, q2.b, Ra, Rb);
         Lb = ghost1<T>(cxl, q2.a, q2.b, Ra, Rb);
       }
-      if (xhi) {  // cells n, n + 1 from cells n - 1 .. n - 4 (the previous pair)
+      if (xhi && wx) {
+        Ra = u[c + 2 - b.n[0]];
+        Rb = u[c + 3 - b.n[0]];
+      } else if (xhi) {  // cells n, n + 1 from cells n - 1 .. n - 4 (the previous pair)
         const T g1 = ghost1<T>(cxh, q2.b, q2.a, Lb, La), g2 = ghost2<T>(cxh, q2.b, q2.a, Lb, La);
         Ra = g1;
         Rb = g2;
@@ -2465,9 +2481,13 @@ struct MarchK {
       else
         hipLaunchKernelGGL((k_march1<T, DIM, OP, PART, false, false>), g, bs, 0, st, tl, (int)n, D.d_box, D.d_codes,
                            u, f, out, a, b, w, col, part, gr, D.d_xsrc);
-    } else
+    } else if (gr && D.wrap) {  // the form that reads wrapped ghosts only where a box wraps
+      hipLaunchKernelGGL((k_march<T, DIM, OP, PART, T, true>), grid8(n), threads<DIM>(), 0, st, tl, (int)n, D.d_box,
+                         D.d_codes, u, f, out, a, b, w, col, part, cboxes, gr, (int64_t)0);
+    } else {
       hipLaunchKernelGGL((k_march<T, DIM, OP, PART>), grid8(n), threads<DIM>(), 0, st, tl, (int)n, D.d_box, D.d_codes,
                          u, f, out, a, b, w, col, part, cboxes, gr, (int64_t)0);
+    }
   }
 };
 
@@ -2899,12 +2919,20 @@ void launch_residual32(int dim, const Depth& D, const double* u, const double* f
   const size_t n = D.tiles.size();
   if (!n) return;
   const int64_t sh = split ? D.nstored / 2 : 0;
-  if (dim == 2)
+  if (gr && D.wrap) {  // the form that reads wrapped ghosts only where a box wraps
+    if (dim == 2)
+      hipLaunchKernelGGL((k_march<double, 2, OP_RESID, true, float, true>), grid8(n), threads<2>(), 0, st, D.d_tiles,
+                         (int)n, D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr, gr, sh);
+    else
+      hipLaunchKernelGGL((k_march<double, 3, OP_RESID, true, float, true>), grid8(n), threads<3>(), 0, st, D.d_tiles,
+                         (int)n, D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr, gr, sh);
+  } else if (dim == 2) {
     hipLaunchKernelGGL((k_march<double, 2, OP_RESID, true, float>), grid8(n), threads<2>(), 0, st, D.d_tiles, (int)n,
                        D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr, gr, sh);
-  else
+  } else {
     hipLaunchKernelGGL((k_march<double, 3, OP_RESID, true, float>), grid8(n), threads<3>(), 0, st, D.d_tiles, (int)n,
                        D.d_box, D.d_codes, u, f, r, alpha, beta, 0.0, 0, part, nullptr, gr, sh);
+  }
 }
 
 void launch_shift_copy(int dim, const Depth& D, const double* f, double* out, const double* delta, hipStream_t st) {
