@@ -645,6 +645,15 @@ typedef struct {
 int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, double* const* u, const double* const* g,
                   const amg_solve_opts* opts, const amg_solve_opts* opts_p, amg_imex_stats* stats, void* stream);
 
+/* The inverse of the dense row-major n x n FP64 matrix a, in place: the
+ * factorisation behind the exact bottom solve (the coarsest depth's system,
+ * Section 6.5 replaced by an exact solve), Gauss-Jordan elimination with
+ * partial pivoting in blocks of 64 columns on up to `threads` host threads.
+ * Host-only: no device call.  Errors: AMG_EINVAL (n < 1, null a, threads
+ * < 1), AMG_EUNSUPPORTED (a zero pivot: a singular matrix; a is then left
+ * unchanged). */
+int amg_dense_inverse(int n, double* a, int threads);
+
 /* ---- regridding and data migration (Section 5.4, RDM-1..4) -----------------
  * Clustering (RDM-2), as read from Berger and Rigoutsos (1991): a box is
  * shrunk to the bounding box of its tags and accepted when tags / cells

@@ -142,6 +142,7 @@ def lib():
         L.amg_convection.argtypes = [vp, pp, pp, vp]
         i32p = C.POINTER(C.c_int32)
         L.amg_cluster.argtypes = [i32, i32p, C.POINTER(C.c_uint8), dbl, i32, i32, i32p, i32p, i32p]
+        L.amg_dense_inverse.argtypes = [i32, C.POINTER(C.c_double), i32]
         L.amg_regrid_boxes.argtypes = [i32, i32p, i32, i32, C.POINTER(C.c_void_p), dbl, i32, i32, i32, i32, i32p, i32p,
                                        i32p]
         L.amg_tag_vorticity.argtypes = [vp, i32, pp, dbl, C.POINTER(C.c_void_p), vp]
@@ -735,6 +736,19 @@ def convection(H, us, outs):
 def _boxes_out(dim, n, lo, hi):
     return [(tuple(int(v) for v in lo[i * dim:(i + 1) * dim]), tuple(int(v) for v in hi[i * dim:(i + 1) * dim]))
             for i in range(n)]
+
+
+def dense_inverse(a, threads=1):
+    """The inverse of the square FP64 matrix a (see amg_dense_inverse: the
+    bottom solve's factorisation, on the host)."""
+    import numpy as np
+    m = np.array(a, dtype=np.float64, order="C", copy=True)
+    if m.ndim != 2 or m.shape[0] != m.shape[1]:
+        raise ValueError("a square matrix is required")
+    rc = lib().amg_dense_inverse(m.shape[0], m.ctypes.data_as(C.POINTER(C.c_double)), int(threads))
+    if rc:
+        raise AmgError(rc, "amg_dense_inverse failed")
+    return m
 
 
 def cluster(tags, efficiency=0.75, min_side=2, max_boxes=4096):

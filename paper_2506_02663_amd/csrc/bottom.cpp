@@ -611,3 +611,11 @@ int build_bottom(amg_hier* H, int l, std::string& err, std::vector<double>& mats
 }
 
 }  // namespace amg
+
+extern "C" int amg_dense_inverse(int n, double* a, int threads) {
+  if (n < 1 || !a || threads < 1) return AMG_EINVAL;
+  std::vector<double> A(a, a + (size_t)n * n);
+  if (!amg::invert(A, n, threads)) return AMG_EUNSUPPORTED;
+  std::copy(A.begin(), A.end(), a);
+  return AMG_OK;
+}
