@@ -417,9 +417,11 @@ __device__ __forceinline__ void tile_ghosts(const TileD& t, const BoxD& b, T* __
 //
 // gr != 0: the ghosts of filled columns (physical and coarse-fine face-data
 // faces, homogeneous) are computed where they are read (gfill), and those of
-// a direction that wraps onto the box are read from its other end, so no
-// fill launch is needed before the sweep for them; ghosts of other exchange
-// and interpolated columns still come from memory.
+// a direction that wraps onto the box are read from its other end (WRAP), so
+// no fill launch is needed before the sweep for them.  XF: so are those of
+// exchange columns (copied from the cells xsrc names) and zero columns
+// (the interpolated ghosts of a correction); without XF those come from
+// memory.
 template <typename T, int DIM, int OP, bool PART, bool WRAP, bool XF>
 __global__ void __launch_bounds__(512) k_march1(const TileD* __restrict__ tiles, int ntiles,
                                                 const BoxD* __restrict__ boxes, const uint8_t* __restrict__ codes,
