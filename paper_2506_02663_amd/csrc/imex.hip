@@ -136,21 +136,23 @@ __global__ __launch_bounds__(256) void k_combo(Geo G, double* dst, Combo cb) {
 }
 
 // *out = max over the cells of |v| (out cleared by the caller): per block a
-// max over its share of the cells (a grid-stride loop over a grid of at
-// most kMaxAbsBlocks), then one atomic max on the bit pattern, which orders
-// non-negative doubles (a NaN, positive, lands above infinity)
+// max over its share of the rows (a grid of at most kMaxAbsBlocks), then
+// one atomic max on the bit pattern, which orders non-negative doubles (a
+// NaN, positive, lands above infinity)
 constexpr int kMaxAbsBlocks = 256;
 __global__ __launch_bounds__(256) void k_maxabs(Geo G, const double* v, unsigned long long* out) {
   __shared__ double sh[4];
-  const int64_t cells = (int64_t)G.n[0] * G.n[1] * G.n[2];
+  // blocks stride over the rows (y, z), threads over x
+  const int rows = G.n[1] * G.n[2];
   double m = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += (int64_t)gridDim.x * blockDim.x) {
-    const int x = (int)(i % G.n[0]);
-    const int y = (int)((i / G.n[0]) % G.n[1]);
-    const int z = (int)(i / ((int64_t)G.n[0] * G.n[1]));
-    const double a = fabs(v[G.off + (x + 2) + (int64_t)(y + 2) * G.s1 + (int64_t)(z + 2) * G.s2]);
-    const double c = (a == a) ? a : __longlong_as_double(0x7ff8000000000000LL);
-    m = (c > m || c != c) ? c : m;
+  for (int r = (int)blockIdx.x; r < rows; r += (int)gridDim.x) {
+    const int y = r % G.n[1], z = r / G.n[1];
+    const double* row = v + G.off + 2 + (int64_t)(y + 2) * G.s1 + (int64_t)(z + 2) * G.s2;
+    for (int x = (int)threadIdx.x; x < G.n[0]; x += (int)blockDim.x) {
+      const double a = fabs(row[x]);
+      const double c = (a == a) ? a : __longlong_as_double(0x7ff8000000000000LL);
+      m = (c > m || c != c) ? c : m;
+    }
   }
   for (int k = 32; k > 0; k >>= 1) {
     const double o = __shfl_xor(m, k, 64);
@@ -294,7 +296,8 @@ extern "C" int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, d
   // ||b||_inf over the cells (one small reduction and a wait for it)
   auto rhs_norm = [&](const double* b, double& out) -> int {
     if (hipMemsetAsync(dnorm, 0, sizeof *dnorm, st) != hipSuccess) return fail(H, AMG_EDEVICE, "norm clear failed");
-    hipLaunchKernelGGL(k_maxabs, dim3(std::min<unsigned>(grid.x, kMaxAbsBlocks)), block, 0, st, G, b, dnorm);
+    const unsigned rows = (unsigned)G.n[1] * (unsigned)G.n[2];
+    hipLaunchKernelGGL(k_maxabs, dim3(std::min<unsigned>(rows, kMaxAbsBlocks)), block, 0, st, G, b, dnorm);
     if (hipGetLastError() != hipSuccess) return fail(H, AMG_EDEVICE, "k_maxabs launch failed");
     unsigned long long bits = 0;
     if (hipMemcpyAsync(&bits, dnorm, sizeof bits, hipMemcpyDeviceToHost, st) != hipSuccess ||
