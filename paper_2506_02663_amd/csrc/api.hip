@@ -183,16 +183,17 @@ void comp_sums(const Run& R, const Depth& D, double* out, const double* in = nul
 }
 
 // max of the tile partials in L.partial
-void global_max(const Run& R, const Depth& D, double* out) {
+// host (may be null): pinned host memory that receives the maximum too
+void global_max(const Run& R, const Depth& D, double* out, double* host = nullptr) {
   Level& L = *R.L;
   const int nseg = (int)D.seg_ptr.size() - 1;
   const int nt = (int)D.tiles.size();
   if (nt <= 16384) {  // one block over all tile partials
-    launch_seg_reduce(L.partial, nullptr, 1, nt, out, true, R.st);
+    launch_seg_reduce(L.partial, nullptr, 1, nt, out, true, R.st, host);
     return;
   }
   launch_seg_reduce(L.partial, D.d_seg, nseg, 0, L.partial2, true, R.st);
-  launch_seg_reduce(L.partial2, nullptr, 1, nseg, out, true, R.st);
+  launch_seg_reduce(L.partial2, nullptr, 1, nseg, out, true, R.st, host);
 }
 
 // Subtract the per-component mean on every singular component (depth k).
@@ -1569,10 +1570,11 @@ static int level_solve(amg_hier* H, int l, double* X, const double* F, const dou
       else
         launch_residual<double>(dim, D0, true, X, frhs, Rb, alpha, beta, L.partial, R.st);
     }
-    global_max(R, D0, L.scal + S_NORM);
+    global_max(R, D0, L.scal + S_NORM, L.h_scal);  // the host reads it after each cycle
   };
+  // the norm kernel also stores the norm into h_scal[0] (pinned host
+  // memory, system scope): no copy, only the wait
   auto read_norm = [&](double& v) -> int {
-    HIPCHK(hipMemcpyAsync(L.h_scal, L.scal + S_NORM, sizeof(double), hipMemcpyDeviceToHost, R.st));
     HIPCHK(hipStreamSynchronize(R.st));
     v = L.h_scal[0];
     return AMG_OK;

@@ -107,7 +107,8 @@ template <typename T>
 void launch_tile_absmax(int dim, const Depth& D, const T* a, double* part, hipStream_t st);
 void launch_reduce_max(const double* part, int n, double* out, hipStream_t st);
 void launch_seg_reduce(const double* in, const int32_t* ptr, int nseg, int n, double* out, bool is_max,
-                       hipStream_t st);
+                       hipStream_t st,
+                       double* host = nullptr);
 // delta[c] = flag[c] ? (sum of component c's tile partials) / cnt[c] : 0, one launch
 void launch_comp_mean_delta(const Depth& D, const double* part, const int32_t* flag, const double* cnt, int ncomp,
                             double* delta, hipStream_t st);

@@ -1836,15 +1836,24 @@ __global__ void __launch_bounds__(256) k_tile_dot(const TileD* __restrict__ tile
 // [ptr[s], ptr[s+1]); ptr == NULL means the single segment [0, n).  One
 // block per segment.
 template <bool MAX>
+// host (may be null): pinned host memory that also receives the results,
+// stored at system scope, so the host reads them after the stream's
+// synchronisation without a copy
 __global__ void __launch_bounds__(256) k_seg_reduce(const double* __restrict__ in, const int32_t* __restrict__ ptr,
-                                                    int n, double* __restrict__ out) {
+                                                    int n, double* __restrict__ out, double* host) {
   __shared__ double sh[4];
   const int s = blockIdx.x;
   const int a = ptr ? ptr[s] : 0, b = ptr ? ptr[s + 1] : n;
   double v = 0.0;
   for (int j = a + (int)threadIdx.x; j < b; j += 256) v = MAX ? fmax(v, in[j]) : v + in[j];
   v = MAX ? block_max<double>(v, sh) : block_sum<double>(v, sh);
-  if (threadIdx.x == 0) out[s] = v;
+  if (threadIdx.x == 0) {
+    out[s] = v;
+    if (host) {
+      __hip_atomic_store(host + s, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __threadfence_system();
+    }
+  }
 }
 
 // per-component sums of chunk partials in a fixed order; one block per component
@@ -2622,12 +2631,12 @@ void launch_tile_absmax(int dim, const Depth& D, const T* a, double* part, hipSt
 }
 
 void launch_seg_reduce(const double* in, const int32_t* ptr, int nseg, int n, double* out, bool is_max,
-                       hipStream_t st) {
+                       hipStream_t st, double* host) {
   if (nseg <= 0) return;
   if (is_max)
-    hipLaunchKernelGGL(k_seg_reduce<true>, dim3(nseg), dim3(256), 0, st, in, ptr, n, out);
+    hipLaunchKernelGGL(k_seg_reduce<true>, dim3(nseg), dim3(256), 0, st, in, ptr, n, out, host);
   else
-    hipLaunchKernelGGL(k_seg_reduce<false>, dim3(nseg), dim3(256), 0, st, in, ptr, n, out);
+    hipLaunchKernelGGL(k_seg_reduce<false>, dim3(nseg), dim3(256), 0, st, in, ptr, n, out, host);
 }
 
 void launch_comp_mean_delta(const Depth& D, const double* part, const int32_t* flag, const double* cnt, int ncomp,
