@@ -654,6 +654,50 @@ int amg_imex_step(amg_hier* hv, amg_hier* hp, double dt, double nu, double* cons
  * unchanged). */
 int amg_dense_inverse(int n, double* a, int threads);
 
+/* ---- Algorithm 1's time schedule (Section 6.2) ------------------------------
+ * The order and times of the level advances of the subcycled AMR method,
+ * host-only (no device call, no level is advanced): a driver runs each
+ * event with the level operations above.
+ *   AMG_SC_SYNCED: one step dt = k0 / ratio^(nlevels-1) of synchronized AMR
+ *     (Section 5.5: all levels together) from t; 3 ratio^(nlevels-1) of them
+ *     take the hierarchy from t0 to t0 + 3 k0 (Algorithm 1, line 1), filling
+ *     the four time slices of every level (eq. vel_slicing);
+ *   AMG_SC_REGRID: regrid and migrate at t, before a coarse step (line 4;
+ *     the criterion read here as a period of regrid_every coarse steps, 0:
+ *     never);
+ *   AMG_SC_ADVANCE: advance `level` by one step dt = k0 / ratio^level from
+ *     t (SingleLevelAdvance, line 5); for level > 0 the interface
+ *     conditions come from the slices of level-1 at t_coarse - i k_coarse,
+ *     i = 0..3, so a stage at t* = t + c dt takes eta = t* - (t_coarse -
+ *     k_coarse) in eq. timeInterp (0 <= eta <= k_coarse) with k = k_coarse;
+ *   AMG_SC_SYNC: the composite projection of levels level..nlevels-1 at t
+ *     (line 11), after the finer levels have caught up with `level`.
+ * Per coarse step the events are those of SingleLevelAdvance(0)'s
+ * recursion: level l advances ratio^l times. */
+#define AMG_SC_SYNCED 0
+#define AMG_SC_REGRID 1
+#define AMG_SC_ADVANCE 2
+#define AMG_SC_SYNC 3
+
+typedef struct {
+  int32_t kind;      /* AMG_SC_* */
+  int32_t level;     /* the level advanced or synchronised from (SYNCED: the finest) */
+  double t;          /* start time of the step, or the time of the regrid / synchronisation */
+  double dt;         /* the step (0 for REGRID and SYNC) */
+  double k_coarse;   /* ADVANCE of a level > 0: the step of level-1; else 0 */
+  double t_coarse;   /* ADVANCE of a level > 0: the newest time slice of level-1; else 0 */
+} amg_sc_event;
+
+/* The events of Algorithm 1 from t0 (step k0 on level 0, refinement ratio
+ * 2 or 4, 1 <= nlevels <= 8): the synchronized start, then ncoarse coarse
+ * steps.  Times are t0 plus integer multiples of the finest step (no drift
+ * over long runs).  events (host, max_events entries) receives at most
+ * max_events of them, *nevents their total.  Errors: AMG_EINVAL (arguments),
+ * AMG_EUNSUPPORTED (more events than max_events; *nevents is still the
+ * total). */
+int amg_subcycle_schedule(int nlevels, int ratio, double t0, double k0, int ncoarse, int regrid_every,
+                          int max_events, int32_t* nevents, amg_sc_event* events);
+
 /* ---- regridding and data migration (Section 5.4, RDM-1..4) -----------------
  * Clustering (RDM-2), as read from Berger and Rigoutsos (1991): a box is
  * shrunk to the bounding box of its tags and accepted when tags / cells

@@ -143,6 +143,7 @@ def lib():
         i32p = C.POINTER(C.c_int32)
         L.amg_cluster.argtypes = [i32, i32p, C.POINTER(C.c_uint8), dbl, i32, i32, i32p, i32p, i32p]
         L.amg_dense_inverse.argtypes = [i32, C.POINTER(C.c_double), i32]
+        L.amg_subcycle_schedule.argtypes = [i32, i32, dbl, dbl, i32, i32, i32, i32p, C.POINTER(ScEvent)]
         L.amg_regrid_boxes.argtypes = [i32, i32p, i32, i32, C.POINTER(C.c_void_p), dbl, i32, i32, i32, i32, i32p, i32p,
                                        i32p]
         L.amg_tag_vorticity.argtypes = [vp, i32, pp, dbl, C.POINTER(C.c_void_p), vp]
@@ -736,6 +737,30 @@ def convection(H, us, outs):
 def _boxes_out(dim, n, lo, hi):
     return [(tuple(int(v) for v in lo[i * dim:(i + 1) * dim]), tuple(int(v) for v in hi[i * dim:(i + 1) * dim]))
             for i in range(n)]
+
+
+SC_KINDS = ("synced", "regrid", "advance", "sync")  # AMG_SC_SYNCED .. AMG_SC_SYNC
+
+
+class ScEvent(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("level", C.c_int32), ("t", C.c_double), ("dt", C.c_double),
+                ("k_coarse", C.c_double), ("t_coarse", C.c_double)]
+
+
+def subcycle_schedule(nlevels, ratio, t0, k0, ncoarse, regrid_every=0):
+    """Algorithm 1's events (see amg_subcycle_schedule) as tuples (kind,
+    level, t, dt, k_coarse, t_coarse), kind one of SC_KINDS."""
+    n = C.c_int32()
+    rc = lib().amg_subcycle_schedule(nlevels, ratio, float(t0), float(k0), ncoarse, regrid_every, 0, C.byref(n),
+                                     None)
+    if rc and rc != EUNSUPPORTED:
+        raise AmgError(rc, "amg_subcycle_schedule failed")
+    ev = (ScEvent * max(1, n.value))()
+    rc = lib().amg_subcycle_schedule(nlevels, ratio, float(t0), float(k0), ncoarse, regrid_every, n.value,
+                                     C.byref(n), ev)
+    if rc:
+        raise AmgError(rc, "amg_subcycle_schedule failed")
+    return [(SC_KINDS[e.kind], e.level, e.t, e.dt, e.k_coarse, e.t_coarse) for e in ev[:n.value]]
 
 
 def dense_inverse(a, threads=1):

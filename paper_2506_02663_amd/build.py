@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamg.so")
-SOURCES = ["layout.cpp", "bottom.cpp", "composite.cpp", "kernels.hip", "api.hip", "imex.hip", "bottom_gmres.hip", "regrid.cpp", "regrid.hip", "tail.hip"]
+SOURCES = ["layout.cpp", "bottom.cpp", "composite.cpp", "kernels.hip", "api.hip", "imex.hip", "bottom_gmres.hip", "regrid.cpp", "regrid.hip", "tail.hip", "subcycle.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of the generated code
